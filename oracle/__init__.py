@@ -1,0 +1,252 @@
+"""FP64 CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+Plain, slow definitions of what the splatting hot path computes (see
+``oracle.c`` for the formulas and the passages of GloSplat they follow).  Only
+``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package; the product path never does.  It shares
+no code with the HIP library.
+
+``build()`` compiles ``oracle.c`` with gcc into ``liboracle.so`` next to it.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+# Default settings (see oracle.h): near, eps2d, frustum pad, alpha_min,
+# alpha_max, T_min, and the ambiguity bands used by the parity rule.
+CFG_DEFAULT = dict(near=0.01, eps2d=0.3, pad=0.3, alpha_min=1.0 / 255.0,
+                   alpha_max=0.99, t_min=1e-4, band_pos=2.4e-7, band_t=2e-4,
+                   band_sig=2e-5, band_depth=1e-6)
+_CFG_ORDER = ["near", "eps2d", "pad", "alpha_min", "alpha_max", "t_min",
+              "band_pos", "band_t", "band_sig", "band_depth"]
+
+_lib = None
+
+
+def build(force=True):
+    """Compile the oracle (gcc, -O2, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               "-Wall", "-Wno-unknown-pragmas", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        _lib = ctypes.CDLL(_LIB)
+        _lib.or_bin_sort.restype = ctypes.c_longlong
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def cfg_array(**over):
+    c = dict(CFG_DEFAULT)
+    c.update(over)
+    return np.array([c[k] for k in _CFG_ORDER], dtype=np.float64)
+
+
+def num_threads():
+    return _load().or_num_threads()
+
+
+def project(scene, viewmat=None, intr=None, wh=None, **cfg):
+    """Per-(view, Gaussian) projection.  Returns a dict of [V*N, ...] arrays."""
+    lib = _load()
+    viewmat = _f64(scene["viewmat"] if viewmat is None else viewmat)
+    intr = _f64(scene["intr"] if intr is None else intr)
+    wh = _i32(scene["wh"] if wh is None else wh)
+    N = scene["means"].shape[1]
+    V = viewmat.shape[0]
+    VN = V * N
+    out = dict(valid=np.zeros(VN, np.int32), depth=np.zeros(VN), mean2d=np.zeros((VN, 2)),
+               cov2d=np.zeros((VN, 3)), conic=np.zeros((VN, 3)), opacity=np.zeros(VN),
+               rgb=np.zeros((VN, 3)), ext=np.zeros((VN, 2)))
+    rc = lib.or_project(
+        ctypes.c_int(N), ctypes.c_int(int(scene["sh_degree"])),
+        _p(_f64(scene["means"])), _p(_f64(scene["log_scales"])), _p(_f64(scene["quats"])),
+        _p(_f64(scene["opacity_logit"])), _p(_f64(scene["sh"])),
+        ctypes.c_int(V), _p(viewmat), _p(intr), _p(wh), _p(cfg_array(**cfg)),
+        _p(out["valid"]), _p(out["depth"]), _p(out["mean2d"]), _p(out["cov2d"]),
+        _p(out["conic"]), _p(out["opacity"]), _p(out["rgb"]), _p(out["ext"]))
+    if rc != 0:
+        raise ValueError("or_project failed")
+    return out
+
+
+def render(proj, wh, bg=None, pix=None, v_rgb=None, **cfg):
+    """Brute-force compositing.  Returns a dict with rgb [n,3], T [n],
+    ncontrib [n], ngate [n], ambiguous [n] and v2d [V*N,9] (None without v_rgb)."""
+    lib = _load()
+    wh = _i32(wh)
+    V = wh.shape[0]
+    VN = proj["valid"].shape[0]
+    N = VN // V
+    P = int(np.sum(wh[:, 0].astype(np.int64) * wh[:, 1]))
+    if pix is not None:
+        pix = np.ascontiguousarray(pix, dtype=np.int64)
+        n = pix.shape[0]
+    else:
+        n = P
+    rgb = np.zeros((n, 3))
+    T = np.zeros(n)
+    nc = np.zeros(n, np.int32)
+    ng = np.zeros(n, np.int32)
+    amb = np.zeros(n, np.int32)
+    v2d = np.zeros((VN, 9)) if v_rgb is not None else None
+    bga = None if bg is None else _f64(bg)
+    rc = lib.or_render(
+        ctypes.c_int(V), _p(wh), ctypes.c_int(N), _p(_i32(proj["valid"])), _p(_f64(proj["depth"])),
+        _p(_f64(proj["mean2d"])), _p(_f64(proj["conic"])), _p(_f64(proj["opacity"])),
+        _p(_f64(proj["rgb"])), _p(bga), _p(cfg_array(**cfg)),
+        ctypes.c_longlong(n), _p(pix), _p(rgb), _p(T), _p(nc), _p(ng), _p(amb),
+        _p(None if v_rgb is None else _f64(v_rgb)), _p(v2d))
+    if rc != 0:
+        raise ValueError("or_render failed")
+    return dict(rgb=rgb, T=T, ncontrib=nc, ngate=ng, ambiguous=amb.astype(bool), v2d=v2d)
+
+
+def project_bwd(scene, v2d, viewmat=None, intr=None, wh=None, **cfg):
+    """Chain the per-pair 2D gradients to the parameters and view twists."""
+    lib = _load()
+    viewmat = _f64(scene["viewmat"] if viewmat is None else viewmat)
+    intr = _f64(scene["intr"] if intr is None else intr)
+    wh = _i32(scene["wh"] if wh is None else wh)
+    N = scene["means"].shape[1]
+    V = viewmat.shape[0]
+    K = (int(scene["sh_degree"]) + 1) ** 2
+    g = dict(means=np.zeros((3, N)), log_scales=np.zeros((3, N)), quats=np.zeros((4, N)),
+             opacity_logit=np.zeros(N), sh=np.zeros((K, 3, N)), twist=np.zeros((V, 6)))
+    rc = lib.or_project_bwd(
+        ctypes.c_int(N), ctypes.c_int(int(scene["sh_degree"])),
+        _p(_f64(scene["means"])), _p(_f64(scene["log_scales"])), _p(_f64(scene["quats"])),
+        _p(_f64(scene["opacity_logit"])), _p(_f64(scene["sh"])),
+        ctypes.c_int(V), _p(viewmat), _p(intr), _p(wh), _p(cfg_array(**cfg)), _p(_f64(v2d)),
+        _p(g["means"]), _p(g["log_scales"]), _p(g["quats"]), _p(g["opacity_logit"]),
+        _p(g["sh"]), _p(g["twist"]))
+    if rc != 0:
+        raise ValueError("or_project_bwd failed")
+    return g
+
+
+def render_fwd_bwd(scene, v_rgb=None, pix=None, bg=None, viewmat=None, **cfg):
+    """Projection + compositing (+ backward when v_rgb is given)."""
+    proj = project(scene, viewmat=viewmat, **cfg)
+    out = render(proj, scene["wh"], bg=bg, pix=pix, v_rgb=v_rgb, **cfg)
+    out["proj"] = proj
+    if v_rgb is not None:
+        out["grads"] = project_bwd(scene, out["v2d"], viewmat=viewmat, **cfg)
+    return out
+
+
+def track(X, viewmat, intr, obs_cam, obs_pt, obs_xy, delta=1.0, lam=1e-4, near=0.01,
+          jacobians=True):
+    lib = _load()
+    X = _f64(X)
+    viewmat = _f64(viewmat)
+    Pt = X.shape[0]
+    ncam = viewmat.shape[0]
+    M = obs_cam.shape[0]
+    out = dict(residual=np.zeros((M, 2)), loss=np.zeros(1), v_X=np.zeros((Pt, 3)),
+               v_twist=np.zeros((ncam, 6)), masked=np.zeros(M, np.int32))
+    if jacobians:
+        out["J_pose"] = np.zeros((M, 2, 6))
+        out["J_X"] = np.zeros((M, 2, 3))
+    rc = lib.or_track(
+        ctypes.c_int(Pt), _p(X), ctypes.c_int(ncam), _p(viewmat), _p(_f64(intr)),
+        ctypes.c_int(M), _p(_i32(obs_cam)), _p(_i32(obs_pt)), _p(_f64(obs_xy)),
+        ctypes.c_double(delta), ctypes.c_double(lam), ctypes.c_double(near),
+        _p(out["residual"]), _p(out["loss"]), _p(out["v_X"]), _p(out["v_twist"]),
+        _p(out.get("J_pose")), _p(out.get("J_X")), _p(out["masked"]))
+    if rc != 0:
+        raise ValueError("or_track failed")
+    out["loss"] = float(out["loss"][0])
+    return out
+
+
+def se3_exp_compose(xi, base):
+    lib = _load()
+    xi = _f64(xi).reshape(-1, 6)
+    base = _f64(base).reshape(-1, 12)
+    out = np.zeros_like(base)
+    lib.or_se3_exp_compose(ctypes.c_int(xi.shape[0]), _p(xi), _p(base), _p(out))
+    return out
+
+
+def se3_jl_transpose(xi, g):
+    lib = _load()
+    xi = _f64(xi).reshape(-1, 6)
+    g = _f64(g).reshape(-1, 6)
+    out = np.zeros_like(g)
+    lib.or_se3_jl_transpose(ctypes.c_int(xi.shape[0]), _p(xi), _p(g), _p(out))
+    return out
+
+
+def adam(p, g, m, v, lr, beta1=0.9, beta2=0.999, eps=1e-15, step=1):
+    """In-place Adam on float64 arrays."""
+    lib = _load()
+    for a in (p, g, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    lib.or_adam(ctypes.c_longlong(p.size), _p(p), _p(g), _p(m), _p(v), ctypes.c_double(lr),
+                ctypes.c_double(beta1), ctypes.c_double(beta2), ctypes.c_double(eps),
+                ctypes.c_int(step))
+
+
+def sh_basis(deg, d, grad=False):
+    lib = _load()
+    K = (deg + 1) ** 2
+    d = _f64(d)
+    Y = np.zeros(K)
+    dY = np.zeros((K, 3)) if grad else None
+    lib.or_sh_basis(ctypes.c_int(deg), _p(d), _p(Y), _p(dY))
+    return (Y, dY) if grad else Y
+
+
+def bin_sort(wh, tile, valid, mean2d, conic, opacity, depth, alpha_min=1.0 / 255.0,
+             margin=0.0):
+    """Tile lists ordered by (float32 depth bits, pair index).  Returns
+    (ranges [T_total,2] int64, ids [I] int32)."""
+    lib = _load()
+    wh = _i32(wh)
+    V = wh.shape[0]
+    VN = valid.shape[0]
+    N = VN // V
+    tw, th = tile
+    T_total = int(sum(((w + tw - 1) // tw) * ((h + th - 1) // th) for w, h in wh))
+    ranges = np.zeros((T_total, 2), np.int64)
+    args = [ctypes.c_int(V), _p(wh), ctypes.c_int(tw), ctypes.c_int(th), ctypes.c_int(N),
+            _p(_i32(valid)), _p(_f32(mean2d)), _p(_f32(conic)), _p(_f32(opacity)),
+            _p(_f32(depth)), ctypes.c_double(alpha_min), ctypes.c_double(margin)]
+    n = lib.or_bin_sort(*args, ctypes.c_longlong(0), _p(ranges), None)
+    need = -n if n < 0 else n
+    ids = np.zeros(max(need, 1), np.int32)
+    n = lib.or_bin_sort(*args, ctypes.c_longlong(need), _p(ranges), _p(ids))
+    return ranges, ids[:need]

@@ -1,0 +1,876 @@
+/*
+ * FP64 CPU oracle for the splatting hot path -- TEST INFRASTRUCTURE ONLY.
+ * See oracle.h for layouts.  Only tests, the smoke check and the benchmark's
+ * CPU-baseline leg use this file.
+ *
+ * What it follows:
+ *  - pinhole projection pi(X) = proj(K (R X + t)), world->camera [R|t]
+ *    (GloSplat Sec. 3.2, "Bundle Adjustment"; Appendix D, projection function);
+ *  - pose composition T = T0 (+) dT with (+) read as Exp(dT) * T0
+ *    (Appendix D, Algorithm 1, pose adjustment);
+ *  - joint BA loss: Huber on the squared reprojection error, delta = 1 px,
+ *    weighted by lambda_BA (Sec. 3.3, eq. L_BA^joint and the total objective);
+ *  - rasterization Rasterize(G, T_i, K_i) (Sec. 3.3 "Implementation",
+ *    Algorithm 1): the paper delegates it to an external 3DGS rasterizer and
+ *    states no formula, so the standard EWA-splatting definition is written
+ *    out here (projected covariance J W Sigma W^T J^T with a 0.3 px^2
+ *    dilation, the 1/255 alpha gate, the 0.99 alpha clamp and the 1e-4
+ *    transmittance stop);
+ *  - Adam with the bias-corrected moments (Algorithm 1, update step).
+ *
+ * Everything is computed per pixel by brute force over all splats: no tiles,
+ * no sorting of intersections.  The backward walks the forward's stored list.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define PI 3.14159265358979323846
+
+int or_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------ small linear algebra */
+
+static void mat3_mul(const double* A, const double* B, double* C) {
+    double T[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double s = 0;
+            for (int k = 0; k < 3; k++) s += A[3 * i + k] * B[3 * k + j];
+            T[3 * i + j] = s;
+        }
+    memcpy(C, T, sizeof T);
+}
+
+static void mat3_transpose(const double* A, double* B) {
+    double T[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) T[3 * i + j] = A[3 * j + i];
+    memcpy(B, T, sizeof T);
+}
+
+static void mat3_vec(const double* A, const double* x, double* y) {
+    double t[3];
+    for (int i = 0; i < 3; i++) t[i] = A[3 * i] * x[0] + A[3 * i + 1] * x[1] + A[3 * i + 2] * x[2];
+    memcpy(y, t, sizeof t);
+}
+
+static void mat3T_vec(const double* A, const double* x, double* y) {
+    double t[3];
+    for (int i = 0; i < 3; i++) t[i] = A[i] * x[0] + A[3 + i] * x[1] + A[6 + i] * x[2];
+    memcpy(y, t, sizeof t);
+}
+
+static void cross3(const double* a, const double* b, double* c) {
+    double t[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+    memcpy(c, t, sizeof t);
+}
+
+/* Rotation of a unit quaternion (w,x,y,z): the standard matrix of v -> q v q*. */
+static void quat_to_rot(const double* q, double* R) {
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
+    R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+    R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
+}
+
+/* d R_ij / d q_c for the matrix above, dR[c][9]. */
+static void quat_to_rot_jac(const double* q, double dR[4][9]) {
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    double J[4][9] = {
+        /* d/dw */ {0, -2 * z, 2 * y, 2 * z, 0, -2 * x, -2 * y, 2 * x, 0},
+        /* d/dx */ {0, 2 * y, 2 * z, 2 * y, -4 * x, -2 * w, 2 * z, 2 * w, -4 * x},
+        /* d/dy */ {-4 * y, 2 * x, 2 * w, 2 * x, 0, 2 * z, -2 * w, 2 * z, -4 * y},
+        /* d/dz */ {-4 * z, -2 * w, 2 * x, 2 * w, -4 * z, 2 * y, 2 * x, 2 * y, 0},
+    };
+    memcpy(dR, J, sizeof J);
+}
+
+/* ------------------------------------------------------------ spherical harmonics */
+/*
+ * Real SH with the Condon-Shortley phase kept, written from the
+ * associated-Legendre closed form:
+ *   Y_l0  = K_l^0 P_l(z)
+ *   Y_lm  = sqrt(2) K_l^m (-1)^m P_l^(m)(z) Re((x+iy)^m)      m > 0
+ *   Y_l-m = sqrt(2) K_l^m (-1)^m P_l^(m)(z) Im((x+iy)^m)      m > 0
+ * with K_l^m = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!), P_l^(m) the m-th derivative
+ * of the Legendre polynomial P_l, and (x+iy)^m = sin^m(theta) e^{i m phi} on
+ * the unit sphere.  Each Y is a polynomial in (x,y,z), so its gradient is
+ * exact.  Index of (l,m) is l*l + l + m.
+ */
+static double factorial(int n) {
+    double f = 1;
+    for (int i = 2; i <= n; i++) f *= i;
+    return f;
+}
+
+static double binom(int n, int k) { return factorial(n) / (factorial(k) * factorial(n - k)); }
+
+/* m-th derivative of P_l at z: P_l(z) = 2^-l sum_k (-1)^k C(l,k) C(2l-2k,l) z^(l-2k). */
+static double legendre_deriv(int l, int m, double z) {
+    double s = 0;
+    for (int k = 0; 2 * k <= l; k++) {
+        int p = l - 2 * k;
+        if (p < m) continue;
+        double c = ((k & 1) ? -1.0 : 1.0) * binom(l, k) * binom(2 * l - 2 * k, l);
+        s += c * factorial(p) / factorial(p - m) * pow(z, p - m);
+    }
+    return s / pow(2.0, l);
+}
+
+void or_sh_basis(int deg, const double* d, double* Y, double* dY) {
+    double x = d[0], y = d[1], z = d[2];
+    /* a[m] + i b[m] = (x + i y)^m */
+    double a[8], b[8];
+    a[0] = 1; b[0] = 0;
+    for (int m = 1; m <= deg; m++) {
+        a[m] = a[m - 1] * x - b[m - 1] * y;
+        b[m] = a[m - 1] * y + b[m - 1] * x;
+    }
+    for (int l = 0; l <= deg; l++) {
+        for (int m = 0; m <= l; m++) {
+            double K = sqrt((2 * l + 1) / (4 * PI) * factorial(l - m) / factorial(l + m));
+            double P = legendre_deriv(l, m, z);
+            double dP = legendre_deriv(l, m + 1, z);
+            if (m == 0) {
+                int i = l * l + l;
+                Y[i] = K * P;
+                if (dY) { dY[3 * i] = 0; dY[3 * i + 1] = 0; dY[3 * i + 2] = K * dP; }
+                continue;
+            }
+            double s = sqrt(2.0) * K * ((m & 1) ? -1.0 : 1.0);
+            int ip = l * l + l + m, in = l * l + l - m;
+            Y[ip] = s * P * a[m];
+            Y[in] = s * P * b[m];
+            if (dY) {
+                /* d a_m/dx = m a_{m-1}, d a_m/dy = -m b_{m-1};
+                   d b_m/dx = m b_{m-1}, d b_m/dy =  m a_{m-1} */
+                dY[3 * ip + 0] = s * P * m * a[m - 1];
+                dY[3 * ip + 1] = s * P * (-m * b[m - 1]);
+                dY[3 * ip + 2] = s * dP * a[m];
+                dY[3 * in + 0] = s * P * m * b[m - 1];
+                dY[3 * in + 1] = s * P * m * a[m - 1];
+                dY[3 * in + 2] = s * dP * b[m];
+            }
+        }
+    }
+}
+
+/* ------------------------------------------------------------ per-pair projection */
+
+typedef struct {
+    double R[9], t[3], fx, fy, cx, cy;
+    int W, H;
+} cam_t;
+
+static void load_cam(const double* viewmat, const double* intr, const int* wh, int v, cam_t* c) {
+    for (int i = 0; i < 3; i++) {
+        for (int j = 0; j < 3; j++) c->R[3 * i + j] = viewmat[12 * v + 4 * i + j];
+        c->t[i] = viewmat[12 * v + 4 * i + 3];
+    }
+    c->fx = intr[4 * v]; c->fy = intr[4 * v + 1]; c->cx = intr[4 * v + 2]; c->cy = intr[4 * v + 3];
+    c->W = wh[2 * v]; c->H = wh[2 * v + 1];
+}
+
+typedef struct {
+    int valid;
+    double mu[3], p[3];         /* world mean, camera-space mean */
+    double qn[4], qnorm;        /* normalised quaternion and |q| */
+    double Rq[9], s[3];         /* rotation of the Gaussian, scales exp(log_scale) */
+    double Sig[9], Sigc[9];     /* world and camera covariance */
+    double J[6];                /* 2x3 projection Jacobian (with the off-screen clamp) */
+    int clampx, clampy;         /* clamp active; then limx/limy hold the clamp value */
+    double limx, limy;
+    double cov2d[3];            /* a, b, c of the dilated 2D covariance */
+    double conic[3];            /* A, B, C of its inverse */
+    double mean2d[2], depth, opacity;
+    double dir[3], dist, camc[3];
+    double shsum[3], rgb[3];
+    double ext[2];
+} pair_t;
+
+static void project_pair(int N, int deg, const double* means, const double* log_scales,
+                         const double* quats, const double* opacity_logit, const double* sh,
+                         const cam_t* c, int g, const double* cfg, pair_t* P) {
+    const double near_plane = cfg[0], eps2d = cfg[1], pad = cfg[2], amin = cfg[3];
+    memset(P, 0, sizeof *P);
+    for (int i = 0; i < 3; i++) P->mu[i] = means[(size_t)i * N + g];
+    mat3_vec(c->R, P->mu, P->p);
+    for (int i = 0; i < 3; i++) P->p[i] += c->t[i];
+    P->depth = P->p[2];
+    double q[4];
+    for (int i = 0; i < 4; i++) q[i] = quats[(size_t)i * N + g];
+    P->qnorm = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    for (int i = 0; i < 4; i++) P->qn[i] = q[i] / P->qnorm;
+    quat_to_rot(P->qn, P->Rq);
+    for (int i = 0; i < 3; i++) P->s[i] = exp((double)log_scales[(size_t)i * N + g]);
+    /* Sigma = Rq S S^T Rq^T */
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double v = 0;
+            for (int k = 0; k < 3; k++) v += P->Rq[3 * i + k] * P->s[k] * P->s[k] * P->Rq[3 * j + k];
+            P->Sig[3 * i + j] = v;
+        }
+    double RS[9], Rt[9];
+    mat3_mul(c->R, P->Sig, RS);
+    mat3_transpose(c->R, Rt);
+    mat3_mul(RS, Rt, P->Sigc);
+    P->opacity = 1.0 / (1.0 + exp(-(double)opacity_logit[g]));
+    /* colour: view direction from the camera centre c = -R^T t */
+    double mt[3] = {-c->t[0], -c->t[1], -c->t[2]};
+    mat3T_vec(c->R, mt, P->camc);
+    double dv[3] = {P->mu[0] - P->camc[0], P->mu[1] - P->camc[1], P->mu[2] - P->camc[2]};
+    P->dist = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+    for (int i = 0; i < 3; i++) P->dir[i] = dv[i] / P->dist;
+    int K = (deg + 1) * (deg + 1);
+    double Y[16];
+    or_sh_basis(deg, P->dir, Y, NULL);
+    for (int ch = 0; ch < 3; ch++) {
+        double s = 0;
+        for (int k = 0; k < K; k++) s += Y[k] * sh[((size_t)k * 3 + ch) * N + g];
+        P->shsum[ch] = s;
+        P->rgb[ch] = s + 0.5 > 0 ? s + 0.5 : 0.0;
+    }
+    if (P->p[2] < near_plane) return;
+    double x = P->p[0], y = P->p[1], z = P->p[2];
+    /* Jacobian of the perspective map, with x/z and y/z clamped to the view
+       frustum widened by pad * (half the field of view) on each side */
+    double lxp = (c->W - c->cx) / c->fx + pad * 0.5 * c->W / c->fx;
+    double lxn = c->cx / c->fx + pad * 0.5 * c->W / c->fx;
+    double lyp = (c->H - c->cy) / c->fy + pad * 0.5 * c->H / c->fy;
+    double lyn = c->cy / c->fy + pad * 0.5 * c->H / c->fy;
+    double tx = x / z, ty = y / z;
+    P->clampx = 0; P->clampy = 0;
+    if (tx > lxp) { tx = lxp; P->clampx = 1; }
+    if (tx < -lxn) { tx = -lxn; P->clampx = 1; }
+    if (ty > lyp) { ty = lyp; P->clampy = 1; }
+    if (ty < -lyn) { ty = -lyn; P->clampy = 1; }
+    P->limx = tx; P->limy = ty;
+    P->J[0] = c->fx / z; P->J[1] = 0; P->J[2] = -c->fx * tx / z;
+    P->J[3] = 0; P->J[4] = c->fy / z; P->J[5] = -c->fy * ty / z;
+    /* cov2d = J Sigc J^T + eps2d I */
+    double JS[6];
+    for (int i = 0; i < 2; i++)
+        for (int j = 0; j < 3; j++) {
+            double v = 0;
+            for (int k = 0; k < 3; k++) v += P->J[3 * i + k] * P->Sigc[3 * k + j];
+            JS[3 * i + j] = v;
+        }
+    double M2[4];
+    for (int i = 0; i < 2; i++)
+        for (int j = 0; j < 2; j++) {
+            double v = 0;
+            for (int k = 0; k < 3; k++) v += JS[3 * i + k] * P->J[3 * j + k];
+            M2[2 * i + j] = v;
+        }
+    double a = M2[0] + eps2d, b = M2[1], cc = M2[3] + eps2d;
+    P->cov2d[0] = a; P->cov2d[1] = b; P->cov2d[2] = cc;
+    double det = a * cc - b * b;
+    if (!(det > 0)) return;
+    P->conic[0] = cc / det; P->conic[1] = -b / det; P->conic[2] = a / det;
+    P->mean2d[0] = c->fx * x / z + c->cx;
+    P->mean2d[1] = c->fy * y / z + c->cy;
+    if (!(P->opacity > amin)) return;
+    double kk = 2.0 * log(P->opacity / amin);
+    P->ext[0] = sqrt(kk * a);
+    P->ext[1] = sqrt(kk * cc);
+    P->valid = 1;
+}
+
+int or_project(int N, int sh_degree, const double* means, const double* log_scales,
+               const double* quats, const double* opacity_logit, const double* sh,
+               int V, const double* viewmat, const double* intr, const int* wh,
+               const double* cfg,
+               int* valid, double* depth, double* mean2d, double* cov2d,
+               double* conic, double* opacity, double* rgb, double* ext) {
+    if (sh_degree < 0 || sh_degree > 3) return -1;
+    for (int v = 0; v < V; v++) {
+        cam_t c;
+        load_cam(viewmat, intr, wh, v, &c);
+#pragma omp parallel for schedule(static)
+        for (int g = 0; g < N; g++) {
+            pair_t P;
+            project_pair(N, sh_degree, means, log_scales, quats, opacity_logit, sh, &c, g, cfg, &P);
+            size_t i = (size_t)v * N + g;
+            if (valid) valid[i] = P.valid;
+            if (depth) depth[i] = P.depth;
+            if (mean2d) { mean2d[2 * i] = P.mean2d[0]; mean2d[2 * i + 1] = P.mean2d[1]; }
+            if (cov2d) for (int k = 0; k < 3; k++) cov2d[3 * i + k] = P.cov2d[k];
+            if (conic) for (int k = 0; k < 3; k++) conic[3 * i + k] = P.conic[k];
+            if (opacity) opacity[i] = P.opacity;
+            if (rgb) for (int k = 0; k < 3; k++) rgb[3 * i + k] = P.rgb[k];
+            if (ext) { ext[2 * i] = P.ext[0]; ext[2 * i + 1] = P.ext[1]; }
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------ per-pixel compositing */
+
+typedef struct {
+    int g;
+    double depth, alpha, araw, sigma, dx, dy, T;
+} hit_t;
+
+static int hit_cmp(const void* pa, const void* pb) {
+    const hit_t* a = (const hit_t*)pa;
+    const hit_t* b = (const hit_t*)pb;
+    if (a->depth < b->depth) return -1;
+    if (a->depth > b->depth) return 1;
+    return (a->g > b->g) - (a->g < b->g);
+}
+
+int or_render(int V, const int* wh, int N, const int* valid, const double* depth,
+              const double* mean2d, const double* conic, const double* opacity,
+              const double* rgb, const double* bg, const double* cfg,
+              long long npix, const long long* pix,
+              double* out_rgb, double* out_T, int* out_ncontrib, int* out_ngate, int* ambiguous,
+              const double* v_rgb, double* v2d) {
+    const double amin = cfg[3], amax = cfg[4], tmin = cfg[5];
+    const double band_pos = cfg[6], band_t = cfg[7], band_sig = cfg[8], band_d = cfg[9];
+    long long* voff = (long long*)malloc(sizeof(long long) * (V + 1));
+    voff[0] = 0;
+    for (int v = 0; v < V; v++) voff[v + 1] = voff[v] + (long long)wh[2 * v] * wh[2 * v + 1];
+    if (pix == NULL) npix = voff[V];
+    int fail = 0;
+#pragma omp parallel
+    {
+        hit_t* hits = (hit_t*)malloc(sizeof(hit_t) * (size_t)(N > 0 ? N : 1));
+        double* gate_depth = (double*)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
+        int* gate_g = (int*)malloc(sizeof(int) * (size_t)(N > 0 ? N : 1));
+#pragma omp for schedule(dynamic, 64)
+        for (long long s = 0; s < npix; s++) {
+            long long gp = pix ? pix[s] : s;
+            int v = 0;
+            while (v < V && gp >= voff[v + 1]) v++;
+            if (v >= V) { fail = 1; continue; }
+            long long local = gp - voff[v];
+            int W = wh[2 * v];
+            double px = (double)(local % W) + 0.5, py = (double)(local / W) + 0.5;
+            int nh = 0, ng = 0;
+            for (int g = 0; g < N; g++) {
+                size_t i = (size_t)v * N + g;
+                if (!valid[i]) continue;
+                double mx = mean2d[2 * i], my = mean2d[2 * i + 1];
+                double dx = mx - px, dy = my - py;
+                double A = conic[3 * i], B = conic[3 * i + 1], C = conic[3 * i + 2];
+                double sigma = 0.5 * (A * dx * dx + C * dy * dy) + B * dx * dy;
+                if (sigma < 0) continue;
+                double araw = opacity[i] * exp(-sigma);
+                double alpha = araw < amax ? araw : amax;
+                /* how far a float32 evaluation of sigma may stray: position error
+                   (relative to the coordinate's magnitude) times |grad sigma|,
+                   plus a relative error of sigma itself */
+                double gsx = A * dx + B * dy, gsy = B * dx + C * dy;
+                double mag = fabs(mx) > fabs(my) ? fabs(mx) : fabs(my);
+                if (mag < 1.0) mag = 1.0;
+                double err = sqrt(gsx * gsx + gsy * gsy) * band_pos * mag + band_sig * sigma;
+                if (fabs(sigma - log(opacity[i] / amin)) <= err) {
+                    gate_depth[ng] = depth[i]; gate_g[ng] = g; ng++;
+                }
+                if (opacity[i] > amax && fabs(sigma - log(opacity[i] / amax)) <= err) {
+                    gate_depth[ng] = depth[i]; gate_g[ng] = g; ng++;
+                }
+                if (alpha < amin) continue;
+                hit_t h = {g, depth[i], alpha, araw, sigma, dx, dy, 0};
+                hits[nh++] = h;
+            }
+            qsort(hits, nh, sizeof(hit_t), hit_cmp);
+            double T = 1.0, Cp[3] = {0, 0, 0};
+            int amb = 0, n = 0, stop = -1;
+            for (int k = 0; k < nh; k++) {
+                double Tn = T * (1.0 - hits[k].alpha);
+                if (fabs(Tn - tmin) <= band_t * tmin) amb = 1;
+                if (k + 1 < nh && fabs(hits[k + 1].depth - hits[k].depth) <= band_d * fabs(hits[k].depth))
+                    amb = 1;
+                if (Tn < tmin) { stop = k; break; }
+                hits[k].T = T;
+                size_t i = (size_t)v * N + hits[k].g;
+                for (int ch = 0; ch < 3; ch++) Cp[ch] += rgb[3 * i + ch] * hits[k].alpha * T;
+                T = Tn;
+                n = k + 1;
+            }
+            /* a splat at the alpha gate or the clamp matters only if it lies
+               before the stop */
+            for (int j = 0; j < ng && !amb; j++) {
+                if (stop < 0) { amb = 1; break; }
+                hit_t key = {gate_g[j], gate_depth[j], 0, 0, 0, 0, 0, 0};
+                if (hit_cmp(&key, &hits[stop]) < 0) amb = 1;
+            }
+            for (int ch = 0; ch < 3; ch++) {
+                double bgc = bg ? bg[ch] : 0.0;
+                if (out_rgb) out_rgb[3 * s + ch] = Cp[ch] + T * bgc;
+            }
+            if (out_T) out_T[s] = T;
+            if (out_ncontrib) out_ncontrib[s] = n;
+            if (out_ngate) out_ngate[s] = nh;
+            if (ambiguous) ambiguous[s] = amb;
+            if (v_rgb && v2d) {
+                /* dC/d alpha_k = c_k T_k - (sum_{j>k} c_j alpha_j T_j + T_N bg) / (1 - alpha_k) */
+                const double* vc = v_rgb + 3 * s;
+                double Bsum[3] = {0, 0, 0};
+                double Tfin = T;
+                for (int k = n - 1; k >= 0; k--) {
+                    hit_t* h = &hits[k];
+                    size_t i = (size_t)v * N + h->g;
+                    double* o = v2d + 9 * i;
+                    double va = 0;
+                    for (int ch = 0; ch < 3; ch++) {
+                        double c = rgb[3 * i + ch];
+                        double bgc = bg ? bg[ch] : 0.0;
+                        double wgt = h->alpha * h->T;
+#pragma omp atomic
+                        o[6 + ch] += wgt * vc[ch];
+                        va += vc[ch] * (c * h->T - (Bsum[ch] + Tfin * bgc) / (1.0 - h->alpha));
+                        Bsum[ch] += c * wgt;
+                    }
+                    if (h->araw < amax) {
+                        double vo = va * exp(-h->sigma);
+                        double vs = -h->alpha * va;
+                        double A = conic[3 * i], B = conic[3 * i + 1], C = conic[3 * i + 2];
+                        double gx = vs * (A * h->dx + B * h->dy);
+                        double gy = vs * (B * h->dx + C * h->dy);
+#pragma omp atomic
+                        o[0] += gx;
+#pragma omp atomic
+                        o[1] += gy;
+#pragma omp atomic
+                        o[2] += vs * 0.5 * h->dx * h->dx;
+#pragma omp atomic
+                        o[3] += vs * h->dx * h->dy;
+#pragma omp atomic
+                        o[4] += vs * 0.5 * h->dy * h->dy;
+#pragma omp atomic
+                        o[5] += vo;
+                    }
+                }
+            }
+        }
+        free(hits);
+        free(gate_depth);
+        free(gate_g);
+    }
+    free(voff);
+    return fail ? -1 : 0;
+}
+
+/* ------------------------------------------------------------ projection backward */
+
+int or_project_bwd(int N, int sh_degree, const double* means, const double* log_scales,
+                   const double* quats, const double* opacity_logit, const double* sh,
+                   int V, const double* viewmat, const double* intr, const int* wh,
+                   const double* cfg, const double* v2d,
+                   double* v_means, double* v_log_scales, double* v_quats,
+                   double* v_opacity_logit, double* v_sh, double* v_twist) {
+    if (sh_degree < 0 || sh_degree > 3) return -1;
+    int K = (sh_degree + 1) * (sh_degree + 1);
+    memset(v_means, 0, sizeof(double) * 3 * N);
+    memset(v_log_scales, 0, sizeof(double) * 3 * N);
+    memset(v_quats, 0, sizeof(double) * 4 * N);
+    memset(v_opacity_logit, 0, sizeof(double) * N);
+    memset(v_sh, 0, sizeof(double) * (size_t)K * 3 * N);
+    memset(v_twist, 0, sizeof(double) * 6 * V);
+    for (int v = 0; v < V; v++) {
+        cam_t c;
+        load_cam(viewmat, intr, wh, v, &c);
+        double tw[6] = {0, 0, 0, 0, 0, 0};
+#pragma omp parallel
+        {
+            double twl[6] = {0, 0, 0, 0, 0, 0};
+#pragma omp for schedule(static)
+            for (int g = 0; g < N; g++) {
+                pair_t P;
+                project_pair(N, sh_degree, means, log_scales, quats, opacity_logit, sh, &c, g, cfg, &P);
+                if (!P.valid) continue;
+                const double* G9 = v2d + 9 * ((size_t)v * N + g);
+                double vp[3] = {0, 0, 0};
+                double vmu[3] = {0, 0, 0};
+                /* opacity */
+                double o = P.opacity;
+                v_opacity_logit[g] += G9[5] * o * (1 - o);
+                /* colour and SH */
+                double Y[16], dY[48];
+                or_sh_basis(sh_degree, P.dir, Y, dY);
+                double vdir[3] = {0, 0, 0};
+                for (int ch = 0; ch < 3; ch++) {
+                    if (!(P.shsum[ch] + 0.5 > 0)) continue;
+                    double vr = G9[6 + ch];
+                    for (int k = 0; k < K; k++) {
+                        v_sh[((size_t)k * 3 + ch) * N + g] += Y[k] * vr;
+                        double co = sh[((size_t)k * 3 + ch) * N + g];
+                        for (int e = 0; e < 3; e++) vdir[e] += vr * co * dY[3 * k + e];
+                    }
+                }
+                /* dir = (mu - c)/|mu - c|: tangential projection */
+                double dd = P.dir[0] * vdir[0] + P.dir[1] * vdir[1] + P.dir[2] * vdir[2];
+                double vmud[3];
+                for (int e = 0; e < 3; e++) vmud[e] = (vdir[e] - P.dir[e] * dd) / P.dist;
+                for (int e = 0; e < 3; e++) vmu[e] += vmud[e];
+                /* camera centre moves by -R^T rho under the left twist */
+                double Rvm[3];
+                mat3_vec(c.R, vmud, Rvm);
+                for (int e = 0; e < 3; e++) twl[e] += Rvm[e];
+                /* mean2d */
+                double x = P.p[0], y = P.p[1], z = P.p[2];
+                double vmx = G9[0], vmy = G9[1];
+                vp[0] += c.fx / z * vmx;
+                vp[1] += c.fy / z * vmy;
+                vp[2] += -(c.fx * x * vmx + c.fy * y * vmy) / (z * z);
+                /* conic -> cov2d: G2 = -M Gc M, Gc = [[vA, vB/2],[vB/2, vC]] */
+                double A = P.conic[0], B = P.conic[1], C = P.conic[2];
+                double gA = G9[2], gB = 0.5 * G9[3], gC = G9[4];
+                double M[4] = {A, B, B, C}, Gc[4] = {gA, gB, gB, gC}, T1[4], G2[4];
+                for (int i = 0; i < 2; i++)
+                    for (int j = 0; j < 2; j++)
+                        T1[2 * i + j] = M[2 * i] * Gc[j] + M[2 * i + 1] * Gc[2 + j];
+                for (int i = 0; i < 2; i++)
+                    for (int j = 0; j < 2; j++)
+                        G2[2 * i + j] = -(T1[2 * i] * M[j] + T1[2 * i + 1] * M[2 + j]);
+                /* v_J = 2 G2 J Sigc ; v_Sigc = J^T G2 J */
+                double JS[6];
+                for (int i = 0; i < 2; i++)
+                    for (int j = 0; j < 3; j++) {
+                        double s = 0;
+                        for (int k = 0; k < 3; k++) s += P.J[3 * i + k] * P.Sigc[3 * k + j];
+                        JS[3 * i + j] = s;
+                    }
+                double vJ[6];
+                for (int i = 0; i < 2; i++)
+                    for (int j = 0; j < 3; j++)
+                        vJ[3 * i + j] = 2 * (G2[2 * i] * JS[j] + G2[2 * i + 1] * JS[3 + j]);
+                double vSc[9];
+                for (int i = 0; i < 3; i++)
+                    for (int j = 0; j < 3; j++) {
+                        double s = 0;
+                        for (int a = 0; a < 2; a++)
+                            for (int b = 0; b < 2; b++) s += P.J[3 * a + i] * G2[2 * a + b] * P.J[3 * b + j];
+                        vSc[3 * i + j] = s;
+                    }
+                /* J = [[fx/z, 0, -fx tx/z], [0, fy/z, -fy ty/z]], tx = x/z unless clamped */
+                vp[2] += -c.fx / (z * z) * vJ[0] - c.fy / (z * z) * vJ[4];
+                if (!P.clampx) {
+                    vp[0] += -c.fx / (z * z) * vJ[2];
+                    vp[2] += 2 * c.fx * x / (z * z * z) * vJ[2];
+                } else {
+                    vp[2] += c.fx * P.limx / (z * z) * vJ[2];
+                }
+                if (!P.clampy) {
+                    vp[1] += -c.fy / (z * z) * vJ[5];
+                    vp[2] += 2 * c.fy * y / (z * z * z) * vJ[5];
+                } else {
+                    vp[2] += c.fy * P.limy / (z * z) * vJ[5];
+                }
+                /* p = R mu + t */
+                double vmp[3];
+                mat3T_vec(c.R, vp, vmp);
+                for (int e = 0; e < 3; e++) vmu[e] += vmp[e];
+                /* twist: rho gets v_p, phi gets p x v_p + 2 axial(Sigc vSigc) */
+                double pxv[3];
+                cross3(P.p, vp, pxv);
+                double W9[9];
+                mat3_mul(P.Sigc, vSc, W9);
+                twl[0] += vp[0]; twl[1] += vp[1]; twl[2] += vp[2];
+                twl[3] += pxv[0] + 2 * (W9[5] - W9[7]);
+                twl[4] += pxv[1] + 2 * (W9[6] - W9[2]);
+                twl[5] += pxv[2] + 2 * (W9[1] - W9[3]);
+                /* Sigc = R Sig R^T -> vSig = R^T vSc R */
+                double Rt[9], T9[9], vS[9];
+                mat3_transpose(c.R, Rt);
+                mat3_mul(Rt, vSc, T9);
+                mat3_mul(T9, c.R, vS);
+                /* Sig = Mm Mm^T, Mm = Rq S -> vMm = 2 vS Mm */
+                double Mm[9];
+                for (int i = 0; i < 3; i++)
+                    for (int j = 0; j < 3; j++) Mm[3 * i + j] = P.Rq[3 * i + j] * P.s[j];
+                double vM[9];
+                mat3_mul(vS, Mm, vM);
+                for (int k = 0; k < 9; k++) vM[k] *= 2;
+                /* scales: vs_j = (Rq^T vM)_jj, then through exp */
+                for (int j = 0; j < 3; j++) {
+                    double s = 0;
+                    for (int i = 0; i < 3; i++) s += P.Rq[3 * i + j] * vM[3 * i + j];
+                    v_log_scales[(size_t)j * N + g] += s * P.s[j];
+                }
+                /* rotation: vRq = vM S, then dRq/dq, then normalisation */
+                double vRq[9];
+                for (int i = 0; i < 3; i++)
+                    for (int j = 0; j < 3; j++) vRq[3 * i + j] = vM[3 * i + j] * P.s[j];
+                double dR[4][9];
+                quat_to_rot_jac(P.qn, dR);
+                double vqn[4];
+                for (int a = 0; a < 4; a++) {
+                    double s = 0;
+                    for (int k = 0; k < 9; k++) s += dR[a][k] * vRq[k];
+                    vqn[a] = s;
+                }
+                double qd = 0;
+                for (int a = 0; a < 4; a++) qd += P.qn[a] * vqn[a];
+                for (int a = 0; a < 4; a++)
+                    v_quats[(size_t)a * N + g] += (vqn[a] - P.qn[a] * qd) / P.qnorm;
+                for (int e = 0; e < 3; e++) v_means[(size_t)e * N + g] += vmu[e];
+            }
+#pragma omp critical
+            for (int k = 0; k < 6; k++) tw[k] += twl[k];
+        }
+        for (int k = 0; k < 6; k++) v_twist[6 * v + k] = tw[k];
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------ track reprojection */
+
+int or_track(int Pt, const double* X, int ncam, const double* viewmat, const double* intr,
+             int M, const int* obs_cam, const int* obs_pt, const double* obs_xy,
+             double delta, double lambda, double near_plane,
+             double* residual, double* loss, double* v_X, double* v_twist,
+             double* J_pose, double* J_X, int* masked) {
+    if (v_X) memset(v_X, 0, sizeof(double) * 3 * (size_t)Pt);
+    if (v_twist) memset(v_twist, 0, sizeof(double) * 6 * (size_t)ncam);
+    double L = 0;
+    for (int o = 0; o < M; o++) {
+        int ci = obs_cam[o], k = obs_pt[o];
+        if (ci < 0 || ci >= ncam || k < 0 || k >= Pt) return -1;
+        double R[9], t[3], Xk[3], p[3];
+        for (int i = 0; i < 3; i++) {
+            for (int j = 0; j < 3; j++) R[3 * i + j] = viewmat[12 * ci + 4 * i + j];
+            t[i] = viewmat[12 * ci + 4 * i + 3];
+            Xk[i] = X[3 * (size_t)k + i];
+        }
+        mat3_vec(R, Xk, p);
+        for (int i = 0; i < 3; i++) p[i] += t[i];
+        double fx = intr[4 * ci], fy = intr[4 * ci + 1], cx = intr[4 * ci + 2], cy = intr[4 * ci + 3];
+        int msk = !(p[2] >= near_plane);
+        if (masked) masked[o] = msk;
+        if (msk) {
+            if (residual) { residual[2 * o] = 0; residual[2 * o + 1] = 0; }
+            if (J_pose) memset(J_pose + 12 * (size_t)o, 0, sizeof(double) * 12);
+            if (J_X) memset(J_X + 6 * (size_t)o, 0, sizeof(double) * 6);
+            continue;
+        }
+        double z = p[2];
+        double r[2] = {fx * p[0] / z + cx - obs_xy[2 * o], fy * p[1] / z + cy - obs_xy[2 * o + 1]};
+        if (residual) { residual[2 * o] = r[0]; residual[2 * o + 1] = r[1]; }
+        double s = r[0] * r[0] + r[1] * r[1];
+        double rho, drho;
+        if (s <= delta * delta) { rho = s; drho = 1.0; }
+        else { rho = 2 * delta * sqrt(s) - delta * delta; drho = delta / sqrt(s); }
+        L += lambda * rho;
+        /* J_pi (2x3) at p */
+        double Jp[6] = {fx / z, 0, -fx * p[0] / (z * z), 0, fy / z, -fy * p[1] / (z * z)};
+        double vr[2] = {lambda * 2 * drho * r[0], lambda * 2 * drho * r[1]};
+        double vp[3];
+        for (int j = 0; j < 3; j++) vp[j] = Jp[j] * vr[0] + Jp[3 + j] * vr[1];
+        if (v_X) {
+            double vx[3];
+            mat3T_vec(R, vp, vx);
+            for (int j = 0; j < 3; j++) v_X[3 * (size_t)k + j] += vx[j];
+        }
+        if (v_twist) {
+            double pxv[3];
+            cross3(p, vp, pxv);
+            for (int j = 0; j < 3; j++) {
+                v_twist[6 * ci + j] += vp[j];
+                v_twist[6 * ci + 3 + j] += pxv[j];
+            }
+        }
+        if (J_pose) {
+            /* d p / d(rho, phi) = [I | -[p]x] */
+            double D[18] = {1, 0, 0, 0, p[2], -p[1],
+                            0, 1, 0, -p[2], 0, p[0],
+                            0, 0, 1, p[1], -p[0], 0};
+            for (int a = 0; a < 2; a++)
+                for (int b = 0; b < 6; b++) {
+                    double v = 0;
+                    for (int e = 0; e < 3; e++) v += Jp[3 * a + e] * D[6 * e + b];
+                    J_pose[12 * (size_t)o + 6 * a + b] = v;
+                }
+        }
+        if (J_X) {
+            for (int a = 0; a < 2; a++)
+                for (int b = 0; b < 3; b++) {
+                    double v = 0;
+                    for (int e = 0; e < 3; e++) v += Jp[3 * a + e] * R[3 * e + b];
+                    J_X[6 * (size_t)o + 3 * a + b] = v;
+                }
+        }
+    }
+    if (loss) *loss = L;
+    return 0;
+}
+
+/* ------------------------------------------------------------ SE(3) by power series */
+
+static void mat_mul_n(int n, const double* A, const double* B, double* C) {
+    double T[36];
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < n; j++) {
+            double s = 0;
+            for (int k = 0; k < n; k++) s += A[n * i + k] * B[n * k + j];
+            T[n * i + j] = s;
+        }
+    memcpy(C, T, sizeof(double) * n * n);
+}
+
+void or_se3_exp_compose(int V, const double* xi, const double* base, double* out) {
+    for (int v = 0; v < V; v++) {
+        const double* x = xi + 6 * v;
+        /* twist matrix [[phi]x, rho; 0 0] */
+        double A[16] = {0, -x[5], x[4], x[0],
+                        x[5], 0, -x[3], x[1],
+                        -x[4], x[3], 0, x[2],
+                        0, 0, 0, 0};
+        double E[16] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1};
+        double P[16];
+        memcpy(P, E, sizeof P);
+        for (int n = 1; n < 80; n++) {
+            mat_mul_n(4, P, A, P);
+            double mx = 0;
+            for (int k = 0; k < 16; k++) { P[k] /= n; E[k] += P[k]; if (fabs(P[k]) > mx) mx = fabs(P[k]); }
+            if (mx < 1e-300) break;
+        }
+        double B[16] = {0};
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 4; j++) B[4 * i + j] = base[12 * v + 4 * i + j];
+        B[15] = 1;
+        double T[16];
+        mat_mul_n(4, E, B, T);
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 4; j++) out[12 * v + 4 * i + j] = T[4 * i + j];
+    }
+}
+
+void or_se3_jl_transpose(int V, const double* xi, const double* g, double* out) {
+    for (int v = 0; v < V; v++) {
+        const double* x = xi + 6 * v;
+        const double *r = x, *f = x + 3;
+        /* ad = [[phi]x, [rho]x; 0, [phi]x] */
+        double ad[36] = {0};
+        double fx[9] = {0, -f[2], f[1], f[2], 0, -f[0], -f[1], f[0], 0};
+        double rx[9] = {0, -r[2], r[1], r[2], 0, -r[0], -r[1], r[0], 0};
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) {
+                ad[6 * i + j] = fx[3 * i + j];
+                ad[6 * i + 3 + j] = rx[3 * i + j];
+                ad[6 * (3 + i) + 3 + j] = fx[3 * i + j];
+            }
+        double J[36] = {0}, P[36] = {0};
+        for (int i = 0; i < 6; i++) { J[7 * i] = 1; P[7 * i] = 1; }
+        for (int n = 1; n < 80; n++) {
+            mat_mul_n(6, P, ad, P);
+            double mx = 0;
+            for (int k = 0; k < 36; k++) { P[k] /= (n + 1); J[k] += P[k]; if (fabs(P[k]) > mx) mx = fabs(P[k]); }
+            if (mx < 1e-300) break;
+        }
+        for (int j = 0; j < 6; j++) {
+            double s = 0;
+            for (int i = 0; i < 6; i++) s += J[6 * i + j] * g[6 * v + i];
+            out[6 * v + j] = s;
+        }
+    }
+}
+
+/* ------------------------------------------------------------ Adam */
+
+void or_adam(long long n, double* p, const double* g, double* m, double* v,
+             double lr, double beta1, double beta2, double eps, int step) {
+    double bc1 = 1 - pow(beta1, step), bc2 = 1 - pow(beta2, step);
+    for (long long i = 0; i < n; i++) {
+        m[i] = beta1 * m[i] + (1 - beta1) * g[i];
+        v[i] = beta2 * v[i] + (1 - beta2) * g[i] * g[i];
+        double mh = m[i] / bc1, vh = v[i] / bc2;
+        p[i] -= lr * mh / (sqrt(vh) + eps);
+    }
+}
+
+/* ------------------------------------------------------------ tile lists */
+
+/* minimum over the rectangle [x0,x1]x[y0,y1] of q(d) = 0.5(A dx^2 + C dy^2) + B dx dy,
+   d = point - m.  q is convex, so off-centre the minimum lies on an edge. */
+static double edge_min(double A, double B, double C, double fixed, int fixed_is_x,
+                       double lo, double hi) {
+    /* along an edge one coordinate is fixed (f), the other (u) runs over [lo,hi]:
+       q(u) = 0.5 P f^2 + Q f u + 0.5 S u^2 */
+    double Pc = fixed_is_x ? A : C, Sc = fixed_is_x ? C : A;
+    double u = -B * fixed / Sc;
+    if (u < lo) u = lo;
+    if (u > hi) u = hi;
+    return 0.5 * Pc * fixed * fixed + B * fixed * u + 0.5 * Sc * u * u;
+}
+
+static double rect_min(double A, double B, double C, double mx, double my,
+                       double x0, double x1, double y0, double y1) {
+    if (mx >= x0 && mx <= x1 && my >= y0 && my <= y1) return 0.0;
+    double lx = x0 - mx, hx = x1 - mx, ly = y0 - my, hy = y1 - my;
+    double q = edge_min(A, B, C, lx, 1, ly, hy);
+    double t = edge_min(A, B, C, hx, 1, ly, hy); if (t < q) q = t;
+    t = edge_min(A, B, C, ly, 0, lx, hx); if (t < q) q = t;
+    t = edge_min(A, B, C, hy, 0, lx, hx); if (t < q) q = t;
+    return q;
+}
+
+typedef struct {
+    uint32_t dbits;
+    int id;
+} key_t;
+
+static int key_cmp(const void* pa, const void* pb) {
+    const key_t* a = (const key_t*)pa;
+    const key_t* b = (const key_t*)pb;
+    if (a->dbits != b->dbits) return a->dbits < b->dbits ? -1 : 1;
+    return (a->id > b->id) - (a->id < b->id);
+}
+
+long long or_bin_sort(int V, const int* wh, int tile_w, int tile_h, int N,
+                      const int* valid, const float* mean2d, const float* conic,
+                      const float* opacity, const float* depth, double alpha_min,
+                      double margin, long long cap, long long* ranges, int* ids) {
+    long long total = 0, tcount = 0;
+    key_t* buf = (key_t*)malloc(sizeof(key_t) * (size_t)(N > 0 ? N : 1));
+    for (int v = 0; v < V; v++) {
+        int W = wh[2 * v], H = wh[2 * v + 1];
+        int gx = (W + tile_w - 1) / tile_w, gy = (H + tile_h - 1) / tile_h;
+        for (int ty = 0; ty < gy; ty++)
+            for (int tx = 0; tx < gx; tx++) {
+                double x0 = tx * tile_w + 0.5, y0 = ty * tile_h + 0.5;
+                double x1 = (tx * tile_w + tile_w < W ? tx * tile_w + tile_w : W) - 0.5;
+                double y1 = (ty * tile_h + tile_h < H ? ty * tile_h + tile_h : H) - 0.5;
+                int n = 0;
+                for (int g = 0; g < N; g++) {
+                    size_t i = (size_t)v * N + g;
+                    if (!valid[i]) continue;
+                    double o = opacity[i];
+                    if (!(o > alpha_min)) continue;
+                    double q = rect_min(conic[3 * i], conic[3 * i + 1], conic[3 * i + 2],
+                                        mean2d[2 * i], mean2d[2 * i + 1], x0, x1, y0, y1);
+                    if (q <= log(o / alpha_min) + margin) {
+                        uint32_t b;
+                        memcpy(&b, &depth[i], 4);
+                        buf[n].dbits = b;
+                        buf[n].id = (int)i;
+                        n++;
+                    }
+                }
+                qsort(buf, n, sizeof(key_t), key_cmp);
+                if (ranges) { ranges[2 * tcount] = total; ranges[2 * tcount + 1] = total + n; }
+                for (int k = 0; k < n; k++) {
+                    if (ids && total + k < cap) ids[total + k] = buf[k].id;
+                }
+                total += n;
+                tcount++;
+            }
+    }
+    free(buf);
+    return total <= cap ? total : -total;
+}

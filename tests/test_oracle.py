@@ -1,0 +1,621 @@
+"""Pins of the FP64 oracle against things other than itself: closed forms,
+special cases that reduce to library routines (scipy), invariants, brute force
+and central finite differences.  CPU only.
+
+The paper prints no image, loss or gradient value, so no pin is the paper's
+own number; every pin below is a closed form or an identity the definition
+implies.
+"""
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.special
+from scipy.spatial.transform import Rotation
+
+import oracle
+
+C0 = 1.0 / (2.0 * np.sqrt(np.pi))
+
+
+# ----------------------------------------------------------------- helpers
+
+def _scene(means, log_scales, quats, logit, sh, deg, viewmat, intr, wh):
+    return dict(means=np.asarray(means, float), log_scales=np.asarray(log_scales, float),
+                quats=np.asarray(quats, float), opacity_logit=np.asarray(logit, float),
+                sh=np.asarray(sh, float), sh_degree=deg,
+                viewmat=np.asarray(viewmat, float).reshape(-1, 12),
+                intr=np.asarray(intr, float).reshape(-1, 4),
+                wh=np.asarray(wh, np.int32).reshape(-1, 2))
+
+
+def _viewmat(R, t):
+    return np.concatenate([R, np.asarray(t)[:, None]], axis=1).reshape(12)
+
+
+def _world_from_cam(R, t, pc):
+    return R.T @ (np.asarray(pc, float) - t)
+
+
+def _cs_real_sh(l, m, d):
+    """Real SH with the Condon-Shortley phase, from scipy's complex SH."""
+    d = np.asarray(d, float) / np.linalg.norm(d)
+    theta = np.arccos(np.clip(d[2], -1, 1))
+    phi = np.arctan2(d[1], d[0]) % (2 * np.pi)
+    if m == 0:
+        return scipy.special.sph_harm_y(l, 0, theta, phi).real
+    Y = scipy.special.sph_harm_y(l, abs(m), theta, phi)
+    return np.sqrt(2) * (Y.real if m > 0 else Y.imag)
+
+
+def _twist_matrix(xi):
+    r, f = xi[:3], xi[3:]
+    return np.array([[0, -f[2], f[1], r[0]],
+                     [f[2], 0, -f[0], r[1]],
+                     [-f[1], f[0], 0, r[2]],
+                     [0, 0, 0, 0]], float)
+
+
+def _left_perturb(viewmat12, xi):
+    """Exp(xi) * T by scipy's matrix exponential (not the oracle's series)."""
+    T = np.eye(4)
+    T[:3, :] = np.asarray(viewmat12, float).reshape(3, 4)
+    return (scipy.linalg.expm(_twist_matrix(xi)) @ T)[:3, :].reshape(12)
+
+
+# ----------------------------------------------------------------- projection
+
+def test_single_isotropic_gaussian_closed_form():
+    # mu = (0,0,4) in camera space, s = 0.05, o = 0.5, f = 300, c = 128
+    # => cov2d = (f s / z)^2 + 0.3 = 14.3625 I; at pixel (128,128) (centre
+    # 128.5) sigma = 0.5 * 0.5 / 14.3625; half extent sqrt(2 ln(127.5) 14.3625).
+    rng = np.random.default_rng(0)
+    R = Rotation.random(random_state=1).as_matrix()
+    t = rng.normal(size=3)
+    mu = _world_from_cam(R, t, [0, 0, 4])
+    q = 3.0 * rng.normal(size=4)                   # not unit: the method normalises
+    c_dc = 0.7
+    sc = _scene(mu[:, None], np.full((3, 1), np.log(0.05)), q[:, None], [0.0],
+                np.full((1, 3, 1), c_dc), 0, _viewmat(R, t), [300, 300, 128, 128], [256, 256])
+    pr = oracle.project(sc)
+    assert pr["valid"][0] == 1
+    np.testing.assert_allclose(pr["cov2d"][0], [14.3625, 0, 14.3625], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(pr["conic"][0], [1 / 14.3625, 0, 1 / 14.3625], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(pr["mean2d"][0], [128, 128], rtol=0, atol=1e-10)
+    np.testing.assert_allclose(pr["depth"][0], 4.0, rtol=1e-13)
+    np.testing.assert_allclose(pr["ext"][0], [11.8009] * 2, rtol=0, atol=1e-4)
+    np.testing.assert_allclose(pr["rgb"][0], [0.5 + C0 * c_dc] * 3, rtol=1e-13)
+    out = oracle.render(pr, sc["wh"], pix=[128 * 256 + 128])
+    sigma = 0.0174064
+    assert abs(0.5 * 0.5 / 14.3625 - sigma) < 1e-7
+    alpha = 0.5 * np.exp(-0.5 * 0.5 / 14.3625)
+    assert abs(alpha - 0.4913721) < 1e-7
+    np.testing.assert_allclose(out["rgb"][0], alpha * pr["rgb"][0], rtol=1e-13)
+    np.testing.assert_allclose(out["T"][0], 1 - alpha, rtol=1e-13)
+
+
+@pytest.mark.parametrize("x_over_z,clamped", [(0.2, False), (1.0, True), (-0.9, True)])
+def test_axis_aligned_offaxis_closed_form(x_over_z, clamped):
+    # identity camera, identity Gaussian rotation, mean (x, 0, z):
+    # J = [[f/z, 0, -f tx/z], [0, f/z, 0]] with tx = x/z clamped to the padded
+    # frustum [-(c/f + 0.15 W/f), (W-c)/f + 0.15 W/f].
+    f, cx, W, z = 300.0, 128.0, 256, 3.0
+    s = np.array([0.04, 0.07, 0.11])
+    x = x_over_z * z
+    sc = _scene([[x], [0.0], [z]], np.log(s)[:, None], [[1.0], [0], [0], [0]], [2.0],
+                np.zeros((1, 3, 1)), 0, _viewmat(np.eye(3), np.zeros(3)),
+                [f, f, cx, 128.0], [W, 256])
+    pr = oracle.project(sc)
+    lim = (W - cx) / f + 0.15 * W / f if x_over_z > 0 else -(cx / f + 0.15 * W / f)
+    tx = lim if clamped else x / z
+    assert (abs(x / z) > abs(lim)) == clamped
+    a = (f / z) ** 2 * s[0] ** 2 + (f * tx / z) ** 2 * s[2] ** 2 + 0.3
+    c = (f / z) ** 2 * s[1] ** 2 + 0.3
+    np.testing.assert_allclose(pr["cov2d"][0], [a, 0, c], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(pr["mean2d"][0], [f * x / z + cx, 128.0], rtol=1e-13)
+
+
+def test_rotated_covariance_against_scipy_rotation():
+    # On the optical axis J = [[f/z,0,0],[0,f/z,0]], so cov2d is the top-left 2x2
+    # of R Rq S^2 Rq^T R^T scaled by (f/z)^2, plus 0.3 I.
+    rng = np.random.default_rng(3)
+    for trial in range(20):
+        R = Rotation.random(random_state=trial + 10).as_matrix()
+        t = rng.normal(size=3)
+        z = rng.uniform(1, 8)
+        q = rng.normal(size=4) * rng.uniform(0.2, 4)
+        s = np.exp(rng.normal(-3, 0.5, size=3))
+        mu = _world_from_cam(R, t, [0, 0, z])
+        sc = _scene(mu[:, None], np.log(s)[:, None], q[:, None], [0.3], np.zeros((1, 3, 1)), 0,
+                    _viewmat(R, t), [500, 400, 320, 240], [640, 480])
+        pr = oracle.project(sc)
+        Rq = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+        Sc = R @ Rq @ np.diag(s ** 2) @ Rq.T @ R.T
+        want = np.array([500 ** 2 * Sc[0, 0] / z ** 2 + 0.3, 500 * 400 * Sc[0, 1] / z ** 2,
+                         400 ** 2 * Sc[1, 1] / z ** 2 + 0.3])
+        np.testing.assert_allclose(pr["cov2d"][0], want, rtol=1e-10, atol=1e-12)
+        np.testing.assert_allclose(pr["depth"][0], z, rtol=1e-12)
+
+
+def test_projection_jacobian_against_finite_differences():
+    # cov2d - 0.3 I = J Sigma_c J^T with J the derivative of the pinhole map.
+    rng = np.random.default_rng(4)
+    fx, fy, cx, cy = 410.0, 380.0, 300.0, 210.0
+    for trial in range(10):
+        R = Rotation.random(random_state=trial + 50).as_matrix()
+        t = rng.normal(size=3)
+        pc = np.array([rng.uniform(-1, 1), rng.uniform(-0.8, 0.8), rng.uniform(2, 6)])
+        q = rng.normal(size=4)
+        s = np.exp(rng.normal(-2.5, 0.5, size=3))
+        sc = _scene(_world_from_cam(R, t, pc)[:, None], np.log(s)[:, None], q[:, None], [0.0],
+                    np.zeros((1, 3, 1)), 0, _viewmat(R, t), [fx, fy, cx, cy], [600, 420])
+        pr = oracle.project(sc)
+
+        def pin(p):
+            return np.array([fx * p[0] / p[2] + cx, fy * p[1] / p[2] + cy])
+        J = np.zeros((2, 3))
+        for k in range(3):
+            e = np.zeros(3); e[k] = 1e-6
+            J[:, k] = (pin(pc + e) - pin(pc - e)) / 2e-6
+        Rq = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+        Sc = R @ Rq @ np.diag(s ** 2) @ Rq.T @ R.T
+        C = J @ Sc @ J.T
+        np.testing.assert_allclose(pr["cov2d"][0], [C[0, 0] + 0.3, C[0, 1], C[1, 1] + 0.3],
+                                   rtol=1e-6, atol=1e-9)
+        np.testing.assert_allclose(pr["mean2d"][0], pin(pc), rtol=1e-12)
+
+
+def test_culling_rules():
+    R, t = np.eye(3), np.zeros(3)
+    means = np.array([[0, 0, 0.005], [0, 0, 3.0], [0, 0, 3.0]]).T
+    logit = [0.0, 0.0, np.log((1 / 255) / (1 - 1 / 255)) - 1e-3]   # 3rd: o < 1/255
+    sc = _scene(means, np.full((3, 3), -3.0), np.tile([[1.0], [0], [0], [0]], 3), logit,
+                np.zeros((1, 3, 3)), 0, _viewmat(R, t), [300, 300, 128, 128], [256, 256])
+    pr = oracle.project(sc)
+    assert list(pr["valid"]) == [0, 1, 0]
+
+
+# ----------------------------------------------------------------- spherical harmonics
+
+def test_sh_low_orders_closed_form():
+    d = np.array([0.3, -0.5, 0.81])
+    d /= np.linalg.norm(d)
+    Y = oracle.sh_basis(1, d)
+    c1 = np.sqrt(3 / (4 * np.pi))
+    np.testing.assert_allclose(Y, [C0, -c1 * d[1], c1 * d[2], -c1 * d[0]], rtol=1e-14)
+
+
+def test_sh_matches_scipy_complex_harmonics():
+    rng = np.random.default_rng(5)
+    for _ in range(25):
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        Y = oracle.sh_basis(3, d)
+        for l in range(4):
+            for m in range(-l, l + 1):
+                assert abs(Y[l * l + l + m] - _cs_real_sh(l, m, d)) < 1e-12, (l, m)
+
+
+def test_sh_orthonormal_by_quadrature():
+    xg, wg = np.polynomial.legendre.leggauss(16)
+    nphi = 32
+    G = np.zeros((16, 16))
+    for z, wz in zip(xg, wg):
+        for k in range(nphi):
+            ph = 2 * np.pi * k / nphi
+            r = np.sqrt(1 - z * z)
+            Y = oracle.sh_basis(3, [r * np.cos(ph), r * np.sin(ph), z])
+            G += wz * (2 * np.pi / nphi) * np.outer(Y, Y)
+    np.testing.assert_allclose(G, np.eye(16), atol=1e-12)
+
+
+def test_sh_gradient_against_finite_differences():
+    rng = np.random.default_rng(6)
+    for _ in range(10):
+        d = rng.normal(size=3)
+        Y, dY = oracle.sh_basis(3, d, grad=True)
+        for k in range(3):
+            e = np.zeros(3); e[k] = 1e-6
+            fd = (oracle.sh_basis(3, d + e) - oracle.sh_basis(3, d - e)) / 2e-6
+            np.testing.assert_allclose(dY[:, k], fd, rtol=1e-6, atol=1e-8)
+
+
+def test_colour_uses_view_direction_from_camera_centre():
+    # Gaussian on the optical axis: the world view direction is the camera's
+    # forward axis, the third row of R.
+    rng = np.random.default_rng(7)
+    R = Rotation.random(random_state=77).as_matrix()
+    t = rng.normal(size=3)
+    sh = rng.normal(0, 0.3, size=(16, 3, 1))
+    sc = _scene(_world_from_cam(R, t, [0, 0, 2.5])[:, None], np.full((3, 1), -3.0),
+                [[1.0], [0], [0], [0]], [0.0], sh, 3, _viewmat(R, t), [300, 300, 128, 128],
+                [256, 256])
+    pr = oracle.project(sc)
+    d = R[2]
+    want = [max(0.0, 0.5 + sum(_cs_real_sh(l, m, d) * sh[l * l + l + m, ch, 0]
+                                for l in range(4) for m in range(-l, l + 1))) for ch in range(3)]
+    np.testing.assert_allclose(pr["rgb"][0], want, rtol=1e-11, atol=1e-13)
+    sh2 = sh.copy()
+    sh2[0] = -10.0                             # colour clamps at 0
+    pr2 = oracle.project(dict(sc, sh=sh2))
+    np.testing.assert_array_equal(pr2["rgb"][0], [0, 0, 0])
+
+
+# ----------------------------------------------------------------- compositing
+
+def _stack_proj(n, alpha, rgb=(0.2, 0.6, 0.9), px=(10.5, 7.5)):
+    """n splats centred on one pixel with opacity alpha (sigma = 0 there)."""
+    return dict(valid=np.ones(n, np.int32), depth=np.linspace(1, 2, n),
+                mean2d=np.tile(px, (n, 1)), conic=np.tile([0.5, 0.0, 0.5], (n, 1)),
+                opacity=np.full(n, alpha), rgb=np.tile(rgb, (n, 1)))
+
+
+@pytest.mark.parametrize("alpha,count", [(0.5, 13), (0.3, 25), (0.7, 7)])
+def test_early_termination_closed_form(alpha, count):
+    # (1-alpha)^count >= 1e-4 > (1-alpha)^(count+1): exactly `count` splats blend.
+    assert (1 - alpha) ** count >= 1e-4 > (1 - alpha) ** (count + 1)
+    n = 40
+    pr = _stack_proj(n, alpha)
+    wh = np.array([[32, 16]], np.int32)
+    out = oracle.render(pr, wh, pix=[7 * 32 + 10])
+    assert out["ncontrib"][0] == count
+    np.testing.assert_allclose(out["T"][0], (1 - alpha) ** count, rtol=1e-13)
+    np.testing.assert_allclose(out["rgb"][0], np.array([0.2, 0.6, 0.9]) * (1 - (1 - alpha) ** count),
+                               rtol=1e-12)
+    assert out["T"][0] >= 1e-4
+
+
+@pytest.mark.parametrize("factor,included", [(1 - 1e-3, False), (1 + 1e-3, True)])
+def test_alpha_gate(factor, included):
+    # o exp(-sigma) = factor / 255 at the pixel
+    o = 0.6
+    sigma = np.log(o * 255 / factor)
+    A = 0.05
+    dx = np.sqrt(2 * sigma / A)
+    pr = dict(valid=np.ones(1, np.int32), depth=np.ones(1), mean2d=np.array([[10.5 + dx, 7.5]]),
+              conic=np.array([[A, 0.0, 0.3]]), opacity=np.array([o]), rgb=np.array([[1.0, 1, 1]]))
+    out = oracle.render(pr, np.array([[64, 16]], np.int32), pix=[7 * 64 + 10])
+    assert out["ngate"][0] == int(included)
+    if included:
+        np.testing.assert_allclose(out["rgb"][0], [factor / 255] * 3, rtol=1e-9)
+    else:
+        np.testing.assert_array_equal(out["rgb"][0], [0, 0, 0])
+
+
+def _small_scene(seed, W=40, H=30, N=60, deg=3, unit_quats=False):
+    import scenegen
+    return scenegen.frustum_scene(seed, W, H, 0.9 * W, 0.9 * W, N, deg, -2.2, 0.4,
+                                  sh_sd=None if deg == 0 else 0.25, unit_quats=unit_quats)
+
+
+def test_partition_of_unity_and_transmittance_bounds():
+    sc = _small_scene(11, N=300, deg=0)
+    pr = oracle.project(sc)
+    pr1 = dict(pr, rgb=np.ones_like(pr["rgb"]))
+    out = oracle.render(pr1, sc["wh"])
+    np.testing.assert_allclose(out["rgb"][:, 0], 1 - out["T"], atol=1e-13)
+    assert np.all(out["T"] >= 1e-4) and np.all(out["T"] <= 1)
+    assert out["ncontrib"].max() > 5
+
+
+def test_result_independent_of_gaussian_order():
+    sc = _small_scene(12, N=200, deg=3)
+    perm = np.random.default_rng(0).permutation(200)
+    sc2 = dict(sc)
+    for k in ("means", "log_scales", "quats"):
+        sc2[k] = sc[k][:, perm]
+    sc2["opacity_logit"] = sc["opacity_logit"][perm]
+    sc2["sh"] = sc["sh"][:, :, perm]
+    a = oracle.render_fwd_bwd(sc)
+    b = oracle.render_fwd_bwd(sc2)
+    np.testing.assert_allclose(a["rgb"], b["rgb"], atol=1e-14)
+
+
+# ----------------------------------------------------------------- gradients
+
+def _loss(sc, w, viewmat=None):
+    out = oracle.render_fwd_bwd(sc, viewmat=viewmat)
+    return float(np.sum(out["rgb"] * w)), out
+
+
+def _clamp_state(out):
+    """Everything that selects a branch: gate counts, contributor counts, the
+    colour clamp and the depth order."""
+    return (out["ncontrib"].copy(), out["ngate"].copy(), (out["proj"]["rgb"] == 0).copy(),
+            np.argsort(out["proj"]["depth"], kind="stable"))
+
+
+def _same_state(a, b):
+    return all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+def test_parameter_gradients_against_central_differences():
+    # 60 Gaussians in a 40x30 view, SH degree 3, non-unit quaternions; a few
+    # large off-screen Gaussians exercise the clamped Jacobian.
+    sc = _small_scene(13, N=60, deg=3)
+    sc = {k: (v.astype(np.float64) if isinstance(v, np.ndarray) and v.dtype == np.float32 else v)
+          for k, v in sc.items()}
+    # push 4 Gaussians outside the padded frustum but big enough to reach the image
+    R = sc["viewmat"][0].reshape(3, 4)[:, :3]
+    t = sc["viewmat"][0].reshape(3, 4)[:, 3]
+    for j, pc in enumerate([[3.2, 0.1, 2.03], [-3.0, 0.2, 2.21], [0.1, 2.6, 2.12], [0.0, -2.5, 1.97]]):
+        sc["means"][:, j] = _world_from_cam(R, t, pc)
+        sc["log_scales"][:, j] = np.log([0.9, 0.9, 0.9])
+    w = np.random.default_rng(1).normal(size=(40 * 30, 3))
+    L0, base = _loss(sc, w)
+    st0 = _clamp_state(base)
+    an = oracle.render_fwd_bwd(sc, v_rgb=w)["grads"]
+    n_checked = 0
+    for key in ("means", "log_scales", "quats", "opacity_logit", "sh"):
+        arr = sc[key]
+        flat = arr.reshape(-1)
+        fd = np.zeros_like(flat)
+        ok = np.zeros(flat.shape, bool)
+        for i in range(flat.size):
+            h = 1e-6 * max(1.0, abs(flat[i]))
+            old = flat[i]
+            flat[i] = old + h
+            Lp, op = _loss(sc, w)
+            flat[i] = old - h
+            Lm, om = _loss(sc, w)
+            flat[i] = old
+            if _same_state(st0, _clamp_state(op)) and _same_state(st0, _clamp_state(om)):
+                fd[i] = (Lp - Lm) / (2 * h)
+                ok[i] = True
+        a = an[key].reshape(-1)
+        scale = np.max(np.abs(a)) + 1e-30
+        err = np.abs(a[ok] - fd[ok])
+        assert ok.mean() > 0.95, key
+        assert np.max(err) <= 1e-6 * scale + 1e-9, (key, np.max(err), scale)
+        n_checked += ok.sum()
+    assert n_checked > 3000
+
+
+def test_pose_twist_gradient_against_central_differences():
+    for deg, seed in ((0, 21), (3, 22)):
+        sc = _small_scene(seed, N=80, deg=deg)
+        w = np.random.default_rng(seed).normal(size=(40 * 30, 3))
+        an = oracle.render_fwd_bwd(sc, v_rgb=w)["grads"]["twist"][0]
+        L0, base = _loss(sc, w)
+        st0 = _clamp_state(base)
+        for k in range(6):
+            xi = np.zeros(6)
+            xi[k] = 1e-6
+            Lp, op = _loss(sc, w, viewmat=_left_perturb(sc["viewmat"][0], xi)[None])
+            Lm, om = _loss(sc, w, viewmat=_left_perturb(sc["viewmat"][0], -xi)[None])
+            assert _same_state(st0, _clamp_state(op)) and _same_state(st0, _clamp_state(om))
+            fd = (Lp - Lm) / 2e-6
+            assert abs(fd - an[k]) <= 1e-6 * np.max(np.abs(an)) + 1e-9, (deg, k, fd, an[k])
+
+
+def test_twist_gauge_identities():
+    # Moving the camera by rho equals moving every Gaussian by R^T rho, so
+    # g_rho = R sum_g dL/dmu_g (any SH degree).  With SH degree 0, turning the
+    # camera by phi equals turning every Gaussian about the camera centre by
+    # omega = R^T phi, so g_phi = R sum_g [(mu_g - c) x dL/dmu_g + dL/domega_g].
+    for deg in (0, 3):
+        sc = dict(_small_scene(30 + deg, N=120, deg=deg, unit_quats=True))
+        # the identities need an exactly orthonormal R (the float32 one is not)
+        M = sc["viewmat"][0].reshape(3, 4).astype(float)
+        U, _, Vt = np.linalg.svd(M[:, :3])
+        sc["viewmat"] = _viewmat(U @ Vt, M[:, 3])[None]
+        sc["quats"] = sc["quats"].astype(float) / np.linalg.norm(sc["quats"].astype(float), axis=0)
+        w = np.random.default_rng(deg).normal(size=(40 * 30, 3))
+        g = oracle.render_fwd_bwd(sc, v_rgb=w)["grads"]
+        M = sc["viewmat"][0].reshape(3, 4).astype(float)
+        R, t = M[:, :3], M[:, 3]
+        vmu = g["means"]                                # [3,N]
+        np.testing.assert_allclose(g["twist"][0, :3], R @ vmu.sum(axis=1),
+                                   rtol=1e-9, atol=1e-12 * np.abs(g["twist"]).max())
+        if deg == 0:
+            c = -R.T @ t
+            mu = sc["means"].astype(float)
+            q = sc["quats"].astype(float)
+            vq = g["quats"]
+            # quaternion left-multiplied by (1, omega/2):  dq = 0.5 (0,omega) (x) q
+            vomega = 0.5 * (-vq[0] * q[1:] + q[0] * vq[1:] + np.cross(q[1:].T, vq[1:].T).T)
+            tot = np.cross((mu - c[:, None]).T, vmu.T).sum(axis=0) + vomega.sum(axis=1)
+            np.testing.assert_allclose(g["twist"][0, 3:], R @ tot, rtol=1e-9,
+                                       atol=1e-12 * np.abs(g["twist"]).max())
+
+
+# ----------------------------------------------------------------- track term
+
+def _track_setup(seed=40, M=60, Pt=20, ncam=3):
+    rng = np.random.default_rng(seed)
+    vms, intr = [], []
+    for i in range(ncam):
+        R = Rotation.random(random_state=seed + i).as_matrix()
+        vms.append(_viewmat(R, rng.normal(size=3)))
+        intr.append([rng.uniform(200, 400), rng.uniform(200, 400), 160.0, 120.0])
+    vms, intr = np.array(vms), np.array(intr)
+    X = np.zeros((Pt, 3))
+    cam = np.sort(rng.integers(0, ncam, size=M))
+    pt = rng.integers(0, Pt, size=M)
+    for k in range(Pt):
+        i = cam[np.nonzero(pt == k)[0][0]] if np.any(pt == k) else 0
+        M3 = vms[i].reshape(3, 4)
+        X[k] = _world_from_cam(M3[:, :3], M3[:, 3], [rng.uniform(-1, 1), rng.uniform(-1, 1), rng.uniform(3, 6)])
+    xy = np.zeros((M, 2))
+    for o in range(M):
+        M3 = vms[cam[o]].reshape(3, 4)
+        p = M3[:, :3] @ X[pt[o]] + M3[:, 3]
+        f = intr[cam[o]]
+        xy[o] = [f[0] * p[0] / p[2] + f[2], f[1] * p[1] / p[2] + f[3]]
+    xy += rng.normal(0, 1.5, size=(M, 2))            # mix of Huber inliers and outliers
+    return X, vms, intr, cam.astype(np.int32), pt.astype(np.int32), xy
+
+
+def test_track_optical_axis_closed_form():
+    vm = _viewmat(np.eye(3), np.zeros(3))
+    for dxy, rho in (((3.0, 4.0), 2 * 5 - 1), ((0.3, 0.4), 0.25)):
+        out = oracle.track(np.array([[0, 0, 5.0]]), vm[None], np.array([[300, 300, 100, 80.0]]),
+                           np.array([0], np.int32), np.array([0], np.int32),
+                           np.array([[100 + dxy[0], 80 + dxy[1]]]), delta=1.0, lam=0.5)
+        np.testing.assert_allclose(out["residual"][0], [-dxy[0], -dxy[1]], atol=1e-12)
+        np.testing.assert_allclose(out["loss"], 0.5 * rho, rtol=1e-12)
+
+
+def test_huber_continuity_at_threshold():
+    vm = _viewmat(np.eye(3), np.zeros(3))
+    vals, slopes = [], []
+    for r in (2.0 - 1e-9, 2.0 + 1e-9):            # delta = 2: |r| = delta
+        out = oracle.track(np.array([[0, 0, 5.0]]), vm[None], np.array([[300, 300, 100, 80.0]]),
+                           np.array([0], np.int32), np.array([0], np.int32),
+                           np.array([[100 + r, 80.0]]), delta=2.0, lam=1.0)
+        vals.append(out["loss"])
+        slopes.append(out["v_X"][0, 0])
+    assert abs(vals[0] - vals[1]) < 1e-7
+    assert abs(slopes[0] - slopes[1]) < 1e-6 * abs(slopes[0])
+
+
+def test_track_gradients_and_jacobians_against_central_differences():
+    X, vms, intr, cam, pt, xy = _track_setup()
+    out = oracle.track(X, vms, intr, cam, pt, xy, delta=1.0, lam=1e-4)
+    assert 0 < np.mean(np.sum(out["residual"] ** 2, 1) <= 1) < 1     # both branches
+    h = 1e-6
+    for k in range(X.shape[0]):
+        for e in range(3):
+            Xp, Xm = X.copy(), X.copy()
+            Xp[k, e] += h
+            Xm[k, e] -= h
+            fd = (oracle.track(Xp, vms, intr, cam, pt, xy)["loss"] -
+                  oracle.track(Xm, vms, intr, cam, pt, xy)["loss"]) / (2 * h)
+            assert abs(fd - out["v_X"][k, e]) <= 1e-6 * np.abs(out["v_X"]).max()
+    for i in range(vms.shape[0]):
+        for k in range(6):
+            xi = np.zeros(6); xi[k] = h
+            vp, vm_ = vms.copy(), vms.copy()
+            vp[i] = _left_perturb(vms[i], xi)
+            vm_[i] = _left_perturb(vms[i], -xi)
+            fd = (oracle.track(X, vp, intr, cam, pt, xy)["loss"] -
+                  oracle.track(X, vm_, intr, cam, pt, xy)["loss"]) / (2 * h)
+            assert abs(fd - out["v_twist"][i, k]) <= 1e-6 * np.abs(out["v_twist"]).max()
+    # Jacobian blocks of the residual
+    for o in range(0, len(cam), 7):
+        i = cam[o]
+        for k in range(6):
+            xi = np.zeros(6); xi[k] = h
+            vp, vm_ = vms.copy(), vms.copy()
+            vp[i] = _left_perturb(vms[i], xi)
+            vm_[i] = _left_perturb(vms[i], -xi)
+            fd = (oracle.track(X, vp, intr, cam, pt, xy)["residual"][o] -
+                  oracle.track(X, vm_, intr, cam, pt, xy)["residual"][o]) / (2 * h)
+            np.testing.assert_allclose(out["J_pose"][o][:, k], fd, rtol=1e-6, atol=1e-6)
+        for e in range(3):
+            Xp, Xm = X.copy(), X.copy()
+            Xp[pt[o], e] += h
+            Xm[pt[o], e] -= h
+            fd = (oracle.track(Xp, vms, intr, cam, pt, xy)["residual"][o] -
+                  oracle.track(Xm, vms, intr, cam, pt, xy)["residual"][o]) / (2 * h)
+            np.testing.assert_allclose(out["J_X"][o][:, e], fd, rtol=1e-6, atol=1e-6)
+
+
+def test_track_single_camera_gauge_and_masking():
+    X, vms, intr, cam, pt, xy = _track_setup(seed=41, ncam=1)
+    out = oracle.track(X, vms, intr, cam, pt, xy, lam=1.0)
+    R = vms[0].reshape(3, 4)[:, :3]
+    np.testing.assert_allclose(out["v_X"].sum(axis=0), R.T @ out["v_twist"][0, :3], rtol=1e-10,
+                               atol=1e-12)
+    # a point behind the camera is masked: no loss, no gradient, counted
+    X2 = X.copy()
+    M3 = vms[0].reshape(3, 4)
+    X2[pt[0]] = _world_from_cam(M3[:, :3], M3[:, 3], [0.1, 0.1, -2.0])
+    out2 = oracle.track(X2, vms, intr, cam, pt, xy, lam=1.0)
+    masked = out2["masked"].astype(bool)
+    assert masked.sum() == np.sum(pt == pt[0])
+    np.testing.assert_array_equal(out2["v_X"][pt[0]], 0)
+
+
+# ----------------------------------------------------------------- SE(3) and Adam
+
+def test_se3_exp_against_scipy():
+    rng = np.random.default_rng(50)
+    for _ in range(10):
+        xi = rng.normal(size=6) * rng.uniform(0.001, 2)
+        base = np.concatenate([Rotation.random(random_state=int(rng.integers(1e6))).as_matrix(),
+                               rng.normal(size=(3, 1))], axis=1).reshape(12)
+        out = oracle.se3_exp_compose(xi, base)[0]
+        np.testing.assert_allclose(out, _left_perturb(base, xi), rtol=1e-12, atol=1e-12)
+        # rotation part is Rodrigues' rotation of the axis-angle phi
+        Rr = Rotation.from_rotvec(xi[3:]).as_matrix() @ base.reshape(3, 4)[:, :3]
+        np.testing.assert_allclose(out.reshape(3, 4)[:, :3], Rr, atol=1e-12)
+
+
+def test_se3_left_jacobian_against_finite_differences():
+    # Exp(xi + d) = Exp(J_l(xi) d) Exp(xi) to first order, so the gradient of a
+    # function of Exp(xi + d) T0 w.r.t. d is J_l(xi)^T times its gradient under a
+    # left perturbation at Exp(xi) T0.
+    rng = np.random.default_rng(51)
+    for _ in range(8):
+        xi = rng.normal(size=6) * rng.uniform(0.01, 1.5)
+        T0 = np.concatenate([Rotation.random(random_state=int(rng.integers(1e6))).as_matrix(),
+                             rng.normal(size=(3, 1))], axis=1).reshape(12)
+        Wt = rng.normal(size=12)
+
+        def f(T):
+            return float(Wt @ T)
+        T = _left_perturb(T0, xi)
+        h = 1e-6
+        g = np.array([(f(_left_perturb(T, h * e)) - f(_left_perturb(T, -h * e))) / (2 * h)
+                      for e in np.eye(6)])
+        gd = np.array([(f(_left_perturb(T0, xi + h * e)) - f(_left_perturb(T0, xi - h * e))) / (2 * h)
+                       for e in np.eye(6)])
+        np.testing.assert_allclose(oracle.se3_jl_transpose(xi, g)[0], gd, rtol=1e-6, atol=1e-7)
+
+
+def test_adam_first_step_and_constant_gradient():
+    rng = np.random.default_rng(52)
+    g = rng.normal(size=100)
+    p = rng.normal(size=100)
+    p0 = p.copy()
+    m = np.zeros(100)
+    v = np.zeros(100)
+    lr, eps = 1e-3, 1e-8
+    oracle.adam(p, g, m, v, lr, eps=eps, step=1)
+    # first step: m_hat = g, v_hat = g^2
+    np.testing.assert_allclose(p, p0 - lr * g / (np.abs(g) + eps), rtol=1e-12)
+    # a constant gradient keeps m_hat = g, v_hat = g^2: every step moves the same
+    for step in range(2, 12):
+        before = p.copy()
+        oracle.adam(p, g, m, v, lr, eps=eps, step=step)
+        np.testing.assert_allclose(before - p, lr * g / (np.abs(g) + eps), rtol=1e-9)
+
+
+# ----------------------------------------------------------------- tile lists
+
+def test_tile_membership_against_dense_sampling():
+    # A pair belongs to a tile iff some point of the tile's pixel-centre
+    # rectangle has alpha >= 1/255.  Brute force: sample the rectangle densely.
+    rng = np.random.default_rng(60)
+    W, H, N = 70, 45, 40
+    mean2d = np.stack([rng.uniform(-10, W + 10, N), rng.uniform(-10, H + 10, N)], 1)
+    cov = []
+    for _ in range(N):
+        A = rng.normal(size=(2, 2)) * rng.uniform(1, 6)
+        cov.append(A @ A.T + 0.3 * np.eye(2))
+    conic = np.array([[c[1, 1], -c[0, 1], c[0, 0]] / np.linalg.det(c) for c in cov])
+    opac = rng.uniform(0.02, 0.99, N)
+    depth = rng.uniform(1, 5, N).astype(np.float32)
+    valid = np.ones(N, np.int32)
+    ranges, ids = oracle.bin_sort(np.array([[W, H]]), (16, 16), valid, mean2d, conic, opac, depth)
+    gx = (W + 15) // 16
+    for t in range(ranges.shape[0]):
+        tx, ty = t % gx, t // gx
+        xs = np.linspace(tx * 16 + 0.5, min(tx * 16 + 16, W) - 0.5, 61)
+        ys = np.linspace(ty * 16 + 0.5, min(ty * 16 + 16, H) - 0.5, 61)
+        X, Y = np.meshgrid(xs, ys)
+        members = set(ids[ranges[t, 0]:ranges[t, 1]].tolist())
+        for g in range(N):
+            dx, dy = mean2d[g, 0] - X, mean2d[g, 1] - Y
+            s = 0.5 * (conic[g, 0] * dx * dx + conic[g, 2] * dy * dy) + conic[g, 1] * dx * dy
+            smin = s.min()
+            thr = np.log(opac[g] * 255)
+            if smin < thr - 1e-6:
+                assert g in members, (t, g)
+            if g in members:
+                assert smin < thr + 0.05 * max(1.0, thr), (t, g)   # the grid is coarse
+        # order: float32 depth bits, then index
+        lst = ids[ranges[t, 0]:ranges[t, 1]]
+        keys = [(depth[i].view(np.uint32), i) for i in lst]
+        assert keys == sorted(keys)
