@@ -1,0 +1,277 @@
+/*
+ * gs.h -- C ABI of the MI355X (gfx950) splatting hot path of GloSplat's joint
+ * pose-appearance step: differentiable tile-based 3D Gaussian splatting
+ * (projection, tile binning and key sort, front-to-back compositing, and its
+ * backward to the Gaussian parameters and to each camera's SE(3) pose), the
+ * track reprojection residual with its Jacobian, the photometric L1 term,
+ * pose composition and the Adam update.
+ *
+ * Paper: GloSplat (arXiv 2603.04847).  The calls follow its statement of the
+ * problem:
+ *   Rasterize(G, T_i, K_i) -> I_i                 Algorithm 1 (render step),
+ *                                                 Sec. 3.3 "Implementation";
+ *   pi(K, T, X) = proj(K (R X + t))               Sec. 3.2 "Bundle Adjustment",
+ *                                                 Appendix D (projection function);
+ *   rho_Huber(||pi_i(X_k) - x_ip||^2; delta)      Sec. 3.3 eq. L_BA^joint;
+ *   L = L_photo + lambda_BA L_BA, poses get both  Sec. 3.3, Algorithm 1
+ *   gradients                                     (backward and update steps);
+ *   T_i = T_i^(0) (+) dT_i                        Algorithm 1 (pose adjustment).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - All buffers are DEVICE pointers (hipMalloc'd or torch CUDA tensors) unless
+ *   marked HOST.  The caller owns every buffer it passes; the library owns only
+ *   the workspace inside a gs_ctx, allocated once by gs_ctx_create.  No call
+ *   allocates, frees, or synchronises the host (except gs_ctx_create/destroy/
+ *   status), so a sequence of calls can be captured in a HIP graph.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *   work of a call is enqueued on it, in order.
+ * - Floats are IEEE binary32.  Gaussian parameters are planar (SoA):
+ *     means[3][N], log_scales[3][N], quats[4][N] (w,x,y,z; need not be unit),
+ *     opacity_logit[N], sh[K][3][N] with K = (deg+1)^2, coefficient index
+ *     l*l + l + m (m = -l..l), real SH with the Condon-Shortley phase.
+ * - Cameras: viewmat[V][12] = world->camera [R|t], 3x4 row-major; camera axes
+ *   x right, y down, z forward.  intr[V][4] = fx, fy, cx, cy (pinhole, no
+ *   skew, no distortion).  wh[V][2] = width, height (HOST).  Pixel (u,v) is
+ *   sampled at (u+0.5, v+0.5).
+ * - Images: views packed view-major, rows y-major, RGB interleaved:
+ *   rgb[sum_v W_v H_v][3].
+ * - Pair index of (view v, Gaussian g) in one call is v*N + g.
+ * - Gradients of the twist are with respect to a LEFT perturbation of the
+ *   current world->camera pose, T <- Exp(xi) T, xi = (rho, phi), translation
+ *   first.  Every twist output ACCUMULATES (+=) so the photometric and the
+ *   reprojection gradients of a pose land in one buffer; the caller zeroes it.
+ * - Errors: host-detectable problems return at once with no work enqueued:
+ *   GS_ERR_INVALID_ARG (null or misaligned pointer, bad size), GS_ERR_CAPACITY
+ *   (a size beyond the context's capacity), GS_ERR_UNSUPPORTED (sh_degree > 3,
+ *   tile shape not offered), GS_ERR_HIP (a launch failed).  Conditions only the
+ *   device sees (too many tile intersections, non-finite inputs, track points
+ *   behind their camera) set flags in the context's status word, read with
+ *   gs_ctx_status after the stream is done; a step that overflowed has
+ *   undefined outputs and must be re-run with a larger capacity.
+ *
+ * Rendering definition (the paper delegates rasterization to an external 3DGS
+ * library and gives no formula; this is the standard EWA-splatting definition):
+ *   p = R mu + t; cull if p_z < near.  Sigma = Rq S S^T Rq^T (S = diag(exp(s))),
+ *   Sigma_c = R Sigma R^T, J = [[fx/z, 0, -fx tx/z], [0, fy/z, -fy ty/z]] with
+ *   tx = x/z clamped to [-(cx/fx + pad W/(2fx)), (W-cx)/fx + pad W/(2fx)] (ty
+ *   alike), Sigma2D = J Sigma_c J^T + eps2d I, conic = Sigma2D^-1,
+ *   mean2d = (fx x/z + cx, fy y/z + cy), o = sigmoid(logit) (cull if
+ *   o <= alpha_min), colour = max(0, sum_lm Y_lm(d) sh_lm + 0.5) with d the unit
+ *   direction from the camera centre -R^T t to mu.
+ *   Per pixel, splats in ascending (float32 depth, pair index) order:
+ *   sigma = 0.5 (A dx^2 + C dy^2) + B dx dy with d = mean2d - pixel centre;
+ *   alpha = min(alpha_max, o exp(-sigma)); skip if alpha < alpha_min; stop
+ *   (excluding this splat) once T (1 - alpha) < T_min; otherwise
+ *   C += colour alpha T, T *= 1 - alpha.  Output C + T bg.
+ */
+#ifndef GLOSPLAT_GS_H
+#define GLOSPLAT_GS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GS_OK = 0,
+    GS_ERR_INVALID_ARG = -1,
+    GS_ERR_CAPACITY = -2,
+    GS_ERR_HIP = -3,
+    GS_ERR_UNSUPPORTED = -4,
+} gs_status;
+
+/* Device status flags (gs_diag.flags). */
+#define GS_FLAG_ISECT_OVERFLOW 1u   /* tile intersections exceeded max_isect */
+#define GS_FLAG_NONFINITE 2u        /* a non-finite projected splat was culled */
+
+/* Most views one render call takes. */
+#define GS_MAX_VIEWS 64
+
+typedef struct gs_ctx gs_ctx;
+
+/* Workspace sizes, fixed at creation. */
+typedef struct {
+    int64_t max_pairs;   /* views x Gaussians per gs_project call */
+    int64_t max_isect;   /* (tile, splat) intersections per gs_bin_sort call */
+    int64_t max_tiles;   /* tiles summed over the views of one call */
+    int32_t max_views;   /* views per call (<= GS_MAX_VIEWS) for twist accumulators */
+    int32_t max_cams;    /* cameras of track_reproj_fwd_bwd (twist accumulators) */
+} gs_capacity;
+
+/* Rendering settings; gs_default_settings fills the reference values. */
+typedef struct {
+    int32_t tile_w, tile_h;   /* 16x16 (default), 16x8, 8x8, 32x16 */
+    float near_plane;         /* 0.01 */
+    float eps2d;              /* 0.3 px^2 dilation of Sigma2D */
+    float fov_pad;            /* 0.3: J clamp at 1.3x the half field of view */
+    float alpha_min;          /* 1/255 */
+    float alpha_max;          /* 0.99 */
+    float t_min;              /* 1e-4 */
+    int32_t grad_accumulate;  /* 0: gs_render_bwd overwrites Gaussian grads; 1: adds */
+    int32_t tile_order;       /* 0: natural tile order; 1: heaviest tiles first */
+} gs_settings;
+
+typedef struct {
+    const float* means;          /* [3][N] */
+    const float* log_scales;     /* [3][N] */
+    const float* quats;          /* [4][N] w,x,y,z */
+    const float* opacity_logit;  /* [N] */
+    const float* sh;             /* [K][3][N] */
+    int32_t N;
+    int32_t sh_degree;           /* 0..3 */
+} gs_gaussians;
+
+typedef struct {
+    float* means;
+    float* log_scales;
+    float* quats;
+    float* opacity_logit;
+    float* sh;
+} gs_gaussians_grad;
+
+typedef struct {
+    const float* viewmat;   /* [V][12] */
+    const float* intr;      /* [V][4] */
+    const int32_t* wh;      /* HOST [V][2] */
+    int32_t V;
+} gs_cameras;
+
+/* Diagnostics read by gs_ctx_status. */
+typedef struct {
+    uint32_t flags;          /* GS_FLAG_* */
+    int64_t n_isect;         /* intersections of the last gs_bin_sort */
+    int64_t n_isect_needed;  /* intersections that call needed (> max_isect on overflow) */
+    int64_t n_masked_obs;    /* observations masked (behind the camera) since reset */
+    int64_t n_visible;       /* pairs with at least one tile in the last gs_bin_sort */
+} gs_diag;
+
+/* A per-step record of the projected splat of each pair, 12 floats (48 B,
+ * 16-B aligned) per pair v*N+g:
+ *   [0] mean2d.x [1] mean2d.y [2] depth (camera z) [3] opacity (<= 0: culled)
+ *   [4] conic A  [5] conic B  [6] conic C          [7] red
+ *   [8] green    [9] blue     [10],[11] unused
+ * gs_project writes it into the context; gs_bin_sort may also be given a
+ * caller-built record array in this layout. */
+#define GS_RECORD_FLOATS 12
+
+/* Per-pair 2D gradient, 9 floats per pair (accumulated by the raster backward):
+ *   d/d(mean2d.x, mean2d.y, conic A, B, C, opacity, red, green, blue). */
+#define GS_GRAD2D_FLOATS 9
+
+const char* gs_strerror(gs_status s);
+void gs_default_settings(gs_settings* s);
+
+/* Create a context: allocates the whole workspace once (device memory of about
+ * 48+36+40 B per pair + 16 B per intersection + 8 B per tile).  *out is NULL on
+ * failure. */
+gs_status gs_ctx_create(gs_ctx** out, const gs_capacity* cap);
+gs_status gs_ctx_destroy(gs_ctx* ctx);
+/* Synchronise the device and read the status word. */
+gs_status gs_ctx_status(gs_ctx* ctx, gs_diag* out);
+/* Clear the status flags and counters (enqueued on stream). */
+gs_status gs_ctx_reset_status(gs_ctx* ctx, void* stream);
+/* Device pointers into the workspace (valid for the context's lifetime):
+ * records [max_pairs][12], sorted pair indices [max_isect], tile ranges
+ * [max_tiles][2] (start, end) int32, and the tile count of the last
+ * gs_bin_sort (HOST value). */
+gs_status gs_ctx_buffers(gs_ctx* ctx, float** records, int32_t** isect_ids,
+                         int32_t** tile_ranges, int64_t* n_tiles);
+
+/* Project every (view, Gaussian) pair (render step of Algorithm 1; the
+ * definition above).  Reads each Gaussian's parameters once for all V views and
+ * writes the V*N records into the context.  Requires V*N <= max_pairs,
+ * V <= max_views, 0 <= sh_degree <= 3. */
+gs_status gs_project(gs_ctx* ctx, const gs_gaussians* g, const gs_cameras* cams,
+                     const gs_settings* s, void* stream);
+
+/* Bin and sort: for every pair, the tiles (tile_w x tile_h) whose pixel-centre
+ * rectangle the splat's alpha >= alpha_min ellipse meets; one (tile, pair)
+ * entry each, then a stable sort so every tile's list is in ascending
+ * (float32 depth, pair) order; tile ranges.  Tiles of view v are numbered
+ * after those of views < v, row-major inside a view.  `records` = NULL uses the
+ * context's records (from gs_project); otherwise a caller array of V*N records
+ * in the layout above.  Overflow of max_isect sets GS_FLAG_ISECT_OVERFLOW. */
+gs_status gs_bin_sort(gs_ctx* ctx, const gs_cameras* cams, int32_t N,
+                      const gs_settings* s, const float* records, void* stream);
+
+/* Forward compositing over the tile lists of the last gs_bin_sort.
+ * bg[3] (device, may be NULL = black).  Outputs rgb[P][3], T_final[P] and
+ * last[P] = 1 + position, within its tile's list, of the pixel's final
+ * contributor (0 if none); P = sum_v W_v H_v.  T_final and last are what the
+ * backward needs (it recomputes the blending state per pixel instead of
+ * storing it). */
+gs_status gs_render_fwd(gs_ctx* ctx, const gs_cameras* cams, const gs_settings* s,
+                        const float* bg, float* rgb, float* T_final, int32_t* last,
+                        void* stream);
+
+/* Backward of gs_project + gs_render_fwd for the image gradient v_rgb[P][3]:
+ * walks each pixel's list back to front from `last`, recovering T by division,
+ * reduces per splat over the wave before any global atomic, then chains the
+ * per-pair 2D gradients to the Gaussian parameters (summed over views; written
+ * or added per s->grad_accumulate) and adds each view's twist gradient into
+ * v_twist[V][6].  `g` and `cams` must be those of the forward. */
+gs_status gs_render_bwd(gs_ctx* ctx, const gs_gaussians* g, const gs_cameras* cams,
+                        const gs_settings* s, const float* bg, const float* T_final,
+                        const int32_t* last, const float* v_rgb, gs_gaussians_grad* grads,
+                        float* v_twist, void* stream);
+
+/* Photometric L1 term (Sec. 3.3 eq. L_photo, its l1 part): loss += mean over
+ * views of the mean over pixels and channels of |rgb - target|; v_rgb =
+ * sign(rgb - target) / (3 P_v V) (sign(0) = 0), overwritten.  loss[1] is a
+ * device float, accumulated. */
+gs_status gs_l1_loss_grad(gs_ctx* ctx, const gs_cameras* cams, const float* rgb,
+                          const float* target, float* v_rgb, float* loss, void* stream);
+
+/* Track reprojection (Sec. 3.3 eq. L_BA^joint; Algorithm 1, joint BA loss):
+ * for each observation o = (camera obs_cam[o], point obs_pt[o], pixel
+ * obs_xy[o][2]):  p = R X + t; masked (no loss, no gradient, counted) if
+ * p_z < near; r = (fx px/pz + cx, fy py/pz + cy) - x; s = |r|^2;
+ * rho(s) = s if s <= delta^2 else 2 delta sqrt(s) - delta^2.
+ *   loss[1]            += lambda sum rho                      (device float)
+ *   v_X[Pt][3]         += d(lambda sum rho)/dX
+ *   v_twist[n_cams][6] += d(lambda sum rho)/dxi               (left twist)
+ *   residual[M][2]      = r                    (may be NULL)
+ *   J_pose[M][2][6]     = dr/dxi, J_X[M][2][3] = dr/dX        (may be NULL)
+ * X[Pt][3] (points, kept separate from the Gaussian means), viewmat[n_cams][12],
+ * intr[n_cams][4].  Observations must be sorted by camera (any order works,
+ * sorted is faster). */
+gs_status track_reproj_fwd_bwd(gs_ctx* ctx, const float* X, int32_t Pt,
+                               const float* viewmat, const float* intr, int32_t n_cams,
+                               const int32_t* obs_cam, const int32_t* obs_pt,
+                               const float* obs_xy, int32_t M, float delta, float lambda,
+                               float near_plane, float* residual, float* loss, float* v_X,
+                               float* v_twist, float* J_pose, float* J_X, void* stream);
+
+/* Pose composition T_i = Exp(dxi_i) T_i^(0) (Algorithm 1, pose adjustment,
+ * with (+) read as left composition): twist[V][6] = (rho, phi), base[V][12],
+ * out[V][12]. */
+gs_status gs_pose_compose(int32_t V, const float* twist, const float* base, float* out,
+                          void* stream);
+
+/* Its backward: out[V][6] = J_l(twist)^T g, with g[V][6] the left-twist
+ * gradient at the composed pose and J_l the SE(3) left Jacobian. */
+gs_status gs_pose_compose_bwd(int32_t V, const float* twist, const float* g, float* out,
+                              void* stream);
+
+/* One Adam step (Algorithm 1, update step) on up to GS_ADAM_MAX_GROUPS
+ * parameter groups in one launch: p -= lr m_hat / (sqrt(v_hat) + eps) with
+ * bias-corrected moments; m, v updated in place. */
+#define GS_ADAM_MAX_GROUPS 16
+typedef struct {
+    float* param;
+    const float* grad;
+    float* exp_avg;
+    float* exp_avg_sq;
+    int64_t n;
+    float lr;
+} gs_adam_group;
+
+gs_status gs_adam_step(const gs_adam_group* groups, int32_t n_groups, int32_t step,
+                       float beta1, float beta2, float eps, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

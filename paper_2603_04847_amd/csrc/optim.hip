@@ -1,0 +1,186 @@
+// Pose composition Exp(xi) T0 and its backward, the multi-tensor Adam step, and
+// small utility kernels (accumulator flush, fill).
+#include "gs_internal.h"
+
+namespace gs {
+
+namespace {
+
+// Coefficients of the SO(3)/SE(3) exponential: A = sin t / t,
+// B = (1 - cos t) / t^2, Cc = (t - sin t) / t^3, by their Taylor series for
+// small angles (where the closed forms cancel catastrophically in float).
+__device__ __forceinline__ void exp_coeffs(float th2, float& A, float& B, float& Cc) {
+    if (th2 < 0.09f) {
+        const float t2 = th2, t4 = t2 * t2, t6 = t4 * t2, t8 = t4 * t4;
+        A = 1.f - t2 / 6.f + t4 / 120.f - t6 / 5040.f + t8 / 362880.f;
+        B = 0.5f - t2 / 24.f + t4 / 720.f - t6 / 40320.f + t8 / 3628800.f;
+        Cc = 1.f / 6.f - t2 / 120.f + t4 / 5040.f - t6 / 362880.f + t8 / 39916800.f;
+    } else {
+        const float th = sqrtf(th2), s = sinf(th), c = cosf(th);
+        A = s / th;
+        B = (1.f - c) / th2;
+        Cc = (th - s) / (th2 * th);
+    }
+}
+
+__device__ __forceinline__ void cross3(const float* a, const float* b, float* c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+__global__ void k_pose_compose(int V, const float* __restrict__ twist, const float* __restrict__ base,
+                               float* __restrict__ out) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    const float* x = twist + 6 * v;
+    const float rho[3] = {x[0], x[1], x[2]}, phi[3] = {x[3], x[4], x[5]};
+    float A, B, Cc;
+    exp_coeffs(phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2], A, B, Cc);
+    // K = [phi]x, K2 = K K
+    const float K[9] = {0.f, -phi[2], phi[1], phi[2], 0.f, -phi[0], -phi[1], phi[0], 0.f};
+    float K2[9];
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++)
+            K2[3 * r + c] = K[3 * r] * K[c] + K[3 * r + 1] * K[3 + c] + K[3 * r + 2] * K[6 + c];
+    float Re[9], Vm[9];
+    for (int i = 0; i < 9; i++) {
+        const float I = (i % 4 == 0) ? 1.f : 0.f;
+        Re[i] = I + A * K[i] + B * K2[i];
+        Vm[i] = I + B * K[i] + Cc * K2[i];
+    }
+    const float* b = base + 12 * v;
+    float* o = out + 12 * v;
+    for (int r = 0; r < 3; r++) {
+        for (int c = 0; c < 3; c++)
+            o[4 * r + c] = Re[3 * r] * b[c] + Re[3 * r + 1] * b[4 + c] + Re[3 * r + 2] * b[8 + c];
+        o[4 * r + 3] = Re[3 * r] * b[3] + Re[3 * r + 1] * b[7] + Re[3 * r + 2] * b[11] +
+                       Vm[3 * r] * rho[0] + Vm[3 * r + 1] * rho[1] + Vm[3 * r + 2] * rho[2];
+    }
+}
+
+// out = J_l(xi)^T g with J_l = sum_n ad_xi^n / (n+1)!, ad_xi = [[phi]x, [rho]x; 0, [phi]x]:
+// (ad^T)(w1, w2) = (w1 x phi, w1 x rho + w2 x phi).
+__global__ void k_pose_compose_bwd(int V, const float* __restrict__ twist, const float* __restrict__ g,
+                                   float* __restrict__ out) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    const float rho[3] = {twist[6 * v], twist[6 * v + 1], twist[6 * v + 2]};
+    const float phi[3] = {twist[6 * v + 3], twist[6 * v + 4], twist[6 * v + 5]};
+    float w1[3] = {g[6 * v], g[6 * v + 1], g[6 * v + 2]};
+    float w2[3] = {g[6 * v + 3], g[6 * v + 4], g[6 * v + 5]};
+    float acc[6] = {w1[0], w1[1], w1[2], w2[0], w2[1], w2[2]};
+    float fact = 1.f;
+    for (int n = 1; n < 30; n++) {
+        float a[3], b1[3], b2[3];
+        cross3(w1, phi, a);
+        cross3(w1, rho, b1);
+        cross3(w2, phi, b2);
+        for (int e = 0; e < 3; e++) {
+            w1[e] = a[e];
+            w2[e] = b1[e] + b2[e];
+        }
+        fact /= (float)(n + 1);
+        for (int e = 0; e < 3; e++) {
+            acc[e] += w1[e] * fact;
+            acc[3 + e] += w2[e] * fact;
+        }
+    }
+    for (int e = 0; e < 6; e++) out[6 * v + e] = acc[e];
+}
+
+struct AdamArgs {
+    float* p[GS_ADAM_MAX_GROUPS];
+    const float* g[GS_ADAM_MAX_GROUPS];
+    float* m[GS_ADAM_MAX_GROUPS];
+    float* v[GS_ADAM_MAX_GROUPS];
+    float lr[GS_ADAM_MAX_GROUPS];
+    int64_t off[GS_ADAM_MAX_GROUPS + 1];
+    int n;
+};
+
+__global__ __launch_bounds__(256) void k_adam(AdamArgs a, float b1, float b2, float eps, float ibc1,
+                                              float ibc2) {
+    const int64_t total = a.off[a.n];
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * 256) {
+        int q = 0;
+        while (q + 1 < a.n && i >= a.off[q + 1]) q++;
+        const int64_t j = i - a.off[q];
+        const float gr = a.g[q][j];
+        const float m = b1 * a.m[q][j] + (1.f - b1) * gr;
+        const float v = b2 * a.v[q][j] + (1.f - b2) * gr * gr;
+        a.m[q][j] = m;
+        a.v[q][j] = v;
+        a.p[q][j] -= a.lr[q] * (m * ibc1) / (sqrtf(v * ibc2) + eps);
+    }
+}
+
+__global__ void k_flush_acc(double* __restrict__ acc, float* __restrict__ out, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        out[i] += (float)acc[i];
+        acc[i] = 0.0;
+    }
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+}  // namespace
+
+hipError_t launch_pose_compose(int V, const float* twist, const float* base, float* out,
+                               hipStream_t st) {
+    if (V <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pose_compose, dim3((V + 63) / 64), dim3(64), 0, st, V, twist, base, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pose_compose_bwd(int V, const float* twist, const float* g, float* out,
+                                   hipStream_t st) {
+    if (V <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pose_compose_bwd, dim3((V + 63) / 64), dim3(64), 0, st, V, twist, g, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(const gs_adam_group* groups, int n, int step, float b1, float b2,
+                       float eps, hipStream_t st) {
+    AdamArgs a{};
+    a.n = n;
+    a.off[0] = 0;
+    for (int q = 0; q < n; q++) {
+        a.p[q] = groups[q].param;
+        a.g[q] = groups[q].grad;
+        a.m[q] = groups[q].exp_avg;
+        a.v[q] = groups[q].exp_avg_sq;
+        a.lr[q] = groups[q].lr;
+        a.off[q + 1] = a.off[q] + groups[q].n;
+    }
+    const int64_t total = a.off[n];
+    if (total <= 0) return hipSuccess;
+    const float ibc1 = (float)(1.0 / (1.0 - pow((double)b1, step)));
+    const float ibc2 = (float)(1.0 / (1.0 - pow((double)b2, step)));
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(256), 0, st, a, b1, b2, eps, ibc1, ibc2);
+    return hipGetLastError();
+}
+
+hipError_t launch_flush_acc(double* acc, float* out, int n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_flush_acc, dim3((n + 255) / 256), dim3(256), 0, st, acc, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+}  // namespace gs

@@ -1,0 +1,260 @@
+// Device-wide exclusive scan and stable LSD radix sort of (u32 key, u32 value)
+// pairs, written for wave64: digit ranks inside a wave come from ballots
+// (match-any over the digit bits), across waves from LDS counters, and each
+// block stages its items in LDS so the global scatter writes contiguous runs.
+#include "gs_internal.h"
+
+namespace gs {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kItems = 16;
+constexpr int kTile = kThreads * kItems;  // 4096 items per block
+constexpr int kWaves = kThreads / kWave;
+
+// ------------------------------------------------------------------ scan
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = __lane_id();
+    for (int off = 1; off < kWave; off <<= 1) {
+        uint32_t t = __shfl_up(v, off, kWave);
+        if (lane >= off) v += t;
+    }
+    return v;
+}
+
+// exclusive scan of one value per thread over the block; returns the block total
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* s_w, uint32_t& total) {
+    const int lane = __lane_id(), w = threadIdx.x / kWave;
+    uint32_t inc = wave_incl_scan(v);
+    if (lane == kWave - 1) s_w[w] = inc;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+    for (int i = 0; i < (int)(blockDim.x / kWave); i++) {
+        if (i < w) before += s_w[i];
+        tot += s_w[i];
+    }
+    __syncthreads();
+    total = tot;
+    return before + inc - v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n,
+                                                          uint32_t* __restrict__ part) {
+    __shared__ uint32_t s_w[kWaves];
+    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kItems; i++) {
+        int64_t j = base + i;
+        if (j < n) s += in[j];
+    }
+    uint32_t tot;
+    block_excl_scan(s, s_w, tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// one block of 1024 threads scans up to 16384 block partials
+__global__ __launch_bounds__(1024) void k_scan_partials(uint32_t* __restrict__ part, int nparts,
+                                                        uint32_t* __restrict__ total_out) {
+    __shared__ uint32_t s_w[16];
+    const int per = (nparts + 1023) / 1024;
+    const int b = threadIdx.x * per;
+    uint32_t loc[16];
+    uint32_t s = 0;
+    for (int i = 0; i < per; i++) {
+        loc[i] = (b + i < nparts) ? part[b + i] : 0u;
+        s += loc[i];
+    }
+    uint32_t tot;
+    uint32_t ex = block_excl_scan(s, s_w, tot);
+    for (int i = 0; i < per; i++) {
+        if (b + i < nparts) part[b + i] = ex;
+        ex += loc[i];
+    }
+    if (threadIdx.x == 0 && total_out) *total_out = tot;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_apply(uint32_t* __restrict__ data, int64_t n,
+                                                         const uint32_t* __restrict__ part) {
+    __shared__ uint32_t s_w[kWaves];
+    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
+    uint32_t v[kItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kItems; i++) {
+        int64_t j = base + i;
+        v[i] = (j < n) ? data[j] : 0u;
+        s += v[i];
+    }
+    uint32_t tot;
+    uint32_t ex = block_excl_scan(s, s_w, tot) + part[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kItems; i++) {
+        int64_t j = base + i;
+        if (j < n) data[j] = ex;
+        ex += v[i];
+    }
+}
+
+// ------------------------------------------------------------------ radix sort
+
+__device__ __forceinline__ uint32_t dev_count(const uint32_t* d_n, int64_t max_n) {
+    if (!d_n) return (uint32_t)max_n;
+    uint32_t n = *d_n;
+    return n < (uint64_t)max_n ? n : (uint32_t)max_n;
+}
+
+// lanes of the wave holding the same 8-bit digit (among lanes with `valid`)
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; b++) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t m = __ballot(bit);
+        peers &= bit ? m : ~m;
+    }
+    return peers;
+}
+
+__global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restrict__ keys,
+                                                         const uint32_t* __restrict__ d_n,
+                                                         int64_t max_n, int shift,
+                                                         uint32_t* __restrict__ hist,
+                                                         uint32_t nblocks) {
+    __shared__ uint32_t s_h[256];
+    const uint32_t n = dev_count(d_n, max_n);
+    s_h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    if (base < n) {
+#pragma unroll 4
+        for (int i = 0; i < kItems; i++) {
+            const int64_t j = base + i * kThreads + threadIdx.x;
+            const bool valid = j < n;
+            const uint32_t d = valid ? (keys[j] >> shift) & 0xFFu : 0u;
+            const uint64_t peers = match_digit(d, valid);
+            if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&s_h[d], (uint32_t)__popcll(peers));
+        }
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = s_h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kThreads) void k_radix_scatter(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+    uint32_t* __restrict__ vout, const uint32_t* __restrict__ d_n, int64_t max_n, int shift,
+    const uint32_t* __restrict__ hist, uint32_t nblocks) {
+    __shared__ uint32_t s_cnt[kWaves][256];
+    __shared__ uint32_t s_run[256];
+    __shared__ uint32_t s_start[256];
+    __shared__ uint32_t s_w[kWaves];
+    __shared__ uint32_t s_key[kTile];
+    __shared__ uint32_t s_val[kTile];
+    const uint32_t n = dev_count(d_n, max_n);
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    if (base >= n) return;  // uniform over the block
+    const int tid = threadIdx.x, w = tid / kWave;
+    uint32_t k[kItems], v[kItems], rank[kItems];
+#pragma unroll
+    for (int i = 0; i < kItems; i++) {
+        const int64_t j = base + i * kThreads + tid;
+        k[i] = j < n ? kin[j] : 0u;
+        v[i] = j < n ? vin[j] : 0u;
+    }
+    for (int r = 0; r < kWaves; r++) s_cnt[r][tid] = 0;
+    s_run[tid] = 0;
+    __syncthreads();
+    for (int i = 0; i < kItems; i++) {
+        const int64_t j = base + i * kThreads + tid;
+        const bool valid = j < n;
+        const uint32_t d = (k[i] >> shift) & 0xFFu;
+        const uint64_t peers = match_digit(d, valid);
+        const uint32_t wr = __popcll(peers & lanemask_lt());
+        if (valid && wr == 0) s_cnt[w][d] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t r = s_run[d] + wr;
+            for (int q = 0; q < w; q++) r += s_cnt[q][d];
+            rank[i] = r;
+        }
+        __syncthreads();
+        {
+            uint32_t add = 0;
+            for (int q = 0; q < kWaves; q++) {
+                add += s_cnt[q][tid];
+                s_cnt[q][tid] = 0;
+            }
+            s_run[tid] += add;
+        }
+        __syncthreads();
+    }
+    uint32_t tot;
+    s_start[tid] = block_excl_scan(s_run[tid], s_w, tot);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kItems; i++) {
+        const int64_t j = base + i * kThreads + tid;
+        if (j < n) {
+            const uint32_t d = (k[i] >> shift) & 0xFFu;
+            const uint32_t pos = s_start[d] + rank[i];
+            s_key[pos] = k[i];
+            s_val[pos] = v[i];
+        }
+    }
+    __syncthreads();
+    const uint32_t cnt = (uint32_t)min((int64_t)kTile, (int64_t)n - base);
+#pragma unroll
+    for (int i = 0; i < kItems; i++) {
+        const uint32_t j = i * kThreads + tid;
+        if (j < cnt) {
+            const uint32_t key = s_key[j];
+            const uint32_t d = (key >> shift) & 0xFFu;
+            const uint32_t g = hist[(int64_t)d * nblocks + blockIdx.x] + (j - s_start[d]);
+            kout[g] = key;
+            vout[g] = s_val[j];
+        }
+    }
+}
+
+}  // namespace
+
+size_t scan_scratch_words(int64_t max_n) { return (size_t)((max_n + kTile - 1) / kTile) + 16; }
+
+hipError_t exclusive_scan_u32(uint32_t* data, int64_t n, uint32_t* total_out, uint32_t* scratch,
+                              hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t nb = (n + kTile - 1) / kTile;
+    if (nb > 16384) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kThreads), 0, st, data, n, scratch);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, scratch, (int)nb, total_out);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kThreads), 0, st, data, n, scratch);
+    return hipGetLastError();
+}
+
+size_t radix_hist_words(int64_t max_n) { return (size_t)256 * ((max_n + kTile - 1) / kTile) + 16; }
+
+int radix_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_t max_n,
+                     const uint32_t* d_n, int lo, int hi, uint32_t* hist, uint32_t* scan_scratch,
+                     hipStream_t st, hipError_t* err) {
+    *err = hipSuccess;
+    if (max_n <= 0) return 0;
+    const uint32_t nb = (uint32_t)((max_n + kTile - 1) / kTile);
+    int cur = 0;
+    uint32_t* K[2] = {ka, kb};
+    uint32_t* Vv[2] = {va, vb};
+    for (int shift = lo; shift < hi; shift += 8) {
+        hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kThreads), 0, st, K[cur], d_n, max_n, shift,
+                           hist, nb);
+        hipError_t e = exclusive_scan_u32(hist, (int64_t)256 * nb, nullptr, scan_scratch, st);
+        if (e != hipSuccess) { *err = e; return cur; }
+        hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kThreads), 0, st, K[cur], Vv[cur],
+                           K[cur ^ 1], Vv[cur ^ 1], d_n, max_n, shift, hist, nb);
+        cur ^= 1;
+    }
+    *err = hipGetLastError();
+    return cur;
+}
+
+}  // namespace gs

@@ -1,0 +1,162 @@
+// Track reprojection residual, Huber loss and their gradients / Jacobian blocks.
+//
+// One thread per observation.  Observations arrive sorted by camera, so most
+// waves see a single camera: their twist gradients are summed over the wave
+// (DPP) and land in one double atomic per component; a wave that straddles a
+// camera boundary falls back to per-lane atomics.  Track-point gradients are
+// scattered with three float atomics per observation (points are spread, so
+// these rarely collide).
+#include "gs_internal.h"
+
+namespace gs {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__global__ __launch_bounds__(kBlock) void k_track(
+    const float* __restrict__ X, int Pt, const float* __restrict__ viewmat,
+    const float* __restrict__ intr, int n_cams, const int32_t* __restrict__ obs_cam,
+    const int32_t* __restrict__ obs_pt, const float* __restrict__ obs_xy, int M, float delta,
+    float lambda, float near_plane, float* __restrict__ residual, float* __restrict__ v_X,
+    float* __restrict__ J_pose, float* __restrict__ J_X, double* __restrict__ twist_acc,
+    double* __restrict__ loss_acc, uint32_t* __restrict__ diag) {
+    const int o = blockIdx.x * kBlock + threadIdx.x;
+    const bool in = o < M;
+    int ci = 0, k = 0;
+    if (in) {
+        ci = obs_cam[o];
+        k = obs_pt[o];
+    }
+    const bool ok_idx = in && ci >= 0 && ci < n_cams && k >= 0 && k < Pt;
+    float tw[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float lo = 0.f;
+    bool masked = false;
+    if (ok_idx) {
+        float R[9], t[3];
+#pragma unroll
+        for (int r = 0; r < 3; r++) {
+#pragma unroll
+            for (int c = 0; c < 3; c++) R[3 * r + c] = viewmat[12 * ci + 4 * r + c];
+            t[r] = viewmat[12 * ci + 4 * r + 3];
+        }
+        const float fx = intr[4 * ci], fy = intr[4 * ci + 1], cx = intr[4 * ci + 2],
+                    cy = intr[4 * ci + 3];
+        const float Xk[3] = {X[3 * (int64_t)k], X[3 * (int64_t)k + 1], X[3 * (int64_t)k + 2]};
+        float p[3];
+#pragma unroll
+        for (int r = 0; r < 3; r++) p[r] = R[3 * r] * Xk[0] + R[3 * r + 1] * Xk[1] + R[3 * r + 2] * Xk[2] + t[r];
+        masked = !(p[2] >= near_plane);
+        if (masked) {
+            if (residual) {
+                residual[2 * (int64_t)o] = 0.f;
+                residual[2 * (int64_t)o + 1] = 0.f;
+            }
+            if (J_pose)
+                for (int e = 0; e < 12; e++) J_pose[12 * (int64_t)o + e] = 0.f;
+            if (J_X)
+                for (int e = 0; e < 6; e++) J_X[6 * (int64_t)o + e] = 0.f;
+        } else {
+            const float iz = 1.f / p[2];
+            const float u = p[0] * iz, w = p[1] * iz;
+            const float r0 = fx * u + cx - obs_xy[2 * (int64_t)o];
+            const float r1 = fy * w + cy - obs_xy[2 * (int64_t)o + 1];
+            const float s = r0 * r0 + r1 * r1;
+            float rho, drho;
+            if (s <= delta * delta) {
+                rho = s;
+                drho = 1.f;
+            } else {
+                const float rs = sqrtf(s);
+                rho = 2.f * delta * rs - delta * delta;
+                drho = delta / rs;
+            }
+            lo = lambda * rho;
+            // J_pi (2x3) = [[fx/z, 0, -fx x/z^2], [0, fy/z, -fy y/z^2]]
+            const float j00 = fx * iz, j02 = -fx * u * iz, j11 = fy * iz, j12 = -fy * w * iz;
+            const float g0 = 2.f * lambda * drho * r0, g1 = 2.f * lambda * drho * r1;
+            const float vp[3] = {j00 * g0, j11 * g1, j02 * g0 + j12 * g1};
+            if (v_X) {
+#pragma unroll
+                for (int c = 0; c < 3; c++)
+                    atomicAdd(v_X + 3 * (int64_t)k + c, R[c] * vp[0] + R[3 + c] * vp[1] + R[6 + c] * vp[2]);
+            }
+            tw[0] = vp[0];
+            tw[1] = vp[1];
+            tw[2] = vp[2];
+            tw[3] = p[1] * vp[2] - p[2] * vp[1];
+            tw[4] = p[2] * vp[0] - p[0] * vp[2];
+            tw[5] = p[0] * vp[1] - p[1] * vp[0];
+            if (residual) {
+                residual[2 * (int64_t)o] = r0;
+                residual[2 * (int64_t)o + 1] = r1;
+            }
+            if (J_pose) {
+                // dr/dxi = J_pi [I | -[p]x]
+                float* Jp = J_pose + 12 * (int64_t)o;
+                Jp[0] = j00; Jp[1] = 0.f; Jp[2] = j02;
+                Jp[3] = j02 * p[1];
+                Jp[4] = j00 * p[2] - j02 * p[0];
+                Jp[5] = -j00 * p[1];
+                Jp[6] = 0.f; Jp[7] = j11; Jp[8] = j12;
+                Jp[9] = -j11 * p[2] + j12 * p[1];
+                Jp[10] = -j12 * p[0];
+                Jp[11] = j11 * p[0];
+            }
+            if (J_X) {
+                float* Jx = J_X + 6 * (int64_t)o;
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    Jx[c] = j00 * R[c] + j02 * R[6 + c];
+                    Jx[3 + c] = j11 * R[3 + c] + j12 * R[6 + c];
+                }
+            }
+        }
+    }
+    // loss: wave sum, one double atomic per wave
+    const float ls = wave_sum(lo);
+    const int lane = __lane_id();
+    if (lane == 0 && ls != 0.f) atomicAdd(loss_acc, (double)ls);
+    const uint64_t mm = __ballot(ok_idx && masked);
+    if (lane == 0 && mm) atomicAdd(&diag[kDiagMasked], (uint32_t)__popcll(mm));
+    // twist: one camera for the whole wave is the common case
+    const uint64_t live = __ballot(ok_idx);
+    if (live == 0) return;
+    const int first = __builtin_ctzll(live);
+    const int c0 = bcast(ci, first);
+    const bool uniform = __ballot(ok_idx && ci != c0) == 0;
+    if (uniform) {
+#pragma unroll
+        for (int e = 0; e < 6; e++) {
+            const float s = wave_sum(tw[e]);
+            if (lane == e && s != 0.f) atomicAdd(twist_acc + 6 * (int64_t)c0 + e, (double)s);
+        }
+    } else if (ok_idx && !masked) {
+#pragma unroll
+        for (int e = 0; e < 6; e++) atomicAdd(twist_acc + 6 * (int64_t)ci + e, (double)tw[e]);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_track(Ctx* c, const float* X, int Pt, const float* viewmat, const float* intr,
+                        int n_cams, const int32_t* obs_cam, const int32_t* obs_pt,
+                        const float* obs_xy, int M, float delta, float lambda, float near_plane,
+                        float* residual, float* loss, float* v_X, float* v_twist, float* J_pose,
+                        float* J_X, hipStream_t st) {
+    if (M > 0) {
+        hipLaunchKernelGGL(k_track, dim3((M + kBlock - 1) / kBlock), dim3(kBlock), 0, st, X, Pt,
+                           viewmat, intr, n_cams, obs_cam, obs_pt, obs_xy, M, delta, lambda,
+                           near_plane, residual, v_X, J_pose, J_X, c->twist_track,
+                           c->loss_acc + 1, c->diag);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipSuccess;
+    if (v_twist && (e = launch_flush_acc(c->twist_track, v_twist, 6 * n_cams, st)) != hipSuccess)
+        return e;
+    if (loss) return launch_flush_acc(c->loss_acc + 1, loss, 1, st);
+    return hipSuccess;
+}
+
+}  // namespace gs

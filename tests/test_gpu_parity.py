@@ -1,0 +1,354 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Rule for floating point: per tensor group, max|gpu - oracle| <= 1e-4 * max|oracle|
+(images: 1e-4 * max(max|oracle|, 1)), over pixels the oracle does not flag as
+ambiguous (a gate, clamp, stop or depth-order decision within float32 error of
+its threshold).  Integer and index results are compared bit-exactly.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def gs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_04847_amd as P
+    P.load()
+    return P
+
+
+def _t(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype)
+
+
+def _params(scene):
+    return {k: _t(scene[k]) for k in ("means", "log_scales", "quats", "opacity_logit", "sh")}
+
+
+def _ctx(gs, scene, max_isect=4_000_000, views=None, max_cams=8):
+    N = scene["means"].shape[1]
+    V = scene["viewmat"].shape[0] if views is None else views
+    return gs.Context(max_pairs=V * N, max_isect=max_isect, max_tiles=200_000, max_views=max(V, 1),
+                      max_cams=max_cams)
+
+
+def _render(gs, scene, ctx=None, settings=None, bg=None):
+    from paper_2603_04847_amd.splat import Splatter
+    ctx = ctx or _ctx(gs, scene)
+    sp = Splatter(ctx, settings or gs.default_settings(), bg)
+    params = _params(scene)
+    rgb, T, last, cams = sp.forward(params, scene["sh_degree"], _t(scene["viewmat"]),
+                                    _t(scene["intr"]), scene["wh"])
+    torch.cuda.synchronize()
+    return sp, params, rgb, T, last, cams, ctx
+
+
+def _close(a, b, scale=None, rtol=RTOL, what=""):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    s = np.max(np.abs(b)) if scale is None else scale
+    err = np.max(np.abs(a - b)) if a.size else 0.0
+    assert err <= rtol * max(s, 1e-30), f"{what}: max err {err:.3e} vs tol {rtol * s:.3e}"
+
+
+def _parity_scene(seed=101, W=203, H=150, N=3000, deg=3):
+    # ragged: 203 = 12*16 + 11, 150 = 9*16 + 6
+    return scenegen.frustum_scene(seed, W, H, 1.1719 * W, 1.1719 * W, N, deg, -3.3, 0.6,
+                                  sh_sd=0.2, unit_quats=False)
+
+
+# ------------------------------------------------------------------ projection
+
+def test_project_matches_oracle(gs):
+    sc = _parity_scene()
+    sp, params, rgb, T, last, cams, ctx = _render(gs, sc)
+    N = sc["means"].shape[1]
+    rec_host = gs._lib.copy_to_host(ctx.buffers()["records"], N * 12, np.float32).reshape(N, 12)
+    pr = oracle.project(sc)
+    valid = pr["valid"].astype(bool)
+    gvalid = rec_host[:, 3] > 0
+    assert np.array_equal(valid, gvalid)
+    _close(rec_host[valid, 0:2], pr["mean2d"][valid], what="mean2d")
+    _close(rec_host[valid, 2], pr["depth"][valid], what="depth")
+    _close(rec_host[valid, 3], pr["opacity"][valid], what="opacity")
+    _close(rec_host[valid, 4:7], pr["conic"][valid], what="conic")
+    _close(rec_host[valid][:, [7, 8, 9]], pr["rgb"][valid], what="rgb")
+
+
+# ------------------------------------------------------------------ bin / sort
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 16)])
+def test_bin_sort_bit_exact_on_synthetic_records(gs, tile):
+    wh = np.array([[203, 150], [64, 48], [130, 77]], np.int32)
+    N = 700
+    r = scenegen.synthetic_records(7, 3, wh, N, tile=tile)
+    rec = np.zeros((3 * N, 12), np.float32)
+    rec[:, 0:2] = r["mean2d"]
+    rec[:, 2] = r["depth"]
+    rec[:, 3] = np.where(r["valid"] > 0, r["opacity"], 0.0)
+    rec[:, 4:7] = r["conic"]
+    rec[:, 7:10] = r["rgb"]
+    ctx = gs.Context(max_pairs=3 * N, max_isect=2_000_000, max_tiles=100_000, max_views=3)
+    s = gs.default_settings(tile_w=tile[0], tile_h=tile[1])
+    cams = gs.Cameras(_t(np.zeros((3, 12))), _t(np.zeros((3, 4))), wh)
+    drec = _t(rec)
+    gs.gs_bin_sort(ctx, cams, N, s, drec)
+    st = ctx.status()
+    assert st["flags"] == 0
+    ranges_o, ids_o = oracle.bin_sort(wh, tile, r["valid"], r["mean2d"], r["conic"],
+                                      r["opacity"], r["depth"])
+    assert st["n_isect"] == len(ids_o)
+    b = ctx.buffers()
+    T = b["n_tiles"]
+    assert T == ranges_o.shape[0]
+    ranges = _read_i32(b["tile_ranges"], 2 * T).reshape(T, 2)
+    ids = _read_i32(b["isect_ids"], len(ids_o))
+    assert np.array_equal(ranges, ranges_o.astype(np.int32))
+    assert np.array_equal(ids, ids_o)
+
+
+def _read_i32(ptr, n):
+    import paper_2603_04847_amd._lib as L
+    return L.copy_to_host(ptr, n, np.int32)
+
+
+def test_bin_sort_real_scene_lists(gs):
+    # Membership: every (tile, splat) the exact float64 test keeps with some
+    # room to spare is listed; nothing listed is far outside.  Order: each
+    # list is ascending in (gpu float32 depth, pair).
+    sc = _parity_scene(seed=5, N=1500)
+    sp, params, rgb, T, last, cams, ctx = _render(gs, sc)
+    st = ctx.status()
+    b = ctx.buffers()
+    nt = b["n_tiles"]
+    ranges = _read_i32(b["tile_ranges"], 2 * nt).reshape(nt, 2)
+    ids = _read_i32(b["isect_ids"], st["n_isect"])
+    pr = oracle.project(sc)
+    inner_r, inner = oracle.bin_sort(sc["wh"], (16, 16), pr["valid"], pr["mean2d"], pr["conic"],
+                                     pr["opacity"], pr["depth"].astype(np.float32), margin=-0.05)
+    outer_r, outer = oracle.bin_sort(sc["wh"], (16, 16), pr["valid"], pr["mean2d"], pr["conic"],
+                                     pr["opacity"], pr["depth"].astype(np.float32), margin=0.05)
+    depth = pr["depth"]
+    for t in range(nt):
+        g = ids[ranges[t, 0]:ranges[t, 1]]
+        gi = set(inner[inner_r[t, 0]:inner_r[t, 1]].tolist())
+        go = set(outer[outer_r[t, 0]:outer_r[t, 1]].tolist())
+        assert gi <= set(g.tolist()) <= go, t
+        d = depth[g]
+        assert np.all(np.diff(d) >= -1e-6 * np.abs(d[1:])), t
+
+
+# ------------------------------------------------------------------ forward
+
+@pytest.mark.parametrize("name", ["parity", "C1"])
+def test_render_fwd_matches_oracle(gs, name):
+    sc = _parity_scene() if name == "parity" else scenegen.make_config("C1")
+    sp, params, rgb, T, last, cams, ctx = _render(gs, sc)
+    o = oracle.render_fwd_bwd(sc)
+    amb = o["ambiguous"]
+    assert amb.mean() < 0.02, amb.mean()
+    ok = ~amb
+    g = rgb.cpu().numpy()
+    _close(g[ok], o["rgb"][ok], scale=max(1.0, np.abs(o["rgb"]).max()), what="rgb")
+    _close(T.cpu().numpy()[ok], o["T"][ok], scale=1.0, what="T_final")
+
+
+def test_render_fwd_bitwise_independent_of_tile_shape(gs):
+    sc = _parity_scene(seed=9)
+    outs = []
+    for tw, th in [(16, 16), (16, 8), (8, 8), (32, 16)]:
+        s = gs.default_settings(tile_w=tw, tile_h=th)
+        outs.append(_render(gs, sc, settings=s)[2].cpu().numpy())
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_batched_views_bitwise_equal_per_view(gs):
+    s = scenegen.blob_scene(11, [(160, 120), (203, 150), (96, 64)], 20000, sh_degree=3)
+    s.pop("_rng")
+    batched = _render(gs, s)[2].cpu().numpy()
+    per = []
+    ctx = _ctx(gs, s)
+    for v in range(3):
+        sv = dict(s, viewmat=s["viewmat"][v:v + 1], intr=s["intr"][v:v + 1], wh=s["wh"][v:v + 1])
+        per.append(_render(gs, sv, ctx=ctx)[2].cpu().numpy())
+    assert np.array_equal(batched, np.concatenate(per))
+
+
+def test_background_colour(gs):
+    sc = _parity_scene(seed=12, N=500)
+    bg = _t(np.array([0.2, 0.5, 0.9]))
+    sp, params, rgb, T, last, cams, ctx = _render(gs, sc, bg=bg)
+    o = oracle.render_fwd_bwd(sc, bg=np.array([0.2, 0.5, 0.9]))
+    ok = ~o["ambiguous"]
+    _close(rgb.cpu().numpy()[ok], o["rgb"][ok], scale=1.0, what="rgb with bg")
+
+
+# ------------------------------------------------------------------ backward
+
+def _backward_case(gs, sc, bg=None, seed=0):
+    sp, params, rgb, T, last, cams, ctx = _render(gs, sc, bg=None if bg is None else _t(bg))
+    P = cams.n_pixels
+    o = oracle.render_fwd_bwd(sc, bg=bg)
+    w = np.random.default_rng(seed).normal(size=(P, 3))
+    w[o["ambiguous"]] = 0.0
+    grads, v_tw = sp.backward(params, sc["sh_degree"], cams, T, last, _t(w))
+    torch.cuda.synchronize()
+    og = oracle.render_fwd_bwd(sc, v_rgb=w, bg=bg)["grads"]
+    return grads, v_tw, og
+
+
+@pytest.mark.parametrize("name", ["parity", "C1"])
+def test_render_bwd_matches_oracle(gs, name):
+    sc = _parity_scene(seed=21) if name == "parity" else scenegen.make_config("C1")
+    grads, v_tw, og = _backward_case(gs, sc)
+    K = (sc["sh_degree"] + 1) ** 2
+    for k in ("means", "log_scales", "quats", "opacity_logit"):
+        _close(grads[k].cpu().numpy(), og[k], what=k)
+    sh = grads["sh"].cpu().numpy()
+    for l in range(sc["sh_degree"] + 1):
+        band = slice(l * l, (l + 1) * (l + 1))
+        _close(sh[band], og["sh"][band], what=f"sh band {l}")
+    assert K == sh.shape[0]
+    tw = v_tw.cpu().numpy()
+    for v in range(tw.shape[0]):
+        _close(tw[v], og["twist"][v], what=f"twist view {v}")
+
+
+def test_render_bwd_batched_views(gs):
+    s = scenegen.blob_scene(31, [(128, 96), (203, 150)], 6000, sh_degree=2)
+    s.pop("_rng")
+    grads, v_tw, og = _backward_case(gs, s, bg=np.array([0.1, 0.3, 0.2]), seed=3)
+    for k in ("means", "log_scales", "quats", "opacity_logit", "sh"):
+        _close(grads[k].cpu().numpy(), og[k], what=k)
+    _close(v_tw.cpu().numpy()[0], og["twist"][0], what="twist 0")
+    _close(v_tw.cpu().numpy()[1], og["twist"][1], what="twist 1")
+
+
+# ------------------------------------------------------------------ L1, track, pose, Adam
+
+def test_l1_loss_grad(gs):
+    rng = np.random.default_rng(4)
+    wh = np.array([[40, 30], [17, 9]], np.int32)
+    P = int((wh[:, 0] * wh[:, 1]).sum())
+    a = rng.uniform(size=(P, 3)).astype(np.float32)
+    b = rng.uniform(size=(P, 3)).astype(np.float32)
+    b[:10] = a[:10]  # exact ties: sign(0) = 0
+    ctx = gs.Context(max_pairs=1, max_isect=1, max_tiles=16, max_views=2)
+    cams = gs.Cameras(_t(np.zeros((2, 12))), _t(np.zeros((2, 4))), wh)
+    v = torch.empty((P, 3), device="cuda")
+    loss = torch.zeros(1, device="cuda")
+    gs.gs_l1_loss_grad(ctx, cams, _t(a), _t(b), v, loss)
+    d = a.astype(np.float64) - b
+    pv = np.repeat(wh[:, 0] * wh[:, 1], wh[:, 0] * wh[:, 1])[:, None]
+    want_v = np.sign(d) / (3 * pv * 2)
+    want_l = np.mean([np.abs(d[:1200]).mean(), np.abs(d[1200:]).mean()])
+    _close(v.cpu().numpy(), want_v, what="v_rgb")
+    assert abs(loss.item() - want_l) <= 1e-5 * want_l
+
+
+def test_track_matches_oracle(gs):
+    sc = scenegen.make_config("C1")
+    X = sc["X"].copy()
+    vm, intr = sc["track_viewmat"], sc["track_intr"]
+    # one point pushed behind camera 0 -> its observations there are masked
+    M3 = vm[0].reshape(3, 4).astype(np.float64)
+    X[0] = M3[:, :3].T @ (np.array([0.1, 0.2, -3.0]) - M3[:, 3])
+    ctx = gs.Context(max_pairs=1, max_isect=1, max_tiles=16, max_views=1, max_cams=8)
+    o = oracle.track(X, vm, intr, sc["obs_cam"], sc["obs_pt"], sc["obs_xy"], delta=1.0, lam=1e-4)
+    M = len(sc["obs_cam"])
+    loss = torch.zeros(1, device="cuda")
+    v_X = torch.zeros((X.shape[0], 3), device="cuda")
+    v_tw = torch.zeros((5, 6), device="cuda")
+    res = torch.empty((M, 2), device="cuda")
+    Jp = torch.empty((M, 12), device="cuda")
+    Jx = torch.empty((M, 6), device="cuda")
+    ctx.reset_status()
+    gs.track_reproj_fwd_bwd(ctx, _t(X), _t(vm), _t(intr), _t(sc["obs_cam"], torch.int32),
+                            _t(sc["obs_pt"], torch.int32), _t(sc["obs_xy"]), 1.0, 1e-4, 0.01,
+                            loss, v_X, v_tw, residual=res, J_pose=Jp, J_X=Jx)
+    st = ctx.status()
+    assert st["n_masked_obs"] == int(o["masked"].sum()) > 0
+    _close(res.cpu().numpy(), o["residual"], what="residual")
+    assert abs(loss.item() - o["loss"]) <= RTOL * o["loss"]
+    _close(v_X.cpu().numpy(), o["v_X"], what="v_X")
+    for v in range(5):
+        _close(v_tw.cpu().numpy()[v], o["v_twist"][v], what=f"twist {v}")
+    _close(Jp.cpu().numpy().reshape(M, 2, 6), o["J_pose"], what="J_pose")
+    _close(Jx.cpu().numpy().reshape(M, 2, 3), o["J_X"], what="J_X")
+
+
+def test_pose_compose_and_backward(gs):
+    rng = np.random.default_rng(8)
+    V = 7
+    xi = rng.normal(size=(V, 6)) * np.array([0.01, 0.01, 0.01, 0.003, 0.003, 0.003])
+    xi[0] *= 0
+    xi[1] *= 100          # a large twist takes the closed-form branch
+    from scipy.spatial.transform import Rotation
+    base = np.stack([np.concatenate([Rotation.random(random_state=i).as_matrix(),
+                                     rng.normal(size=(3, 1))], 1).reshape(12) for i in range(V)])
+    out = torch.empty((V, 12), device="cuda")
+    gs.gs_pose_compose(_t(xi), _t(base), out)
+    want = oracle.se3_exp_compose(xi.astype(np.float32), base.astype(np.float32))
+    _close(out.cpu().numpy(), want, what="Exp(xi) T0")
+    g = rng.normal(size=(V, 6))
+    outg = torch.empty((V, 6), device="cuda")
+    gs.gs_pose_compose_bwd(_t(xi), _t(g), outg)
+    wantg = oracle.se3_jl_transpose(xi.astype(np.float32), g.astype(np.float32))
+    _close(outg.cpu().numpy(), wantg, what="J_l^T g")
+
+
+def test_adam_matches_oracle(gs):
+    rng = np.random.default_rng(9)
+    sizes = [1000, 37, 5000]
+    lrs = [1e-3, 5e-2, 2.5e-3]
+    ps = [rng.normal(size=n) for n in sizes]
+    dev = [[_t(p), None, torch.zeros(len(p), device="cuda"), torch.zeros(len(p), device="cuda")]
+           for p in ps]
+    ref = [[p.astype(np.float32).astype(np.float64), np.zeros(len(p)), np.zeros(len(p))] for p in ps]
+    for step in range(1, 4):
+        gr = [rng.normal(size=n).astype(np.float32) for n in sizes]
+        groups = []
+        for q in range(3):
+            dev[q][1] = _t(gr[q])
+            groups.append((dev[q][0], dev[q][1], dev[q][2], dev[q][3], lrs[q]))
+            oracle.adam(ref[q][0], gr[q].astype(np.float64), ref[q][1], ref[q][2], lrs[q],
+                        eps=1e-8, step=step)
+        gs.gs_adam_step(groups, step, eps=1e-8)
+    for q in range(3):
+        d = dev[q][0].cpu().numpy() - ref[q][0]
+        assert np.max(np.abs(d)) <= 1e-6 + 1e-5 * lrs[q] * 3
+
+
+# ------------------------------------------------------------------ error paths
+
+def test_capacity_overflow_is_flagged(gs):
+    sc = _parity_scene(seed=40, N=800)
+    ctx = _ctx(gs, sc, max_isect=100)
+    _render(gs, sc, ctx=ctx)
+    st = ctx.status()
+    assert st["flags"] & 1
+    assert st["n_isect_needed"] > 100 and st["n_isect"] == 0
+
+
+def test_host_argument_errors(gs):
+    sc = _parity_scene(seed=41, N=100)
+    ctx = _ctx(gs, sc)
+    with pytest.raises(gs.GsError) as e:
+        _render(gs, sc, ctx=ctx, settings=gs.default_settings(tile_w=12))
+    assert e.value.code == -4
+    big = dict(sc, means=np.zeros((3, 10**6), np.float32))
+    with pytest.raises(gs.GsError) as e:
+        sp, *_ = _render(gs, dict(sc, means=sc["means"]), ctx=gs.Context(10, 10, 10, 1))
+    assert e.value.code == -2
+    del big
