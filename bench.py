@@ -1,0 +1,384 @@
+#!/usr/bin/env python
+"""Throughput of the joint pose-appearance step on one MI355X.
+
+Metric: forward+backward megapixels per second with pose gradients.  The
+default workload is the full joint step on 150 cameras at 1237x822, 1M
+Gaussians (SH degree 3), 100k tracks, 4 views per step: every step runs pose
+composition, projection, bin/sort, compositing, L1, raster and projection
+backward, track reprojection, the twist chain and Adam.  Inputs are seeded
+synthetic scenes resident in HBM before the timed region.
+
+Also reported: a per-call breakdown (HIP events on the launch stream), the
+roofline of the dominant kernel, the batched-vs-per-view comparison on the
+8-view uneven-resolution scene (3M Gaussians), and the FP64 oracle timed on a
+bounded sample of the same workload on the host cores.
+
+  python bench.py [--steps K] [--warmup W] [--workload C4|C2|C3|C5]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+WORKLOADS = {
+    "C2": "single view 1237x822, 1M Gaussians SH3, 16x16 tiles",
+    "C3": "8 views 640x480..1600x1066 on a sphere around 3M blob Gaussians SH3",
+    "C4": "joint step: 150 cameras 1237x822, 1M Gaussians SH3, 100k tracks, 4 views/step",
+    "C5": "large scene: 1000 cameras 1600x1066, 5M Gaussians SH3, 1.5M tracks, 4 views/step",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class EventTimer:
+    """HIP events around named calls on the current stream; mean ms per name."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.ev = {}
+        self.on = True
+
+    def __call__(self, name):
+        timer = self
+
+        class _Ctx:
+            def __enter__(self_):
+                if timer.on:
+                    self_.a = timer.torch.cuda.Event(enable_timing=True)
+                    self_.a.record()
+                return self_
+
+            def __exit__(self_, *exc):
+                if timer.on:
+                    b = timer.torch.cuda.Event(enable_timing=True)
+                    b.record()
+                    timer.ev.setdefault(name, []).append((self_.a, b))
+                return False
+        return _Ctx()
+
+    def means(self):
+        self.torch.cuda.synchronize()
+        return {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in self.ev.items()}
+
+
+def tile_last_sum(last, wh, tw=16, th=16):
+    """Sum over tiles of the largest `last` of the tile's pixels: the records a
+    tile's compositing must read (C_f)."""
+    off = 0
+    tot = 0
+    for W, H in wh:
+        img = last[off:off + W * H].reshape(H, W)
+        off += W * H
+        gy, gx = (H + th - 1) // th, (W + tw - 1) // tw
+        pad = np.zeros((gy * th, gx * tw), np.int64)
+        pad[:H, :W] = img
+        tot += int(pad.reshape(gy, th, gx, tw).max(axis=(1, 3)).sum())
+    return tot
+
+
+def make_workload(name):
+    import scenegen
+    t0 = time.time()
+    sc = scenegen.make_config(name)
+    if name in ("C4", "C5"):
+        nv = sc["viewmat"].shape[0]
+        batches = scenegen.batch_views(int(name[1]), nv, 4, 4)
+        targets = [scenegen.view_targets(int(name[1]), sc["wh"], b) for b in batches]
+    else:
+        batches = [np.arange(sc["viewmat"].shape[0])]
+        targets = [sc["target"]]
+        n = sc["means"].shape[1]
+        sc["X"] = np.zeros((0, 3), np.float32)
+        sc["obs_cam"] = np.zeros(0, np.int32)
+        sc["obs_pt"] = np.zeros(0, np.int32)
+        sc["obs_xy"] = np.zeros((0, 2), np.float32)
+        del n
+    log(f"[bench] generated {name} in {time.time() - t0:.1f}s")
+    return sc, batches, targets
+
+
+def probe_isect(JointStep, sc, batches, targets):
+    """Intersections the batches need, from a pass with a generous capacity."""
+    P = max(int(sum(int(sc["wh"][v, 0]) * int(sc["wh"][v, 1]) for v in b)) for b in batches)
+    st = JointStep(sc, batches, targets, max_isect=min(2**30, 48 * P))
+    need = 0
+    for b in range(len(batches)):
+        st.forward_backward(b)
+        need = max(need, st.ctx.status()["n_isect_needed"])
+    st.ctx.close()
+    return need
+
+
+def run_joint(torch, name, steps, warmup, graph=False):
+    from paper_2603_04847_amd.step import JointStep
+    sc, batches, targets = make_workload(name)
+    need = probe_isect(JointStep, sc, batches, targets)
+    st = JointStep(sc, batches, targets, max_isect=int(need * 1.15) + 4096)
+    log(f"[bench] {name}: {need} intersections per batch (max), capacity {st.ctx.cap.max_isect}")
+    timer = EventTimer(torch)
+    for i in range(warmup):
+        st.run(i % len(batches))
+    torch.cuda.synchronize()
+    g_all = None
+    if graph:
+        # one captured graph per batch (view choice and sizes are baked in)
+        graphs = []
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            for b in range(len(batches)):
+                st.run(b)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        for b in range(len(batches)):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                st.run(b, step=st.step_count + 1)
+            graphs.append(g)
+        g_all = graphs
+        torch.cuda.synchronize()
+    st.ctx.reset_status()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b_ = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for i in range(steps):
+        if g_all is not None:
+            g_all[i % len(batches)].replay()
+        else:
+            st.run(i % len(batches), timer=timer)
+    b_.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b_) / steps
+    per_call = timer.means() if g_all is None else {}
+    status = st.ctx.status()
+    # workload sizes for the roofline (outside the timed region)
+    st.forward_backward(0)
+    torch.cuda.synchronize()
+    stat0 = st.ctx.status()
+    last = st.last.cpu().numpy()
+    wh_b = st.wh_all[batches[0]]
+    P = int((wh_b[:, 0].astype(np.int64) * wh_b[:, 1]).sum())
+    C_f = tile_last_sum(last[:P], wh_b)
+    sizes = dict(P=P, N=st.N, V=len(batches[0]), K=(st.sh_degree + 1) ** 2,
+                 n_visible=stat0["n_visible"], n_isect=stat0["n_isect"], C_f=C_f,
+                 M=int(st.obs_cam.shape[0]), Pt=int(st.X.shape[0]),
+                 n_params=int(sum(v.numel() for v in st._opt_params().values())))
+    return dict(ms=ms, per_call=per_call, status=status, sizes=sizes, st=st, sc=sc,
+                batches=batches)
+
+
+def algorithmic_bytes(sz):
+    """Bytes each call must move at least (per launch), by the model of the
+    hot-path table: parameter streams, records up to tile termination, pixel
+    I/O, per-pair 2D gradients, intersections through one sort pass."""
+    pg = 44 + 12 * sz["K"]
+    return {
+        "project": sz["N"] * pg + sz["n_visible"] * 48,
+        "bin_sort": sz["n_isect"] * 36,
+        "render_fwd": sz["C_f"] * 40 + sz["P"] * 20,
+        "l1": sz["P"] * 36,
+        "raster_bwd": sz["C_f"] * 40 + sz["P"] * 20 + sz["n_visible"] * 36,
+        "project_bwd": sz["n_visible"] * 36 + 2 * sz["N"] * pg,
+        "track": sz["M"] * 28 + 2 * sz["Pt"] * 12,
+        "adam": sz["n_params"] * 28,
+    }
+
+
+def batched_vs_per_view(torch, steps, warmup):
+    """fwd+bwd (pose grads included) over the 8 uneven views of C3: one batched
+    call per stage vs the same library called once per view."""
+    import scenegen
+    import paper_2603_04847_amd as P
+    from paper_2603_04847_amd import _lib as L
+    sc = scenegen.make_config("C3")
+    f = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda().float()
+    params = {k: f(sc[k]) for k in ("means", "log_scales", "quats", "opacity_logit", "sh")}
+    N = params["means"].shape[1]
+    V = sc["viewmat"].shape[0]
+    wh = sc["wh"]
+    Ptot = int((wh[:, 0].astype(np.int64) * wh[:, 1]).sum())
+    vm, intr = f(sc["viewmat"]), f(sc["intr"])
+    target = f(sc["target"])
+    g = L.make_gaussians(*(params[k] for k in ("means", "log_scales", "quats", "opacity_logit", "sh")), 3)
+    grads = {k: torch.empty_like(v) for k, v in params.items()}
+    gg = L.make_grads(*(grads[k] for k in ("means", "log_scales", "quats", "opacity_logit", "sh")))
+    rgb = torch.empty((Ptot, 3), device="cuda")
+    T = torch.empty((Ptot,), device="cuda")
+    last = torch.empty((Ptot,), device="cuda", dtype=torch.int32)
+    v_rgb = torch.empty((Ptot, 3), device="cuda")
+    loss = torch.zeros(1, device="cuda")
+    v_tw = torch.zeros((V, 6), device="cuda")
+    pix_off = np.concatenate([[0], np.cumsum(wh[:, 0].astype(np.int64) * wh[:, 1])])
+    tiles = int(sum(((w + 15) // 16) * ((h + 15) // 16) for w, h in wh))
+    # probe the intersection count
+    ctx = P.Context(max_pairs=V * N, max_isect=2**28, max_tiles=tiles, max_views=V)
+    cams_b = L.Cameras(vm, intr, wh)
+    s = L.default_settings()
+    L.gs_project(ctx, g, cams_b, s)
+    L.gs_bin_sort(ctx, cams_b, N, s)
+    need = ctx.status()["n_isect_needed"]
+    ctx.close()
+    ctx = P.Context(max_pairs=V * N, max_isect=int(need * 1.1) + 4096, max_tiles=tiles, max_views=V)
+    cams_v = [L.Cameras(vm[v:v + 1], intr[v:v + 1], wh[v:v + 1]) for v in range(V)]
+    s_acc = L.default_settings(grad_accumulate=1)
+
+    def batched():
+        L.gs_project(ctx, g, cams_b, s)
+        L.gs_bin_sort(ctx, cams_b, N, s)
+        L.gs_render_fwd(ctx, cams_b, s, None, rgb, T, last)
+        L.gs_l1_loss_grad(ctx, cams_b, rgb, target, v_rgb, loss)
+        L.gs_render_bwd(ctx, g, cams_b, s, None, T, last, v_rgb, gg, v_tw)
+
+    def per_view():
+        for v in range(V):
+            a, b = int(pix_off[v]), int(pix_off[v + 1])
+            c = cams_v[v]
+            L.gs_project(ctx, g, c, s)
+            L.gs_bin_sort(ctx, c, N, s)
+            L.gs_render_fwd(ctx, c, s, None, rgb[a:b], T[a:b], last[a:b])
+            L.gs_l1_loss_grad(ctx, c, rgb[a:b], target[a:b], v_rgb[a:b], loss)
+            L.gs_render_bwd(ctx, g, c, s if v == 0 else s_acc, None, T[a:b], last[a:b],
+                            v_rgb[a:b], gg, v_tw[v:v + 1])
+
+    out = {}
+    for name, fn in (("batched", batched), ("per_view", per_view)):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        out[name] = dict(ms=round(ms, 3), mp_s=round(Ptot / ms / 1e3, 1))
+    out["speedup"] = round(out["per_view"]["ms"] / out["batched"]["ms"], 2)
+    out["config"] = WORKLOADS["C3"]
+    out["n_isect"] = int(need)
+    ctx.close()
+    return out
+
+
+def cpu_baseline(res, seconds_target=15.0):
+    """The FP64 oracle on the host cores, on a bounded sample of the same
+    workload: the projection and its backward for the batch's views, the track
+    term over all observations, and compositing (with backward) of a random
+    sample of pixels; the compositing time is scaled to all pixels."""
+    import oracle
+    sc, b = res["sc"], res["batches"][0]
+    st = res["st"]
+    sz = res["sizes"]
+    vm = st.viewmat.cpu().numpy()[b]
+    intr = sc["intr"][b]
+    wh = sc["wh"][b]
+    sub = dict(sc, viewmat=vm, intr=intr, wh=wh)
+    t0 = time.time()
+    proj = oracle.project(sub)
+    t_proj = time.time() - t0
+    rng = np.random.default_rng(0)
+    # size the pixel sample from a short calibration run
+    n_cal = 64
+    pix = rng.choice(sz["P"], size=n_cal, replace=False)
+    t0 = time.time()
+    oracle.render(proj, wh, pix=pix, v_rgb=np.ones((n_cal, 3)))
+    per_px = (time.time() - t0) / n_cal
+    n_pix = int(max(64, min(20000, seconds_target / max(per_px, 1e-9) * 0.6)))
+    pix = rng.choice(sz["P"], size=n_pix, replace=False)
+    t0 = time.time()
+    r = oracle.render(proj, wh, pix=pix, v_rgb=np.ones((n_pix, 3)))
+    t_pix = time.time() - t0
+    t0 = time.time()
+    oracle.project_bwd(sub, r["v2d"])
+    t_pbwd = time.time() - t0
+    t_track = 0.0
+    if sz["M"] > 0:
+        t0 = time.time()
+        oracle.track(sc["X"], st.viewmat.cpu().numpy(), sc["intr"], sc["obs_cam"], sc["obs_pt"],
+                     sc["obs_xy"], jacobians=False)
+        t_track = time.time() - t0
+    t_step = t_proj + t_pix * sz["P"] / n_pix + t_pbwd + t_track
+    return dict(value=round(sz["P"] / t_step / 1e6, 6), unit="MP/s", cores=oracle.num_threads(),
+                kind="oracle",
+                sample=(f"batch 0 of the workload: projection + its backward of {sz['V']} views x "
+                        f"{sz['N']} Gaussians, track term over {sz['M']} observations, and "
+                        f"compositing + backward of {n_pix} random pixels of {sz['P']} "
+                        f"(their time scaled by {sz['P'] / n_pix:.0f}); "
+                        f"measured {t_proj + t_pix + t_pbwd + t_track:.1f}s"))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="C4", choices=sorted(WORKLOADS))
+    ap.add_argument("--graph", action="store_true", help="replay the step as captured HIP graphs")
+    ap.add_argument("--no-compare", action="store_true", help="skip batched vs per-view (C3)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the hot path "
+              "here has no multi-GPU code", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    import paper_2603_04847_amd as P
+    P.load()
+
+    res = run_joint(torch, args.workload, args.steps, args.warmup, graph=args.graph)
+    sz = res["sizes"]
+    ms = res["ms"]
+    value = sz["P"] / ms / 1e3  # megapixels / s
+    per_call = {k: round(v, 4) for k, v in res["per_call"].items()}
+    alg = algorithmic_bytes(sz)
+    roof = None
+    if per_call:
+        dom = max((k for k in per_call if k in alg), key=lambda k: per_call[k])
+        ach = alg[dom] / (per_call[dom] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "algorithmic_bytes": int(alg[dom]), "avg_ms": per_call[dom]}
+    line = {
+        "metric": "fwd+bwd megapixels/sec with pose grads (batched vs per-view), %HBM roofline",
+        "value": round(value, 2), "unit": "MP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}",
+                   "views_per_step": sz["V"], "pixels_per_step": sz["P"], "gaussians": sz["N"],
+                   "observations": sz["M"], "graph": bool(args.graph)},
+        "roofline": roof,
+        "per_call_ms": per_call,
+        "sizes": {k: int(v) for k, v in sz.items()},
+    }
+    if res["status"]["flags"]:
+        line["status_flags"] = res["status"]["flags"]
+    if not args.no_compare:
+        log("[bench] batched vs per-view on C3")
+        line["batched_vs_per_view"] = batched_vs_per_view(torch, max(2, args.steps // 4), 1)
+    if not args.no_cpu_baseline:
+        log("[bench] oracle CPU baseline")
+        line["cpu_baseline"] = cpu_baseline(res)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

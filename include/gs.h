@@ -132,10 +132,13 @@ typedef struct {
 } gs_gaussians_grad;
 
 typedef struct {
-    const float* viewmat;   /* [V][12] */
-    const float* intr;      /* [V][4] */
-    const int32_t* wh;      /* HOST [V][2] */
-    int32_t V;
+    const float* viewmat;   /* [n_rows][12] */
+    const float* intr;      /* [n_rows][4] */
+    const int32_t* wh;      /* HOST [V][2]: size of each view of the call */
+    int32_t V;              /* views in this call */
+    const int32_t* index;   /* HOST [V] or NULL: view v of the call uses row index[v] of
+                               viewmat, intr and v_twist (a sampled batch of a larger
+                               camera set); NULL means row v */
 } gs_cameras;
 
 /* Diagnostics read by gs_ctx_status. */
@@ -211,11 +214,23 @@ gs_status gs_render_fwd(gs_ctx* ctx, const gs_cameras* cams, const gs_settings* 
  * reduces per splat over the wave before any global atomic, then chains the
  * per-pair 2D gradients to the Gaussian parameters (summed over views; written
  * or added per s->grad_accumulate) and adds each view's twist gradient into
- * v_twist[V][6].  `g` and `cams` must be those of the forward. */
+ * row index[v] (or v) of v_twist.  `g` and `cams` must be those of the forward. */
 gs_status gs_render_bwd(gs_ctx* ctx, const gs_gaussians* g, const gs_cameras* cams,
                         const gs_settings* s, const float* bg, const float* T_final,
                         const int32_t* last, const float* v_rgb, gs_gaussians_grad* grads,
                         float* v_twist, void* stream);
+
+/* The two halves of gs_render_bwd, for callers that time or schedule them
+ * separately.  gs_raster_bwd: the per-pixel walk, adding the per-pair 2D
+ * gradients into the context.  gs_project_bwd: consumes (and clears) them,
+ * writing the Gaussian gradients and adding the twists.  gs_render_bwd is
+ * gs_raster_bwd followed by gs_project_bwd. */
+gs_status gs_raster_bwd(gs_ctx* ctx, const gs_cameras* cams, const gs_settings* s,
+                        const float* bg, const float* T_final, const int32_t* last,
+                        const float* v_rgb, void* stream);
+gs_status gs_project_bwd(gs_ctx* ctx, const gs_gaussians* g, const gs_cameras* cams,
+                         const gs_settings* s, gs_gaussians_grad* grads, float* v_twist,
+                         void* stream);
 
 /* Photometric L1 term (Sec. 3.3 eq. L_photo, its l1 part): loss += mean over
  * views of the mean over pixels and channels of |rgb - target|; v_rgb =

@@ -231,9 +231,10 @@ def sh_basis(deg, d, grad=False):
 
 
 def bin_sort(wh, tile, valid, mean2d, conic, opacity, depth, alpha_min=1.0 / 255.0,
-             margin=0.0):
+             margin=0.0, with_masks=False):
     """Tile lists ordered by (float32 depth bits, pair index).  Returns
-    (ranges [T_total,2] int64, ids [I] int32)."""
+    (ranges [T_total,2] int64, ids [I] int32) and, with_masks, the quadrant
+    masks [I] int32."""
     lib = _load()
     wh = _i32(wh)
     V = wh.shape[0]
@@ -245,8 +246,11 @@ def bin_sort(wh, tile, valid, mean2d, conic, opacity, depth, alpha_min=1.0 / 255
     args = [ctypes.c_int(V), _p(wh), ctypes.c_int(tw), ctypes.c_int(th), ctypes.c_int(N),
             _p(_i32(valid)), _p(_f32(mean2d)), _p(_f32(conic)), _p(_f32(opacity)),
             _p(_f32(depth)), ctypes.c_double(alpha_min), ctypes.c_double(margin)]
-    n = lib.or_bin_sort(*args, ctypes.c_longlong(0), _p(ranges), None)
+    n = lib.or_bin_sort(*args, ctypes.c_longlong(0), _p(ranges), None, None)
     need = -n if n < 0 else n
     ids = np.zeros(max(need, 1), np.int32)
-    n = lib.or_bin_sort(*args, ctypes.c_longlong(need), _p(ranges), _p(ids))
+    masks = np.zeros(max(need, 1), np.int32)
+    n = lib.or_bin_sort(*args, ctypes.c_longlong(need), _p(ranges), _p(ids), _p(masks))
+    if with_masks:
+        return ranges, ids[:need], masks[:need]
     return ranges, ids[:need]

@@ -835,26 +835,34 @@ static int key_cmp(const void* pa, const void* pb) {
 long long or_bin_sort(int V, const int* wh, int tile_w, int tile_h, int N,
                       const int* valid, const float* mean2d, const float* conic,
                       const float* opacity, const float* depth, double alpha_min,
-                      double margin, long long cap, long long* ranges, int* ids) {
+                      double margin, long long cap, long long* ranges, int* ids, int* masks) {
     long long total = 0, tcount = 0;
     key_t* buf = (key_t*)malloc(sizeof(key_t) * (size_t)(N > 0 ? N : 1));
+    int* mbuf = (int*)malloc(sizeof(int) * (size_t)(N > 0 ? N : 1));
+    const int hw = tile_w / 2, hh = tile_h / 2;
     for (int v = 0; v < V; v++) {
         int W = wh[2 * v], H = wh[2 * v + 1];
         int gx = (W + tile_w - 1) / tile_w, gy = (H + tile_h - 1) / tile_h;
         for (int ty = 0; ty < gy; ty++)
             for (int tx = 0; tx < gx; tx++) {
-                double x0 = tx * tile_w + 0.5, y0 = ty * tile_h + 0.5;
-                double x1 = (tx * tile_w + tile_w < W ? tx * tile_w + tile_w : W) - 0.5;
-                double y1 = (ty * tile_h + tile_h < H ? ty * tile_h + tile_h : H) - 0.5;
                 int n = 0;
                 for (int g = 0; g < N; g++) {
                     size_t i = (size_t)v * N + g;
                     if (!valid[i]) continue;
                     double o = opacity[i];
                     if (!(o > alpha_min)) continue;
-                    double q = rect_min(conic[3 * i], conic[3 * i + 1], conic[3 * i + 2],
-                                        mean2d[2 * i], mean2d[2 * i + 1], x0, x1, y0, y1);
-                    if (q <= log(o / alpha_min) + margin) {
+                    int m = 0;
+                    for (int q = 0; q < 4; q++) {
+                        int xs = tx * tile_w + (q & 1) * hw, ys = ty * tile_h + (q >> 1) * hh;
+                        if (xs >= W || ys >= H) continue;
+                        double x0 = xs + 0.5, y0 = ys + 0.5;
+                        double x1 = (xs + hw < W ? xs + hw : W) - 0.5;
+                        double y1 = (ys + hh < H ? ys + hh : H) - 0.5;
+                        double qm = rect_min(conic[3 * i], conic[3 * i + 1], conic[3 * i + 2],
+                                             mean2d[2 * i], mean2d[2 * i + 1], x0, x1, y0, y1);
+                        if (qm <= log(o / alpha_min) + margin) m |= 1 << q;
+                    }
+                    if (m) {
                         uint32_t b;
                         memcpy(&b, &depth[i], 4);
                         buf[n].dbits = b;
@@ -865,12 +873,31 @@ long long or_bin_sort(int V, const int* wh, int tile_w, int tile_h, int N,
                 qsort(buf, n, sizeof(key_t), key_cmp);
                 if (ranges) { ranges[2 * tcount] = total; ranges[2 * tcount + 1] = total + n; }
                 for (int k = 0; k < n; k++) {
-                    if (ids && total + k < cap) ids[total + k] = buf[k].id;
+                    if (total + k >= cap) continue;
+                    if (ids) ids[total + k] = buf[k].id;
+                    if (masks) {
+                        /* recompute the mask of the sorted entry */
+                        size_t i = (size_t)buf[k].id;
+                        double o = opacity[i];
+                        int m = 0;
+                        for (int q = 0; q < 4; q++) {
+                            int xs = tx * tile_w + (q & 1) * hw, ys = ty * tile_h + (q >> 1) * hh;
+                            if (xs >= W || ys >= H) continue;
+                            double x0 = xs + 0.5, y0 = ys + 0.5;
+                            double x1 = (xs + hw < W ? xs + hw : W) - 0.5;
+                            double y1 = (ys + hh < H ? ys + hh : H) - 0.5;
+                            double qm = rect_min(conic[3 * i], conic[3 * i + 1], conic[3 * i + 2],
+                                                 mean2d[2 * i], mean2d[2 * i + 1], x0, x1, y0, y1);
+                            if (qm <= log(o / alpha_min) + margin) m |= 1 << q;
+                        }
+                        masks[total + k] = m;
+                    }
                 }
                 total += n;
                 tcount++;
             }
     }
     free(buf);
+    free(mbuf);
     return total <= cap ? total : -total;
 }

@@ -90,15 +90,17 @@ void or_se3_jl_transpose(int V, const double* xi, const double* g, double* out);
 void or_adam(long long n, double* p, const double* g, double* m, double* v,
              double lr, double beta1, double beta2, double eps, int step);
 
-/* Tile lists: pair (v,g) is listed in tile t of view v iff the minimum of
- * sigma over the rectangle spanned by t's pixel centres is <= ln(o/alpha_min)
- * + margin.  Lists are ordered by (float32 depth bits, pair index).
- * ranges[T_total][2] (start, end) into ids[]; returns the total count, or
+/* Tile lists: pair (v,g) is listed in tile t of view v iff, for some quadrant
+ * (tile_w/2 x tile_h/2 block) of t, the minimum of sigma over the rectangle
+ * spanned by that quadrant's pixel centres is <= ln(o/alpha_min) + margin; the
+ * quadrants that pass form the entry's 4-bit mask (bit qx + 2 qy).  Lists are
+ * ordered by (float32 depth bits, pair index).  ranges[T_total][2] (start,
+ * end) into ids[] / masks[] (masks may be NULL); returns the total count, or
  * -(needed) if it exceeds cap. */
 long long or_bin_sort(int V, const int* wh, int tile_w, int tile_h, int N,
                       const int* valid, const float* mean2d, const float* conic,
                       const float* opacity, const float* depth, double alpha_min,
-                      double margin, long long cap, long long* ranges, int* ids);
+                      double margin, long long cap, long long* ranges, int* ids, int* masks);
 
 /* Real spherical-harmonic basis (Condon-Shortley phase) at unit direction d,
  * K = (deg+1)^2 values; dY[K][3] = gradient of the polynomial form, may be

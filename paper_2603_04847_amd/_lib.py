@@ -53,7 +53,8 @@ class gs_gaussians_grad(ctypes.Structure):
 
 
 class gs_cameras(ctypes.Structure):
-    _fields_ = [("viewmat", c_vp), ("intr", c_vp), ("wh", c_vp), ("V", ctypes.c_int32)]
+    _fields_ = [("viewmat", c_vp), ("intr", c_vp), ("wh", c_vp), ("V", ctypes.c_int32),
+                ("index", c_vp)]
 
 
 class gs_diag(ctypes.Structure):
@@ -70,7 +71,7 @@ class gs_adam_group(ctypes.Structure):
 EXPORTS = [
     "gs_strerror", "gs_default_settings", "gs_ctx_create", "gs_ctx_destroy", "gs_ctx_status",
     "gs_ctx_reset_status", "gs_ctx_buffers", "gs_project", "gs_bin_sort", "gs_render_fwd",
-    "gs_render_bwd", "gs_l1_loss_grad", "track_reproj_fwd_bwd", "gs_pose_compose",
+    "gs_render_bwd", "gs_raster_bwd", "gs_project_bwd", "gs_l1_loss_grad", "track_reproj_fwd_bwd", "gs_pose_compose",
     "gs_pose_compose_bwd", "gs_adam_step",
 ]
 
@@ -113,6 +114,11 @@ def load():
     lib.gs_render_bwd.argtypes = [c_vp, ctypes.POINTER(gs_gaussians), ctypes.POINTER(gs_cameras),
                                   ctypes.POINTER(gs_settings), c_vp, c_vp, c_vp, c_vp,
                                   ctypes.POINTER(gs_gaussians_grad), c_vp, c_vp]
+    lib.gs_raster_bwd.argtypes = [c_vp, ctypes.POINTER(gs_cameras), ctypes.POINTER(gs_settings),
+                                  c_vp, c_vp, c_vp, c_vp, c_vp]
+    lib.gs_project_bwd.argtypes = [c_vp, ctypes.POINTER(gs_gaussians), ctypes.POINTER(gs_cameras),
+                                   ctypes.POINTER(gs_settings), ctypes.POINTER(gs_gaussians_grad),
+                                   c_vp, c_vp]
     lib.gs_l1_loss_grad.argtypes = [c_vp, ctypes.POINTER(gs_cameras), c_vp, c_vp, c_vp, c_vp, c_vp]
     lib.track_reproj_fwd_bwd.argtypes = [
         c_vp, c_vp, ctypes.c_int32, c_vp, c_vp, ctypes.c_int32, c_vp, c_vp, c_vp, ctypes.c_int32,
@@ -202,16 +208,18 @@ def make_grads(means, log_scales, quats, opacity_logit, sh):
 
 
 class Cameras:
-    """Camera arguments: device viewmat [V,12], intr [V,4]; host wh [V,2] int32."""
+    """Camera arguments: device viewmat [rows,12], intr [rows,4]; host wh [V,2]
+    int32; optional host index [V] (camera row of each view of the call)."""
 
-    def __init__(self, viewmat, intr, wh):
+    def __init__(self, viewmat, intr, wh, index=None):
         import numpy as np
         self.viewmat = viewmat
         self.intr = intr
         self.wh = np.ascontiguousarray(np.asarray(wh, dtype=np.int32).reshape(-1, 2))
         self.V = self.wh.shape[0]
-        self._c = gs_cameras(_ptr(viewmat), _ptr(intr),
-                             self.wh.ctypes.data_as(c_vp), self.V)
+        self.index = None if index is None else np.ascontiguousarray(index, dtype=np.int32)
+        self._c = gs_cameras(_ptr(viewmat), _ptr(intr), self.wh.ctypes.data_as(c_vp), self.V,
+                             None if self.index is None else self.index.ctypes.data_as(c_vp))
 
     @property
     def struct(self):
@@ -287,6 +295,19 @@ def gs_render_bwd(ctx, gaussians, cams, settings, bg, T_final, last, v_rgb, grad
         ctx.handle, ctypes.byref(gaussians), ctypes.byref(cams.struct), ctypes.byref(settings),
         _ptr(bg), _ptr(T_final), _ptr(last), _ptr(v_rgb), ctypes.byref(grads), _ptr(v_twist),
         _stream(stream)))
+
+
+def gs_raster_bwd(ctx, cams, settings, bg, T_final, last, v_rgb, stream=None):
+    _check("gs_raster_bwd", load().gs_raster_bwd(ctx.handle, ctypes.byref(cams.struct),
+                                                 ctypes.byref(settings), _ptr(bg), _ptr(T_final),
+                                                 _ptr(last), _ptr(v_rgb), _stream(stream)))
+
+
+def gs_project_bwd(ctx, gaussians, cams, settings, grads, v_twist, stream=None):
+    _check("gs_project_bwd", load().gs_project_bwd(ctx.handle, ctypes.byref(gaussians),
+                                                   ctypes.byref(cams.struct),
+                                                   ctypes.byref(settings), ctypes.byref(grads),
+                                                   _ptr(v_twist), _stream(stream)))
 
 
 def gs_l1_loss_grad(ctx, cams, rgb, target, v_rgb, loss, stream=None):

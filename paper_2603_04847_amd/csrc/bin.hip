@@ -1,7 +1,7 @@
 // Tile binning and key sort.
 //
-//  1. count:   per pair, the tiles its alpha >= alpha_min ellipse meets (an exact
-//              ellipse/rectangle test inside the splat's bounding box), and its
+//  1. count:   per pair, the tiles its alpha >= alpha_min ellipse meets (row by
+//              row, from the ellipse's x-span in each quadrant band), and its
 //              depth key (float32 depth bits; positive floats order like their
 //              bits).  Culled pairs get key 0xFFFFFFFF and no tiles.
 //  2. sort the pairs by depth key (stable LSD radix from pair order, so equal
@@ -12,6 +12,8 @@
 //     the depth order of step 2 survives, so each tile list ends up in
 //     ascending (depth, pair) order without sorting on depth again.
 //  5. tile ranges from the boundaries of the sorted tile ids.
+#include <algorithm>
+
 #include "gs_internal.h"
 
 namespace gs {
@@ -19,42 +21,114 @@ namespace gs {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / kWave;
+
+// Valid, finite record with a positive-definite conic and a splat that can
+// pass the alpha gate.
+__device__ __forceinline__ bool record_ok(const float4& a, const float4& b, float alpha_min) {
+    return isfinite(a.x) && isfinite(a.y) && isfinite(a.z) && isfinite(a.w) && isfinite(b.x) &&
+           isfinite(b.y) && isfinite(b.z) && b.x > 0.f && b.z > 0.f && b.x * b.z > b.y * b.y &&
+           a.w > alpha_min && a.w <= 1.f;
+}
+
+// Work of one wave, flattened: its 64 splats' tile rows ("units") are laid end
+// to end and handed to the lanes in turn, so a wave costs its total number of
+// tile rows rather than 64 times its tallest splat.
+struct WaveUnits {
+    SplatSpan sp[kWave];
+    int v[kWave];
+    uint32_t upre[kWave + 1];  // exclusive prefix of units per splat
+};
+
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, uint32_t& total) {
+    const int lane = __lane_id();
+    uint32_t inc = x;
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t t = __shfl_up(inc, off, kWave);
+        if (lane >= off) inc += t;
+    }
+    total = __shfl(inc, kWave - 1, kWave);
+    return inc - x;
+}
+
+// largest q in [0, n) with pre[q] <= j (the entry of the segment holding j)
+__device__ __forceinline__ int seg_search(const uint32_t* pre, int n, uint32_t j) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pre[mid] <= j) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void wave_units_load(WaveUnits& wu, int lane, bool ok, const float4& a,
+                                                const float4& b, int v, const ViewTable& vt,
+                                                const RasterParams& rp, uint32_t& total) {
+    uint32_t units = 0;
+    if (ok) {
+        const SplatSpan sp = splat_span(a, b, vt.H[v], rp.tile_h, rp.alpha_min);
+        wu.sp[lane] = sp;
+        if (sp.r0 <= sp.r1) units = (uint32_t)((sp.r1 >> 1) - (sp.r0 >> 1) + 1);
+    }
+    wu.v[lane] = v;
+    const uint32_t ex = wave_excl_scan(units, total);
+    wu.upre[lane] = ex;
+    if (lane == 0) wu.upre[kWave] = total;
+}
 
 __global__ __launch_bounds__(kBlock) void k_count(const float4* __restrict__ rec, int N,
                                                   ViewTable vt, RasterParams rp,
                                                   uint32_t* __restrict__ cnt,
                                                   uint32_t* __restrict__ key,
-                                                  uint32_t* __restrict__ val,
-                                                  uint32_t* __restrict__ diag) {
+                                                  uint32_t* __restrict__ val) {
+    __shared__ WaveUnits s_wu[kWaves];
+    __shared__ uint32_t s_cnt[kWaves][kWave];
     const int64_t pair = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t npairs = (int64_t)vt.V * N;
-    bool vis = false;
-    if (pair < npairs) {
-        const int v = (int)(pair / N);
-        const float4 a = rec[3 * pair];
-        uint32_t c = 0;
-        const float4 b = rec[3 * pair + 1];
-        const bool fin = isfinite(a.x) && isfinite(a.y) && isfinite(a.z) && isfinite(a.w) &&
-                         isfinite(b.x) && isfinite(b.y) && isfinite(b.z) && b.x > 0.f && b.z > 0.f &&
-                         b.x * b.z > b.y * b.y;
-        if (fin && a.w > rp.alpha_min && a.w <= 1.f) {
-            c = for_each_tile(a, b, vt.W[v], vt.H[v], vt.gx[v], rp.tile_w, rp.tile_h,
-                              rp.alpha_min, [](int) {});
-        }
-        vis = c > 0;
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    WaveUnits& wu = s_wu[w];
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
+    int v = 0;
+    bool ok = false;
+    if (pair < (int64_t)vt.V * N) {
+        v = (int)(pair / N);
+        a = rec[3 * pair];
+        b = rec[3 * pair + 1];
+        ok = record_ok(a, b, rp.alpha_min);
+    }
+    uint32_t U;
+    wave_units_load(wu, lane, ok, a, b, v, vt, rp, U);
+    s_cnt[w][lane] = 0;
+    __syncthreads();
+    for (uint32_t j = lane; j < U; j += kWave) {
+        const int q = seg_search(wu.upre, kWave, j);
+        const int vq = wu.v[q];
+        const int tr = (wu.sp[q].r0 >> 1) + (int)(j - wu.upre[q]);
+        const TileRowSpan z = tile_row_span(wu.sp[q], tr, vt.W[vq], vt.H[vq], rp.tile_w, rp.tile_h);
+        if (z.count) atomicAdd(&s_cnt[w][q], (uint32_t)z.count);
+    }
+    __syncthreads();
+    if (pair < (int64_t)vt.V * N) {
+        const uint32_t c = s_cnt[w][lane];
         cnt[pair] = c;
-        key[pair] = vis ? __float_as_uint(a.z) : 0xFFFFFFFFu;
+        key[pair] = c > 0 ? __float_as_uint(a.z) : 0xFFFFFFFFu;
         val[pair] = (uint32_t)pair;
     }
-    const uint64_t m = __ballot(vis);
-    if (__lane_id() == 0 && m) atomicAdd(&diag[kDiagVisible], (uint32_t)__popcll(m));
 }
 
+// tile counts in depth order; also the number of visible pairs (they sort first)
 __global__ __launch_bounds__(kBlock) void k_gather_cnt(const uint32_t* __restrict__ order,
+                                                       const uint32_t* __restrict__ keys,
                                                        const uint32_t* __restrict__ cnt,
-                                                       uint32_t* __restrict__ out, int64_t n) {
+                                                       uint32_t* __restrict__ out, int64_t n,
+                                                       uint32_t* __restrict__ diag) {
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (r < n) out[r] = cnt[order[r]];
+    if (r >= n) return;
+    out[r] = cnt[order[r]];
+    const bool vis = keys[r] != 0xFFFFFFFFu;
+    const bool next_vis = (r + 1 < n) && keys[r + 1] != 0xFFFFFFFFu;
+    if (r == 0 && !vis) diag[kDiagVisible] = 0;
+    if (vis && !next_vis) diag[kDiagVisible] = (uint32_t)(r + 1);
 }
 
 __global__ void k_isect_total(const uint32_t* __restrict__ total, int64_t cap,
@@ -69,6 +143,16 @@ __global__ void k_isect_total(const uint32_t* __restrict__ total, int64_t cap,
     }
 }
 
+// One (tile, pair | mask) entry per intersection, pairs in depth order: rank r's
+// entries fill [off[r], off[r] + cnt).  The 64 ranks of a wave own one
+// contiguous output range, so after the units of a round are laid out (an
+// exclusive scan of their entry counts, in rank order) the lanes write
+// consecutive slots of it: every store of the wave is coalesced.
+struct UnitDesc {
+    int q, tr, t0, n0, t1;      // splat, tile row, union = [t0, t0+n0) u [t1, ...)
+    int a0, b0, a1, b1;         // quadrant-column ranges of the two bands
+};
+
 __global__ __launch_bounds__(kBlock) void k_emit(const float4* __restrict__ rec, int N, ViewTable vt,
                                                  RasterParams rp, const uint32_t* __restrict__ order,
                                                  const uint32_t* __restrict__ off,
@@ -76,36 +160,141 @@ __global__ __launch_bounds__(kBlock) void k_emit(const float4* __restrict__ rec,
                                                  const uint32_t* __restrict__ used,
                                                  uint32_t* __restrict__ okey,
                                                  uint32_t* __restrict__ oval) {
+    __shared__ WaveUnits s_wu[kWaves];
+    __shared__ uint32_t s_pair[kWaves][kWave];
+    __shared__ UnitDesc s_ud[kWaves][kWave];
+    __shared__ uint32_t s_epre[kWaves][kWave + 1];
+    __shared__ uint32_t s_U[kWaves];
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (r >= n) return;
-    if (*used == 0) return;  // nothing fits (overflow) or nothing visible
-    const uint32_t pair = order[r];
-    const float4 a = rec[3 * (int64_t)pair];
-    if (!(a.w > rp.alpha_min)) return;
-    const float4 b = rec[3 * (int64_t)pair + 1];
-    const int v = (int)(pair / (uint32_t)N);
-    const uint32_t toff = (uint32_t)vt.tile_off[v];
-    uint32_t o = off[r];
-    const uint32_t o_end = o + cnt[pair];  // never write outside this pair's slots
-    for_each_tile(a, b, vt.W[v], vt.H[v], vt.gx[v], rp.tile_w, rp.tile_h, rp.alpha_min,
-                  [&](int t) {
-                      if (o < o_end) {
-                          okey[o] = toff + (uint32_t)t;
-                          oval[o] = pair;
-                      }
-                      o++;
-                  });
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    WaveUnits& wu = s_wu[w];
+    const bool any = *used != 0u;  // nothing is written after an overflow
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
+    int v = 0;
+    bool ok = false;
+    uint32_t pair = 0, c = 0, o0 = 0xFFFFFFFFu;
+    if (r < n && any) {
+        pair = order[r];
+        c = cnt[pair];
+        o0 = off[r];
+        if (c > 0) {
+            a = rec[3 * (int64_t)pair];
+            b = rec[3 * (int64_t)pair + 1];
+            v = (int)(pair / (uint32_t)N);
+            ok = record_ok(a, b, rp.alpha_min);
+        }
+    }
+    // the wave's output range: [first offset, first offset + sum of counts)
+    uint32_t base = o0;
+    for (int sh = 32; sh > 0; sh >>= 1) base = min(base, (uint32_t)__shfl_xor((int)base, sh, kWave));
+    uint32_t wave_total = c;
+    for (int sh = 32; sh > 0; sh >>= 1) wave_total += (uint32_t)__shfl_xor((int)wave_total, sh, kWave);
+    uint32_t U;
+    wave_units_load(wu, lane, ok, a, b, v, vt, rp, U);
+    s_pair[w][lane] = pair;
+    if (lane == 0) s_U[w] = U;
+    __syncthreads();
+    // rounds run block-wide (they contain block barriers): up to the largest U
+    uint32_t Umax = 0;
+    for (int q = 0; q < kWaves; q++) Umax = max(Umax, s_U[q]);
+    uint32_t done = 0;  // entries of the wave written so far
+    for (uint32_t ub = 0; ub < Umax; ub += kWave) {
+        // lay out one round of units
+        const uint32_t j = ub + lane;
+        uint32_t ne = 0;
+        if (j < U) {
+            const int q = seg_search(wu.upre, kWave, j);
+            const int vq = wu.v[q];
+            const int tr = (wu.sp[q].r0 >> 1) + (int)(j - wu.upre[q]);
+            const TileRowSpan z = tile_row_span(wu.sp[q], tr, vt.W[vq], vt.H[vq], rp.tile_w, rp.tile_h);
+            UnitDesc d;
+            d.q = q;
+            d.tr = tr;
+            d.a0 = z.a0;
+            d.b0 = z.b0;
+            d.a1 = z.a1;
+            d.b1 = z.b1;
+            ne = (uint32_t)z.count;
+            // the union of the bands' tile columns: one run, or two disjoint runs
+            const bool e0 = z.a0 > z.b0, e1 = z.a1 > z.b1;
+            const int p0 = z.a0 >> 1, q0 = z.b0 >> 1, p1 = z.a1 >> 1, q1 = z.b1 >> 1;
+            if (!e0 && !e1 && (q0 + 1 < p1 || q1 + 1 < p0)) {
+                const bool first0 = p0 < p1;
+                d.t0 = first0 ? p0 : p1;
+                d.n0 = first0 ? q0 - p0 + 1 : q1 - p1 + 1;
+                d.t1 = first0 ? p1 : p0;
+            } else {
+                d.t0 = z.tc0;
+                d.n0 = z.count;
+                d.t1 = 0;
+            }
+            s_ud[w][lane] = d;
+        }
+        uint32_t rt;
+        const uint32_t ex = wave_excl_scan(ne, rt);
+        s_epre[w][lane] = ex;
+        if (lane == 0) s_epre[w][kWave] = rt;
+        __syncthreads();
+        const int nu = ub < U ? (int)min((uint32_t)kWave, U - ub) : 0;
+        for (uint32_t e = lane; e < rt; e += kWave) {
+            const int u = seg_search(s_epre[w], nu, e);
+            const UnitDesc& d = s_ud[w][u];
+            const int k = (int)(e - s_epre[w][u]);
+            const int tc = k < d.n0 ? d.t0 + k : d.t1 + (k - d.n0);
+            TileRowSpan z;
+            z.a0 = d.a0;
+            z.b0 = d.b0;
+            z.a1 = d.a1;
+            z.b1 = d.b1;
+            const uint32_t m = tile_row_mask(z, tc);
+            const uint32_t o = done + e;
+            if (o < wave_total) {  // never write outside the wave's slots
+                const int vq = wu.v[d.q];
+                okey[base + o] = (uint32_t)vt.tile_off[vq] + (uint32_t)(d.tr * vt.gx[vq] + tc);
+                oval[base + o] = s_pair[w][d.q] | (m << kPairBits);
+            }
+        }
+        done += rt;
+        __syncthreads();
+    }
+    // slots not filled (only if the two passes ever disagreed) get a sentinel
+    // tile id past every tile, so no list ever sees stale entries
+    for (uint32_t o = done + lane; o < wave_total; o += kWave) {
+        okey[base + o] = (uint32_t)vt.tile_off[vt.V];
+        oval[base + o] = s_pair[w][0];
+    }
 }
 
+// tile ranges from the boundaries of the sorted keys, four keys per thread
 __global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t* __restrict__ keys,
                                                    const uint32_t* __restrict__ used,
-                                                   int32_t* __restrict__ ranges) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+                                                   int32_t* __restrict__ ranges, uint32_t T) {
     const int64_t n = *used;
-    if (i >= n) return;
-    const uint32_t k = keys[i];
-    if (i == 0 || keys[i - 1] != k) ranges[2 * (int64_t)k] = (int32_t)i;
-    if (i == n - 1 || keys[i + 1] != k) ranges[2 * (int64_t)k + 1] = (int32_t)i + 1;
+    const int64_t nq = (n + 3) / 4;
+    for (int64_t qd = (int64_t)blockIdx.x * kBlock + threadIdx.x; qd < nq;
+         qd += (int64_t)gridDim.x * kBlock) {
+        const int64_t i0 = 4 * qd;
+        uint32_t k[6];
+        k[0] = i0 > 0 ? keys[i0 - 1] : 0xFFFFFFFFu;
+        if (i0 + 4 <= n) {
+            const uint4 q4 = *reinterpret_cast<const uint4*>(keys + i0);
+            k[1] = q4.x;
+            k[2] = q4.y;
+            k[3] = q4.z;
+            k[4] = q4.w;
+        } else {
+            for (int t = 0; t < 4; t++) k[1 + t] = i0 + t < n ? keys[i0 + t] : 0xFFFFFFFFu;
+        }
+        k[5] = i0 + 4 < n ? keys[i0 + 4] : 0xFFFFFFFFu;
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            const int64_t i = i0 + t;
+            const uint32_t kk = k[1 + t];
+            if (i >= n || kk >= T) continue;
+            if (i == 0 || k[t] != kk) ranges[2 * (int64_t)kk] = (int32_t)i;
+            if (i == n - 1 || k[2 + t] != kk) ranges[2 * (int64_t)kk + 1] = (int32_t)i + 1;
+        }
+    }
 }
 
 }  // namespace
@@ -119,17 +308,16 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
     // tile ranges start empty
     if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(c->ranges), 0u, 2 * T, st)) != hipSuccess)
         return e;
-    if ((e = launch_fill_u32(c->diag + kDiagVisible, 0u, 1, st)) != hipSuccess) return e;
     if (npairs > 0) {
         const unsigned gp = (unsigned)((npairs + kBlock - 1) / kBlock);
         hipLaunchKernelGGL(k_count, dim3(gp), dim3(kBlock), 0, st, rec, N, vt, rp, c->cnt, c->pk[0],
-                           c->pv[0], c->diag);
+                           c->pv[0]);
         const int side = radix_sort_pairs(c->pk[0], c->pv[0], c->pk[1], c->pv[1], npairs, nullptr,
                                           0, 32, c->hist, c->scan_scratch, st, &e);
         if (e != hipSuccess) return e;
         const uint32_t* order = c->pv[side];
-        hipLaunchKernelGGL(k_gather_cnt, dim3(gp), dim3(kBlock), 0, st, order, c->cnt, c->off,
-                           npairs);
+        hipLaunchKernelGGL(k_gather_cnt, dim3(gp), dim3(kBlock), 0, st, order, c->pk[side], c->cnt,
+                           c->off, npairs, c->diag);
         uint32_t* total = c->scalars + 0;
         uint32_t* used = c->scalars + 1;
         if ((e = exclusive_scan_u32(c->off, npairs, total, c->scan_scratch, st)) != hipSuccess)
@@ -138,14 +326,15 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
                            c->diag);
         hipLaunchKernelGGL(k_emit, dim3(gp), dim3(kBlock), 0, st, rec, N, vt, rp, order, c->off,
                            c->cnt, npairs, used, c->ik[0], c->iv[0]);
-        int tbits = 1;
-        while (((int64_t)1 << tbits) < T) tbits++;
+        int tbits = 1;  // tile ids and the sentinel T
+        while (((int64_t)1 << tbits) <= T) tbits++;
         const int side2 = radix_sort_pairs(c->ik[0], c->iv[0], c->ik[1], c->iv[1],
                                            c->cap.max_isect, used, 0, tbits, c->hist,
                                            c->scan_scratch, st, &e);
         if (e != hipSuccess) return e;
-        const unsigned gi = (unsigned)((c->cap.max_isect + kBlock - 1) / kBlock);
-        hipLaunchKernelGGL(k_ranges, dim3(gi), dim3(kBlock), 0, st, c->ik[side2], used, c->ranges);
+        const unsigned gi = (unsigned)std::min<int64_t>((c->cap.max_isect + kBlock - 1) / kBlock, 4096);
+        hipLaunchKernelGGL(k_ranges, dim3(gi), dim3(kBlock), 0, st, c->ik[side2], used, c->ranges,
+                           (uint32_t)T);
         c->ids = reinterpret_cast<const int32_t*>(c->iv[side2]);
     } else {
         c->ids = reinterpret_cast<const int32_t*>(c->iv[0]);

@@ -12,12 +12,13 @@ struct gs_ctx {
 
 namespace gs {
 
-ViewTable make_view_table(const int32_t* wh, int V, int TW, int TH) {
+ViewTable make_view_table(const int32_t* wh, int V, int TW, int TH, const int32_t* index) {
     ViewTable vt;
     memset(&vt, 0, sizeof vt);
     vt.V = V;
     int toff = 0, poff = 0;
     for (int v = 0; v < V; v++) {
+        vt.cam[v] = index ? index[v] : v;
         vt.W[v] = wh[2 * v];
         vt.H[v] = wh[2 * v + 1];
         vt.gx[v] = (vt.W[v] + TW - 1) / TW;
@@ -71,6 +72,9 @@ gs_status check_cams(const gs::Ctx& c, const gs_cameras* cams, bool need_device)
                    ? GS_ERR_CAPACITY
                    : GS_ERR_INVALID_ARG;
     if (need_device && (!cams->viewmat || !cams->intr)) return GS_ERR_INVALID_ARG;
+    if (cams->index)
+        for (int v = 0; v < cams->V; v++)
+            if (cams->index[v] < 0) return GS_ERR_INVALID_ARG;
     int64_t P = 0;
     for (int v = 0; v < cams->V; v++) {
         const int W = cams->wh[2 * v], H = cams->wh[2 * v + 1];
@@ -237,7 +241,7 @@ gs_status gs_project(gs_ctx* h, const gs_gaussians* g, const gs_cameras* cams, c
     if ((r = check_gaussians(g)) != GS_OK) return r;
     if ((r = check_cams(h->c, cams, true)) != GS_OK) return r;
     if ((int64_t)cams->V * g->N > h->c.cap.max_pairs) return GS_ERR_CAPACITY;
-    const gs::ViewTable vt = gs::make_view_table(cams->wh, cams->V, s->tile_w, s->tile_h);
+    const gs::ViewTable vt = gs::make_view_table(cams->wh, cams->V, s->tile_w, s->tile_h, cams->index);
     const gs::RasterParams rp = gs::make_raster_params(s);
     return from_hip(gs::launch_project_fwd(&h->c, g, cams, vt, rp, (hipStream_t)stream));
 }
@@ -251,7 +255,7 @@ gs_status gs_bin_sort(gs_ctx* h, const gs_cameras* cams, int32_t N, const gs_set
     if (N < 0) return GS_ERR_INVALID_ARG;
     if (records && !aligned(records, 16)) return GS_ERR_INVALID_ARG;
     if ((int64_t)cams->V * N > h->c.cap.max_pairs) return GS_ERR_CAPACITY;
-    const gs::ViewTable vt = gs::make_view_table(cams->wh, cams->V, s->tile_w, s->tile_h);
+    const gs::ViewTable vt = gs::make_view_table(cams->wh, cams->V, s->tile_w, s->tile_h, cams->index);
     if (vt.tile_off[vt.V] > h->c.cap.max_tiles) return GS_ERR_CAPACITY;
     const gs::RasterParams rp = gs::make_raster_params(s);
     return from_hip(gs::launch_bin(&h->c, vt, N, rp, records, (hipStream_t)stream));
@@ -269,15 +273,26 @@ gs_status gs_render_fwd(gs_ctx* h, const gs_cameras* cams, const gs_settings* s,
     if ((r = check_settings(s)) != GS_OK) return r;
     if ((r = check_cams(h->c, cams, false)) != GS_OK) return r;
     if ((r = check_bins_match(h->c, cams, s)) != GS_OK) return r;
-    const gs::ViewTable vt = gs::make_view_table(cams->wh, cams->V, s->tile_w, s->tile_h);
+    const gs::ViewTable vt = gs::make_view_table(cams->wh, cams->V, s->tile_w, s->tile_h, cams->index);
     const gs::RasterParams rp = gs::make_raster_params(s);
     return from_hip(gs::launch_render_fwd(&h->c, vt, rp, bg, rgb, T_final, last, (hipStream_t)stream));
 }
 
-gs_status gs_render_bwd(gs_ctx* h, const gs_gaussians* g, const gs_cameras* cams, const gs_settings* s,
-                        const float* bg, const float* T_final, const int32_t* last, const float* v_rgb,
-                        gs_gaussians_grad* grads, float* v_twist, void* stream) {
-    if (!h || !T_final || !last || !v_rgb || !grads || !v_twist) return GS_ERR_INVALID_ARG;
+gs_status gs_raster_bwd(gs_ctx* h, const gs_cameras* cams, const gs_settings* s, const float* bg,
+                        const float* T_final, const int32_t* last, const float* v_rgb, void* stream) {
+    if (!h || !T_final || !last || !v_rgb) return GS_ERR_INVALID_ARG;
+    gs_status r;
+    if ((r = check_settings(s)) != GS_OK) return r;
+    if ((r = check_cams(h->c, cams, false)) != GS_OK) return r;
+    if ((r = check_bins_match(h->c, cams, s)) != GS_OK) return r;
+    const gs::ViewTable vt = gs::make_view_table(cams->wh, cams->V, s->tile_w, s->tile_h, cams->index);
+    const gs::RasterParams rp = gs::make_raster_params(s);
+    return from_hip(gs::launch_render_bwd(&h->c, vt, rp, bg, T_final, last, v_rgb, (hipStream_t)stream));
+}
+
+gs_status gs_project_bwd(gs_ctx* h, const gs_gaussians* g, const gs_cameras* cams, const gs_settings* s,
+                         gs_gaussians_grad* grads, float* v_twist, void* stream) {
+    if (!h || !grads || !v_twist) return GS_ERR_INVALID_ARG;
     gs_status r;
     if ((r = check_settings(s)) != GS_OK) return r;
     if ((r = check_gaussians(g)) != GS_OK) return r;
@@ -287,12 +302,21 @@ gs_status gs_render_bwd(gs_ctx* h, const gs_gaussians* g, const gs_cameras* cams
     if (g->N > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logit ||
                      !grads->sh))
         return GS_ERR_INVALID_ARG;
-    const gs::ViewTable vt = gs::make_view_table(cams->wh, cams->V, s->tile_w, s->tile_h);
+    const gs::ViewTable vt = gs::make_view_table(cams->wh, cams->V, s->tile_w, s->tile_h, cams->index);
     const gs::RasterParams rp = gs::make_raster_params(s);
-    hipError_t e = gs::launch_render_bwd(&h->c, vt, rp, bg, T_final, last, v_rgb, (hipStream_t)stream);
-    if (e != hipSuccess) return GS_ERR_HIP;
     return from_hip(gs::launch_project_bwd(&h->c, g, cams, vt, rp, grads, s->grad_accumulate, v_twist,
                                            (hipStream_t)stream));
+}
+
+gs_status gs_render_bwd(gs_ctx* h, const gs_gaussians* g, const gs_cameras* cams, const gs_settings* s,
+                        const float* bg, const float* T_final, const int32_t* last, const float* v_rgb,
+                        gs_gaussians_grad* grads, float* v_twist, void* stream) {
+    if (!h || !grads || !v_twist) return GS_ERR_INVALID_ARG;
+    gs_status r;
+    if ((r = check_gaussians(g)) != GS_OK) return r;
+    if ((r = check_cams(h->c, cams, true)) != GS_OK) return r;
+    if ((r = gs_raster_bwd(h, cams, s, bg, T_final, last, v_rgb, stream)) != GS_OK) return r;
+    return gs_project_bwd(h, g, cams, s, grads, v_twist, stream);
 }
 
 gs_status gs_l1_loss_grad(gs_ctx* h, const gs_cameras* cams, const float* rgb, const float* target,
@@ -300,7 +324,7 @@ gs_status gs_l1_loss_grad(gs_ctx* h, const gs_cameras* cams, const float* rgb, c
     if (!h || !rgb || !target || !v_rgb || !loss) return GS_ERR_INVALID_ARG;
     gs_status r;
     if ((r = check_cams(h->c, cams, false)) != GS_OK) return r;
-    const gs::ViewTable vt = gs::make_view_table(cams->wh, cams->V, 16, 16);
+    const gs::ViewTable vt = gs::make_view_table(cams->wh, cams->V, 16, 16, cams->index);
     return from_hip(gs::launch_l1(&h->c, vt, rgb, target, v_rgb, loss, (hipStream_t)stream));
 }
 

@@ -19,6 +19,7 @@ struct ViewTable {
     int gx[GS_MAX_VIEWS];
     int tile_off[GS_MAX_VIEWS + 1];  // first global tile of each view
     int pix_off[GS_MAX_VIEWS + 1];   // first packed pixel of each view
+    int cam[GS_MAX_VIEWS];           // row of viewmat / intr / v_twist used by the view
 };
 
 struct RasterParams {
@@ -63,6 +64,33 @@ __device__ __forceinline__ float wave_sum(float v) {
     v += dpp_f<0x142, 0xA>(v);
     v += dpp_f<0x143, 0xC>(v);
     return bcast(v, 63);
+}
+
+// Wave totals of eight per-lane values in about a third of the instructions of
+// eight separate sums: the set is halved by exchanging with the quad partner
+// lane^1 and lane^2 (keeping the half picked by that lane bit) and with the
+// lane four places round the 16-lane row, then summed over the row (rotate by
+// 8) and across rows (xor 16, xor 32).  On return lane l holds the total of
+// value sum8_index(l) = bit-reverse of (l & 7).
+__device__ __forceinline__ float wave_sum8_t(float a0, float a1, float a2, float a3, float a4, float a5,
+                                             float a6, float a7) {
+    const int lane = __lane_id();
+    const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
+    const float c0 = (b0 ? a4 : a0) + dpp_f<0xB1>(b0 ? a0 : a4);
+    const float c1 = (b0 ? a5 : a1) + dpp_f<0xB1>(b0 ? a1 : a5);
+    const float c2 = (b0 ? a6 : a2) + dpp_f<0xB1>(b0 ? a2 : a6);
+    const float c3 = (b0 ? a7 : a3) + dpp_f<0xB1>(b0 ? a3 : a7);
+    const float d0 = (b1 ? c2 : c0) + dpp_f<0x4E>(b1 ? c0 : c2);
+    const float d1 = (b1 ? c3 : c1) + dpp_f<0x4E>(b1 ? c1 : c3);
+    float e = (b2 ? d1 : d0) + dpp_f<0x124>(b2 ? d0 : d1);  // row_ror:4
+    e += dpp_f<0x128>(e);                                     // row_ror:8
+    e += __shfl_xor(e, 16, kWave);
+    e += __shfl_xor(e, 32, kWave);
+    return e;
+}
+
+__device__ __forceinline__ int sum8_index(int lane) {
+    return ((lane & 1) << 2) | (lane & 2) | ((lane >> 2) & 1);
 }
 
 __device__ __forceinline__ double wave_sum_d(double v) {
@@ -116,48 +144,122 @@ __device__ __forceinline__ float rect_sigma_min(float A, float B, float C, float
     return q;
 }
 
-// Iterate the tiles of view `v` met by the splat's alpha >= alpha_min ellipse.
-// `fn(tile_local)` is called in row-major order.  Shared by the counting and the
-// emitting pass so both see exactly the same tiles.
-template <typename F>
-__device__ __forceinline__ int for_each_tile(const float4& a, const float4& b, int W, int H,
-                                             int gx, int TW, int TH, float alpha_min, F&& fn) {
-    const float mx = a.x, my = a.y, o = a.w;
-    const float A = b.x, B = b.y, C = b.z;
-    const float thr = __logf(o / alpha_min);
-    // conservative threshold: a splat is kept in a tile if its minimum exponent
-    // there is within a relative 1e-4 (plus 1e-4) of the gate
-    const float thr_c = thr * 1.0001f + 1e-4f;
-    const float detc = A * C - B * B;
-    const float sxx = C / detc, syy = A / detc;  // Sigma2D diagonal
-    const float ex = sqrtf(2.f * thr_c * sxx) + 0.01f;
-    const float ey = sqrtf(2.f * thr_c * syy) + 0.01f;
-    const int gy = (H + TH - 1) / TH;
-    int tx0 = (int)floorf((mx - ex) / TW), tx1 = (int)floorf((mx + ex) / TW);
-    int ty0 = (int)floorf((my - ey) / TH), ty1 = (int)floorf((my + ey) / TH);
-    tx0 = max(tx0, 0);
-    ty0 = max(ty0, 0);
-    tx1 = min(tx1, gx - 1);
-    ty1 = min(ty1, gy - 1);
-    int n = 0;
-    for (int ty = ty0; ty <= ty1; ty++) {
-        const float y0 = ty * TH + 0.5f;
-        const float y1 = (float)min(ty * TH + TH, H) - 0.5f;
-        for (int tx = tx0; tx <= tx1; tx++) {
-            const float x0 = tx * TW + 0.5f;
-            const float x1 = (float)min(tx * TW + TW, W) - 0.5f;
-            if (rect_sigma_min(A, B, C, mx, my, x0, x1, y0, y1) <= thr_c) {
-                fn(ty * gx + tx);
-                n++;
-            }
-        }
-    }
-    return n;
+// Tile-space footprint of a splat, by spans.  The tile is split into four
+// quadrants (TW/2 x TH/2); a quadrant row is a band of pixel-centre rows.  In a
+// band the splat's alpha >= alpha_min ellipse covers one x-interval, found in
+// closed form (the ellipse boundary is convex on the left, concave on the
+// right, with its extremes at the leftmost / rightmost points), so a splat's
+// quadrants follow from O(bands) work with no per-tile test.  The threshold is
+// made conservative (relative 1e-4 plus 1e-4, and 1e-3 px on every interval)
+// so float rounding can only add quadrants that contribute nothing.
+struct SplatSpan {
+    float mx, my, A, B, C, t, det, ey, dyL;
+    int r0, r1;  // quadrant rows that may be met (r0 > r1: none)
+};
+
+constexpr float kSpanEps = 1e-3f;
+
+__device__ __forceinline__ SplatSpan splat_span(const float4& a, const float4& b, int H, int TH,
+                                                float alpha_min) {
+    SplatSpan s;
+    s.mx = a.x;
+    s.my = a.y;
+    s.A = b.x;
+    s.B = b.y;
+    s.C = b.z;
+    s.t = __logf(a.w / alpha_min) * 1.0001f + 1e-4f;
+    s.det = s.A * s.C - s.B * s.B;
+    const float sxx = s.C / s.det, syy = s.A / s.det, sxy = -s.B / s.det;  // Sigma2D
+    s.ey = sqrtf(2.f * s.t * syy);
+    s.dyL = -sxy * sqrtf(2.f * s.t / sxx);  // dy of the leftmost point
+    const int hh = TH / 2;
+    const int nrows = (H + hh - 1) / hh;
+    s.r0 = max((int)floorf((s.my - s.ey - kSpanEps) / hh), 0);
+    s.r1 = min((int)floorf((s.my + s.ey + kSpanEps) / hh), nrows - 1);
+    return s;
 }
+
+// Quadrant columns [c0, c1] of quadrant row r met by the splat (c0 > c1: none).
+__device__ __forceinline__ void span_cols(const SplatSpan& s, int r, int W, int H, int TW, int TH,
+                                          int& c0, int& c1) {
+    const int hh = TH / 2, hw = TW / 2;
+    c0 = 1;
+    c1 = 0;
+    const float ya = r * hh + 0.5f, yb = (float)min(r * hh + hh, H) - 0.5f;
+    float la = fmaxf(ya - s.my, -s.ey), lb = fminf(yb - s.my, s.ey);
+    if (la > lb + kSpanEps) return;
+    if (la > lb) la = lb = 0.5f * (la + lb);
+    // x offsets of the ellipse boundary at height dy: (-B dy -/+ sqrt(2 A t - det dy^2)) / A
+    const float dl = fminf(fmaxf(s.dyL, la), lb), dr = fminf(fmaxf(-s.dyL, la), lb);
+    const float iA = 1.f / s.A;
+    const float xl = s.mx + (-s.B * dl - sqrtf(fmaxf(2.f * s.A * s.t - s.det * dl * dl, 0.f))) * iA - kSpanEps;
+    const float xr = s.mx + (-s.B * dr + sqrtf(fmaxf(2.f * s.A * s.t - s.det * dr * dr, 0.f))) * iA + kSpanEps;
+    if (!(xl <= (float)W - 0.5f) || !(xr >= 0.5f)) return;
+    const int ncols = (W + hw - 1) / hw;
+    c0 = max((int)ceilf((xl + 0.5f) / hw - 1.f), 0);
+    c1 = min((int)floorf((xr - 0.5f) / hw), ncols - 1);
+}
+
+// The tiles of tile row `tr` met by the splat: the union of the tile columns of
+// its two quadrant rows.  Returns the tile-column range [tc0, tc1] to scan and
+// the quadrant-column ranges of the two bands; count = tiles with a non-zero mask.
+struct TileRowSpan {
+    int a0, b0, a1, b1;  // quadrant-column ranges of the upper and lower band
+    int tc0, tc1;
+    int count;
+};
+
+__device__ __forceinline__ TileRowSpan tile_row_span(const SplatSpan& s, int tr, int W, int H, int TW,
+                                                     int TH) {
+    TileRowSpan z;
+    const int hh = TH / 2;
+    const int nrows = (H + hh - 1) / hh;
+    z.a0 = z.a1 = 1;
+    z.b0 = z.b1 = 0;
+    const int r = 2 * tr;
+    if (r >= s.r0 && r <= s.r1) span_cols(s, r, W, H, TW, TH, z.a0, z.b0);
+    if (r + 1 < nrows && r + 1 >= s.r0 && r + 1 <= s.r1) span_cols(s, r + 1, W, H, TW, TH, z.a1, z.b1);
+    const bool e0 = z.a0 > z.b0, e1 = z.a1 > z.b1;
+    const int p0 = z.a0 >> 1, q0 = z.b0 >> 1, p1 = z.a1 >> 1, q1 = z.b1 >> 1;
+    if (e0 && e1) {
+        z.tc0 = 1;
+        z.tc1 = 0;
+        z.count = 0;
+    } else if (e0) {
+        z.tc0 = p1;
+        z.tc1 = q1;
+        z.count = q1 - p1 + 1;
+    } else if (e1) {
+        z.tc0 = p0;
+        z.tc1 = q0;
+        z.count = q0 - p0 + 1;
+    } else {
+        z.tc0 = min(p0, p1);
+        z.tc1 = max(q0, q1);
+        const int ov = min(q0, q1) - max(p0, p1) + 1;  // overlap of the two tile ranges
+        z.count = (q0 - p0 + 1) + (q1 - p1 + 1) - max(ov, 0);
+    }
+    return z;
+}
+
+__device__ __forceinline__ uint32_t tile_row_mask(const TileRowSpan& z, int tc) {
+    uint32_t m = 0;
+    const int c = 2 * tc;
+    if (c >= z.a0 && c <= z.b0) m |= 1u;
+    if (c + 1 >= z.a0 && c + 1 <= z.b0) m |= 2u;
+    if (c >= z.a1 && c <= z.b1) m |= 4u;
+    if (c + 1 >= z.a1 && c + 1 <= z.b1) m |= 8u;
+    return m;
+}
+
+// A listed intersection carries the pair index in its low 28 bits and the
+// quadrant mask in the top 4.
+constexpr uint32_t kPairBits = 28;
+constexpr uint32_t kPairMask = (1u << kPairBits) - 1u;
 
 // ------------------------------------------------------------------ host launchers
 
-ViewTable make_view_table(const int32_t* wh, int V, int TW, int TH);
+ViewTable make_view_table(const int32_t* wh, int V, int TW, int TH, const int32_t* index = nullptr);
 RasterParams make_raster_params(const gs_settings* s);
 
 // scan.hip / sort.hip
@@ -208,6 +310,8 @@ hipError_t launch_pose_compose_bwd(int V, const float* twist, const float* g, fl
 hipError_t launch_adam(const gs_adam_group* groups, int n, int step, float b1, float b2,
                        float eps, hipStream_t st);
 hipError_t launch_flush_acc(double* acc, float* out, int n, hipStream_t st);
+// out[6 * rows[v] + e] += acc[6 * v + e]; acc cleared (twists of a sampled batch)
+hipError_t launch_flush_twist_rows(double* acc, float* out, const ViewTable& vt, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 
 // The context (workspace), shared by the launchers.

@@ -95,24 +95,46 @@ struct AdamArgs {
     float* m[GS_ADAM_MAX_GROUPS];
     float* v[GS_ADAM_MAX_GROUPS];
     float lr[GS_ADAM_MAX_GROUPS];
-    int64_t off[GS_ADAM_MAX_GROUPS + 1];
-    int n;
+    int64_t n[GS_ADAM_MAX_GROUPS];
+    int64_t blk[GS_ADAM_MAX_GROUPS + 1];  // first block of each group
+    int vec[GS_ADAM_MAX_GROUPS];          // all four arrays 16-byte aligned
+    int ng;
 };
 
+constexpr int kAdamPerBlock = 256 * 4;
+
+__device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, float lr, float b1,
+                                         float b2, float eps, float ibc1, float ibc2) {
+    m = b1 * m + (1.f - b1) * g;
+    v = b2 * v + (1.f - b2) * g * g;
+    p -= lr * (m * ibc1) / (sqrtf(v * ibc2) + eps);
+}
+
+// Each block updates 1024 consecutive elements of one group (float4 loads
+// when the group is 16-byte aligned).
 __global__ __launch_bounds__(256) void k_adam(AdamArgs a, float b1, float b2, float eps, float ibc1,
                                               float ibc2) {
-    const int64_t total = a.off[a.n];
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * 256) {
-        int q = 0;
-        while (q + 1 < a.n && i >= a.off[q + 1]) q++;
-        const int64_t j = i - a.off[q];
-        const float gr = a.g[q][j];
-        const float m = b1 * a.m[q][j] + (1.f - b1) * gr;
-        const float v = b2 * a.v[q][j] + (1.f - b2) * gr * gr;
-        a.m[q][j] = m;
-        a.v[q][j] = v;
-        a.p[q][j] -= a.lr[q] * (m * ibc1) / (sqrtf(v * ibc2) + eps);
+    int q = 0;
+    while (q + 1 < a.ng && (int64_t)blockIdx.x >= a.blk[q + 1]) q++;
+    const int64_t i0 = ((int64_t)blockIdx.x - a.blk[q]) * kAdamPerBlock;
+    const int64_t n = a.n[q];
+    const float lr = a.lr[q];
+    if (a.vec[q] && i0 + kAdamPerBlock <= n) {
+        const int64_t j = i0 / 4 + threadIdx.x;
+        float4 p = reinterpret_cast<float4*>(a.p[q])[j];
+        const float4 g = reinterpret_cast<const float4*>(a.g[q])[j];
+        float4 m = reinterpret_cast<float4*>(a.m[q])[j];
+        float4 v = reinterpret_cast<float4*>(a.v[q])[j];
+        adam_one(p.x, g.x, m.x, v.x, lr, b1, b2, eps, ibc1, ibc2);
+        adam_one(p.y, g.y, m.y, v.y, lr, b1, b2, eps, ibc1, ibc2);
+        adam_one(p.z, g.z, m.z, v.z, lr, b1, b2, eps, ibc1, ibc2);
+        adam_one(p.w, g.w, m.w, v.w, lr, b1, b2, eps, ibc1, ibc2);
+        reinterpret_cast<float4*>(a.p[q])[j] = p;
+        reinterpret_cast<float4*>(a.m[q])[j] = m;
+        reinterpret_cast<float4*>(a.v[q])[j] = v;
+    } else {
+        for (int64_t j = i0 + threadIdx.x; j < min(n, i0 + kAdamPerBlock); j += 256)
+            adam_one(a.p[q][j], a.g[q][j], a.m[q][j], a.v[q][j], lr, b1, b2, eps, ibc1, ibc2);
     }
 }
 
@@ -120,6 +142,15 @@ __global__ void k_flush_acc(double* __restrict__ acc, float* __restrict__ out, i
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
         out[i] += (float)acc[i];
+        acc[i] = 0.0;
+    }
+}
+
+__global__ void k_flush_twist_rows(double* __restrict__ acc, float* __restrict__ out, ViewTable vt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 6 * vt.V) {
+        const int v = i / 6, e = i % 6;
+        out[6 * vt.cam[v] + e] += (float)acc[i];
         acc[i] = 0.0;
     }
 }
@@ -149,22 +180,24 @@ hipError_t launch_pose_compose_bwd(int V, const float* twist, const float* g, fl
 hipError_t launch_adam(const gs_adam_group* groups, int n, int step, float b1, float b2,
                        float eps, hipStream_t st) {
     AdamArgs a{};
-    a.n = n;
-    a.off[0] = 0;
+    a.ng = n;
+    a.blk[0] = 0;
+    auto al = [](const void* p) { return ((uintptr_t)p & 15u) == 0; };
     for (int q = 0; q < n; q++) {
         a.p[q] = groups[q].param;
         a.g[q] = groups[q].grad;
         a.m[q] = groups[q].exp_avg;
         a.v[q] = groups[q].exp_avg_sq;
         a.lr[q] = groups[q].lr;
-        a.off[q + 1] = a.off[q] + groups[q].n;
+        a.n[q] = groups[q].n;
+        a.vec[q] = al(a.p[q]) && al(a.g[q]) && al(a.m[q]) && al(a.v[q]);
+        a.blk[q + 1] = a.blk[q] + (groups[q].n + kAdamPerBlock - 1) / kAdamPerBlock;
     }
-    const int64_t total = a.off[n];
-    if (total <= 0) return hipSuccess;
+    const int64_t blocks = a.blk[n];
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
     const float ibc1 = (float)(1.0 / (1.0 - pow((double)b1, step)));
     const float ibc2 = (float)(1.0 / (1.0 - pow((double)b2, step)));
-    int64_t blocks = (total + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(256), 0, st, a, b1, b2, eps, ibc1, ibc2);
     return hipGetLastError();
 }
@@ -172,6 +205,12 @@ hipError_t launch_adam(const gs_adam_group* groups, int n, int step, float b1, f
 hipError_t launch_flush_acc(double* acc, float* out, int n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_flush_acc, dim3((n + 255) / 256), dim3(256), 0, st, acc, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_flush_twist_rows(double* acc, float* out, const ViewTable& vt, hipStream_t st) {
+    if (vt.V <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_flush_twist_rows, dim3((6 * vt.V + 255) / 256), dim3(256), 0, st, acc, out, vt);
     return hipGetLastError();
 }
 

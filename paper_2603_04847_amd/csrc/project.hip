@@ -7,6 +7,8 @@
 // and summed over the views in registers (no atomics for Gaussian gradients),
 // and each view's twist gradient is reduced wave -> block -> one double atomic
 // per block.
+#include <algorithm>
+
 #include "gs_internal.h"
 
 namespace gs {
@@ -241,7 +243,7 @@ __global__ __launch_bounds__(kBlock) void k_project_fwd(gs_gaussians g, const fl
         for (int ch = 0; ch < 3; ch++) sh[k][ch] = g.sh[((int64_t)k * 3 + ch) * g.N + i];
     bool nonfinite = false;
     for (int v = 0; v < vt.V; v++) {
-        const Cam cam = load_cam(viewmat, intr, v);
+        const Cam cam = load_cam(viewmat, intr, vt.cam[v]);
         Proj P;
         project_one(G, cam, vt.W[v], vt.H[v], rp, P);
         const int64_t pair = (int64_t)v * g.N + i;
@@ -283,9 +285,15 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, const fl
                                                         double* __restrict__ twist_acc) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     __shared__ float s_tw[kBlock / kWave][6];
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    const bool active = i < g.N;
+    __shared__ double s_acc[6 * GS_MAX_VIEWS];  // this block's twist sums, all iterations
+    for (int k = threadIdx.x; k < 6 * vt.V; k += kBlock) s_acc[k] = 0.0;
+    __syncthreads();
     const int N = g.N;
+    // grid-stride over Gaussians: a bounded number of blocks keeps the twist
+    // atomics (one per block, view and component) few
+    for (int base = blockIdx.x * kBlock; base < N; base += gridDim.x * kBlock) {
+    const int i = base + threadIdx.x;
+    const bool active = i < N;
     GaussLocal G;
     float sh[K][3];
     float v_sh[K][3];
@@ -317,7 +325,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, const fl
             if (nz) {
 #pragma unroll
                 for (int k = 0; k < 9; k++) gp[k] = 0.f;  // leave the accumulator clean
-                const Cam cam = load_cam(viewmat, intr, v);
+                const Cam cam = load_cam(viewmat, intr, vt.cam[v]);
                 Proj P;
                 project_one(G, cam, vt.W[v], vt.H[v], rp, P);
                 if (P.valid) {
@@ -491,11 +499,11 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, const fl
         if (threadIdx.x < 6) {
             double s = 0.0;
             for (int q = 0; q < kBlock / kWave; q++) s += (double)s_tw[q][threadIdx.x];
-            if (s != 0.0) atomicAdd(&twist_acc[6 * v + threadIdx.x], s);
+            s_acc[6 * v + threadIdx.x] += s;
         }
         __syncthreads();
     }
-    if (!active) return;
+    if (active) {
     auto put = [&](float* dst, int64_t idx, float val) {
         if (accumulate) dst[idx] += val;
         else dst[idx] = val;
@@ -511,6 +519,11 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, const fl
     for (int k = 0; k < K; k++)
 #pragma unroll
         for (int ch = 0; ch < 3; ch++) put(out.sh, ((int64_t)k * 3 + ch) * N + i, v_sh[k][ch]);
+    }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < 6 * vt.V; k += kBlock)
+        if (s_acc[k] != 0.0) atomicAdd(&twist_acc[k], s_acc[k]);
 }
 
 }  // namespace
@@ -534,7 +547,7 @@ hipError_t launch_project_bwd(Ctx* c, const gs_gaussians* g, const gs_cameras* c
                               gs_gaussians_grad* grads, int accumulate, float* v_twist,
                               hipStream_t st) {
     if (g->N > 0) {
-        const dim3 grid((g->N + kBlock - 1) / kBlock), block(kBlock);
+        const dim3 grid(std::min((g->N + kBlock - 1) / kBlock, 1024)), block(kBlock);
         switch (g->sh_degree) {
             case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, block, 0, st, *g, cams->viewmat, cams->intr, vt, rp, c->grad2d, *grads, accumulate, c->twist_render); break;
             case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, block, 0, st, *g, cams->viewmat, cams->intr, vt, rp, c->grad2d, *grads, accumulate, c->twist_render); break;
@@ -544,7 +557,7 @@ hipError_t launch_project_bwd(Ctx* c, const gs_gaussians* g, const gs_cameras* c
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    return launch_flush_acc(c->twist_render, v_twist, 6 * vt.V, st);
+    return launch_flush_twist_rows(c->twist_render, v_twist, vt, st);
 }
 
 }  // namespace gs

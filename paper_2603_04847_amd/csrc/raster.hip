@@ -2,7 +2,9 @@
 // the photometric L1 term.
 //
 // One wave (64 lanes) owns one tile of TW x TH pixels, PPL = TW*TH/64 pixels per
-// lane.  The tile's list is consumed in batches of 64: each lane loads one
+// lane, laid out so that each of a lane's pixel slots stays in fixed tile
+// quadrants; every list entry carries the quadrants its splat reaches, and a
+// slot whose quadrants the splat misses is skipped by the whole wave.  The tile's list is consumed in batches of 64: each lane loads one
 // splat record (a gather of 40 B) and the wave then walks the batch with the
 // splat's parameters broadcast by readlane, i.e. held in scalar registers, so
 // every pixel of the tile tests each splat with no LDS traffic at all.  The
@@ -10,6 +12,8 @@
 // contributor, recovering the transmittance by division, and sums each
 // splat's nine 2D gradients over the whole wave (DPP) before one lane per
 // component issues the global atomic.
+#include <algorithm>
+
 #include "gs_internal.h"
 
 namespace gs {
@@ -22,6 +26,42 @@ __device__ __forceinline__ int tile_view(const ViewTable& vt, int t) {
     return v;
 }
 
+// Pixel of slot k of a lane inside a TW x TH tile, and the quadrants (TW/2 x
+// TH/2 blocks, bit qx + 2 qy) that slot's 64 pixels lie in.  Slots are laid out
+// so each one stays inside fixed quadrants: a splat whose entry mask misses
+// them is skipped by the whole wave at once.
+template <int TW, int TH>
+struct TileMap {
+    static constexpr int PPL = TW * TH / kWave;
+    static_assert(PPL == 1 || PPL == 2 || PPL == 4 || PPL == 8, "tile shape");
+    __device__ static __forceinline__ void pixel(int l, int k, int& x, int& y) {
+        if constexpr (PPL == 1) {          // 8x8
+            x = l % 8;
+            y = l / 8;
+        } else if constexpr (PPL == 2) {   // 16x8: two 8x8 halves
+            x = 8 * k + l % 8;
+            y = l / 8;
+        } else if constexpr (PPL == 4) {   // 16x16: one 8x8 quadrant per slot
+            x = (k % 2) * 8 + l % 8;
+            y = (k / 2) * 8 + l / 8;
+        } else {                            // 32x16: two 16x4 bands per 16x8 quadrant
+            const int q = k / 2;
+            x = (q % 2) * 16 + l % 16;
+            y = (q / 2) * 8 + (k % 2) * 4 + l / 16;
+        }
+    }
+    static constexpr uint32_t quads(int k) {
+        return PPL == 1 ? 0xFu : PPL == 2 ? ((1u << k) | (1u << (k + 2)))
+                        : PPL == 4 ? (1u << k) : (1u << (k / 2));
+    }
+};
+
+// exponent beyond which o e^-sigma < alpha_min for sure (a conservative bound:
+// it only lets the exact test run less often, never changes its outcome)
+__device__ __forceinline__ float sigma_cut(float o, float amin) {
+    return __logf(o / amin) * 1.00001f + 1e-5f;
+}
+
 template <int TW, int TH>
 __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ rec,
                                                    const int32_t* __restrict__ ids,
@@ -31,25 +71,27 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
                                                    float* __restrict__ out_rgb,
                                                    float* __restrict__ out_T,
                                                    int32_t* __restrict__ out_last) {
-    constexpr int PPL = TW * TH / kWave;
-    constexpr int RSTEP = kWave / TW;
+    using TM = TileMap<TW, TH>;
+    constexpr int PPL = TM::PPL;
     const int t = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
     const int v = tile_view(vt, t);
     const int lt = t - vt.tile_off[v];
     const int gx = vt.gx[v], W = vt.W[v], H = vt.H[v];
     const int tx = lt % gx, ty = lt / gx;
     const int lane = threadIdx.x;
-    const int px = tx * TW + lane % TW;
-    const int py0 = ty * TH + lane / TW;
-    const float fx = px + 0.5f;
-    float fy[PPL], T[PPL], C0[PPL], C1[PPL], C2[PPL];
+    int px[PPL], py[PPL];
+    float fx[PPL], fy[PPL], T[PPL], C0[PPL], C1[PPL], C2[PPL];
     int last[PPL];
     bool done[PPL];
 #pragma unroll
     for (int k = 0; k < PPL; k++) {
-        const int py = py0 + k * RSTEP;
-        fy[k] = py + 0.5f;
-        done[k] = !(px < W && py < H);
+        int x, y;
+        TM::pixel(lane, k, x, y);
+        px[k] = tx * TW + x;
+        py[k] = ty * TH + y;
+        fx[k] = px[k] + 0.5f;
+        fy[k] = py[k] + 0.5f;
+        done[k] = !(px[k] < W && py[k] < H);
         T[k] = 1.f;
         C0[k] = C1[k] = C2[k] = 0.f;
         last[k] = 0;
@@ -64,46 +106,54 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
         const int j = b + lane;
         float4 ra = make_float4(0.f, 0.f, 0.f, 0.f), rb = ra;
         float2 rc = make_float2(0.f, 0.f);
+        uint32_t id = 0;
+        float cut = 0.f;
         if (j < e) {
-            const int64_t p = ids[j];
+            id = (uint32_t)ids[j];
+            const int64_t p = id & kPairMask;
             ra = rec[3 * p];
             rb = rec[3 * p + 1];
             rc = *reinterpret_cast<const float2*>(rec + 3 * p + 2);
+            cut = sigma_cut(ra.w, amin);
         }
         const int nb = min(kWave, e - b);
         for (int i = 0; i < nb; i++) {
+            const uint32_t m = (uint32_t)bcast((int)id, i) >> kPairBits;
             const float mx = bcast(ra.x, i), my = bcast(ra.y, i), o = bcast(ra.w, i);
             const float A = bcast(rb.x, i), B = bcast(rb.y, i), C = bcast(rb.z, i);
             const float cr = bcast(rb.w, i), cg = bcast(rc.x, i), cb = bcast(rc.y, i);
-            const float dx = mx - fx;
+            const float sc = bcast(cut, i);
+            const int pos = b + i - s + 1;
+            // one branch per slot (skipped by the whole wave when no lane is in
+            // range); inside it the update is branch-free
 #pragma unroll
             for (int k = 0; k < PPL; k++) {
-                if (done[k]) continue;
+                if (!(m & TM::quads(k))) continue;  // wave-uniform
+                const float dx = mx - fx[k];
                 const float dy = my - fy[k];
                 const float sig = splat_sigma(A, B, C, dx, dy);
-                if (sig < 0.f) continue;
-                const float alpha = fminf(amax, o * fast_exp_neg(sig));
-                if (alpha < amin) continue;
-                const float Tn = T[k] * (1.f - alpha);
-                if (Tn < tmin) {
-                    done[k] = true;
-                    continue;
+                if (!done[k] && sig >= 0.f && sig <= sc) {
+                    const float alpha = fminf(amax, o * fast_exp_neg(sig));
+                    const float Tn = T[k] * (1.f - alpha);
+                    const bool live = alpha >= amin;
+                    const bool stop = live && Tn < tmin;
+                    const bool use = live && !stop;
+                    done[k] = stop;
+                    const float w = use ? alpha * T[k] : 0.f;
+                    C0[k] = __builtin_fmaf(cr, w, C0[k]);
+                    C1[k] = __builtin_fmaf(cg, w, C1[k]);
+                    C2[k] = __builtin_fmaf(cb, w, C2[k]);
+                    T[k] = use ? Tn : T[k];
+                    last[k] = use ? pos : last[k];
                 }
-                const float w = alpha * T[k];
-                C0[k] = __builtin_fmaf(cr, w, C0[k]);
-                C1[k] = __builtin_fmaf(cg, w, C1[k]);
-                C2[k] = __builtin_fmaf(cb, w, C2[k]);
-                T[k] = Tn;
-                last[k] = b + i - s + 1;
             }
         }
     }
     const float b0 = bg ? bg[0] : 0.f, b1 = bg ? bg[1] : 0.f, b2 = bg ? bg[2] : 0.f;
 #pragma unroll
     for (int k = 0; k < PPL; k++) {
-        const int py = py0 + k * RSTEP;
-        if (px < W && py < H) {
-            const int64_t pix = (int64_t)vt.pix_off[v] + (int64_t)py * W + px;
+        if (px[k] < W && py[k] < H) {
+            const int64_t pix = (int64_t)vt.pix_off[v] + (int64_t)py[k] * W + px[k];
             out_rgb[3 * pix] = C0[k] + T[k] * b0;
             out_rgb[3 * pix + 1] = C1[k] + T[k] * b1;
             out_rgb[3 * pix + 2] = C2[k] + T[k] * b2;
@@ -123,24 +173,24 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ re
                                                    const int32_t* __restrict__ last_in,
                                                    const float* __restrict__ v_rgb,
                                                    float* __restrict__ grad2d) {
-    constexpr int PPL = TW * TH / kWave;
-    constexpr int RSTEP = kWave / TW;
+    using TM = TileMap<TW, TH>;
+    constexpr int PPL = TM::PPL;
     const int t = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
     const int v = tile_view(vt, t);
     const int lt = t - vt.tile_off[v];
     const int gx = vt.gx[v], W = vt.W[v], H = vt.H[v];
     const int tx = lt % gx, ty = lt / gx;
     const int lane = threadIdx.x;
-    const int px = tx * TW + lane % TW;
-    const int py0 = ty * TH + lane / TW;
-    const float fx = px + 0.5f;
     const float b0 = bg ? bg[0] : 0.f, b1 = bg ? bg[1] : 0.f, b2 = bg ? bg[2] : 0.f;
-    float fy[PPL], Tc[PPL], Tf[PPL], V0[PPL], V1[PPL], V2[PPL], S0[PPL], S1[PPL], S2[PPL];
+    float fx[PPL], fy[PPL], Tc[PPL], Tf[PPL], V0[PPL], V1[PPL], V2[PPL], S0[PPL], S1[PPL], S2[PPL];
     int L[PPL];
     int lmax = 0;
 #pragma unroll
     for (int k = 0; k < PPL; k++) {
-        const int py = py0 + k * RSTEP;
+        int x, y;
+        TM::pixel(lane, k, x, y);
+        const int px = tx * TW + x, py = ty * TH + y;
+        fx[k] = px + 0.5f;
         fy[k] = py + 0.5f;
         L[k] = 0;
         Tc[k] = Tf[k] = 1.f;
@@ -168,81 +218,96 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ re
         const int j = b + lane;
         float4 ra = make_float4(0.f, 0.f, 0.f, 0.f), rb = ra;
         float2 rc = make_float2(0.f, 0.f);
-        int pid = 0;
+        uint32_t id = 0;
+        float cut = 0.f;
         if (j < s + lmax) {
-            pid = ids[j];
-            const int64_t p = pid;
+            id = (uint32_t)ids[j];
+            const int64_t p = id & kPairMask;
             ra = rec[3 * p];
             rb = rec[3 * p + 1];
             rc = *reinterpret_cast<const float2*>(rec + 3 * p + 2);
+            cut = sigma_cut(ra.w, amin);
         }
         const int nb = min(kWave, s + lmax - b);
         for (int i = nb - 1; i >= 0; i--) {
+            const uint32_t idb = (uint32_t)bcast((int)id, i);
+            const uint32_t m = idb >> kPairBits;
             const float mx = bcast(ra.x, i), my = bcast(ra.y, i), o = bcast(ra.w, i);
             const float A = bcast(rb.x, i), B = bcast(rb.y, i), C = bcast(rb.z, i);
             const float cr = bcast(rb.w, i), cg = bcast(rc.x, i), cb = bcast(rc.y, i);
+            const float sc = bcast(cut, i);
             const int pos = b + i - s;
-            const float dx = mx - fx;
-            float g_mx = 0.f, g_my = 0.f, g_A = 0.f, g_B = 0.f, g_C = 0.f, g_o = 0.f;
-            float g_r = 0.f, g_g = 0.f, g_b = 0.f;
+            // per-lane sums over the lane's pixels: colour weights, opacity, and
+            // the moments sum vs dx, vs dy, vs dx^2, vs dx dy, vs dy^2 of the
+            // exponent's gradient, from which the mean and conic gradients follow
+            float g_r = 0.f, g_g = 0.f, g_b = 0.f, g_o = 0.f;
+            float m_x = 0.f, m_y = 0.f, m_xx = 0.f, m_xy = 0.f, m_yy = 0.f;
             bool any = false;
 #pragma unroll
             for (int k = 0; k < PPL; k++) {
-                if (pos >= L[k]) continue;
+                if (!(m & TM::quads(k))) continue;  // wave-uniform
+                const float dx = mx - fx[k];
                 const float dy = my - fy[k];
                 const float sig = splat_sigma(A, B, C, dx, dy);
-                if (sig < 0.f) continue;
                 const float ex = fast_exp_neg(sig);
                 const float araw = o * ex;
                 const float alpha = fminf(amax, araw);
-                if (alpha < amin) continue;
-                any = true;
-                const float om = 1.f - alpha;
-                const float iom = 1.f / om;
-                const float Tb = Tc[k] * iom;  // transmittance in front of this splat
-                const float w = alpha * Tb;
-                g_r = __builtin_fmaf(w, V0[k], g_r);
-                g_g = __builtin_fmaf(w, V1[k], g_g);
-                g_b = __builtin_fmaf(w, V2[k], g_b);
-                const float va = V0[k] * (cr * Tb - S0[k] * iom) + V1[k] * (cg * Tb - S1[k] * iom) +
-                                 V2[k] * (cb * Tb - S2[k] * iom);
-                S0[k] = __builtin_fmaf(cr, w, S0[k]);
-                S1[k] = __builtin_fmaf(cg, w, S1[k]);
-                S2[k] = __builtin_fmaf(cb, w, S2[k]);
-                Tc[k] = Tb;
-                if (araw < amax) {
-                    g_o = __builtin_fmaf(va, ex, g_o);
-                    const float vs = -alpha * va;
-                    g_mx += vs * (A * dx + B * dy);
-                    g_my += vs * (B * dx + C * dy);
-                    g_A += vs * 0.5f * dx * dx;
-                    g_B += vs * dx * dy;
-                    g_C += vs * 0.5f * dy * dy;
+                const bool live = pos < L[k] && sig >= 0.f && sig <= sc && alpha >= amin;
+                if (live) {
+                    any = true;
+                    const float iom = __builtin_amdgcn_rcpf(1.f - alpha);
+                    const float Tb = Tc[k] * iom;  // transmittance in front of this splat
+                    const float w = alpha * Tb;
+                    g_r = __builtin_fmaf(w, V0[k], g_r);
+                    g_g = __builtin_fmaf(w, V1[k], g_g);
+                    g_b = __builtin_fmaf(w, V2[k], g_b);
+                    const float va = V0[k] * (cr * Tb - S0[k] * iom) + V1[k] * (cg * Tb - S1[k] * iom) +
+                                     V2[k] * (cb * Tb - S2[k] * iom);
+                    S0[k] = __builtin_fmaf(cr, w, S0[k]);
+                    S1[k] = __builtin_fmaf(cg, w, S1[k]);
+                    S2[k] = __builtin_fmaf(cb, w, S2[k]);
+                    Tc[k] = Tb;
+                    const bool unc = araw < amax;  // clamped alpha passes no gradient
+                    g_o += unc ? va * ex : 0.f;
+                    const float vs = unc ? -alpha * va : 0.f;
+                    const float vx = vs * dx, vy = vs * dy;
+                    m_x += vx;
+                    m_y += vy;
+                    m_xx = __builtin_fmaf(vx, dx, m_xx);
+                    m_xy = __builtin_fmaf(vx, dy, m_xy);
+                    m_yy = __builtin_fmaf(vy, dy, m_yy);
                 }
             }
             if (__ballot(any) == 0) continue;
-            const float s_mx = wave_sum(g_mx), s_my = wave_sum(g_my), s_A = wave_sum(g_A);
-            const float s_B = wave_sum(g_B), s_C = wave_sum(g_C), s_o = wave_sum(g_o);
-            const float s_r = wave_sum(g_r), s_g = wave_sum(g_g), s_b = wave_sum(g_b);
+            // wave totals: eight through one transposed butterfly, blue on its own
+            const float e = wave_sum8_t(m_x, m_y, m_xx, m_xy, m_yy, g_o, g_r, g_g);
+            const float tb = wave_sum(g_b);
+            const float SX = bcast(e, 0), SY = bcast(e, 4);  // lanes holding m_x, m_y
             if (lane < 9) {
-                const float val = lane == 0 ? s_mx : lane == 1 ? s_my : lane == 2 ? s_A
-                                : lane == 3 ? s_B : lane == 4 ? s_C : lane == 5 ? s_o
-                                : lane == 6 ? s_r : lane == 7 ? s_g : s_b;
-                const int64_t p = bcast(pid, i);
-                atomicAdd(grad2d + 9 * p + lane, val);
+                // component: 0 mean.x, 1 mean.y, 2 A, 3 B, 4 C, 5 opacity, 6 r, 7 g, 8 b
+                const int comp = lane < 8 ? sum8_index(lane) : 8;
+                const float val = comp == 0 ? A * SX + B * SY
+                                : comp == 1 ? B * SX + C * SY
+                                : (comp == 2 || comp == 4) ? 0.5f * e
+                                : comp == 8 ? tb : e;
+                const int64_t p = idb & kPairMask;
+                atomicAdd(grad2d + 9 * p + comp, val);
             }
         }
     }
 }
 
+constexpr int kL1Blocks = 1024;
+
 __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ rgb,
                                             const float* __restrict__ target,
                                             float* __restrict__ v_rgb, ViewTable vt,
                                             double* __restrict__ loss_acc) {
+    __shared__ float s_w[4];
     const int64_t P = vt.pix_off[vt.V];
-    const int64_t pix = (int64_t)blockIdx.x * 256 + threadIdx.x;
     float part = 0.f;
-    if (pix < P) {
+    for (int64_t pix = (int64_t)blockIdx.x * 256 + threadIdx.x; pix < P;
+         pix += (int64_t)gridDim.x * 256) {
         int v = 0;
         while (v + 1 < vt.V && pix >= vt.pix_off[v + 1]) v++;
         const float wgt = 1.f / (3.f * (float)(vt.pix_off[v + 1] - vt.pix_off[v]) * (float)vt.V);
@@ -253,8 +318,14 @@ __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ rgb,
             part += fabsf(d) * wgt;
         }
     }
+    // one double atomic per block
     const float s = wave_sum(part);
-    if (__lane_id() == 0 && s != 0.f) atomicAdd(loss_acc, (double)s);
+    if (__lane_id() == 0) s_w[threadIdx.x / kWave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double tot = (double)s_w[0] + s_w[1] + s_w[2] + s_w[3];
+        if (tot != 0.0) atomicAdd(loss_acc, tot);
+    }
 }
 
 template <int TW, int TH>
@@ -308,8 +379,8 @@ hipError_t launch_l1(Ctx* c, const ViewTable& vt, const float* rgb, const float*
                      float* v_rgb, float* loss, hipStream_t st) {
     const int64_t P = vt.pix_off[vt.V];
     if (P > 0) {
-        hipLaunchKernelGGL(k_l1, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, rgb, target,
-                           v_rgb, vt, c->loss_acc);
+        const unsigned nb = (unsigned)std::min<int64_t>((P + 255) / 256, kL1Blocks);
+        hipLaunchKernelGGL(k_l1, dim3(nb), dim3(256), 0, st, rgb, target, v_rgb, vt, c->loss_acc);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

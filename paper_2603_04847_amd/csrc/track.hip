@@ -6,6 +6,8 @@
 // camera boundary falls back to per-lane atomics.  Track-point gradients are
 // scattered with three float atomics per observation (points are spread, so
 // these rarely collide).
+#include <algorithm>
+
 #include "gs_internal.h"
 
 namespace gs {
@@ -14,6 +16,8 @@ namespace {
 
 constexpr int kBlock = 256;
 
+constexpr int kTrackBlocks = 1024;
+
 __global__ __launch_bounds__(kBlock) void k_track(
     const float* __restrict__ X, int Pt, const float* __restrict__ viewmat,
     const float* __restrict__ intr, int n_cams, const int32_t* __restrict__ obs_cam,
@@ -21,7 +25,15 @@ __global__ __launch_bounds__(kBlock) void k_track(
     float lambda, float near_plane, float* __restrict__ residual, float* __restrict__ v_X,
     float* __restrict__ J_pose, float* __restrict__ J_X, double* __restrict__ twist_acc,
     double* __restrict__ loss_acc, uint32_t* __restrict__ diag) {
-    const int o = blockIdx.x * kBlock + threadIdx.x;
+    __shared__ float s_loss[kBlock / kWave];
+    __shared__ uint32_t s_mask[kBlock / kWave];
+    const int lane = __lane_id();
+    float lo_sum = 0.f;
+    uint32_t n_masked = 0;
+    // grid-stride: block-level sums of the loss and the masked count end in one
+    // atomic per block; the twist is summed per wave (mostly one camera each)
+    for (int base = blockIdx.x * kBlock; base < M; base += gridDim.x * kBlock) {
+    const int o = base + threadIdx.x;
     const bool in = o < M;
     int ci = 0, k = 0;
     if (in) {
@@ -30,7 +42,6 @@ __global__ __launch_bounds__(kBlock) void k_track(
     }
     const bool ok_idx = in && ci >= 0 && ci < n_cams && k >= 0 && k < Pt;
     float tw[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    float lo = 0.f;
     bool masked = false;
     if (ok_idx) {
         float R[9], t[3];
@@ -48,6 +59,7 @@ __global__ __launch_bounds__(kBlock) void k_track(
         for (int r = 0; r < 3; r++) p[r] = R[3 * r] * Xk[0] + R[3 * r + 1] * Xk[1] + R[3 * r + 2] * Xk[2] + t[r];
         masked = !(p[2] >= near_plane);
         if (masked) {
+            n_masked++;
             if (residual) {
                 residual[2 * (int64_t)o] = 0.f;
                 residual[2 * (int64_t)o + 1] = 0.f;
@@ -71,7 +83,7 @@ __global__ __launch_bounds__(kBlock) void k_track(
                 rho = 2.f * delta * rs - delta * delta;
                 drho = delta / rs;
             }
-            lo = lambda * rho;
+            lo_sum += lambda * rho;
             // J_pi (2x3) = [[fx/z, 0, -fx x/z^2], [0, fy/z, -fy y/z^2]]
             const float j00 = fx * iz, j02 = -fx * u * iz, j11 = fy * iz, j12 = -fy * w * iz;
             const float g0 = 2.f * lambda * drho * r0, g1 = 2.f * lambda * drho * r1;
@@ -113,27 +125,41 @@ __global__ __launch_bounds__(kBlock) void k_track(
             }
         }
     }
-    // loss: wave sum, one double atomic per wave
-    const float ls = wave_sum(lo);
-    const int lane = __lane_id();
-    if (lane == 0 && ls != 0.f) atomicAdd(loss_acc, (double)ls);
-    const uint64_t mm = __ballot(ok_idx && masked);
-    if (lane == 0 && mm) atomicAdd(&diag[kDiagMasked], (uint32_t)__popcll(mm));
     // twist: one camera for the whole wave is the common case
-    const uint64_t live = __ballot(ok_idx);
-    if (live == 0) return;
-    const int first = __builtin_ctzll(live);
-    const int c0 = bcast(ci, first);
-    const bool uniform = __ballot(ok_idx && ci != c0) == 0;
-    if (uniform) {
+    const uint64_t live = __ballot(ok_idx && !masked);
+    if (live != 0) {
+        const int first = __builtin_ctzll(live);
+        const int c0 = bcast(ci, first);
+        const bool uniform = __ballot(ok_idx && !masked && ci != c0) == 0;
+        if (uniform) {
 #pragma unroll
-        for (int e = 0; e < 6; e++) {
-            const float s = wave_sum(tw[e]);
-            if (lane == e && s != 0.f) atomicAdd(twist_acc + 6 * (int64_t)c0 + e, (double)s);
+            for (int e = 0; e < 6; e++) {
+                const float s = wave_sum(tw[e]);
+                if (lane == e && s != 0.f) atomicAdd(twist_acc + 6 * (int64_t)c0 + e, (double)s);
+            }
+        } else if (ok_idx && !masked) {
+#pragma unroll
+            for (int e = 0; e < 6; e++) atomicAdd(twist_acc + 6 * (int64_t)ci + e, (double)tw[e]);
         }
-    } else if (ok_idx && !masked) {
-#pragma unroll
-        for (int e = 0; e < 6; e++) atomicAdd(twist_acc + 6 * (int64_t)ci + e, (double)tw[e]);
+    }
+    }
+    const float ls = wave_sum(lo_sum);
+    uint32_t nm = n_masked;
+    for (int off = 32; off > 0; off >>= 1) nm += __shfl_xor(nm, off, kWave);
+    if (lane == 0) {
+        s_loss[threadIdx.x / kWave] = ls;
+        s_mask[threadIdx.x / kWave] = nm;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        uint32_t tm = 0;
+        for (int q = 0; q < kBlock / kWave; q++) {
+            tot += s_loss[q];
+            tm += s_mask[q];
+        }
+        if (tot != 0.0) atomicAdd(loss_acc, tot);
+        if (tm) atomicAdd(&diag[kDiagMasked], tm);
     }
 }
 
@@ -145,7 +171,8 @@ hipError_t launch_track(Ctx* c, const float* X, int Pt, const float* viewmat, co
                         float* residual, float* loss, float* v_X, float* v_twist, float* J_pose,
                         float* J_X, hipStream_t st) {
     if (M > 0) {
-        hipLaunchKernelGGL(k_track, dim3((M + kBlock - 1) / kBlock), dim3(kBlock), 0, st, X, Pt,
+        hipLaunchKernelGGL(k_track, dim3(std::min((M + kBlock - 1) / kBlock, kTrackBlocks)),
+                           dim3(kBlock), 0, st, X, Pt,
                            viewmat, intr, n_cams, obs_cam, obs_pt, obs_xy, M, delta, lambda,
                            near_plane, residual, v_X, J_pose, J_X, c->twist_track,
                            c->loss_acc + 1, c->diag);

@@ -1,0 +1,153 @@
+"""One joint pose-appearance step (GloSplat Algorithm 1, one iteration) through
+the C ABI, without Python-side arithmetic:
+
+  a1  compose every pose T_i = Exp(dT_i) T_i^(0)           gs_pose_compose
+  a2  project the Gaussians into the sampled views          gs_project
+  a3+a4 bin and key-sort the tile intersections             gs_bin_sort
+  a5  front-to-back composite                               gs_render_fwd
+  a6  L1 loss and its image gradient                        gs_l1_loss_grad
+  a7  raster backward (2D gradients)                        gs_raster_bwd
+  a8  chain to Gaussian parameters + per-view twists        gs_project_bwd
+  a9  track reprojection Huber loss, grads to X and twists  track_reproj_fwd_bwd
+      (the same twist buffer: poses get both gradients)
+  a1' twist gradient through the composition                gs_pose_compose_bwd
+  a10 Adam on Gaussians, poses and track points             gs_adam_step
+
+Learning rates follow Sec. 3.3 "Implementation" and the pose rate of Sec. 3.3;
+the track-point rate (not given in the paper) is the position rate.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+PARAM_KEYS = ("means", "log_scales", "quats", "opacity_logit", "sh")
+
+
+def learning_rates(extent):
+    return dict(means=1.6e-4 * extent, log_scales=5e-3, quats=1e-3, opacity_logit=5e-2,
+                sh=2.5e-3, twist=1e-5, X=1.6e-4 * extent)
+
+
+class JointStep:
+    """State and buffers of the joint step; `run(b)` executes one iteration on
+    batch b (views batches[b]); every buffer is allocated up front so a run
+    can be captured in a HIP graph."""
+
+    def __init__(self, scene, batches, targets, device="cuda", settings=None, max_isect=None,
+                 lam=1e-4, delta=1.0, extent=None):
+        f = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device, torch.float32)
+        self.sh_degree = int(scene["sh_degree"])
+        self.params = {k: f(scene[k]) for k in PARAM_KEYS}
+        self.N = self.params["means"].shape[1]
+        self.base = f(scene["viewmat"])
+        self.intr = f(scene["intr"])
+        self.wh_all = np.asarray(scene["wh"], np.int32)
+        self.n_cams = self.base.shape[0]
+        self.twist = torch.zeros((self.n_cams, 6), device=device)
+        self.viewmat = torch.empty_like(self.base)
+        self.X = f(scene["X"])
+        self.obs_cam = torch.from_numpy(scene["obs_cam"]).to(device, torch.int32)
+        self.obs_pt = torch.from_numpy(scene["obs_pt"]).to(device, torch.int32)
+        self.obs_xy = f(scene["obs_xy"])
+        self.batches = [np.asarray(b, np.int32) for b in batches]
+        self.targets = [f(t) for t in targets]
+        self.settings = settings if settings is not None else L.default_settings()
+        self.lam, self.delta = lam, delta
+        if extent is None:
+            c = np.stack([-(np.asarray(scene["viewmat"][i]).reshape(3, 4)[:, :3].T
+                            @ np.asarray(scene["viewmat"][i]).reshape(3, 4)[:, 3])
+                          for i in range(self.n_cams)])
+            extent = 1.1 * float(np.max(np.linalg.norm(c - c.mean(0), axis=1)))
+        self.lr = learning_rates(extent)
+        Vb = max(len(b) for b in self.batches)
+        P = max(int(sum(int(self.wh_all[v, 0]) * int(self.wh_all[v, 1]) for v in b))
+                for b in self.batches)
+        tiles = max(int(sum(((self.wh_all[v, 0] + 15) // 16) * ((self.wh_all[v, 1] + 15) // 16)
+                            for v in b)) for b in self.batches)
+        tiles = max(tiles, 4 * tiles)  # room for the smallest tile shape
+        self.ctx = L.Context(max_pairs=Vb * self.N, max_isect=max_isect or 32 * P,
+                             max_tiles=tiles, max_views=Vb, max_cams=self.n_cams)
+        self.rgb = torch.empty((P, 3), device=device)
+        self.T = torch.empty((P,), device=device)
+        self.last = torch.empty((P,), device=device, dtype=torch.int32)
+        self.v_rgb = torch.empty((P, 3), device=device)
+        self.loss = torch.zeros((2,), device=device)
+        self.grads = {k: torch.empty_like(v) for k, v in self.params.items()}
+        self.v_X = torch.zeros_like(self.X)
+        self.v_tw_cur = torch.zeros_like(self.twist)
+        self.v_tw = torch.zeros_like(self.twist)
+        self.m = {k: torch.zeros_like(v) for k, v in self._opt_params().items()}
+        self.v = {k: torch.zeros_like(v) for k, v in self._opt_params().items()}
+        self.step_count = 0
+        self.cams = [L.Cameras(self.viewmat, self.intr, self.wh_all[b], index=b) for b in self.batches]
+        self.g = L.make_gaussians(*(self.params[k] for k in PARAM_KEYS), self.sh_degree)
+        self.gg = L.make_grads(*(self.grads[k] for k in PARAM_KEYS))
+
+    def _opt_params(self):
+        d = dict(self.params)
+        d["twist"] = self.twist
+        d["X"] = self.X
+        return d
+
+    def _opt_grads(self):
+        d = dict(self.grads)
+        d["twist"] = self.v_tw
+        d["X"] = self.v_X
+        return d
+
+    def forward_backward(self, b, timer=None):
+        """a1-a9 and the twist chain, for batch b.  `timer(name)` brackets calls."""
+        t = timer or (lambda name: _Null())
+        cams = self.cams[b]
+        P = cams.n_pixels
+        s = self.settings
+        with t("pose_compose"):
+            L.gs_pose_compose(self.twist, self.base, self.viewmat)
+        with t("project"):
+            L.gs_project(self.ctx, self.g, cams, s)
+        with t("bin_sort"):
+            L.gs_bin_sort(self.ctx, cams, self.N, s)
+        with t("render_fwd"):
+            L.gs_render_fwd(self.ctx, cams, s, None, self.rgb, self.T, self.last)
+        self.loss.zero_()
+        self.v_tw_cur.zero_()
+        self.v_X.zero_()
+        with t("l1"):
+            L.gs_l1_loss_grad(self.ctx, cams, self.rgb, self.targets[b], self.v_rgb, self.loss[0:1])
+        with t("raster_bwd"):
+            L.gs_raster_bwd(self.ctx, cams, s, None, self.T, self.last, self.v_rgb)
+        with t("project_bwd"):
+            L.gs_project_bwd(self.ctx, self.g, cams, s, self.gg, self.v_tw_cur)
+        with t("track"):
+            L.track_reproj_fwd_bwd(self.ctx, self.X, self.viewmat, self.intr, self.obs_cam,
+                                   self.obs_pt, self.obs_xy, self.delta, self.lam, 0.01,
+                                   self.loss[1:2], self.v_X, self.v_tw_cur)
+        with t("pose_compose_bwd"):
+            L.gs_pose_compose_bwd(self.twist, self.v_tw_cur, self.v_tw)
+        del P
+
+    def adam(self, timer=None, step=None):
+        t = timer or (lambda name: _Null())
+        if step is None:
+            self.step_count += 1
+            step = self.step_count
+        p, g = self._opt_params(), self._opt_grads()
+        groups = [(p[k], g[k], self.m[k], self.v[k], self.lr[k]) for k in p]
+        with t("adam"):
+            L.gs_adam_step(groups, step)
+
+    def run(self, b, timer=None, step=None):
+        self.forward_backward(b, timer)
+        self.adam(timer, step)
+
+
+class _Null:
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        return False

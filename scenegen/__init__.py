@@ -3,8 +3,8 @@
 This module only draws inputs.  It holds none of the renderer's arithmetic:
 no covariance, no EWA projection, no spherical harmonics, no compositing and
 no gradients.  The one piece of geometry it carries is a pinhole placement
-(``_pixel_of``) used to put synthetic feature observations where a camera
-would see a track point; both the oracle and the HIP path then read the same
+(``_pixel_of`` and its vectorised form in ``make_tracks``) used to put
+synthetic feature observations where a camera would see a track point; both the oracle and the HIP path then read the same
 observation arrays, so neither depends on it for its own correctness.
 
 Every array is drawn with numpy's PCG64 generator, in float64, and cast to
@@ -258,59 +258,59 @@ def blob_scene(seed, resolutions, N, sh_degree=3, log_scale_mu=-4.0, log_scale_s
 
 
 def make_tracks(rng, n_tracks, viewmat, intr, wh, max_len, n_cand=None, n_blobs=50,
-                points=None):
+                points=None, chunk=4096):
     """Track points seen by 2 + Geom(0.3) cameras (capped at ``max_len``).
 
-    Each point is observed by cameras in whose image it falls, chosen among
-    all cameras (or among ``n_cand`` random candidates for large camera sets);
-    observations get N(0, 1 px) noise per axis.
+    Each point is observed by cameras in whose image it falls, chosen uniformly
+    among all cameras (or among ``n_cand`` random candidate cameras for large
+    camera sets); points seen by fewer than two cameras are dropped.
+    Observations get N(0, 1 px) noise per axis.
     """
     V = viewmat.shape[0]
     X = points if points is not None else _blob_points(rng, n_tracks, n_blobs)
-    L = np.minimum(max_len, 2 + rng.geometric(0.3, size=n_tracks) - 1)
+    L = np.minimum(max_len, 1 + rng.geometric(0.3, size=n_tracks))
+    M3 = viewmat.astype(np.float64).reshape(V, 3, 4)
+    Rall, tall = M3[:, :, :3], M3[:, :, 3]
+    fi = intr.astype(np.float64)
     cams, pts, xys = [], [], []
     keep = np.zeros(n_tracks, dtype=bool)
-    chunk = 4096
     for s in range(0, n_tracks, chunk):
         e = min(n_tracks, s + chunk)
-        Xi = X[s:e]
+        n = e - s
         if n_cand is None:
-            cand = np.broadcast_to(np.arange(V), (e - s, V))
+            cand = np.broadcast_to(np.arange(V), (n, V))
+            dup = np.zeros(cand.shape, dtype=bool)
         else:
-            cand = rng.integers(0, V, size=(e - s, n_cand))
-        vis = np.zeros(cand.shape, dtype=bool)
-        uvs = np.zeros(cand.shape + (2,))
-        for ci in np.unique(cand):
-            m = cand == ci
-            rows = np.nonzero(m.any(axis=1))[0]
-            R = viewmat[ci, :].reshape(3, 4)[:, :3].astype(np.float64)
-            t = viewmat[ci, :].reshape(3, 4)[:, 3].astype(np.float64)
-            fx, fy, cx, cy = intr[ci].astype(np.float64)
-            uv, z = _pixel_of(R, t, fx, fy, cx, cy, Xi[rows])
-            W, H = wh[ci]
-            ok = (z > 0.01) & (uv[:, 0] >= 0) & (uv[:, 0] < W) & (uv[:, 1] >= 0) & (uv[:, 1] < H)
-            for jj, r in enumerate(rows):
-                cols = np.nonzero(m[r])[0]
-                vis[r, cols] = ok[jj]
-                uvs[r, cols] = uv[jj]
-        for r in range(e - s):
-            vc, first = np.unique(cand[r][vis[r]], return_index=True)
-            if vc.size < 2:
-                continue
-            uv_r = uvs[r][vis[r]][first]
-            k = min(int(L[s + r]), vc.size)
-            pick = np.sort(rng.choice(vc.size, size=k, replace=False))
-            keep[s + r] = True
-            cams.append(vc[pick])
-            pts.append(np.full(k, s + r))
-            xys.append(uv_r[pick] + rng.normal(0.0, 1.0, size=(k, 2)))
+            cand = np.sort(rng.integers(0, V, size=(n, n_cand)), axis=1)
+            dup = np.zeros(cand.shape, dtype=bool)
+            dup[:, 1:] = cand[:, 1:] == cand[:, :-1]
+        Xc = np.einsum("ncij,nj->nci", Rall[cand], X[s:e]) + tall[cand]
+        z = Xc[..., 2]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            u = fi[cand, 0] * Xc[..., 0] / z + fi[cand, 2]
+            v = fi[cand, 1] * Xc[..., 1] / z + fi[cand, 3]
+        W = wh[cand, 0]
+        H = wh[cand, 1]
+        vis = (z > 0.01) & (u >= 0) & (u < W) & (v >= 0) & (v < H) & ~dup
+        key = rng.uniform(size=vis.shape)
+        key[~vis] = 2.0
+        order = np.argsort(key, axis=1)
+        nvis = vis.sum(axis=1)
+        k = np.minimum(L[s:e], nvis)
+        ok = nvis >= 2
+        rank = np.arange(cand.shape[1])[None, :]
+        sel = (rank < k[:, None]) & ok[:, None]
+        rows, cols = np.nonzero(sel)
+        j = order[rows, cols]
+        cams.append(cand[rows, j])
+        pts.append(s + rows)
+        xys.append(np.stack([u[rows, j], v[rows, j]], axis=1))
+        keep[s:e] = ok
     cams = np.concatenate(cams)
     pts = np.concatenate(pts)
-    xys = np.concatenate(xys)
-    # renumber the kept tracks densely
-    new_id = np.cumsum(keep) - 1
-    pts = new_id[pts]
-    return _sorted_obs(X[keep], cams, pts, xys)
+    xys = np.concatenate(xys) + rng.normal(0.0, 1.0, size=(len(cams), 2))
+    new_id = np.cumsum(keep) - 1          # renumber the kept tracks densely
+    return _sorted_obs(X[keep], cams, new_id[pts], xys)
 
 
 def perturb_poses(rng, viewmat, rho_sd=0.005, phi_sd=0.002):
@@ -329,16 +329,19 @@ def perturb_poses(rng, viewmat, rho_sd=0.005, phi_sd=0.002):
 def synthetic_records(seed, V, wh, N, tile=(16, 16), depth_ties=True):
     """Projected-splat records for testing the bin/sort step on its own.
 
-    Every splat is either tiny (its support stays inside the tile holding its
-    centre, which is kept away from tile edges) or huge (it covers the whole
-    image), so which tiles a splat meets is never a near-tie.  Depths are drawn
-    from a small set of values when ``depth_ties`` so equal depths occur often.
+    Every splat is either tiny (its support stays inside the tile quadrant
+    -- a tile_w/2 x tile_h/2 block -- holding its centre, which is kept at least
+    1 px away from the quadrant's pixel-centre edges) or huge (it covers the
+    whole image), so which tiles and quadrants a splat meets is never a
+    near-tie.  Depths are drawn from a small set of values when ``depth_ties``
+    so equal depths occur often.
 
     Returns float arrays laid out as the projected record (mean2d [V*N,2],
     conic [V*N,3], opacity [V*N], depth [V*N], rgb [V*N,3]) and ``valid``.
     """
     rng = _rng(seed)
     tw, th = tile
+    qw, qh = tw // 2, th // 2
     VN = V * N
     mean2d = np.zeros((VN, 2))
     conic = np.zeros((VN, 3))
@@ -347,19 +350,18 @@ def synthetic_records(seed, V, wh, N, tile=(16, 16), depth_ties=True):
     kind = rng.uniform(size=VN)
     for v in range(V):
         W, H = wh[v]
-        gx, gy = (W + tw - 1) // tw, (H + th - 1) // th
+        gx, gy = (W + qw - 1) // qw, (H + qh - 1) // qh     # quadrant grid
         sl = slice(v * N, (v + 1) * N)
-        tx = rng.integers(0, gx, size=N)
-        ty = rng.integers(0, gy, size=N)
-        # centres inside the tile, at least 4 px from its pixel-centre edges
-        x0 = tx * tw + 0.5
-        x1 = np.minimum(tx * tw + tw, W) - 0.5
-        y0 = ty * th + 0.5
-        y1 = np.minimum(ty * th + th, H) - 0.5
+        qx = rng.integers(0, gx, size=N)
+        qy = rng.integers(0, gy, size=N)
+        x0 = qx * qw + 0.5
+        x1 = np.minimum(qx * qw + qw, W) - 0.5
+        y0 = qy * qh + 0.5
+        y1 = np.minimum(qy * qh + qh, H) - 0.5
         fx = rng.uniform(size=N)
         fy = rng.uniform(size=N)
-        mx = np.where(x1 - x0 > 8, x0 + 4 + fx * (x1 - x0 - 8), 0.5 * (x0 + x1))
-        my = np.where(y1 - y0 > 8, y0 + 4 + fy * (y1 - y0 - 8), 0.5 * (y0 + y1))
+        mx = np.where(x1 - x0 > 2, x0 + 1 + fx * (x1 - x0 - 2), 0.5 * (x0 + x1))
+        my = np.where(y1 - y0 > 2, y0 + 1 + fy * (y1 - y0 - 2), 0.5 * (y0 + y1))
         mean2d[sl, 0] = mx
         mean2d[sl, 1] = my
     big = kind[:] > 0.97

@@ -105,16 +105,18 @@ def test_bin_sort_bit_exact_on_synthetic_records(gs, tile):
     gs.gs_bin_sort(ctx, cams, N, s, drec)
     st = ctx.status()
     assert st["flags"] == 0
-    ranges_o, ids_o = oracle.bin_sort(wh, tile, r["valid"], r["mean2d"], r["conic"],
-                                      r["opacity"], r["depth"])
+    ranges_o, ids_o, masks_o = oracle.bin_sort(wh, tile, r["valid"], r["mean2d"], r["conic"],
+                                               r["opacity"], r["depth"], with_masks=True)
     assert st["n_isect"] == len(ids_o)
     b = ctx.buffers()
     T = b["n_tiles"]
     assert T == ranges_o.shape[0]
     ranges = _read_i32(b["tile_ranges"], 2 * T).reshape(T, 2)
-    ids = _read_i32(b["isect_ids"], len(ids_o))
+    ent = _read_i32(b["isect_ids"], len(ids_o)).view(np.uint32)
     assert np.array_equal(ranges, ranges_o.astype(np.int32))
-    assert np.array_equal(ids, ids_o)
+    # an entry is the pair index (low 28 bits) and the quadrant mask (top 4)
+    assert np.array_equal(ent & 0x0FFFFFFF, ids_o.astype(np.uint32))
+    assert np.array_equal(ent >> 28, masks_o.astype(np.uint32))
 
 
 def _read_i32(ptr, n):
@@ -132,7 +134,7 @@ def test_bin_sort_real_scene_lists(gs):
     b = ctx.buffers()
     nt = b["n_tiles"]
     ranges = _read_i32(b["tile_ranges"], 2 * nt).reshape(nt, 2)
-    ids = _read_i32(b["isect_ids"], st["n_isect"])
+    ids = (_read_i32(b["isect_ids"], st["n_isect"]).view(np.uint32) & 0x0FFFFFFF).astype(np.int64)
     pr = oracle.project(sc)
     inner_r, inner = oracle.bin_sort(sc["wh"], (16, 16), pr["valid"], pr["mean2d"], pr["conic"],
                                      pr["opacity"], pr["depth"].astype(np.float32), margin=-0.05)

@@ -585,8 +585,9 @@ def test_adam_first_step_and_constant_gradient():
 # ----------------------------------------------------------------- tile lists
 
 def test_tile_membership_against_dense_sampling():
-    # A pair belongs to a tile iff some point of the tile's pixel-centre
-    # rectangle has alpha >= 1/255.  Brute force: sample the rectangle densely.
+    # A pair belongs to a tile iff some point of one of the tile's quadrant
+    # rectangles (spanned by the quadrant's pixel centres) has alpha >= 1/255.
+    # Brute force: sample every quadrant rectangle densely.
     rng = np.random.default_rng(60)
     W, H, N = 70, 45, 40
     mean2d = np.stack([rng.uniform(-10, W + 10, N), rng.uniform(-10, H + 10, N)], 1)
@@ -598,23 +599,33 @@ def test_tile_membership_against_dense_sampling():
     opac = rng.uniform(0.02, 0.99, N)
     depth = rng.uniform(1, 5, N).astype(np.float32)
     valid = np.ones(N, np.int32)
-    ranges, ids = oracle.bin_sort(np.array([[W, H]]), (16, 16), valid, mean2d, conic, opac, depth)
+    ranges, ids, masks = oracle.bin_sort(np.array([[W, H]]), (16, 16), valid, mean2d, conic, opac,
+                                         depth, with_masks=True)
     gx = (W + 15) // 16
     for t in range(ranges.shape[0]):
         tx, ty = t % gx, t // gx
-        xs = np.linspace(tx * 16 + 0.5, min(tx * 16 + 16, W) - 0.5, 61)
-        ys = np.linspace(ty * 16 + 0.5, min(ty * 16 + 16, H) - 0.5, 61)
-        X, Y = np.meshgrid(xs, ys)
-        members = set(ids[ranges[t, 0]:ranges[t, 1]].tolist())
+        members = dict(zip(ids[ranges[t, 0]:ranges[t, 1]].tolist(),
+                           masks[ranges[t, 0]:ranges[t, 1]].tolist()))
         for g in range(N):
-            dx, dy = mean2d[g, 0] - X, mean2d[g, 1] - Y
-            s = 0.5 * (conic[g, 0] * dx * dx + conic[g, 2] * dy * dy) + conic[g, 1] * dx * dy
-            smin = s.min()
-            thr = np.log(opac[g] * 255)
-            if smin < thr - 1e-6:
-                assert g in members, (t, g)
-            if g in members:
-                assert smin < thr + 0.05 * max(1.0, thr), (t, g)   # the grid is coarse
+            want = 0
+            loose = 0
+            for q in range(4):
+                xs, ys = tx * 16 + (q & 1) * 8, ty * 16 + (q >> 1) * 8
+                if xs >= W or ys >= H:
+                    continue
+                xq = np.linspace(xs + 0.5, min(xs + 8, W) - 0.5, 41)
+                yq = np.linspace(ys + 0.5, min(ys + 8, H) - 0.5, 41)
+                X, Y = np.meshgrid(xq, yq)
+                dx, dy = mean2d[g, 0] - X, mean2d[g, 1] - Y
+                sg = 0.5 * (conic[g, 0] * dx * dx + conic[g, 2] * dy * dy) + conic[g, 1] * dx * dy
+                thr = np.log(opac[g] * 255)
+                if sg.min() < thr - 1e-6:
+                    want |= 1 << q
+                if sg.min() < thr + 0.05 * max(1.0, thr):   # the grid is coarse
+                    loose |= 1 << q
+            m = members.get(g, 0)
+            assert (m & want) == want, (t, g, m, want)
+            assert (m & ~loose) == 0, (t, g, m, loose)
         # order: float32 depth bits, then index
         lst = ids[ranges[t, 0]:ranges[t, 1]]
         keys = [(depth[i].view(np.uint32), i) for i in lst]
