@@ -110,7 +110,8 @@ typedef struct {
     float alpha_max;          /* 0.99 */
     float t_min;              /* 1e-4 */
     int32_t grad_accumulate;  /* 0: gs_render_bwd overwrites Gaussian grads; 1: adds */
-    int32_t tile_order;       /* 0: natural tile order; 1: heaviest tiles first */
+    int32_t tile_order;       /* 0: natural tile order; 1: launch the raster kernels on
+                                 the tiles in order of decreasing list length */
 } gs_settings;
 
 typedef struct {
@@ -181,6 +182,13 @@ gs_status gs_ctx_reset_status(gs_ctx* ctx, void* stream);
  * gs_bin_sort (HOST value). */
 gs_status gs_ctx_buffers(gs_ctx* ctx, float** records, int32_t** isect_ids,
                          int32_t** tile_ranges, int64_t* n_tiles);
+
+/* Workload statistics of the last gs_render_fwd (device pointers, valid for
+ * the context's lifetime): tile_contrib[t] = number of (pixel, splat) pairs
+ * that contributed to tile t; tile_order = launch order of the tiles when the
+ * last gs_bin_sort ran with tile_order = 1 (*ordered = 1), heaviest first. */
+gs_status gs_ctx_tile_stats(gs_ctx* ctx, const int32_t** tile_contrib,
+                            const uint32_t** tile_order, int32_t* ordered);
 
 /* Project every (view, Gaussian) pair (render step of Algorithm 1; the
  * definition above).  Reads each Gaussian's parameters once for all V views and

@@ -70,7 +70,7 @@ class gs_adam_group(ctypes.Structure):
 
 EXPORTS = [
     "gs_strerror", "gs_default_settings", "gs_ctx_create", "gs_ctx_destroy", "gs_ctx_status",
-    "gs_ctx_reset_status", "gs_ctx_buffers", "gs_project", "gs_bin_sort", "gs_render_fwd",
+    "gs_ctx_reset_status", "gs_ctx_buffers", "gs_ctx_tile_stats", "gs_project", "gs_bin_sort", "gs_render_fwd",
     "gs_render_bwd", "gs_raster_bwd", "gs_project_bwd", "gs_l1_loss_grad", "track_reproj_fwd_bwd", "gs_pose_compose",
     "gs_pose_compose_bwd", "gs_adam_step",
 ]
@@ -105,6 +105,8 @@ def load():
     lib.gs_ctx_reset_status.argtypes = [c_vp, c_vp]
     lib.gs_ctx_buffers.argtypes = [c_vp, ctypes.POINTER(c_vp), ctypes.POINTER(c_vp),
                                    ctypes.POINTER(c_vp), ctypes.POINTER(ctypes.c_int64)]
+    lib.gs_ctx_tile_stats.argtypes = [c_vp, ctypes.POINTER(c_vp), ctypes.POINTER(c_vp),
+                                      ctypes.POINTER(ctypes.c_int32)]
     lib.gs_project.argtypes = [c_vp, ctypes.POINTER(gs_gaussians), ctypes.POINTER(gs_cameras),
                                ctypes.POINTER(gs_settings), c_vp]
     lib.gs_bin_sort.argtypes = [c_vp, ctypes.POINTER(gs_cameras), ctypes.c_int32,
@@ -269,6 +271,15 @@ class Context:
                                                        ctypes.byref(nt)))
         return dict(records=rec.value, isect_ids=ids.value, tile_ranges=rng.value,
                     n_tiles=nt.value)
+
+
+def gs_ctx_tile_stats(ctx):
+    """Device addresses of the per-tile contributor counts and the tile order."""
+    a, b = c_vp(), c_vp()
+    o = ctypes.c_int32()
+    _check("gs_ctx_tile_stats", load().gs_ctx_tile_stats(ctx.handle, ctypes.byref(a),
+                                                         ctypes.byref(b), ctypes.byref(o)))
+    return dict(tile_contrib=a.value, tile_order=b.value, ordered=bool(o.value))
 
 
 def gs_project(ctx, gaussians, cams, settings, stream=None):

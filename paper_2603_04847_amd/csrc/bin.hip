@@ -297,10 +297,22 @@ __global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t* __restrict__ 
     }
 }
 
+// heaviest tiles first: key = 2^24 - 1 - min(list length, 2^24 - 1), stable
+// radix on 24 bits, so equal lengths keep the natural tile order
+__global__ __launch_bounds__(kBlock) void k_tile_keys(const int32_t* __restrict__ ranges, int64_t T,
+                                                      uint32_t* __restrict__ key,
+                                                      uint32_t* __restrict__ val) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= T) return;
+    const uint32_t len = (uint32_t)max(ranges[2 * t + 1] - ranges[2 * t], 0);
+    key[t] = 0xFFFFFFu - min(len, 0xFFFFFFu);
+    val[t] = (uint32_t)t;
+}
+
 }  // namespace
 
 hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp,
-                      const float* records, hipStream_t st) {
+                      const float* records, int tile_order, hipStream_t st) {
     const int64_t npairs = (int64_t)vt.V * N;
     const float4* rec = reinterpret_cast<const float4*>(records ? records : c->rec);
     const int64_t T = vt.tile_off[vt.V];
@@ -336,6 +348,23 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
         hipLaunchKernelGGL(k_ranges, dim3(gi), dim3(kBlock), 0, st, c->ik[side2], used, c->ranges,
                            (uint32_t)T);
         c->ids = reinterpret_cast<const int32_t*>(c->iv[side2]);
+        c->ordered = false;
+        if (tile_order && T > 0) {
+            hipLaunchKernelGGL(k_tile_keys, dim3((unsigned)((T + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                               st, c->ranges, T, c->tk[0], c->tile_order);
+            // sort (key, tile) pairs: tile_order holds the values of the first buffer pair
+            uint32_t* kk[2] = {c->tk[0], c->tk[1]};
+            uint32_t* vv[2] = {c->tile_order, reinterpret_cast<uint32_t*>(c->tile_contrib)};
+            // 32 bits = 4 passes: the result lands back in tile_order
+            const int side3 = radix_sort_pairs(kk[0], vv[0], kk[1], vv[1], T, nullptr, 0, 32, c->hist,
+                                               c->scan_scratch, st, &e);
+            if (e != hipSuccess) return e;
+            if (side3 == 1) {
+                e = hipMemcpyAsync(c->tile_order, vv[1], sizeof(uint32_t) * T, hipMemcpyDeviceToDevice, st);
+                if (e != hipSuccess) return e;
+            }
+            c->ordered = true;
+        }
     } else {
         c->ids = reinterpret_cast<const int32_t*>(c->iv[0]);
     }

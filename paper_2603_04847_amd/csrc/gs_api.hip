@@ -1,6 +1,8 @@
 // Host side of the C ABI declared in gs.h: context and workspace, argument
 // validation, error codes, and dispatch to the kernel launchers.
 #include <math.h>
+
+#include <algorithm>
 #include <stdlib.h>
 #include <string.h>
 
@@ -149,7 +151,7 @@ gs_status gs_ctx_create(gs_ctx** out, const gs_capacity* cap) {
     c.cap = *cap;
     hipGetDevice(&c.device);
     const int64_t P = cap->max_pairs, I = cap->max_isect, T = cap->max_tiles;
-    const int64_t sortmax = P > I ? P : I;
+    const int64_t sortmax = std::max(P, std::max(I, T));
     hipError_t e = hipSuccess;
     auto A = [&](hipError_t r) {
         if (e == hipSuccess) e = r;
@@ -166,6 +168,9 @@ gs_status gs_ctx_create(gs_ctx** out, const gs_capacity* cap) {
     }
     A(dalloc(&c.ranges, (size_t)2 * T));
     A(dalloc(&c.tile_order, (size_t)T));
+    A(dalloc(&c.tk[0], (size_t)T));
+    A(dalloc(&c.tk[1], (size_t)T));
+    A(dalloc(&c.tile_contrib, (size_t)T));
     const size_t hw = gs::radix_hist_words(sortmax);
     A(dalloc(&c.hist, hw));
     A(dalloc(&c.scan_scratch, gs::scan_scratch_words((int64_t)hw)));
@@ -196,7 +201,8 @@ gs_status gs_ctx_destroy(gs_ctx* h) {
     if (!h) return GS_ERR_INVALID_ARG;
     gs::Ctx& c = h->c;
     void* ptrs[] = {c.rec, c.grad2d, c.cnt, c.off, c.pk[0], c.pk[1], c.pv[0], c.pv[1],
-                    c.ik[0], c.ik[1], c.iv[0], c.iv[1], c.ranges, c.tile_order, c.hist,
+                    c.ik[0], c.ik[1], c.iv[0], c.iv[1], c.ranges, c.tile_order, c.tk[0], c.tk[1],
+                    c.tile_contrib, c.hist,
                     c.scan_scratch, c.scalars, c.twist_render, c.twist_track, c.loss_acc, c.diag};
     hipDeviceSynchronize();
     for (void* p : ptrs)
@@ -233,6 +239,15 @@ gs_status gs_ctx_buffers(gs_ctx* h, float** records, int32_t** isect_ids, int32_
     return GS_OK;
 }
 
+gs_status gs_ctx_tile_stats(gs_ctx* h, const int32_t** tile_contrib, const uint32_t** tile_order,
+                            int32_t* ordered) {
+    if (!h) return GS_ERR_INVALID_ARG;
+    if (tile_contrib) *tile_contrib = h->c.tile_contrib;
+    if (tile_order) *tile_order = h->c.tile_order;
+    if (ordered) *ordered = h->c.ordered ? 1 : 0;
+    return GS_OK;
+}
+
 gs_status gs_project(gs_ctx* h, const gs_gaussians* g, const gs_cameras* cams, const gs_settings* s,
                      void* stream) {
     if (!h) return GS_ERR_INVALID_ARG;
@@ -258,7 +273,7 @@ gs_status gs_bin_sort(gs_ctx* h, const gs_cameras* cams, int32_t N, const gs_set
     const gs::ViewTable vt = gs::make_view_table(cams->wh, cams->V, s->tile_w, s->tile_h, cams->index);
     if (vt.tile_off[vt.V] > h->c.cap.max_tiles) return GS_ERR_CAPACITY;
     const gs::RasterParams rp = gs::make_raster_params(s);
-    return from_hip(gs::launch_bin(&h->c, vt, N, rp, records, (hipStream_t)stream));
+    return from_hip(gs::launch_bin(&h->c, vt, N, rp, records, s->tile_order, (hipStream_t)stream));
 }
 
 static gs_status check_bins_match(const gs::Ctx& c, const gs_cameras* cams, const gs_settings* s) {

@@ -276,7 +276,7 @@ int radix_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int
 
 // bin.hip
 hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp,
-                      const float* records, hipStream_t st);
+                      const float* records, int tile_order, hipStream_t st);
 
 // project.hip
 hipError_t launch_project_fwd(Ctx* c, const gs_gaussians* g, const gs_cameras* cams,
@@ -327,7 +327,9 @@ struct Ctx {
     uint32_t* ik[2];       // [max_isect] tile keys (ping-pong)
     uint32_t* iv[2];       // [max_isect] pair indices (ping-pong)
     int32_t* ranges;       // [max_tiles][2]
-    uint32_t* tile_order;  // [max_tiles]
+    uint32_t* tile_order;  // [max_tiles] launch order of the tiles (heaviest first)
+    uint32_t* tk[2];       // [max_tiles] sort scratch for the tile order
+    int32_t* tile_contrib; // [max_tiles] contributing (pixel, splat) pairs per tile
     uint32_t* hist;        // radix histograms
     uint32_t* scan_scratch;
     uint32_t* scalars;     // small device counters
@@ -339,6 +341,7 @@ struct Ctx {
     const int32_t* ids;    // sorted pair indices (points into iv[])
     int64_t n_tiles;
     int bin_V, bin_N, bin_tw, bin_th;
+    bool ordered;          // tile_order holds the order of the last bin step
 };
 
 }  // namespace gs

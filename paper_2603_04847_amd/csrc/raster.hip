@@ -70,7 +70,8 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
                                                    RasterParams rp, const float* __restrict__ bg,
                                                    float* __restrict__ out_rgb,
                                                    float* __restrict__ out_T,
-                                                   int32_t* __restrict__ out_last) {
+                                                   int32_t* __restrict__ out_last,
+                                                   int32_t* __restrict__ tile_contrib) {
     using TM = TileMap<TW, TH>;
     constexpr int PPL = TM::PPL;
     const int t = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
@@ -98,6 +99,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
     }
     const int s = ranges[2 * t], e = ranges[2 * t + 1];
     const float amin = rp.alpha_min, amax = rp.alpha_max, tmin = rp.t_min;
+    int ncontrib = 0;
     for (int b = s; b < e; b += kWave) {
         bool alive = false;
 #pragma unroll
@@ -124,31 +126,34 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
             const float cr = bcast(rb.w, i), cg = bcast(rc.x, i), cb = bcast(rc.y, i);
             const float sc = bcast(cut, i);
             const int pos = b + i - s + 1;
-            // one branch per slot (skipped by the whole wave when no lane is in
-            // range); inside it the update is branch-free
 #pragma unroll
             for (int k = 0; k < PPL; k++) {
                 if (!(m & TM::quads(k))) continue;  // wave-uniform
+                if (done[k]) continue;
                 const float dx = mx - fx[k];
                 const float dy = my - fy[k];
                 const float sig = splat_sigma(A, B, C, dx, dy);
-                if (!done[k] && sig >= 0.f && sig <= sc) {
-                    const float alpha = fminf(amax, o * fast_exp_neg(sig));
-                    const float Tn = T[k] * (1.f - alpha);
-                    const bool live = alpha >= amin;
-                    const bool stop = live && Tn < tmin;
-                    const bool use = live && !stop;
-                    done[k] = stop;
-                    const float w = use ? alpha * T[k] : 0.f;
-                    C0[k] = __builtin_fmaf(cr, w, C0[k]);
-                    C1[k] = __builtin_fmaf(cg, w, C1[k]);
-                    C2[k] = __builtin_fmaf(cb, w, C2[k]);
-                    T[k] = use ? Tn : T[k];
-                    last[k] = use ? pos : last[k];
+                if (sig < 0.f || sig > sc) continue;
+                const float alpha = fminf(amax, o * fast_exp_neg(sig));
+                if (alpha < amin) continue;
+                const float Tn = T[k] * (1.f - alpha);
+                if (Tn < tmin) {
+                    done[k] = true;
+                    continue;
                 }
+                const float w = alpha * T[k];
+                C0[k] = __builtin_fmaf(cr, w, C0[k]);
+                C1[k] = __builtin_fmaf(cg, w, C1[k]);
+                C2[k] = __builtin_fmaf(cb, w, C2[k]);
+                T[k] = Tn;
+                last[k] = pos;
+                ncontrib++;
             }
         }
     }
+    // contributing (pixel, splat) pairs of the tile: a workload statistic
+    for (int sh = 32; sh > 0; sh >>= 1) ncontrib += __shfl_xor(ncontrib, sh, kWave);
+    if (lane == 0) tile_contrib[t] = ncontrib;
     const float b0 = bg ? bg[0] : 0.f, b1 = bg ? bg[1] : 0.f, b2 = bg ? bg[2] : 0.f;
 #pragma unroll
     for (int k = 0; k < PPL; k++) {
@@ -334,7 +339,7 @@ hipError_t fwd_impl(Ctx* c, const ViewTable& vt, const RasterParams& rp, const f
                     hipStream_t st) {
     hipLaunchKernelGGL((k_render_fwd<TW, TH>), dim3((unsigned)c->n_tiles), dim3(64), 0, st,
                        reinterpret_cast<const float4*>(c->rec), c->ids, c->ranges, order, vt, rp,
-                       bg, rgb, T_final, last);
+                       bg, rgb, T_final, last, c->tile_contrib);
     return hipGetLastError();
 }
 
@@ -353,7 +358,7 @@ hipError_t bwd_impl(Ctx* c, const ViewTable& vt, const RasterParams& rp, const f
 hipError_t launch_render_fwd(Ctx* c, const ViewTable& vt, const RasterParams& rp, const float* bg,
                              float* rgb, float* T_final, int32_t* last, hipStream_t st) {
     if (c->n_tiles <= 0) return hipSuccess;
-    const uint32_t* order = nullptr;
+    const uint32_t* order = c->ordered ? c->tile_order : nullptr;
     const int TW = rp.tile_w, TH = rp.tile_h;
     if (TW == 16 && TH == 16) return fwd_impl<16, 16>(c, vt, rp, bg, rgb, T_final, last, order, st);
     if (TW == 16 && TH == 8) return fwd_impl<16, 8>(c, vt, rp, bg, rgb, T_final, last, order, st);
@@ -366,7 +371,7 @@ hipError_t launch_render_bwd(Ctx* c, const ViewTable& vt, const RasterParams& rp
                              const float* T_final, const int32_t* last, const float* v_rgb,
                              hipStream_t st) {
     if (c->n_tiles <= 0) return hipSuccess;
-    const uint32_t* order = nullptr;
+    const uint32_t* order = c->ordered ? c->tile_order : nullptr;
     const int TW = rp.tile_w, TH = rp.tile_h;
     if (TW == 16 && TH == 16) return bwd_impl<16, 16>(c, vt, rp, bg, T_final, last, v_rgb, order, st);
     if (TW == 16 && TH == 8) return bwd_impl<16, 8>(c, vt, rp, bg, T_final, last, v_rgb, order, st);

@@ -118,36 +118,44 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
     return peers;
 }
 
+// Items of a block: wave w owns the contiguous chunk [base + 1024 w, base +
+// 1024 (w+1)), read 64 at a time; so (wave, step, lane) order is index order and
+// ranks can be kept per wave without block barriers.
+__device__ __forceinline__ int64_t item_index(int64_t base, int w, int i, int lane) {
+    return base + (int64_t)w * (kWave * kItems) + i * kWave + lane;
+}
+
 __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                          const uint32_t* __restrict__ d_n,
                                                          int64_t max_n, int shift,
                                                          uint32_t* __restrict__ hist,
                                                          uint32_t nblocks) {
-    __shared__ uint32_t s_h[256];
+    __shared__ uint32_t s_h[kWaves][256];
     const uint32_t n = dev_count(d_n, max_n);
-    s_h[threadIdx.x] = 0;
+    const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
+    for (int q = 0; q < kWaves; q++) s_h[q][tid] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kTile;
     if (base < n) {
 #pragma unroll 4
         for (int i = 0; i < kItems; i++) {
-            const int64_t j = base + i * kThreads + threadIdx.x;
+            const int64_t j = item_index(base, w, i, lane);
             const bool valid = j < n;
             const uint32_t d = valid ? (keys[j] >> shift) & 0xFFu : 0u;
             const uint64_t peers = match_digit(d, valid);
-            if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&s_h[d], (uint32_t)__popcll(peers));
+            // one lane per digit adds the digit's count in this wave's histogram
+            if (valid && (peers & lanemask_lt()) == 0) s_h[w][d] += (uint32_t)__popcll(peers);
         }
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = s_h[threadIdx.x];
+    hist[(int64_t)tid * nblocks + blockIdx.x] = s_h[0][tid] + s_h[1][tid] + s_h[2][tid] + s_h[3][tid];
 }
 
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ d_n, int64_t max_n, int shift,
     const uint32_t* __restrict__ hist, uint32_t nblocks) {
-    __shared__ uint32_t s_cnt[kWaves][256];
-    __shared__ uint32_t s_run[256];
+    __shared__ uint32_t s_h[kWaves][256];  // per-wave digit counts, then offsets
     __shared__ uint32_t s_start[256];
     __shared__ uint32_t s_w[kWaves];
     __shared__ uint32_t s_key[kTile];
@@ -155,50 +163,44 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     const uint32_t n = dev_count(d_n, max_n);
     const int64_t base = (int64_t)blockIdx.x * kTile;
     if (base >= n) return;  // uniform over the block
-    const int tid = threadIdx.x, w = tid / kWave;
+    const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
     uint32_t k[kItems], v[kItems], rank[kItems];
 #pragma unroll
     for (int i = 0; i < kItems; i++) {
-        const int64_t j = base + i * kThreads + tid;
+        const int64_t j = item_index(base, w, i, lane);
         k[i] = j < n ? kin[j] : 0u;
         v[i] = j < n ? vin[j] : 0u;
     }
-    for (int r = 0; r < kWaves; r++) s_cnt[r][tid] = 0;
-    s_run[tid] = 0;
+    for (int q = 0; q < kWaves; q++) s_h[q][tid] = 0;
     __syncthreads();
+    // stable rank inside the wave's chunk: earlier steps (LDS count) + earlier lanes
+#pragma unroll
     for (int i = 0; i < kItems; i++) {
-        const int64_t j = base + i * kThreads + tid;
+        const int64_t j = item_index(base, w, i, lane);
         const bool valid = j < n;
         const uint32_t d = (k[i] >> shift) & 0xFFu;
         const uint64_t peers = match_digit(d, valid);
-        const uint32_t wr = __popcll(peers & lanemask_lt());
-        if (valid && wr == 0) s_cnt[w][d] = __popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t r = s_run[d] + wr;
-            for (int q = 0; q < w; q++) r += s_cnt[q][d];
-            rank[i] = r;
-        }
-        __syncthreads();
-        {
-            uint32_t add = 0;
-            for (int q = 0; q < kWaves; q++) {
-                add += s_cnt[q][tid];
-                s_cnt[q][tid] = 0;
-            }
-            s_run[tid] += add;
-        }
-        __syncthreads();
+        const uint32_t before = s_h[w][d];
+        rank[i] = before + (uint32_t)__popcll(peers & lanemask_lt());
+        if (valid && (peers & lanemask_lt()) == 0) s_h[w][d] = before + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    // per digit: offsets of the waves, then the block-wide exclusive scan
+    uint32_t run = 0;
+    for (int q = 0; q < kWaves; q++) {
+        const uint32_t c = s_h[q][tid];
+        s_h[q][tid] = run;
+        run += c;
     }
     uint32_t tot;
-    s_start[tid] = block_excl_scan(s_run[tid], s_w, tot);
+    s_start[tid] = block_excl_scan(run, s_w, tot);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kItems; i++) {
-        const int64_t j = base + i * kThreads + tid;
+        const int64_t j = item_index(base, w, i, lane);
         if (j < n) {
             const uint32_t d = (k[i] >> shift) & 0xFFu;
-            const uint32_t pos = s_start[d] + rank[i];
+            const uint32_t pos = s_start[d] + s_h[w][d] + rank[i];
             s_key[pos] = k[i];
             s_val[pos] = v[i];
         }

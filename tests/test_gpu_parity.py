@@ -175,6 +175,40 @@ def test_render_fwd_bitwise_independent_of_tile_shape(gs):
         assert np.array_equal(o, outs[0])
 
 
+def test_tile_order_and_contributor_counts(gs):
+    # Launching the tiles heaviest-first changes nothing in the image; the
+    # per-tile contributor counts equal the oracle's per-pixel counts summed
+    # over tiles free of ambiguous pixels.
+    sc = _parity_scene(seed=14)
+    a = _render(gs, sc)
+    ctx = _ctx(gs, sc)
+    b = _render(gs, sc, ctx=ctx, settings=gs.default_settings(tile_order=1))
+    assert np.array_equal(a[2].cpu().numpy(), b[2].cpu().numpy())
+    st = gs._lib.gs_ctx_tile_stats(ctx)
+    assert st["ordered"]
+    nt = ctx.buffers()["n_tiles"]
+    order = gs._lib.copy_to_host(st["tile_order"], nt, np.uint32)
+    assert np.array_equal(np.sort(order), np.arange(nt))
+    ranges = _read_i32(ctx.buffers()["tile_ranges"], 2 * nt).reshape(nt, 2)
+    lens = (ranges[:, 1] - ranges[:, 0])[order]
+    assert np.all(np.diff(lens) <= 0)
+    contrib = gs._lib.copy_to_host(st["tile_contrib"], nt, np.int32)
+    o = oracle.render_fwd_bwd(sc)
+    W, H = sc["wh"][0]
+    gx = (W + 15) // 16
+    nc = o["ncontrib"].reshape(H, W)
+    amb = o["ambiguous"].reshape(H, W)
+    checked = 0
+    for t in range(nt):
+        ty, tx = divmod(t, gx)
+        blk = (slice(ty * 16, ty * 16 + 16), slice(tx * 16, tx * 16 + 16))
+        if amb[blk].any():
+            continue
+        assert contrib[t] == nc[blk].sum(), t
+        checked += 1
+    assert checked > nt // 2
+
+
 def test_batched_views_bitwise_equal_per_view(gs):
     s = scenegen.blob_scene(11, [(160, 120), (203, 150), (96, 64)], 20000, sh_degree=3)
     s.pop("_rng")
