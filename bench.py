@@ -76,8 +76,8 @@ class EventTimer:
 
 
 def tile_last_sum(last, wh, tw=16, th=16):
-    """Sum over tiles of the largest `last` of the tile's pixels: the records a
-    tile's compositing must read (C_f)."""
+    """C_f: sum over tiles of the largest `last` of the tile's pixels, i.e. the
+    list entries a tile's compositing must read."""
     off = 0
     tot = 0
     for W, H in wh:
@@ -111,75 +111,94 @@ def make_workload(name):
     return sc, batches, targets
 
 
-def probe_isect(JointStep, sc, batches, targets):
-    """Intersections the batches need, from a pass with a generous capacity."""
-    P = max(int(sum(int(sc["wh"][v, 0]) * int(sc["wh"][v, 1]) for v in b)) for b in batches)
-    st = JointStep(sc, batches, targets, max_isect=min(2**30, 48 * P))
-    need = 0
-    for b in range(len(batches)):
-        st.forward_backward(b)
-        need = max(need, st.ctx.status()["n_isect_needed"])
-    st.ctx.close()
-    return need
-
-
-def run_joint(torch, name, steps, warmup, graph=False):
+def run_joint(torch, name, steps, warmup, tune=True, tile=None, order=0):
+    from paper_2603_04847_amd.autotune import autotune
     from paper_2603_04847_amd.step import JointStep
     sc, batches, targets = make_workload(name)
-    need = probe_isect(JointStep, sc, batches, targets)
-    st = JointStep(sc, batches, targets, max_isect=int(need * 1.15) + 4096)
-    log(f"[bench] {name}: {need} intersections per batch (max), capacity {st.ctx.cap.max_isect}")
+    P = max(int(sum(int(sc["wh"][v, 0]) * int(sc["wh"][v, 1]) for v in b)) for b in batches)
+    st = JointStep(sc, batches, targets, max_isect=min(2**30, 48 * P))
+    tuning = None
+    if tile is not None:
+        from paper_2603_04847_amd import _lib as L
+        st.settings = L.default_settings(tile_w=tile[0], tile_h=tile[1], tile_order=order)
+    if tune and tile is None:
+        results, best = autotune(st)
+        tuning = dict(best=f"{best['tile'][0]}x{best['tile'][1]} order={best['order']}",
+                      candidates={f"{r['tile'][0]}x{r['tile'][1]}/{r['order']}": round(r["ms"], 3)
+                                  for r in results})
+    else:
+        need = 0
+        for b in range(len(batches)):
+            st.forward_backward(b)
+            need = max(need, st.ctx.status()["n_isect_needed"])
+        st.set_capacity(int(need * 1.15) + 4096)
+    log(f"[bench] {name}: settings {st.settings.tile_w}x{st.settings.tile_h} "
+        f"order={st.settings.tile_order}, capacity {st.ctx.cap.max_isect}")
     timer = EventTimer(torch)
     for i in range(warmup):
         st.run(i % len(batches))
     torch.cuda.synchronize()
-    g_all = None
-    if graph:
-        # one captured graph per batch (view choice and sizes are baked in)
-        graphs = []
-        s = torch.cuda.Stream()
-        s.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(s):
-            for b in range(len(batches)):
-                st.run(b)
-        torch.cuda.current_stream().wait_stream(s)
-        torch.cuda.synchronize()
-        for b in range(len(batches)):
-            g = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(g):
-                st.run(b, step=st.step_count + 1)
-            graphs.append(g)
-        g_all = graphs
-        torch.cuda.synchronize()
     st.ctx.reset_status()
     torch.cuda.synchronize()
     a = torch.cuda.Event(enable_timing=True)
     b_ = torch.cuda.Event(enable_timing=True)
     a.record()
     for i in range(steps):
-        if g_all is not None:
-            g_all[i % len(batches)].replay()
-        else:
-            st.run(i % len(batches), timer=timer)
+        st.run(i % len(batches), timer=timer)
     b_.record()
     torch.cuda.synchronize()
     ms = a.elapsed_time(b_) / steps
-    per_call = timer.means() if g_all is None else {}
+    per_call = timer.means()
     status = st.ctx.status()
+    # the same steps replayed from captured HIP graphs (one per batch)
+    graph_ms = None
+    try:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for bb in range(len(batches)):
+                st.run(bb)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graphs = []
+        for bb in range(len(batches)):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                st.run(bb, step=st.step_count + 1)
+            graphs.append(g)
+        torch.cuda.synchronize()
+        a.record()
+        for i in range(steps):
+            graphs[i % len(batches)].replay()
+        b_.record()
+        torch.cuda.synchronize()
+        graph_ms = a.elapsed_time(b_) / steps
+        del graphs
+    except Exception as e:  # report, do not hide
+        log(f"[bench] graph replay failed: {e!r}")
     # workload sizes for the roofline (outside the timed region)
     st.forward_backward(0)
     torch.cuda.synchronize()
     stat0 = st.ctx.status()
+    from paper_2603_04847_amd import _lib as L
     last = st.last.cpu().numpy()
     wh_b = st.wh_all[batches[0]]
     P = int((wh_b[:, 0].astype(np.int64) * wh_b[:, 1]).sum())
-    C_f = tile_last_sum(last[:P], wh_b)
+    tw, th = st.settings.tile_w, st.settings.tile_h
+    C_f = tile_last_sum(last[:P], wh_b, tw, th)
+    # (pixel, list entry) evaluations the definition needs: each pixel up to
+    # its final contributor
+    n_eval = int(last[:P].astype(np.int64).sum())
+    nt = st.ctx.buffers()["n_tiles"]
+    n_contrib = int(L.copy_to_host(L.gs_ctx_tile_stats(st.ctx)["tile_contrib"], nt, np.int32)
+                    .astype(np.int64).sum())
     sizes = dict(P=P, N=st.N, V=len(batches[0]), K=(st.sh_degree + 1) ** 2,
                  n_visible=stat0["n_visible"], n_isect=stat0["n_isect"], C_f=C_f,
+                 n_eval=n_eval, n_contrib=n_contrib,
                  M=int(st.obs_cam.shape[0]), Pt=int(st.X.shape[0]),
                  n_params=int(sum(v.numel() for v in st._opt_params().values())))
-    return dict(ms=ms, per_call=per_call, status=status, sizes=sizes, st=st, sc=sc,
-                batches=batches)
+    return dict(ms=ms, graph_ms=graph_ms, per_call=per_call, status=status, sizes=sizes, st=st,
+                sc=sc, batches=batches, tuning=tuning)
 
 
 def algorithmic_bytes(sz):
@@ -197,6 +216,43 @@ def algorithmic_bytes(sz):
         "track": sz["M"] * 28 + 2 * sz["Pt"] * 12,
         "adam": sz["n_params"] * 28,
     }
+
+
+# flops of the definition per (pixel, list entry) evaluation and per
+# contributing (pixel, splat) pair, forward and backward
+FLOPS_EVAL = 13
+FLOPS_CONTRIB = {"render_fwd": 9, "raster_bwd": 51}
+FP32_PEAK_TFLOPS = 157.3
+ALU_KERNELS = ("render_fwd", "raster_bwd")
+KERNEL_SOURCE = {"render_fwd": "raster.hip", "raster_bwd": "raster.hip", "project": "project.hip",
+                 "project_bwd": "project.hip", "bin_sort": "bin.hip", "track": "track.hip",
+                 "adam": "optim.hip", "l1": "raster.hip"}
+
+
+def algorithmic_flops(sz, call):
+    return sz["n_eval"] * FLOPS_EVAL + sz["n_contrib"] * FLOPS_CONTRIB[call]
+
+
+def source_sha(call):
+    """Hash of the source of a call's kernels (its file and the shared header)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in (KERNEL_SOURCE[call], "gs_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2603_04847_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(call, workload):
+    """HBM bytes per launch from the committed counter runs, if they were taken
+    on the current source of that call's kernels (else None)."""
+    f = os.path.join(ROOT, "profiles", f"kernels_{workload}_hbm_traffic.json")
+    if not os.path.exists(f):
+        return None
+    d = json.load(open(f))
+    e = d.get(call)
+    if not e or e.get("src_sha") != source_sha(call):
+        return None
+    return int(e["fetch_bytes"] + e["write_bytes"])
 
 
 def batched_vs_per_view(torch, steps, warmup):
@@ -276,7 +332,7 @@ def batched_vs_per_view(torch, steps, warmup):
     return out
 
 
-def cpu_baseline(res, seconds_target=15.0):
+def cpu_baseline(res, seconds_target=20.0):
     """The FP64 oracle on the host cores, on a bounded sample of the same
     workload: the projection and its backward for the batch's views, the track
     term over all observations, and compositing (with backward) of a random
@@ -293,13 +349,13 @@ def cpu_baseline(res, seconds_target=15.0):
     proj = oracle.project(sub)
     t_proj = time.time() - t0
     rng = np.random.default_rng(0)
-    # size the pixel sample from a short calibration run
-    n_cal = 64
+    # size the pixel sample from a calibration run
+    n_cal = 256
     pix = rng.choice(sz["P"], size=n_cal, replace=False)
     t0 = time.time()
     oracle.render(proj, wh, pix=pix, v_rgb=np.ones((n_cal, 3)))
     per_px = (time.time() - t0) / n_cal
-    n_pix = int(max(64, min(20000, seconds_target / max(per_px, 1e-9) * 0.6)))
+    n_pix = int(max(256, min(200000, 0.7 * seconds_target / max(per_px, 1e-9))))
     pix = rng.choice(sz["P"], size=n_pix, replace=False)
     t0 = time.time()
     r = oracle.render(proj, wh, pix=pix, v_rgb=np.ones((n_pix, 3)))
@@ -329,7 +385,13 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="C4", choices=sorted(WORKLOADS))
-    ap.add_argument("--graph", action="store_true", help="replay the step as captured HIP graphs")
+    ap.add_argument("--no-tune", action="store_true", help="keep 16x16 tiles, natural order")
+    ap.add_argument("--tile", default=None, help="fixed tile shape WxH (skips the autotuner)")
+    ap.add_argument("--order", type=int, default=0, help="tile launch order with --tile")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized buffer 5 times with an elementwise kernel (counter calibration) and exit")
+    ap.add_argument("--print-sha", action="store_true",
+                    help="print the kernel source hashes used to validate stored counters")
     ap.add_argument("--no-compare", action="store_true", help="skip batched vs per-view (C3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -337,14 +399,28 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the hot path "
               "here has no multi-GPU code", file=sys.stderr)
         sys.exit(2)
+    if args.print_sha:
+        print(json.dumps({k: source_sha(k) for k in KERNEL_SOURCE}))
+        return
     import torch
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        a = torch.ones(n, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            torch.mul(a, 1.0, out=b)  # a plain streaming copy: reads and writes MIB each
+        torch.cuda.synchronize()
+        log(f"[bench] copied {args.copy_probe} MiB x 5")
+        return
     import paper_2603_04847_amd as P
     P.load()
 
-    res = run_joint(torch, args.workload, args.steps, args.warmup, graph=args.graph)
+    tile = tuple(int(x) for x in args.tile.split("x")) if args.tile else None
+    res = run_joint(torch, args.workload, args.steps, args.warmup, tune=not args.no_tune,
+                    tile=tile, order=args.order)
     sz = res["sizes"]
     ms = res["ms"]
     value = sz["P"] / ms / 1e3  # megapixels / s
@@ -353,10 +429,21 @@ def main():
     roof = None
     if per_call:
         dom = max((k for k in per_call if k in alg), key=lambda k: per_call[k])
-        ach = alg[dom] / (per_call[dom] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                "algorithmic_bytes": int(alg[dom]), "avg_ms": per_call[dom]}
+        t = per_call[dom] * 1e-3
+        if dom in ALU_KERNELS:
+            ach = algorithmic_flops(sz, dom) / t / 1e12
+            roof = {"bound": "alu", "kernel": dom, "achieved": round(ach, 2),
+                    "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(ach / FP32_PEAK_TFLOPS, 4),
+                    "algorithmic_flops": int(algorithmic_flops(sz, dom)),
+                    "hbm_gbs_algorithmic": round(alg[dom] / t / 1e9, 1)}
+        else:
+            ach = alg[dom] / t / 1e9
+            roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                    "algorithmic_bytes": int(alg[dom])}
+        roof["traffic"] = measured_traffic(dom, args.workload)
+        roof["avg_ms"] = per_call[dom]
     line = {
         "metric": "fwd+bwd megapixels/sec with pose grads (batched vs per-view), %HBM roofline",
         "value": round(value, 2), "unit": "MP/s", "n_gpus": 1, "steps": args.steps,
@@ -364,9 +451,13 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}",
                    "views_per_step": sz["V"], "pixels_per_step": sz["P"], "gaussians": sz["N"],
-                   "observations": sz["M"], "graph": bool(args.graph)},
+                   "observations": sz["M"],
+                   "tile": f"{res['st'].settings.tile_w}x{res['st'].settings.tile_h}",
+                   "tile_order": int(res["st"].settings.tile_order)},
         "roofline": roof,
         "per_call_ms": per_call,
+        "graph_ms_per_step": None if res["graph_ms"] is None else round(res["graph_ms"], 4),
+        "autotune": res["tuning"],
         "sizes": {k: int(v) for k, v in sz.items()},
     }
     if res["status"]["flags"]:

@@ -11,7 +11,7 @@
  *   Rasterize(G, T_i, K_i) -> I_i                 Algorithm 1 (render step),
  *                                                 Sec. 3.3 "Implementation";
  *   pi(K, T, X) = proj(K (R X + t))               Sec. 3.2 "Bundle Adjustment",
- *                                                 Appendix D (projection function);
+ *                                                 Appendix E (projection function);
  *   rho_Huber(||pi_i(X_k) - x_ip||^2; delta)      Sec. 3.3 eq. L_BA^joint;
  *   L = L_photo + lambda_BA L_BA, poses get both  Sec. 3.3, Algorithm 1
  *   gradients                                     (backward and update steps);

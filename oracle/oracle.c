@@ -5,9 +5,9 @@
  *
  * What it follows:
  *  - pinhole projection pi(X) = proj(K (R X + t)), world->camera [R|t]
- *    (GloSplat Sec. 3.2, "Bundle Adjustment"; Appendix D, projection function);
+ *    (GloSplat Sec. 3.2, "Bundle Adjustment"; Appendix E, projection function);
  *  - pose composition T = T0 (+) dT with (+) read as Exp(dT) * T0
- *    (Appendix D, Algorithm 1, pose adjustment);
+ *    (Appendix E, Algorithm 1, pose adjustment);
  *  - joint BA loss: Huber on the squared reprojection error, delta = 1 px,
  *    weighted by lambda_BA (Sec. 3.3, eq. L_BA^joint and the total objective);
  *  - rasterization Rasterize(G, T_i, K_i) (Sec. 3.3 "Implementation",

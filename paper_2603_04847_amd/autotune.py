@@ -1,0 +1,53 @@
+"""Pick the tile shape and the tile launch order for a workload by timing them.
+
+Every candidate runs the forward + backward of the joint step (a1-a9) at a
+context sized for its own intersection count; the fastest wins.  The image
+does not depend on the choice (the tile lists are truncation-free), so this
+only trades binning work (more, smaller tiles) against raster work (fewer,
+larger tiles).
+"""
+
+from __future__ import annotations
+
+import torch
+
+from . import _lib as L
+
+TILE_SHAPES = ((16, 16), (16, 8), (32, 16), (8, 8))
+
+
+def _need(step, b):
+    step.forward_backward(b)
+    st = step.ctx.status()
+    return st["n_isect_needed"]
+
+
+def autotune(step, shapes=TILE_SHAPES, orders=(0, 1), iters=3, batch=0, big=None):
+    """Time each (tile shape, order) on `step` (a JointStep) and leave the
+    fastest in step.settings with a tight capacity.  Returns the timings."""
+    P = step.cams[batch].n_pixels
+    big = big or min(2**30, 64 * P)
+    results = []
+    for tw, th in shapes:
+        step.settings = L.default_settings(tile_w=tw, tile_h=th)
+        step.set_capacity(big)
+        need = max(_need(step, b) for b in range(len(step.batches)))
+        step.set_capacity(int(need * 1.15) + 4096)
+        for order in orders:
+            step.settings = L.default_settings(tile_w=tw, tile_h=th, tile_order=order)
+            step.forward_backward(batch)
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(iters):
+                step.forward_backward(batch)
+            b.record()
+            torch.cuda.synchronize()
+            results.append(dict(tile=(tw, th), order=order, need=int(need),
+                                ms=a.elapsed_time(b) / iters))
+    best = min(results, key=lambda r: r["ms"])
+    tw, th = best["tile"]
+    step.settings = L.default_settings(tile_w=tw, tile_h=th, tile_order=best["order"])
+    step.set_capacity(int(best["need"] * 1.15) + 4096)
+    return results, best

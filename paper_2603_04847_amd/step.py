@@ -69,8 +69,9 @@ class JointStep:
         tiles = max(int(sum(((self.wh_all[v, 0] + 15) // 16) * ((self.wh_all[v, 1] + 15) // 16)
                             for v in b)) for b in self.batches)
         tiles = max(tiles, 4 * tiles)  # room for the smallest tile shape
-        self.ctx = L.Context(max_pairs=Vb * self.N, max_isect=max_isect or 32 * P,
-                             max_tiles=tiles, max_views=Vb, max_cams=self.n_cams)
+        self._cap = dict(max_pairs=Vb * self.N, max_tiles=tiles, max_views=Vb,
+                         max_cams=self.n_cams)
+        self.ctx = L.Context(max_isect=max_isect or 32 * P, **self._cap)
         self.rgb = torch.empty((P, 3), device=device)
         self.T = torch.empty((P,), device=device)
         self.last = torch.empty((P,), device=device, dtype=torch.int32)
@@ -86,6 +87,11 @@ class JointStep:
         self.cams = [L.Cameras(self.viewmat, self.intr, self.wh_all[b], index=b) for b in self.batches]
         self.g = L.make_gaussians(*(self.params[k] for k in PARAM_KEYS), self.sh_degree)
         self.gg = L.make_grads(*(self.grads[k] for k in PARAM_KEYS))
+
+    def set_capacity(self, max_isect):
+        """Re-create the context with room for `max_isect` tile intersections."""
+        self.ctx.close()
+        self.ctx = L.Context(max_isect=int(max_isect), **self._cap)
 
     def _opt_params(self):
         d = dict(self.params)
