@@ -355,8 +355,7 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
             // sort (key, tile) pairs: tile_order holds the values of the first buffer pair
             uint32_t* kk[2] = {c->tk[0], c->tk[1]};
             uint32_t* vv[2] = {c->tile_order, reinterpret_cast<uint32_t*>(c->tile_contrib)};
-            // 32 bits = 4 passes: the result lands back in tile_order
-            const int side3 = radix_sort_pairs(kk[0], vv[0], kk[1], vv[1], T, nullptr, 0, 32, c->hist,
+            const int side3 = radix_sort_pairs(kk[0], vv[0], kk[1], vv[1], T, nullptr, 0, 24, c->hist,
                                                c->scan_scratch, st, &e);
             if (e != hipSuccess) return e;
             if (side3 == 1) {

@@ -111,37 +111,25 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 // Gaussian falloff exponent sigma = 0.5 (A dx^2 + C dy^2) + B dx dy with a
 // fixed operation order, shared by the forward and the backward raster so both
 // take identical alpha-gate decisions.
-__device__ __forceinline__ float splat_sigma(float A, float B, float C, float dx, float dy) {
-    const float q = __builtin_fmaf(A * dx, dx, C * dy * dy);
-    return __builtin_fmaf(B * dx, dy, 0.5f * q);
+// The exponent of a splat in base 2: e2 = -log2(e) sigma(dx, dy), sigma = A dx^2 / 2
+// + B dx dy + C dy^2 / 2, with the conic scaled once per splat (a = -log2(e) A / 2,
+// b = -log2(e) B, c = -log2(e) C / 2) so a pixel pays three operations and the
+// hardware exp2.  The forward and the backward evaluate it with this one fixed
+// operation order, so both take the same decisions.
+constexpr float kLog2E = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+
+struct ConicE2 {
+    float a, b, c;
+};
+
+__device__ __forceinline__ ConicE2 conic_e2(float A, float B, float C) {
+    return {-0.5f * kLog2E * A, -kLog2E * B, -0.5f * kLog2E * C};
 }
 
-__device__ __forceinline__ float fast_exp_neg(float s) {
-    // e^-s = 2^(-s log2 e) on the hardware exp2
-    return __builtin_amdgcn_exp2f(-s * 1.4426950408889634f);
-}
-
-// Minimum of sigma(d) over the rectangle [x0,x1]x[y0,y1] of pixel centres for a
-// splat at (mx,my): 0 if the centre is inside, else the smallest value on the
-// four edges (sigma is convex).
-__device__ __forceinline__ float edge_min_x(float A, float B, float C, float fx, float lo, float hi) {
-    // x fixed at fx, y in [lo,hi]: 0.5 A fx^2 + B fx y + 0.5 C y^2
-    float y = fminf(fmaxf(-B * fx / C, lo), hi);
-    return 0.5f * (A * fx * fx + C * y * y) + B * fx * y;
-}
-__device__ __forceinline__ float edge_min_y(float A, float B, float C, float fy, float lo, float hi) {
-    float x = fminf(fmaxf(-B * fy / A, lo), hi);
-    return 0.5f * (A * x * x + C * fy * fy) + B * x * fy;
-}
-__device__ __forceinline__ float rect_sigma_min(float A, float B, float C, float mx, float my,
-                                                float x0, float x1, float y0, float y1) {
-    if (mx >= x0 && mx <= x1 && my >= y0 && my <= y1) return 0.f;
-    const float lx = x0 - mx, hx = x1 - mx, ly = y0 - my, hy = y1 - my;
-    float q = edge_min_x(A, B, C, lx, ly, hy);
-    q = fminf(q, edge_min_x(A, B, C, hx, ly, hy));
-    q = fminf(q, edge_min_y(A, B, C, ly, lx, hx));
-    q = fminf(q, edge_min_y(A, B, C, hy, lx, hx));
-    return q;
+__device__ __forceinline__ float splat_e2(float a, float b, float c, float dx, float dy) {
+    const float q = __builtin_fmaf(a * dx, dx, c * dy * dy);
+    return __builtin_fmaf(b * dx, dy, q);
 }
 
 // Tile-space footprint of a splat, by spans.  The tile is split into four

@@ -56,10 +56,25 @@ struct TileMap {
     }
 };
 
-// exponent beyond which o e^-sigma < alpha_min for sure (a conservative bound:
+// base-2 exponent below which o 2^e2 < alpha_min for sure (a conservative bound:
 // it only lets the exact test run less often, never changes its outcome)
-__device__ __forceinline__ float sigma_cut(float o, float amin) {
-    return __logf(o / amin) * 1.00001f + 1e-5f;
+__device__ __forceinline__ float e2_cut(float o, float amin) {
+    return -(__log2f(o / amin) * 1.00001f + 1.5e-5f);
+}
+
+// One splat record as a lane loads it: position, opacity, the base-2 conic,
+// colour, and the fast-reject bound.
+struct LaneSplat {
+    float mx, my, o, a, b, c, cr, cg, cb, cut;
+};
+
+__device__ __forceinline__ LaneSplat load_splat(const float4* __restrict__ rec, uint32_t id,
+                                                float amin) {
+    const int64_t p = id & kPairMask;
+    const float4 ra = rec[3 * p], rb = rec[3 * p + 1];
+    const float2 rc = *reinterpret_cast<const float2*>(rec + 3 * p + 2);
+    const ConicE2 q = conic_e2(rb.x, rb.y, rb.z);
+    return {ra.x, ra.y, ra.w, q.a, q.b, q.c, rb.w, rc.x, rc.y, e2_cut(ra.w, amin)};
 }
 
 template <int TW, int TH>
@@ -106,25 +121,19 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
         for (int k = 0; k < PPL; k++) alive |= !done[k];
         if (__ballot(alive) == 0) break;
         const int j = b + lane;
-        float4 ra = make_float4(0.f, 0.f, 0.f, 0.f), rb = ra;
-        float2 rc = make_float2(0.f, 0.f);
         uint32_t id = 0;
-        float cut = 0.f;
+        LaneSplat ls = {};
         if (j < e) {
             id = (uint32_t)ids[j];
-            const int64_t p = id & kPairMask;
-            ra = rec[3 * p];
-            rb = rec[3 * p + 1];
-            rc = *reinterpret_cast<const float2*>(rec + 3 * p + 2);
-            cut = sigma_cut(ra.w, amin);
+            ls = load_splat(rec, id, amin);
         }
         const int nb = min(kWave, e - b);
         for (int i = 0; i < nb; i++) {
             const uint32_t m = (uint32_t)bcast((int)id, i) >> kPairBits;
-            const float mx = bcast(ra.x, i), my = bcast(ra.y, i), o = bcast(ra.w, i);
-            const float A = bcast(rb.x, i), B = bcast(rb.y, i), C = bcast(rb.z, i);
-            const float cr = bcast(rb.w, i), cg = bcast(rc.x, i), cb = bcast(rc.y, i);
-            const float sc = bcast(cut, i);
+            const float mx = bcast(ls.mx, i), my = bcast(ls.my, i), o = bcast(ls.o, i);
+            const float qa = bcast(ls.a, i), qb = bcast(ls.b, i), qc = bcast(ls.c, i);
+            const float cr = bcast(ls.cr, i), cg = bcast(ls.cg, i), cb = bcast(ls.cb, i);
+            const float cut = bcast(ls.cut, i);
             const int pos = b + i - s + 1;
 #pragma unroll
             for (int k = 0; k < PPL; k++) {
@@ -132,9 +141,9 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
                 if (done[k]) continue;
                 const float dx = mx - fx[k];
                 const float dy = my - fy[k];
-                const float sig = splat_sigma(A, B, C, dx, dy);
-                if (sig < 0.f || sig > sc) continue;
-                const float alpha = fminf(amax, o * fast_exp_neg(sig));
+                const float e2 = splat_e2(qa, qb, qc, dx, dy);
+                if (e2 > 0.f || e2 < cut) continue;
+                const float alpha = fminf(amax, o * __builtin_amdgcn_exp2f(e2));
                 if (alpha < amin) continue;
                 const float Tn = T[k] * (1.f - alpha);
                 if (Tn < tmin) {
@@ -187,7 +196,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ re
     const int tx = lt % gx, ty = lt / gx;
     const int lane = threadIdx.x;
     const float b0 = bg ? bg[0] : 0.f, b1 = bg ? bg[1] : 0.f, b2 = bg ? bg[2] : 0.f;
-    float fx[PPL], fy[PPL], Tc[PPL], Tf[PPL], V0[PPL], V1[PPL], V2[PPL], S0[PPL], S1[PPL], S2[PPL];
+    float fx[PPL], fy[PPL], Tc[PPL], V0[PPL], V1[PPL], V2[PPL], VS[PPL];
     int L[PPL];
     int lmax = 0;
 #pragma unroll
@@ -198,20 +207,19 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ re
         fx[k] = px + 0.5f;
         fy[k] = py + 0.5f;
         L[k] = 0;
-        Tc[k] = Tf[k] = 1.f;
+        Tc[k] = 1.f;
         V0[k] = V1[k] = V2[k] = 0.f;
         if (px < W && py < H) {
             const int64_t pix = (int64_t)vt.pix_off[v] + (int64_t)py * W + px;
             L[k] = last_in[pix];
-            Tf[k] = Tc[k] = T_final[pix];
+            Tc[k] = T_final[pix];
             V0[k] = v_rgb[3 * pix];
             V1[k] = v_rgb[3 * pix + 1];
             V2[k] = v_rgb[3 * pix + 2];
         }
-        // S = sum_{later} colour alpha T + T_final bg (the background term seeds it)
-        S0[k] = Tf[k] * b0;
-        S1[k] = Tf[k] * b1;
-        S2[k] = Tf[k] * b2;
+        // VS = dL/dC . S, S = sum over later splats of colour alpha T, plus
+        // T_final bg (the background term seeds it)
+        VS[k] = Tc[k] * (V0[k] * b0 + V1[k] * b1 + V2[k] * b2);
         lmax = max(lmax, L[k]);
     }
     lmax = wave_max_i(lmax);
@@ -221,30 +229,24 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ re
     const float amin = rp.alpha_min, amax = rp.alpha_max;
     for (int b = s + ((lmax - 1) / kWave) * kWave; b >= s; b -= kWave) {
         const int j = b + lane;
-        float4 ra = make_float4(0.f, 0.f, 0.f, 0.f), rb = ra;
-        float2 rc = make_float2(0.f, 0.f);
         uint32_t id = 0;
-        float cut = 0.f;
+        LaneSplat ls = {};
         if (j < s + lmax) {
             id = (uint32_t)ids[j];
-            const int64_t p = id & kPairMask;
-            ra = rec[3 * p];
-            rb = rec[3 * p + 1];
-            rc = *reinterpret_cast<const float2*>(rec + 3 * p + 2);
-            cut = sigma_cut(ra.w, amin);
+            ls = load_splat(rec, id, amin);
         }
         const int nb = min(kWave, s + lmax - b);
         for (int i = nb - 1; i >= 0; i--) {
             const uint32_t idb = (uint32_t)bcast((int)id, i);
             const uint32_t m = idb >> kPairBits;
-            const float mx = bcast(ra.x, i), my = bcast(ra.y, i), o = bcast(ra.w, i);
-            const float A = bcast(rb.x, i), B = bcast(rb.y, i), C = bcast(rb.z, i);
-            const float cr = bcast(rb.w, i), cg = bcast(rc.x, i), cb = bcast(rc.y, i);
-            const float sc = bcast(cut, i);
+            const float mx = bcast(ls.mx, i), my = bcast(ls.my, i), o = bcast(ls.o, i);
+            const float qa = bcast(ls.a, i), qb = bcast(ls.b, i), qc = bcast(ls.c, i);
+            const float cr = bcast(ls.cr, i), cg = bcast(ls.cg, i), cb = bcast(ls.cb, i);
             const int pos = b + i - s;
-            // per-lane sums over the lane's pixels: colour weights, opacity, and
-            // the moments sum vs dx, vs dy, vs dx^2, vs dx dy, vs dy^2 of the
-            // exponent's gradient, from which the mean and conic gradients follow
+            // per-lane sums over the lane's pixels: colour weights, q = dL/dalpha
+            // e^-sigma (zero where alpha is clamped), and the moments q dx, q dy,
+            // q dx^2, q dx dy, q dy^2; the exponent's gradient is -o q, so the
+            // mean and conic gradients follow from these after the wave sum
             float g_r = 0.f, g_g = 0.f, g_b = 0.f, g_o = 0.f;
             float m_x = 0.f, m_y = 0.f, m_xx = 0.f, m_xy = 0.f, m_yy = 0.f;
             bool any = false;
@@ -253,11 +255,13 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ re
                 if (!(m & TM::quads(k))) continue;  // wave-uniform
                 const float dx = mx - fx[k];
                 const float dy = my - fy[k];
-                const float sig = splat_sigma(A, B, C, dx, dy);
-                const float ex = fast_exp_neg(sig);
+                const float e2 = splat_e2(qa, qb, qc, dx, dy);
+                const float ex = __builtin_amdgcn_exp2f(e2);
                 const float araw = o * ex;
                 const float alpha = fminf(amax, araw);
-                const bool live = pos < L[k] && sig >= 0.f && sig <= sc && alpha >= amin;
+                // same decisions as the forward: before the pixel's last
+                // contributor, inside the support, above the alpha gate
+                const bool live = pos < L[k] && e2 <= 0.f && alpha >= amin;
                 if (live) {
                     any = true;
                     const float iom = __builtin_amdgcn_rcpf(1.f - alpha);
@@ -266,34 +270,36 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ re
                     g_r = __builtin_fmaf(w, V0[k], g_r);
                     g_g = __builtin_fmaf(w, V1[k], g_g);
                     g_b = __builtin_fmaf(w, V2[k], g_b);
-                    const float va = V0[k] * (cr * Tb - S0[k] * iom) + V1[k] * (cg * Tb - S1[k] * iom) +
-                                     V2[k] * (cb * Tb - S2[k] * iom);
-                    S0[k] = __builtin_fmaf(cr, w, S0[k]);
-                    S1[k] = __builtin_fmaf(cg, w, S1[k]);
-                    S2[k] = __builtin_fmaf(cb, w, S2[k]);
+                    const float Vc = __builtin_fmaf(V2[k], cb, __builtin_fmaf(V1[k], cg, V0[k] * cr));
+                    // dL/dalpha = T (dL/dC . c) - (dL/dC . S) / (1 - alpha)
+                    const float va = __builtin_fmaf(Tb, Vc, -(iom * VS[k]));
+                    VS[k] = __builtin_fmaf(w, Vc, VS[k]);
                     Tc[k] = Tb;
-                    const bool unc = araw < amax;  // clamped alpha passes no gradient
-                    g_o += unc ? va * ex : 0.f;
-                    const float vs = unc ? -alpha * va : 0.f;
-                    const float vx = vs * dx, vy = vs * dy;
-                    m_x += vx;
-                    m_y += vy;
-                    m_xx = __builtin_fmaf(vx, dx, m_xx);
-                    m_xy = __builtin_fmaf(vx, dy, m_xy);
-                    m_yy = __builtin_fmaf(vy, dy, m_yy);
+                    const float q = araw < amax ? va * ex : 0.f;  // clamped alpha passes no gradient
+                    g_o += q;
+                    const float qx = q * dx, qy = q * dy;
+                    m_x += qx;
+                    m_y += qy;
+                    m_xx = __builtin_fmaf(qx, dx, m_xx);
+                    m_xy = __builtin_fmaf(qx, dy, m_xy);
+                    m_yy = __builtin_fmaf(qy, dy, m_yy);
                 }
             }
             if (__ballot(any) == 0) continue;
             // wave totals: eight through one transposed butterfly, blue on its own
             const float e = wave_sum8_t(m_x, m_y, m_xx, m_xy, m_yy, g_o, g_r, g_g);
             const float tb = wave_sum(g_b);
-            const float SX = bcast(e, 0), SY = bcast(e, 4);  // lanes holding m_x, m_y
+            const float QX = bcast(e, 0), QY = bcast(e, 4);  // lanes holding m_x, m_y
             if (lane < 9) {
-                // component: 0 mean.x, 1 mean.y, 2 A, 3 B, 4 C, 5 opacity, 6 r, 7 g, 8 b
+                // component: 0 mean.x, 1 mean.y, 2 A, 3 B, 4 C, 5 opacity, 6 r, 7 g, 8 b.
+                // With vs = -o q the sums of vs dx, vs dy, ... are -o times the
+                // moments; A = -2 a / log2(e), B = -b / log2(e), C = -2 c / log2(e).
                 const int comp = lane < 8 ? sum8_index(lane) : 8;
-                const float val = comp == 0 ? A * SX + B * SY
-                                : comp == 1 ? B * SX + C * SY
-                                : (comp == 2 || comp == 4) ? 0.5f * e
+                const float ko = o * kLn2;
+                const float val = comp == 0 ? ko * __builtin_fmaf(2.f * qa, QX, qb * QY)
+                                : comp == 1 ? ko * __builtin_fmaf(qb, QX, 2.f * qc * QY)
+                                : (comp == 2 || comp == 4) ? -0.5f * o * e
+                                : comp == 3 ? -o * e
                                 : comp == 8 ? tb : e;
                 const int64_t p = idb & kPairMask;
                 atomicAdd(grad2d + 9 * p + comp, val);

@@ -106,11 +106,10 @@ __device__ __forceinline__ uint32_t dev_count(const uint32_t* d_n, int64_t max_n
     return n < (uint64_t)max_n ? n : (uint32_t)max_n;
 }
 
-// lanes of the wave holding the same 8-bit digit (among lanes with `valid`)
-__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
+// lanes of the wave holding the same digit of `bits` bits (among lanes with `valid`)
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid, int bits) {
     uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; b++) {
+    for (int b = 0; b < bits; b++) {
         const bool bit = (d >> b) & 1u;
         const uint64_t m = __ballot(bit);
         peers &= bit ? m : ~m;
@@ -118,70 +117,87 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
     return peers;
 }
 
-// Items of a block: wave w owns the contiguous chunk [base + 1024 w, base +
-// 1024 (w+1)), read 64 at a time; so (wave, step, lane) order is index order and
-// ranks can be kept per wave without block barriers.
+// Items of a block: wave w owns the contiguous chunk [base + 64 ITEMS w,
+// base + 64 ITEMS (w+1)), read 64 at a time; so (wave, step, lane) order is
+// index order and ranks can be kept per wave without block barriers.
+template <int ITEMS>
 __device__ __forceinline__ int64_t item_index(int64_t base, int w, int i, int lane) {
-    return base + (int64_t)w * (kWave * kItems) + i * kWave + lane;
+    return base + (int64_t)w * (kWave * ITEMS) + i * kWave + lane;
 }
 
+// Per-block digit counts, digit-major: hist[d * nblocks + block].  All loads
+// of a thread are issued before the first ballot.
+template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                          const uint32_t* __restrict__ d_n,
-                                                         int64_t max_n, int shift,
+                                                         int64_t max_n, int shift, int bits,
                                                          uint32_t* __restrict__ hist,
                                                          uint32_t nblocks) {
+    constexpr int TILE = kThreads * ITEMS;
     __shared__ uint32_t s_h[kWaves][256];
     const uint32_t n = dev_count(d_n, max_n);
     const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
+    const uint32_t mask = (1u << bits) - 1u;
     for (int q = 0; q < kWaves; q++) s_h[q][tid] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kTile;
+    const int64_t base = (int64_t)blockIdx.x * TILE;
     if (base < n) {
-#pragma unroll 4
-        for (int i = 0; i < kItems; i++) {
-            const int64_t j = item_index(base, w, i, lane);
-            const bool valid = j < n;
-            const uint32_t d = valid ? (keys[j] >> shift) & 0xFFu : 0u;
-            const uint64_t peers = match_digit(d, valid);
+        uint32_t k[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++) {
+            const int64_t j = item_index<ITEMS>(base, w, i, lane);
+            k[i] = j < n ? keys[j] : 0u;
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++) {
+            const bool valid = item_index<ITEMS>(base, w, i, lane) < n;
+            const uint32_t d = (k[i] >> shift) & mask;
+            const uint64_t peers = match_digit(d, valid, bits);
             // one lane per digit adds the digit's count in this wave's histogram
             if (valid && (peers & lanemask_lt()) == 0) s_h[w][d] += (uint32_t)__popcll(peers);
         }
     }
     __syncthreads();
-    hist[(int64_t)tid * nblocks + blockIdx.x] = s_h[0][tid] + s_h[1][tid] + s_h[2][tid] + s_h[3][tid];
+    if (tid <= (int)mask)
+        hist[(int64_t)tid * nblocks + blockIdx.x] = s_h[0][tid] + s_h[1][tid] + s_h[2][tid] + s_h[3][tid];
 }
 
+template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ d_n, int64_t max_n, int shift,
-    const uint32_t* __restrict__ hist, uint32_t nblocks) {
+    int bits, const uint32_t* __restrict__ hist, uint32_t nblocks) {
+    constexpr int TILE = kThreads * ITEMS;
     __shared__ uint32_t s_h[kWaves][256];  // per-wave digit counts, then offsets
     __shared__ uint32_t s_start[256];
+    __shared__ uint32_t s_glob[256];
     __shared__ uint32_t s_w[kWaves];
-    __shared__ uint32_t s_key[kTile];
-    __shared__ uint32_t s_val[kTile];
+    __shared__ uint32_t s_key[TILE];
+    __shared__ uint32_t s_val[TILE];
     const uint32_t n = dev_count(d_n, max_n);
-    const int64_t base = (int64_t)blockIdx.x * kTile;
+    const int64_t base = (int64_t)blockIdx.x * TILE;
     if (base >= n) return;  // uniform over the block
     const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
-    uint32_t k[kItems], v[kItems], rank[kItems];
+    const uint32_t mask = (1u << bits) - 1u;
+    uint32_t k[ITEMS], v[ITEMS];
+    uint16_t rank[ITEMS];
 #pragma unroll
-    for (int i = 0; i < kItems; i++) {
-        const int64_t j = item_index(base, w, i, lane);
+    for (int i = 0; i < ITEMS; i++) {
+        const int64_t j = item_index<ITEMS>(base, w, i, lane);
         k[i] = j < n ? kin[j] : 0u;
         v[i] = j < n ? vin[j] : 0u;
     }
     for (int q = 0; q < kWaves; q++) s_h[q][tid] = 0;
+    s_glob[tid] = tid <= (int)mask ? hist[(int64_t)tid * nblocks + blockIdx.x] : 0u;
     __syncthreads();
     // stable rank inside the wave's chunk: earlier steps (LDS count) + earlier lanes
 #pragma unroll
-    for (int i = 0; i < kItems; i++) {
-        const int64_t j = item_index(base, w, i, lane);
-        const bool valid = j < n;
-        const uint32_t d = (k[i] >> shift) & 0xFFu;
-        const uint64_t peers = match_digit(d, valid);
+    for (int i = 0; i < ITEMS; i++) {
+        const bool valid = item_index<ITEMS>(base, w, i, lane) < n;
+        const uint32_t d = (k[i] >> shift) & mask;
+        const uint64_t peers = match_digit(d, valid, bits);
         const uint32_t before = s_h[w][d];
-        rank[i] = before + (uint32_t)__popcll(peers & lanemask_lt());
+        rank[i] = (uint16_t)(before + (uint32_t)__popcll(peers & lanemask_lt()));
         if (valid && (peers & lanemask_lt()) == 0) s_h[w][d] = before + (uint32_t)__popcll(peers);
     }
     __syncthreads();
@@ -196,24 +212,23 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     s_start[tid] = block_excl_scan(run, s_w, tot);
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kItems; i++) {
-        const int64_t j = item_index(base, w, i, lane);
-        if (j < n) {
-            const uint32_t d = (k[i] >> shift) & 0xFFu;
+    for (int i = 0; i < ITEMS; i++) {
+        if (item_index<ITEMS>(base, w, i, lane) < n) {
+            const uint32_t d = (k[i] >> shift) & mask;
             const uint32_t pos = s_start[d] + s_h[w][d] + rank[i];
             s_key[pos] = k[i];
             s_val[pos] = v[i];
         }
     }
     __syncthreads();
-    const uint32_t cnt = (uint32_t)min((int64_t)kTile, (int64_t)n - base);
+    const uint32_t cnt = (uint32_t)min((int64_t)TILE, (int64_t)n - base);
 #pragma unroll
-    for (int i = 0; i < kItems; i++) {
+    for (int i = 0; i < ITEMS; i++) {
         const uint32_t j = i * kThreads + tid;
         if (j < cnt) {
             const uint32_t key = s_key[j];
-            const uint32_t d = (key >> shift) & 0xFFu;
-            const uint32_t g = hist[(int64_t)d * nblocks + blockIdx.x] + (j - s_start[d]);
+            const uint32_t d = (key >> shift) & mask;
+            const uint32_t g = s_glob[d] + (j - s_start[d]);
             kout[g] = key;
             vout[g] = s_val[j];
         }
@@ -237,25 +252,49 @@ hipError_t exclusive_scan_u32(uint32_t* data, int64_t n, uint32_t* total_out, ui
 
 size_t radix_hist_words(int64_t max_n) { return (size_t)256 * ((max_n + kTile - 1) / kTile) + 16; }
 
+namespace {
+
+// one pass over `bits` bits at `shift`; blocks of 256 x ITEMS items
+template <int ITEMS>
+hipError_t radix_pass(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, uint32_t* vo,
+                      int64_t max_n, const uint32_t* d_n, int shift, int bits, uint32_t* hist,
+                      uint32_t* scan_scratch, hipStream_t st) {
+    const uint32_t nb = (uint32_t)((max_n + kThreads * ITEMS - 1) / (kThreads * ITEMS));
+    hipLaunchKernelGGL(k_radix_hist<ITEMS>, dim3(nb), dim3(kThreads), 0, st, ki, d_n, max_n, shift,
+                       bits, hist, nb);
+    hipError_t e = exclusive_scan_u32(hist, ((int64_t)1 << bits) * nb, nullptr, scan_scratch, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_radix_scatter<ITEMS>, dim3(nb), dim3(kThreads), 0, st, ki, vi, ko, vo, d_n,
+                       max_n, shift, bits, hist, nb);
+    return hipGetLastError();
+}
+
+}  // namespace
+
 int radix_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_t max_n,
                      const uint32_t* d_n, int lo, int hi, uint32_t* hist, uint32_t* scan_scratch,
                      hipStream_t st, hipError_t* err) {
     *err = hipSuccess;
-    if (max_n <= 0) return 0;
-    const uint32_t nb = (uint32_t)((max_n + kTile - 1) / kTile);
+    if (max_n <= 0 || hi <= lo) return 0;
+    // equal digit widths of at most 8 bits
+    const int total = hi - lo;
+    const int passes = (total + 7) / 8;
     int cur = 0;
     uint32_t* K[2] = {ka, kb};
     uint32_t* Vv[2] = {va, vb};
-    for (int shift = lo; shift < hi; shift += 8) {
-        hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kThreads), 0, st, K[cur], d_n, max_n, shift,
-                           hist, nb);
-        hipError_t e = exclusive_scan_u32(hist, (int64_t)256 * nb, nullptr, scan_scratch, st);
-        if (e != hipSuccess) { *err = e; return cur; }
-        hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kThreads), 0, st, K[cur], Vv[cur],
-                           K[cur ^ 1], Vv[cur ^ 1], d_n, max_n, shift, hist, nb);
+    int shift = lo;
+    for (int p = 0; p < passes; p++) {
+        const int bits = (total - (shift - lo) + (passes - p) - 1) / (passes - p);
+        // large inputs: 8192 items per block (longer runs per digit in the scatter)
+        *err = max_n > ((int64_t)1 << 22)
+                   ? radix_pass<32>(K[cur], Vv[cur], K[cur ^ 1], Vv[cur ^ 1], max_n, d_n, shift,
+                                    bits, hist, scan_scratch, st)
+                   : radix_pass<16>(K[cur], Vv[cur], K[cur ^ 1], Vv[cur ^ 1], max_n, d_n, shift,
+                                    bits, hist, scan_scratch, st);
+        if (*err != hipSuccess) return cur;
+        shift += bits;
         cur ^= 1;
     }
-    *err = hipGetLastError();
     return cur;
 }
 
