@@ -111,7 +111,7 @@ def make_workload(name):
     return sc, batches, targets
 
 
-def run_joint(torch, name, steps, warmup, tune=True, tile=None, order=0):
+def run_joint(torch, name, steps, warmup, tune=True, tile=None, order=0, graph=True):
     from paper_2603_04847_amd.autotune import autotune
     from paper_2603_04847_amd.step import JointStep
     sc, batches, targets = make_workload(name)
@@ -153,6 +153,8 @@ def run_joint(torch, name, steps, warmup, tune=True, tile=None, order=0):
     # the same steps replayed from captured HIP graphs (one per batch)
     graph_ms = None
     try:
+        if not graph:
+            raise RuntimeError("graph replay skipped (--no-graph)")
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):
@@ -218,10 +220,15 @@ def algorithmic_bytes(sz):
     }
 
 
-# flops of the definition per (pixel, list entry) evaluation and per
-# contributing (pixel, splat) pair, forward and backward
-FLOPS_EVAL = 13
-FLOPS_CONTRIB = {"render_fwd": 9, "raster_bwd": 51}
+# Arithmetic of the definition, one per add, multiply, compare, select, min,
+# exp2 or reciprocal and two per fused multiply-add: per (pixel, list entry)
+# evaluation (offset 2, exponent 8, exp2, opacity, clamp, gate = 14) and per
+# contributing (pixel, splat) pair (forward: 1 - alpha, T update, stop test,
+# weight, colour 3 fma = 10; backward: 1 - alpha, rcp, T, weight, colour
+# gradient 3 fma, dL/dC.c, dL/dalpha, dL/dC.S update, q with clamp, opacity
+# gradient, five moments = 34)
+FLOPS_EVAL = 14
+FLOPS_CONTRIB = {"render_fwd": 10, "raster_bwd": 34}
 FP32_PEAK_TFLOPS = 157.3
 ALU_KERNELS = ("render_fwd", "raster_bwd")
 # calls that launch one kernel (the others are sequences: bin_sort is ~25)
@@ -396,6 +403,7 @@ def main():
                     help="print the kernel source hashes used to validate stored counters")
     ap.add_argument("--no-compare", action="store_true", help="skip batched vs per-view (C3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the hot path "
@@ -422,7 +430,7 @@ def main():
 
     tile = tuple(int(x) for x in args.tile.split("x")) if args.tile else None
     res = run_joint(torch, args.workload, args.steps, args.warmup, tune=not args.no_tune,
-                    tile=tile, order=args.order)
+                    tile=tile, order=args.order, graph=not args.no_graph)
     sz = res["sizes"]
     ms = res["ms"]
     value = sz["P"] / ms / 1e3  # megapixels / s

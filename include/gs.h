@@ -111,7 +111,10 @@ typedef struct {
     float t_min;              /* 1e-4 */
     int32_t grad_accumulate;  /* 0: gs_render_bwd overwrites Gaussian grads; 1: adds */
     int32_t tile_order;       /* 0: natural tile order; 1: launch the raster kernels on
-                                 the tiles in order of decreasing list length */
+                                 the tiles heaviest first: by decreasing bucket of the
+                                 list length, 16 buckets per octave (bucket of n > 0:
+                                 1 + 16 floor(log2 n) + the 4 bits after n's leading
+                                 bit; 0 for an empty list), any order inside a bucket */
 } gs_settings;
 
 typedef struct {
@@ -186,7 +189,8 @@ gs_status gs_ctx_buffers(gs_ctx* ctx, float** records, int32_t** isect_ids,
 /* Workload statistics of the last gs_render_fwd (device pointers, valid for
  * the context's lifetime): tile_contrib[t] = number of (pixel, splat) pairs
  * that contributed to tile t; tile_order = launch order of the tiles when the
- * last gs_bin_sort ran with tile_order = 1 (*ordered = 1), heaviest first. */
+ * last gs_bin_sort ran with tile_order = 1 (*ordered = 1), heaviest first as
+ * gs_settings.tile_order describes. */
 gs_status gs_ctx_tile_stats(gs_ctx* ctx, const int32_t** tile_contrib,
                             const uint32_t** tile_order, int32_t* ordered);
 

@@ -297,8 +297,51 @@ __global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t* __restrict__ 
     }
 }
 
-// heaviest tiles first: key = 2^24 - 1 - min(list length, 2^24 - 1), stable
-// radix on 24 bits, so equal lengths keep the natural tile order
+// Launch order of the tiles, heaviest first.  The weight is a log-scale bucket
+// of the list length, exact in integers: 16 buckets per octave from the leading
+// bit and the four bits after it (0 for an empty list).  Inside a bucket the
+// order is free: tiles are independent, so it never changes a result.
+__device__ __forceinline__ uint32_t length_bucket(uint32_t len) {
+    if (len == 0) return 0;
+    const int msb = 31 - __clz(len);
+    const uint32_t frac = msb >= 4 ? (len >> (msb - 4)) & 15u : (len << (4 - msb)) & 15u;
+    return 1u + 16u * (uint32_t)msb + frac;  // <= 1 + 16*31 + 15 = 512
+}
+constexpr int kOrderBuckets = 513;
+constexpr int kOrderThreads = 1024;
+
+// One block: histogram of the buckets, their scan from the heaviest down, and
+// a scatter through LDS cursors.  For up to 2^20 tiles.
+__global__ __launch_bounds__(kOrderThreads) void k_tile_order(const int32_t* __restrict__ ranges,
+                                                               int64_t T,
+                                                               uint32_t* __restrict__ order) {
+    __shared__ uint32_t s_n[kOrderBuckets];
+    for (int q = threadIdx.x; q < kOrderBuckets; q += kOrderThreads) s_n[q] = 0;
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < T; t += kOrderThreads) {
+        const uint32_t len = (uint32_t)max(ranges[2 * t + 1] - ranges[2 * t], 0);
+        atomicAdd(&s_n[length_bucket(len)], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // heaviest bucket first
+        uint32_t run = 0;
+        for (int q = kOrderBuckets - 1; q >= 0; q--) {
+            const uint32_t c = s_n[q];
+            s_n[q] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < T; t += kOrderThreads) {
+        const uint32_t len = (uint32_t)max(ranges[2 * t + 1] - ranges[2 * t], 0);
+        const uint32_t pos = atomicAdd(&s_n[length_bucket(len)], 1u);
+        order[pos] = (uint32_t)t;
+    }
+}
+
+// Larger tile counts: key = 2^24 - 1 - min(list length, 2^24 - 1) through the
+// stable radix sort (exact lengths, which also orders the buckets)
 __global__ __launch_bounds__(kBlock) void k_tile_keys(const int32_t* __restrict__ ranges, int64_t T,
                                                       uint32_t* __restrict__ key,
                                                       uint32_t* __restrict__ val) {
@@ -349,7 +392,11 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
                            (uint32_t)T);
         c->ids = reinterpret_cast<const int32_t*>(c->iv[side2]);
         c->ordered = false;
-        if (tile_order && T > 0) {
+        if (tile_order && T > 0 && T <= ((int64_t)1 << 20)) {
+            hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, st, c->ranges, T,
+                               c->tile_order);
+            c->ordered = true;
+        } else if (tile_order && T > 0) {
             hipLaunchKernelGGL(k_tile_keys, dim3((unsigned)((T + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                                st, c->ranges, T, c->tk[0], c->tile_order);
             // sort (key, tile) pairs: tile_order holds the values of the first buffer pair

@@ -141,8 +141,10 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
                 if (done[k]) continue;
                 const float dx = mx - fx[k];
                 const float dy = my - fy[k];
+                // listed splats have positive-definite conics (binning drops the
+                // rest), so sigma >= 0 needs no test of its own
                 const float e2 = splat_e2(qa, qb, qc, dx, dy);
-                if (e2 > 0.f || e2 < cut) continue;
+                if (e2 < cut) continue;
                 const float alpha = fminf(amax, o * __builtin_amdgcn_exp2f(e2));
                 if (alpha < amin) continue;
                 const float Tn = T[k] * (1.f - alpha);
@@ -260,8 +262,8 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ re
                 const float araw = o * ex;
                 const float alpha = fminf(amax, araw);
                 // same decisions as the forward: before the pixel's last
-                // contributor, inside the support, above the alpha gate
-                const bool live = pos < L[k] && e2 <= 0.f && alpha >= amin;
+                // contributor and above the alpha gate
+                const bool live = pos < L[k] && alpha >= amin;
                 if (live) {
                     any = true;
                     const float iom = __builtin_amdgcn_rcpf(1.f - alpha);
