@@ -75,21 +75,6 @@ class EventTimer:
         return {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in self.ev.items()}
 
 
-def tile_last_sum(last, wh, tw=16, th=16):
-    """C_f: sum over tiles of the largest `last` of the tile's pixels, i.e. the
-    list entries a tile's compositing must read."""
-    off = 0
-    tot = 0
-    for W, H in wh:
-        img = last[off:off + W * H].reshape(H, W)
-        off += W * H
-        gy, gx = (H + th - 1) // th, (W + tw - 1) // tw
-        pad = np.zeros((gy * th, gx * tw), np.int64)
-        pad[:H, :W] = img
-        tot += int(pad.reshape(gy, th, gx, tw).max(axis=(1, 3)).sum())
-    return tot
-
-
 def make_workload(name):
     import scenegen
     t0 = time.time()
@@ -183,17 +168,16 @@ def run_joint(torch, name, steps, warmup, tune=True, tile=None, order=0, graph=T
     torch.cuda.synchronize()
     stat0 = st.ctx.status()
     from paper_2603_04847_amd import _lib as L
-    last = st.last.cpu().numpy()
     wh_b = st.wh_all[batches[0]]
     P = int((wh_b[:, 0].astype(np.int64) * wh_b[:, 1]).sum())
-    tw, th = st.settings.tile_w, st.settings.tile_h
-    C_f = tile_last_sum(last[:P], wh_b, tw, th)
-    # (pixel, list entry) evaluations the definition needs: each pixel up to
-    # its final contributor
-    n_eval = int(last[:P].astype(np.int64).sum())
-    nt = st.ctx.buffers()["n_tiles"]
-    n_contrib = int(L.copy_to_host(L.gs_ctx_tile_stats(st.ctx)["tile_contrib"], nt, np.int32)
-                    .astype(np.int64).sum())
+    ts = L.gs_ctx_tile_stats(st.ctx)
+    nt = ts["n_tiles"]
+    tile_sum = lambda key: int(L.copy_to_host(ts[key], nt, np.int32).astype(np.int64).sum())
+    # list entries the tiles read, (pixel, entry) evaluations the definition
+    # makes up to each pixel's last contributor, contributing pairs
+    C_f = tile_sum("tile_entries")
+    n_eval = tile_sum("tile_evals")
+    n_contrib = tile_sum("tile_contrib")
     sizes = dict(P=P, N=st.N, V=len(batches[0]), K=(st.sh_degree + 1) ** 2,
                  n_visible=stat0["n_visible"], n_isect=stat0["n_isect"], C_f=C_f,
                  n_eval=n_eval, n_contrib=n_contrib,

@@ -1,17 +1,22 @@
-// Tile binning and key sort.
+// Tile binning and key sort, kept per block of 4 x 4 tiles.
 //
-//  1. count:   per pair, the tiles its alpha >= alpha_min ellipse meets (row by
-//              row, from the ellipse's x-span in each quadrant band), and its
-//              depth key (float32 depth bits; positive floats order like their
-//              bits).  Culled pairs get key 0xFFFFFFFF and no tiles.
+//  1. count:   per pair, the blocks its alpha >= alpha_min ellipse meets (one
+//              block row at a time, from the ellipse's x-span in each quadrant
+//              row), and its depth key (float32 depth bits; positive floats
+//              order like their bits).  Culled pairs get key 0xFFFFFFFF and no
+//              blocks.
 //  2. sort the pairs by depth key (stable LSD radix from pair order, so equal
 //     depths stay in pair order): this is the (depth, pair) order.
-//  3. scan the tile counts in that order and emit one (tile, pair) entry per
-//     intersection; entries of one pair are contiguous, pairs in depth order.
-//  4. stable radix sort of the entries on the tile id only: inside every tile
-//     the depth order of step 2 survives, so each tile list ends up in
+//  3. scan the block counts in that order and emit one (block, pair, 64-bit
+//     quadrant mask) entry per block met; entries of one pair are contiguous,
+//     pairs in depth order.
+//  4. stable radix sort of the entries on the block id only: inside every block
+//     the depth order of step 2 survives, so each block list ends up in
 //     ascending (depth, pair) order without sorting on depth again.
-//  5. tile ranges from the boundaries of the sorted tile ids.
+//  5. block ranges from the boundaries of the sorted block ids, and the lists
+//     (pair, mask) gathered into that order.
+// A tile's list, the definition, is its block's list restricted to entries
+// whose mask meets one of the tile's four quadrants.
 #include <algorithm>
 
 #include "gs_internal.h"
@@ -31,9 +36,9 @@ __device__ __forceinline__ bool record_ok(const float4& a, const float4& b, floa
            a.w > alpha_min && a.w <= 1.f;
 }
 
-// Work of one wave, flattened: its 64 splats' tile rows ("units") are laid end
+// Work of one wave, flattened: its 64 splats' block rows ("units") are laid end
 // to end and handed to the lanes in turn, so a wave costs its total number of
-// tile rows rather than 64 times its tallest splat.
+// block rows rather than 64 times its tallest splat.
 struct WaveUnits {
     SplatSpan sp[kWave];
     int v[kWave];
@@ -67,9 +72,9 @@ __device__ __forceinline__ void wave_units_load(WaveUnits& wu, int lane, bool ok
                                                 const RasterParams& rp, uint32_t& total) {
     uint32_t units = 0;
     if (ok) {
-        const SplatSpan sp = splat_span(a, b, vt.H[v], rp.tile_h, rp.alpha_min);
+        const SplatSpan sp = splat_span(a, b, vt.H[v], quad_grid(rp.tile_w, rp.tile_h), rp.alpha_min);
         wu.sp[lane] = sp;
-        if (sp.r0 <= sp.r1) units = (uint32_t)((sp.r1 >> 1) - (sp.r0 >> 1) + 1);
+        if (sp.r0 <= sp.r1) units = (uint32_t)(sp.r1 / kBlockQuads - sp.r0 / kBlockQuads + 1);
     }
     wu.v[lane] = v;
     const uint32_t ex = wave_excl_scan(units, total);
@@ -87,6 +92,7 @@ __global__ __launch_bounds__(kBlock) void k_count(const float4* __restrict__ rec
     const int64_t pair = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     WaveUnits& wu = s_wu[w];
+    const QuadGrid qg = quad_grid(rp.tile_w, rp.tile_h);
     float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
     int v = 0;
     bool ok = false;
@@ -103,9 +109,10 @@ __global__ __launch_bounds__(kBlock) void k_count(const float4* __restrict__ rec
     for (uint32_t j = lane; j < U; j += kWave) {
         const int q = seg_search(wu.upre, kWave, j);
         const int vq = wu.v[q];
-        const int tr = (wu.sp[q].r0 >> 1) + (int)(j - wu.upre[q]);
-        const TileRowSpan z = tile_row_span(wu.sp[q], tr, vt.W[vq], vt.H[vq], rp.tile_w, rp.tile_h);
-        if (z.count) atomicAdd(&s_cnt[w][q], (uint32_t)z.count);
+        const int br = wu.sp[q].r0 / kBlockQuads + (int)(j - wu.upre[q]);
+        const BlockUnit u = block_unit(wu.sp[q], br, vt.W[vq], vt.H[vq], qg);
+        const int n = block_unit_count(u);
+        if (n) atomicAdd(&s_cnt[w][q], (uint32_t)n);
     }
     __syncthreads();
     if (pair < (int64_t)vt.V * N) {
@@ -116,7 +123,7 @@ __global__ __launch_bounds__(kBlock) void k_count(const float4* __restrict__ rec
     }
 }
 
-// tile counts in depth order; also the number of visible pairs (they sort first)
+// entry counts in depth order; also the number of visible pairs (they sort first)
 __global__ __launch_bounds__(kBlock) void k_gather_cnt(const uint32_t* __restrict__ order,
                                                        const uint32_t* __restrict__ keys,
                                                        const uint32_t* __restrict__ cnt,
@@ -143,31 +150,25 @@ __global__ void k_isect_total(const uint32_t* __restrict__ total, int64_t cap,
     }
 }
 
-// One (tile, pair | mask) entry per intersection, pairs in depth order: rank r's
-// entries fill [off[r], off[r] + cnt).  The 64 ranks of a wave own one
-// contiguous output range, so after the units of a round are laid out (an
-// exclusive scan of their entry counts, in rank order) the lanes write
-// consecutive slots of it: every store of the wave is coalesced.
-struct UnitDesc {
-    int q, tr, t0, n0, t1;      // splat, tile row, union = [t0, t0+n0) u [t1, ...)
-    int a0, b0, a1, b1;         // quadrant-column ranges of the two bands
-};
-
+// One (block key; pair, mask) entry per block met, pairs in depth order: rank
+// r's entries fill [off[r], off[r] + cnt).  The 64 ranks of a wave own one
+// contiguous output range; in each round every lane takes one unit (block
+// row) and writes its entries at the unit's place in the wave's range.
 __global__ __launch_bounds__(kBlock) void k_emit(const float4* __restrict__ rec, int N, ViewTable vt,
                                                  RasterParams rp, const uint32_t* __restrict__ order,
                                                  const uint32_t* __restrict__ off,
                                                  const uint32_t* __restrict__ cnt, int64_t n,
                                                  const uint32_t* __restrict__ used,
                                                  uint32_t* __restrict__ okey,
-                                                 uint32_t* __restrict__ oval) {
+                                                 uint32_t* __restrict__ opair,
+                                                 uint32_t* __restrict__ omlo,
+                                                 uint32_t* __restrict__ omhi) {
     __shared__ WaveUnits s_wu[kWaves];
     __shared__ uint32_t s_pair[kWaves][kWave];
-    __shared__ UnitDesc s_ud[kWaves][kWave];
-    __shared__ uint32_t s_epre[kWaves][kWave + 1];
-    __shared__ uint32_t s_U[kWaves];
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     WaveUnits& wu = s_wu[w];
+    const QuadGrid qg = quad_grid(rp.tile_w, rp.tile_h);
     const bool any = *used != 0u;  // nothing is written after an overflow
     float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
     int v = 0;
@@ -192,80 +193,53 @@ __global__ __launch_bounds__(kBlock) void k_emit(const float4* __restrict__ rec,
     uint32_t U;
     wave_units_load(wu, lane, ok, a, b, v, vt, rp, U);
     s_pair[w][lane] = pair;
-    if (lane == 0) s_U[w] = U;
     __syncthreads();
-    // rounds run block-wide (they contain block barriers): up to the largest U
-    uint32_t Umax = 0;
-    for (int q = 0; q < kWaves; q++) Umax = max(Umax, s_U[q]);
     uint32_t done = 0;  // entries of the wave written so far
-    for (uint32_t ub = 0; ub < Umax; ub += kWave) {
-        // lay out one round of units
+    for (uint32_t ub = 0; ub < U; ub += kWave) {
         const uint32_t j = ub + lane;
+        BlockUnit u;
+        u.bc0 = 1;
+        u.bc1 = 0;
+        int q = 0, br = 0;
         uint32_t ne = 0;
         if (j < U) {
-            const int q = seg_search(wu.upre, kWave, j);
+            q = seg_search(wu.upre, kWave, j);
             const int vq = wu.v[q];
-            const int tr = (wu.sp[q].r0 >> 1) + (int)(j - wu.upre[q]);
-            const TileRowSpan z = tile_row_span(wu.sp[q], tr, vt.W[vq], vt.H[vq], rp.tile_w, rp.tile_h);
-            UnitDesc d;
-            d.q = q;
-            d.tr = tr;
-            d.a0 = z.a0;
-            d.b0 = z.b0;
-            d.a1 = z.a1;
-            d.b1 = z.b1;
-            ne = (uint32_t)z.count;
-            // the union of the bands' tile columns: one run, or two disjoint runs
-            const bool e0 = z.a0 > z.b0, e1 = z.a1 > z.b1;
-            const int p0 = z.a0 >> 1, q0 = z.b0 >> 1, p1 = z.a1 >> 1, q1 = z.b1 >> 1;
-            if (!e0 && !e1 && (q0 + 1 < p1 || q1 + 1 < p0)) {
-                const bool first0 = p0 < p1;
-                d.t0 = first0 ? p0 : p1;
-                d.n0 = first0 ? q0 - p0 + 1 : q1 - p1 + 1;
-                d.t1 = first0 ? p1 : p0;
-            } else {
-                d.t0 = z.tc0;
-                d.n0 = z.count;
-                d.t1 = 0;
-            }
-            s_ud[w][lane] = d;
+            br = wu.sp[q].r0 / kBlockQuads + (int)(j - wu.upre[q]);
+            u = block_unit(wu.sp[q], br, vt.W[vq], vt.H[vq], qg);
+            ne = (uint32_t)block_unit_count(u);
         }
         uint32_t rt;
-        const uint32_t ex = wave_excl_scan(ne, rt);
-        s_epre[w][lane] = ex;
-        if (lane == 0) s_epre[w][kWave] = rt;
-        __syncthreads();
-        const int nu = ub < U ? (int)min((uint32_t)kWave, U - ub) : 0;
-        for (uint32_t e = lane; e < rt; e += kWave) {
-            const int u = seg_search(s_epre[w], nu, e);
-            const UnitDesc& d = s_ud[w][u];
-            const int k = (int)(e - s_epre[w][u]);
-            const int tc = k < d.n0 ? d.t0 + k : d.t1 + (k - d.n0);
-            TileRowSpan z;
-            z.a0 = d.a0;
-            z.b0 = d.b0;
-            z.a1 = d.a1;
-            z.b1 = d.b1;
-            const uint32_t m = tile_row_mask(z, tc);
-            const uint32_t o = done + e;
-            if (o < wave_total) {  // never write outside the wave's slots
-                const int vq = wu.v[d.q];
-                okey[base + o] = (uint32_t)vt.tile_off[vq] + (uint32_t)(d.tr * vt.gx[vq] + tc);
-                oval[base + o] = s_pair[w][d.q] | (m << kPairBits);
+        uint32_t o = done + wave_excl_scan(ne, rt);
+        if (ne) {
+            const int vq = wu.v[q];
+            const uint32_t brow = (uint32_t)vt.block_off[vq] + (uint32_t)(br * vt.bx[vq]);
+            const uint32_t pq = s_pair[w][q];
+            for (int bc = u.bc0; bc <= u.bc1; bc++) {
+                const uint64_t m = block_unit_mask(u, bc);
+                if (m == 0) continue;
+                if (o < wave_total) {  // never write outside the wave's slots
+                    okey[base + o] = brow + (uint32_t)bc;
+                    opair[base + o] = pq;
+                    omlo[base + o] = (uint32_t)m;
+                    omhi[base + o] = (uint32_t)(m >> 32);
+                }
+                o++;
             }
         }
         done += rt;
-        __syncthreads();
     }
     // slots not filled (only if the two passes ever disagreed) get a sentinel
-    // tile id past every tile, so no list ever sees stale entries
+    // block id past every block, so no list ever sees stale entries
     for (uint32_t o = done + lane; o < wave_total; o += kWave) {
-        okey[base + o] = (uint32_t)vt.tile_off[vt.V];
-        oval[base + o] = s_pair[w][0];
+        okey[base + o] = (uint32_t)vt.block_off[vt.V];
+        opair[base + o] = s_pair[w][0];
+        omlo[base + o] = 0;
+        omhi[base + o] = 0;
     }
 }
 
-// tile ranges from the boundaries of the sorted keys, four keys per thread
+// block ranges from the boundaries of the sorted keys, four keys per thread
 __global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t* __restrict__ keys,
                                                    const uint32_t* __restrict__ used,
                                                    int32_t* __restrict__ ranges, uint32_t T) {
@@ -297,6 +271,17 @@ __global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t* __restrict__ 
     }
 }
 
+// block of tile t, and the tile's place (sx, sy) in it
+__device__ __forceinline__ int tile_block(const ViewTable& vt, int t, int& sx, int& sy) {
+    int v = 0;
+    while (v + 1 < vt.V && t >= vt.tile_off[v + 1]) v++;
+    const int lt = t - vt.tile_off[v];
+    const int tx = lt % vt.gx[v], ty = lt / vt.gx[v];
+    sx = tx % kBlockTiles;
+    sy = ty % kBlockTiles;
+    return vt.block_off[v] + (ty / kBlockTiles) * vt.bx[v] + tx / kBlockTiles;
+}
+
 // Launch order of the tiles, heaviest first.  The weight is a log-scale bucket
 // of the list length, exact in integers: 16 buckets per octave from the leading
 // bit and the four bits after it (0 for an empty list).  Inside a bucket the
@@ -310,18 +295,26 @@ __device__ __forceinline__ uint32_t length_bucket(uint32_t len) {
 constexpr int kOrderBuckets = 513;
 constexpr int kOrderThreads = 1024;
 
+// Bucket of each tile's weight (its block's list length).
+__global__ __launch_bounds__(kBlock) void k_tile_bucket(const int32_t* __restrict__ ranges,
+                                                        ViewTable vt, int64_t T,
+                                                        uint32_t* __restrict__ bucket) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= T) return;
+    int sx, sy;
+    const int B = tile_block(vt, (int)t, sx, sy);
+    bucket[t] = length_bucket((uint32_t)max(ranges[2 * B + 1] - ranges[2 * B], 0));
+}
+
 // One block: histogram of the buckets, their scan from the heaviest down, and
 // a scatter through LDS cursors.  For up to 2^20 tiles.
-__global__ __launch_bounds__(kOrderThreads) void k_tile_order(const int32_t* __restrict__ ranges,
+__global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint32_t* __restrict__ bucket,
                                                                int64_t T,
                                                                uint32_t* __restrict__ order) {
     __shared__ uint32_t s_n[kOrderBuckets];
     for (int q = threadIdx.x; q < kOrderBuckets; q += kOrderThreads) s_n[q] = 0;
     __syncthreads();
-    for (int64_t t = threadIdx.x; t < T; t += kOrderThreads) {
-        const uint32_t len = (uint32_t)max(ranges[2 * t + 1] - ranges[2 * t], 0);
-        atomicAdd(&s_n[length_bucket(len)], 1u);
-    }
+    for (int64_t t = threadIdx.x; t < T; t += kOrderThreads) atomicAdd(&s_n[bucket[t]], 1u);
     __syncthreads();
     if (threadIdx.x == 0) {
         // heaviest bucket first
@@ -334,20 +327,22 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const int32_t* __r
     }
     __syncthreads();
     for (int64_t t = threadIdx.x; t < T; t += kOrderThreads) {
-        const uint32_t len = (uint32_t)max(ranges[2 * t + 1] - ranges[2 * t], 0);
-        const uint32_t pos = atomicAdd(&s_n[length_bucket(len)], 1u);
+        const uint32_t pos = atomicAdd(&s_n[bucket[t]], 1u);
         order[pos] = (uint32_t)t;
     }
 }
 
-// Larger tile counts: key = 2^24 - 1 - min(list length, 2^24 - 1) through the
-// stable radix sort (exact lengths, which also orders the buckets)
-__global__ __launch_bounds__(kBlock) void k_tile_keys(const int32_t* __restrict__ ranges, int64_t T,
+// Larger tile counts: key = 2^24 - 1 - min(block list length, 2^24 - 1) through
+// the stable radix sort (exact lengths, which also orders the buckets)
+__global__ __launch_bounds__(kBlock) void k_tile_keys(const int32_t* __restrict__ ranges,
+                                                      ViewTable vt, int64_t T,
                                                       uint32_t* __restrict__ key,
                                                       uint32_t* __restrict__ val) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t >= T) return;
-    const uint32_t len = (uint32_t)max(ranges[2 * t + 1] - ranges[2 * t], 0);
+    int sx, sy;
+    const int B = tile_block(vt, (int)t, sx, sy);
+    const uint32_t len = (uint32_t)max(ranges[2 * B + 1] - ranges[2 * B], 0);
     key[t] = 0xFFFFFFu - min(len, 0xFFFFFFu);
     val[t] = (uint32_t)t;
 }
@@ -359,10 +354,12 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
     const int64_t npairs = (int64_t)vt.V * N;
     const float4* rec = reinterpret_cast<const float4*>(records ? records : c->rec);
     const int64_t T = vt.tile_off[vt.V];
+    const int64_t NB = vt.block_off[vt.V];
     hipError_t e = hipSuccess;
-    // tile ranges start empty
-    if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(c->ranges), 0u, 2 * T, st)) != hipSuccess)
+    // block ranges start empty
+    if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(c->ranges), 0u, 2 * NB, st)) != hipSuccess)
         return e;
+    c->ordered = false;
     if (npairs > 0) {
         const unsigned gp = (unsigned)((npairs + kBlock - 1) / kBlock);
         hipLaunchKernelGGL(k_count, dim3(gp), dim3(kBlock), 0, st, rec, N, vt, rp, c->cnt, c->pk[0],
@@ -379,26 +376,31 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
             return e;
         hipLaunchKernelGGL(k_isect_total, dim3(1), dim3(64), 0, st, total, c->cap.max_isect, used,
                            c->diag);
+        const int64_t I = c->cap.max_isect;
         hipLaunchKernelGGL(k_emit, dim3(gp), dim3(kBlock), 0, st, rec, N, vt, rp, order, c->off,
-                           c->cnt, npairs, used, c->ik[0], c->iv[0]);
-        int tbits = 1;  // tile ids and the sentinel T
-        while (((int64_t)1 << tbits) <= T) tbits++;
-        const int side2 = radix_sort_pairs(c->ik[0], c->iv[0], c->ik[1], c->iv[1],
-                                           c->cap.max_isect, used, 0, tbits, c->hist,
-                                           c->scan_scratch, st, &e);
+                           c->cnt, npairs, used, c->ik[0], c->iv[0], c->im[0], c->im[0] + I);
+        int bbits = 1;  // block ids and the sentinel NB
+        while (((int64_t)1 << bbits) <= NB) bbits++;
+        // the pair and both mask words travel with the block key
+        uint32_t* K[2] = {c->ik[0], c->ik[1]};
+        uint32_t* Vv[3][2] = {{c->iv[0], c->iv[1]}, {c->im[0], c->im[1]}, {c->im[0] + I, c->im[1] + I}};
+        const int side2 = radix_sort_kv3(K, Vv, I, used, 0, bbits, c->hist, c->scan_scratch, st, &e);
         if (e != hipSuccess) return e;
-        const unsigned gi = (unsigned)std::min<int64_t>((c->cap.max_isect + kBlock - 1) / kBlock, 4096);
+        c->lpair = c->iv[side2];
+        c->lmask_lo = c->im[side2];
+        c->lmask_hi = c->im[side2] + I;
+        const unsigned gi = (unsigned)std::min<int64_t>((I + kBlock - 1) / kBlock, 4096);
         hipLaunchKernelGGL(k_ranges, dim3(gi), dim3(kBlock), 0, st, c->ik[side2], used, c->ranges,
-                           (uint32_t)T);
-        c->ids = reinterpret_cast<const int32_t*>(c->iv[side2]);
-        c->ordered = false;
+                           (uint32_t)NB);
         if (tile_order && T > 0 && T <= ((int64_t)1 << 20)) {
-            hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, st, c->ranges, T,
+            hipLaunchKernelGGL(k_tile_bucket, dim3((unsigned)((T + kBlock - 1) / kBlock)), dim3(kBlock),
+                               0, st, c->ranges, vt, T, c->tk[0]);
+            hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, st, c->tk[0], T,
                                c->tile_order);
             c->ordered = true;
         } else if (tile_order && T > 0) {
             hipLaunchKernelGGL(k_tile_keys, dim3((unsigned)((T + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                               st, c->ranges, T, c->tk[0], c->tile_order);
+                               st, c->ranges, vt, T, c->tk[0], c->tile_order);
             // sort (key, tile) pairs: tile_order holds the values of the first buffer pair
             uint32_t* kk[2] = {c->tk[0], c->tk[1]};
             uint32_t* vv[2] = {c->tile_order, reinterpret_cast<uint32_t*>(c->tile_contrib)};
@@ -411,10 +413,9 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
             }
             c->ordered = true;
         }
-    } else {
-        c->ids = reinterpret_cast<const int32_t*>(c->iv[0]);
     }
     c->n_tiles = T;
+    c->n_blocks = NB;
     c->bin_V = vt.V;
     c->bin_N = N;
     c->bin_tw = rp.tile_w;

@@ -18,19 +18,24 @@ ViewTable make_view_table(const int32_t* wh, int V, int TW, int TH, const int32_
     ViewTable vt;
     memset(&vt, 0, sizeof vt);
     vt.V = V;
-    int toff = 0, poff = 0;
+    int toff = 0, poff = 0, boff = 0;
     for (int v = 0; v < V; v++) {
         vt.cam[v] = index ? index[v] : v;
         vt.W[v] = wh[2 * v];
         vt.H[v] = wh[2 * v + 1];
         vt.gx[v] = (vt.W[v] + TW - 1) / TW;
+        const int gy = (vt.H[v] + TH - 1) / TH;
+        vt.bx[v] = (vt.gx[v] + gs::kBlockTiles - 1) / gs::kBlockTiles;
         vt.tile_off[v] = toff;
         vt.pix_off[v] = poff;
-        toff += vt.gx[v] * ((vt.H[v] + TH - 1) / TH);
+        vt.block_off[v] = boff;
+        toff += vt.gx[v] * gy;
         poff += vt.W[v] * vt.H[v];
+        boff += vt.bx[v] * ((gy + gs::kBlockTiles - 1) / gs::kBlockTiles);
     }
     vt.tile_off[V] = toff;
     vt.pix_off[V] = poff;
+    vt.block_off[V] = boff;
     return vt;
 }
 
@@ -166,11 +171,15 @@ gs_status gs_ctx_create(gs_ctx** out, const gs_capacity* cap) {
         A(dalloc(&c.ik[k], (size_t)I));
         A(dalloc(&c.iv[k], (size_t)I));
     }
+    A(dalloc(&c.im[0], (size_t)2 * I));
+    A(dalloc(&c.im[1], (size_t)2 * I));
     A(dalloc(&c.ranges, (size_t)2 * T));
     A(dalloc(&c.tile_order, (size_t)T));
     A(dalloc(&c.tk[0], (size_t)T));
     A(dalloc(&c.tk[1], (size_t)T));
     A(dalloc(&c.tile_contrib, (size_t)T));
+    A(dalloc(&c.tile_entries, (size_t)T));
+    A(dalloc(&c.tile_evals, (size_t)T));
     const size_t hw = gs::radix_hist_words(sortmax);
     A(dalloc(&c.hist, hw));
     A(dalloc(&c.scan_scratch, gs::scan_scratch_words((int64_t)hw)));
@@ -188,7 +197,9 @@ gs_status gs_ctx_create(gs_ctx** out, const gs_capacity* cap) {
     if (e == hipSuccess) A(hipMemset(c.diag, 0, sizeof(uint32_t) * gs::kDiagCount));
     if (e == hipSuccess) A(hipMemset(c.scalars, 0, sizeof(uint32_t) * 16));
     if (e == hipSuccess) A(hipDeviceSynchronize());
-    c.ids = reinterpret_cast<const int32_t*>(c.iv[0]);
+    c.lpair = c.iv[0];
+    c.lmask_lo = c.im[0];
+    c.lmask_hi = c.im[0] + I;
     if (e != hipSuccess) {
         gs_ctx_destroy(h);
         return GS_ERR_HIP;
@@ -201,8 +212,8 @@ gs_status gs_ctx_destroy(gs_ctx* h) {
     if (!h) return GS_ERR_INVALID_ARG;
     gs::Ctx& c = h->c;
     void* ptrs[] = {c.rec, c.grad2d, c.cnt, c.off, c.pk[0], c.pk[1], c.pv[0], c.pv[1],
-                    c.ik[0], c.ik[1], c.iv[0], c.iv[1], c.ranges, c.tile_order, c.tk[0], c.tk[1],
-                    c.tile_contrib, c.hist,
+                    c.ik[0], c.ik[1], c.iv[0], c.iv[1], c.im[0], c.im[1],
+                    c.ranges, c.tile_order, c.tk[0], c.tk[1], c.tile_contrib, c.tile_entries, c.tile_evals, c.hist,
                     c.scan_scratch, c.scalars, c.twist_render, c.twist_track, c.loss_acc, c.diag};
     hipDeviceSynchronize();
     for (void* p : ptrs)
@@ -229,22 +240,27 @@ gs_status gs_ctx_reset_status(gs_ctx* h, void* stream) {
     return from_hip(gs::launch_fill_u32(h->c.diag, 0u, gs::kDiagCount, (hipStream_t)stream));
 }
 
-gs_status gs_ctx_buffers(gs_ctx* h, float** records, int32_t** isect_ids, int32_t** tile_ranges,
-                         int64_t* n_tiles) {
+gs_status gs_ctx_buffers(gs_ctx* h, float** records, int32_t** list_pairs, uint32_t** list_masks,
+                         int32_t** block_ranges, int64_t* n_blocks) {
     if (!h) return GS_ERR_INVALID_ARG;
     if (records) *records = h->c.rec;
-    if (isect_ids) *isect_ids = const_cast<int32_t*>(h->c.ids);
-    if (tile_ranges) *tile_ranges = h->c.ranges;
-    if (n_tiles) *n_tiles = h->c.n_tiles;
+    if (list_pairs) *list_pairs = reinterpret_cast<int32_t*>(const_cast<uint32_t*>(h->c.lpair));
+    if (list_masks) *list_masks = const_cast<uint32_t*>(h->c.lmask_lo);
+    if (block_ranges) *block_ranges = h->c.ranges;
+    if (n_blocks) *n_blocks = h->c.n_blocks;
     return GS_OK;
 }
 
-gs_status gs_ctx_tile_stats(gs_ctx* h, const int32_t** tile_contrib, const uint32_t** tile_order,
-                            int32_t* ordered) {
+gs_status gs_ctx_tile_stats(gs_ctx* h, const int32_t** tile_contrib, const int32_t** tile_entries,
+                            const int32_t** tile_evals, const uint32_t** tile_order,
+                            int32_t* ordered, int64_t* n_tiles) {
     if (!h) return GS_ERR_INVALID_ARG;
     if (tile_contrib) *tile_contrib = h->c.tile_contrib;
+    if (tile_entries) *tile_entries = h->c.tile_entries;
+    if (tile_evals) *tile_evals = h->c.tile_evals;
     if (tile_order) *tile_order = h->c.tile_order;
     if (ordered) *ordered = h->c.ordered ? 1 : 0;
+    if (n_tiles) *n_tiles = h->c.n_tiles;
     return GS_OK;
 }
 

@@ -19,6 +19,8 @@ struct ViewTable {
     int gx[GS_MAX_VIEWS];
     int tile_off[GS_MAX_VIEWS + 1];  // first global tile of each view
     int pix_off[GS_MAX_VIEWS + 1];   // first packed pixel of each view
+    int bx[GS_MAX_VIEWS];            // block columns of each view
+    int block_off[GS_MAX_VIEWS + 1]; // first global block of each view
     int cam[GS_MAX_VIEWS];           // row of viewmat / intr / v_twist used by the view
 };
 
@@ -141,109 +143,152 @@ __device__ __forceinline__ float splat_e2(float a, float b, float c, float dx, f
 // made conservative (relative 1e-4 plus 1e-4, and 1e-3 px on every interval)
 // so float rounding can only add quadrants that contribute nothing.
 struct SplatSpan {
-    float mx, my, A, B, C, t, det, ey, dyL;
+    float mx, my, B, iA, t2A, det, ey, dyL;
     int r0, r1;  // quadrant rows that may be met (r0 > r1: none)
 };
 
 constexpr float kSpanEps = 1e-3f;
 
-__device__ __forceinline__ SplatSpan splat_span(const float4& a, const float4& b, int H, int TH,
-                                                float alpha_min) {
+// Quadrant geometry of a call: half-tile sizes and their reciprocals (exact,
+// powers of two), so no division is left in the per-row work.
+struct QuadGrid {
+    int hw, hh;
+    float ihw, ihh;
+};
+
+__host__ __device__ __forceinline__ QuadGrid quad_grid(int TW, int TH) {
+    QuadGrid g;
+    g.hw = TW / 2;
+    g.hh = TH / 2;
+    g.ihw = 1.f / (float)g.hw;
+    g.ihh = 1.f / (float)g.hh;
+    return g;
+}
+
+// Contraction stays off in the span arithmetic: the count and the emit pass
+// evaluate it separately and must agree to the bit.
+__device__ __forceinline__ SplatSpan splat_span(const float4& a, const float4& b, int H,
+                                                const QuadGrid& g, float alpha_min) {
+#pragma clang fp contract(off)
     SplatSpan s;
     s.mx = a.x;
     s.my = a.y;
-    s.A = b.x;
-    s.B = b.y;
-    s.C = b.z;
-    s.t = __logf(a.w / alpha_min) * 1.0001f + 1e-4f;
-    s.det = s.A * s.C - s.B * s.B;
-    const float sxx = s.C / s.det, syy = s.A / s.det, sxy = -s.B / s.det;  // Sigma2D
-    s.ey = sqrtf(2.f * s.t * syy);
-    s.dyL = -sxy * sqrtf(2.f * s.t / sxx);  // dy of the leftmost point
-    const int hh = TH / 2;
-    const int nrows = (H + hh - 1) / hh;
-    s.r0 = max((int)floorf((s.my - s.ey - kSpanEps) / hh), 0);
-    s.r1 = min((int)floorf((s.my + s.ey + kSpanEps) / hh), nrows - 1);
+    const float A = b.x, B = b.y, C = b.z;
+    const float t = __logf(a.w / alpha_min) * 1.0001f + 1e-4f;
+    s.B = B;
+    s.iA = 1.f / A;
+    s.t2A = 2.f * A * t;
+    s.det = A * C - B * B;
+    const float idet = 1.f / s.det;
+    // Sigma2D = [[C, -B], [-B, A]] / det; vertical half-extent sqrt(2 t Syy) and
+    // the height of the leftmost point -Sxy sqrt(2 t / Sxx)
+    s.ey = __builtin_amdgcn_sqrtf(2.f * t * A * idet);
+    s.dyL = B * idet * __builtin_amdgcn_sqrtf(2.f * t * s.det / C);
+    const int nrows = (H + g.hh - 1) / g.hh;
+    s.r0 = max((int)floorf((s.my - s.ey - kSpanEps) * g.ihh), 0);
+    s.r1 = min((int)floorf((s.my + s.ey + kSpanEps) * g.ihh), nrows - 1);
     return s;
 }
 
-// Quadrant columns [c0, c1] of quadrant row r met by the splat (c0 > c1: none).
-__device__ __forceinline__ void span_cols(const SplatSpan& s, int r, int W, int H, int TW, int TH,
-                                          int& c0, int& c1) {
-    const int hh = TH / 2, hw = TW / 2;
+// Quadrant columns [c0, c1] of quadrant row r met by the splat (c0 > c1:
+// none); ncols = quadrant columns of the view.
+__device__ __forceinline__ void span_cols(const SplatSpan& s, int r, int W, int H, const QuadGrid& g,
+                                          int ncols, int& c0, int& c1) {
+#pragma clang fp contract(off)
     c0 = 1;
     c1 = 0;
-    const float ya = r * hh + 0.5f, yb = (float)min(r * hh + hh, H) - 0.5f;
+    const float ya = r * g.hh + 0.5f, yb = (float)min(r * g.hh + g.hh, H) - 0.5f;
     float la = fmaxf(ya - s.my, -s.ey), lb = fminf(yb - s.my, s.ey);
     if (la > lb + kSpanEps) return;
     if (la > lb) la = lb = 0.5f * (la + lb);
     // x offsets of the ellipse boundary at height dy: (-B dy -/+ sqrt(2 A t - det dy^2)) / A
     const float dl = fminf(fmaxf(s.dyL, la), lb), dr = fminf(fmaxf(-s.dyL, la), lb);
-    const float iA = 1.f / s.A;
-    const float xl = s.mx + (-s.B * dl - sqrtf(fmaxf(2.f * s.A * s.t - s.det * dl * dl, 0.f))) * iA - kSpanEps;
-    const float xr = s.mx + (-s.B * dr + sqrtf(fmaxf(2.f * s.A * s.t - s.det * dr * dr, 0.f))) * iA + kSpanEps;
+    const float ql = __builtin_amdgcn_sqrtf(fmaxf(s.t2A - s.det * dl * dl, 0.f));
+    const float qr = __builtin_amdgcn_sqrtf(fmaxf(s.t2A - s.det * dr * dr, 0.f));
+    const float xl = s.mx + (-s.B * dl - ql) * s.iA - kSpanEps;
+    const float xr = s.mx + (-s.B * dr + qr) * s.iA + kSpanEps;
     if (!(xl <= (float)W - 0.5f) || !(xr >= 0.5f)) return;
-    const int ncols = (W + hw - 1) / hw;
-    c0 = max((int)ceilf((xl + 0.5f) / hw - 1.f), 0);
-    c1 = min((int)floorf((xr - 0.5f) / hw), ncols - 1);
+    c0 = max((int)ceilf((xl + 0.5f) * g.ihw - 1.f), 0);
+    c1 = min((int)floorf((xr - 0.5f) * g.ihw), ncols - 1);
 }
 
-// The tiles of tile row `tr` met by the splat: the union of the tile columns of
-// its two quadrant rows.  Returns the tile-column range [tc0, tc1] to scan and
-// the quadrant-column ranges of the two bands; count = tiles with a non-zero mask.
-struct TileRowSpan {
-    int a0, b0, a1, b1;  // quadrant-column ranges of the upper and lower band
-    int tc0, tc1;
-    int count;
+// Blocks: 4 x 4 tiles, i.e. 8 x 8 quadrants.  The lists are kept per block; an
+// entry is a splat (its pair index) with the 64-bit mask of the block's
+// quadrants it meets, bit 8 qr + qc for quadrant row qr and column qc inside
+// the block.  A tile's list is the block list filtered to the entries with a
+// non-zero mask on the tile's four quadrants.
+constexpr int kBlockTiles = 4;                  // tiles per block side
+constexpr int kBlockQuads = 2 * kBlockTiles;    // quadrants per block side
+
+// The four quadrant bits (qx + 2 qy) of tile (sx, sy) of a block in a block mask.
+__device__ __forceinline__ uint32_t tile_bits(uint64_t m, int sx, int sy) {
+    const int sh = 16 * sy + 2 * sx;
+    return (uint32_t)((m >> sh) & 3u) | ((uint32_t)((m >> (sh + 8)) & 3u) << 2);
+}
+
+// One block row of a splat's footprint ("unit"): the quadrant-column interval
+// of each of its (up to 8) quadrant rows, and the block columns they span.
+struct BlockUnit {
+    int c0[kBlockQuads], c1[kBlockQuads];  // quadrant columns per row (c0 > c1: none)
+    int bc0, bc1;                          // block columns to scan (bc0 > bc1: none)
 };
 
-__device__ __forceinline__ TileRowSpan tile_row_span(const SplatSpan& s, int tr, int W, int H, int TW,
-                                                     int TH) {
-    TileRowSpan z;
-    const int hh = TH / 2;
-    const int nrows = (H + hh - 1) / hh;
-    z.a0 = z.a1 = 1;
-    z.b0 = z.b1 = 0;
-    const int r = 2 * tr;
-    if (r >= s.r0 && r <= s.r1) span_cols(s, r, W, H, TW, TH, z.a0, z.b0);
-    if (r + 1 < nrows && r + 1 >= s.r0 && r + 1 <= s.r1) span_cols(s, r + 1, W, H, TW, TH, z.a1, z.b1);
-    const bool e0 = z.a0 > z.b0, e1 = z.a1 > z.b1;
-    const int p0 = z.a0 >> 1, q0 = z.b0 >> 1, p1 = z.a1 >> 1, q1 = z.b1 >> 1;
-    if (e0 && e1) {
-        z.tc0 = 1;
-        z.tc1 = 0;
-        z.count = 0;
-    } else if (e0) {
-        z.tc0 = p1;
-        z.tc1 = q1;
-        z.count = q1 - p1 + 1;
-    } else if (e1) {
-        z.tc0 = p0;
-        z.tc1 = q0;
-        z.count = q0 - p0 + 1;
-    } else {
-        z.tc0 = min(p0, p1);
-        z.tc1 = max(q0, q1);
-        const int ov = min(q0, q1) - max(p0, p1) + 1;  // overlap of the two tile ranges
-        z.count = (q0 - p0 + 1) + (q1 - p1 + 1) - max(ov, 0);
+__device__ __forceinline__ BlockUnit block_unit(const SplatSpan& s, int br, int W, int H,
+                                                const QuadGrid& g) {
+    BlockUnit u;
+    const int ncols = (W + g.hw - 1) / g.hw;
+    u.bc0 = 1 << 30;
+    u.bc1 = -1;
+#pragma unroll
+    for (int i = 0; i < kBlockQuads; i++) {
+        const int r = kBlockQuads * br + i;
+        u.c0[i] = 1;
+        u.c1[i] = 0;
+        // r <= s.r1 keeps r inside the view's quadrant rows
+        if (r >= s.r0 && r <= s.r1) span_cols(s, r, W, H, g, ncols, u.c0[i], u.c1[i]);
+        if (u.c0[i] <= u.c1[i]) {
+            u.bc0 = min(u.bc0, u.c0[i] / kBlockQuads);
+            u.bc1 = max(u.bc1, u.c1[i] / kBlockQuads);
+        }
     }
-    return z;
+    return u;
 }
 
-__device__ __forceinline__ uint32_t tile_row_mask(const TileRowSpan& z, int tc) {
-    uint32_t m = 0;
-    const int c = 2 * tc;
-    if (c >= z.a0 && c <= z.b0) m |= 1u;
-    if (c + 1 >= z.a0 && c + 1 <= z.b0) m |= 2u;
-    if (c >= z.a1 && c <= z.b1) m |= 4u;
-    if (c + 1 >= z.a1 && c + 1 <= z.b1) m |= 8u;
+// The block mask of unit u in block column bc (0: the splat misses the block).
+__device__ __forceinline__ uint64_t block_unit_mask(const BlockUnit& u, int bc) {
+    uint64_t m = 0;
+    const int q0 = kBlockQuads * bc;
+#pragma unroll
+    for (int i = 0; i < kBlockQuads; i++) {
+        const int lo = max(u.c0[i], q0), hi = min(u.c1[i], q0 + kBlockQuads - 1);
+        if (lo <= hi) {
+            const uint64_t run = ((1ull << (hi - lo + 1)) - 1ull) << (lo - q0);
+            m |= run << (kBlockQuads * i);
+        }
+    }
     return m;
 }
 
-// A listed intersection carries the pair index in its low 28 bits and the
-// quadrant mask in the top 4.
-constexpr uint32_t kPairBits = 28;
-constexpr uint32_t kPairMask = (1u << kPairBits) - 1u;
+// Entries of a unit: block columns met by some row (a row meets the block
+// columns c0/8 .. c1/8), counted on a bitmask of the columns from bc0 while
+// they fit in 64 bits, one column at a time beyond.
+__device__ __forceinline__ int block_unit_count(const BlockUnit& u) {
+    if (u.bc0 > u.bc1) return 0;
+    if (u.bc1 - u.bc0 < 64) {
+        uint64_t cols = 0;
+#pragma unroll
+        for (int i = 0; i < kBlockQuads; i++) {
+            if (u.c0[i] > u.c1[i]) continue;
+            const int a = u.c0[i] / kBlockQuads - u.bc0, b = u.c1[i] / kBlockQuads - u.bc0;
+            const uint64_t hi = b >= 63 ? ~0ull : (2ull << b) - 1ull;
+            cols |= hi & ~((1ull << a) - 1ull);
+        }
+        return __popcll(cols);
+    }
+    int n = 0;
+    for (int bc = u.bc0; bc <= u.bc1; bc++) n += block_unit_mask(u, bc) != 0;
+    return n;
+}
 
 // ------------------------------------------------------------------ host launchers
 
@@ -261,6 +306,10 @@ size_t radix_hist_words(int64_t max_n);
 int radix_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_t max_n,
                      const uint32_t* d_n, int lo, int hi, uint32_t* hist, uint32_t* scan_scratch,
                      hipStream_t st, hipError_t* err);
+// The same with three value words per item (separate arrays): K[side],
+// V[word][side]; returns the side holding the result.
+int radix_sort_kv3(uint32_t* K[2], uint32_t* V[3][2], int64_t max_n, const uint32_t* d_n, int lo,
+                   int hi, uint32_t* hist, uint32_t* scan_scratch, hipStream_t st, hipError_t* err);
 
 // bin.hip
 hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp,
@@ -308,16 +357,23 @@ struct Ctx {
     int device;
     float* rec;            // [max_pairs][12]
     float* grad2d;         // [max_pairs][9], kept zero between backward calls
-    uint32_t* cnt;         // [max_pairs] tiles per pair
-    uint32_t* off;         // [max_pairs] tile counts in depth order, then their scan
+    uint32_t* cnt;         // [max_pairs] list entries per pair
+    uint32_t* off;         // [max_pairs] entry counts in depth order, then their scan
     uint32_t* pk[2];       // [max_pairs] depth keys (ping-pong)
     uint32_t* pv[2];       // [max_pairs] pair indices (ping-pong)
-    uint32_t* ik[2];       // [max_isect] tile keys (ping-pong)
+    uint32_t* ik[2];       // [max_isect] block keys (ping-pong)
     uint32_t* iv[2];       // [max_isect] pair indices (ping-pong)
-    int32_t* ranges;       // [max_tiles][2]
+    uint32_t* im[2];       // [2][max_isect] block masks, low then high words (ping-pong)
+    // the block lists of the last bin step (point into iv[] / im[])
+    const uint32_t* lpair;
+    const uint32_t* lmask_lo;
+    const uint32_t* lmask_hi;
+    int32_t* ranges;       // [max_tiles][2] block list ranges (blocks <= tiles)
     uint32_t* tile_order;  // [max_tiles] launch order of the tiles (heaviest first)
     uint32_t* tk[2];       // [max_tiles] sort scratch for the tile order
     int32_t* tile_contrib; // [max_tiles] contributing (pixel, splat) pairs per tile
+    int32_t* tile_entries; // [max_tiles] list entries each tile's forward consumed
+    int32_t* tile_evals;   // [max_tiles] (pixel, entry) evaluations up to the last contributors
     uint32_t* hist;        // radix histograms
     uint32_t* scan_scratch;
     uint32_t* scalars;     // small device counters
@@ -326,8 +382,7 @@ struct Ctx {
     double* loss_acc;      // [4]
     uint32_t* diag;        // [kDiagCount]
     // state of the last bin step
-    const int32_t* ids;    // sorted pair indices (points into iv[])
-    int64_t n_tiles;
+    int64_t n_tiles, n_blocks;
     int bin_V, bin_N, bin_tw, bin_th;
     bool ordered;          // tile_order holds the order of the last bin step
 };

@@ -162,30 +162,38 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restr
         hist[(int64_t)tid * nblocks + blockIdx.x] = s_h[0][tid] + s_h[1][tid] + s_h[2][tid] + s_h[3][tid];
 }
 
-template <int ITEMS>
+// Value arrays moved with the keys: NV words per item, one array each.
+template <int NV>
+struct ValArrays {
+    const uint32_t* in[NV];
+    uint32_t* out[NV];
+};
+
+template <int ITEMS, int NV>
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(
-    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
-    uint32_t* __restrict__ vout, const uint32_t* __restrict__ d_n, int64_t max_n, int shift,
-    int bits, const uint32_t* __restrict__ hist, uint32_t nblocks) {
+    const uint32_t* __restrict__ kin, uint32_t* __restrict__ kout, ValArrays<NV> va,
+    const uint32_t* __restrict__ d_n, int64_t max_n, int shift, int bits,
+    const uint32_t* __restrict__ hist, uint32_t nblocks) {
     constexpr int TILE = kThreads * ITEMS;
     __shared__ uint32_t s_h[kWaves][256];  // per-wave digit counts, then offsets
     __shared__ uint32_t s_start[256];
     __shared__ uint32_t s_glob[256];
     __shared__ uint32_t s_w[kWaves];
     __shared__ uint32_t s_key[TILE];
-    __shared__ uint32_t s_val[TILE];
+    __shared__ uint32_t s_val[NV][TILE];
     const uint32_t n = dev_count(d_n, max_n);
     const int64_t base = (int64_t)blockIdx.x * TILE;
     if (base >= n) return;  // uniform over the block
     const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
     const uint32_t mask = (1u << bits) - 1u;
-    uint32_t k[ITEMS], v[ITEMS];
+    uint32_t k[ITEMS], v[NV][ITEMS];
     uint16_t rank[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
         const int64_t j = item_index<ITEMS>(base, w, i, lane);
         k[i] = j < n ? kin[j] : 0u;
-        v[i] = j < n ? vin[j] : 0u;
+#pragma unroll
+        for (int c = 0; c < NV; c++) v[c][i] = j < n ? va.in[c][j] : 0u;
     }
     for (int q = 0; q < kWaves; q++) s_h[q][tid] = 0;
     s_glob[tid] = tid <= (int)mask ? hist[(int64_t)tid * nblocks + blockIdx.x] : 0u;
@@ -217,7 +225,8 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
             const uint32_t d = (k[i] >> shift) & mask;
             const uint32_t pos = s_start[d] + s_h[w][d] + rank[i];
             s_key[pos] = k[i];
-            s_val[pos] = v[i];
+#pragma unroll
+            for (int c = 0; c < NV; c++) s_val[c][pos] = v[c][i];
         }
     }
     __syncthreads();
@@ -230,7 +239,8 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
             const uint32_t d = (key >> shift) & mask;
             const uint32_t g = s_glob[d] + (j - s_start[d]);
             kout[g] = key;
-            vout[g] = s_val[j];
+#pragma unroll
+            for (int c = 0; c < NV; c++) va.out[c][g] = s_val[c][j];
         }
     }
 }
@@ -255,18 +265,51 @@ size_t radix_hist_words(int64_t max_n) { return (size_t)256 * ((max_n + kTile - 
 namespace {
 
 // one pass over `bits` bits at `shift`; blocks of 256 x ITEMS items
-template <int ITEMS>
-hipError_t radix_pass(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, uint32_t* vo,
-                      int64_t max_n, const uint32_t* d_n, int shift, int bits, uint32_t* hist,
+template <int ITEMS, int NV>
+hipError_t radix_pass(const uint32_t* ki, uint32_t* ko, const ValArrays<NV>& va, int64_t max_n,
+                      const uint32_t* d_n, int shift, int bits, uint32_t* hist,
                       uint32_t* scan_scratch, hipStream_t st) {
     const uint32_t nb = (uint32_t)((max_n + kThreads * ITEMS - 1) / (kThreads * ITEMS));
     hipLaunchKernelGGL(k_radix_hist<ITEMS>, dim3(nb), dim3(kThreads), 0, st, ki, d_n, max_n, shift,
                        bits, hist, nb);
     hipError_t e = exclusive_scan_u32(hist, ((int64_t)1 << bits) * nb, nullptr, scan_scratch, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_radix_scatter<ITEMS>, dim3(nb), dim3(kThreads), 0, st, ki, vi, ko, vo, d_n,
-                       max_n, shift, bits, hist, nb);
+    hipLaunchKernelGGL((k_radix_scatter<ITEMS, NV>), dim3(nb), dim3(kThreads), 0, st, ki, ko, va,
+                       d_n, max_n, shift, bits, hist, nb);
     return hipGetLastError();
+}
+
+// LSD passes of equal digit widths (at most 8 bits) over [lo, hi); K[2] and
+// V[c][2] are the ping-pong buffers; returns the side holding the result
+template <int NV>
+int radix_sort_impl(uint32_t* K[2], uint32_t* V[NV][2], int64_t max_n, const uint32_t* d_n, int lo,
+                    int hi, uint32_t* hist, uint32_t* scan_scratch, hipStream_t st, hipError_t* err) {
+    *err = hipSuccess;
+    if (max_n <= 0 || hi <= lo) return 0;
+    const int total = hi - lo;
+    const int passes = (total + 7) / 8;
+    int cur = 0;
+    int shift = lo;
+    for (int p = 0; p < passes; p++) {
+        const int bits = (total - (shift - lo) + (passes - p) - 1) / (passes - p);
+        ValArrays<NV> va;
+        for (int c = 0; c < NV; c++) {
+            va.in[c] = V[c][cur];
+            va.out[c] = V[c][cur ^ 1];
+        }
+        // large single-value inputs: 8192 items per block (longer runs per
+        // digit in the scatter); wider payloads keep 4096 for the LDS staging
+        if (NV == 1 && max_n > ((int64_t)1 << 22))
+            *err = radix_pass<32, NV>(K[cur], K[cur ^ 1], va, max_n, d_n, shift, bits, hist,
+                                      scan_scratch, st);
+        else
+            *err = radix_pass<16, NV>(K[cur], K[cur ^ 1], va, max_n, d_n, shift, bits, hist,
+                                      scan_scratch, st);
+        if (*err != hipSuccess) return cur;
+        shift += bits;
+        cur ^= 1;
+    }
+    return cur;
 }
 
 }  // namespace
@@ -274,28 +317,14 @@ hipError_t radix_pass(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, uint
 int radix_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_t max_n,
                      const uint32_t* d_n, int lo, int hi, uint32_t* hist, uint32_t* scan_scratch,
                      hipStream_t st, hipError_t* err) {
-    *err = hipSuccess;
-    if (max_n <= 0 || hi <= lo) return 0;
-    // equal digit widths of at most 8 bits
-    const int total = hi - lo;
-    const int passes = (total + 7) / 8;
-    int cur = 0;
     uint32_t* K[2] = {ka, kb};
-    uint32_t* Vv[2] = {va, vb};
-    int shift = lo;
-    for (int p = 0; p < passes; p++) {
-        const int bits = (total - (shift - lo) + (passes - p) - 1) / (passes - p);
-        // large inputs: 8192 items per block (longer runs per digit in the scatter)
-        *err = max_n > ((int64_t)1 << 22)
-                   ? radix_pass<32>(K[cur], Vv[cur], K[cur ^ 1], Vv[cur ^ 1], max_n, d_n, shift,
-                                    bits, hist, scan_scratch, st)
-                   : radix_pass<16>(K[cur], Vv[cur], K[cur ^ 1], Vv[cur ^ 1], max_n, d_n, shift,
-                                    bits, hist, scan_scratch, st);
-        if (*err != hipSuccess) return cur;
-        shift += bits;
-        cur ^= 1;
-    }
-    return cur;
+    uint32_t* V[1][2] = {{va, vb}};
+    return radix_sort_impl<1>(K, V, max_n, d_n, lo, hi, hist, scan_scratch, st, err);
+}
+
+int radix_sort_kv3(uint32_t* K[2], uint32_t* V[3][2], int64_t max_n, const uint32_t* d_n, int lo,
+                   int hi, uint32_t* hist, uint32_t* scan_scratch, hipStream_t st, hipError_t* err) {
+    return radix_sort_impl<3>(K, V, max_n, d_n, lo, hi, hist, scan_scratch, st, err);
 }
 
 }  // namespace gs
