@@ -83,7 +83,7 @@ typedef enum {
 } gs_status;
 
 /* Device status flags (gs_diag.flags). */
-#define GS_FLAG_ISECT_OVERFLOW 1u   /* block-list entries exceeded max_isect */
+#define GS_FLAG_ISECT_OVERFLOW 1u   /* tile-list entries exceeded max_isect */
 #define GS_FLAG_NONFINITE 2u        /* a non-finite projected splat was culled */
 
 /* Most views one render call takes. */
@@ -94,7 +94,7 @@ typedef struct gs_ctx gs_ctx;
 /* Workspace sizes, fixed at creation. */
 typedef struct {
     int64_t max_pairs;   /* views x Gaussians per gs_project call */
-    int64_t max_isect;   /* block-list entries (block, splat) per gs_bin_sort call */
+    int64_t max_isect;   /* tile-list entries (tile, splat) per gs_bin_sort call */
     int64_t max_tiles;   /* tiles summed over the views of one call */
     int32_t max_views;   /* views per call (<= GS_MAX_VIEWS) for twist accumulators */
     int32_t max_cams;    /* cameras of track_reproj_fwd_bwd (twist accumulators) */
@@ -115,6 +115,8 @@ typedef struct {
                                  list length, 16 buckets per octave (bucket of n > 0:
                                  1 + 16 floor(log2 n) + the 4 bits after n's leading
                                  bit; 0 for an empty list), any order inside a bucket */
+    int32_t eval_stats;       /* 0; 1: gs_render_fwd also counts each tile's (pixel,
+                                 splat) evaluations (gs_ctx_tile_stats), a slower variant */
 } gs_settings;
 
 typedef struct {
@@ -148,10 +150,10 @@ typedef struct {
 /* Diagnostics read by gs_ctx_status. */
 typedef struct {
     uint32_t flags;          /* GS_FLAG_* */
-    int64_t n_isect;         /* block-list entries of the last gs_bin_sort */
+    int64_t n_isect;         /* tile-list entries of the last gs_bin_sort */
     int64_t n_isect_needed;  /* entries that call needed (> max_isect on overflow) */
     int64_t n_masked_obs;    /* observations masked (behind the camera) since reset */
-    int64_t n_visible;       /* pairs listed in at least one block in the last gs_bin_sort */
+    int64_t n_visible;       /* pairs listed in at least one tile in the last gs_bin_sort */
 } gs_diag;
 
 /* A per-step record of the projected splat of each pair, 12 floats (48 B,
@@ -171,22 +173,21 @@ const char* gs_strerror(gs_status s);
 void gs_default_settings(gs_settings* s);
 
 /* Create a context: allocates the whole workspace once (device memory of about
- * 48+36+24 B per pair + 32 B per block-list entry + 32 B per tile).  *out is
- * NULL on failure. */
+ * 48+36+24 B per pair + 36 B per list entry + 40 B per tile).  *out is NULL
+ * on failure. */
 gs_status gs_ctx_create(gs_ctx** out, const gs_capacity* cap);
 gs_status gs_ctx_destroy(gs_ctx* ctx);
 /* Synchronise the device and read the status word. */
 gs_status gs_ctx_status(gs_ctx* ctx, gs_diag* out);
 /* Clear the status flags and counters (enqueued on stream). */
 gs_status gs_ctx_reset_status(gs_ctx* ctx, void* stream);
-/* Device pointers into the workspace, in the list layout gs_bin_sort
- * describes, valid until the next gs_bin_sort: records [max_pairs][12], the
- * block lists as pair indices list_pairs [max_isect] int32 and quadrant masks
- * list_masks [2][max_isect] uint32 (low 32 bits of every mask, then the high
- * 32 bits), block ranges [n_blocks][2] (start, end) int32, and the block count
- * of the last gs_bin_sort (HOST value). */
-gs_status gs_ctx_buffers(gs_ctx* ctx, float** records, int32_t** list_pairs,
-                         uint32_t** list_masks, int32_t** block_ranges, int64_t* n_blocks);
+/* Device pointers into the workspace (valid for the context's lifetime):
+ * records [max_pairs][12], the tile lists [max_isect] (pair index in the low
+ * 28 bits, the 4-bit quadrant mask in the top 4), tile ranges [max_tiles][2]
+ * (start, end) int32, and the tile count of the last gs_bin_sort (HOST
+ * value). */
+gs_status gs_ctx_buffers(gs_ctx* ctx, float** records, int32_t** isect_ids,
+                         int32_t** tile_ranges, int64_t* n_tiles);
 
 /* Workload statistics of the last gs_render_fwd (device pointers, valid for
  * the context's lifetime): tile_contrib[t] = number of (pixel, splat) pairs
@@ -194,10 +195,11 @@ gs_status gs_ctx_buffers(gs_ctx* ctx, float** records, int32_t** list_pairs,
  * forward read (up to the batch in which its last pixel stopped);
  * tile_evals[t] = sum over tile t's pixels of the entries of its list, up to
  * the pixel's last contributor, whose mask covers the pixel's quadrant (the
- * (pixel, splat) evaluations the definition makes, forward or backward);
+ * (pixel, splat) evaluations the definition makes, forward or backward; only
+ * written by a forward with settings eval_stats = 1);
  * tile_order = launch order of the tiles when the last gs_bin_sort ran with
  * tile_order = 1 (*ordered = 1), heaviest first as gs_settings.tile_order
- * describes, weighing each tile by its block's list length; n_tiles = tiles of
+ * describes; n_tiles = tiles of
  * the last gs_bin_sort (HOST value). */
 gs_status gs_ctx_tile_stats(gs_ctx* ctx, const int32_t** tile_contrib,
                             const int32_t** tile_entries, const int32_t** tile_evals,
@@ -215,24 +217,21 @@ gs_status gs_project(gs_ctx* ctx, const gs_gaussians* g, const gs_cameras* cams,
  * (tile_w x tile_h) has four quadrants (tile_w/2 x tile_h/2); a splat meets a
  * quadrant when its alpha >= alpha_min ellipse meets the rectangle of the
  * quadrant's pixel centres.  Tile t's list holds every pair meeting one of its
- * quadrants, in ascending (float32 depth, pair) order, each with the 4-bit mask
- * of the quadrants met (bit qx + 2 qy).  Tiles of view v are numbered after
- * those of views < v, row-major inside a view.
- * Layout: the lists are stored per block of 4 x 4 tiles (blocks numbered like
- * tiles, ceil(gx/4) per row); a block list holds every pair meeting one of the
- * block's 8 x 8 quadrants, in the same order, with a 64-bit mask (bit 8 qr + qc
- * for quadrant row qr, column qc inside the block).  Tile (sx, sy) of a block
- * (sx, sy in 0..3) takes the entries whose mask has a bit among 16 sy + 2 sx
- * + {0, 1, 8, 9}: those bits in that order are its 4-bit mask.
- * `records` = NULL uses the context's records (from gs_project); otherwise a
- * caller array of V*N records in the layout above.  Overflow of max_isect sets
- * GS_FLAG_ISECT_OVERFLOW. */
+ * quadrants, in ascending (float32 depth, pair) order, each entry the pair
+ * index with the 4-bit mask of the quadrants met (bit qx + 2 qy) in its top 4
+ * bits; tile ranges index the lists.  Tiles of view v are numbered after those
+ * of views < v, row-major inside a view.  `records` = NULL uses the context's
+ * records (from gs_project); otherwise a caller array of V*N records in the
+ * layout above.  max_isect bounds the total list length; overflow sets
+ * GS_FLAG_ISECT_OVERFLOW, leaves every list empty, and n_isect_needed reports
+ * the need (or, when even the 4x4-tile blocks the lists are built from
+ * overflowed, a lower bound of it). */
 gs_status gs_bin_sort(gs_ctx* ctx, const gs_cameras* cams, int32_t N,
                       const gs_settings* s, const float* records, void* stream);
 
 /* Forward compositing over the tile lists of the last gs_bin_sort.
  * bg[3] (device, may be NULL = black).  Outputs rgb[P][3], T_final[P] and
- * last[P] = 1 + position, within its block's list, of the pixel's final
+ * last[P] = 1 + position, within its tile's list, of the pixel's final
  * contributor (0 if none); P = sum_v W_v H_v.  T_final and last are what the
  * backward needs (it recomputes the blending state per pixel instead of
  * storing it). */

@@ -38,7 +38,8 @@ class gs_settings(ctypes.Structure):
                 ("near_plane", ctypes.c_float), ("eps2d", ctypes.c_float),
                 ("fov_pad", ctypes.c_float), ("alpha_min", ctypes.c_float),
                 ("alpha_max", ctypes.c_float), ("t_min", ctypes.c_float),
-                ("grad_accumulate", ctypes.c_int32), ("tile_order", ctypes.c_int32)]
+                ("grad_accumulate", ctypes.c_int32), ("tile_order", ctypes.c_int32),
+                ("eval_stats", ctypes.c_int32)]
 
 
 class gs_gaussians(ctypes.Structure):
@@ -104,8 +105,7 @@ def load():
     lib.gs_ctx_status.argtypes = [c_vp, ctypes.POINTER(gs_diag)]
     lib.gs_ctx_reset_status.argtypes = [c_vp, c_vp]
     lib.gs_ctx_buffers.argtypes = [c_vp, ctypes.POINTER(c_vp), ctypes.POINTER(c_vp),
-                                   ctypes.POINTER(c_vp), ctypes.POINTER(c_vp),
-                                   ctypes.POINTER(ctypes.c_int64)]
+                                   ctypes.POINTER(c_vp), ctypes.POINTER(ctypes.c_int64)]
     lib.gs_ctx_tile_stats.argtypes = [c_vp, ctypes.POINTER(c_vp), ctypes.POINTER(c_vp),
                                       ctypes.POINTER(c_vp), ctypes.POINTER(c_vp),
                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]
@@ -266,15 +266,15 @@ class Context:
         _check("gs_ctx_reset_status", load().gs_ctx_reset_status(self.handle, _stream(stream)))
 
     def buffers(self):
-        """Device addresses of the records and the block lists (pairs, masks,
-        ranges) and the block count of the last gs_bin_sort."""
-        rec, pairs, masks, rng = c_vp(), c_vp(), c_vp(), c_vp()
-        nb = ctypes.c_int64()
+        """Device addresses of the records, the tile lists and their ranges, and
+        the tile count of the last gs_bin_sort."""
+        rec, ids, rng = c_vp(), c_vp(), c_vp()
+        nt = ctypes.c_int64()
         _check("gs_ctx_buffers", load().gs_ctx_buffers(self.handle, ctypes.byref(rec),
-                                                       ctypes.byref(pairs), ctypes.byref(masks),
-                                                       ctypes.byref(rng), ctypes.byref(nb)))
-        return dict(records=rec.value, list_pairs=pairs.value, list_masks=masks.value,
-                    block_ranges=rng.value, n_blocks=nb.value)
+                                                       ctypes.byref(ids), ctypes.byref(rng),
+                                                       ctypes.byref(nt)))
+        return dict(records=rec.value, isect_ids=ids.value, tile_ranges=rng.value,
+                    n_tiles=nt.value)
 
 
 def gs_ctx_tile_stats(ctx):
@@ -362,48 +362,3 @@ def gs_adam_step(groups, step, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):
         arr[i] = gs_adam_group(_ptr(p), _ptr(g), _ptr(m), _ptr(v), int(p.numel()), float(lr))
     _check("gs_adam_step", load().gs_adam_step(arr, len(groups), int(step), float(beta1),
                                                float(beta2), float(eps), _stream(stream)))
-
-
-def list_masks(ctx, n):
-    """The first n block-list masks of the last gs_bin_sort as uint64."""
-    import numpy as np
-    cap = ctx.cap.max_isect
-    b = ctx.buffers()
-    lo = copy_to_host(b["list_masks"], n, np.uint32).astype(np.uint64)
-    hi = copy_to_host(b["list_masks"] + 4 * cap, n, np.uint32).astype(np.uint64)
-    return lo | (hi << np.uint64(32))
-
-
-def tile_lists(ctx, wh, tile_w=16, tile_h=16):
-    """The per-tile lists of the last gs_bin_sort, read back and expanded from
-    the block lists: (ranges [T][2], pair indices, 4-bit quadrant masks), tiles
-    numbered as gs_bin_sort numbers them."""
-    import numpy as np
-    b = ctx.buffers()
-    nb = b["n_blocks"]
-    br = copy_to_host(b["block_ranges"], 2 * nb, np.int32).reshape(nb, 2)
-    n = int(br[:, 1].max()) if nb else 0
-    pairs = copy_to_host(b["list_pairs"], n, np.int32).view(np.uint32).astype(np.int64)
-    masks = list_masks(ctx, n)
-    ranges, ids, qm = [], [], []
-    pos = 0
-    boff = 0
-    for W, H in np.asarray(wh).reshape(-1, 2):
-        gx, gy = -(-int(W) // tile_w), -(-int(H) // tile_h)
-        bx = -(-gx // 4)
-        for ty in range(gy):
-            for tx in range(gx):
-                B = boff + (ty // 4) * bx + tx // 4
-                sx, sy = tx % 4, ty % 4
-                m = masks[br[B, 0]:br[B, 1]]
-                sh = np.uint64(16 * sy + 2 * sx)
-                m4 = ((m >> sh) & np.uint64(3)) | (((m >> (sh + np.uint64(8))) & np.uint64(3)) << np.uint64(2))
-                keep = m4 != 0
-                ids.append(pairs[br[B, 0]:br[B, 1]][keep])
-                qm.append(m4[keep].astype(np.int64))
-                ranges.append((pos, pos + int(keep.sum())))
-                pos += int(keep.sum())
-        boff += bx * (-(-gy // 4))
-    return (np.array(ranges, np.int64).reshape(-1, 2),
-            np.concatenate(ids) if ids else np.zeros(0, np.int64),
-            np.concatenate(qm) if qm else np.zeros(0, np.int64))

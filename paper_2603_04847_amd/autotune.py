@@ -26,7 +26,7 @@ def autotune(step, shapes=TILE_SHAPES, orders=(0, 1), iters=3, batch=0, big=None
     """Time each (tile shape, order) on `step` (a JointStep) and leave the
     fastest in step.settings with a tight capacity.  Returns the timings."""
     P = step.cams[batch].n_pixels
-    big = big or min(2**30, 64 * P)
+    big = big or min(2**30 - 65536, 64 * P)
     results = []
     for tw, th in shapes:
         step.settings = L.default_settings(tile_w=tw, tile_h=th)

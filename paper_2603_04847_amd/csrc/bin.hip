@@ -13,10 +13,13 @@
 //  4. stable radix sort of the entries on the block id only: inside every block
 //     the depth order of step 2 survives, so each block list ends up in
 //     ascending (depth, pair) order without sorting on depth again.
-//  5. block ranges from the boundaries of the sorted block ids, and the lists
-//     (pair, mask) gathered into that order.
-// A tile's list, the definition, is its block's list restricted to entries
-// whose mask meets one of the tile's four quadrants.
+//  5. block ranges from the boundaries of the sorted block ids.
+//  6. expand to tile lists, the definition: a tile's list is its block's list
+//     restricted to the entries whose mask meets one of the tile's four
+//     quadrants.  One workgroup per block counts its 16 tiles' entries, a scan
+//     places the lists, and a second pass writes (pair | 4-bit mask << 28) in
+//     block-list order.  Sorting (block, pair) entries instead of (tile, pair)
+//     ones moves about a quarter of the data through the radix passes.
 #include <algorithm>
 
 #include "gs_internal.h"
@@ -138,12 +141,19 @@ __global__ __launch_bounds__(kBlock) void k_gather_cnt(const uint32_t* __restric
     if (vis && !next_vis) diag[kDiagVisible] = (uint32_t)(r + 1);
 }
 
+// Capacity check of a list total.  `prev_over` (may be NULL) is the check of
+// an earlier stage: once that overflowed, the counts it reported stay (they
+// are a lower bound of the need) and this stage writes nothing.
 __global__ void k_isect_total(const uint32_t* __restrict__ total, int64_t cap,
-                              uint32_t* __restrict__ used, uint32_t* __restrict__ diag) {
+                              uint32_t* __restrict__ used, uint32_t* __restrict__ diag,
+                              const uint32_t* __restrict__ prev_total,
+                              const uint32_t* __restrict__ prev_used) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         const uint32_t t = *total;
-        const bool over = (int64_t)t > cap;
+        const bool prev_over = prev_total && *prev_total != 0u && *prev_used == 0u;
+        const bool over = prev_over || (int64_t)t > cap;
         *used = over ? 0u : t;
+        if (prev_over) return;
         diag[kDiagIsectTotal] = t;
         diag[kDiagIsectUsed] = over ? 0u : t;
         if (over) atomicOr(&diag[kDiagFlags], (uint32_t)GS_FLAG_ISECT_OVERFLOW);
@@ -271,15 +281,182 @@ __global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t* __restrict__ 
     }
 }
 
-// block of tile t, and the tile's place (sx, sy) in it
-__device__ __forceinline__ int tile_block(const ViewTable& vt, int t, int& sx, int& sy) {
+// Block B's place: view, and block column / row in it.
+__device__ __forceinline__ void block_place(const ViewTable& vt, int B, int& v, int& bxi, int& byi) {
+    v = 0;
+    while (v + 1 < vt.V && B >= vt.block_off[v + 1]) v++;
+    const int lb = B - vt.block_off[v];
+    bxi = lb % vt.bx[v];
+    byi = lb / vt.bx[v];
+}
+
+constexpr int kBlockSub = kBlockTiles * kBlockTiles;  // tiles per block (sub-tile q = 4 sy + sx)
+constexpr int kChunk = 256;                           // block-list entries per expansion workgroup
+constexpr int kChunkWaves = kChunk / kWave;
+
+// The tile lists come out of the sorted block lists through 16 prefix counts:
+// P_q(j) = entries before position j whose mask touches sub-tile q of their own
+// block.  Entry j of block B lands in the list of B's sub-tile q (if it touches
+// it) at P_q(j) - P_q(start of B); that list has P_q(end of B) - P_q(start of
+// B) entries.  P_q is kept per 256-entry chunk (a scan of the chunk counts) and
+// finished inside a chunk with ballots.
+
+// touch bits of sub-tile q of a block mask
+__device__ __forceinline__ bool touches(uint64_t m, int q) {
+    return tile_bits(m, q % kBlockTiles, q / kBlockTiles) != 0;
+}
+
+// Per chunk and sub-tile: entries touching it.  ccnt is [16][nchunks] (column q
+// contiguous).
+__global__ __launch_bounds__(kChunk) void k_chunk_count(const uint32_t* __restrict__ mlo,
+                                                        const uint32_t* __restrict__ mhi,
+                                                        const uint32_t* __restrict__ used,
+                                                        int64_t nchunks, uint32_t* __restrict__ ccnt) {
+    __shared__ uint32_t s_wn[kChunkWaves][kBlockSub];
+    const int64_t n = *used;
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    // chunks past the entries keep stale counts: every prefix that is used is a
+    // difference inside one column, where such constants cancel (mod 2^32)
+    for (int64_t c = blockIdx.x; c * kChunk < n; c += gridDim.x) {
+        const int64_t j = c * kChunk + threadIdx.x;
+        uint64_t m = 0;
+        if (j < n) m = ((uint64_t)mhi[j] << 32) | mlo[j];
+#pragma unroll
+        for (int q = 0; q < kBlockSub; q++) {
+            const uint64_t b = __ballot(touches(m, q));
+            if (lane == q) s_wn[w][q] = (uint32_t)__popcll(b);
+        }
+        __syncthreads();
+        if (threadIdx.x < kBlockSub) {
+            uint32_t cn = 0;
+            for (int u = 0; u < kChunkWaves; u++) cn += s_wn[u][threadIdx.x];
+            ccnt[(int64_t)threadIdx.x * nchunks + c] = cn;
+        }
+        __syncthreads();
+    }
+}
+
+// P_q at list position x (x <= used): the chunk prefix plus the entries of x's
+// chunk before x, counted by one wave.  Returns the value for q = lane (lanes < 16).
+__device__ __forceinline__ uint32_t prefix_at(const uint32_t* __restrict__ mlo,
+                                              const uint32_t* __restrict__ mhi,
+                                              const uint32_t* __restrict__ cpre, int64_t nchunks,
+                                              int64_t x) {
+    const int lane = __lane_id();
+    const int64_t c = x / kChunk, c0 = c * kChunk;
+    uint32_t part = 0;
+    for (int64_t j0 = c0; j0 < x; j0 += kWave) {
+        const int64_t j = j0 + lane;
+        uint64_t m = 0;
+        if (j < x) m = ((uint64_t)mhi[j] << 32) | mlo[j];
+#pragma unroll
+        for (int q = 0; q < kBlockSub; q++) {
+            const uint32_t n = (uint32_t)__popcll(__ballot(touches(m, q)));
+            if (lane == q) part += n;
+        }
+    }
+    return lane < kBlockSub ? cpre[(int64_t)lane * nchunks + c] + part : 0u;
+}
+
+// Per block (one wave): the prefixes at its list's start, its sub-tiles' list
+// lengths, and where its tiles are (first tile, row stride, tiles per side).
+__global__ __launch_bounds__(kWave) void k_block_tiles(const int32_t* __restrict__ branges,
+                                                       const uint32_t* __restrict__ mlo,
+                                                       const uint32_t* __restrict__ mhi,
+                                                       const uint32_t* __restrict__ cpre,
+                                                       int64_t nchunks, ViewTable vt, int TH,
+                                                       uint32_t* __restrict__ bpre,
+                                                       int4* __restrict__ bplace,
+                                                       uint32_t* __restrict__ tcnt) {
+    const int B = blockIdx.x, lane = threadIdx.x;
+    int v, bxi, byi;
+    block_place(vt, B, v, bxi, byi);
+    const int gy = (vt.H[v] + TH - 1) / TH;
+    const int nx = min(kBlockTiles, vt.gx[v] - kBlockTiles * bxi);
+    const int ny = min(kBlockTiles, gy - kBlockTiles * byi);
+    const int tile0 = vt.tile_off[v] + kBlockTiles * byi * vt.gx[v] + kBlockTiles * bxi;
+    if (lane == 0) bplace[B] = make_int4(tile0, vt.gx[v], nx, ny);
+    const int rs = branges[2 * B], re = branges[2 * B + 1];
+    uint32_t ps = 0, pe = 0;
+    if (rs < re) {
+        ps = prefix_at(mlo, mhi, cpre, nchunks, rs);
+        pe = prefix_at(mlo, mhi, cpre, nchunks, re);
+    }
+    if (lane < kBlockSub) {
+        bpre[(int64_t)B * kBlockSub + lane] = ps;
+        const int sx = lane % kBlockTiles, sy = lane / kBlockTiles;
+        if (sx < nx && sy < ny) tcnt[tile0 + sy * vt.gx[v] + sx] = pe - ps;
+    }
+}
+
+// Tile ranges from the scanned counts (empty everywhere after an overflow),
+// and for each (block, sub-tile) the base that turns a prefix P_q(j) into the
+// entry's slot: tile start - P_q(start of the block).
+__global__ __launch_bounds__(kBlock) void k_tile_ranges(const uint32_t* __restrict__ toff,
+                                                        const uint32_t* __restrict__ total,
+                                                        const uint32_t* __restrict__ used,
+                                                        ViewTable vt, int TH, int64_t T,
+                                                        const uint32_t* __restrict__ bpre,
+                                                        int32_t* __restrict__ tranges,
+                                                        uint32_t* __restrict__ tbase) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= T) return;
+    const bool ok = *used != 0u || *total == 0u;
+    tranges[2 * t] = ok ? (int32_t)toff[t] : 0;
+    tranges[2 * t + 1] = ok ? (int32_t)(t + 1 < T ? toff[t + 1] : *total) : 0;
     int v = 0;
     while (v + 1 < vt.V && t >= vt.tile_off[v + 1]) v++;
-    const int lt = t - vt.tile_off[v];
+    const int lt = (int)t - vt.tile_off[v];
     const int tx = lt % vt.gx[v], ty = lt / vt.gx[v];
-    sx = tx % kBlockTiles;
-    sy = ty % kBlockTiles;
-    return vt.block_off[v] + (ty / kBlockTiles) * vt.bx[v] + tx / kBlockTiles;
+    const int64_t B = vt.block_off[v] + (ty / kBlockTiles) * vt.bx[v] + tx / kBlockTiles;
+    const int q = (ty % kBlockTiles) * kBlockTiles + tx % kBlockTiles;
+    tbase[B * kBlockSub + q] = toff[t] - bpre[B * kBlockSub + q];
+    (void)TH;
+}
+
+// The tile lists: each block-list entry copied, as (pair | 4-bit mask << 28), to
+// every sub-tile of its block it touches, at the place the prefixes give.
+__global__ __launch_bounds__(kChunk) void k_chunk_expand(
+    const uint32_t* __restrict__ bkey, const uint32_t* __restrict__ pairs,
+    const uint32_t* __restrict__ mlo, const uint32_t* __restrict__ mhi,
+    const uint32_t* __restrict__ used, const uint32_t* __restrict__ tused, int64_t nchunks,
+    const uint32_t* __restrict__ cpre, const uint32_t* __restrict__ tbase, uint32_t NB,
+    uint32_t* __restrict__ tids) {
+    __shared__ uint32_t s_wn[kChunkWaves][kBlockSub];
+    if (*tused == 0u) return;  // nothing is written after an overflow
+    const int64_t n = *used;
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const uint64_t lt = lanemask_lt();
+    for (int64_t c = blockIdx.x; c * kChunk < n; c += gridDim.x) {
+        const int64_t j = c * kChunk + threadIdx.x;
+        uint64_t m = 0;
+        uint32_t B = NB;  // sentinel entries (unfilled slots) have B = NB and no mask
+        uint32_t pr = 0;
+        if (j < n) {
+            m = ((uint64_t)mhi[j] << 32) | mlo[j];
+            B = bkey[j];
+            pr = pairs[j];
+        }
+        if (B >= NB) m = 0;
+        uint64_t bal[kBlockSub];
+#pragma unroll
+        for (int q = 0; q < kBlockSub; q++) {
+            bal[q] = __ballot(touches(m, q));
+            if (lane == q) s_wn[w][q] = (uint32_t)__popcll(bal[q]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kBlockSub; q++) {
+            if (bal[q] == 0) continue;  // wave-uniform
+            const uint32_t m4 = tile_bits(m, q % kBlockTiles, q / kBlockTiles);
+            if (!m4) continue;
+            uint32_t rank = (uint32_t)__popcll(bal[q] & lt);
+            for (int u = 0; u < w; u++) rank += s_wn[u][q];
+            const uint32_t pos = tbase[(int64_t)B * kBlockSub + q] + cpre[(int64_t)q * nchunks + c] + rank;
+            tids[pos] = pr | (m4 << kPairBits);
+        }
+        __syncthreads();
+    }
 }
 
 // Launch order of the tiles, heaviest first.  The weight is a log-scale bucket
@@ -295,15 +472,12 @@ __device__ __forceinline__ uint32_t length_bucket(uint32_t len) {
 constexpr int kOrderBuckets = 513;
 constexpr int kOrderThreads = 1024;
 
-// Bucket of each tile's weight (its block's list length).
-__global__ __launch_bounds__(kBlock) void k_tile_bucket(const int32_t* __restrict__ ranges,
-                                                        ViewTable vt, int64_t T,
-                                                        uint32_t* __restrict__ bucket) {
+// Bucket of each tile's weight (its list length).
+__global__ __launch_bounds__(kBlock) void k_tile_bucket(const int32_t* __restrict__ tranges,
+                                                        int64_t T, uint32_t* __restrict__ bucket) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t >= T) return;
-    int sx, sy;
-    const int B = tile_block(vt, (int)t, sx, sy);
-    bucket[t] = length_bucket((uint32_t)max(ranges[2 * B + 1] - ranges[2 * B], 0));
+    bucket[t] = length_bucket((uint32_t)max(tranges[2 * t + 1] - tranges[2 * t], 0));
 }
 
 // One block: histogram of the buckets, their scan from the heaviest down, and
@@ -332,17 +506,14 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint32_t* __
     }
 }
 
-// Larger tile counts: key = 2^24 - 1 - min(block list length, 2^24 - 1) through
-// the stable radix sort (exact lengths, which also orders the buckets)
-__global__ __launch_bounds__(kBlock) void k_tile_keys(const int32_t* __restrict__ ranges,
-                                                      ViewTable vt, int64_t T,
+// Larger tile counts: key = 2^24 - 1 - min(list length, 2^24 - 1) through the
+// stable radix sort (exact lengths, which also orders the buckets)
+__global__ __launch_bounds__(kBlock) void k_tile_keys(const int32_t* __restrict__ tranges, int64_t T,
                                                       uint32_t* __restrict__ key,
                                                       uint32_t* __restrict__ val) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t >= T) return;
-    int sx, sy;
-    const int B = tile_block(vt, (int)t, sx, sy);
-    const uint32_t len = (uint32_t)max(ranges[2 * B + 1] - ranges[2 * B], 0);
+    const uint32_t len = (uint32_t)max(tranges[2 * t + 1] - tranges[2 * t], 0);
     key[t] = 0xFFFFFFu - min(len, 0xFFFFFFu);
     val[t] = (uint32_t)t;
 }
@@ -375,7 +546,7 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
         if ((e = exclusive_scan_u32(c->off, npairs, total, c->scan_scratch, st)) != hipSuccess)
             return e;
         hipLaunchKernelGGL(k_isect_total, dim3(1), dim3(64), 0, st, total, c->cap.max_isect, used,
-                           c->diag);
+                           c->diag, nullptr, nullptr);
         const int64_t I = c->cap.max_isect;
         hipLaunchKernelGGL(k_emit, dim3(gp), dim3(kBlock), 0, st, rec, N, vt, rp, order, c->off,
                            c->cnt, npairs, used, c->ik[0], c->iv[0], c->im[0], c->im[0] + I);
@@ -386,21 +557,47 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
         uint32_t* Vv[3][2] = {{c->iv[0], c->iv[1]}, {c->im[0], c->im[1]}, {c->im[0] + I, c->im[1] + I}};
         const int side2 = radix_sort_kv3(K, Vv, I, used, 0, bbits, c->hist, c->scan_scratch, st, &e);
         if (e != hipSuccess) return e;
-        c->lpair = c->iv[side2];
-        c->lmask_lo = c->im[side2];
-        c->lmask_hi = c->im[side2] + I;
+        const uint32_t* bpair = c->iv[side2];
+        const uint32_t* bmlo = c->im[side2];
+        const uint32_t* bmhi = c->im[side2] + I;
         const unsigned gi = (unsigned)std::min<int64_t>((I + kBlock - 1) / kBlock, 4096);
         hipLaunchKernelGGL(k_ranges, dim3(gi), dim3(kBlock), 0, st, c->ik[side2], used, c->ranges,
                            (uint32_t)NB);
+        // tile lists: chunk counts and their scan, per-block prefixes and tile
+        // list lengths, the tile scan and ranges, then the lists
+        if (T > 0) {
+            uint32_t* ttotal = c->scalars + 2;
+            uint32_t* tused = c->scalars + 3;
+            const int64_t nch = c->nchunks;
+            const unsigned gch = (unsigned)std::min<int64_t>(nch, 4096);
+            hipLaunchKernelGGL(k_chunk_count, dim3(gch), dim3(kChunk), 0, st, bmlo, bmhi, used, nch,
+                               c->ccnt);
+            if ((e = exclusive_scan_u32(c->ccnt, kBlockSub * nch, nullptr, c->scan_scratch, st)) != hipSuccess)
+                return e;
+            if ((e = launch_fill_u32(c->tcnt, 0u, T, st)) != hipSuccess) return e;
+            if (NB > 0)
+                hipLaunchKernelGGL(k_block_tiles, dim3((unsigned)NB), dim3(kWave), 0, st, c->ranges, bmlo,
+                                   bmhi, c->ccnt, nch, vt, rp.tile_h, c->bpre, c->bplace, c->tcnt);
+            if ((e = exclusive_scan_u32(c->tcnt, T, ttotal, c->scan_scratch, st)) != hipSuccess)
+                return e;
+            // the tile lists must fit too (their total replaces the block count)
+            hipLaunchKernelGGL(k_isect_total, dim3(1), dim3(64), 0, st, ttotal, c->cap.max_isect, tused,
+                               c->diag, total, used);
+            const unsigned gt = (unsigned)((T + kBlock - 1) / kBlock);
+            hipLaunchKernelGGL(k_tile_ranges, dim3(gt), dim3(kBlock), 0, st, c->tcnt, ttotal, tused, vt,
+                               rp.tile_h, T, c->bpre, c->tranges, c->tbase);
+            hipLaunchKernelGGL(k_chunk_expand, dim3(gch), dim3(kChunk), 0, st, c->ik[side2], bpair, bmlo,
+                               bmhi, used, tused, nch, c->ccnt, c->tbase, (uint32_t)NB, c->tids);
+        }
         if (tile_order && T > 0 && T <= ((int64_t)1 << 20)) {
             hipLaunchKernelGGL(k_tile_bucket, dim3((unsigned)((T + kBlock - 1) / kBlock)), dim3(kBlock),
-                               0, st, c->ranges, vt, T, c->tk[0]);
+                               0, st, c->tranges, T, c->tk[0]);
             hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, st, c->tk[0], T,
                                c->tile_order);
             c->ordered = true;
         } else if (tile_order && T > 0) {
             hipLaunchKernelGGL(k_tile_keys, dim3((unsigned)((T + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                               st, c->ranges, vt, T, c->tk[0], c->tile_order);
+                               st, c->tranges, T, c->tk[0], c->tile_order);
             // sort (key, tile) pairs: tile_order holds the values of the first buffer pair
             uint32_t* kk[2] = {c->tk[0], c->tk[1]};
             uint32_t* vv[2] = {c->tile_order, reinterpret_cast<uint32_t*>(c->tile_contrib)};
@@ -413,6 +610,10 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
             }
             c->ordered = true;
         }
+    } else if (T > 0) {
+        // no pairs: every tile list is empty
+        if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(c->tranges), 0u, 2 * T, st)) != hipSuccess)
+            return e;
     }
     c->n_tiles = T;
     c->n_blocks = NB;

@@ -49,6 +49,7 @@ RasterParams make_raster_params(const gs_settings* s) {
     rp.fov_pad = s->fov_pad;
     rp.tile_w = s->tile_w;
     rp.tile_h = s->tile_h;
+    rp.eval_stats = s->eval_stats;
     return rp;
 }
 
@@ -137,6 +138,7 @@ void gs_default_settings(gs_settings* s) {
     s->t_min = 1e-4f;
     s->grad_accumulate = 0;
     s->tile_order = 0;
+    s->eval_stats = 0;
 }
 
 gs_status gs_ctx_create(gs_ctx** out, const gs_capacity* cap) {
@@ -147,7 +149,7 @@ gs_status gs_ctx_create(gs_ctx** out, const gs_capacity* cap) {
         return GS_ERR_INVALID_ARG;
     // limits of the device scan (16384 blocks of 4096 items) and of the radix
     // histograms (256 digits per 4096-item block go through that scan)
-    if (cap->max_pairs > (int64_t)16384 * 4096 || cap->max_isect > ((int64_t)1 << 30) ||
+    if (cap->max_pairs > (int64_t)16384 * 4096 || cap->max_isect > ((int64_t)1 << 30) - 65536 ||
         cap->max_tiles > ((int64_t)1 << 24))
         return GS_ERR_CAPACITY;
     gs_ctx* h = (gs_ctx*)calloc(1, sizeof(gs_ctx));
@@ -174,6 +176,14 @@ gs_status gs_ctx_create(gs_ctx** out, const gs_capacity* cap) {
     A(dalloc(&c.im[0], (size_t)2 * I));
     A(dalloc(&c.im[1], (size_t)2 * I));
     A(dalloc(&c.ranges, (size_t)2 * T));
+    A(dalloc(&c.tcnt, (size_t)T));
+    c.nchunks = I / 256 + 1;
+    A(dalloc(&c.ccnt, (size_t)16 * c.nchunks));
+    A(dalloc(&c.bpre, (size_t)16 * T));
+    A(dalloc(&c.bplace, (size_t)T));
+    A(dalloc(&c.tbase, (size_t)16 * T));
+    A(dalloc(&c.tranges, (size_t)2 * T));
+    A(dalloc(&c.tids, (size_t)I));
     A(dalloc(&c.tile_order, (size_t)T));
     A(dalloc(&c.tk[0], (size_t)T));
     A(dalloc(&c.tk[1], (size_t)T));
@@ -197,9 +207,6 @@ gs_status gs_ctx_create(gs_ctx** out, const gs_capacity* cap) {
     if (e == hipSuccess) A(hipMemset(c.diag, 0, sizeof(uint32_t) * gs::kDiagCount));
     if (e == hipSuccess) A(hipMemset(c.scalars, 0, sizeof(uint32_t) * 16));
     if (e == hipSuccess) A(hipDeviceSynchronize());
-    c.lpair = c.iv[0];
-    c.lmask_lo = c.im[0];
-    c.lmask_hi = c.im[0] + I;
     if (e != hipSuccess) {
         gs_ctx_destroy(h);
         return GS_ERR_HIP;
@@ -212,7 +219,7 @@ gs_status gs_ctx_destroy(gs_ctx* h) {
     if (!h) return GS_ERR_INVALID_ARG;
     gs::Ctx& c = h->c;
     void* ptrs[] = {c.rec, c.grad2d, c.cnt, c.off, c.pk[0], c.pk[1], c.pv[0], c.pv[1],
-                    c.ik[0], c.ik[1], c.iv[0], c.iv[1], c.im[0], c.im[1],
+                    c.ik[0], c.ik[1], c.iv[0], c.iv[1], c.im[0], c.im[1], c.tcnt, c.ccnt, c.bpre, c.bplace, c.tbase, c.tranges, c.tids,
                     c.ranges, c.tile_order, c.tk[0], c.tk[1], c.tile_contrib, c.tile_entries, c.tile_evals, c.hist,
                     c.scan_scratch, c.scalars, c.twist_render, c.twist_track, c.loss_acc, c.diag};
     hipDeviceSynchronize();
@@ -240,14 +247,13 @@ gs_status gs_ctx_reset_status(gs_ctx* h, void* stream) {
     return from_hip(gs::launch_fill_u32(h->c.diag, 0u, gs::kDiagCount, (hipStream_t)stream));
 }
 
-gs_status gs_ctx_buffers(gs_ctx* h, float** records, int32_t** list_pairs, uint32_t** list_masks,
-                         int32_t** block_ranges, int64_t* n_blocks) {
+gs_status gs_ctx_buffers(gs_ctx* h, float** records, int32_t** isect_ids, int32_t** tile_ranges,
+                         int64_t* n_tiles) {
     if (!h) return GS_ERR_INVALID_ARG;
     if (records) *records = h->c.rec;
-    if (list_pairs) *list_pairs = reinterpret_cast<int32_t*>(const_cast<uint32_t*>(h->c.lpair));
-    if (list_masks) *list_masks = const_cast<uint32_t*>(h->c.lmask_lo);
-    if (block_ranges) *block_ranges = h->c.ranges;
-    if (n_blocks) *n_blocks = h->c.n_blocks;
+    if (isect_ids) *isect_ids = reinterpret_cast<int32_t*>(h->c.tids);
+    if (tile_ranges) *tile_ranges = h->c.tranges;
+    if (n_tiles) *n_tiles = h->c.n_tiles;
     return GS_OK;
 }
 

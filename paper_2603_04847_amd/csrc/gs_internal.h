@@ -28,6 +28,7 @@ struct RasterParams {
     float alpha_min, alpha_max, t_min;
     float near_plane, eps2d, fov_pad;
     int tile_w, tile_h;
+    int eval_stats;
 };
 
 // Device status words (one array in the context).
@@ -212,6 +213,11 @@ __device__ __forceinline__ void span_cols(const SplatSpan& s, int r, int W, int 
     c1 = min((int)floorf((xr - 0.5f) * g.ihw), ncols - 1);
 }
 
+// A tile-list entry carries the pair index in its low 28 bits and the
+// quadrant mask in the top 4.
+constexpr uint32_t kPairBits = 28;
+constexpr uint32_t kPairMask = (1u << kPairBits) - 1u;
+
 // Blocks: 4 x 4 tiles, i.e. 8 x 8 quadrants.  The lists are kept per block; an
 // entry is a splat (its pair index) with the 64-bit mask of the block's
 // quadrants it meets, bit 8 qr + qc for quadrant row qr and column qc inside
@@ -364,11 +370,15 @@ struct Ctx {
     uint32_t* ik[2];       // [max_isect] block keys (ping-pong)
     uint32_t* iv[2];       // [max_isect] pair indices (ping-pong)
     uint32_t* im[2];       // [2][max_isect] block masks, low then high words (ping-pong)
-    // the block lists of the last bin step (point into iv[] / im[])
-    const uint32_t* lpair;
-    const uint32_t* lmask_lo;
-    const uint32_t* lmask_hi;
     int32_t* ranges;       // [max_tiles][2] block list ranges (blocks <= tiles)
+    uint32_t* tcnt;        // [max_tiles] tile list lengths, then their scan
+    uint32_t* ccnt;        // [16][nchunks] sub-tile counts per 256-entry chunk, then their scan
+    int64_t nchunks;       // max_isect / 256 + 1
+    uint32_t* bpre;        // [max_tiles][16] sub-tile prefixes at each block's list start
+    int4* bplace;          // [max_tiles] first tile, row stride, tiles across / down per block
+    uint32_t* tbase;       // [max_tiles][16] tile start - prefix at the block start
+    int32_t* tranges;      // [max_tiles][2] tile list ranges
+    uint32_t* tids;        // [max_isect] tile lists: pair | quadrant mask << 28
     uint32_t* tile_order;  // [max_tiles] launch order of the tiles (heaviest first)
     uint32_t* tk[2];       // [max_tiles] sort scratch for the tile order
     int32_t* tile_contrib; // [max_tiles] contributing (pixel, splat) pairs per tile

@@ -1,17 +1,17 @@
-// Front-to-back compositing over the depth-sorted lists, its backward, and the
-// photometric L1 term.
+// Front-to-back compositing over the depth-sorted tile lists, its backward,
+// and the photometric L1 term.
 //
 // One wave (64 lanes) owns one tile of TW x TH pixels, PPL = TW*TH/64 pixels per
 // lane, laid out so that each of a lane's pixel slots stays in fixed tile
-// quadrants.  The lists are kept per block of 4 x 4 tiles with a 64-bit mask
-// of the quadrants each splat meets; a tile reads its block's list 64 entries
-// at a time, keeps the entries with a bit on its own quadrants (one ballot),
-// and each lane gathers one kept splat's record (40 B).  The wave then walks
-// the kept entries in list order with the splat's parameters broadcast by
-// readlane, i.e. held in scalar registers, so every pixel of the tile tests
-// each splat with no LDS traffic at all, and a slot whose quadrants the splat
-// misses is skipped by the whole wave.  The backward walks the same entries
-// back to front from each pixel's last contributor, recovering the
+// quadrants; every list entry carries the quadrants its splat reaches, and a
+// slot whose quadrants the splat misses is skipped by the whole wave.  The
+// tile's list is consumed in batches of 64: each lane loads one splat record
+// (a gather of 40 B) and the wave then walks the batch with the splat's
+// parameters broadcast by readlane, i.e. held in scalar registers, so every
+// pixel of the tile tests each splat with no LDS traffic at all.  The next
+// batch's list entries are requested right after the current records, so
+// their latency hides behind the compositing.  The backward walks the same
+// lists back to front from each pixel's last contributor, recovering the
 // transmittance by division, and sums each splat's nine 2D gradients over the
 // whole wave (DPP) before one lane per component issues the global atomic.
 #include <algorithm>
@@ -79,31 +79,18 @@ __device__ __forceinline__ LaneSplat load_splat(const float4* __restrict__ rec, 
     return {ra.x, ra.y, ra.w, q.a, q.b, q.c, rb.w, rc.x, rc.y, e2_cut(ra.w, amin)};
 }
 
-// The list of tile t: its block's range, and the tile's place in the block.
-struct TileList {
-    int v, tx, ty, sx, sy, s, e;
-};
-
-__device__ __forceinline__ TileList tile_list(const ViewTable& vt, const int32_t* __restrict__ ranges,
-                                              int t) {
-    TileList L;
-    L.v = tile_view(vt, t);
-    const int lt = t - vt.tile_off[L.v];
-    L.tx = lt % vt.gx[L.v];
-    L.ty = lt / vt.gx[L.v];
-    L.sx = L.tx % kBlockTiles;
-    L.sy = L.ty % kBlockTiles;
-    const int B = vt.block_off[L.v] + (L.ty / kBlockTiles) * vt.bx[L.v] + L.tx / kBlockTiles;
-    L.s = ranges[2 * B];
-    L.e = ranges[2 * B + 1];
-    return L;
+// One batch's list entries, loaded by every lane (index clamped into the
+// list, which is not empty) and zeroed outside [s, e): the load stays
+// unconditional, so the compiler's wait bookkeeping sees it on every path.
+__device__ __forceinline__ uint32_t batch_ids(const int32_t* __restrict__ ids, int b, int s, int e) {
+    const int j = b + (int)threadIdx.x;
+    const uint32_t id = (uint32_t)ids[min(max(j, s), e - 1)];
+    return (j >= s && j < e) ? id : 0u;
 }
 
-template <int TW, int TH>
+template <int TW, int TH, bool EVALS>
 __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ rec,
-                                                   const uint32_t* __restrict__ lpair,
-                                                   const uint32_t* __restrict__ lmlo,
-                                                   const uint32_t* __restrict__ lmhi,
+                                                   const int32_t* __restrict__ ids,
                                                    const int32_t* __restrict__ ranges,
                                                    const uint32_t* __restrict__ order, ViewTable vt,
                                                    RasterParams rp, const float* __restrict__ bg,
@@ -116,12 +103,11 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
     using TM = TileMap<TW, TH>;
     constexpr int PPL = TM::PPL;
     const int t = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
-    const TileList tl = tile_list(vt, ranges, t);
-    const int v = tl.v;
-    const int W = vt.W[v], H = vt.H[v];
-    const int tx = tl.tx, ty = tl.ty;
+    const int v = tile_view(vt, t);
+    const int lt = t - vt.tile_off[v];
+    const int gx = vt.gx[v], W = vt.W[v], H = vt.H[v];
+    const int tx = lt % gx, ty = lt / gx;
     const int lane = threadIdx.x;
-    int px[PPL], py[PPL];
     float fx[PPL], fy[PPL], T[PPL], C0[PPL], C1[PPL], C2[PPL];
     int last[PPL];
     // per slot: entries met so far whose mask covers the slot's quadrants (the
@@ -132,37 +118,32 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
     for (int k = 0; k < PPL; k++) {
         int x, y;
         TM::pixel(lane, k, x, y);
-        px[k] = tx * TW + x;
-        py[k] = ty * TH + y;
-        fx[k] = px[k] + 0.5f;
-        fy[k] = py[k] + 0.5f;
-        done[k] = !(px[k] < W && py[k] < H);
+        const int px = tx * TW + x, py = ty * TH + y;
+        fx[k] = px + 0.5f;
+        fy[k] = py + 0.5f;
+        done[k] = !(px < W && py < H);
         T[k] = 1.f;
         C0[k] = C1[k] = C2[k] = 0.f;
         last[k] = 0;
         qn[k] = lastq[k] = 0;
     }
-    const int s = tl.s, e = tl.e;
+    const int s = ranges[2 * t], e = ranges[2 * t + 1];
     const float amin = rp.alpha_min, amax = rp.alpha_max, tmin = rp.t_min;
     int ncontrib = 0, nent = 0;
+    uint32_t idn = s < e ? batch_ids(ids, s, s, e) : 0u;
     for (int b = s; b < e; b += kWave) {
         bool alive = false;
 #pragma unroll
         for (int k = 0; k < PPL; k++) alive |= !done[k];
         if (__ballot(alive) == 0) break;
-        const int j = b + lane;
-        uint32_t m4 = 0;
+        const uint32_t id = idn;
+        const int nb = min(kWave, e - b);
         LaneSplat ls = {};
-        if (j < e) {
-            m4 = tile_bits(((uint64_t)lmhi[j] << 32) | lmlo[j], tl.sx, tl.sy);
-            if (m4) ls = load_splat(rec, lpair[j], amin);
-        }
-        uint64_t keep = __ballot(m4 != 0);
-        nent += __popcll(keep);
-        while (keep) {
-            const int i = __builtin_ctzll(keep);
-            keep &= keep - 1;
-            const uint32_t m = (uint32_t)bcast((int)m4, i);
+        if (lane < nb) ls = load_splat(rec, id & kPairMask, amin);
+        idn = batch_ids(ids, b + kWave, s, e);  // next batch, behind the records
+        nent += nb;
+        for (int i = 0; i < nb; i++) {
+            const uint32_t m = (uint32_t)bcast((int)id, i) >> kPairBits;
             const float mx = bcast(ls.mx, i), my = bcast(ls.my, i), o = bcast(ls.o, i);
             const float qa = bcast(ls.a, i), qb = bcast(ls.b, i), qc = bcast(ls.c, i);
             const float cr = bcast(ls.cr, i), cg = bcast(ls.cg, i), cb = bcast(ls.cb, i);
@@ -171,7 +152,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
 #pragma unroll
             for (int k = 0; k < PPL; k++) {
                 if (!(m & TM::quads(k))) continue;  // wave-uniform
-                qn[k]++;
+                if (EVALS) qn[k]++;
                 if (done[k]) continue;
                 const float dx = mx - fx[k];
                 const float dy = my - fy[k];
@@ -192,12 +173,11 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
                 C2[k] = __builtin_fmaf(cb, w, C2[k]);
                 T[k] = Tn;
                 last[k] = pos;
-                lastq[k] = qn[k];
+                if (EVALS) lastq[k] = qn[k];
                 ncontrib++;
             }
         }
     }
-    // contributing (pixel, splat) pairs of the tile: a workload statistic
     // workload statistics of the tile: contributing (pixel, splat) pairs, list
     // entries read, and (pixel, entry) evaluations up to each pixel's last
     // contributor over the entries covering its quadrant
@@ -211,13 +191,16 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
     if (lane == 0) {
         tile_contrib[t] = ncontrib;
         tile_entries[t] = nent;
-        tile_evals[t] = nev;
+        if (EVALS) tile_evals[t] = nev;
     }
     const float b0 = bg ? bg[0] : 0.f, b1 = bg ? bg[1] : 0.f, b2 = bg ? bg[2] : 0.f;
 #pragma unroll
     for (int k = 0; k < PPL; k++) {
-        if (px[k] < W && py[k] < H) {
-            const int64_t pix = (int64_t)vt.pix_off[v] + (int64_t)py[k] * W + px[k];
+        int x, y;
+        TM::pixel(lane, k, x, y);
+        const int px = tx * TW + x, py = ty * TH + y;
+        if (px < W && py < H) {
+            const int64_t pix = (int64_t)vt.pix_off[v] + (int64_t)py * W + px;
             out_rgb[3 * pix] = C0[k] + T[k] * b0;
             out_rgb[3 * pix + 1] = C1[k] + T[k] * b1;
             out_rgb[3 * pix + 2] = C2[k] + T[k] * b2;
@@ -229,9 +212,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
 
 template <int TW, int TH>
 __global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ rec,
-                                                   const uint32_t* __restrict__ lpair,
-                                                   const uint32_t* __restrict__ lmlo,
-                                                   const uint32_t* __restrict__ lmhi,
+                                                   const int32_t* __restrict__ ids,
                                                    const int32_t* __restrict__ ranges,
                                                    const uint32_t* __restrict__ order, ViewTable vt,
                                                    RasterParams rp, const float* __restrict__ bg,
@@ -242,10 +223,10 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ re
     using TM = TileMap<TW, TH>;
     constexpr int PPL = TM::PPL;
     const int t = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
-    const TileList tl = tile_list(vt, ranges, t);
-    const int v = tl.v;
-    const int W = vt.W[v], H = vt.H[v];
-    const int tx = tl.tx, ty = tl.ty;
+    const int v = tile_view(vt, t);
+    const int lt = t - vt.tile_off[v];
+    const int gx = vt.gx[v], W = vt.W[v], H = vt.H[v];
+    const int tx = lt % gx, ty = lt / gx;
     const int lane = threadIdx.x;
     const float b0 = bg ? bg[0] : 0.f, b1 = bg ? bg[1] : 0.f, b2 = bg ? bg[2] : 0.f;
     float fx[PPL], fy[PPL], Tc[PPL], V0[PPL], V1[PPL], V2[PPL], VS[PPL];
@@ -275,26 +256,22 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ re
         lmax = max(lmax, L[k]);
     }
     lmax = wave_max_i(lmax);
-    const int s = tl.s, e = tl.e;
-    lmax = min(lmax, e - s);  // a pixel's last contributor lies inside its block's list
+    const int s = ranges[2 * t], e = ranges[2 * t + 1];
+    lmax = min(lmax, e - s);  // a pixel's last contributor lies inside its tile's list
     if (lmax <= 0) return;
     const float amin = rp.alpha_min, amax = rp.alpha_max;
-    for (int b = s + ((lmax - 1) / kWave) * kWave; b >= s; b -= kWave) {
-        const int j = b + lane;
-        uint32_t m4 = 0, pair = 0;
+    const int top = s + lmax;  // entries [s, top) can matter
+    int b = s + ((lmax - 1) / kWave) * kWave;
+    uint32_t idn = batch_ids(ids, b, s, top);
+    for (; b >= s; b -= kWave) {
+        const uint32_t id = idn;
+        const int nb = min(kWave, top - b);
         LaneSplat ls = {};
-        if (j < s + lmax) {
-            m4 = tile_bits(((uint64_t)lmhi[j] << 32) | lmlo[j], tl.sx, tl.sy);
-            if (m4) {
-                pair = lpair[j];
-                ls = load_splat(rec, pair, amin);
-            }
-        }
-        uint64_t keep = __ballot(m4 != 0);
-        while (keep) {
-            const int i = 63 - __builtin_clzll(keep);
-            keep &= ~(1ull << i);
-            const uint32_t m = (uint32_t)bcast((int)m4, i);
+        if (lane < nb) ls = load_splat(rec, id & kPairMask, amin);
+        idn = batch_ids(ids, b - kWave, s, top);  // next (lower) batch, behind the records
+        for (int i = nb - 1; i >= 0; i--) {
+            const uint32_t idb = (uint32_t)bcast((int)id, i);
+            const uint32_t m = idb >> kPairBits;
             const float mx = bcast(ls.mx, i), my = bcast(ls.my, i), o = bcast(ls.o, i);
             const float qa = bcast(ls.a, i), qb = bcast(ls.b, i), qc = bcast(ls.c, i);
             const float cr = bcast(ls.cr, i), cg = bcast(ls.cg, i), cb = bcast(ls.cb, i);
@@ -357,8 +334,8 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ re
                                 : (comp == 2 || comp == 4) ? -0.5f * o * e8
                                 : comp == 3 ? -o * e8
                                 : comp == 8 ? tb : e8;
-                const int64_t p = (uint32_t)bcast((int)pair, i);
-                atomicAdd(grad2d + 9 * p + comp, val);
+                const int64_t p = idb & kPairMask;
+                atomicAdd(grad2d + GS_GRAD2D_FLOATS * p + comp, val);
             }
         }
     }
@@ -399,10 +376,16 @@ template <int TW, int TH>
 hipError_t fwd_impl(Ctx* c, const ViewTable& vt, const RasterParams& rp, const float* bg,
                     float* rgb, float* T_final, int32_t* last, const uint32_t* order,
                     hipStream_t st) {
-    hipLaunchKernelGGL((k_render_fwd<TW, TH>), dim3((unsigned)c->n_tiles), dim3(64), 0, st,
-                       reinterpret_cast<const float4*>(c->rec), c->lpair, c->lmask_lo, c->lmask_hi, c->ranges, order,
-                       vt, rp, bg, rgb, T_final, last, c->tile_contrib, c->tile_entries,
-                       c->tile_evals);
+    if (rp.eval_stats)
+        hipLaunchKernelGGL((k_render_fwd<TW, TH, true>), dim3((unsigned)c->n_tiles), dim3(64), 0, st,
+                           reinterpret_cast<const float4*>(c->rec), reinterpret_cast<const int32_t*>(c->tids),
+                           c->tranges, order, vt, rp, bg, rgb, T_final, last, c->tile_contrib,
+                           c->tile_entries, c->tile_evals);
+    else
+        hipLaunchKernelGGL((k_render_fwd<TW, TH, false>), dim3((unsigned)c->n_tiles), dim3(64), 0, st,
+                           reinterpret_cast<const float4*>(c->rec), reinterpret_cast<const int32_t*>(c->tids),
+                           c->tranges, order, vt, rp, bg, rgb, T_final, last, c->tile_contrib,
+                           c->tile_entries, c->tile_evals);
     return hipGetLastError();
 }
 
@@ -411,7 +394,7 @@ hipError_t bwd_impl(Ctx* c, const ViewTable& vt, const RasterParams& rp, const f
                     const float* T_final, const int32_t* last, const float* v_rgb,
                     const uint32_t* order, hipStream_t st) {
     hipLaunchKernelGGL((k_render_bwd<TW, TH>), dim3((unsigned)c->n_tiles), dim3(64), 0, st,
-                       reinterpret_cast<const float4*>(c->rec), c->lpair, c->lmask_lo, c->lmask_hi, c->ranges, order,
+                       reinterpret_cast<const float4*>(c->rec), reinterpret_cast<const int32_t*>(c->tids), c->tranges, order,
                        vt, rp, bg, T_final, last, v_rgb, c->grad2d);
     return hipGetLastError();
 }

@@ -107,17 +107,16 @@ def test_bin_sort_bit_exact_on_synthetic_records(gs, tile):
     assert st["flags"] == 0
     ranges_o, ids_o, masks_o = oracle.bin_sort(wh, tile, r["valid"], r["mean2d"], r["conic"],
                                                r["opacity"], r["depth"], with_masks=True)
-    # the tile lists, expanded from the block lists, equal the definition's
-    ranges, ids, masks = gs._lib.tile_lists(ctx, wh, tile[0], tile[1])
-    assert ranges.shape[0] == ranges_o.shape[0]
-    assert np.array_equal(ranges, ranges_o.astype(np.int64))
-    assert np.array_equal(ids, ids_o.astype(np.int64))
-    assert np.array_equal(masks, masks_o.astype(np.int64))
-    # every block-list entry reaches at least one of its block's tiles
+    assert st["n_isect"] == len(ids_o)
     b = ctx.buffers()
-    assert st["n_isect"] == int(_read_i32(b["block_ranges"], 2 * b["n_blocks"])[1::2].max())
-    m = gs._lib.list_masks(ctx, st["n_isect"])
-    assert np.all(m != 0)
+    T = b["n_tiles"]
+    assert T == ranges_o.shape[0]
+    ranges = _read_i32(b["tile_ranges"], 2 * T).reshape(T, 2)
+    ent = _read_i32(b["isect_ids"], len(ids_o)).view(np.uint32)
+    assert np.array_equal(ranges, ranges_o.astype(np.int32))
+    # an entry is the pair index (low 28 bits) and the quadrant mask (top 4)
+    assert np.array_equal(ent & 0x0FFFFFFF, ids_o.astype(np.uint32))
+    assert np.array_equal(ent >> 28, masks_o.astype(np.uint32))
 
 
 def _read_i32(ptr, n):
@@ -131,8 +130,11 @@ def test_bin_sort_real_scene_lists(gs):
     # list is ascending in (gpu float32 depth, pair).
     sc = _parity_scene(seed=5, N=1500)
     sp, params, rgb, T, last, cams, ctx = _render(gs, sc)
-    ranges, ids, _ = gs._lib.tile_lists(ctx, sc["wh"])
-    nt = ranges.shape[0]
+    st = ctx.status()
+    b = ctx.buffers()
+    nt = b["n_tiles"]
+    ranges = _read_i32(b["tile_ranges"], 2 * nt).reshape(nt, 2)
+    ids = (_read_i32(b["isect_ids"], st["n_isect"]).view(np.uint32) & 0x0FFFFFFF).astype(np.int64)
     pr = oracle.project(sc)
     inner_r, inner = oracle.bin_sort(sc["wh"], (16, 16), pr["valid"], pr["mean2d"], pr["conic"],
                                      pr["opacity"], pr["depth"].astype(np.float32), margin=-0.05)
@@ -198,22 +200,19 @@ def test_tile_order_and_contributor_counts(gs):
     sc = _parity_scene(seed=14)
     a = _render(gs, sc)
     ctx = _ctx(gs, sc)
-    r = _render(gs, sc, ctx=ctx, settings=gs.default_settings(tile_order=1))
+    r = _render(gs, sc, ctx=ctx, settings=gs.default_settings(tile_order=1, eval_stats=1))
     assert np.array_equal(a[2].cpu().numpy(), r[2].cpu().numpy())
     st = gs._lib.gs_ctx_tile_stats(ctx)
     assert st["ordered"]
     nt = st["n_tiles"]
     order = gs._lib.copy_to_host(st["tile_order"], nt, np.uint32)
     assert np.array_equal(np.sort(order), np.arange(nt))
-    # a tile weighs its block's list length
     bufs = ctx.buffers()
-    br = _read_i32(bufs["block_ranges"], 2 * bufs["n_blocks"]).reshape(-1, 2)
+    ranges = _read_i32(bufs["tile_ranges"], 2 * nt).reshape(nt, 2)
+    lens = ranges[:, 1] - ranges[:, 0]
+    assert np.all(np.diff(_length_bucket(lens[order])) <= 0)
     W, H = sc["wh"][0]
     gx = (W + 15) // 16
-    bx = (gx + 3) // 4
-    tb = np.array([(t // gx // 4) * bx + (t % gx) // 4 for t in range(nt)])
-    lens = (br[tb, 1] - br[tb, 0])[order]
-    assert np.all(np.diff(_length_bucket(lens)) <= 0)
     contrib = gs._lib.copy_to_host(st["tile_contrib"], nt, np.int32)
     o = oracle.render_fwd_bwd(sc)
     nc = o["ncontrib"].reshape(H, W)
@@ -229,24 +228,20 @@ def test_tile_order_and_contributor_counts(gs):
     assert checked > nt // 2
     # entries read per tile: no more than the tile's list
     ent = gs._lib.copy_to_host(st["tile_entries"], nt, np.int32)
-    tr, _, _ = gs._lib.tile_lists(ctx, sc["wh"])
-    assert np.all(ent <= tr[:, 1] - tr[:, 0])
+    assert np.all(ent <= lens)
     # evaluations per tile: over its pixels, the entries covering the pixel's
-    # quadrant up to the pixel's last contributor (a block-list position)
+    # quadrant up to the pixel's last contributor
     last = r[4].cpu().numpy().reshape(H, W)
-    masks = gs._lib.list_masks(ctx, int(br[:, 1].max()))
+    ids = _read_i32(bufs["isect_ids"], int(ranges[:, 1].max())).view(np.uint32)
     ev = gs._lib.copy_to_host(st["tile_evals"], nt, np.int32)
     for t in range(nt):
         ty, tx = divmod(t, gx)
-        B = tb[t]
-        m = masks[br[B, 0]:br[B, 1]]
-        sh = np.uint64(16 * (ty % 4) + 2 * (tx % 4))
-        m4 = ((m >> sh) & np.uint64(3)) | (((m >> (sh + np.uint64(8))) & np.uint64(3)) << np.uint64(2))
+        m4 = ids[ranges[t, 0]:ranges[t, 1]] >> 28
         want = 0
         for y in range(ty * 16, min(ty * 16 + 16, H)):
             for x in range(tx * 16, min(tx * 16 + 16, W)):
                 q = ((x % 16) >= 8) + 2 * ((y % 16) >= 8)
-                want += int(((m4[:last[y, x]] >> np.uint64(q)) & np.uint64(1)).sum())
+                want += int(((m4[:last[y, x]] >> q) & 1).sum())
         assert ev[t] == want, t
 
 
