@@ -445,15 +445,46 @@ __global__ __launch_bounds__(kChunk) void k_chunk_expand(
             if (lane == q) s_wn[w][q] = (uint32_t)__popcll(bal[q]);
         }
         __syncthreads();
+        // entries of earlier waves of the chunk touching sub-tile q: lane q holds it
+        uint32_t woff = 0;
+        if (lane < kBlockSub)
+            for (int u = 0; u < w; u++) woff += s_wn[u][lane];
+        const uint64_t live = __ballot(m != 0);
+        if (live) {
+            // every sub-tile's list base first (all loads in flight together),
+            // the stores after: one scalar load each when the wave's entries
+            // share one block (the usual case), a gather each otherwise
+            const uint32_t B0 = (uint32_t)__builtin_amdgcn_readlane((int)B, __builtin_ctzll(live));
+            if (__ballot(m != 0 && B != B0) == 0) {
+                // the usual case, the wave's entries share one block: lane q
+                // loads sub-tile q's base (list start - block-start prefix +
+                // chunk prefix + earlier waves), one readlane per sub-tile after
+                uint32_t vq = 0;
+                if (lane < kBlockSub)
+                    vq = tbase[(int64_t)B0 * kBlockSub + lane] + cpre[(int64_t)lane * nchunks + c] + woff;
 #pragma unroll
-        for (int q = 0; q < kBlockSub; q++) {
-            if (bal[q] == 0) continue;  // wave-uniform
-            const uint32_t m4 = tile_bits(m, q % kBlockTiles, q / kBlockTiles);
-            if (!m4) continue;
-            uint32_t rank = (uint32_t)__popcll(bal[q] & lt);
-            for (int u = 0; u < w; u++) rank += s_wn[u][q];
-            const uint32_t pos = tbase[(int64_t)B * kBlockSub + q] + cpre[(int64_t)q * nchunks + c] + rank;
-            tids[pos] = pr | (m4 << kPairBits);
+                for (int q = 0; q < kBlockSub; q++) {
+                    if (bal[q] == 0) continue;  // wave-uniform
+                    const uint32_t m4 = tile_bits(m, q % kBlockTiles, q / kBlockTiles);
+                    const uint32_t bq = (uint32_t)__builtin_amdgcn_readlane((int)vq, q);
+                    if (m4) tids[bq + (uint32_t)__popcll(bal[q] & lt)] = pr | (m4 << kPairBits);
+                }
+            } else {
+                // entries of several blocks: every base gathered per lane (all
+                // loads in flight together, the stores after)
+                const uint32_t Bq = m != 0 ? B : B0;
+                uint32_t base[kBlockSub];
+#pragma unroll
+                for (int q = 0; q < kBlockSub; q++)
+                    base[q] = tbase[(int64_t)Bq * kBlockSub + q] + cpre[(int64_t)q * nchunks + c];
+#pragma unroll
+                for (int q = 0; q < kBlockSub; q++) {
+                    if (bal[q] == 0) continue;  // wave-uniform
+                    const uint32_t m4 = tile_bits(m, q % kBlockTiles, q / kBlockTiles);
+                    const uint32_t wq = (uint32_t)__builtin_amdgcn_readlane((int)woff, q);
+                    if (m4) tids[base[q] + wq + (uint32_t)__popcll(bal[q] & lt)] = pr | (m4 << kPairBits);
+                }
+            }
         }
         __syncthreads();
     }
@@ -569,7 +600,7 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
             uint32_t* ttotal = c->scalars + 2;
             uint32_t* tused = c->scalars + 3;
             const int64_t nch = c->nchunks;
-            const unsigned gch = (unsigned)std::min<int64_t>(nch, 4096);
+            const unsigned gch = (unsigned)std::min<int64_t>(nch, 16384);
             hipLaunchKernelGGL(k_chunk_count, dim3(gch), dim3(kChunk), 0, st, bmlo, bmhi, used, nch,
                                c->ccnt);
             if ((e = exclusive_scan_u32(c->ccnt, kBlockSub * nch, nullptr, c->scan_scratch, st)) != hipSuccess)
