@@ -79,6 +79,28 @@ __device__ __forceinline__ LaneSplat load_splat(const float4* __restrict__ rec, 
     return {ra.x, ra.y, ra.w, q.a, q.b, q.c, rb.w, rc.x, rc.y, e2_cut(ra.w, amin)};
 }
 
+// The raster workgroup is one wave: ordering its LDS accesses needs no
+// workgroup barrier (which would also wait for the loads in flight).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// A batch's splats staged in LDS, one entry per lane as three float4:
+// (mx, my, o, cut), (a, b, c, r), (g, b, -, -).  Entry i is then read by the
+// whole wave from one address (a broadcast), not gathered by readlane.
+struct BatchLds {
+    float4 f[3][kWave];
+};
+
+__device__ __forceinline__ void stage_splat(BatchLds& sb, const LaneSplat& ls) {
+    const int lane = threadIdx.x;
+    sb.f[0][lane] = make_float4(ls.mx, ls.my, ls.o, ls.cut);
+    sb.f[1][lane] = make_float4(ls.a, ls.b, ls.c, ls.cr);
+    sb.f[2][lane] = make_float4(ls.cg, ls.cb, 0.f, 0.f);
+}
+
 // One batch's list entries, loaded by every lane (index clamped into the
 // list, which is not empty) and zeroed outside [s, e): the load stays
 // unconditional, so the compiler's wait bookkeeping sees it on every path.
@@ -130,6 +152,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
     const int s = ranges[2 * t], e = ranges[2 * t + 1];
     const float amin = rp.alpha_min, amax = rp.alpha_max, tmin = rp.t_min;
     int ncontrib = 0, nent = 0;
+    __shared__ BatchLds sb;
     uint32_t idn = s < e ? batch_ids(ids, s, s, e) : 0u;
     for (int b = s; b < e; b += kWave) {
         bool alive = false;
@@ -138,16 +161,20 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
         if (__ballot(alive) == 0) break;
         const uint32_t id = idn;
         const int nb = min(kWave, e - b);
-        LaneSplat ls = {};
-        if (lane < nb) ls = load_splat(rec, id & kPairMask, amin);
+        {
+            LaneSplat ls = {};
+            if (lane < nb) ls = load_splat(rec, id & kPairMask, amin);
+            wave_lds_sync();  // the previous batch is read
+            stage_splat(sb, ls);
+        }
         idn = batch_ids(ids, b + kWave, s, e);  // next batch, behind the records
+        wave_lds_sync();
         nent += nb;
         for (int i = 0; i < nb; i++) {
             const uint32_t m = (uint32_t)bcast((int)id, i) >> kPairBits;
-            const float mx = bcast(ls.mx, i), my = bcast(ls.my, i), o = bcast(ls.o, i);
-            const float qa = bcast(ls.a, i), qb = bcast(ls.b, i), qc = bcast(ls.c, i);
-            const float cr = bcast(ls.cr, i), cg = bcast(ls.cg, i), cb = bcast(ls.cb, i);
-            const float cut = bcast(ls.cut, i);
+            const float4 f0 = sb.f[0][i], f1 = sb.f[1][i], f2 = sb.f[2][i];
+            const float mx = f0.x, my = f0.y, o = f0.z, cut = f0.w;
+            const float qa = f1.x, qb = f1.y, qc = f1.z, cr = f1.w, cg = f2.x, cb = f2.y;
             const int pos = b + i - s + 1;
 #pragma unroll
             for (int k = 0; k < PPL; k++) {
@@ -255,26 +282,37 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ re
         VS[k] = Tc[k] * (V0[k] * b0 + V1[k] * b1 + V2[k] * b2);
         lmax = max(lmax, L[k]);
     }
+    // per slot, the largest `last` of its pixels: past it the whole wave skips
+    // the slot (all its pixels are behind their last contributor)
+    int Lk[PPL];
+#pragma unroll
+    for (int k = 0; k < PPL; k++) Lk[k] = wave_max_i(L[k]);
     lmax = wave_max_i(lmax);
     const int s = ranges[2 * t], e = ranges[2 * t + 1];
     lmax = min(lmax, e - s);  // a pixel's last contributor lies inside its tile's list
     if (lmax <= 0) return;
     const float amin = rp.alpha_min, amax = rp.alpha_max;
     const int top = s + lmax;  // entries [s, top) can matter
+    __shared__ BatchLds sb;
     int b = s + ((lmax - 1) / kWave) * kWave;
     uint32_t idn = batch_ids(ids, b, s, top);
     for (; b >= s; b -= kWave) {
         const uint32_t id = idn;
         const int nb = min(kWave, top - b);
-        LaneSplat ls = {};
-        if (lane < nb) ls = load_splat(rec, id & kPairMask, amin);
+        {
+            LaneSplat ls = {};
+            if (lane < nb) ls = load_splat(rec, id & kPairMask, amin);
+            wave_lds_sync();  // the previous batch is read
+            stage_splat(sb, ls);
+        }
         idn = batch_ids(ids, b - kWave, s, top);  // next (lower) batch, behind the records
+        wave_lds_sync();
         for (int i = nb - 1; i >= 0; i--) {
             const uint32_t idb = (uint32_t)bcast((int)id, i);
             const uint32_t m = idb >> kPairBits;
-            const float mx = bcast(ls.mx, i), my = bcast(ls.my, i), o = bcast(ls.o, i);
-            const float qa = bcast(ls.a, i), qb = bcast(ls.b, i), qc = bcast(ls.c, i);
-            const float cr = bcast(ls.cr, i), cg = bcast(ls.cg, i), cb = bcast(ls.cb, i);
+            const float4 f0 = sb.f[0][i], f1 = sb.f[1][i], f2 = sb.f[2][i];
+            const float mx = f0.x, my = f0.y, o = f0.z;
+            const float qa = f1.x, qb = f1.y, qc = f1.z, cr = f1.w, cg = f2.x, cb = f2.y;
             const int pos = b + i - s;
             // per-lane sums over the lane's pixels: colour weights, q = dL/dalpha
             // e^-sigma (zero where alpha is clamped), and the moments q dx, q dy,
@@ -285,7 +323,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ re
             bool any = false;
 #pragma unroll
             for (int k = 0; k < PPL; k++) {
-                if (!(m & TM::quads(k))) continue;  // wave-uniform
+                if (!(m & TM::quads(k)) || pos >= Lk[k]) continue;  // wave-uniform
                 const float dx = mx - fx[k];
                 const float dy = my - fy[k];
                 const float e2 = splat_e2(qa, qb, qc, dx, dy);
