@@ -186,7 +186,8 @@ def run_joint(torch, name, steps, warmup, tune=True, tile=None, order=0, graph=T
                  n_visible=stat0["n_visible"], n_isect=stat0["n_isect"], C_f=C_f,
                  n_eval=n_eval, n_contrib=n_contrib,
                  M=int(st.obs_cam.shape[0]), Pt=int(st.X.shape[0]),
-                 n_params=int(sum(v.numel() for v in st._opt_params().values())))
+                 n_params=int(sum(v.numel() for v in st._opt_params().values())),
+                 n_adam=int(st.twist.numel() + st.X.numel()))
     return dict(ms=ms, graph_ms=graph_ms, per_call=per_call, status=status, sizes=sizes, st=st,
                 sc=sc, batches=batches, tuning=tuning)
 
@@ -203,8 +204,11 @@ def algorithmic_bytes(sz):
         "l1": sz["P"] * 36,
         "raster_bwd": sz["C_f"] * 40 + sz["P"] * 20 + sz["n_visible"] * 36,
         "project_bwd": sz["n_visible"] * 36 + 2 * sz["N"] * pg,
+        # 2D gradients in; parameters, first and second moments in and out
+        "project_bwd_adam": sz["n_visible"] * 36 + 6 * sz["N"] * pg,
         "track": sz["M"] * 28 + 2 * sz["Pt"] * 12,
-        "adam": sz["n_params"] * 28,
+        # twists and track points (the Gaussians step inside project_bwd_adam)
+        "adam": sz["n_adam"] * 28,
     }
 
 
@@ -222,7 +226,8 @@ ALU_KERNELS = ("render_fwd", "raster_bwd")
 # calls that launch one kernel (the others are sequences: bin_sort is ~25)
 SINGLE_KERNEL = ("project", "render_fwd", "l1", "raster_bwd", "track", "adam")
 KERNEL_SOURCE = {"render_fwd": "raster.hip", "raster_bwd": "raster.hip", "project": "project.hip",
-                 "project_bwd": "project.hip", "bin_sort": "bin.hip", "track": "track.hip",
+                 "project_bwd": "project.hip", "project_bwd_adam": "project.hip",
+                 "bin_sort": "bin.hip", "track": "track.hip",
                  "adam": "optim.hip", "l1": "raster.hip"}
 
 

@@ -316,6 +316,28 @@ typedef struct {
 gs_status gs_adam_step(const gs_adam_group* groups, int32_t n_groups, int32_t step,
                        float beta1, float beta2, float eps, void* stream);
 
+/* Adam state of the five Gaussian arrays for gs_project_bwd_adam: params[q] is
+ * the array of gs_gaussians it steps (means, log_scales, quats, opacity_logit,
+ * sh, in that order; the same pointers), exp_avg / exp_avg_sq its moments in
+ * the same layout, lr[q] its learning rate. */
+typedef struct {
+    float* params[5];
+    float* exp_avg[5];
+    float* exp_avg_sq[5];
+    float lr[5];
+} gs_gaussian_adam;
+
+/* gs_project_bwd followed by gs_adam_step on the five Gaussian arrays, in one
+ * pass (the backward and update steps of Algorithm 1): each Gaussian's
+ * gradient, summed over the views, is spent on its Adam step in place instead
+ * of being written, so the gradients never reach memory.  Same results as the
+ * two calls (the element update is the same code); the twists are added into
+ * v_twist as gs_project_bwd does.  The arrays of `adam->params` must be those
+ * of `g`; step >= 1. */
+gs_status gs_project_bwd_adam(gs_ctx* ctx, const gs_gaussians* g, const gs_cameras* cams,
+                              const gs_settings* s, const gs_gaussian_adam* adam, int32_t step,
+                              float beta1, float beta2, float eps, float* v_twist, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

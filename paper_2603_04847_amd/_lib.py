@@ -69,11 +69,16 @@ class gs_adam_group(ctypes.Structure):
                 ("n", ctypes.c_int64), ("lr", ctypes.c_float)]
 
 
+class gs_gaussian_adam(ctypes.Structure):
+    _fields_ = [("params", c_vp * 5), ("exp_avg", c_vp * 5), ("exp_avg_sq", c_vp * 5),
+                ("lr", ctypes.c_float * 5)]
+
+
 EXPORTS = [
     "gs_strerror", "gs_default_settings", "gs_ctx_create", "gs_ctx_destroy", "gs_ctx_status",
     "gs_ctx_reset_status", "gs_ctx_buffers", "gs_ctx_tile_stats", "gs_project", "gs_bin_sort", "gs_render_fwd",
     "gs_render_bwd", "gs_raster_bwd", "gs_project_bwd", "gs_l1_loss_grad", "track_reproj_fwd_bwd", "gs_pose_compose",
-    "gs_pose_compose_bwd", "gs_adam_step",
+    "gs_pose_compose_bwd", "gs_adam_step", "gs_project_bwd_adam",
 ]
 
 _lib = None
@@ -131,6 +136,10 @@ def load():
     lib.gs_pose_compose_bwd.argtypes = [ctypes.c_int32, c_vp, c_vp, c_vp, c_vp]
     lib.gs_adam_step.argtypes = [ctypes.POINTER(gs_adam_group), ctypes.c_int32, ctypes.c_int32,
                                  ctypes.c_float, ctypes.c_float, ctypes.c_float, c_vp]
+    lib.gs_project_bwd_adam.argtypes = [c_vp, ctypes.POINTER(gs_gaussians), ctypes.POINTER(gs_cameras),
+                                        ctypes.POINTER(gs_settings), ctypes.POINTER(gs_gaussian_adam),
+                                        ctypes.c_int32, ctypes.c_float, ctypes.c_float,
+                                        ctypes.c_float, c_vp, c_vp]
     _lib = lib
     return lib
 
@@ -353,6 +362,22 @@ def gs_pose_compose(twist, base, out, stream=None):
 def gs_pose_compose_bwd(twist, g, out, stream=None):
     _check("gs_pose_compose_bwd", load().gs_pose_compose_bwd(int(twist.shape[0]), _ptr(twist),
                                                              _ptr(g), _ptr(out), _stream(stream)))
+
+
+def gs_project_bwd_adam(ctx, gaussians, cams, settings, params, exp_avg, exp_avg_sq, lrs, step,
+                        v_twist, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):
+    """params / exp_avg / exp_avg_sq: the five Gaussian tensors (means,
+    log_scales, quats, opacity_logit, sh) and their moments; lrs: five rates."""
+    a = gs_gaussian_adam()
+    for q in range(5):
+        a.params[q] = _ptr(params[q])
+        a.exp_avg[q] = _ptr(exp_avg[q])
+        a.exp_avg_sq[q] = _ptr(exp_avg_sq[q])
+        a.lr[q] = float(lrs[q])
+    _check("gs_project_bwd_adam", load().gs_project_bwd_adam(
+        ctx.handle, ctypes.byref(gaussians), ctypes.byref(cams.struct), ctypes.byref(settings),
+        ctypes.byref(a), int(step), float(beta1), float(beta2), float(eps), _ptr(v_twist),
+        _stream(stream)))
 
 
 def gs_adam_step(groups, step, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):

@@ -341,7 +341,41 @@ gs_status gs_project_bwd(gs_ctx* h, const gs_gaussians* g, const gs_cameras* cam
         return GS_ERR_INVALID_ARG;
     const gs::ViewTable vt = gs::make_view_table(cams->wh, cams->V, s->tile_w, s->tile_h, cams->index);
     const gs::RasterParams rp = gs::make_raster_params(s);
-    return from_hip(gs::launch_project_bwd(&h->c, g, cams, vt, rp, grads, s->grad_accumulate, v_twist,
+    return from_hip(gs::launch_project_bwd(&h->c, g, cams, vt, rp, nullptr, grads, s->grad_accumulate,
+                                           v_twist, (hipStream_t)stream));
+}
+
+gs_status gs_project_bwd_adam(gs_ctx* h, const gs_gaussians* g, const gs_cameras* cams,
+                              const gs_settings* s, const gs_gaussian_adam* adam, int32_t step,
+                              float beta1, float beta2, float eps, float* v_twist, void* stream) {
+    if (!h || !adam || !v_twist || step <= 0) return GS_ERR_INVALID_ARG;
+    if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f))
+        return GS_ERR_INVALID_ARG;
+    gs_status r;
+    if ((r = check_settings(s)) != GS_OK) return r;
+    if ((r = check_gaussians(g)) != GS_OK) return r;
+    if ((r = check_cams(h->c, cams, true)) != GS_OK) return r;
+    if ((r = check_bins_match(h->c, cams, s)) != GS_OK) return r;
+    if (h->c.bin_N != g->N) return GS_ERR_INVALID_ARG;
+    // the parameters stepped are the arrays g points to (updated in place)
+    const float* arrays[5] = {g->means, g->log_scales, g->quats, g->opacity_logit, g->sh};
+    gs::AdamGauss a{};
+    for (int q = 0; q < 5; q++) {
+        if (g->N > 0 && (adam->params[q] != arrays[q] || !adam->exp_avg[q] || !adam->exp_avg_sq[q]))
+            return GS_ERR_INVALID_ARG;
+        a.p[q] = adam->params[q];
+        a.m[q] = adam->exp_avg[q];
+        a.v[q] = adam->exp_avg_sq[q];
+        a.lr[q] = adam->lr[q];
+    }
+    a.b1 = beta1;
+    a.b2 = beta2;
+    a.eps = eps;
+    a.ibc1 = (float)(1.0 / (1.0 - pow((double)beta1, step)));
+    a.ibc2 = (float)(1.0 / (1.0 - pow((double)beta2, step)));
+    const gs::ViewTable vt = gs::make_view_table(cams->wh, cams->V, s->tile_w, s->tile_h, cams->index);
+    const gs::RasterParams rp = gs::make_raster_params(s);
+    return from_hip(gs::launch_project_bwd(&h->c, g, cams, vt, rp, &a, nullptr, 0, v_twist,
                                            (hipStream_t)stream));
 }
 

@@ -213,6 +213,26 @@ __device__ __forceinline__ void span_cols(const SplatSpan& s, int r, int W, int 
     c1 = min((int)floorf((xr - 0.5f) * g.ihw), ncols - 1);
 }
 
+// One Adam step of one element (Algorithm 1 update step): bias-corrected
+// moments through ibc1 = 1 / (1 - b1^t), ibc2 = 1 / (1 - b2^t).  Every Adam
+// in the library goes through this one function.
+__device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, float lr, float b1,
+                                         float b2, float eps, float ibc1, float ibc2) {
+    m = b1 * m + (1.f - b1) * g;
+    v = b2 * v + (1.f - b2) * g * g;
+    p -= lr * (m * ibc1) / (sqrtf(v * ibc2) + eps);
+}
+
+// Adam state of the five Gaussian arrays (means, log_scales, quats,
+// opacity_logit, sh) for the projection backward that also steps them.
+struct AdamGauss {
+    float* p[5];
+    float* m[5];
+    float* v[5];
+    float lr[5];
+    float b1, b2, eps, ibc1, ibc2;
+};
+
 // A tile-list entry carries the pair index in its low 28 bits and the
 // quadrant mask in the top 4.
 constexpr uint32_t kPairBits = 28;
@@ -324,8 +344,10 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
 // project.hip
 hipError_t launch_project_fwd(Ctx* c, const gs_gaussians* g, const gs_cameras* cams,
                               const ViewTable& vt, const RasterParams& rp, hipStream_t st);
+// with adam non-null the Gaussian gradients are not written: each one takes
+// its Adam step in place instead
 hipError_t launch_project_bwd(Ctx* c, const gs_gaussians* g, const gs_cameras* cams,
-                              const ViewTable& vt, const RasterParams& rp,
+                              const ViewTable& vt, const RasterParams& rp, const AdamGauss* adam,
                               gs_gaussians_grad* grads, int accumulate, float* v_twist,
                               hipStream_t st);
 

@@ -103,13 +103,6 @@ struct AdamArgs {
 
 constexpr int kAdamPerBlock = 256 * 4;
 
-__device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, float lr, float b1,
-                                         float b2, float eps, float ibc1, float ibc2) {
-    m = b1 * m + (1.f - b1) * g;
-    v = b2 * v + (1.f - b2) * g * g;
-    p -= lr * (m * ibc1) / (sqrtf(v * ibc2) + eps);
-}
-
 // Each block updates 1024 consecutive elements of one group (float4 loads
 // when the group is 16-byte aligned).
 __global__ __launch_bounds__(256) void k_adam(AdamArgs a, float b1, float b2, float eps, float ibc1,

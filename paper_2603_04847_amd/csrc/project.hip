@@ -277,11 +277,12 @@ __global__ __launch_bounds__(kBlock) void k_project_fwd(gs_gaussians g, const fl
     if (nonfinite) atomicOr(&diag[kDiagFlags], (uint32_t)GS_FLAG_NONFINITE);
 }
 
-template <int DEG>
+template <int DEG, bool ADAM>
 __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, const float* __restrict__ viewmat,
                                                         const float* __restrict__ intr, ViewTable vt,
                                                         RasterParams rp, float* __restrict__ grad2d,
                                                         gs_gaussians_grad out, int accumulate,
+                                                        AdamGauss adam,
                                                         double* __restrict__ twist_acc) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     __shared__ float s_tw[kBlock / kWave][6];
@@ -503,7 +504,60 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, const fl
         }
         __syncthreads();
     }
-    if (active) {
+    if (active && ADAM) {
+        // the Gaussian's 11 + 3K gradients in one flat list (means, log_scales,
+        // quats, opacity, sh); each Adam batch issues all its parameter and
+        // moment loads before its first store, so the loads of a batch are in
+        // flight together
+        constexpr int NP = 11 + 3 * K;
+        constexpr int BATCH = 20;
+        float gr[NP];
+#pragma unroll
+        for (int e = 0; e < 3; e++) gr[e] = v_mu[e];
+#pragma unroll
+        for (int e = 0; e < 3; e++) gr[3 + e] = v_ls[e];
+#pragma unroll
+        for (int e = 0; e < 4; e++) gr[6 + e] = v_q[e];
+        gr[10] = v_logit;
+#pragma unroll
+        for (int k = 0; k < K; k++)
+#pragma unroll
+            for (int ch = 0; ch < 3; ch++) gr[11 + 3 * k + ch] = v_sh[k][ch];
+        // array and row of flat entry j
+        auto arr = [](int j) { return j < 3 ? 0 : j < 6 ? 1 : j < 10 ? 2 : j < 11 ? 3 : 4; };
+        auto row = [](int j) { return j < 3 ? j : j < 6 ? j - 3 : j < 10 ? j - 6 : j < 11 ? 0 : j - 11; };
+        // element i of a row: the row start is uniform, the byte offset i * 4
+        // one 32-bit lane value shared by every access (N < 2^28, as pairs are)
+        const uint32_t off = (uint32_t)i * 4u;
+        auto at = [&](float* base, int r) -> float& {
+            return *reinterpret_cast<float*>(reinterpret_cast<char*>(base + (int64_t)r * N) + off);
+        };
+#pragma unroll
+        for (int j0 = 0; j0 < NP; j0 += BATCH) {
+            float pb[BATCH], mb[BATCH], vb[BATCH];
+#pragma unroll
+            for (int u = 0; u < BATCH; u++) {
+                const int j = j0 + u;
+                if (j < NP) {
+                    pb[u] = at(adam.p[arr(j)], row(j));
+                    mb[u] = at(adam.m[arr(j)], row(j));
+                    vb[u] = at(adam.v[arr(j)], row(j));
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < BATCH; u++) {
+                const int j = j0 + u;
+                if (j < NP) {
+                    const int q = arr(j);
+                    adam_one(pb[u], gr[j], mb[u], vb[u], adam.lr[q], adam.b1, adam.b2, adam.eps,
+                             adam.ibc1, adam.ibc2);
+                    at(adam.p[q], row(j)) = pb[u];
+                    at(adam.m[q], row(j)) = mb[u];
+                    at(adam.v[q], row(j)) = vb[u];
+                }
+            }
+        }
+    } else if (active) {
     auto put = [&](float* dst, int64_t idx, float val) {
         if (accumulate) dst[idx] += val;
         else dst[idx] = val;
@@ -542,17 +596,31 @@ hipError_t launch_project_fwd(Ctx* c, const gs_gaussians* g, const gs_cameras* c
     return hipGetLastError();
 }
 
+template <int DEG>
+void project_bwd_impl(Ctx* c, const gs_gaussians* g, const gs_cameras* cams, const ViewTable& vt,
+                      const RasterParams& rp, const AdamGauss* adam, const gs_gaussians_grad* grads,
+                      int accumulate, hipStream_t st) {
+    const dim3 grid(std::min((g->N + kBlock - 1) / kBlock, 1024)), block(kBlock);
+    const gs_gaussians_grad none{};
+    const AdamGauss no_adam{};
+    if (adam)
+        hipLaunchKernelGGL((k_project_bwd<DEG, true>), grid, block, 0, st, *g, cams->viewmat, cams->intr,
+                           vt, rp, c->grad2d, none, 0, *adam, c->twist_render);
+    else
+        hipLaunchKernelGGL((k_project_bwd<DEG, false>), grid, block, 0, st, *g, cams->viewmat,
+                           cams->intr, vt, rp, c->grad2d, *grads, accumulate, no_adam, c->twist_render);
+}
+
 hipError_t launch_project_bwd(Ctx* c, const gs_gaussians* g, const gs_cameras* cams,
-                              const ViewTable& vt, const RasterParams& rp,
+                              const ViewTable& vt, const RasterParams& rp, const AdamGauss* adam,
                               gs_gaussians_grad* grads, int accumulate, float* v_twist,
                               hipStream_t st) {
     if (g->N > 0) {
-        const dim3 grid(std::min((g->N + kBlock - 1) / kBlock, 1024)), block(kBlock);
         switch (g->sh_degree) {
-            case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, block, 0, st, *g, cams->viewmat, cams->intr, vt, rp, c->grad2d, *grads, accumulate, c->twist_render); break;
-            case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, block, 0, st, *g, cams->viewmat, cams->intr, vt, rp, c->grad2d, *grads, accumulate, c->twist_render); break;
-            case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, block, 0, st, *g, cams->viewmat, cams->intr, vt, rp, c->grad2d, *grads, accumulate, c->twist_render); break;
-            default: hipLaunchKernelGGL(k_project_bwd<3>, grid, block, 0, st, *g, cams->viewmat, cams->intr, vt, rp, c->grad2d, *grads, accumulate, c->twist_render); break;
+            case 0: project_bwd_impl<0>(c, g, cams, vt, rp, adam, grads, accumulate, st); break;
+            case 1: project_bwd_impl<1>(c, g, cams, vt, rp, adam, grads, accumulate, st); break;
+            case 2: project_bwd_impl<2>(c, g, cams, vt, rp, adam, grads, accumulate, st); break;
+            default: project_bwd_impl<3>(c, g, cams, vt, rp, adam, grads, accumulate, st); break;
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

@@ -12,6 +12,8 @@ the C ABI, without Python-side arithmetic:
       (the same twist buffer: poses get both gradients)
   a1' twist gradient through the composition                gs_pose_compose_bwd
   a10 Adam on Gaussians, poses and track points             gs_adam_step
+      (in `run`, the Gaussians' Adam step is taken inside the projection
+      backward, gs_project_bwd_adam, so their gradients never reach memory)
 
 Learning rates follow Sec. 3.3 "Implementation" and the pose rate of Sec. 3.3;
 the track-point rate (not given in the paper) is the position rate.
@@ -105,8 +107,10 @@ class JointStep:
         d["X"] = self.v_X
         return d
 
-    def forward_backward(self, b, timer=None):
-        """a1-a9 and the twist chain, for batch b.  `timer(name)` brackets calls."""
+    def forward_backward(self, b, timer=None, adam_step=None):
+        """a1-a9 and the twist chain, for batch b.  `timer(name)` brackets calls.
+        With `adam_step` (the Adam step number t), the projection backward also
+        takes the Gaussians' Adam step and self.grads is left untouched."""
         t = timer or (lambda name: _Null())
         cams = self.cams[b]
         P = cams.n_pixels
@@ -126,8 +130,16 @@ class JointStep:
             L.gs_l1_loss_grad(self.ctx, cams, self.rgb, self.targets[b], self.v_rgb, self.loss[0:1])
         with t("raster_bwd"):
             L.gs_raster_bwd(self.ctx, cams, s, None, self.T, self.last, self.v_rgb)
-        with t("project_bwd"):
-            L.gs_project_bwd(self.ctx, self.g, cams, s, self.gg, self.v_tw_cur)
+        if adam_step is None:
+            with t("project_bwd"):
+                L.gs_project_bwd(self.ctx, self.g, cams, s, self.gg, self.v_tw_cur)
+        else:
+            with t("project_bwd_adam"):
+                L.gs_project_bwd_adam(self.ctx, self.g, cams, s,
+                                      [self.params[k] for k in PARAM_KEYS],
+                                      [self.m[k] for k in PARAM_KEYS],
+                                      [self.v[k] for k in PARAM_KEYS],
+                                      [self.lr[k] for k in PARAM_KEYS], adam_step, self.v_tw_cur)
         with t("track"):
             L.track_reproj_fwd_bwd(self.ctx, self.X, self.viewmat, self.intr, self.obs_cam,
                                    self.obs_pt, self.obs_xy, self.delta, self.lam, 0.01,
@@ -136,19 +148,27 @@ class JointStep:
             L.gs_pose_compose_bwd(self.twist, self.v_tw_cur, self.v_tw)
         del P
 
-    def adam(self, timer=None, step=None):
-        t = timer or (lambda name: _Null())
+    def _next_step(self, step):
         if step is None:
             self.step_count += 1
             step = self.step_count
+        return step
+
+    def adam(self, timer=None, step=None, keys=None):
+        """Adam on the groups `keys` (default: all) from their gradients."""
+        t = timer or (lambda name: _Null())
+        step = self._next_step(step)
         p, g = self._opt_params(), self._opt_grads()
-        groups = [(p[k], g[k], self.m[k], self.v[k], self.lr[k]) for k in p]
+        groups = [(p[k], g[k], self.m[k], self.v[k], self.lr[k]) for k in (keys or p)]
         with t("adam"):
             L.gs_adam_step(groups, step)
 
     def run(self, b, timer=None, step=None):
-        self.forward_backward(b, timer)
-        self.adam(timer, step)
+        """One iteration: forward, backward with the Gaussians' Adam step fused
+        into the projection backward, then Adam on the twists and track points."""
+        step = self._next_step(step)
+        self.forward_backward(b, timer, adam_step=step)
+        self.adam(timer, step, keys=("twist", "X"))
 
 
 class _Null:
