@@ -85,6 +85,8 @@ typedef enum {
 /* Device status flags (gs_diag.flags). */
 #define GS_FLAG_ISECT_OVERFLOW 1u   /* tile-list entries exceeded max_isect */
 #define GS_FLAG_NONFINITE 2u        /* a non-finite projected splat was culled */
+#define GS_FLAG_SCAN_STALLED 4u     /* a device-wide scan stopped waiting for a preceding
+                                       workgroup (bounded wait); that step's lists are invalid */
 
 /* Most views one render call takes. */
 #define GS_MAX_VIEWS 64

@@ -306,17 +306,25 @@ __device__ __forceinline__ bool touches(uint64_t m, int q) {
     return tile_bits(m, q % kBlockTiles, q / kBlockTiles) != 0;
 }
 
-// Per chunk and sub-tile: entries touching it.  ccnt is [16][nchunks] (column q
-// contiguous).
+// Column stride of the chunk counts: one slot per chunk of the live entries
+// and a last one that stays 0, so the prefix at the very end of the list is
+// still read inside its column.
+__device__ __forceinline__ int64_t chunk_stride(const uint32_t* used) {
+    return ((int64_t)*used + kChunk - 1) / kChunk + 1;
+}
+
+// Per chunk and sub-tile: entries touching it.  ccnt is [16][stride] (column q
+// contiguous), scanned as one array: every prefix that is used is a
+// difference inside one column.
 __global__ __launch_bounds__(kChunk) void k_chunk_count(const uint32_t* __restrict__ mlo,
                                                         const uint32_t* __restrict__ mhi,
                                                         const uint32_t* __restrict__ used,
-                                                        int64_t nchunks, uint32_t* __restrict__ ccnt) {
+                                                        uint32_t* __restrict__ ccnt) {
     __shared__ uint32_t s_wn[kChunkWaves][kBlockSub];
     const int64_t n = *used;
+    const int64_t stride = chunk_stride(used);
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    // chunks past the entries keep stale counts: every prefix that is used is a
-    // difference inside one column, where such constants cancel (mod 2^32)
+    if (blockIdx.x == 0 && threadIdx.x < kBlockSub) ccnt[(int64_t)threadIdx.x * stride + stride - 1] = 0u;
     for (int64_t c = blockIdx.x; c * kChunk < n; c += gridDim.x) {
         const int64_t j = c * kChunk + threadIdx.x;
         uint64_t m = 0;
@@ -330,7 +338,7 @@ __global__ __launch_bounds__(kChunk) void k_chunk_count(const uint32_t* __restri
         if (threadIdx.x < kBlockSub) {
             uint32_t cn = 0;
             for (int u = 0; u < kChunkWaves; u++) cn += s_wn[u][threadIdx.x];
-            ccnt[(int64_t)threadIdx.x * nchunks + c] = cn;
+            ccnt[(int64_t)threadIdx.x * stride + c] = cn;
         }
         __syncthreads();
     }
@@ -340,7 +348,7 @@ __global__ __launch_bounds__(kChunk) void k_chunk_count(const uint32_t* __restri
 // chunk before x, counted by one wave.  Returns the value for q = lane (lanes < 16).
 __device__ __forceinline__ uint32_t prefix_at(const uint32_t* __restrict__ mlo,
                                               const uint32_t* __restrict__ mhi,
-                                              const uint32_t* __restrict__ cpre, int64_t nchunks,
+                                              const uint32_t* __restrict__ cpre, int64_t stride,
                                               int64_t x) {
     const int lane = __lane_id();
     const int64_t c = x / kChunk, c0 = c * kChunk;
@@ -355,7 +363,7 @@ __device__ __forceinline__ uint32_t prefix_at(const uint32_t* __restrict__ mlo,
             if (lane == q) part += n;
         }
     }
-    return lane < kBlockSub ? cpre[(int64_t)lane * nchunks + c] + part : 0u;
+    return lane < kBlockSub ? cpre[(int64_t)lane * stride + c] + part : 0u;
 }
 
 // Per block (one wave): the prefixes at its list's start, its sub-tiles' list
@@ -364,7 +372,8 @@ __global__ __launch_bounds__(kWave) void k_block_tiles(const int32_t* __restrict
                                                        const uint32_t* __restrict__ mlo,
                                                        const uint32_t* __restrict__ mhi,
                                                        const uint32_t* __restrict__ cpre,
-                                                       int64_t nchunks, ViewTable vt, int TH,
+                                                       const uint32_t* __restrict__ used,
+                                                       ViewTable vt, int TH,
                                                        uint32_t* __restrict__ bpre,
                                                        int4* __restrict__ bplace,
                                                        uint32_t* __restrict__ tcnt) {
@@ -379,8 +388,9 @@ __global__ __launch_bounds__(kWave) void k_block_tiles(const int32_t* __restrict
     const int rs = branges[2 * B], re = branges[2 * B + 1];
     uint32_t ps = 0, pe = 0;
     if (rs < re) {
-        ps = prefix_at(mlo, mhi, cpre, nchunks, rs);
-        pe = prefix_at(mlo, mhi, cpre, nchunks, re);
+        const int64_t stride = chunk_stride(used);
+        ps = prefix_at(mlo, mhi, cpre, stride, rs);
+        pe = prefix_at(mlo, mhi, cpre, stride, re);
     }
     if (lane < kBlockSub) {
         bpre[(int64_t)B * kBlockSub + lane] = ps;
@@ -419,12 +429,13 @@ __global__ __launch_bounds__(kBlock) void k_tile_ranges(const uint32_t* __restri
 __global__ __launch_bounds__(kChunk) void k_chunk_expand(
     const uint32_t* __restrict__ bkey, const uint32_t* __restrict__ pairs,
     const uint32_t* __restrict__ mlo, const uint32_t* __restrict__ mhi,
-    const uint32_t* __restrict__ used, const uint32_t* __restrict__ tused, int64_t nchunks,
+    const uint32_t* __restrict__ used, const uint32_t* __restrict__ tused,
     const uint32_t* __restrict__ cpre, const uint32_t* __restrict__ tbase, uint32_t NB,
     uint32_t* __restrict__ tids) {
     __shared__ uint32_t s_wn[kChunkWaves][kBlockSub];
     if (*tused == 0u) return;  // nothing is written after an overflow
     const int64_t n = *used;
+    const int64_t stride = chunk_stride(used);
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const uint64_t lt = lanemask_lt();
     for (int64_t c = blockIdx.x; c * kChunk < n; c += gridDim.x) {
@@ -461,7 +472,7 @@ __global__ __launch_bounds__(kChunk) void k_chunk_expand(
                 // chunk prefix + earlier waves), one readlane per sub-tile after
                 uint32_t vq = 0;
                 if (lane < kBlockSub)
-                    vq = tbase[(int64_t)B0 * kBlockSub + lane] + cpre[(int64_t)lane * nchunks + c] + woff;
+                    vq = tbase[(int64_t)B0 * kBlockSub + lane] + cpre[(int64_t)lane * stride + c] + woff;
 #pragma unroll
                 for (int q = 0; q < kBlockSub; q++) {
                     if (bal[q] == 0) continue;  // wave-uniform
@@ -476,7 +487,7 @@ __global__ __launch_bounds__(kChunk) void k_chunk_expand(
                 uint32_t base[kBlockSub];
 #pragma unroll
                 for (int q = 0; q < kBlockSub; q++)
-                    base[q] = tbase[(int64_t)Bq * kBlockSub + q] + cpre[(int64_t)q * nchunks + c];
+                    base[q] = tbase[(int64_t)Bq * kBlockSub + q] + cpre[(int64_t)q * stride + c];
 #pragma unroll
                 for (int q = 0; q < kBlockSub; q++) {
                     if (bal[q] == 0) continue;  // wave-uniform
@@ -567,14 +578,14 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
         hipLaunchKernelGGL(k_count, dim3(gp), dim3(kBlock), 0, st, rec, N, vt, rp, c->cnt, c->pk[0],
                            c->pv[0]);
         const int side = radix_sort_pairs(c->pk[0], c->pv[0], c->pk[1], c->pv[1], npairs, nullptr,
-                                          0, 32, c->hist, c->scan_scratch, st, &e);
+                                          0, 32, c->hist, c->scan_scratch, c->diag + kDiagFlags, st, &e);
         if (e != hipSuccess) return e;
         const uint32_t* order = c->pv[side];
         hipLaunchKernelGGL(k_gather_cnt, dim3(gp), dim3(kBlock), 0, st, order, c->pk[side], c->cnt,
                            c->off, npairs, c->diag);
         uint32_t* total = c->scalars + 0;
         uint32_t* used = c->scalars + 1;
-        if ((e = exclusive_scan_u32(c->off, npairs, total, c->scan_scratch, st)) != hipSuccess)
+        if ((e = exclusive_scan_u32(c->off, npairs, total, c->scan_scratch, c->diag + kDiagFlags, st)) != hipSuccess)
             return e;
         hipLaunchKernelGGL(k_isect_total, dim3(1), dim3(64), 0, st, total, c->cap.max_isect, used,
                            c->diag, nullptr, nullptr);
@@ -586,7 +597,7 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
         // the pair and both mask words travel with the block key
         uint32_t* K[2] = {c->ik[0], c->ik[1]};
         uint32_t* Vv[3][2] = {{c->iv[0], c->iv[1]}, {c->im[0], c->im[1]}, {c->im[0] + I, c->im[1] + I}};
-        const int side2 = radix_sort_kv3(K, Vv, I, used, 0, bbits, c->hist, c->scan_scratch, st, &e);
+        const int side2 = radix_sort_kv3(K, Vv, I, used, 0, bbits, c->hist, c->scan_scratch, c->diag + kDiagFlags, st, &e);
         if (e != hipSuccess) return e;
         const uint32_t* bpair = c->iv[side2];
         const uint32_t* bmlo = c->im[side2];
@@ -601,15 +612,15 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
             uint32_t* tused = c->scalars + 3;
             const int64_t nch = c->nchunks;
             const unsigned gch = (unsigned)std::min<int64_t>(nch, 16384);
-            hipLaunchKernelGGL(k_chunk_count, dim3(gch), dim3(kChunk), 0, st, bmlo, bmhi, used, nch,
-                               c->ccnt);
-            if ((e = exclusive_scan_u32(c->ccnt, kBlockSub * nch, nullptr, c->scan_scratch, st)) != hipSuccess)
+            hipLaunchKernelGGL(k_chunk_count, dim3(gch), dim3(kChunk), 0, st, bmlo, bmhi, used, c->ccnt);
+            if ((e = exclusive_scan_u32_dev(c->ccnt, kBlockSub * (nch + 1), used, kChunk, kBlockSub, 1,
+                                            nullptr, c->scan_scratch, c->diag + kDiagFlags, st)) != hipSuccess)
                 return e;
             if ((e = launch_fill_u32(c->tcnt, 0u, T, st)) != hipSuccess) return e;
             if (NB > 0)
                 hipLaunchKernelGGL(k_block_tiles, dim3((unsigned)NB), dim3(kWave), 0, st, c->ranges, bmlo,
-                                   bmhi, c->ccnt, nch, vt, rp.tile_h, c->bpre, c->bplace, c->tcnt);
-            if ((e = exclusive_scan_u32(c->tcnt, T, ttotal, c->scan_scratch, st)) != hipSuccess)
+                                   bmhi, c->ccnt, used, vt, rp.tile_h, c->bpre, c->bplace, c->tcnt);
+            if ((e = exclusive_scan_u32(c->tcnt, T, ttotal, c->scan_scratch, c->diag + kDiagFlags, st)) != hipSuccess)
                 return e;
             // the tile lists must fit too (their total replaces the block count)
             hipLaunchKernelGGL(k_isect_total, dim3(1), dim3(64), 0, st, ttotal, c->cap.max_isect, tused,
@@ -618,7 +629,7 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
             hipLaunchKernelGGL(k_tile_ranges, dim3(gt), dim3(kBlock), 0, st, c->tcnt, ttotal, tused, vt,
                                rp.tile_h, T, c->bpre, c->tranges, c->tbase);
             hipLaunchKernelGGL(k_chunk_expand, dim3(gch), dim3(kChunk), 0, st, c->ik[side2], bpair, bmlo,
-                               bmhi, used, tused, nch, c->ccnt, c->tbase, (uint32_t)NB, c->tids);
+                               bmhi, used, tused, c->ccnt, c->tbase, (uint32_t)NB, c->tids);
         }
         if (tile_order && T > 0 && T <= ((int64_t)1 << 20)) {
             hipLaunchKernelGGL(k_tile_bucket, dim3((unsigned)((T + kBlock - 1) / kBlock)), dim3(kBlock),
@@ -633,7 +644,7 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
             uint32_t* kk[2] = {c->tk[0], c->tk[1]};
             uint32_t* vv[2] = {c->tile_order, reinterpret_cast<uint32_t*>(c->tile_contrib)};
             const int side3 = radix_sort_pairs(kk[0], vv[0], kk[1], vv[1], T, nullptr, 0, 24, c->hist,
-                                               c->scan_scratch, st, &e);
+                                               c->scan_scratch, c->diag + kDiagFlags, st, &e);
             if (e != hipSuccess) return e;
             if (side3 == 1) {
                 e = hipMemcpyAsync(c->tile_order, vv[1], sizeof(uint32_t) * T, hipMemcpyDeviceToDevice, st);

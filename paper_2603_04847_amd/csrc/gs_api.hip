@@ -178,7 +178,7 @@ gs_status gs_ctx_create(gs_ctx** out, const gs_capacity* cap) {
     A(dalloc(&c.ranges, (size_t)2 * T));
     A(dalloc(&c.tcnt, (size_t)T));
     c.nchunks = I / 256 + 1;
-    A(dalloc(&c.ccnt, (size_t)16 * c.nchunks));
+    A(dalloc(&c.ccnt, (size_t)16 * (c.nchunks + 1)));
     A(dalloc(&c.bpre, (size_t)16 * T));
     A(dalloc(&c.bplace, (size_t)T));
     A(dalloc(&c.tbase, (size_t)16 * T));
@@ -192,7 +192,9 @@ gs_status gs_ctx_create(gs_ctx** out, const gs_capacity* cap) {
     A(dalloc(&c.tile_evals, (size_t)T));
     const size_t hw = gs::radix_hist_words(sortmax);
     A(dalloc(&c.hist, hw));
-    A(dalloc(&c.scan_scratch, gs::scan_scratch_words((int64_t)hw)));
+    // the largest scan: radix digit counts, chunk counts, pair counts or tiles
+    const int64_t scanmax = std::max<int64_t>(std::max<int64_t>((int64_t)hw, 16 * (c.nchunks + 1)), sortmax);
+    A(dalloc(&c.scan_scratch, gs::scan_scratch_words(scanmax)));
     A(dalloc(&c.scalars, 16));
     const int nv = cap->max_views;
     const int nc = cap->max_cams > 0 ? cap->max_cams : 1;
@@ -206,6 +208,8 @@ gs_status gs_ctx_create(gs_ctx** out, const gs_capacity* cap) {
     if (e == hipSuccess) A(hipMemset(c.loss_acc, 0, sizeof(double) * 4));
     if (e == hipSuccess) A(hipMemset(c.diag, 0, sizeof(uint32_t) * gs::kDiagCount));
     if (e == hipSuccess) A(hipMemset(c.scalars, 0, sizeof(uint32_t) * 16));
+    // scans expect a zero workspace and leave it zero
+    if (e == hipSuccess) A(hipMemset(c.scan_scratch, 0, sizeof(uint32_t) * gs::scan_scratch_words(scanmax)));
     if (e == hipSuccess) A(hipDeviceSynchronize());
     if (e != hipSuccess) {
         gs_ctx_destroy(h);

@@ -323,19 +323,29 @@ RasterParams make_raster_params(const gs_settings* s);
 
 // scan.hip / sort.hip
 size_t scan_scratch_words(int64_t max_n);
+// Exclusive scan in place (mod 2^32); total_out (device, nullable) gets the
+// total.  scratch: scan_scratch_words(n) words, zero before the first scan and
+// left zero by every scan; flags (device, nullable) gets GS_FLAG_SCAN_STALLED
+// if a look-back gave up.
 hipError_t exclusive_scan_u32(uint32_t* data, int64_t n, uint32_t* total_out, uint32_t* scratch,
-                              hipStream_t st);
+                              uint32_t* flags, hipStream_t st);
+// The same over a length the device holds: mul * (ceil(*d_cnt / per) + add),
+// at most max_n (the launch covers max_n).
+hipError_t exclusive_scan_u32_dev(uint32_t* data, int64_t max_n, const uint32_t* d_cnt, int64_t per,
+                                  int64_t mul, int64_t add, uint32_t* total_out, uint32_t* scratch,
+                                  uint32_t* flags, hipStream_t st);
 size_t radix_hist_words(int64_t max_n);
 // Stable LSD radix sort of (key, value) u32 pairs on bits [lo, hi). n items
 // (device count d_n if non-null, clamped to max_n). Returns the buffer pair
 // holding the result: 0 = (ka, va), 1 = (kb, vb).
 int radix_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_t max_n,
                      const uint32_t* d_n, int lo, int hi, uint32_t* hist, uint32_t* scan_scratch,
-                     hipStream_t st, hipError_t* err);
+                     uint32_t* flags, hipStream_t st, hipError_t* err);
 // The same with three value words per item (separate arrays): K[side],
 // V[word][side]; returns the side holding the result.
 int radix_sort_kv3(uint32_t* K[2], uint32_t* V[3][2], int64_t max_n, const uint32_t* d_n, int lo,
-                   int hi, uint32_t* hist, uint32_t* scan_scratch, hipStream_t st, hipError_t* err);
+                   int hi, uint32_t* hist, uint32_t* scan_scratch, uint32_t* flags, hipStream_t st,
+                   hipError_t* err);
 
 // bin.hip
 hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp,
@@ -394,7 +404,7 @@ struct Ctx {
     uint32_t* im[2];       // [2][max_isect] block masks, low then high words (ping-pong)
     int32_t* ranges;       // [max_tiles][2] block list ranges (blocks <= tiles)
     uint32_t* tcnt;        // [max_tiles] tile list lengths, then their scan
-    uint32_t* ccnt;        // [16][nchunks] sub-tile counts per 256-entry chunk, then their scan
+    uint32_t* ccnt;        // [16][ceil(used / 256) + 1] sub-tile counts per 256-entry chunk, then their scan
     int64_t nchunks;       // max_isect / 256 + 1
     uint32_t* bpre;        // [max_tiles][16] sub-tile prefixes at each block's list start
     int4* bplace;          // [max_tiles] first tile, row stride, tiles across / down per block

@@ -1,4 +1,4 @@
-// Device-wide exclusive scan and stable LSD radix sort of (u32 key, u32 value)
+// Device-wide exclusive scan (single pass) and stable LSD radix sort of (u32 key, u32 value)
 // pairs, written for wave64: digit ranks inside a wave come from ballots
 // (match-any over the digit bits), across waves from LDS counters, and each
 // block stages its items in LDS so the global scatter writes contiguous runs.
@@ -40,61 +40,148 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* s_w, u
     return before + inc - v;
 }
 
-__global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n,
-                                                          uint32_t* __restrict__ part) {
-    __shared__ uint32_t s_w[kWaves];
-    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
-    uint32_t s = 0;
-#pragma unroll
-    for (int i = 0; i < kItems; i++) {
-        int64_t j = base + i;
-        if (j < n) s += in[j];
-    }
-    uint32_t tot;
-    block_excl_scan(s, s_w, tot);
-    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+// Single-pass scan with decoupled look-back.  Tiles of kScanTile items are taken
+// in launch order from a counter, so every tile a workgroup waits on belongs
+// to a workgroup that is already running.  A tile publishes its own total
+// (flag kAgg), then its first wave reads the words of the 64 preceding tiles
+// at once and adds back to the nearest one that carries an inclusive prefix
+// (flag kIncl), which it then publishes for itself.  The last workgroup to
+// finish clears the words and counters, so the workspace is clean for the
+// next scan without a separate fill.
+//
+// Workspace (u32 words): [0] tile counter, [1] finished counter, then one
+// 64-bit word per tile from word kScanHeader: flag << 32 | value.
+constexpr int kScanHeader = 64;
+constexpr uint32_t kAgg = 1u, kIncl = 2u;
+// bound on the polls of one look-back (each ~1 us): a wait that never ends is
+// reported (GS_FLAG_SCAN_STALLED) instead of hanging the device
+constexpr int kSpinLimit = 1 << 21;
+
+__device__ __forceinline__ uint64_t ld_word(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_word(uint64_t* p, uint32_t flag, uint32_t v) {
+    __hip_atomic_store(p, ((uint64_t)flag << 32) | v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// one block of 1024 threads scans up to 16384 block partials
-__global__ __launch_bounds__(1024) void k_scan_partials(uint32_t* __restrict__ part, int nparts,
-                                                        uint32_t* __restrict__ total_out) {
-    __shared__ uint32_t s_w[16];
-    const int per = (nparts + 1023) / 1024;
-    const int b = threadIdx.x * per;
-    uint32_t loc[16];
-    uint32_t s = 0;
-    for (int i = 0; i < per; i++) {
-        loc[i] = (b + i < nparts) ? part[b + i] : 0u;
-        s += loc[i];
-    }
-    uint32_t tot;
-    uint32_t ex = block_excl_scan(s, s_w, tot);
-    for (int i = 0; i < per; i++) {
-        if (b + i < nparts) part[b + i] = ex;
-        ex += loc[i];
-    }
-    if (threadIdx.x == 0 && total_out) *total_out = tot;
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
 }
 
-__global__ __launch_bounds__(kThreads) void k_scan_apply(uint32_t* __restrict__ data, int64_t n,
-                                                         const uint32_t* __restrict__ part) {
-    __shared__ uint32_t s_w[kWaves];
-    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
-    uint32_t v[kItems];
-    uint32_t s = 0;
-#pragma unroll
-    for (int i = 0; i < kItems; i++) {
-        int64_t j = base + i;
-        v[i] = (j < n) ? data[j] : 0u;
-        s += v[i];
+// Called by one whole wave: the sum of the values of tiles [0, t) (mod 2^32).
+__device__ uint32_t wave_lookback(const uint64_t* words, int64_t t, uint32_t* flags) {
+    const int lane = __lane_id();
+    uint32_t excl = 0;
+    int64_t top = t - 1;
+    int polls = 0;
+    while (top >= 0) {
+        const int64_t idx = top - lane;
+        const uint64_t w = idx >= 0 ? ld_word(words + idx) : ((uint64_t)kIncl << 32);
+        const uint32_t flag = (uint32_t)(w >> 32);
+        const uint64_t incl = __ballot(flag == kIncl);
+        const uint64_t none = __ballot(flag == 0u);
+        const int first = incl ? __builtin_ctzll(incl) : kWave;  // nearest inclusive tile
+        const uint64_t need = first >= kWave - 1 ? ~0ull : ((2ull << first) - 1ull);
+        if (none & need) {
+            if (++polls > kSpinLimit) {
+                if (lane == 0 && flags) atomicOr(flags, (uint32_t)GS_FLAG_SCAN_STALLED);
+                return excl;
+            }
+            __builtin_amdgcn_s_sleep(2);
+            continue;
+        }
+        excl += wave_sum_u32(lane <= first ? (uint32_t)w : 0u);
+        if (first < kWave) break;
+        top -= kWave;
     }
-    uint32_t tot;
-    uint32_t ex = block_excl_scan(s, s_w, tot) + part[blockIdx.x];
+    return excl;
+}
+
+// 32 items per thread, read and written as 16-byte vectors: 8192 per tile
+constexpr int kScanItems = 32;
+constexpr int kScanTile = kThreads * kScanItems;
+
+// The length is max_n, or, with d_cnt, mul * (ceil(*d_cnt / per) + add)
+// clamped to max_n (a count only the device knows: the grid covers max_n and
+// tiles past the length only take their tickets).
+__global__ __launch_bounds__(kThreads) void k_scan(uint32_t* __restrict__ data, int64_t max_n,
+                                                   const uint32_t* __restrict__ d_cnt, int64_t per,
+                                                   int64_t mul, int64_t add,
+                                                   uint32_t* __restrict__ total_out,
+                                                   uint32_t* __restrict__ ws,
+                                                   uint32_t* __restrict__ flags) {
+    __shared__ uint32_t s_w[kWaves];
+    __shared__ uint32_t s_t, s_excl, s_last;
+    uint64_t* words = reinterpret_cast<uint64_t*>(ws + kScanHeader);
+    int64_t n = max_n;
+    if (d_cnt) n = min(max_n, mul * (((int64_t)*d_cnt + per - 1) / per + add));
+    const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
+    if (threadIdx.x == 0) s_t = atomicAdd(&ws[0], 1u);
+    __syncthreads();
+    const int64_t t = s_t;
+    if (t >= ntiles) {
+        if (t == 0 && total_out && threadIdx.x == 0) *total_out = 0u;
+    } else {
+        const int64_t base = t * kScanTile + (int64_t)threadIdx.x * kScanItems;
+        const bool full = base + kScanItems <= n;
+        uint32_t v[kScanItems];
+        if (full) {
+            const uint4* p = reinterpret_cast<const uint4*>(data + base);
 #pragma unroll
-    for (int i = 0; i < kItems; i++) {
-        int64_t j = base + i;
-        if (j < n) data[j] = ex;
-        ex += v[i];
+            for (int i = 0; i < kScanItems / 4; i++) {
+                const uint4 q = p[i];
+                v[4 * i] = q.x;
+                v[4 * i + 1] = q.y;
+                v[4 * i + 2] = q.z;
+                v[4 * i + 3] = q.w;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < kScanItems; i++) v[i] = base + i < n ? data[base + i] : 0u;
+        }
+        uint32_t s = 0;
+#pragma unroll
+        for (int i = 0; i < kScanItems; i++) s += v[i];
+        uint32_t tot;
+        uint32_t ex = block_excl_scan(s, s_w, tot);
+        if (threadIdx.x < kWave) {
+            if (threadIdx.x == 0) st_word(words + t, t == 0 ? kIncl : kAgg, tot);
+            const uint32_t excl = t > 0 ? wave_lookback(words, t, flags) : 0u;
+            if (threadIdx.x == 0) {
+                if (t > 0) st_word(words + t, kIncl, excl + tot);
+                s_excl = excl;
+                if (t == ntiles - 1 && total_out) *total_out = excl + tot;
+            }
+        }
+        __syncthreads();
+        ex += s_excl;
+#pragma unroll
+        for (int i = 0; i < kScanItems; i++) {
+            const uint32_t x = v[i];
+            v[i] = ex;
+            ex += x;
+        }
+        if (full) {
+            uint4* p = reinterpret_cast<uint4*>(data + base);
+#pragma unroll
+            for (int i = 0; i < kScanItems / 4; i++)
+                p[i] = make_uint4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < kScanItems; i++)
+                if (base + i < n) data[base + i] = v[i];
+        }
+    }
+    // every tile has finished its look-back once all have taken a ticket here
+    if (threadIdx.x == 0) s_last = atomicAdd(&ws[1], 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (s_last) {
+        for (int64_t k = threadIdx.x; k < ntiles; k += kThreads) st_word(words + k, 0u, 0u);
+        if (threadIdx.x == 0) {
+            __hip_atomic_store(&ws[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ws[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 }
 
@@ -125,14 +212,14 @@ __device__ __forceinline__ int64_t item_index(int64_t base, int w, int i, int la
     return base + (int64_t)w * (kWave * ITEMS) + i * kWave + lane;
 }
 
-// Per-block digit counts, digit-major: hist[d * nblocks + block].  All loads
-// of a thread are issued before the first ballot.
+// Per-block digit counts, digit-major: hist[d * nb + block] with nb the number
+// of blocks that hold items (the live count), so the scan covers only those.
+// All loads of a thread are issued before the first ballot.
 template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                          const uint32_t* __restrict__ d_n,
                                                          int64_t max_n, int shift, int bits,
-                                                         uint32_t* __restrict__ hist,
-                                                         uint32_t nblocks) {
+                                                         uint32_t* __restrict__ hist) {
     constexpr int TILE = kThreads * ITEMS;
     __shared__ uint32_t s_h[kWaves][256];
     const uint32_t n = dev_count(d_n, max_n);
@@ -158,8 +245,9 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restr
         }
     }
     __syncthreads();
-    if (tid <= (int)mask)
-        hist[(int64_t)tid * nblocks + blockIdx.x] = s_h[0][tid] + s_h[1][tid] + s_h[2][tid] + s_h[3][tid];
+    const int64_t nb = ((int64_t)n + TILE - 1) / TILE;
+    if (tid <= (int)mask && (int64_t)blockIdx.x < nb)
+        hist[(int64_t)tid * nb + blockIdx.x] = s_h[0][tid] + s_h[1][tid] + s_h[2][tid] + s_h[3][tid];
 }
 
 // Value arrays moved with the keys: NV words per item, one array each.
@@ -173,7 +261,7 @@ template <int ITEMS, int NV>
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     const uint32_t* __restrict__ kin, uint32_t* __restrict__ kout, ValArrays<NV> va,
     const uint32_t* __restrict__ d_n, int64_t max_n, int shift, int bits,
-    const uint32_t* __restrict__ hist, uint32_t nblocks) {
+    const uint32_t* __restrict__ hist) {
     constexpr int TILE = kThreads * ITEMS;
     __shared__ uint32_t s_h[kWaves][256];  // per-wave digit counts, then offsets
     __shared__ uint32_t s_start[256];
@@ -196,7 +284,8 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
         for (int c = 0; c < NV; c++) v[c][i] = j < n ? va.in[c][j] : 0u;
     }
     for (int q = 0; q < kWaves; q++) s_h[q][tid] = 0;
-    s_glob[tid] = tid <= (int)mask ? hist[(int64_t)tid * nblocks + blockIdx.x] : 0u;
+    const int64_t nb = ((int64_t)n + TILE - 1) / TILE;
+    s_glob[tid] = tid <= (int)mask ? hist[(int64_t)tid * nb + blockIdx.x] : 0u;
     __syncthreads();
     // stable rank inside the wave's chunk: earlier steps (LDS count) + earlier lanes
 #pragma unroll
@@ -247,17 +336,27 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
 
 }  // namespace
 
-size_t scan_scratch_words(int64_t max_n) { return (size_t)((max_n + kTile - 1) / kTile) + 16; }
+size_t scan_scratch_words(int64_t max_n) {
+    return (size_t)kScanHeader + 2 * (size_t)((max_n + kScanTile - 1) / kScanTile) + 16;
+}
+
+hipError_t exclusive_scan_u32_dev(uint32_t* data, int64_t max_n, const uint32_t* d_cnt, int64_t per,
+                                  int64_t mul, int64_t add, uint32_t* total_out, uint32_t* scratch,
+                                  uint32_t* flags, hipStream_t st) {
+    if (max_n <= 0) return hipSuccess;
+    // whole-tile vector accesses need 16-byte alignment
+    if (reinterpret_cast<uintptr_t>(data) % 16 != 0 || (d_cnt && (per <= 0 || mul <= 0 || add < 0)))
+        return hipErrorInvalidValue;
+    const int64_t nt = (max_n + kScanTile - 1) / kScanTile;
+    if (nt > ((int64_t)1 << 31)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_scan, dim3((unsigned)nt), dim3(kThreads), 0, st, data, max_n, d_cnt, per, mul,
+                       add, total_out, scratch, flags);
+    return hipGetLastError();
+}
 
 hipError_t exclusive_scan_u32(uint32_t* data, int64_t n, uint32_t* total_out, uint32_t* scratch,
-                              hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    const int64_t nb = (n + kTile - 1) / kTile;
-    if (nb > 16384) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kThreads), 0, st, data, n, scratch);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, scratch, (int)nb, total_out);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kThreads), 0, st, data, n, scratch);
-    return hipGetLastError();
+                              uint32_t* flags, hipStream_t st) {
+    return exclusive_scan_u32_dev(data, n, nullptr, 1, 1, 0, total_out, scratch, flags, st);
 }
 
 size_t radix_hist_words(int64_t max_n) { return (size_t)256 * ((max_n + kTile - 1) / kTile) + 16; }
@@ -268,14 +367,15 @@ namespace {
 template <int ITEMS, int NV>
 hipError_t radix_pass(const uint32_t* ki, uint32_t* ko, const ValArrays<NV>& va, int64_t max_n,
                       const uint32_t* d_n, int shift, int bits, uint32_t* hist,
-                      uint32_t* scan_scratch, hipStream_t st) {
+                      uint32_t* scan_scratch, uint32_t* flags, hipStream_t st) {
     const uint32_t nb = (uint32_t)((max_n + kThreads * ITEMS - 1) / (kThreads * ITEMS));
     hipLaunchKernelGGL(k_radix_hist<ITEMS>, dim3(nb), dim3(kThreads), 0, st, ki, d_n, max_n, shift,
-                       bits, hist, nb);
-    hipError_t e = exclusive_scan_u32(hist, ((int64_t)1 << bits) * nb, nullptr, scan_scratch, st);
+                       bits, hist);
+    hipError_t e = exclusive_scan_u32_dev(hist, ((int64_t)1 << bits) * nb, d_n, kThreads * ITEMS,
+                                          (int64_t)1 << bits, 0, nullptr, scan_scratch, flags, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_radix_scatter<ITEMS, NV>), dim3(nb), dim3(kThreads), 0, st, ki, ko, va,
-                       d_n, max_n, shift, bits, hist, nb);
+                       d_n, max_n, shift, bits, hist);
     return hipGetLastError();
 }
 
@@ -283,7 +383,8 @@ hipError_t radix_pass(const uint32_t* ki, uint32_t* ko, const ValArrays<NV>& va,
 // V[c][2] are the ping-pong buffers; returns the side holding the result
 template <int NV>
 int radix_sort_impl(uint32_t* K[2], uint32_t* V[NV][2], int64_t max_n, const uint32_t* d_n, int lo,
-                    int hi, uint32_t* hist, uint32_t* scan_scratch, hipStream_t st, hipError_t* err) {
+                    int hi, uint32_t* hist, uint32_t* scan_scratch, uint32_t* flags, hipStream_t st,
+                    hipError_t* err) {
     *err = hipSuccess;
     if (max_n <= 0 || hi <= lo) return 0;
     const int total = hi - lo;
@@ -301,10 +402,10 @@ int radix_sort_impl(uint32_t* K[2], uint32_t* V[NV][2], int64_t max_n, const uin
         // digit in the scatter); wider payloads keep 4096 for the LDS staging
         if (NV == 1 && max_n > ((int64_t)1 << 22))
             *err = radix_pass<32, NV>(K[cur], K[cur ^ 1], va, max_n, d_n, shift, bits, hist,
-                                      scan_scratch, st);
+                                      scan_scratch, flags, st);
         else
             *err = radix_pass<16, NV>(K[cur], K[cur ^ 1], va, max_n, d_n, shift, bits, hist,
-                                      scan_scratch, st);
+                                      scan_scratch, flags, st);
         if (*err != hipSuccess) return cur;
         shift += bits;
         cur ^= 1;
@@ -316,15 +417,16 @@ int radix_sort_impl(uint32_t* K[2], uint32_t* V[NV][2], int64_t max_n, const uin
 
 int radix_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_t max_n,
                      const uint32_t* d_n, int lo, int hi, uint32_t* hist, uint32_t* scan_scratch,
-                     hipStream_t st, hipError_t* err) {
+                     uint32_t* flags, hipStream_t st, hipError_t* err) {
     uint32_t* K[2] = {ka, kb};
     uint32_t* V[1][2] = {{va, vb}};
-    return radix_sort_impl<1>(K, V, max_n, d_n, lo, hi, hist, scan_scratch, st, err);
+    return radix_sort_impl<1>(K, V, max_n, d_n, lo, hi, hist, scan_scratch, flags, st, err);
 }
 
 int radix_sort_kv3(uint32_t* K[2], uint32_t* V[3][2], int64_t max_n, const uint32_t* d_n, int lo,
-                   int hi, uint32_t* hist, uint32_t* scan_scratch, hipStream_t st, hipError_t* err) {
-    return radix_sort_impl<3>(K, V, max_n, d_n, lo, hi, hist, scan_scratch, st, err);
+                   int hi, uint32_t* hist, uint32_t* scan_scratch, uint32_t* flags, hipStream_t st,
+                   hipError_t* err) {
+    return radix_sort_impl<3>(K, V, max_n, d_n, lo, hi, hist, scan_scratch, flags, st, err);
 }
 
 }  // namespace gs

@@ -119,6 +119,39 @@ def test_bin_sort_bit_exact_on_synthetic_records(gs, tile):
     assert np.array_equal(ent >> 28, masks_o.astype(np.uint32))
 
 
+def test_bin_sort_bit_exact_with_many_scan_tiles(gs):
+    """A large capacity makes the capacity-sized scans (chunk counts, block-key
+    digit counts) span hundreds of 4096-item tiles, so the single-pass scans
+    walk back over more than one 64-tile window; lists stay bit-exact."""
+    wh = np.array([[1237, 822], [640, 480]], np.int32)
+    N = 12000
+    r = scenegen.synthetic_records(11, 2, wh, N, tile=(16, 16))
+    rec = np.zeros((2 * N, 12), np.float32)
+    rec[:, 0:2] = r["mean2d"]
+    rec[:, 2] = r["depth"]
+    rec[:, 3] = np.where(r["valid"] > 0, r["opacity"], 0.0)
+    rec[:, 4:7] = r["conic"]
+    rec[:, 7:10] = r["rgb"]
+    ctx = gs.Context(max_pairs=2 * N, max_isect=40_000_000, max_tiles=100_000, max_views=2)
+    s = gs.default_settings(tile_w=16, tile_h=16)
+    cams = gs.Cameras(_t(np.zeros((2, 12))), _t(np.zeros((2, 4))), wh)
+    drec = _t(rec)
+    ranges_o, ids_o, masks_o = oracle.bin_sort(wh, (16, 16), r["valid"], r["mean2d"], r["conic"],
+                                               r["opacity"], r["depth"], with_masks=True)
+    for rep in range(2):  # the second call finds the scan workspace as the first left it
+        gs.gs_bin_sort(ctx, cams, N, s, drec)
+        st = ctx.status()
+        assert st["flags"] == 0
+        assert st["n_isect"] == len(ids_o)
+        b = ctx.buffers()
+        T = b["n_tiles"]
+        ranges = _read_i32(b["tile_ranges"], 2 * T).reshape(T, 2)
+        ent = _read_i32(b["isect_ids"], len(ids_o)).view(np.uint32)
+        assert np.array_equal(ranges, ranges_o.astype(np.int32)), rep
+        assert np.array_equal(ent & 0x0FFFFFFF, ids_o.astype(np.uint32)), rep
+        assert np.array_equal(ent >> 28, masks_o.astype(np.uint32)), rep
+
+
 def _read_i32(ptr, n):
     import paper_2603_04847_amd._lib as L
     return L.copy_to_host(ptr, n, np.int32)
