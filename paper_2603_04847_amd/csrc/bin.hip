@@ -292,7 +292,6 @@ __device__ __forceinline__ void block_place(const ViewTable& vt, int B, int& v, 
 
 constexpr int kBlockSub = kBlockTiles * kBlockTiles;  // tiles per block (sub-tile q = 4 sy + sx)
 constexpr int kChunk = 256;                           // block-list entries per expansion workgroup
-constexpr int kChunkWaves = kChunk / kWave;
 
 // The tile lists come out of the sorted block lists through 16 prefix counts:
 // P_q(j) = entries before position j whose mask touches sub-tile q of their own
@@ -316,31 +315,37 @@ __device__ __forceinline__ int64_t chunk_stride(const uint32_t* used) {
 // Per chunk and sub-tile: entries touching it.  ccnt is [16][stride] (column q
 // contiguous), scanned as one array: every prefix that is used is a
 // difference inside one column.
-__global__ __launch_bounds__(kChunk) void k_chunk_count(const uint32_t* __restrict__ mlo,
+// One wave per chunk: its 256 entries are read four per lane, all loads in
+// flight together, and counted by ballots; nothing is exchanged between waves.
+constexpr int kChunkSteps = kChunk / kWave;
+
+__global__ __launch_bounds__(kBlock) void k_chunk_count(const uint32_t* __restrict__ mlo,
                                                         const uint32_t* __restrict__ mhi,
                                                         const uint32_t* __restrict__ used,
                                                         uint32_t* __restrict__ ccnt) {
-    __shared__ uint32_t s_wn[kChunkWaves][kBlockSub];
     const int64_t n = *used;
     const int64_t stride = chunk_stride(used);
-    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int lane = threadIdx.x % kWave;
     if (blockIdx.x == 0 && threadIdx.x < kBlockSub) ccnt[(int64_t)threadIdx.x * stride + stride - 1] = 0u;
-    for (int64_t c = blockIdx.x; c * kChunk < n; c += gridDim.x) {
-        const int64_t j = c * kChunk + threadIdx.x;
-        uint64_t m = 0;
-        if (j < n) m = ((uint64_t)mhi[j] << 32) | mlo[j];
+    const int64_t nw = (int64_t)gridDim.x * kWaves;
+    for (int64_t c = (int64_t)blockIdx.x * kWaves + threadIdx.x / kWave; c * kChunk < n; c += nw) {
+        uint64_t m[kChunkSteps];
+#pragma unroll
+        for (int u = 0; u < kChunkSteps; u++) {
+            const int64_t j = c * kChunk + u * kWave + lane;
+            const int64_t jc = min(j, n - 1);  // unconditional loads, zeroed past the end
+            const uint64_t mm = ((uint64_t)mhi[jc] << 32) | mlo[jc];
+            m[u] = j < n ? mm : 0ull;
+        }
+        uint32_t cn = 0;
 #pragma unroll
         for (int q = 0; q < kBlockSub; q++) {
-            const uint64_t b = __ballot(touches(m, q));
-            if (lane == q) s_wn[w][q] = (uint32_t)__popcll(b);
+            uint32_t k = 0;
+#pragma unroll
+            for (int u = 0; u < kChunkSteps; u++) k += (uint32_t)__popcll(__ballot(touches(m[u], q)));
+            if (lane == q) cn = k;
         }
-        __syncthreads();
-        if (threadIdx.x < kBlockSub) {
-            uint32_t cn = 0;
-            for (int u = 0; u < kChunkWaves; u++) cn += s_wn[u][threadIdx.x];
-            ccnt[(int64_t)threadIdx.x * stride + c] = cn;
-        }
-        __syncthreads();
+        if (lane < kBlockSub) ccnt[(int64_t)lane * stride + c] = cn;
     }
 }
 
@@ -424,80 +429,96 @@ __global__ __launch_bounds__(kBlock) void k_tile_ranges(const uint32_t* __restri
     (void)TH;
 }
 
-// The tile lists: each block-list entry copied, as (pair | 4-bit mask << 28), to
-// every sub-tile of its block it touches, at the place the prefixes give.
-__global__ __launch_bounds__(kChunk) void k_chunk_expand(
+// Per chunk and sub-tile q, the place in q's list of the chunk's first entry
+// of q, for the block of the chunk's first entry: tbase of that block plus the
+// chunk prefix (cb[16 c + q]).  Chunks whose entries all lie in that block
+// (nearly all) need nothing else.
+__global__ __launch_bounds__(kBlock) void k_chunk_bases(const uint32_t* __restrict__ bkey,
+                                                        const uint32_t* __restrict__ used,
+                                                        const uint32_t* __restrict__ cpre,
+                                                        const uint32_t* __restrict__ tbase,
+                                                        uint32_t NB, int64_t max_chunks,
+                                                        uint32_t* __restrict__ cb) {
+    const int64_t n = *used;
+    const int64_t stride = chunk_stride(used);
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t c = g / kBlockSub;
+    const int q = (int)(g % kBlockSub);
+    if (c >= max_chunks || c * kChunk >= n) return;
+    const uint32_t B0 = bkey[c * kChunk];
+    if (B0 < NB) cb[g] = tbase[(int64_t)B0 * kBlockSub + q] + cpre[(int64_t)q * stride + c];
+}
+
+// The tile lists: each block-list entry copied, as (pair | 4-bit mask << 28),
+// to every sub-tile of its block it touches, at the place the prefixes give.
+// One wave per chunk, four entries per lane, every load of the chunk (entries
+// and its sub-tiles' bases) issued at once; the running counts per sub-tile
+// are wave-uniform.
+__global__ __launch_bounds__(kBlock) void k_chunk_expand(
     const uint32_t* __restrict__ bkey, const uint32_t* __restrict__ pairs,
     const uint32_t* __restrict__ mlo, const uint32_t* __restrict__ mhi,
     const uint32_t* __restrict__ used, const uint32_t* __restrict__ tused,
-    const uint32_t* __restrict__ cpre, const uint32_t* __restrict__ tbase, uint32_t NB,
-    uint32_t* __restrict__ tids) {
-    __shared__ uint32_t s_wn[kChunkWaves][kBlockSub];
+    const uint32_t* __restrict__ cpre, const uint32_t* __restrict__ tbase,
+    const uint32_t* __restrict__ cb, uint32_t NB, uint32_t* __restrict__ tids) {
     if (*tused == 0u) return;  // nothing is written after an overflow
     const int64_t n = *used;
     const int64_t stride = chunk_stride(used);
-    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int lane = threadIdx.x % kWave;
     const uint64_t lt = lanemask_lt();
-    for (int64_t c = blockIdx.x; c * kChunk < n; c += gridDim.x) {
-        const int64_t j = c * kChunk + threadIdx.x;
-        uint64_t m = 0;
-        uint32_t B = NB;  // sentinel entries (unfilled slots) have B = NB and no mask
-        uint32_t pr = 0;
-        if (j < n) {
-            m = ((uint64_t)mhi[j] << 32) | mlo[j];
-            B = bkey[j];
-            pr = pairs[j];
-        }
-        if (B >= NB) m = 0;
-        uint64_t bal[kBlockSub];
+    const int64_t nw = (int64_t)gridDim.x * kWaves;
+    for (int64_t c = (int64_t)blockIdx.x * kWaves + threadIdx.x / kWave; c * kChunk < n; c += nw) {
+        uint64_t m[kChunkSteps];
+        uint32_t B[kChunkSteps], pr[kChunkSteps];
 #pragma unroll
-        for (int q = 0; q < kBlockSub; q++) {
-            bal[q] = __ballot(touches(m, q));
-            if (lane == q) s_wn[w][q] = (uint32_t)__popcll(bal[q]);
+        for (int u = 0; u < kChunkSteps; u++) {
+            const int64_t j = c * kChunk + u * kWave + lane;
+            const int64_t jc = min(j, n - 1);  // unconditional loads, dropped past the end
+            const uint64_t mm = ((uint64_t)mhi[jc] << 32) | mlo[jc];
+            B[u] = bkey[jc];
+            pr[u] = pairs[jc];
+            // sentinel entries (unfilled slots) have B = NB and no mask
+            m[u] = (j < n && B[u] < NB) ? mm : 0ull;
         }
-        __syncthreads();
-        // entries of earlier waves of the chunk touching sub-tile q: lane q holds it
-        uint32_t woff = 0;
-        if (lane < kBlockSub)
-            for (int u = 0; u < w; u++) woff += s_wn[u][lane];
-        const uint64_t live = __ballot(m != 0);
-        if (live) {
-            // every sub-tile's list base first (all loads in flight together),
-            // the stores after: one scalar load each when the wave's entries
-            // share one block (the usual case), a gather each otherwise
-            const uint32_t B0 = (uint32_t)__builtin_amdgcn_readlane((int)B, __builtin_ctzll(live));
-            if (__ballot(m != 0 && B != B0) == 0) {
-                // the usual case, the wave's entries share one block: lane q
-                // loads sub-tile q's base (list start - block-start prefix +
-                // chunk prefix + earlier waves), one readlane per sub-tile after
-                uint32_t vq = 0;
-                if (lane < kBlockSub)
-                    vq = tbase[(int64_t)B0 * kBlockSub + lane] + cpre[(int64_t)lane * stride + c] + woff;
+        const uint32_t cbq = cb[c * kBlockSub + (lane % kBlockSub)];
+        const uint32_t B0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)B[0]);
+        bool other = false;
+#pragma unroll
+        for (int u = 0; u < kChunkSteps; u++) other |= m[u] != 0 && B[u] != B0;
+        uint32_t run[kBlockSub];  // entries of the chunk so far touching sub-tile q
+#pragma unroll
+        for (int q = 0; q < kBlockSub; q++) run[q] = 0;
+        if (__ballot(other) == 0) {
+#pragma unroll
+            for (int u = 0; u < kChunkSteps; u++) {
 #pragma unroll
                 for (int q = 0; q < kBlockSub; q++) {
-                    if (bal[q] == 0) continue;  // wave-uniform
-                    const uint32_t m4 = tile_bits(m, q % kBlockTiles, q / kBlockTiles);
-                    const uint32_t bq = (uint32_t)__builtin_amdgcn_readlane((int)vq, q);
-                    if (m4) tids[bq + (uint32_t)__popcll(bal[q] & lt)] = pr | (m4 << kPairBits);
+                    const uint64_t bal = __ballot(touches(m[u], q));
+                    if (bal == 0) continue;  // wave-uniform
+                    const uint32_t m4 = tile_bits(m[u], q % kBlockTiles, q / kBlockTiles);
+                    const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)cbq, q) + run[q];
+                    if (m4) tids[base + (uint32_t)__popcll(bal & lt)] = pr[u] | (m4 << kPairBits);
+                    run[q] += (uint32_t)__popcll(bal);
                 }
-            } else {
-                // entries of several blocks: every base gathered per lane (all
-                // loads in flight together, the stores after)
-                const uint32_t Bq = m != 0 ? B : B0;
-                uint32_t base[kBlockSub];
+            }
+        } else {
+            // entries of several blocks: every base gathered per lane
 #pragma unroll
-                for (int q = 0; q < kBlockSub; q++)
-                    base[q] = tbase[(int64_t)Bq * kBlockSub + q] + cpre[(int64_t)q * stride + c];
+            for (int u = 0; u < kChunkSteps; u++) {
+                const uint32_t Bq = m[u] != 0 ? B[u] : B0;
 #pragma unroll
                 for (int q = 0; q < kBlockSub; q++) {
-                    if (bal[q] == 0) continue;  // wave-uniform
-                    const uint32_t m4 = tile_bits(m, q % kBlockTiles, q / kBlockTiles);
-                    const uint32_t wq = (uint32_t)__builtin_amdgcn_readlane((int)woff, q);
-                    if (m4) tids[base[q] + wq + (uint32_t)__popcll(bal[q] & lt)] = pr | (m4 << kPairBits);
+                    const uint64_t bal = __ballot(touches(m[u], q));
+                    if (bal == 0) continue;  // wave-uniform
+                    const uint32_t m4 = tile_bits(m[u], q % kBlockTiles, q / kBlockTiles);
+                    if (m4) {
+                        const uint32_t base = tbase[(int64_t)Bq * kBlockSub + q] +
+                                              cpre[(int64_t)q * stride + c] + run[q];
+                        tids[base + (uint32_t)__popcll(bal & lt)] = pr[u] | (m4 << kPairBits);
+                    }
+                    run[q] += (uint32_t)__popcll(bal);
                 }
             }
         }
-        __syncthreads();
     }
 }
 
@@ -611,8 +632,9 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
             uint32_t* ttotal = c->scalars + 2;
             uint32_t* tused = c->scalars + 3;
             const int64_t nch = c->nchunks;
-            const unsigned gch = (unsigned)std::min<int64_t>(nch, 16384);
-            hipLaunchKernelGGL(k_chunk_count, dim3(gch), dim3(kChunk), 0, st, bmlo, bmhi, used, c->ccnt);
+            // one wave per chunk, grid-stride beyond 32768 waves
+            const unsigned gch = (unsigned)std::min<int64_t>((nch + kWaves - 1) / kWaves, 8192);
+            hipLaunchKernelGGL(k_chunk_count, dim3(gch), dim3(kBlock), 0, st, bmlo, bmhi, used, c->ccnt);
             if ((e = exclusive_scan_u32_dev(c->ccnt, kBlockSub * (nch + 1), used, kChunk, kBlockSub, 1,
                                             nullptr, c->scan_scratch, c->diag + kDiagFlags, st)) != hipSuccess)
                 return e;
@@ -628,8 +650,11 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
             const unsigned gt = (unsigned)((T + kBlock - 1) / kBlock);
             hipLaunchKernelGGL(k_tile_ranges, dim3(gt), dim3(kBlock), 0, st, c->tcnt, ttotal, tused, vt,
                                rp.tile_h, T, c->bpre, c->tranges, c->tbase);
-            hipLaunchKernelGGL(k_chunk_expand, dim3(gch), dim3(kChunk), 0, st, c->ik[side2], bpair, bmlo,
-                               bmhi, used, tused, c->ccnt, c->tbase, (uint32_t)NB, c->tids);
+            hipLaunchKernelGGL(k_chunk_bases, dim3((unsigned)((nch * kBlockSub + kBlock - 1) / kBlock)),
+                               dim3(kBlock), 0, st, c->ik[side2], used, c->ccnt, c->tbase, (uint32_t)NB, nch,
+                               c->cbase);
+            hipLaunchKernelGGL(k_chunk_expand, dim3(gch), dim3(kBlock), 0, st, c->ik[side2], bpair, bmlo,
+                               bmhi, used, tused, c->ccnt, c->tbase, c->cbase, (uint32_t)NB, c->tids);
         }
         if (tile_order && T > 0 && T <= ((int64_t)1 << 20)) {
             hipLaunchKernelGGL(k_tile_bucket, dim3((unsigned)((T + kBlock - 1) / kBlock)), dim3(kBlock),

@@ -179,6 +179,7 @@ gs_status gs_ctx_create(gs_ctx** out, const gs_capacity* cap) {
     A(dalloc(&c.tcnt, (size_t)T));
     c.nchunks = I / 256 + 1;
     A(dalloc(&c.ccnt, (size_t)16 * (c.nchunks + 1)));
+    A(dalloc(&c.cbase, (size_t)16 * c.nchunks));
     A(dalloc(&c.bpre, (size_t)16 * T));
     A(dalloc(&c.bplace, (size_t)T));
     A(dalloc(&c.tbase, (size_t)16 * T));
@@ -223,7 +224,7 @@ gs_status gs_ctx_destroy(gs_ctx* h) {
     if (!h) return GS_ERR_INVALID_ARG;
     gs::Ctx& c = h->c;
     void* ptrs[] = {c.rec, c.grad2d, c.cnt, c.off, c.pk[0], c.pk[1], c.pv[0], c.pv[1],
-                    c.ik[0], c.ik[1], c.iv[0], c.iv[1], c.im[0], c.im[1], c.tcnt, c.ccnt, c.bpre, c.bplace, c.tbase, c.tranges, c.tids,
+                    c.ik[0], c.ik[1], c.iv[0], c.iv[1], c.im[0], c.im[1], c.tcnt, c.ccnt, c.cbase, c.bpre, c.bplace, c.tbase, c.tranges, c.tids,
                     c.ranges, c.tile_order, c.tk[0], c.tk[1], c.tile_contrib, c.tile_entries, c.tile_evals, c.hist,
                     c.scan_scratch, c.scalars, c.twist_render, c.twist_track, c.loss_acc, c.diag};
     hipDeviceSynchronize();

@@ -406,6 +406,7 @@ struct Ctx {
     uint32_t* tcnt;        // [max_tiles] tile list lengths, then their scan
     uint32_t* ccnt;        // [16][ceil(used / 256) + 1] sub-tile counts per 256-entry chunk, then their scan
     int64_t nchunks;       // max_isect / 256 + 1
+    uint32_t* cbase;       // [nchunks][16] list place of each chunk's first entry per sub-tile
     uint32_t* bpre;        // [max_tiles][16] sub-tile prefixes at each block's list start
     int4* bplace;          // [max_tiles] first tile, row stride, tiles across / down per block
     uint32_t* tbase;       // [max_tiles][16] tile start - prefix at the block start
