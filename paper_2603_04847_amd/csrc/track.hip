@@ -1,9 +1,12 @@
 // Track reprojection residual, Huber loss and their gradients / Jacobian blocks.
 //
-// One thread per observation.  Observations arrive sorted by camera, so most
-// waves see a single camera: their twist gradients are summed over the wave
-// (DPP) and land in one double atomic per component; a wave that straddles a
-// camera boundary falls back to per-lane atomics.  Track-point gradients are
+// One thread per observation; each workgroup walks one contiguous range of
+// observations.  Observations arrive sorted by camera, so a wave sees the same
+// camera for many steps: it keeps per-lane twist sums while the camera stays
+// and adds them (one wave sum, one double atomic per component) only when the
+// camera changes and at the end, which keeps the atomics on each camera's six
+// words few.  A step whose lanes straddle a camera boundary uses per-lane
+// atomics.  Track-point gradients are
 // scattered with three float atomics per observation (points are spread, so
 // these rarely collide).
 #include <algorithm>
@@ -30,11 +33,26 @@ __global__ __launch_bounds__(kBlock) void k_track(
     const int lane = __lane_id();
     float lo_sum = 0.f;
     uint32_t n_masked = 0;
-    // grid-stride: block-level sums of the loss and the masked count end in one
-    // atomic per block; the twist is summed per wave (mostly one camera each)
-    for (int base = blockIdx.x * kBlock; base < M; base += gridDim.x * kBlock) {
+    // this workgroup's range, a multiple of the workgroup size long
+    const int per = ((M + (int)gridDim.x - 1) / (int)gridDim.x + kBlock - 1) / kBlock * kBlock;
+    const int lo = (int)min((int64_t)blockIdx.x * per, (int64_t)M);
+    const int hi = min(lo + per, M);
+    float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // lane sums for camera `cur`
+    int cur = -1;                                   // wave-uniform
+    auto flush = [&]() {
+        if (cur >= 0) {
+#pragma unroll
+            for (int e = 0; e < 6; e++) {
+                const float s = wave_sum(acc[e]);
+                if (lane == e && s != 0.f) atomicAdd(twist_acc + 6 * (int64_t)cur + e, (double)s);
+                acc[e] = 0.f;
+            }
+        }
+    };
+    // block-level sums of the loss and the masked count end in one atomic per block
+    for (int base = lo; base < hi; base += kBlock) {
     const int o = base + threadIdx.x;
-    const bool in = o < M;
+    const bool in = o < hi;
     int ci = 0, k = 0;
     if (in) {
         ci = obs_cam[o];
@@ -132,17 +150,19 @@ __global__ __launch_bounds__(kBlock) void k_track(
         const int c0 = bcast(ci, first);
         const bool uniform = __ballot(ok_idx && !masked && ci != c0) == 0;
         if (uniform) {
-#pragma unroll
-            for (int e = 0; e < 6; e++) {
-                const float s = wave_sum(tw[e]);
-                if (lane == e && s != 0.f) atomicAdd(twist_acc + 6 * (int64_t)c0 + e, (double)s);
+            if (c0 != cur) {
+                flush();
+                cur = c0;
             }
+#pragma unroll
+            for (int e = 0; e < 6; e++) acc[e] += tw[e];
         } else if (ok_idx && !masked) {
 #pragma unroll
             for (int e = 0; e < 6; e++) atomicAdd(twist_acc + 6 * (int64_t)ci + e, (double)tw[e]);
         }
     }
     }
+    flush();
     const float ls = wave_sum(lo_sum);
     uint32_t nm = n_masked;
     for (int off = 32; off > 0; off >>= 1) nm += __shfl_xor(nm, off, kWave);
