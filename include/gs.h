@@ -87,6 +87,8 @@ typedef enum {
 #define GS_FLAG_NONFINITE 2u        /* a non-finite projected splat was culled */
 #define GS_FLAG_SCAN_STALLED 4u     /* a device-wide scan stopped waiting for a preceding
                                        workgroup (bounded wait); that step's lists are invalid */
+#define GS_FLAG_COUNT_BOUND 8u      /* internal check: a pair met more blocks than the bound its
+                                       slots were sized by; that step's lists are incomplete */
 
 /* Most views one render call takes. */
 #define GS_MAX_VIEWS 64

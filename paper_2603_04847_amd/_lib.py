@@ -20,6 +20,7 @@ GS_ERR = {-1: "GS_ERR_INVALID_ARG", -2: "GS_ERR_CAPACITY", -3: "GS_ERR_HIP",
 GS_FLAG_ISECT_OVERFLOW = 1
 GS_FLAG_NONFINITE = 2
 GS_FLAG_SCAN_STALLED = 4
+GS_FLAG_COUNT_BOUND = 8
 GS_MAX_VIEWS = 64
 GS_RECORD_FLOATS = 12
 GS_GRAD2D_FLOATS = 9

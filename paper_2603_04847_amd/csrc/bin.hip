@@ -1,15 +1,17 @@
 // Tile binning and key sort, kept per block of 4 x 4 tiles.
 //
-//  1. count:   per pair, the blocks its alpha >= alpha_min ellipse meets (one
-//              block row at a time, from the ellipse's x-span in each quadrant
-//              row), and its depth key (float32 depth bits; positive floats
-//              order like their bits).  Culled pairs get key 0xFFFFFFFF and no
-//              blocks.
+//  1. count:   per pair, an upper bound of the blocks its alpha >= alpha_min
+//              ellipse meets (one block row at a time, from the ellipse's
+//              x-span over the row's whole band), and its depth key (float32
+//              depth bits; positive floats order like their bits).  Culled
+//              pairs get key 0xFFFFFFFF and no blocks.
 //  2. sort the pairs by depth key (stable LSD radix from pair order, so equal
 //     depths stay in pair order): this is the (depth, pair) order.
 //  3. scan the block counts in that order and emit one (block, pair, 64-bit
-//     quadrant mask) entry per block met; entries of one pair are contiguous,
-//     pairs in depth order.
+//     quadrant mask) entry per block met, from the exact per-quadrant-row
+//     spans; entries of one pair are contiguous, pairs in depth order, and the
+//     slots the bound over-counts (at the end of each wave's range) get a
+//     sentinel block id that sorts after every block.
 //  4. stable radix sort of the entries on the block id only: inside every block
 //     the depth order of step 2 survives, so each block list ends up in
 //     ascending (depth, pair) order without sorting on depth again.
@@ -109,12 +111,12 @@ __global__ __launch_bounds__(kBlock) void k_count(const float4* __restrict__ rec
     wave_units_load(wu, lane, ok, a, b, v, vt, rp, U);
     s_cnt[w][lane] = 0;
     __syncthreads();
+    // an upper bound per unit (the emit pass fills what it over-counts)
     for (uint32_t j = lane; j < U; j += kWave) {
         const int q = seg_search(wu.upre, kWave, j);
         const int vq = wu.v[q];
         const int br = wu.sp[q].r0 / kBlockQuads + (int)(j - wu.upre[q]);
-        const BlockUnit u = block_unit(wu.sp[q], br, vt.W[vq], vt.H[vq], qg);
-        const int n = block_unit_count(u);
+        const int n = unit_band_count(wu.sp[q], br, vt.W[vq], vt.H[vq], qg);
         if (n) atomicAdd(&s_cnt[w][q], (uint32_t)n);
     }
     __syncthreads();
@@ -172,7 +174,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(const float4* __restrict__ rec,
                                                  uint32_t* __restrict__ okey,
                                                  uint32_t* __restrict__ opair,
                                                  uint32_t* __restrict__ omlo,
-                                                 uint32_t* __restrict__ omhi) {
+                                                 uint32_t* __restrict__ omhi,
+                                                 uint32_t* __restrict__ diag) {
     __shared__ WaveUnits s_wu[kWaves];
     __shared__ uint32_t s_pair[kWaves][kWave];
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -205,6 +208,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(const float4* __restrict__ rec,
     s_pair[w][lane] = pair;
     __syncthreads();
     uint32_t done = 0;  // entries of the wave written so far
+    bool bound_broken = false;
     for (uint32_t ub = 0; ub < U; ub += kWave) {
         const uint32_t j = ub + lane;
         BlockUnit u;
@@ -233,20 +237,24 @@ __global__ __launch_bounds__(kBlock) void k_emit(const float4* __restrict__ rec,
                     opair[base + o] = pq;
                     omlo[base + o] = (uint32_t)m;
                     omhi[base + o] = (uint32_t)(m >> 32);
+                } else {
+                    bound_broken = true;
                 }
                 o++;
             }
         }
         done += rt;
     }
-    // slots not filled (only if the two passes ever disagreed) get a sentinel
-    // block id past every block, so no list ever sees stale entries
+    // slots the count's bound left over get a sentinel block id past every
+    // block and no mask, so no list ever reads them
     for (uint32_t o = done + lane; o < wave_total; o += kWave) {
         okey[base + o] = (uint32_t)vt.block_off[vt.V];
         opair[base + o] = s_pair[w][0];
         omlo[base + o] = 0;
         omhi[base + o] = 0;
     }
+    // the bound must hold; if it ever did not, entries were dropped: say so
+    if (bound_broken) atomicOr(&diag[kDiagFlags], (uint32_t)GS_FLAG_COUNT_BOUND);
 }
 
 // block ranges from the boundaries of the sorted keys, four keys per thread
@@ -612,7 +620,7 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
                            c->diag, nullptr, nullptr);
         const int64_t I = c->cap.max_isect;
         hipLaunchKernelGGL(k_emit, dim3(gp), dim3(kBlock), 0, st, rec, N, vt, rp, order, c->off,
-                           c->cnt, npairs, used, c->ik[0], c->iv[0], c->im[0], c->im[0] + I);
+                           c->cnt, npairs, used, c->ik[0], c->iv[0], c->im[0], c->im[0] + I, c->diag);
         int bbits = 1;  // block ids and the sentinel NB
         while (((int64_t)1 << bbits) <= NB) bbits++;
         // the pair and both mask words travel with the block key

@@ -316,6 +316,36 @@ __device__ __forceinline__ int block_unit_count(const BlockUnit& u) {
     return n;
 }
 
+// Upper bound of a unit's entries, for sizing only: the block columns met by
+// the ellipse over the unit's whole band of quadrant rows (one x-span instead
+// of eight).  The band covers every row's pixel-centre range, and the minimum
+// (maximum) of a convex (concave) boundary over a larger interval is no larger
+// (smaller), so the band's columns contain each row's; kBandEps absorbs the
+// rounding of the two evaluations.  The emit pass fills slots the bound
+// over-counts with entries that no list reads.
+constexpr float kBandEps = 0.125f;
+
+__device__ __forceinline__ int unit_band_count(const SplatSpan& s, int br, int W, int H,
+                                               const QuadGrid& g) {
+#pragma clang fp contract(off)
+    const int ra = max(s.r0, kBlockQuads * br), rb = min(s.r1, kBlockQuads * br + kBlockQuads - 1);
+    if (ra > rb) return 0;
+    const float ya = ra * g.hh + 0.5f, yb = (float)min(rb * g.hh + g.hh, H) - 0.5f;
+    float la = fmaxf(ya - s.my, -s.ey), lb = fminf(yb - s.my, s.ey);
+    if (la > lb + kSpanEps) return 0;
+    if (la > lb) la = lb = 0.5f * (la + lb);
+    const float dl = fminf(fmaxf(s.dyL, la), lb), dr = fminf(fmaxf(-s.dyL, la), lb);
+    const float ql = __builtin_amdgcn_sqrtf(fmaxf(s.t2A - s.det * dl * dl, 0.f));
+    const float qr = __builtin_amdgcn_sqrtf(fmaxf(s.t2A - s.det * dr * dr, 0.f));
+    const float xl = s.mx + (-s.B * dl - ql) * s.iA - (kSpanEps + kBandEps);
+    const float xr = s.mx + (-s.B * dr + qr) * s.iA + (kSpanEps + kBandEps);
+    if (!(xl <= (float)W - 0.5f) || !(xr >= 0.5f)) return 0;
+    const int ncols = (W + g.hw - 1) / g.hw;
+    const int c0 = max((int)ceilf((xl + 0.5f) * g.ihw - 1.f), 0);
+    const int c1 = min((int)floorf((xr - 0.5f) * g.ihw), ncols - 1);
+    return c0 <= c1 ? c1 / kBlockQuads - c0 / kBlockQuads + 1 : 0;
+}
+
 // ------------------------------------------------------------------ host launchers
 
 ViewTable make_view_table(const int32_t* wh, int V, int TW, int TH, const int32_t* index = nullptr);
