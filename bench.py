@@ -8,6 +8,10 @@ composition, projection, bin/sort, compositing, L1, raster and projection
 backward, track reprojection, the twist chain and Adam.  Inputs are seeded
 synthetic scenes resident in HBM before the timed region.
 
+The timed steps are replayed from captured HIP graphs (one per batch of
+views, every kernel of the step); the same steps run eagerly, call by call,
+are reported beside them and give the per-call breakdown.
+
 Also reported: a per-call breakdown (HIP events on the launch stream), the
 roofline of the dominant kernel, the batched-vs-per-view comparison on the
 8-view uneven-resolution scene (3M Gaussians), and the FP64 oracle timed on a
@@ -154,6 +158,9 @@ def run_joint(torch, name, steps, warmup, tune=True, tile=None, order=0, graph=T
                 st.run(bb, step=st.step_count + 1)
             graphs.append(g)
         torch.cuda.synchronize()
+        for g in graphs:  # untimed first replays (graph upload)
+            g.replay()
+        torch.cuda.synchronize()
         a.record()
         for i in range(steps):
             graphs[i % len(batches)].replay()
@@ -161,6 +168,7 @@ def run_joint(torch, name, steps, warmup, tune=True, tile=None, order=0, graph=T
         torch.cuda.synchronize()
         graph_ms = a.elapsed_time(b_) / steps
         del graphs
+        status = st.ctx.status()  # flags of the eager and the replayed steps
     except Exception as e:  # report, do not hide
         log(f"[bench] graph replay failed: {e!r}")
     # workload sizes for the roofline (outside the timed region; the forward's
@@ -338,7 +346,8 @@ def cpu_baseline(res, seconds_target=20.0):
     """The FP64 oracle on the host cores, on a bounded sample of the same
     workload: the projection and its backward for the batch's views, the track
     term over all observations, and compositing (with backward) of a random
-    sample of pixels; the compositing time is scaled to all pixels."""
+    sample of pixels; the compositing time is fitted over sample sizes and
+    taken at all pixels."""
     import oracle
     sc, b = res["sc"], res["batches"][0]
     st = res["st"]
@@ -351,17 +360,28 @@ def cpu_baseline(res, seconds_target=20.0):
     proj = oracle.project(sub)
     t_proj = time.time() - t0
     rng = np.random.default_rng(0)
-    # size the pixel sample from a calibration run
-    n_cal = 256
-    pix = rng.choice(sz["P"], size=n_cal, replace=False)
-    t0 = time.time()
-    oracle.render(proj, wh, pix=pix, v_rgb=np.ones((n_cal, 3)))
-    per_px = (time.time() - t0) / n_cal
-    n_pix = int(max(256, min(200000, 0.7 * seconds_target / max(per_px, 1e-9))))
-    pix = rng.choice(sz["P"], size=n_pix, replace=False)
-    t0 = time.time()
-    r = oracle.render(proj, wh, pix=pix, v_rgb=np.ones((n_pix, 3)))
-    t_pix = time.time() - t0
+    # the oracle's compositing time is a fixed part (per-view set-up) plus a
+    # part per pixel: two calibration sizes give the per-pixel cost, a third,
+    # larger sample (most of the time budget) the fit used for all pixels
+    def timed(n):
+        pix = rng.choice(sz["P"], size=n, replace=False)
+        t0 = time.time()
+        r = oracle.render(proj, wh, pix=pix, v_rgb=np.ones((n, 3)))
+        return time.time() - t0, r
+    timed(64)  # untimed: first-call set-up
+    n1, n2 = 256, 1024
+    t1, _ = timed(n1)
+    t2, _ = timed(n2)
+    # per-pixel cost for sizing: the marginal one, but never below half the
+    # mean (timing noise must not size a sample that runs for minutes)
+    b0 = max((t2 - t1) / (n2 - n1), 0.5 * t2 / n2, 1e-9)
+    n_pix = int(max(2 * n2, min(400000, 0.6 * seconds_target / b0)))
+    log(f"[bench] oracle: {n1} px {t1:.1f}s, {n2} px {t2:.1f}s; sampling {n_pix} px")
+    t_pix, r = timed(n_pix)
+    log(f"[bench] oracle: {n_pix} px {t_pix:.1f}s")
+    per_px = max((t_pix - t1) / (n_pix - n1), 1e-12)
+    fixed = max(t1 - per_px * n1, 0.0)
+    t_pix_all = fixed + per_px * sz["P"]
     t0 = time.time()
     oracle.project_bwd(sub, r["v2d"])
     t_pbwd = time.time() - t0
@@ -371,14 +391,15 @@ def cpu_baseline(res, seconds_target=20.0):
         oracle.track(sc["X"], st.viewmat.cpu().numpy(), sc["intr"], sc["obs_cam"], sc["obs_pt"],
                      sc["obs_xy"], jacobians=False)
         t_track = time.time() - t0
-    t_step = t_proj + t_pix * sz["P"] / n_pix + t_pbwd + t_track
+    t_step = t_proj + t_pix_all + t_pbwd + t_track
     return dict(value=round(sz["P"] / t_step / 1e6, 6), unit="MP/s", cores=oracle.num_threads(),
                 kind="oracle",
                 sample=(f"batch 0 of the workload: projection + its backward of {sz['V']} views x "
                         f"{sz['N']} Gaussians, track term over {sz['M']} observations, and "
                         f"compositing + backward of {n_pix} random pixels of {sz['P']} "
-                        f"(their time scaled by {sz['P'] / n_pix:.0f}); "
-                        f"measured {t_proj + t_pix + t_pbwd + t_track:.1f}s"))
+                        f"(its time fitted as {fixed:.2f}s + {per_px * 1e3:.3f} ms per pixel from "
+                        f"samples of {n1}, {n2} and {n_pix} pixels, then taken at all pixels); "
+                        f"measured {t_proj + t1 + t2 + t_pix + t_pbwd + t_track:.1f}s"))
 
 
 def main():
@@ -425,7 +446,10 @@ def main():
     res = run_joint(torch, args.workload, args.steps, args.warmup, tune=not args.no_tune,
                     tile=tile, order=args.order, graph=not args.no_graph)
     sz = res["sizes"]
-    ms = res["ms"]
+    # the timed steps: replayed from captured HIP graphs (the production mode:
+    # the same kernels, no per-call host work between them), else eager
+    ms_eager = res["ms"]
+    ms = res["graph_ms"] if res["graph_ms"] is not None else ms_eager
     value = sz["P"] / ms / 1e3  # megapixels / s
     per_call = {k: round(v, 4) for k, v in res["per_call"].items()}
     alg = algorithmic_bytes(sz)
@@ -462,7 +486,8 @@ def main():
         "per_call_ms": per_call,
         "per_call_algorithmic_gbs": {k: round(alg[k] / (per_call[k] * 1e-3) / 1e9, 1)
                                      for k in per_call if k in alg},
-        "graph_ms_per_step": None if res["graph_ms"] is None else round(res["graph_ms"], 4),
+        "timed_as": "hip_graph_replay" if res["graph_ms"] is not None else "eager",
+        "eager_ms_per_step": round(ms_eager, 4),
         "autotune": res["tuning"],
         "sizes": {k: int(v) for k, v in sz.items()},
     }

@@ -281,18 +281,21 @@ __device__ __forceinline__ BlockUnit block_unit(const SplatSpan& s, int br, int 
 }
 
 // The block mask of unit u in block column bc (0: the splat misses the block).
+// Row i's byte is the run of quadrant columns [c0 - q0, c1 - q0] clipped to
+// [0, 7], built without branches: (0xFF << lo) & (0xFF >> (7 - hi)) with lo
+// clamped to [0, 8] and hi to [-1, 7] is empty whenever lo > hi.
 __device__ __forceinline__ uint64_t block_unit_mask(const BlockUnit& u, int bc) {
-    uint64_t m = 0;
     const int q0 = kBlockQuads * bc;
+    uint32_t lo32 = 0, hi32 = 0;
 #pragma unroll
     for (int i = 0; i < kBlockQuads; i++) {
-        const int lo = max(u.c0[i], q0), hi = min(u.c1[i], q0 + kBlockQuads - 1);
-        if (lo <= hi) {
-            const uint64_t run = ((1ull << (hi - lo + 1)) - 1ull) << (lo - q0);
-            m |= run << (kBlockQuads * i);
-        }
+        const int lo = min(max(u.c0[i] - q0, 0), 8);
+        const int hi = min(max(u.c1[i] - q0, -1), 7);
+        const uint32_t byte = (0xFFu << lo) & (0xFFu >> (7 - hi));
+        if (i < 4) lo32 |= byte << (8 * i);
+        else hi32 |= byte << (8 * (i - 4));
     }
-    return m;
+    return ((uint64_t)hi32 << 32) | lo32;
 }
 
 // Entries of a unit: block columns met by some row (a row meets the block
