@@ -141,6 +141,7 @@ def run_joint(torch, name, steps, warmup, tune=True, tile=None, order=0, graph=T
     status = st.ctx.status()
     # the same steps replayed from captured HIP graphs (one per batch)
     graph_ms = None
+    step_ms = None
     try:
         if not graph:
             raise RuntimeError("graph replay skipped (--no-graph)")
@@ -161,12 +162,16 @@ def run_joint(torch, name, steps, warmup, tune=True, tile=None, order=0, graph=T
         for g in graphs:  # untimed first replays (graph upload)
             g.replay()
         torch.cuda.synchronize()
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
         a.record()
+        evs[0].record()
         for i in range(steps):
             graphs[i % len(batches)].replay()
+            evs[i + 1].record()
         b_.record()
         torch.cuda.synchronize()
         graph_ms = a.elapsed_time(b_) / steps
+        step_ms = [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)]
         del graphs
         status = st.ctx.status()  # flags of the eager and the replayed steps
     except Exception as e:  # report, do not hide
@@ -196,7 +201,7 @@ def run_joint(torch, name, steps, warmup, tune=True, tile=None, order=0, graph=T
                  M=int(st.obs_cam.shape[0]), Pt=int(st.X.shape[0]),
                  n_params=int(sum(v.numel() for v in st._opt_params().values())),
                  n_adam=int(st.twist.numel() + st.X.numel()))
-    return dict(ms=ms, graph_ms=graph_ms, per_call=per_call, status=status, sizes=sizes, st=st,
+    return dict(ms=ms, graph_ms=graph_ms, step_ms=step_ms, per_call=per_call, status=status, sizes=sizes, st=st,
                 sc=sc, batches=batches, tuning=tuning)
 
 
@@ -340,6 +345,26 @@ def batched_vs_per_view(torch, steps, warmup):
     out["n_isect"] = int(need)
     ctx.close()
     return out
+
+
+def copy_bandwidth(torch, mib=1024, reps=5):
+    """Device copy rate (GB/s, bytes read + written) of a plain elementwise
+    copy of `mib` MiB, beside the 8 TB/s HBM peak."""
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, device="cuda")
+    y = torch.empty_like(x)
+    torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        torch.mul(x, 1.0, out=y)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del x, y
+    return round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)
 
 
 def cpu_baseline(res, seconds_target=20.0):
@@ -488,6 +513,14 @@ def main():
                                      for k in per_call if k in alg},
         "timed_as": "hip_graph_replay" if res["graph_ms"] is not None else "eager",
         "eager_ms_per_step": round(ms_eager, 4),
+        "step_ms_p10_p50_p90": (None if res["step_ms"] is None else
+                                [round(float(np.percentile(res["step_ms"], q)), 4) for q in (10, 50, 90)]),
+        # the raster kernels are VALU-bound: their algorithmic rate against the FP32 peak
+        "raster_alu_tflops": {k: round(algorithmic_flops(sz, k) / (per_call[k] * 1e-3) / 1e12, 2)
+                              for k in ALU_KERNELS if k in per_call},
+        # track reprojection (a9) as a share of the step (the paper quotes about 3 %)
+        "track_share": (round(per_call["track"] / res["ms"], 4) if "track" in per_call else None),
+        "copy_gbs": copy_bandwidth(torch),
         "autotune": res["tuning"],
         "sizes": {k: int(v) for k, v in sz.items()},
     }
