@@ -100,9 +100,11 @@ __device__ __forceinline__ Cam load_cam(const float* __restrict__ viewmat,
     return c;
 }
 
-// Per-Gaussian quantities that do not depend on the view.
+// Per-Gaussian quantities that do not depend on the view.  The covariance
+// and everything the EWA step derives from it are formed per view in double
+// precision (see project_one), from the raw parameters kept here.
 struct GaussLocal {
-    float mu[3], qn[4], qnorm, s[3], Rq[9], Sig[6];  // Sig: 00 01 02 11 12 22
+    float mu[3], q[4], s[3];
     float o;
 };
 
@@ -110,56 +112,48 @@ __device__ __forceinline__ void load_gaussian(const gs_gaussians& g, int i, Gaus
     const int N = g.N;
 #pragma unroll
     for (int k = 0; k < 3; k++) G.mu[k] = g.means[k * N + i];
-    float q[4];
 #pragma unroll
-    for (int k = 0; k < 4; k++) q[k] = g.quats[k * N + i];
-    G.qnorm = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-    const float inv = 1.f / G.qnorm;
-#pragma unroll
-    for (int k = 0; k < 4; k++) G.qn[k] = q[k] * inv;
-    const float w = G.qn[0], x = G.qn[1], y = G.qn[2], z = G.qn[3];
-    G.Rq[0] = 1.f - 2.f * (y * y + z * z);
-    G.Rq[1] = 2.f * (x * y - w * z);
-    G.Rq[2] = 2.f * (x * z + w * y);
-    G.Rq[3] = 2.f * (x * y + w * z);
-    G.Rq[4] = 1.f - 2.f * (x * x + z * z);
-    G.Rq[5] = 2.f * (y * z - w * x);
-    G.Rq[6] = 2.f * (x * z - w * y);
-    G.Rq[7] = 2.f * (y * z + w * x);
-    G.Rq[8] = 1.f - 2.f * (x * x + y * y);
+    for (int k = 0; k < 4; k++) G.q[k] = g.quats[k * N + i];
 #pragma unroll
     for (int k = 0; k < 3; k++) G.s[k] = __expf(g.log_scales[k * N + i]);
-    float M[9];
-#pragma unroll
-    for (int r = 0; r < 3; r++)
-#pragma unroll
-        for (int c = 0; c < 3; c++) M[3 * r + c] = G.Rq[3 * r + c] * G.s[c];
-    G.Sig[0] = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
-    G.Sig[1] = M[0] * M[3] + M[1] * M[4] + M[2] * M[5];
-    G.Sig[2] = M[0] * M[6] + M[1] * M[7] + M[2] * M[8];
-    G.Sig[3] = M[3] * M[3] + M[4] * M[4] + M[5] * M[5];
-    G.Sig[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
-    G.Sig[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
     G.o = 1.f / (1.f + __expf(-g.opacity_logit[i]));
 }
 
-__device__ __forceinline__ float sym(const float* S, int i, int j) {
+__device__ __forceinline__ double symd(const double* S, int i, int j) {
     // symmetric 3x3 stored as 00 01 02 11 12 22
     const int a = min(i, j), b = max(i, j);
     return a == 0 ? S[b] : (a == 1 ? S[2 + b] : S[5]);
 }
 
-// Per-(view, Gaussian) projection state, recomputed identically in the backward.
+// View direction (unit) and distance from the camera centre -R^T t to the mean.
+__device__ __forceinline__ void view_dir(const GaussLocal& G, const Cam& cam, float* dir, float& dist) {
+    float cc[3];
+#pragma unroll
+    for (int j = 0; j < 3; j++)
+        cc[j] = -(cam.R[j] * cam.t[0] + cam.R[3 + j] * cam.t[1] + cam.R[6 + j] * cam.t[2]);
+    const float d[3] = {G.mu[0] - cc[0], G.mu[1] - cc[1], G.mu[2] - cc[2]};
+    dist = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const float id = 1.f / dist;
+#pragma unroll
+    for (int j = 0; j < 3; j++) dir[j] = d[j] * id;
+}
+
+// Per-(view, Gaussian) projection state, recomputed identically in the
+// backward.  The EWA chain runs in double: for needle-like splats the 2D
+// covariance and its inverse are ill-conditioned (eigenvalue ratios of 1e5
+// and more), and in float the conic's small eigenvalue, and the gradients that
+// project onto the needle's axis, lose most of their digits.
 struct Proj {
     bool valid;
-    float p[3];
-    float Sc[6];          // camera covariance (sym)
+    double p[3];
+    double qn[4], qnorm;  // unit quaternion and the raw norm
+    float Rq[9];          // its rotation (rounded from double)
+    double Sc[6];         // camera covariance (sym)
     float J00, J02, J11, J12;
     bool clx, cly;
     float tx, ty;         // clamped x/z, y/z
-    float a, b, c;        // cov2d
-    float A, B, C;        // conic
-    float mx, my;
+    double A, B, C;       // conic
+    double mx, my;
     float dir[3], dist;
 };
 
@@ -168,59 +162,83 @@ __device__ __forceinline__ void project_one(const GaussLocal& G, const Cam& cam,
     P.valid = false;
 #pragma unroll
     for (int i = 0; i < 3; i++)
-        P.p[i] = cam.R[3 * i] * G.mu[0] + cam.R[3 * i + 1] * G.mu[1] + cam.R[3 * i + 2] * G.mu[2] +
-                 cam.t[i];
-    // view direction from the camera centre -R^T t
-    float cc[3];
-#pragma unroll
-    for (int j = 0; j < 3; j++)
-        cc[j] = -(cam.R[j] * cam.t[0] + cam.R[3 + j] * cam.t[1] + cam.R[6 + j] * cam.t[2]);
-    float d[3] = {G.mu[0] - cc[0], G.mu[1] - cc[1], G.mu[2] - cc[2]};
-    P.dist = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    const float id = 1.f / P.dist;
-#pragma unroll
-    for (int j = 0; j < 3; j++) P.dir[j] = d[j] * id;
-    const float z = P.p[2];
+        P.p[i] = (double)cam.R[3 * i] * G.mu[0] + (double)cam.R[3 * i + 1] * G.mu[1] +
+                 (double)cam.R[3 * i + 2] * G.mu[2] + cam.t[i];
+    // view direction from the camera centre (the colour's input: float)
+    view_dir(G, cam, P.dir, P.dist);
+    const double z = P.p[2];
     if (!(z >= rp.near_plane)) return;
-    // Sc = R Sig R^T
-    float RS[9];
+    // rotation of the unit quaternion (w, x, y, z)
+    P.qnorm = sqrt((double)G.q[0] * G.q[0] + (double)G.q[1] * G.q[1] + (double)G.q[2] * G.q[2] +
+                   (double)G.q[3] * G.q[3]);
+    const double inv = 1.0 / P.qnorm;
+#pragma unroll
+    for (int k = 0; k < 4; k++) P.qn[k] = G.q[k] * inv;
+    double Rq[9];
+    {
+        const double w = P.qn[0], x = P.qn[1], y = P.qn[2], zq = P.qn[3];
+        Rq[0] = 1.0 - 2.0 * (y * y + zq * zq);
+        Rq[1] = 2.0 * (x * y - w * zq);
+        Rq[2] = 2.0 * (x * zq + w * y);
+        Rq[3] = 2.0 * (x * y + w * zq);
+        Rq[4] = 1.0 - 2.0 * (x * x + zq * zq);
+        Rq[5] = 2.0 * (y * zq - w * x);
+        Rq[6] = 2.0 * (x * zq - w * y);
+        Rq[7] = 2.0 * (y * zq + w * x);
+        Rq[8] = 1.0 - 2.0 * (x * x + y * y);
+    }
+#pragma unroll
+    for (int k = 0; k < 9; k++) P.Rq[k] = (float)Rq[k];
+    // Sc = (R Rq S)(R Rq S)^T
+    double RM[9];  // R Rq S
 #pragma unroll
     for (int i = 0; i < 3; i++)
 #pragma unroll
         for (int j = 0; j < 3; j++)
-            RS[3 * i + j] = cam.R[3 * i] * sym(G.Sig, 0, j) + cam.R[3 * i + 1] * sym(G.Sig, 1, j) +
-                            cam.R[3 * i + 2] * sym(G.Sig, 2, j);
+            RM[3 * i + j] = ((double)cam.R[3 * i] * Rq[j] + (double)cam.R[3 * i + 1] * Rq[3 + j] +
+                             (double)cam.R[3 * i + 2] * Rq[6 + j]) * G.s[j];
     int k = 0;
 #pragma unroll
     for (int i = 0; i < 3; i++)
 #pragma unroll
         for (int j = i; j < 3; j++)
-            P.Sc[k++] = RS[3 * i] * cam.R[3 * j] + RS[3 * i + 1] * cam.R[3 * j + 1] +
-                        RS[3 * i + 2] * cam.R[3 * j + 2];
-    const float iz = 1.f / z;
-    const float lxp = (W - cam.cx) / cam.fx + rp.fov_pad * 0.5f * W / cam.fx;
-    const float lxn = cam.cx / cam.fx + rp.fov_pad * 0.5f * W / cam.fx;
-    const float lyp = (H - cam.cy) / cam.fy + rp.fov_pad * 0.5f * H / cam.fy;
-    const float lyn = cam.cy / cam.fy + rp.fov_pad * 0.5f * H / cam.fy;
-    const float rx = P.p[0] * iz, ry = P.p[1] * iz;
-    P.tx = fminf(fmaxf(rx, -lxn), lxp);
-    P.ty = fminf(fmaxf(ry, -lyn), lyp);
+            P.Sc[k++] = RM[3 * i] * RM[3 * j] + RM[3 * i + 1] * RM[3 * j + 1] + RM[3 * i + 2] * RM[3 * j + 2];
+    const double iz = 1.0 / z;
+    const double lxp = ((double)W - cam.cx) / cam.fx + rp.fov_pad * 0.5 * W / cam.fx;
+    const double lxn = (double)cam.cx / cam.fx + rp.fov_pad * 0.5 * W / cam.fx;
+    const double lyp = ((double)H - cam.cy) / cam.fy + rp.fov_pad * 0.5 * H / cam.fy;
+    const double lyn = (double)cam.cy / cam.fy + rp.fov_pad * 0.5 * H / cam.fy;
+    const double rx = P.p[0] * iz, ry = P.p[1] * iz;
+    const double tx = fmin(fmax(rx, -lxn), lxp), ty = fmin(fmax(ry, -lyn), lyp);
+    P.tx = (float)tx;
+    P.ty = (float)ty;
     P.clx = (rx > lxp) || (rx < -lxn);
     P.cly = (ry > lyp) || (ry < -lyn);
-    P.J00 = cam.fx * iz;
-    P.J02 = -cam.fx * P.tx * iz;
-    P.J11 = cam.fy * iz;
-    P.J12 = -cam.fy * P.ty * iz;
-    const float* S = P.Sc;  // 00 01 02 11 12 22
-    P.a = P.J00 * P.J00 * S[0] + 2.f * P.J00 * P.J02 * S[2] + P.J02 * P.J02 * S[5] + rp.eps2d;
-    P.b = P.J00 * P.J11 * S[1] + P.J00 * P.J12 * S[2] + P.J02 * P.J11 * S[4] + P.J02 * P.J12 * S[5];
-    P.c = P.J11 * P.J11 * S[3] + 2.f * P.J11 * P.J12 * S[4] + P.J12 * P.J12 * S[5] + rp.eps2d;
-    const float det = P.a * P.c - P.b * P.b;
-    if (!(det > 0.f)) return;
-    const float idet = 1.f / det;
-    P.A = P.c * idet;
-    P.B = -P.b * idet;
-    P.C = P.a * idet;
+    const double J00 = cam.fx * iz, J02 = -cam.fx * tx * iz, J11 = cam.fy * iz, J12 = -cam.fy * ty * iz;
+    P.J00 = (float)J00;
+    P.J02 = (float)J02;
+    P.J11 = (float)J11;
+    P.J12 = (float)J12;
+    // U = J R Rq S (2 x 3): cov2d = U U^T + eps I.  det without the
+    // cancellation of a c - b^2: a' c' - b^2 = |u0 x u1|^2 (Lagrange).
+    double u0[3], u1[3];
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        u0[j] = J00 * RM[j] + J02 * RM[6 + j];
+        u1[j] = J11 * RM[3 + j] + J12 * RM[6 + j];
+    }
+    const double ap = u0[0] * u0[0] + u0[1] * u0[1] + u0[2] * u0[2];
+    const double cp = u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2];
+    const double b = u0[0] * u1[0] + u0[1] * u1[1] + u0[2] * u1[2];
+    const double x0 = u0[1] * u1[2] - u0[2] * u1[1], x1 = u0[2] * u1[0] - u0[0] * u1[2],
+                 x2 = u0[0] * u1[1] - u0[1] * u1[0];
+    const double eps = rp.eps2d;
+    const double det = (x0 * x0 + x1 * x1 + x2 * x2) + eps * (ap + cp) + eps * eps;
+    if (!(det > 0.0)) return;
+    const double idet = 1.0 / det;
+    P.A = (cp + eps) * idet;
+    P.B = -b * idet;
+    P.C = (ap + eps) * idet;
     P.mx = cam.fx * rx + cam.cx;
     P.my = cam.fy * ry + cam.cy;
     P.valid = true;
@@ -262,21 +280,80 @@ __global__ __launch_bounds__(kBlock) void k_project_fwd(gs_gaussians g, const fl
             for (int k = 0; k < K; k++) s += Y[k] * sh[k][ch];
             col[ch] = fmaxf(s + 0.5f, 0.f);
         }
-        const bool fin = isfinite(P.mx) && isfinite(P.my) && isfinite(P.A) && isfinite(P.B) &&
-                         isfinite(P.C) && isfinite(col[0]) && isfinite(col[1]) &&
-                         isfinite(col[2]) && isfinite(G.o) && isfinite(P.p[2]);
+        // the record in float32, each value rounded once from double
+        const float mx = (float)P.mx, my = (float)P.my, depth = (float)P.p[2];
+        const float cA = (float)P.A, cB = (float)P.B, cC = (float)P.C;
+        const bool fin = isfinite(mx) && isfinite(my) && isfinite(cA) && isfinite(cB) &&
+                         isfinite(cC) && isfinite(col[0]) && isfinite(col[1]) &&
+                         isfinite(col[2]) && isfinite(G.o) && isfinite(depth);
         if (!fin) {
             nonfinite = true;
             r[0] = make_float4(0.f, 0.f, 0.f, 0.f);
             continue;
         }
-        r[0] = make_float4(P.mx, P.my, P.p[2], G.o);
-        r[1] = make_float4(P.A, P.B, P.C, col[0]);
+        r[0] = make_float4(mx, my, depth, G.o);
+        r[1] = make_float4(cA, cB, cC, col[0]);
         r[2] = make_float4(col[1], col[2], 0.f, 0.f);
     }
     if (nonfinite) atomicOr(&diag[kDiagFlags], (uint32_t)GS_FLAG_NONFINITE);
 }
 
+// One Adam step (ADAM) or the gradient written / added (!ADAM) for n entries
+// of one Gaussian: entry j is element i of row row(j) of array arr(j) (0
+// means, 1 log_scales, 2 quats, 3 opacity_logit, 4 sh).  Adam batches issue
+// every parameter and moment load of a batch before the batch's stores; each
+// access is a uniform row base plus one 32-bit lane offset (N < 2^28).
+template <bool ADAM, int NE, typename Arr, typename Row>
+__device__ __forceinline__ void step_entries(const float (&gr)[NE], Arr arr, Row row, int i, int N,
+                                             const AdamGauss& adam, const gs_gaussians_grad& out,
+                                             int accumulate) {
+    const uint32_t off = (uint32_t)i * 4u;
+    auto at = [&](float* base, int r) -> float& {
+        return *reinterpret_cast<float*>(reinterpret_cast<char*>(base + (int64_t)r * N) + off);
+    };
+    if (ADAM) {
+        constexpr int BATCH = 20;
+#pragma unroll
+        for (int j0 = 0; j0 < NE; j0 += BATCH) {
+            float pb[BATCH], mb[BATCH], vb[BATCH];
+#pragma unroll
+            for (int u = 0; u < BATCH; u++) {
+                const int j = j0 + u;
+                if (j < NE) {
+                    pb[u] = at(adam.p[arr(j)], row(j));
+                    mb[u] = at(adam.m[arr(j)], row(j));
+                    vb[u] = at(adam.v[arr(j)], row(j));
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < BATCH; u++) {
+                const int j = j0 + u;
+                if (j < NE) {
+                    const int q = arr(j);
+                    adam_one(pb[u], gr[j], mb[u], vb[u], adam.lr[q], adam.b1, adam.b2, adam.eps,
+                             adam.ibc1, adam.ibc2);
+                    at(adam.p[q], row(j)) = pb[u];
+                    at(adam.m[q], row(j)) = mb[u];
+                    at(adam.v[q], row(j)) = vb[u];
+                }
+            }
+        }
+    } else {
+        float* dst[5] = {out.means, out.log_scales, out.quats, out.opacity_logit, out.sh};
+#pragma unroll
+        for (int j = 0; j < NE; j++) {
+            float& d = at(dst[arr(j)], row(j));
+            d = accumulate ? d + gr[j] : gr[j];
+        }
+    }
+}
+
+// The projection backward, one thread per Gaussian over the call's views, in
+// two phases so their register sets never coexist: the colour (SH
+// coefficients, and the view direction's share of the mean and twist
+// gradients), whose step is taken before the geometry (the EWA chain in
+// double: mean, scales, rotation, opacity, and the rest of the twist).  Each
+// phase reads and clears its part of the per-pair 2D gradients.
 template <int DEG, bool ADAM>
 __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, const float* __restrict__ viewmat,
                                                         const float* __restrict__ intr, ViewTable vt,
@@ -290,290 +367,255 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, const fl
     for (int k = threadIdx.x; k < 6 * vt.V; k += kBlock) s_acc[k] = 0.0;
     __syncthreads();
     const int N = g.N;
-    // grid-stride over Gaussians: a bounded number of blocks keeps the twist
-    // atomics (one per block, view and component) few
-    for (int base = blockIdx.x * kBlock; base < N; base += gridDim.x * kBlock) {
-    const int i = base + threadIdx.x;
-    const bool active = i < N;
-    GaussLocal G;
-    float sh[K][3];
-    float v_sh[K][3];
-    float v_mu[3] = {0.f, 0.f, 0.f}, v_ls[3] = {0.f, 0.f, 0.f}, v_q[4] = {0.f, 0.f, 0.f, 0.f};
-    float v_logit = 0.f;
-#pragma unroll
-    for (int k = 0; k < K; k++)
-#pragma unroll
-        for (int ch = 0; ch < 3; ch++) v_sh[k][ch] = 0.f;
-    if (active) {
-        load_gaussian(g, i, G);
-#pragma unroll
-        for (int k = 0; k < K; k++)
-#pragma unroll
-            for (int ch = 0; ch < 3; ch++) sh[k][ch] = g.sh[((int64_t)k * 3 + ch) * N + i];
-    }
-    for (int v = 0; v < vt.V; v++) {
-        float tw[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        if (active) {
-            const int64_t pair = (int64_t)v * N + i;
-            float* gp = grad2d + 9 * pair;
-            float G9[9];
-            bool nz = false;
-#pragma unroll
-            for (int k = 0; k < 9; k++) {
-                G9[k] = gp[k];
-                nz |= G9[k] != 0.f;
-            }
-            if (nz) {
-#pragma unroll
-                for (int k = 0; k < 9; k++) gp[k] = 0.f;  // leave the accumulator clean
-                const Cam cam = load_cam(viewmat, intr, vt.cam[v]);
-                Proj P;
-                project_one(G, cam, vt.W[v], vt.H[v], rp, P);
-                if (P.valid) {
-                    // opacity
-                    v_logit += G9[5] * G.o * (1.f - G.o);
-                    // colour through SH (zero where the colour clamp is active)
-                    float Y[K];
-                    sh_basis(DEG, P.dir[0], P.dir[1], P.dir[2], Y);
-                    float vr[3];
-#pragma unroll
-                    for (int ch = 0; ch < 3; ch++) {
-                        float s = 0.f;
-#pragma unroll
-                        for (int k = 0; k < K; k++) s += Y[k] * sh[k][ch];
-                        vr[ch] = (s + 0.5f > 0.f) ? G9[6 + ch] : 0.f;
-                    }
-                    float sk[K];
-#pragma unroll
-                    for (int k = 0; k < K; k++) {
-                        sk[k] = 0.f;
-#pragma unroll
-                        for (int ch = 0; ch < 3; ch++) {
-                            v_sh[k][ch] += Y[k] * vr[ch];
-                            sk[k] += vr[ch] * sh[k][ch];
-                        }
-                    }
-                    float gd[3] = {0.f, 0.f, 0.f};
-                    sh_basis_grad(DEG, P.dir[0], P.dir[1], P.dir[2], sk, gd[0], gd[1], gd[2]);
-                    const float dd = P.dir[0] * gd[0] + P.dir[1] * gd[1] + P.dir[2] * gd[2];
-                    const float idist = 1.f / P.dist;
-                    float vmd[3];
-#pragma unroll
-                    for (int e = 0; e < 3; e++) {
-                        vmd[e] = (gd[e] - P.dir[e] * dd) * idist;
-                        v_mu[e] += vmd[e];
-                    }
-                    // the camera centre moves by -R^T rho under the left twist
-#pragma unroll
-                    for (int e = 0; e < 3; e++)
-                        tw[e] += cam.R[3 * e] * vmd[0] + cam.R[3 * e + 1] * vmd[1] +
-                                 cam.R[3 * e + 2] * vmd[2];
-                    // mean2d
-                    const float x = P.p[0], y = P.p[1], z = P.p[2];
-                    const float iz = 1.f / z, iz2 = iz * iz;
-                    float vp[3];
-                    vp[0] = cam.fx * iz * G9[0];
-                    vp[1] = cam.fy * iz * G9[1];
-                    vp[2] = -(cam.fx * x * G9[0] + cam.fy * y * G9[1]) * iz2;
-                    // conic -> cov2d: G2 = -Mc Gc Mc, Gc = [[vA, vB/2], [vB/2, vC]]
-                    const float gA = G9[2], gB = 0.5f * G9[3], gC = G9[4];
-                    const float t00 = P.A * gA + P.B * gB, t01 = P.A * gB + P.B * gC;
-                    const float t10 = P.B * gA + P.C * gB, t11 = P.B * gB + P.C * gC;
-                    const float G00 = -(t00 * P.A + t01 * P.B);
-                    const float G01 = -(t00 * P.B + t01 * P.C);
-                    const float G11 = -(t10 * P.B + t11 * P.C);
-                    // J rows: (J00, 0, J02), (0, J11, J12)
-                    const float* S = P.Sc;
-                    float JS0[3], JS1[3];
-#pragma unroll
-                    for (int j = 0; j < 3; j++) {
-                        JS0[j] = P.J00 * sym(S, 0, j) + P.J02 * sym(S, 2, j);
-                        JS1[j] = P.J11 * sym(S, 1, j) + P.J12 * sym(S, 2, j);
-                    }
-                    // v_J = 2 G2 J Sc
-                    const float vJ00 = 2.f * (G00 * JS0[0] + G01 * JS1[0]);
-                    const float vJ02 = 2.f * (G00 * JS0[2] + G01 * JS1[2]);
-                    const float vJ11 = 2.f * (G01 * JS0[1] + G11 * JS1[1]);
-                    const float vJ12 = 2.f * (G01 * JS0[2] + G11 * JS1[2]);
-                    vp[2] += -cam.fx * iz2 * vJ00 - cam.fy * iz2 * vJ11;
-                    if (!P.clx) {
-                        vp[0] += -cam.fx * iz2 * vJ02;
-                        vp[2] += 2.f * cam.fx * x * iz2 * iz * vJ02;
-                    } else {
-                        vp[2] += cam.fx * P.tx * iz2 * vJ02;
-                    }
-                    if (!P.cly) {
-                        vp[1] += -cam.fy * iz2 * vJ12;
-                        vp[2] += 2.f * cam.fy * y * iz2 * iz * vJ12;
-                    } else {
-                        vp[2] += cam.fy * P.ty * iz2 * vJ12;
-                    }
-                    // v_Sc = J^T G2 J (full 3x3, symmetric)
-                    const float J0[3] = {P.J00, 0.f, P.J02}, J1[3] = {0.f, P.J11, P.J12};
-                    float U0[3], U1[3];
-#pragma unroll
-                    for (int j = 0; j < 3; j++) {
-                        U0[j] = G00 * J0[j] + G01 * J1[j];
-                        U1[j] = G01 * J0[j] + G11 * J1[j];
-                    }
-                    float vSc[9];
-#pragma unroll
-                    for (int r = 0; r < 3; r++)
-#pragma unroll
-                        for (int c = 0; c < 3; c++) vSc[3 * r + c] = J0[r] * U0[c] + J1[r] * U1[c];
-                    // twist: rho gets v_p, phi gets p x v_p + 2 axial(Sc vSc)
-                    float Wm[9];
-#pragma unroll
-                    for (int r = 0; r < 3; r++)
-#pragma unroll
-                        for (int c = 0; c < 3; c++)
-                            Wm[3 * r + c] = sym(S, r, 0) * vSc[c] + sym(S, r, 1) * vSc[3 + c] +
-                                            sym(S, r, 2) * vSc[6 + c];
-                    tw[0] += vp[0];
-                    tw[1] += vp[1];
-                    tw[2] += vp[2];
-                    tw[3] += y * vp[2] - z * vp[1] + 2.f * (Wm[5] - Wm[7]);
-                    tw[4] += z * vp[0] - x * vp[2] + 2.f * (Wm[6] - Wm[2]);
-                    tw[5] += x * vp[1] - y * vp[0] + 2.f * (Wm[1] - Wm[3]);
-                    // mean: p = R mu + t
-#pragma unroll
-                    for (int e = 0; e < 3; e++)
-                        v_mu[e] += cam.R[e] * vp[0] + cam.R[3 + e] * vp[1] + cam.R[6 + e] * vp[2];
-                    // Sc = R Sig R^T -> vSig = R^T vSc R
-                    float T9[9], vS[9];
-#pragma unroll
-                    for (int r = 0; r < 3; r++)
-#pragma unroll
-                        for (int c = 0; c < 3; c++)
-                            T9[3 * r + c] = cam.R[r] * vSc[c] + cam.R[3 + r] * vSc[3 + c] +
-                                            cam.R[6 + r] * vSc[6 + c];
-#pragma unroll
-                    for (int r = 0; r < 3; r++)
-#pragma unroll
-                        for (int c = 0; c < 3; c++)
-                            vS[3 * r + c] = T9[3 * r] * cam.R[c] + T9[3 * r + 1] * cam.R[3 + c] +
-                                            T9[3 * r + 2] * cam.R[6 + c];
-                    // Sig = M M^T, M = Rq S: vM = 2 vS M
-                    float vM[9];
-#pragma unroll
-                    for (int r = 0; r < 3; r++)
-#pragma unroll
-                        for (int c = 0; c < 3; c++)
-                            vM[3 * r + c] =
-                                2.f * (vS[3 * r] * G.Rq[c] + vS[3 * r + 1] * G.Rq[3 + c] +
-                                       vS[3 * r + 2] * G.Rq[6 + c]) * G.s[c];
-#pragma unroll
-                    for (int c = 0; c < 3; c++)
-                        v_ls[c] += (G.Rq[c] * vM[c] + G.Rq[3 + c] * vM[3 + c] +
-                                    G.Rq[6 + c] * vM[6 + c]) * G.s[c];
-                    float vR[9];
-#pragma unroll
-                    for (int r = 0; r < 3; r++)
-#pragma unroll
-                        for (int c = 0; c < 3; c++) vR[3 * r + c] = vM[3 * r + c] * G.s[c];
-                    const float w = G.qn[0], qx = G.qn[1], qy = G.qn[2], qz = G.qn[3];
-                    float vqn[4];
-                    vqn[0] = 2.f * (-qz * vR[1] + qy * vR[2] + qz * vR[3] - qx * vR[5] - qy * vR[6] +
-                                    qx * vR[7]);
-                    vqn[1] = 2.f * (qy * vR[1] + qz * vR[2] + qy * vR[3] - w * vR[5] + qz * vR[6] +
-                                    w * vR[7]) - 4.f * qx * (vR[4] + vR[8]);
-                    vqn[2] = 2.f * (qx * vR[1] + w * vR[2] + qx * vR[3] + qz * vR[5] - w * vR[6] +
-                                    qz * vR[7]) - 4.f * qy * (vR[0] + vR[8]);
-                    vqn[3] = 2.f * (-w * vR[1] + qx * vR[2] + w * vR[3] + qy * vR[5] + qx * vR[6] +
-                                    qy * vR[7]) - 4.f * qz * (vR[0] + vR[4]);
-                    const float qd = G.qn[0] * vqn[0] + G.qn[1] * vqn[1] + G.qn[2] * vqn[2] +
-                                     G.qn[3] * vqn[3];
-                    const float iq = 1.f / G.qnorm;
-#pragma unroll
-                    for (int e = 0; e < 4; e++) v_q[e] += (vqn[e] - G.qn[e] * qd) * iq;
-                }
-            }
-        }
-        // per-view twist: wave sum, then the block's waves, then one double atomic
-        const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+    // one view's twist terms of the block: wave sums, then the block's waves
+    auto twist_reduce = [&](int v, const float* tw) {
 #pragma unroll
         for (int e = 0; e < 6; e++) {
-            const float s = wave_sum(tw[e]);
-            if (lane == 0) s_tw[wv][e] = s;
+            const float sm = wave_sum(tw[e]);
+            if (lane == 0) s_tw[wv][e] = sm;
         }
         __syncthreads();
         if (threadIdx.x < 6) {
-            double s = 0.0;
-            for (int q = 0; q < kBlock / kWave; q++) s += (double)s_tw[q][threadIdx.x];
-            s_acc[6 * v + threadIdx.x] += s;
+            double sm = 0.0;
+            for (int q = 0; q < kBlock / kWave; q++) sm += (double)s_tw[q][threadIdx.x];
+            s_acc[6 * v + threadIdx.x] += sm;
         }
         __syncthreads();
-    }
-    if (active && ADAM) {
-        // the Gaussian's 11 + 3K gradients in one flat list (means, log_scales,
-        // quats, opacity, sh); each Adam batch issues all its parameter and
-        // moment loads before its first store, so the loads of a batch are in
-        // flight together
-        constexpr int NP = 11 + 3 * K;
-        constexpr int BATCH = 20;
-        float gr[NP];
+    };
+    // grid-stride over Gaussians: a bounded number of blocks keeps the twist
+    // atomics (one per block, view and component) few
+    for (int base = blockIdx.x * kBlock; base < N; base += gridDim.x * kBlock) {
+        const int i = base + threadIdx.x;
+        const bool active = i < N;
+        GaussLocal G;
+        if (active) load_gaussian(g, i, G);
+        float v_mu[3] = {0.f, 0.f, 0.f};
+        // ---- colour
+        {
+            float sh[K][3];
+            float v_sh[3 * K];
 #pragma unroll
-        for (int e = 0; e < 3; e++) gr[e] = v_mu[e];
+            for (int j = 0; j < 3 * K; j++) v_sh[j] = 0.f;
+            if (active) {
 #pragma unroll
-        for (int e = 0; e < 3; e++) gr[3 + e] = v_ls[e];
+                for (int k = 0; k < K; k++)
 #pragma unroll
-        for (int e = 0; e < 4; e++) gr[6 + e] = v_q[e];
-        gr[10] = v_logit;
-#pragma unroll
-        for (int k = 0; k < K; k++)
-#pragma unroll
-            for (int ch = 0; ch < 3; ch++) gr[11 + 3 * k + ch] = v_sh[k][ch];
-        // array and row of flat entry j
-        auto arr = [](int j) { return j < 3 ? 0 : j < 6 ? 1 : j < 10 ? 2 : j < 11 ? 3 : 4; };
-        auto row = [](int j) { return j < 3 ? j : j < 6 ? j - 3 : j < 10 ? j - 6 : j < 11 ? 0 : j - 11; };
-        // element i of a row: the row start is uniform, the byte offset i * 4
-        // one 32-bit lane value shared by every access (N < 2^28, as pairs are)
-        const uint32_t off = (uint32_t)i * 4u;
-        auto at = [&](float* base, int r) -> float& {
-            return *reinterpret_cast<float*>(reinterpret_cast<char*>(base + (int64_t)r * N) + off);
-        };
-#pragma unroll
-        for (int j0 = 0; j0 < NP; j0 += BATCH) {
-            float pb[BATCH], mb[BATCH], vb[BATCH];
-#pragma unroll
-            for (int u = 0; u < BATCH; u++) {
-                const int j = j0 + u;
-                if (j < NP) {
-                    pb[u] = at(adam.p[arr(j)], row(j));
-                    mb[u] = at(adam.m[arr(j)], row(j));
-                    vb[u] = at(adam.v[arr(j)], row(j));
-                }
+                    for (int ch = 0; ch < 3; ch++) sh[k][ch] = g.sh[((int64_t)k * 3 + ch) * N + i];
             }
+            for (int v = 0; v < vt.V; v++) {
+                float tw[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                if (active) {
+                    float* gp = grad2d + 9 * ((int64_t)v * N + i) + 6;
+                    const float gc[3] = {gp[0], gp[1], gp[2]};
+                    // a pair that was never rendered (culled, or outside every
+                    // list) has no gradient at all
+                    if (gc[0] != 0.f || gc[1] != 0.f || gc[2] != 0.f) {
+                        gp[0] = gp[1] = gp[2] = 0.f;  // leave the accumulator clean
+                        const Cam cam = load_cam(viewmat, intr, vt.cam[v]);
+                        float dir[3], dist;
+                        view_dir(G, cam, dir, dist);
+                        // colour through SH (zero where the colour clamp is active)
+                        float Y[K];
+                        sh_basis(DEG, dir[0], dir[1], dir[2], Y);
+                        float vr[3];
 #pragma unroll
-            for (int u = 0; u < BATCH; u++) {
-                const int j = j0 + u;
-                if (j < NP) {
-                    const int q = arr(j);
-                    adam_one(pb[u], gr[j], mb[u], vb[u], adam.lr[q], adam.b1, adam.b2, adam.eps,
-                             adam.ibc1, adam.ibc2);
-                    at(adam.p[q], row(j)) = pb[u];
-                    at(adam.m[q], row(j)) = mb[u];
-                    at(adam.v[q], row(j)) = vb[u];
+                        for (int ch = 0; ch < 3; ch++) {
+                            float sm = 0.f;
+#pragma unroll
+                            for (int k = 0; k < K; k++) sm += Y[k] * sh[k][ch];
+                            vr[ch] = (sm + 0.5f > 0.f) ? gc[ch] : 0.f;
+                        }
+                        float sk[K];
+#pragma unroll
+                        for (int k = 0; k < K; k++) {
+                            sk[k] = 0.f;
+#pragma unroll
+                            for (int ch = 0; ch < 3; ch++) {
+                                v_sh[3 * k + ch] += Y[k] * vr[ch];
+                                sk[k] += vr[ch] * sh[k][ch];
+                            }
+                        }
+                        float gd[3] = {0.f, 0.f, 0.f};
+                        sh_basis_grad(DEG, dir[0], dir[1], dir[2], sk, gd[0], gd[1], gd[2]);
+                        const float dd = dir[0] * gd[0] + dir[1] * gd[1] + dir[2] * gd[2];
+                        const float idist = 1.f / dist;
+                        float vmd[3];
+#pragma unroll
+                        for (int e = 0; e < 3; e++) {
+                            vmd[e] = (gd[e] - dir[e] * dd) * idist;
+                            v_mu[e] += vmd[e];
+                        }
+                        // the camera centre moves by -R^T rho under the left twist
+#pragma unroll
+                        for (int e = 0; e < 3; e++)
+                            tw[e] += cam.R[3 * e] * vmd[0] + cam.R[3 * e + 1] * vmd[1] +
+                                     cam.R[3 * e + 2] * vmd[2];
+                    }
                 }
+                twist_reduce(v, tw);
+            }
+            if (active)
+                step_entries<ADAM>(v_sh, [](int) { return 4; }, [](int j) { return j; }, i, N, adam, out,
+                                   accumulate);
+        }
+        // ---- geometry
+        {
+            float v_ls[3] = {0.f, 0.f, 0.f}, v_q[4] = {0.f, 0.f, 0.f, 0.f};
+            float v_logit = 0.f;
+            for (int v = 0; v < vt.V; v++) {
+                float tw[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                if (active) {
+                    float* gp = grad2d + 9 * ((int64_t)v * N + i);
+                    float G9[6];
+                    bool nz = false;
+#pragma unroll
+                    for (int k = 0; k < 6; k++) {
+                        G9[k] = gp[k];
+                        nz |= G9[k] != 0.f;
+                    }
+                    if (nz) {
+#pragma unroll
+                        for (int k = 0; k < 6; k++) gp[k] = 0.f;  // leave the accumulator clean
+                        const Cam cam = load_cam(viewmat, intr, vt.cam[v]);
+                        Proj P;
+                        project_one(G, cam, vt.W[v], vt.H[v], rp, P);
+                        if (P.valid) {
+                            // opacity
+                            v_logit += G9[5] * G.o * (1.f - G.o);
+                // the EWA chain in double (the conic and covariances are
+                            // ill-conditioned for needle-like splats)
+                            // mean2d
+                            const double x = P.p[0], y = P.p[1], z = P.p[2];
+                            const double iz = 1.0 / z, iz2 = iz * iz;
+                            const double fx = cam.fx, fy = cam.fy;
+                            double vp[3];
+                            vp[0] = fx * iz * G9[0];
+                            vp[1] = fy * iz * G9[1];
+                            vp[2] = -(fx * x * G9[0] + fy * y * G9[1]) * iz2;
+                            // conic -> cov2d: G2 = -Mc Gc Mc, Gc = [[vA, vB/2], [vB/2, vC]]
+                            const double gA = G9[2], gB = 0.5 * G9[3], gC = G9[4];
+                            const double t00 = P.A * gA + P.B * gB, t01 = P.A * gB + P.B * gC;
+                            const double t10 = P.B * gA + P.C * gB, t11 = P.B * gB + P.C * gC;
+                            const double G00 = -(t00 * P.A + t01 * P.B);
+                            const double G01 = -(t00 * P.B + t01 * P.C);
+                            const double G11 = -(t10 * P.B + t11 * P.C);
+                            // J rows: (J00, 0, J02), (0, J11, J12)
+                            const double* S = P.Sc;
+                            double JS0[3], JS1[3];
+#pragma unroll
+                            for (int j = 0; j < 3; j++) {
+                                JS0[j] = P.J00 * symd(S, 0, j) + P.J02 * symd(S, 2, j);
+                                JS1[j] = P.J11 * symd(S, 1, j) + P.J12 * symd(S, 2, j);
+                            }
+                            // v_J = 2 G2 J Sc
+                            const double vJ00 = 2.0 * (G00 * JS0[0] + G01 * JS1[0]);
+                            const double vJ02 = 2.0 * (G00 * JS0[2] + G01 * JS1[2]);
+                            const double vJ11 = 2.0 * (G01 * JS0[1] + G11 * JS1[1]);
+                            const double vJ12 = 2.0 * (G01 * JS0[2] + G11 * JS1[2]);
+                            vp[2] += -fx * iz2 * vJ00 - fy * iz2 * vJ11;
+                            if (!P.clx) {
+                                vp[0] += -fx * iz2 * vJ02;
+                                vp[2] += 2.0 * fx * x * iz2 * iz * vJ02;
+                            } else {
+                                vp[2] += fx * P.tx * iz2 * vJ02;
+                            }
+                            if (!P.cly) {
+                                vp[1] += -fy * iz2 * vJ12;
+                                vp[2] += 2.0 * fy * y * iz2 * iz * vJ12;
+                            } else {
+                                vp[2] += fy * P.ty * iz2 * vJ12;
+                            }
+                            // v_Sc = J^T G2 J, symmetric: 00 01 02 11 12 22
+                            double vSc[6];
+                            vSc[0] = G00 * P.J00 * P.J00;
+                            vSc[1] = G01 * P.J00 * P.J11;
+                            vSc[2] = P.J00 * (G00 * P.J02 + G01 * P.J12);
+                            vSc[3] = G11 * P.J11 * P.J11;
+                            vSc[4] = P.J11 * (G01 * P.J02 + G11 * P.J12);
+                            vSc[5] = G00 * P.J02 * P.J02 + 2.0 * G01 * P.J02 * P.J12 + G11 * P.J12 * P.J12;
+                            // twist: rho gets v_p, phi gets p x v_p + 2 axial(Sc vSc), axial
+                            // of W = Sc vSc: (W12 - W21, W20 - W02, W01 - W10)
+                            auto Wrc = [&](int r, int c) {
+                                return symd(S, r, 0) * symd(vSc, 0, c) + symd(S, r, 1) * symd(vSc, 1, c) +
+                                       symd(S, r, 2) * symd(vSc, 2, c);
+                            };
+                            tw[0] += (float)vp[0];
+                            tw[1] += (float)vp[1];
+                            tw[2] += (float)vp[2];
+                            tw[3] += (float)(y * vp[2] - z * vp[1] + 2.0 * (Wrc(1, 2) - Wrc(2, 1)));
+                            tw[4] += (float)(z * vp[0] - x * vp[2] + 2.0 * (Wrc(2, 0) - Wrc(0, 2)));
+                            tw[5] += (float)(x * vp[1] - y * vp[0] + 2.0 * (Wrc(0, 1) - Wrc(1, 0)));
+                            // mean: p = R mu + t
+#pragma unroll
+                            for (int e = 0; e < 3; e++)
+                                v_mu[e] += (float)(cam.R[e] * vp[0] + cam.R[3 + e] * vp[1] + cam.R[6 + e] * vp[2]);
+                            // Sc = R Sig R^T, Sig = M M^T, M = Rq S.  Q = Rq^T vSig Rq
+                            // = (R Rq)^T vSc (R Rq) (symmetric): the scale gradient is
+                            // 2 s_c^2 Q_cc and vR = 2 vSig Rq S^2 = 2 Rq Q S^2
+                            double Q[6];
+                            {
+                                double RR[9];  // R Rq
+#pragma unroll
+                                for (int r = 0; r < 3; r++)
+#pragma unroll
+                                    for (int c = 0; c < 3; c++)
+                                        RR[3 * r + c] = cam.R[3 * r] * P.Rq[c] + cam.R[3 * r + 1] * P.Rq[3 + c] +
+                                                        cam.R[3 * r + 2] * P.Rq[6 + c];
+                                int k = 0;
+#pragma unroll
+                                for (int r = 0; r < 3; r++)
+#pragma unroll
+                                    for (int c = r; c < 3; c++) {
+                                        double acc = 0.0;
+#pragma unroll
+                                        for (int m = 0; m < 3; m++)
+#pragma unroll
+                                            for (int n = 0; n < 3; n++)
+                                                acc += RR[3 * m + r] * symd(vSc, m, n) * RR[3 * n + c];
+                                        Q[k++] = acc;
+                                    }
+                            }
+                            const double s2[3] = {(double)G.s[0] * G.s[0], (double)G.s[1] * G.s[1],
+                                                  (double)G.s[2] * G.s[2]};
+#pragma unroll
+                            for (int c = 0; c < 3; c++) v_ls[c] += (float)(2.0 * symd(Q, c, c) * s2[c]);
+                            double vR[9];  // 2 Rq Q S^2
+#pragma unroll
+                            for (int r = 0; r < 3; r++)
+#pragma unroll
+                                for (int c = 0; c < 3; c++)
+                                    vR[3 * r + c] = 2.0 * (P.Rq[3 * r] * symd(Q, 0, c) + P.Rq[3 * r + 1] * symd(Q, 1, c) +
+                                                           P.Rq[3 * r + 2] * symd(Q, 2, c)) * s2[c];
+                            const double w = P.qn[0], qx = P.qn[1], qy = P.qn[2], qz = P.qn[3];
+                            double vqn[4];
+                            vqn[0] = 2.0 * (-qz * vR[1] + qy * vR[2] + qz * vR[3] - qx * vR[5] - qy * vR[6] +
+                                            qx * vR[7]);
+                            vqn[1] = 2.0 * (qy * vR[1] + qz * vR[2] + qy * vR[3] - w * vR[5] + qz * vR[6] +
+                                            w * vR[7]) - 4.0 * qx * (vR[4] + vR[8]);
+                            vqn[2] = 2.0 * (qx * vR[1] + w * vR[2] + qx * vR[3] + qz * vR[5] - w * vR[6] +
+                                            qz * vR[7]) - 4.0 * qy * (vR[0] + vR[8]);
+                            vqn[3] = 2.0 * (-w * vR[1] + qx * vR[2] + w * vR[3] + qy * vR[5] + qx * vR[6] +
+                                            qy * vR[7]) - 4.0 * qz * (vR[0] + vR[4]);
+                            const double qd = P.qn[0] * vqn[0] + P.qn[1] * vqn[1] + P.qn[2] * vqn[2] +
+                                              P.qn[3] * vqn[3];
+                            const double iq = 1.0 / P.qnorm;
+#pragma unroll
+                            for (int e = 0; e < 4; e++) v_q[e] += (float)((vqn[e] - P.qn[e] * qd) * iq);
+                        }
+                    }
+                }
+                twist_reduce(v, tw);
+            }
+            if (active) {
+                const float gr[11] = {v_mu[0], v_mu[1], v_mu[2], v_ls[0], v_ls[1], v_ls[2],
+                                      v_q[0],  v_q[1],  v_q[2],  v_q[3],  v_logit};
+                step_entries<ADAM>(
+                    gr, [](int j) { return j < 3 ? 0 : j < 6 ? 1 : j < 10 ? 2 : 3; },
+                    [](int j) { return j < 3 ? j : j < 6 ? j - 3 : j < 10 ? j - 6 : 0; }, i, N, adam, out,
+                    accumulate);
             }
         }
-    } else if (active) {
-    auto put = [&](float* dst, int64_t idx, float val) {
-        if (accumulate) dst[idx] += val;
-        else dst[idx] = val;
-    };
-#pragma unroll
-    for (int e = 0; e < 3; e++) put(out.means, (int64_t)e * N + i, v_mu[e]);
-#pragma unroll
-    for (int e = 0; e < 3; e++) put(out.log_scales, (int64_t)e * N + i, v_ls[e]);
-#pragma unroll
-    for (int e = 0; e < 4; e++) put(out.quats, (int64_t)e * N + i, v_q[e]);
-    put(out.opacity_logit, i, v_logit);
-#pragma unroll
-    for (int k = 0; k < K; k++)
-#pragma unroll
-        for (int ch = 0; ch < 3; ch++) put(out.sh, ((int64_t)k * 3 + ch) * N + i, v_sh[k][ch]);
-    }
     }
     __syncthreads();
     for (int k = threadIdx.x; k < 6 * vt.V; k += kBlock)
