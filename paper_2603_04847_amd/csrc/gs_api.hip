@@ -166,6 +166,7 @@ gs_status gs_ctx_create(gs_ctx** out, const gs_capacity* cap) {
     A(dalloc(&c.rec, (size_t)P * GS_RECORD_FLOATS));
     A(dalloc(&c.grad2d, (size_t)P * GS_GRAD2D_FLOATS));
     A(dalloc(&c.cnt, (size_t)P));
+    A(dalloc(&c.vmu_dir, (size_t)3 * (P > 0 ? P : 1)));
     A(dalloc(&c.off, (size_t)P));
     for (int k = 0; k < 2; k++) {
         A(dalloc(&c.pk[k], (size_t)P));
@@ -223,7 +224,7 @@ gs_status gs_ctx_create(gs_ctx** out, const gs_capacity* cap) {
 gs_status gs_ctx_destroy(gs_ctx* h) {
     if (!h) return GS_ERR_INVALID_ARG;
     gs::Ctx& c = h->c;
-    void* ptrs[] = {c.rec, c.grad2d, c.cnt, c.off, c.pk[0], c.pk[1], c.pv[0], c.pv[1],
+    void* ptrs[] = {c.rec, c.grad2d, c.vmu_dir, c.cnt, c.off, c.pk[0], c.pk[1], c.pv[0], c.pv[1],
                     c.ik[0], c.ik[1], c.iv[0], c.iv[1], c.im[0], c.im[1], c.tcnt, c.ccnt, c.cbase, c.bpre, c.bplace, c.tbase, c.tranges, c.tids,
                     c.ranges, c.tile_order, c.tk[0], c.tk[1], c.tile_contrib, c.tile_entries, c.tile_evals, c.hist,
                     c.scan_scratch, c.scalars, c.twist_render, c.twist_track, c.loss_acc, c.diag};

@@ -428,6 +428,7 @@ struct Ctx {
     int device;
     float* rec;            // [max_pairs][12]
     float* grad2d;         // [max_pairs][9], kept zero between backward calls
+    float* vmu_dir;        // [3][max_pairs] the colour's share of the mean gradient (backward)
     uint32_t* cnt;         // [max_pairs] list entries per pair
     uint32_t* off;         // [max_pairs] entry counts in depth order, then their scan
     uint32_t* pk[2];       // [max_pairs] depth keys (ping-pong)

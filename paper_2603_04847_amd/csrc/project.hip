@@ -145,7 +145,7 @@ __device__ __forceinline__ void view_dir(const GaussLocal& G, const Cam& cam, fl
 // project onto the needle's axis, lose most of their digits.
 struct Proj {
     bool valid;
-    double p[3];
+    double p[3], iz;      // camera-frame mean and 1 / z
     double qn[4], qnorm;  // unit quaternion and the raw norm
     float Rq[9];          // its rotation (rounded from double)
     double Sc[6];         // camera covariance (sym)
@@ -204,10 +204,12 @@ __device__ __forceinline__ void project_one(const GaussLocal& G, const Cam& cam,
         for (int j = i; j < 3; j++)
             P.Sc[k++] = RM[3 * i] * RM[3 * j] + RM[3 * i + 1] * RM[3 * j + 1] + RM[3 * i + 2] * RM[3 * j + 2];
     const double iz = 1.0 / z;
-    const double lxp = ((double)W - cam.cx) / cam.fx + rp.fov_pad * 0.5 * W / cam.fx;
-    const double lxn = (double)cam.cx / cam.fx + rp.fov_pad * 0.5 * W / cam.fx;
-    const double lyp = ((double)H - cam.cy) / cam.fy + rp.fov_pad * 0.5 * H / cam.fy;
-    const double lyn = (double)cam.cy / cam.fy + rp.fov_pad * 0.5 * H / cam.fy;
+    P.iz = iz;
+    // the x/z, y/z clamp limits of J (1.3x the field of view): per view, in float
+    const float ifx = 1.f / cam.fx, ify = 1.f / cam.fy;
+    const float padx = rp.fov_pad * 0.5f * W * ifx, pady = rp.fov_pad * 0.5f * H * ify;
+    const double lxp = ((float)W - cam.cx) * ifx + padx, lxn = cam.cx * ifx + padx;
+    const double lyp = ((float)H - cam.cy) * ify + pady, lyn = cam.cy * ify + pady;
     const double rx = P.p[0] * iz, ry = P.p[1] * iz;
     const double tx = fmin(fmax(rx, -lxn), lxp), ty = fmin(fmax(ry, -lyn), lyp);
     P.tx = (float)tx;
@@ -303,7 +305,7 @@ __global__ __launch_bounds__(kBlock) void k_project_fwd(gs_gaussians g, const fl
 // means, 1 log_scales, 2 quats, 3 opacity_logit, 4 sh).  Adam batches issue
 // every parameter and moment load of a batch before the batch's stores; each
 // access is a uniform row base plus one 32-bit lane offset (N < 2^28).
-template <bool ADAM, int NE, typename Arr, typename Row>
+template <bool ADAM, int NE, int BATCH = 20, typename Arr, typename Row>
 __device__ __forceinline__ void step_entries(const float (&gr)[NE], Arr arr, Row row, int i, int N,
                                              const AdamGauss& adam, const gs_gaussians_grad& out,
                                              int accumulate) {
@@ -312,7 +314,6 @@ __device__ __forceinline__ void step_entries(const float (&gr)[NE], Arr arr, Row
         return *reinterpret_cast<float*>(reinterpret_cast<char*>(base + (int64_t)r * N) + off);
     };
     if (ADAM) {
-        constexpr int BATCH = 20;
 #pragma unroll
         for (int j0 = 0; j0 < NE; j0 += BATCH) {
             float pb[BATCH], mb[BATCH], vb[BATCH];
@@ -348,19 +349,20 @@ __device__ __forceinline__ void step_entries(const float (&gr)[NE], Arr arr, Row
     }
 }
 
-// The projection backward, one thread per Gaussian over the call's views, in
-// two phases so their register sets never coexist: the colour (SH
-// coefficients, and the view direction's share of the mean and twist
-// gradients), whose step is taken before the geometry (the EWA chain in
-// double: mean, scales, rotation, opacity, and the rest of the twist).  Each
-// phase reads and clears its part of the per-pair 2D gradients.
+// The projection backward, one thread per Gaussian over the call's views, as
+// two kernels so their register sets stay apart: the colour (SH coefficients,
+// and the view direction's share of the mean and twist gradients: float),
+// then the geometry (the EWA chain in double: mean, scales, rotation,
+// opacity and the rest of the twist).  Each reads and clears its part of the
+// per-pair 2D gradients; the colour's share of the mean gradient passes to
+// the geometry through vmu_dir [3][N]; both add twist terms to one
+// accumulator.
 template <int DEG, bool ADAM>
-__global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, const float* __restrict__ viewmat,
-                                                        const float* __restrict__ intr, ViewTable vt,
-                                                        RasterParams rp, float* __restrict__ grad2d,
-                                                        gs_gaussians_grad out, int accumulate,
-                                                        AdamGauss adam,
-                                                        double* __restrict__ twist_acc) {
+__global__ __launch_bounds__(kBlock) void k_project_bwd_color(gs_gaussians g, const float* __restrict__ viewmat,
+                                 const float* __restrict__ intr, ViewTable vt, RasterParams rp,
+                                 float* __restrict__ grad2d, gs_gaussians_grad out, int accumulate,
+                                 AdamGauss adam, float* __restrict__ vmu_dir,
+                                 double* __restrict__ twist_acc) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     __shared__ float s_tw[kBlock / kWave][6];
     __shared__ double s_acc[6 * GS_MAX_VIEWS];  // this block's twist sums, all iterations
@@ -403,11 +405,23 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, const fl
 #pragma unroll
                     for (int ch = 0; ch < 3; ch++) sh[k][ch] = g.sh[((int64_t)k * 3 + ch) * N + i];
             }
+            // the next view's colour gradients are requested ahead, as above
+            float gcn[3];
+            {
+                const float* gp0 = grad2d + 9 * (int64_t)(active ? i : 0) + 6;
+#pragma unroll
+                for (int k = 0; k < 3; k++) gcn[k] = (active && vt.V > 0) ? gp0[k] : 0.f;
+            }
             for (int v = 0; v < vt.V; v++) {
                 float tw[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                const float gc[3] = {gcn[0], gcn[1], gcn[2]};
+                if (v + 1 < vt.V) {
+                    const float* gq = grad2d + 9 * ((int64_t)(v + 1) * N + (active ? i : 0)) + 6;
+#pragma unroll
+                    for (int k = 0; k < 3; k++) gcn[k] = active ? gq[k] : 0.f;
+                }
                 if (active) {
                     float* gp = grad2d + 9 * ((int64_t)v * N + i) + 6;
-                    const float gc[3] = {gp[0], gp[1], gp[2]};
                     // a pair that was never rendered (culled, or outside every
                     // list) has no gradient at all
                     if (gc[0] != 0.f || gc[1] != 0.f || gc[2] != 0.f) {
@@ -455,25 +469,85 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, const fl
                 }
                 twist_reduce(v, tw);
             }
-            if (active)
-                step_entries<ADAM>(v_sh, [](int) { return 4; }, [](int j) { return j; }, i, N, adam, out,
-                                   accumulate);
+            if (active) {
+#pragma unroll
+                for (int e = 0; e < 3; e++) vmu_dir[(int64_t)e * N + i] = v_mu[e];
+                step_entries<ADAM, 3 * K, 12>(v_sh, [](int) { return 4; }, [](int j) { return j; }, i, N, adam,
+                                              out, accumulate);
+            }
         }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < 6 * vt.V; k += kBlock)
+        if (s_acc[k] != 0.0) atomicAdd(&twist_acc[k], s_acc[k]);
+}
+
+template <bool ADAM>
+__global__ __launch_bounds__(kBlock) void k_project_bwd_geom(gs_gaussians g, const float* __restrict__ viewmat,
+                                 const float* __restrict__ intr, ViewTable vt, RasterParams rp,
+                                 float* __restrict__ grad2d, gs_gaussians_grad out, int accumulate,
+                                 AdamGauss adam, float* __restrict__ vmu_dir,
+                                 double* __restrict__ twist_acc) {
+    __shared__ float s_tw[kBlock / kWave][6];
+    __shared__ double s_acc[6 * GS_MAX_VIEWS];  // this block's twist sums, all iterations
+    for (int k = threadIdx.x; k < 6 * vt.V; k += kBlock) s_acc[k] = 0.0;
+    __syncthreads();
+    const int N = g.N;
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+    // one view's twist terms of the block: wave sums, then the block's waves
+    auto twist_reduce = [&](int v, const float* tw) {
+#pragma unroll
+        for (int e = 0; e < 6; e++) {
+            const float sm = wave_sum(tw[e]);
+            if (lane == 0) s_tw[wv][e] = sm;
+        }
+        __syncthreads();
+        if (threadIdx.x < 6) {
+            double sm = 0.0;
+            for (int q = 0; q < kBlock / kWave; q++) sm += (double)s_tw[q][threadIdx.x];
+            s_acc[6 * v + threadIdx.x] += sm;
+        }
+        __syncthreads();
+    };
+    // grid-stride over Gaussians: a bounded number of blocks keeps the twist
+    // atomics (one per block, view and component) few
+    for (int base = blockIdx.x * kBlock; base < N; base += gridDim.x * kBlock) {
+        const int i = base + threadIdx.x;
+        const bool active = i < N;
+        GaussLocal G;
+        if (active) load_gaussian(g, i, G);
+        float v_mu[3] = {0.f, 0.f, 0.f};
         // ---- geometry
         {
+            if (active) {
+#pragma unroll
+                for (int e = 0; e < 3; e++) v_mu[e] = vmu_dir[(int64_t)e * N + i];
+            }
             float v_ls[3] = {0.f, 0.f, 0.f}, v_q[4] = {0.f, 0.f, 0.f, 0.f};
             float v_logit = 0.f;
+            // the next view's 2D gradients are requested before this view's
+            // chain runs, so their latency hides behind it
+            float G9n[6];
+            {
+                const float* gp0 = grad2d + 9 * (int64_t)(active ? i : 0);
+#pragma unroll
+                for (int k = 0; k < 6; k++) G9n[k] = (active && vt.V > 0) ? gp0[k] : 0.f;
+            }
             for (int v = 0; v < vt.V; v++) {
                 float tw[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                float G9[6];
+#pragma unroll
+                for (int k = 0; k < 6; k++) G9[k] = G9n[k];
+                if (v + 1 < vt.V) {
+                    const float* gq = grad2d + 9 * ((int64_t)(v + 1) * N + (active ? i : 0));
+#pragma unroll
+                    for (int k = 0; k < 6; k++) G9n[k] = active ? gq[k] : 0.f;
+                }
                 if (active) {
                     float* gp = grad2d + 9 * ((int64_t)v * N + i);
-                    float G9[6];
                     bool nz = false;
 #pragma unroll
-                    for (int k = 0; k < 6; k++) {
-                        G9[k] = gp[k];
-                        nz |= G9[k] != 0.f;
-                    }
+                    for (int k = 0; k < 6; k++) nz |= G9[k] != 0.f;
                     if (nz) {
 #pragma unroll
                         for (int k = 0; k < 6; k++) gp[k] = 0.f;  // leave the accumulator clean
@@ -487,7 +561,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, const fl
                             // ill-conditioned for needle-like splats)
                             // mean2d
                             const double x = P.p[0], y = P.p[1], z = P.p[2];
-                            const double iz = 1.0 / z, iz2 = iz * iz;
+                            const double iz = P.iz, iz2 = iz * iz;
                             const double fx = cam.fx, fy = cam.fy;
                             double vp[3];
                             vp[0] = fx * iz * G9[0];
@@ -645,12 +719,19 @@ void project_bwd_impl(Ctx* c, const gs_gaussians* g, const gs_cameras* cams, con
     const dim3 grid(std::min((g->N + kBlock - 1) / kBlock, 1024)), block(kBlock);
     const gs_gaussians_grad none{};
     const AdamGauss no_adam{};
-    if (adam)
-        hipLaunchKernelGGL((k_project_bwd<DEG, true>), grid, block, 0, st, *g, cams->viewmat, cams->intr,
-                           vt, rp, c->grad2d, none, 0, *adam, c->twist_render);
-    else
-        hipLaunchKernelGGL((k_project_bwd<DEG, false>), grid, block, 0, st, *g, cams->viewmat,
-                           cams->intr, vt, rp, c->grad2d, *grads, accumulate, no_adam, c->twist_render);
+    if (adam) {
+        hipLaunchKernelGGL((k_project_bwd_color<DEG, true>), grid, block, 0, st, *g, cams->viewmat,
+                           cams->intr, vt, rp, c->grad2d, none, 0, *adam, c->vmu_dir, c->twist_render);
+        hipLaunchKernelGGL((k_project_bwd_geom<true>), grid, block, 0, st, *g, cams->viewmat, cams->intr,
+                           vt, rp, c->grad2d, none, 0, *adam, c->vmu_dir, c->twist_render);
+    } else {
+        hipLaunchKernelGGL((k_project_bwd_color<DEG, false>), grid, block, 0, st, *g, cams->viewmat,
+                           cams->intr, vt, rp, c->grad2d, *grads, accumulate, no_adam, c->vmu_dir,
+                           c->twist_render);
+        hipLaunchKernelGGL((k_project_bwd_geom<false>), grid, block, 0, st, *g, cams->viewmat,
+                           cams->intr, vt, rp, c->grad2d, *grads, accumulate, no_adam, c->vmu_dir,
+                           c->twist_render);
+    }
 }
 
 hipError_t launch_project_bwd(Ctx* c, const gs_gaussians* g, const gs_cameras* cams,
