@@ -305,10 +305,10 @@ __global__ __launch_bounds__(kBlock) void k_project_fwd(gs_gaussians g, const fl
 // means, 1 log_scales, 2 quats, 3 opacity_logit, 4 sh).  Adam batches issue
 // every parameter and moment load of a batch before the batch's stores; each
 // access is a uniform row base plus one 32-bit lane offset (N < 2^28).
-template <bool ADAM, int NE, int BATCH = 20, typename Arr, typename Row>
+template <bool ADAM, int NE, int BATCH = 20, bool HAS_P = false, typename Arr, typename Row>
 __device__ __forceinline__ void step_entries(const float (&gr)[NE], Arr arr, Row row, int i, int N,
                                              const AdamGauss& adam, const gs_gaussians_grad& out,
-                                             int accumulate) {
+                                             int accumulate, const float (&pval)[NE]) {
     const uint32_t off = (uint32_t)i * 4u;
     auto at = [&](float* base, int r) -> float& {
         return *reinterpret_cast<float*>(reinterpret_cast<char*>(base + (int64_t)r * N) + off);
@@ -321,7 +321,8 @@ __device__ __forceinline__ void step_entries(const float (&gr)[NE], Arr arr, Row
             for (int u = 0; u < BATCH; u++) {
                 const int j = j0 + u;
                 if (j < NE) {
-                    pb[u] = at(adam.p[arr(j)], row(j));
+                    // the parameter itself, when the caller still holds it
+                    pb[u] = HAS_P ? pval[j] : at(adam.p[arr(j)], row(j));
                     mb[u] = at(adam.m[arr(j)], row(j));
                     vb[u] = at(adam.v[arr(j)], row(j));
                 }
@@ -395,7 +396,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_color(gs_gaussians g, co
         float v_mu[3] = {0.f, 0.f, 0.f};
         // ---- colour
         {
-            float sh[K][3];
+            float sh[3 * K];  // coefficient k, channel ch at 3 k + ch
             float v_sh[3 * K];
 #pragma unroll
             for (int j = 0; j < 3 * K; j++) v_sh[j] = 0.f;
@@ -403,7 +404,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_color(gs_gaussians g, co
 #pragma unroll
                 for (int k = 0; k < K; k++)
 #pragma unroll
-                    for (int ch = 0; ch < 3; ch++) sh[k][ch] = g.sh[((int64_t)k * 3 + ch) * N + i];
+                    for (int ch = 0; ch < 3; ch++) sh[3 * k + ch] = g.sh[((int64_t)k * 3 + ch) * N + i];
             }
             // the next view's colour gradients are requested ahead, as above
             float gcn[3];
@@ -437,7 +438,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_color(gs_gaussians g, co
                         for (int ch = 0; ch < 3; ch++) {
                             float sm = 0.f;
 #pragma unroll
-                            for (int k = 0; k < K; k++) sm += Y[k] * sh[k][ch];
+                            for (int k = 0; k < K; k++) sm += Y[k] * sh[3 * k + ch];
                             vr[ch] = (sm + 0.5f > 0.f) ? gc[ch] : 0.f;
                         }
                         float sk[K];
@@ -447,7 +448,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_color(gs_gaussians g, co
 #pragma unroll
                             for (int ch = 0; ch < 3; ch++) {
                                 v_sh[3 * k + ch] += Y[k] * vr[ch];
-                                sk[k] += vr[ch] * sh[k][ch];
+                                sk[k] += vr[ch] * sh[3 * k + ch];
                             }
                         }
                         float gd[3] = {0.f, 0.f, 0.f};
@@ -472,8 +473,8 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_color(gs_gaussians g, co
             if (active) {
 #pragma unroll
                 for (int e = 0; e < 3; e++) vmu_dir[(int64_t)e * N + i] = v_mu[e];
-                step_entries<ADAM, 3 * K, 12>(v_sh, [](int) { return 4; }, [](int j) { return j; }, i, N, adam,
-                                              out, accumulate);
+                step_entries<ADAM, 3 * K, 8, true>(v_sh, [](int) { return 4; }, [](int j) { return j; }, i, N,
+                                                    adam, out, accumulate, sh);
             }
         }
     }
@@ -687,7 +688,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_geom(gs_gaussians g, con
                 step_entries<ADAM>(
                     gr, [](int j) { return j < 3 ? 0 : j < 6 ? 1 : j < 10 ? 2 : 3; },
                     [](int j) { return j < 3 ? j : j < 6 ? j - 3 : j < 10 ? j - 6 : 0; }, i, N, adam, out,
-                    accumulate);
+                    accumulate, gr);
             }
         }
     }

@@ -187,7 +187,8 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
                 // rest), so sigma >= 0 needs no test of its own
                 const float e2 = splat_e2(qa, qb, qc, dx, dy);
                 if (e2 < cut) continue;
-                const float alpha = fminf(amax, o * __builtin_amdgcn_exp2f(e2));
+                // min(amax, o 2^e2) as one median (the product is >= 0)
+                const float alpha = __builtin_amdgcn_fmed3f(o * __builtin_amdgcn_exp2f(e2), 0.f, amax);
                 if (alpha < amin) continue;
                 const float Tn = T[k] * (1.f - alpha);
                 if (Tn < tmin) {
@@ -329,7 +330,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ re
                 const float e2 = splat_e2(qa, qb, qc, dx, dy);
                 const float ex = __builtin_amdgcn_exp2f(e2);
                 const float araw = o * ex;
-                const float alpha = fminf(amax, araw);
+                const float alpha = __builtin_amdgcn_fmed3f(araw, 0.f, amax);
                 // same decisions as the forward: before the pixel's last
                 // contributor and above the alpha gate
                 const bool live = pos < L[k] && alpha >= amin;
