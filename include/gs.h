@@ -119,8 +119,9 @@ typedef struct {
                                  list length, 16 buckets per octave (bucket of n > 0:
                                  1 + 16 floor(log2 n) + the 4 bits after n's leading
                                  bit; 0 for an empty list), any order inside a bucket */
-    int32_t eval_stats;       /* 0; 1: gs_render_fwd also counts each tile's (pixel,
-                                 splat) evaluations (gs_ctx_tile_stats), a slower variant */
+    int32_t eval_stats;       /* 0; 1: gs_render_fwd also counts per tile the contributing
+                                 pairs, list entries read and (pixel, splat) evaluations
+                                 (gs_ctx_tile_stats), a slower variant */
 } gs_settings;
 
 typedef struct {
@@ -193,14 +194,14 @@ gs_status gs_ctx_reset_status(gs_ctx* ctx, void* stream);
 gs_status gs_ctx_buffers(gs_ctx* ctx, float** records, int32_t** isect_ids,
                          int32_t** tile_ranges, int64_t* n_tiles);
 
-/* Workload statistics of the last gs_render_fwd (device pointers, valid for
- * the context's lifetime): tile_contrib[t] = number of (pixel, splat) pairs
+/* Workload statistics of the last gs_render_fwd run with settings
+ * eval_stats = 1 (device pointers, valid for the context's lifetime; the
+ * plain forward leaves them as they were): tile_contrib[t] = number of (pixel, splat) pairs
  * that contributed to tile t; tile_entries[t] = entries of tile t's list the
  * forward read (up to the batch in which its last pixel stopped);
  * tile_evals[t] = sum over tile t's pixels of the entries of its list, up to
  * the pixel's last contributor, whose mask covers the pixel's quadrant (the
- * (pixel, splat) evaluations the definition makes, forward or backward; only
- * written by a forward with settings eval_stats = 1);
+ * (pixel, splat) evaluations the definition makes, forward or backward);
  * tile_order = launch order of the tiles when the last gs_bin_sort ran with
  * tile_order = 1 (*ordered = 1), heaviest first as gs_settings.tile_order
  * describes; n_tiles = tiles of

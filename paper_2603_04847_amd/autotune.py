@@ -22,10 +22,11 @@ def _need(step, b):
     return st["n_isect_needed"]
 
 
-def autotune(step, shapes=TILE_SHAPES, orders=(0, 1), iters=3, batch=0, big=None):
-    """Time each (tile shape, order) on `step` (a JointStep) and leave the
-    fastest in step.settings with a tight capacity.  Returns the timings."""
-    P = step.cams[batch].n_pixels
+def autotune(step, shapes=TILE_SHAPES, orders=(0, 1), iters=3, big=None):
+    """Time each (tile shape, order) on `step` (a JointStep) over every batch
+    of views (`iters` rounds; their loads differ) and leave the fastest in
+    step.settings with a tight capacity.  Returns the timings."""
+    P = max(c.n_pixels for c in step.cams)
     big = big or min(2**30 - 65536, 64 * P)
     results = []
     for tw, th in shapes:
@@ -35,17 +36,20 @@ def autotune(step, shapes=TILE_SHAPES, orders=(0, 1), iters=3, batch=0, big=None
         step.set_capacity(int(need * 1.15) + 4096)
         for order in orders:
             step.settings = L.default_settings(tile_w=tw, tile_h=th, tile_order=order)
-            step.forward_backward(batch)
+            nb = len(step.batches)
+            for bb in range(nb):
+                step.forward_backward(bb)
             torch.cuda.synchronize()
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
             a.record()
             for _ in range(iters):
-                step.forward_backward(batch)
+                for bb in range(nb):
+                    step.forward_backward(bb)
             b.record()
             torch.cuda.synchronize()
             results.append(dict(tile=(tw, th), order=order, need=int(need),
-                                ms=a.elapsed_time(b) / iters))
+                                ms=a.elapsed_time(b) / (iters * nb)))
     best = min(results, key=lambda r: r["ms"])
     tw, th = best["tile"]
     step.settings = L.default_settings(tile_w=tw, tile_h=th, tile_order=best["order"])

@@ -6,9 +6,9 @@
 // quadrants; every list entry carries the quadrants its splat reaches, and a
 // slot whose quadrants the splat misses is skipped by the whole wave.  The
 // tile's list is consumed in batches of 64: each lane loads one splat record
-// (a gather of 40 B) and the wave then walks the batch with the splat's
-// parameters broadcast by readlane, i.e. held in scalar registers, so every
-// pixel of the tile tests each splat with no LDS traffic at all.  The next
+// (a gather of 40 B) and stages it in the wave's own LDS region; the wave then
+// walks the batch reading each splat's parameters with broadcast LDS loads
+// (one address for all lanes), synchronising only with itself.  The next
 // batch's list entries are requested right after the current records, so
 // their latency hides behind the compositing.  The backward walks the same
 // lists back to front from each pixel's last contributor, recovering the
@@ -201,25 +201,29 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
                 C2[k] = __builtin_fmaf(cb, w, C2[k]);
                 T[k] = Tn;
                 last[k] = pos;
-                if (EVALS) lastq[k] = qn[k];
-                ncontrib++;
+                if (EVALS) {
+                    lastq[k] = qn[k];
+                    ncontrib++;
+                }
             }
         }
     }
-    // workload statistics of the tile: contributing (pixel, splat) pairs, list
-    // entries read, and (pixel, entry) evaluations up to each pixel's last
-    // contributor over the entries covering its quadrant
-    int nev = 0;
+    // workload statistics of the tile (the counting variant only): contributing
+    // (pixel, splat) pairs, list entries read, and (pixel, entry) evaluations
+    // up to each pixel's last contributor over the entries covering its quadrant
+    if (EVALS) {
+        int nev = 0;
 #pragma unroll
-    for (int k = 0; k < PPL; k++) nev += lastq[k];
-    for (int sh = 32; sh > 0; sh >>= 1) {
-        ncontrib += __shfl_xor(ncontrib, sh, kWave);
-        nev += __shfl_xor(nev, sh, kWave);
-    }
-    if (lane == 0) {
-        tile_contrib[t] = ncontrib;
-        tile_entries[t] = nent;
-        if (EVALS) tile_evals[t] = nev;
+        for (int k = 0; k < PPL; k++) nev += lastq[k];
+        for (int sh = 32; sh > 0; sh >>= 1) {
+            ncontrib += __shfl_xor(ncontrib, sh, kWave);
+            nev += __shfl_xor(nev, sh, kWave);
+        }
+        if (lane == 0) {
+            tile_contrib[t] = ncontrib;
+            tile_entries[t] = nent;
+            tile_evals[t] = nev;
+        }
     }
     const float b0 = bg ? bg[0] : 0.f, b1 = bg ? bg[1] : 0.f, b2 = bg ? bg[2] : 0.f;
 #pragma unroll
@@ -297,6 +301,15 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ re
     __shared__ BatchLds sb;
     int b = s + ((lmax - 1) / kWave) * kWave;
     uint32_t idn = batch_ids(ids, b, s, top);
+    // per-lane sums over the lane's pixels for the current splat: colour
+    // weights, q = dL/dalpha e^-sigma (zero where alpha is clamped), and the
+    // moments q dx, q dy, q dx^2, q dx dy, q dy^2; the exponent's gradient is
+    // -o q, so the mean and conic gradients follow from these after the wave
+    // sum.  They are zero at every splat's start: a splat nobody contributes
+    // to leaves them untouched, one that is summed clears them afterwards.
+    float g_r = 0.f, g_g = 0.f, g_b = 0.f, g_o = 0.f;
+    float m_x = 0.f, m_y = 0.f, m_xx = 0.f, m_xy = 0.f, m_yy = 0.f;
+    bool any = false;
     for (; b >= s; b -= kWave) {
         const uint32_t id = idn;
         const int nb = min(kWave, top - b);
@@ -315,13 +328,6 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ re
             const float mx = f0.x, my = f0.y, o = f0.z;
             const float qa = f1.x, qb = f1.y, qc = f1.z, cr = f1.w, cg = f2.x, cb = f2.y;
             const int pos = b + i - s;
-            // per-lane sums over the lane's pixels: colour weights, q = dL/dalpha
-            // e^-sigma (zero where alpha is clamped), and the moments q dx, q dy,
-            // q dx^2, q dx dy, q dy^2; the exponent's gradient is -o q, so the
-            // mean and conic gradients follow from these after the wave sum
-            float g_r = 0.f, g_g = 0.f, g_b = 0.f, g_o = 0.f;
-            float m_x = 0.f, m_y = 0.f, m_xx = 0.f, m_xy = 0.f, m_yy = 0.f;
-            bool any = false;
 #pragma unroll
             for (int k = 0; k < PPL; k++) {
                 if (!(m & TM::quads(k)) || pos >= Lk[k]) continue;  // wave-uniform
@@ -376,6 +382,9 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ re
                 const int64_t p = idb & kPairMask;
                 atomicAdd(grad2d + GS_GRAD2D_FLOATS * p + comp, val);
             }
+            g_r = g_g = g_b = g_o = 0.f;
+            m_x = m_y = m_xx = m_xy = m_yy = 0.f;
+            any = false;
         }
     }
 }
