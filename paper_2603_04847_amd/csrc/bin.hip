@@ -6,7 +6,8 @@
 //              depth bits; positive floats order like their bits).  Culled
 //              pairs get key 0xFFFFFFFF and no blocks.
 //  2. sort the pairs by depth key (stable LSD radix from pair order, so equal
-//     depths stay in pair order): this is the (depth, pair) order.
+//     depths stay in pair order): this is the (depth, pair) order.  The pair
+//     index and its block count travel with the key.
 //  3. scan the block counts in that order and emit one (block, pair, 64-bit
 //     quadrant mask) entry per block met, from the exact per-quadrant-row
 //     spans; entries of one pair are contiguous, pairs in depth order, and the
@@ -18,9 +19,10 @@
 //  5. block ranges from the boundaries of the sorted block ids.
 //  6. expand to tile lists, the definition: a tile's list is its block's list
 //     restricted to the entries whose mask meets one of the tile's four
-//     quadrants.  One workgroup per block counts its 16 tiles' entries, a scan
-//     places the lists, and a second pass writes (pair | 4-bit mask << 28) in
-//     block-list order.  Sorting (block, pair) entries instead of (tile, pair)
+//     quadrants.  Per 256-entry chunk of the sorted block array, the entries
+//     touching each of a block's 16 tiles are counted; scans of those counts
+//     and of the tile totals place every entry, written as (pair | 4-bit mask
+//     << 28) in block-list order.  Sorting (block, pair) entries instead of (tile, pair)
 //     ones moves about a quarter of the data through the radix passes.
 #include <algorithm>
 
@@ -128,21 +130,6 @@ __global__ __launch_bounds__(kBlock) void k_count(const float4* __restrict__ rec
     }
 }
 
-// entry counts in depth order; also the number of visible pairs (they sort first)
-__global__ __launch_bounds__(kBlock) void k_gather_cnt(const uint32_t* __restrict__ order,
-                                                       const uint32_t* __restrict__ keys,
-                                                       const uint32_t* __restrict__ cnt,
-                                                       uint32_t* __restrict__ out, int64_t n,
-                                                       uint32_t* __restrict__ diag) {
-    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (r >= n) return;
-    out[r] = cnt[order[r]];
-    const bool vis = keys[r] != 0xFFFFFFFFu;
-    const bool next_vis = (r + 1 < n) && keys[r + 1] != 0xFFFFFFFFu;
-    if (r == 0 && !vis) diag[kDiagVisible] = 0;
-    if (vis && !next_vis) diag[kDiagVisible] = (uint32_t)(r + 1);
-}
-
 // Capacity check of a list total.  `prev_over` (may be NULL) is the check of
 // an earlier stage: once that overflowed, the counts it reported stay (they
 // are a lower bound of the need) and this stage writes nothing.
@@ -163,13 +150,16 @@ __global__ void k_isect_total(const uint32_t* __restrict__ total, int64_t cap,
 }
 
 // One (block key; pair, mask) entry per block met, pairs in depth order: rank
-// r's entries fill [off[r], off[r] + cnt).  The 64 ranks of a wave own one
-// contiguous output range; in each round every lane takes one unit (block
-// row) and writes its entries at the unit's place in the wave's range.
+// r's entries fill [off[r], off[r + 1]) (the last rank ends at the total).  The
+// 64 ranks of a wave own one contiguous output range; in each round every lane
+// takes one unit (block row) and writes its entries at the unit's place in the
+// wave's range.  Counts come from adjacent offsets, so the only access by pair
+// index is the record.  Also reports the number of visible pairs (their depth
+// keys sort before the culled ones' 0xFFFFFFFF).
 __global__ __launch_bounds__(kBlock) void k_emit(const float4* __restrict__ rec, int N, ViewTable vt,
                                                  RasterParams rp, const uint32_t* __restrict__ order,
                                                  const uint32_t* __restrict__ off,
-                                                 const uint32_t* __restrict__ cnt, int64_t n,
+                                                 const uint32_t* __restrict__ keys, int64_t n,
                                                  const uint32_t* __restrict__ used,
                                                  uint32_t* __restrict__ okey,
                                                  uint32_t* __restrict__ opair,
@@ -187,10 +177,16 @@ __global__ __launch_bounds__(kBlock) void k_emit(const float4* __restrict__ rec,
     int v = 0;
     bool ok = false;
     uint32_t pair = 0, c = 0, o0 = 0xFFFFFFFFu;
+    if (r < n) {
+        const bool vis = keys[r] != 0xFFFFFFFFu;
+        const bool next_vis = r + 1 < n && keys[r + 1] != 0xFFFFFFFFu;
+        if (r == 0 && !vis) diag[kDiagVisible] = 0;
+        if (vis && !next_vis) diag[kDiagVisible] = (uint32_t)(r + 1);
+    }
     if (r < n && any) {
         pair = order[r];
-        c = cnt[pair];
         o0 = off[r];
+        c = (r + 1 < n ? off[r + 1] : *used) - o0;
         if (c > 0) {
             a = rec[3 * (int64_t)pair];
             b = rec[3 * (int64_t)pair + 1];
@@ -606,21 +602,24 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
         const unsigned gp = (unsigned)((npairs + kBlock - 1) / kBlock);
         hipLaunchKernelGGL(k_count, dim3(gp), dim3(kBlock), 0, st, rec, N, vt, rp, c->cnt, c->pk[0],
                            c->pv[0]);
-        const int side = radix_sort_pairs(c->pk[0], c->pv[0], c->pk[1], c->pv[1], npairs, nullptr,
-                                          0, 32, c->hist, c->scan_scratch, c->diag + kDiagFlags, st, &e);
+        // the pair and its entry count travel with the depth key; the sorted
+        // counts are then scanned in place into the entry offsets
+        uint32_t* PK[2] = {c->pk[0], c->pk[1]};
+        uint32_t* PV[2][2] = {{c->pv[0], c->pv[1]}, {c->cnt, c->off}};
+        const int side = radix_sort_kv2(PK, PV, npairs, nullptr, 0, 32, c->hist, c->scan_scratch,
+                                        c->diag + kDiagFlags, st, &e);
         if (e != hipSuccess) return e;
         const uint32_t* order = c->pv[side];
-        hipLaunchKernelGGL(k_gather_cnt, dim3(gp), dim3(kBlock), 0, st, order, c->pk[side], c->cnt,
-                           c->off, npairs, c->diag);
+        uint32_t* off = PV[1][side];
         uint32_t* total = c->scalars + 0;
         uint32_t* used = c->scalars + 1;
-        if ((e = exclusive_scan_u32(c->off, npairs, total, c->scan_scratch, c->diag + kDiagFlags, st)) != hipSuccess)
+        if ((e = exclusive_scan_u32(off, npairs, total, c->scan_scratch, c->diag + kDiagFlags, st)) != hipSuccess)
             return e;
         hipLaunchKernelGGL(k_isect_total, dim3(1), dim3(64), 0, st, total, c->cap.max_isect, used,
                            c->diag, nullptr, nullptr);
         const int64_t I = c->cap.max_isect;
-        hipLaunchKernelGGL(k_emit, dim3(gp), dim3(kBlock), 0, st, rec, N, vt, rp, order, c->off,
-                           c->cnt, npairs, used, c->ik[0], c->iv[0], c->im[0], c->im[0] + I, c->diag);
+        hipLaunchKernelGGL(k_emit, dim3(gp), dim3(kBlock), 0, st, rec, N, vt, rp, order, off,
+                           c->pk[side], npairs, used, c->ik[0], c->iv[0], c->im[0], c->im[0] + I, c->diag);
         int bbits = 1;  // block ids and the sentinel NB
         while (((int64_t)1 << bbits) <= NB) bbits++;
         // the pair and both mask words travel with the block key

@@ -69,14 +69,18 @@ __device__ __forceinline__ float wave_sum(float v) {
     return bcast(v, 63);
 }
 
-// Wave totals of eight per-lane values in about a third of the instructions of
-// eight separate sums: the set is halved by exchanging with the quad partner
-// lane^1 and lane^2 (keeping the half picked by that lane bit) and with the
-// lane four places round the 16-lane row, then summed over the row (rotate by
-// 8) and across rows (xor 16, xor 32).  On return lane l holds the total of
-// value sum8_index(l) = bit-reverse of (l & 7).
-__device__ __forceinline__ float wave_sum8_t(float a0, float a1, float a2, float a3, float a4, float a5,
-                                             float a6, float a7) {
+// Wave totals of nine per-lane values in about a third of the instructions of
+// nine separate sums.  The first eight are halved three times by exchanging
+// with the quad partner lane^1 and lane^2 (keeping the half picked by that lane
+// bit) and with the lane four places round the 16-lane row; the ninth is summed
+// over its quads alone; both are then summed over the row (rotate by 8).  The
+// last two steps need no LDS: v_permlane16_swap swaps the odd rows of one
+// register with the even rows of another (rows 0 and 2 then hold the eight,
+// rows 1 and 3 the ninth), and v_permlane32_swap the upper half of one with
+// the lower half of another.  On return lanes 0-15 and 32-47 hold the total of
+// value sum8_index(lane & 7), lanes 16-31 and 48-63 the total of a8.
+__device__ __forceinline__ float wave_sum9_t(float a0, float a1, float a2, float a3, float a4, float a5,
+                                             float a6, float a7, float a8) {
     const int lane = __lane_id();
     const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
     const float c0 = (b0 ? a4 : a0) + dpp_f<0xB1>(b0 ? a0 : a4);
@@ -87,9 +91,17 @@ __device__ __forceinline__ float wave_sum8_t(float a0, float a1, float a2, float
     const float d1 = (b1 ? c3 : c1) + dpp_f<0x4E>(b1 ? c1 : c3);
     float e = (b2 ? d1 : d0) + dpp_f<0x124>(b2 ? d0 : d1);  // row_ror:4
     e += dpp_f<0x128>(e);                                     // row_ror:8
-    e += __shfl_xor(e, 16, kWave);
-    e += __shfl_xor(e, 32, kWave);
-    return e;
+    float z = a8 + dpp_f<0xB1>(a8);
+    z += dpp_f<0x4E>(z);
+    z += dpp_f<0x124>(z);
+    z += dpp_f<0x128>(z);
+    // (the pair's elements are copied out before any bit cast)
+    const auto r16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(e), __float_as_uint(z), false, false);
+    const unsigned s0 = r16[0], s1 = r16[1];
+    const float f = __uint_as_float(s0) + __uint_as_float(s1);
+    const auto r32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(f), __float_as_uint(f), false, false);
+    const unsigned t0 = r32[0], t1 = r32[1];
+    return __uint_as_float(t0) + __uint_as_float(t1);
 }
 
 __device__ __forceinline__ int sum8_index(int lane) {
@@ -377,6 +389,10 @@ int radix_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int
 // The same with three value words per item (separate arrays): K[side],
 // V[word][side]; returns the side holding the result.
 int radix_sort_kv3(uint32_t* K[2], uint32_t* V[3][2], int64_t max_n, const uint32_t* d_n, int lo,
+                   int hi, uint32_t* hist, uint32_t* scan_scratch, uint32_t* flags, hipStream_t st,
+                   hipError_t* err);
+// ... and with two
+int radix_sort_kv2(uint32_t* K[2], uint32_t* V[2][2], int64_t max_n, const uint32_t* d_n, int lo,
                    int hi, uint32_t* hist, uint32_t* scan_scratch, uint32_t* flags, hipStream_t st,
                    hipError_t* err);
 

@@ -13,7 +13,8 @@
 // their latency hides behind the compositing.  The backward walks the same
 // lists back to front from each pixel's last contributor, recovering the
 // transmittance by division, and sums each splat's nine 2D gradients over the
-// whole wave (DPP) before one lane per component issues the global atomic.
+// whole wave (DPP and lane-swap steps) before one lane per component issues
+// the global atomic.
 #include <algorithm>
 
 #include "gs_internal.h"
@@ -289,15 +290,26 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ re
     }
     // per slot, the largest `last` of its pixels: past it the whole wave skips
     // the slot (all its pixels are behind their last contributor)
+    // (wave-uniform: read from the first lane, so the loops below stay scalar)
     int Lk[PPL];
 #pragma unroll
-    for (int k = 0; k < PPL; k++) Lk[k] = wave_max_i(L[k]);
-    lmax = wave_max_i(lmax);
+    for (int k = 0; k < PPL; k++) Lk[k] = __builtin_amdgcn_readfirstlane(wave_max_i(L[k]));
+    lmax = __builtin_amdgcn_readfirstlane(wave_max_i(lmax));
     const int s = ranges[2 * t], e = ranges[2 * t + 1];
     lmax = min(lmax, e - s);  // a pixel's last contributor lies inside its tile's list
     if (lmax <= 0) return;
     const float amin = rp.alpha_min, amax = rp.alpha_max;
     const int top = s + lmax;  // entries [s, top) can matter
+    // The gradient component this lane adds after each splat's wave sum E
+    // (lanes 0-7 hold value sum8_index(lane), lane 16 the blue sum; the rest
+    // add none): 0 mean.x, 1 mean.y, 2 A, 3 B, 4 C, 5 opacity, 6 r, 7 g, 8 b.
+    // It is E (kS o + kE) + o ln2 ((ua a + ub b) QX + (vb b + vc c) QY) with
+    // QX, QY the first two moments, so every lane runs the same instructions.
+    const int comp = lane < 8 ? sum8_index(lane) : lane == 16 ? 8 : -1;
+    const float kS = (comp == 2 || comp == 4) ? -0.5f : comp == 3 ? -1.f : 0.f;
+    const float kE = comp >= 5 ? 1.f : 0.f;
+    const float ua = comp == 0 ? 2.f : 0.f, ub = comp == 1 ? 1.f : 0.f;
+    const float vb = comp == 0 ? 1.f : 0.f, vc = comp == 1 ? 2.f : 0.f;
     __shared__ BatchLds sb;
     int b = s + ((lmax - 1) / kWave) * kWave;
     uint32_t idn = batch_ids(ids, b, s, top);
@@ -364,21 +376,15 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ re
                 }
             }
             if (__ballot(any) == 0) continue;
-            // wave totals: eight through one transposed butterfly, blue on its own
-            const float e8 = wave_sum8_t(m_x, m_y, m_xx, m_xy, m_yy, g_o, g_r, g_g);
-            const float tb = wave_sum(g_b);
-            const float QX = bcast(e8, 0), QY = bcast(e8, 4);  // lanes holding m_x, m_y
-            if (lane < 9) {
-                // component: 0 mean.x, 1 mean.y, 2 A, 3 B, 4 C, 5 opacity, 6 r, 7 g, 8 b.
+            // wave totals of the nine sums in one transposed butterfly
+            const float E = wave_sum9_t(m_x, m_y, m_xx, m_xy, m_yy, g_o, g_r, g_g, g_b);
+            const float QX = bcast(E, 0), QY = bcast(E, 4);  // lanes holding m_x, m_y
+            if (comp >= 0) {
                 // With vs = -o q the sums of vs dx, vs dy, ... are -o times the
                 // moments; A = -2 a / log2(e), B = -b / log2(e), C = -2 c / log2(e).
-                const int comp = lane < 8 ? sum8_index(lane) : 8;
-                const float ko = o * kLn2;
-                const float val = comp == 0 ? ko * __builtin_fmaf(2.f * qa, QX, qb * QY)
-                                : comp == 1 ? ko * __builtin_fmaf(qb, QX, 2.f * qc * QY)
-                                : (comp == 2 || comp == 4) ? -0.5f * o * e8
-                                : comp == 3 ? -o * e8
-                                : comp == 8 ? tb : e8;
+                const float mean = __builtin_fmaf(__builtin_fmaf(ua, qa, ub * qb), QX,
+                                                  __builtin_fmaf(vb, qb, vc * qc) * QY);
+                const float val = __builtin_fmaf(o * kLn2, mean, E * __builtin_fmaf(kS, o, kE));
                 const int64_t p = idb & kPairMask;
                 atomicAdd(grad2d + GS_GRAD2D_FLOATS * p + comp, val);
             }

@@ -429,4 +429,10 @@ int radix_sort_kv3(uint32_t* K[2], uint32_t* V[3][2], int64_t max_n, const uint3
     return radix_sort_impl<3>(K, V, max_n, d_n, lo, hi, hist, scan_scratch, flags, st, err);
 }
 
+int radix_sort_kv2(uint32_t* K[2], uint32_t* V[2][2], int64_t max_n, const uint32_t* d_n, int lo,
+                   int hi, uint32_t* hist, uint32_t* scan_scratch, uint32_t* flags, hipStream_t st,
+                   hipError_t* err) {
+    return radix_sort_impl<2>(K, V, max_n, d_n, lo, hi, hist, scan_scratch, flags, st, err);
+}
+
 }  // namespace gs
