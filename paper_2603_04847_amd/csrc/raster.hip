@@ -59,25 +59,18 @@ struct TileMap {
     }
 };
 
-// base-2 exponent below which o 2^e2 < alpha_min for sure (a conservative bound:
-// it only lets the exact test run less often, never changes its outcome)
-__device__ __forceinline__ float e2_cut(float o, float amin) {
-    return -(__log2f(o / amin) * 1.00001f + 1.5e-5f);
-}
-
 // One splat record as a lane loads it: position, opacity, the base-2 conic,
-// colour, and the fast-reject bound.
+// colour.
 struct LaneSplat {
-    float mx, my, o, a, b, c, cr, cg, cb, cut;
+    float mx, my, o, a, b, c, cr, cg, cb;
 };
 
-__device__ __forceinline__ LaneSplat load_splat(const float4* __restrict__ rec, uint32_t pair,
-                                                float amin) {
+__device__ __forceinline__ LaneSplat load_splat(const float4* __restrict__ rec, uint32_t pair) {
     const int64_t p = pair;
     const float4 ra = rec[3 * p], rb = rec[3 * p + 1];
     const float2 rc = *reinterpret_cast<const float2*>(rec + 3 * p + 2);
     const ConicE2 q = conic_e2(rb.x, rb.y, rb.z);
-    return {ra.x, ra.y, ra.w, q.a, q.b, q.c, rb.w, rc.x, rc.y, e2_cut(ra.w, amin)};
+    return {ra.x, ra.y, ra.w, q.a, q.b, q.c, rb.w, rc.x, rc.y};
 }
 
 // The raster workgroup is one wave: ordering its LDS accesses needs no
@@ -89,7 +82,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // A batch's splats staged in LDS, one entry per lane as three float4:
-// (mx, my, o, cut), (a, b, c, r), (g, b, -, -).  Entry i is then read by the
+// (mx, my, o, -), (a, b, c, r), (g, b, -, -).  Entry i is then read by the
 // whole wave from one address (a broadcast), not gathered by readlane.
 struct BatchLds {
     float4 f[3][kWave];
@@ -97,7 +90,7 @@ struct BatchLds {
 
 __device__ __forceinline__ void stage_splat(BatchLds& sb, const LaneSplat& ls) {
     const int lane = threadIdx.x;
-    sb.f[0][lane] = make_float4(ls.mx, ls.my, ls.o, ls.cut);
+    sb.f[0][lane] = make_float4(ls.mx, ls.my, ls.o, 0.f);
     sb.f[1][lane] = make_float4(ls.a, ls.b, ls.c, ls.cr);
     sb.f[2][lane] = make_float4(ls.cg, ls.cb, 0.f, 0.f);
 }
@@ -164,7 +157,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
         const int nb = min(kWave, e - b);
         {
             LaneSplat ls = {};
-            if (lane < nb) ls = load_splat(rec, id & kPairMask, amin);
+            if (lane < nb) ls = load_splat(rec, id & kPairMask);
             wave_lds_sync();  // the previous batch is read
             stage_splat(sb, ls);
         }
@@ -174,37 +167,39 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
         for (int i = 0; i < nb; i++) {
             const uint32_t m = (uint32_t)bcast((int)id, i) >> kPairBits;
             const float4 f0 = sb.f[0][i], f1 = sb.f[1][i], f2 = sb.f[2][i];
-            const float mx = f0.x, my = f0.y, o = f0.z, cut = f0.w;
+            const float mx = f0.x, my = f0.y, o = f0.z;
             const float qa = f1.x, qb = f1.y, qc = f1.z, cr = f1.w, cg = f2.x, cb = f2.y;
             const int pos = b + i - s + 1;
 #pragma unroll
             for (int k = 0; k < PPL; k++) {
                 if (!(m & TM::quads(k))) continue;  // wave-uniform
                 if (EVALS) qn[k]++;
-                if (done[k]) continue;
+                if (__ballot(!done[k]) == 0) continue;  // wave-uniform: the slot has stopped
                 const float dx = mx - fx[k];
                 const float dy = my - fy[k];
                 // listed splats have positive-definite conics (binning drops the
                 // rest), so sigma >= 0 needs no test of its own
                 const float e2 = splat_e2(qa, qb, qc, dx, dy);
-                if (e2 < cut) continue;
                 // min(amax, o 2^e2) as one median (the product is >= 0)
                 const float alpha = __builtin_amdgcn_fmed3f(o * __builtin_amdgcn_exp2f(e2), 0.f, amax);
-                if (alpha < amin) continue;
                 const float Tn = T[k] * (1.f - alpha);
-                if (Tn < tmin) {
-                    done[k] = true;
-                    continue;
-                }
-                const float w = alpha * T[k];
-                C0[k] = __builtin_fmaf(cr, w, C0[k]);
-                C1[k] = __builtin_fmaf(cg, w, C1[k]);
-                C2[k] = __builtin_fmaf(cb, w, C2[k]);
-                T[k] = Tn;
-                last[k] = pos;
-                if (EVALS) {
-                    lastq[k] = qn[k];
-                    ncontrib++;
+                // the gate; then the splat that would take T below t_min stops
+                // the pixel instead of contributing.  Decided without branches,
+                // one branch for the update.
+                const bool gate = !done[k] && alpha >= amin;
+                const bool stop = gate && Tn < tmin;
+                done[k] = done[k] || stop;
+                if (gate && !stop) {
+                    const float w = alpha * T[k];
+                    C0[k] = __builtin_fmaf(cr, w, C0[k]);
+                    C1[k] = __builtin_fmaf(cg, w, C1[k]);
+                    C2[k] = __builtin_fmaf(cb, w, C2[k]);
+                    T[k] = Tn;
+                    last[k] = pos;
+                    if (EVALS) {
+                        lastq[k] = qn[k];
+                        ncontrib++;
+                    }
                 }
             }
         }
@@ -327,7 +322,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ re
         const int nb = min(kWave, top - b);
         {
             LaneSplat ls = {};
-            if (lane < nb) ls = load_splat(rec, id & kPairMask, amin);
+            if (lane < nb) ls = load_splat(rec, id & kPairMask);
             wave_lds_sync();  // the previous batch is read
             stage_splat(sb, ls);
         }
