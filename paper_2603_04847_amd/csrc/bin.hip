@@ -457,20 +457,29 @@ __global__ __launch_bounds__(kBlock) void k_chunk_bases(const uint32_t* __restri
 // to every sub-tile of its block it touches, at the place the prefixes give.
 // One wave per chunk, four entries per lane, every load of the chunk (entries
 // and its sub-tiles' bases) issued at once; the running counts per sub-tile
-// are wave-uniform.
+// are wave-uniform.  A chunk inside one block (nearly all) is staged in LDS
+// grouped by sub-tile (the group sizes are differences of the chunk prefixes)
+// and written out with dense stores, 64 consecutive staged entries per store,
+// which land in at most a few contiguous runs; chunks that span blocks, or
+// whose entries would overflow the stage, store each entry directly.
+constexpr int kStage = 2048;  // staged tile entries per wave
+
 __global__ __launch_bounds__(kBlock) void k_chunk_expand(
     const uint32_t* __restrict__ bkey, const uint32_t* __restrict__ pairs,
     const uint32_t* __restrict__ mlo, const uint32_t* __restrict__ mhi,
     const uint32_t* __restrict__ used, const uint32_t* __restrict__ tused,
     const uint32_t* __restrict__ cpre, const uint32_t* __restrict__ tbase,
     const uint32_t* __restrict__ cb, uint32_t NB, uint32_t* __restrict__ tids) {
+    __shared__ uint32_t s_stage[kWaves][kStage];
+    __shared__ uint32_t s_gpre[kWaves][kBlockSub + 1];  // group starts in the stage
+    __shared__ uint32_t s_gbase[kWaves][kBlockSub];     // group starts in the lists
     if (*tused == 0u) return;  // nothing is written after an overflow
     const int64_t n = *used;
     const int64_t stride = chunk_stride(used);
-    const int lane = threadIdx.x % kWave;
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     const uint64_t lt = lanemask_lt();
     const int64_t nw = (int64_t)gridDim.x * kWaves;
-    for (int64_t c = (int64_t)blockIdx.x * kWaves + threadIdx.x / kWave; c * kChunk < n; c += nw) {
+    for (int64_t c = (int64_t)blockIdx.x * kWaves + w; c * kChunk < n; c += nw) {
         uint64_t m[kChunkSteps];
         uint32_t B[kChunkSteps], pr[kChunkSteps];
 #pragma unroll
@@ -483,7 +492,10 @@ __global__ __launch_bounds__(kBlock) void k_chunk_expand(
             // sentinel entries (unfilled slots) have B = NB and no mask
             m[u] = (j < n && B[u] < NB) ? mm : 0ull;
         }
-        const uint32_t cbq = cb[c * kBlockSub + (lane % kBlockSub)];
+        const int ql = lane % kBlockSub;
+        const uint32_t cbq = cb[c * kBlockSub + ql];
+        // this chunk's entries touching sub-tile ql: a difference of its prefixes
+        const uint32_t cq = cpre[(int64_t)ql * stride + c + 1] - cpre[(int64_t)ql * stride + c];
         const uint32_t B0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)B[0]);
         bool other = false;
 #pragma unroll
@@ -491,7 +503,44 @@ __global__ __launch_bounds__(kBlock) void k_chunk_expand(
         uint32_t run[kBlockSub];  // entries of the chunk so far touching sub-tile q
 #pragma unroll
         for (int q = 0; q < kBlockSub; q++) run[q] = 0;
-        if (__ballot(other) == 0) {
+        // group starts: exclusive prefix of the counts over sub-tiles (lanes 0-15)
+        uint32_t inc = lane < kBlockSub ? cq : 0u;
+#pragma unroll
+        for (int off = 1; off < kBlockSub; off <<= 1) {
+            const uint32_t t = __shfl_up(inc, off, kWave);
+            if (lane >= off) inc += t;
+        }
+        const uint32_t staged = (uint32_t)__builtin_amdgcn_readlane((int)inc, kBlockSub - 1);
+        if (__ballot(other) == 0 && staged <= (uint32_t)kStage) {
+            if (lane < kBlockSub) {
+                s_gpre[w][lane + 1] = inc;
+                s_gbase[w][lane] = cbq;
+            }
+            if (lane == 0) s_gpre[w][0] = 0u;
+#pragma unroll
+            for (int u = 0; u < kChunkSteps; u++) {
+#pragma unroll
+                for (int q = 0; q < kBlockSub; q++) {
+                    const uint64_t bal = __ballot(touches(m[u], q));
+                    if (bal == 0) continue;  // wave-uniform
+                    const uint32_t m4 = tile_bits(m[u], q % kBlockTiles, q / kBlockTiles);
+                    // group q starts after the counts of sub-tiles 0 .. q-1
+                    const uint32_t g0 = q == 0 ? 0u : (uint32_t)__builtin_amdgcn_readlane((int)inc, q - 1);
+                    if (m4) s_stage[w][g0 + run[q] + (uint32_t)__popcll(bal & lt)] = pr[u] | (m4 << kPairBits);
+                    run[q] += (uint32_t)__popcll(bal);
+                }
+            }
+            wave_lds_sync();
+            // staged entry f belongs to the group whose start is the last <= f
+            for (uint32_t f = lane; f < staged; f += kWave) {
+                int q = 0;
+#pragma unroll
+                for (int h = kBlockSub / 2; h > 0; h >>= 1)
+                    if (s_gpre[w][q + h] <= f) q += h;
+                tids[s_gbase[w][q] + (f - s_gpre[w][q])] = s_stage[w][f];
+            }
+            wave_lds_sync();  // the stage is read before the next chunk's writes
+        } else if (__ballot(other) == 0) {
 #pragma unroll
             for (int u = 0; u < kChunkSteps; u++) {
 #pragma unroll

@@ -118,6 +118,14 @@ __device__ __forceinline__ int wave_max_i(int v) {
     return v;
 }
 
+// Orders one wave's own LDS accesses (its stores before its later loads) with
+// no workgroup barrier, which would also wait for the loads in flight.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
     const int lane = __lane_id();
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));

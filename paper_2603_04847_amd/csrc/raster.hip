@@ -73,14 +73,6 @@ __device__ __forceinline__ LaneSplat load_splat(const float4* __restrict__ rec, 
     return {ra.x, ra.y, ra.w, q.a, q.b, q.c, rb.w, rc.x, rc.y};
 }
 
-// The raster workgroup is one wave: ordering its LDS accesses needs no
-// workgroup barrier (which would also wait for the loads in flight).
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // A batch's splats staged in LDS, one entry per lane as three float4:
 // (mx, my, o, -), (a, b, c, r), (g, b, -, -).  Entry i is then read by the
 // whole wave from one address (a broadcast), not gathered by readlane.
