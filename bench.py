@@ -113,7 +113,8 @@ def run_joint(torch, name, steps, warmup, tune=True, tile=None, order=0, graph=T
     if tune and tile is None:
         results, best = autotune(st)
         tuning = dict(best=f"{best['tile'][0]}x{best['tile'][1]} order={best['order']}",
-                      candidates={f"{r['tile'][0]}x{r['tile'][1]}/{r['order']}": round(r["ms"], 3)
+                      candidates={f"{r['tile'][0]}x{r['tile'][1]}/{'-' if r['order'] is None else r['order']}":
+                                  (round(r["ms"], 3) if r["ms"] is not None else r["skipped"])
                                   for r in results})
     else:
         need = 0

@@ -152,6 +152,42 @@ def test_bin_sort_bit_exact_with_many_scan_tiles(gs):
         assert np.array_equal(ent >> 28, masks_o.astype(np.uint32)), rep
 
 
+def test_bin_sort_bit_exact_with_wide_splats(gs):
+    """Most splats cover the whole view, so a 256-entry chunk of a block list
+    holds more tile entries than the expansion stages in LDS (2048): those
+    chunks take the direct-store path, the rest the staged one; lists stay
+    bit-exact."""
+    wh = np.array([[256, 192]], np.int32)
+    N = 2000
+    r = scenegen.synthetic_records(13, 1, wh, N, tile=(16, 16))
+    huge = np.random.default_rng(5).uniform(size=N) < 0.6
+    r["conic"][huge] = np.array([1e-8, 0.0, 1e-8], np.float32)  # support far beyond the view
+    rec = np.zeros((N, 12), np.float32)
+    rec[:, 0:2] = r["mean2d"]
+    rec[:, 2] = r["depth"]
+    rec[:, 3] = np.where(r["valid"] > 0, r["opacity"], 0.0)
+    rec[:, 4:7] = r["conic"]
+    rec[:, 7:10] = r["rgb"]
+    ctx = gs.Context(max_pairs=N, max_isect=2_000_000, max_tiles=10_000, max_views=1)
+    s = gs.default_settings(tile_w=16, tile_h=16)
+    cams = gs.Cameras(_t(np.zeros((1, 12))), _t(np.zeros((1, 4))), wh)
+    gs.gs_bin_sort(ctx, cams, N, s, _t(rec))
+    st = ctx.status()
+    assert st["flags"] == 0
+    ranges_o, ids_o, masks_o = oracle.bin_sort(wh, (16, 16), r["valid"], r["mean2d"], r["conic"],
+                                               r["opacity"], r["depth"], with_masks=True)
+    # a block list of ~1200 whole-view splats: 16 tile entries per block entry
+    assert len(ids_o) > 150_000
+    assert st["n_isect"] == len(ids_o)
+    b = ctx.buffers()
+    T = b["n_tiles"]
+    ranges = _read_i32(b["tile_ranges"], 2 * T).reshape(T, 2)
+    ent = _read_i32(b["isect_ids"], len(ids_o)).view(np.uint32)
+    assert np.array_equal(ranges, ranges_o.astype(np.int32))
+    assert np.array_equal(ent & 0x0FFFFFFF, ids_o.astype(np.uint32))
+    assert np.array_equal(ent >> 28, masks_o.astype(np.uint32))
+
+
 def _read_i32(ptr, n):
     import paper_2603_04847_amd._lib as L
     return L.copy_to_host(ptr, n, np.int32)
