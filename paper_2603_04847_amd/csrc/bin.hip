@@ -93,7 +93,11 @@ __global__ __launch_bounds__(kBlock) void k_count(const float4* __restrict__ rec
                                                   ViewTable vt, RasterParams rp,
                                                   uint32_t* __restrict__ cnt,
                                                   uint32_t* __restrict__ key,
-                                                  uint32_t* __restrict__ val) {
+                                                  uint32_t* __restrict__ val,
+                                                  int32_t* __restrict__ branges, int64_t nbr) {
+    // the block ranges start empty (the sorted keys fill the blocks that have entries)
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < nbr; k += (int64_t)gridDim.x * kBlock)
+        branges[k] = 0;
     __shared__ WaveUnits s_wu[kWaves];
     __shared__ uint32_t s_cnt[kWaves][kWave];
     const int64_t pair = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -127,25 +131,6 @@ __global__ __launch_bounds__(kBlock) void k_count(const float4* __restrict__ rec
         cnt[pair] = c;
         key[pair] = c > 0 ? __float_as_uint(a.z) : 0xFFFFFFFFu;
         val[pair] = (uint32_t)pair;
-    }
-}
-
-// Capacity check of a list total.  `prev_over` (may be NULL) is the check of
-// an earlier stage: once that overflowed, the counts it reported stay (they
-// are a lower bound of the need) and this stage writes nothing.
-__global__ void k_isect_total(const uint32_t* __restrict__ total, int64_t cap,
-                              uint32_t* __restrict__ used, uint32_t* __restrict__ diag,
-                              const uint32_t* __restrict__ prev_total,
-                              const uint32_t* __restrict__ prev_used) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        const uint32_t t = *total;
-        const bool prev_over = prev_total && *prev_total != 0u && *prev_used == 0u;
-        const bool over = prev_over || (int64_t)t > cap;
-        *used = over ? 0u : t;
-        if (prev_over) return;
-        diag[kDiagIsectTotal] = t;
-        diag[kDiagIsectUsed] = over ? 0u : t;
-        if (over) atomicOr(&diag[kDiagFlags], (uint32_t)GS_FLAG_ISECT_OVERFLOW);
     }
 }
 
@@ -408,21 +393,37 @@ __global__ __launch_bounds__(kWave) void k_block_tiles(const int32_t* __restrict
     }
 }
 
+// Launch order of the tiles, heaviest first.  The weight is a log-scale bucket
+// of the list length, exact in integers: 16 buckets per octave from the leading
+// bit and the four bits after it (0 for an empty list).  Inside a bucket the
+// order is free: tiles are independent, so it never changes a result.
+__device__ __forceinline__ uint32_t length_bucket(uint32_t len) {
+    if (len == 0) return 0;
+    const int msb = 31 - __clz(len);
+    const uint32_t frac = msb >= 4 ? (len >> (msb - 4)) & 15u : (len << (4 - msb)) & 15u;
+    return 1u + 16u * (uint32_t)msb + frac;  // <= 1 + 16*31 + 15 = 512
+}
 // Tile ranges from the scanned counts (empty everywhere after an overflow),
-// and for each (block, sub-tile) the base that turns a prefix P_q(j) into the
-// entry's slot: tile start - P_q(start of the block).
+// for each (block, sub-tile) the base that turns a prefix P_q(j) into the
+// entry's slot: tile start - P_q(start of the block), and, if `bucket` is set,
+// each tile's launch-order weight.
 __global__ __launch_bounds__(kBlock) void k_tile_ranges(const uint32_t* __restrict__ toff,
                                                         const uint32_t* __restrict__ total,
                                                         const uint32_t* __restrict__ used,
                                                         ViewTable vt, int TH, int64_t T,
                                                         const uint32_t* __restrict__ bpre,
                                                         int32_t* __restrict__ tranges,
-                                                        uint32_t* __restrict__ tbase) {
+                                                        uint32_t* __restrict__ tbase,
+                                                        uint32_t* __restrict__ bucket) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t >= T) return;
     const bool ok = *used != 0u || *total == 0u;
-    tranges[2 * t] = ok ? (int32_t)toff[t] : 0;
-    tranges[2 * t + 1] = ok ? (int32_t)(t + 1 < T ? toff[t + 1] : *total) : 0;
+    const int32_t ts = ok ? (int32_t)toff[t] : 0;
+    const int32_t te = ok ? (int32_t)(t + 1 < T ? toff[t + 1] : *total) : 0;
+    tranges[2 * t] = ts;
+    tranges[2 * t + 1] = te;
+    // the launch-order weight of the tile (when an order is asked for)
+    if (bucket) bucket[t] = length_bucket((uint32_t)max(te - ts, 0));
     int v = 0;
     while (v + 1 < vt.V && t >= vt.tile_off[v + 1]) v++;
     const int lt = (int)t - vt.tile_off[v];
@@ -575,26 +576,8 @@ __global__ __launch_bounds__(kBlock) void k_chunk_expand(
     }
 }
 
-// Launch order of the tiles, heaviest first.  The weight is a log-scale bucket
-// of the list length, exact in integers: 16 buckets per octave from the leading
-// bit and the four bits after it (0 for an empty list).  Inside a bucket the
-// order is free: tiles are independent, so it never changes a result.
-__device__ __forceinline__ uint32_t length_bucket(uint32_t len) {
-    if (len == 0) return 0;
-    const int msb = 31 - __clz(len);
-    const uint32_t frac = msb >= 4 ? (len >> (msb - 4)) & 15u : (len << (4 - msb)) & 15u;
-    return 1u + 16u * (uint32_t)msb + frac;  // <= 1 + 16*31 + 15 = 512
-}
 constexpr int kOrderBuckets = 513;
 constexpr int kOrderThreads = 1024;
-
-// Bucket of each tile's weight (its list length).
-__global__ __launch_bounds__(kBlock) void k_tile_bucket(const int32_t* __restrict__ tranges,
-                                                        int64_t T, uint32_t* __restrict__ bucket) {
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (t >= T) return;
-    bucket[t] = length_bucket((uint32_t)max(tranges[2 * t + 1] - tranges[2 * t], 0));
-}
 
 // One block: histogram of the buckets, their scan from the heaviest down, and
 // a scatter through LDS cursors.  For up to 2^20 tiles.
@@ -643,14 +626,11 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
     const int64_t T = vt.tile_off[vt.V];
     const int64_t NB = vt.block_off[vt.V];
     hipError_t e = hipSuccess;
-    // block ranges start empty
-    if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(c->ranges), 0u, 2 * NB, st)) != hipSuccess)
-        return e;
     c->ordered = false;
     if (npairs > 0) {
         const unsigned gp = (unsigned)((npairs + kBlock - 1) / kBlock);
         hipLaunchKernelGGL(k_count, dim3(gp), dim3(kBlock), 0, st, rec, N, vt, rp, c->cnt, c->pk[0],
-                           c->pv[0]);
+                           c->pv[0], c->ranges, 2 * NB);
         // the pair and its entry count travel with the depth key; the sorted
         // counts are then scanned in place into the entry offsets
         uint32_t* PK[2] = {c->pk[0], c->pk[1]};
@@ -662,10 +642,11 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
         uint32_t* off = PV[1][side];
         uint32_t* total = c->scalars + 0;
         uint32_t* used = c->scalars + 1;
-        if ((e = exclusive_scan_u32(off, npairs, total, c->scan_scratch, c->diag + kDiagFlags, st)) != hipSuccess)
+        // the scan's last tile checks the block-entry total against the capacity
+        const CapCheck chk_blocks = {c->cap.max_isect, used, c->diag, nullptr, nullptr};
+        if ((e = exclusive_scan_u32(off, npairs, total, c->scan_scratch, c->diag + kDiagFlags, st,
+                                    &chk_blocks)) != hipSuccess)
             return e;
-        hipLaunchKernelGGL(k_isect_total, dim3(1), dim3(64), 0, st, total, c->cap.max_isect, used,
-                           c->diag, nullptr, nullptr);
         const int64_t I = c->cap.max_isect;
         hipLaunchKernelGGL(k_emit, dim3(gp), dim3(kBlock), 0, st, rec, N, vt, rp, order, off,
                            c->pk[side], npairs, used, c->ik[0], c->iv[0], c->im[0], c->im[0] + I, c->diag);
@@ -694,18 +675,19 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
             if ((e = exclusive_scan_u32_dev(c->ccnt, kBlockSub * (nch + 1), used, kChunk, kBlockSub, 1,
                                             nullptr, c->scan_scratch, c->diag + kDiagFlags, st)) != hipSuccess)
                 return e;
-            if ((e = launch_fill_u32(c->tcnt, 0u, T, st)) != hipSuccess) return e;
+            // every tile's count is written by its block's k_block_tiles
             if (NB > 0)
                 hipLaunchKernelGGL(k_block_tiles, dim3((unsigned)NB), dim3(kWave), 0, st, c->ranges, bmlo,
                                    bmhi, c->ccnt, used, vt, rp.tile_h, c->bpre, c->bplace, c->tcnt);
-            if ((e = exclusive_scan_u32(c->tcnt, T, ttotal, c->scan_scratch, c->diag + kDiagFlags, st)) != hipSuccess)
-                return e;
             // the tile lists must fit too (their total replaces the block count)
-            hipLaunchKernelGGL(k_isect_total, dim3(1), dim3(64), 0, st, ttotal, c->cap.max_isect, tused,
-                               c->diag, total, used);
+            const CapCheck chk_tiles = {c->cap.max_isect, tused, c->diag, total, used};
+            if ((e = exclusive_scan_u32(c->tcnt, T, ttotal, c->scan_scratch, c->diag + kDiagFlags, st,
+                                        &chk_tiles)) != hipSuccess)
+                return e;
             const unsigned gt = (unsigned)((T + kBlock - 1) / kBlock);
+            const bool bucketed = tile_order && T <= ((int64_t)1 << 20);
             hipLaunchKernelGGL(k_tile_ranges, dim3(gt), dim3(kBlock), 0, st, c->tcnt, ttotal, tused, vt,
-                               rp.tile_h, T, c->bpre, c->tranges, c->tbase);
+                               rp.tile_h, T, c->bpre, c->tranges, c->tbase, bucketed ? c->tk[0] : nullptr);
             hipLaunchKernelGGL(k_chunk_bases, dim3((unsigned)((nch * kBlockSub + kBlock - 1) / kBlock)),
                                dim3(kBlock), 0, st, c->ik[side2], used, c->ccnt, c->tbase, (uint32_t)NB, nch,
                                c->cbase);
@@ -713,8 +695,7 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
                                bmhi, used, tused, c->ccnt, c->tbase, c->cbase, (uint32_t)NB, c->tids);
         }
         if (tile_order && T > 0 && T <= ((int64_t)1 << 20)) {
-            hipLaunchKernelGGL(k_tile_bucket, dim3((unsigned)((T + kBlock - 1) / kBlock)), dim3(kBlock),
-                               0, st, c->tranges, T, c->tk[0]);
+            // the weights were written with the tile ranges
             hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, st, c->tk[0], T,
                                c->tile_order);
             c->ordered = true;

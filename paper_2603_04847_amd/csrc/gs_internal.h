@@ -380,8 +380,20 @@ size_t scan_scratch_words(int64_t max_n);
 // total.  scratch: scan_scratch_words(n) words, zero before the first scan and
 // left zero by every scan; flags (device, nullable) gets GS_FLAG_SCAN_STALLED
 // if a look-back gave up.
+// Capacity check of a list total, run by the scan's last tile: used = total
+// if it fits cap, else 0 with GS_FLAG_ISECT_OVERFLOW; the totals go to
+// diag[kDiagIsectTotal / kDiagIsectUsed].  Once an earlier stage (prev_total,
+// prev_used; both may be NULL) overflowed, its counts stay (a lower bound of
+// the need) and this stage only sets used = 0.
+struct CapCheck {
+    int64_t cap;
+    uint32_t* used;  // NULL: no check
+    uint32_t* diag;
+    const uint32_t* prev_total;
+    const uint32_t* prev_used;
+};
 hipError_t exclusive_scan_u32(uint32_t* data, int64_t n, uint32_t* total_out, uint32_t* scratch,
-                              uint32_t* flags, hipStream_t st);
+                              uint32_t* flags, hipStream_t st, const CapCheck* chk = nullptr);
 // The same over a length the device holds: mul * (ceil(*d_cnt / per) + add),
 // at most max_n (the launch covers max_n).
 hipError_t exclusive_scan_u32_dev(uint32_t* data, int64_t max_n, const uint32_t* d_cnt, int64_t per,

@@ -98,6 +98,17 @@ __device__ uint32_t wave_lookback(const uint64_t* words, int64_t t, uint32_t* fl
     return excl;
 }
 
+__device__ __forceinline__ void cap_check(uint32_t t, const CapCheck& c) {
+    if (!c.used) return;
+    const bool prev_over = c.prev_total && *c.prev_total != 0u && *c.prev_used == 0u;
+    const bool over = prev_over || (int64_t)t > c.cap;
+    *c.used = over ? 0u : t;
+    if (prev_over) return;
+    c.diag[kDiagIsectTotal] = t;
+    c.diag[kDiagIsectUsed] = over ? 0u : t;
+    if (over) atomicOr(&c.diag[kDiagFlags], (uint32_t)GS_FLAG_ISECT_OVERFLOW);
+}
+
 // 32 items per thread, read and written as 16-byte vectors: 8192 per tile
 constexpr int kScanItems = 32;
 constexpr int kScanTile = kThreads * kScanItems;
@@ -110,7 +121,7 @@ __global__ __launch_bounds__(kThreads) void k_scan(uint32_t* __restrict__ data, 
                                                    int64_t mul, int64_t add,
                                                    uint32_t* __restrict__ total_out,
                                                    uint32_t* __restrict__ ws,
-                                                   uint32_t* __restrict__ flags) {
+                                                   uint32_t* __restrict__ flags, CapCheck chk) {
     __shared__ uint32_t s_w[kWaves];
     __shared__ uint32_t s_t, s_excl, s_last;
     uint64_t* words = reinterpret_cast<uint64_t*>(ws + kScanHeader);
@@ -121,7 +132,10 @@ __global__ __launch_bounds__(kThreads) void k_scan(uint32_t* __restrict__ data, 
     __syncthreads();
     const int64_t t = s_t;
     if (t >= ntiles) {
-        if (t == 0 && total_out && threadIdx.x == 0) *total_out = 0u;
+        if (t == 0 && threadIdx.x == 0) {
+            if (total_out) *total_out = 0u;
+            cap_check(0u, chk);
+        }
     } else {
         const int64_t base = t * kScanTile + (int64_t)threadIdx.x * kScanItems;
         const bool full = base + kScanItems <= n;
@@ -151,7 +165,10 @@ __global__ __launch_bounds__(kThreads) void k_scan(uint32_t* __restrict__ data, 
             if (threadIdx.x == 0) {
                 if (t > 0) st_word(words + t, kIncl, excl + tot);
                 s_excl = excl;
-                if (t == ntiles - 1 && total_out) *total_out = excl + tot;
+                if (t == ntiles - 1) {
+                    if (total_out) *total_out = excl + tot;
+                    cap_check(excl + tot, chk);
+                }
             }
         }
         __syncthreads();
@@ -340,23 +357,37 @@ size_t scan_scratch_words(int64_t max_n) {
     return (size_t)kScanHeader + 2 * (size_t)((max_n + kScanTile - 1) / kScanTile) + 16;
 }
 
-hipError_t exclusive_scan_u32_dev(uint32_t* data, int64_t max_n, const uint32_t* d_cnt, int64_t per,
-                                  int64_t mul, int64_t add, uint32_t* total_out, uint32_t* scratch,
-                                  uint32_t* flags, hipStream_t st) {
-    if (max_n <= 0) return hipSuccess;
+namespace {
+
+hipError_t scan_launch(uint32_t* data, int64_t max_n, const uint32_t* d_cnt, int64_t per, int64_t mul,
+                       int64_t add, uint32_t* total_out, uint32_t* scratch, uint32_t* flags,
+                       hipStream_t st, const CapCheck* chk) {
+    CapCheck ck = {};
+    if (chk) ck = *chk;
+    // nothing to scan: done, unless a capacity check must still see the 0 total
+    if (max_n <= 0 && !ck.used) return hipSuccess;
+    if (max_n < 0) max_n = 0;
     // whole-tile vector accesses need 16-byte alignment
     if (reinterpret_cast<uintptr_t>(data) % 16 != 0 || (d_cnt && (per <= 0 || mul <= 0 || add < 0)))
         return hipErrorInvalidValue;
-    const int64_t nt = (max_n + kScanTile - 1) / kScanTile;
+    const int64_t nt = std::max<int64_t>((max_n + kScanTile - 1) / kScanTile, 1);
     if (nt > ((int64_t)1 << 31)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_scan, dim3((unsigned)nt), dim3(kThreads), 0, st, data, max_n, d_cnt, per, mul,
-                       add, total_out, scratch, flags);
+                       add, total_out, scratch, flags, ck);
     return hipGetLastError();
 }
 
+}  // namespace
+
+hipError_t exclusive_scan_u32_dev(uint32_t* data, int64_t max_n, const uint32_t* d_cnt, int64_t per,
+                                  int64_t mul, int64_t add, uint32_t* total_out, uint32_t* scratch,
+                                  uint32_t* flags, hipStream_t st) {
+    return scan_launch(data, max_n, d_cnt, per, mul, add, total_out, scratch, flags, st, nullptr);
+}
+
 hipError_t exclusive_scan_u32(uint32_t* data, int64_t n, uint32_t* total_out, uint32_t* scratch,
-                              uint32_t* flags, hipStream_t st) {
-    return exclusive_scan_u32_dev(data, n, nullptr, 1, 1, 0, total_out, scratch, flags, st);
+                              uint32_t* flags, hipStream_t st, const CapCheck* chk) {
+    return scan_launch(data, n, nullptr, 1, 1, 0, total_out, scratch, flags, st, chk);
 }
 
 size_t radix_hist_words(int64_t max_n) { return (size_t)256 * ((max_n + kTile - 1) / kTile) + 16; }
