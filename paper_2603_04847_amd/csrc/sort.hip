@@ -390,7 +390,8 @@ hipError_t exclusive_scan_u32(uint32_t* data, int64_t n, uint32_t* total_out, ui
     return scan_launch(data, n, nullptr, 1, 1, 0, total_out, scratch, flags, st, chk);
 }
 
-size_t radix_hist_words(int64_t max_n) { return (size_t)256 * ((max_n + kTile - 1) / kTile) + 16; }
+// sized for the smallest block (2048 items)
+size_t radix_hist_words(int64_t max_n) { return (size_t)256 * ((max_n + kTile / 2 - 1) / (kTile / 2)) + 16; }
 
 namespace {
 
@@ -430,10 +431,15 @@ int radix_sort_impl(uint32_t* K[2], uint32_t* V[NV][2], int64_t max_n, const uin
             va.out[c] = V[c][cur ^ 1];
         }
         // large single-value inputs: 8192 items per block (longer runs per
-        // digit in the scatter); wider payloads keep 4096 for the LDS staging
+        // digit in the scatter); the two-value (depth) sort uses 2048 so its
+        // few-million items still give every CU several blocks; the others
+        // keep 4096 for the LDS staging
         if (NV == 1 && max_n > ((int64_t)1 << 22))
             *err = radix_pass<32, NV>(K[cur], K[cur ^ 1], va, max_n, d_n, shift, bits, hist,
                                       scan_scratch, flags, st);
+        else if (NV == 2)
+            *err = radix_pass<8, NV>(K[cur], K[cur ^ 1], va, max_n, d_n, shift, bits, hist,
+                                     scan_scratch, flags, st);
         else
             *err = radix_pass<16, NV>(K[cur], K[cur ^ 1], va, max_n, d_n, shift, bits, hist,
                                       scan_scratch, flags, st);
