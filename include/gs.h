@@ -286,13 +286,27 @@ gs_status gs_l1_loss_grad(gs_ctx* ctx, const gs_cameras* cams, const float* rgb,
  *   J_pose[M][2][6]     = dr/dxi, J_X[M][2][3] = dr/dX        (may be NULL)
  * X[Pt][3] (points, kept separate from the Gaussian means), viewmat[n_cams][12],
  * intr[n_cams][4].  Observations must be sorted by camera (any order works,
- * sorted is faster). */
+ * sorted is faster).  pt_off / pt_obs (both NULL, or both set): a point-major
+ * index of the observations built by track_point_index for these obs_pt, M and
+ * Pt; with it v_X is summed per point (no atomics, a fixed order) instead of
+ * scattered with atomics per observation; the results agree up to rounding. */
 gs_status track_reproj_fwd_bwd(gs_ctx* ctx, const float* X, int32_t Pt,
                                const float* viewmat, const float* intr, int32_t n_cams,
                                const int32_t* obs_cam, const int32_t* obs_pt,
                                const float* obs_xy, int32_t M, float delta, float lambda,
                                float near_plane, float* residual, float* loss, float* v_X,
-                               float* v_twist, float* J_pose, float* J_X, void* stream);
+                               float* v_twist, float* J_pose, float* J_X,
+                               const int32_t* pt_off, const int32_t* pt_obs, void* stream);
+
+/* The point-major index of track observations that track_reproj_fwd_bwd can
+ * take (it depends on obs_pt only, so a scene builds it once):
+ * pt_off[Pt + 1] (device, 16-byte aligned): point k's observations are
+ * pt_obs[pt_off[k] .. pt_off[k + 1]), ascending; pt_obs[M] (device) receives
+ * pt_off[Pt] <= M indices (observations whose point is outside [0, Pt) are left
+ * out).  Both caller-owned.  GS_ERR_CAPACITY if Pt exceeds the context's
+ * max_pairs or its scan workspace. */
+gs_status track_point_index(gs_ctx* ctx, const int32_t* obs_pt, int32_t M, int32_t Pt,
+                            int32_t* pt_off, int32_t* pt_obs, void* stream);
 
 /* Pose composition T_i = Exp(dxi_i) T_i^(0) (Algorithm 1, pose adjustment,
  * with (+) read as left composition): twist[V][6] = (rho, phi), base[V][12],

@@ -80,7 +80,7 @@ EXPORTS = [
     "gs_strerror", "gs_default_settings", "gs_ctx_create", "gs_ctx_destroy", "gs_ctx_status",
     "gs_ctx_reset_status", "gs_ctx_buffers", "gs_ctx_tile_stats", "gs_project", "gs_bin_sort", "gs_render_fwd",
     "gs_render_bwd", "gs_raster_bwd", "gs_project_bwd", "gs_l1_loss_grad", "track_reproj_fwd_bwd", "gs_pose_compose",
-    "gs_pose_compose_bwd", "gs_adam_step", "gs_project_bwd_adam",
+    "gs_pose_compose_bwd", "gs_adam_step", "gs_project_bwd_adam", "track_point_index",
 ]
 
 _lib = None
@@ -133,7 +133,9 @@ def load():
     lib.gs_l1_loss_grad.argtypes = [c_vp, ctypes.POINTER(gs_cameras), c_vp, c_vp, c_vp, c_vp, c_vp]
     lib.track_reproj_fwd_bwd.argtypes = [
         c_vp, c_vp, ctypes.c_int32, c_vp, c_vp, ctypes.c_int32, c_vp, c_vp, c_vp, ctypes.c_int32,
-        ctypes.c_float, ctypes.c_float, ctypes.c_float, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]
+        ctypes.c_float, ctypes.c_float, ctypes.c_float, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
+        c_vp, c_vp]
+    lib.track_point_index.argtypes = [c_vp, c_vp, ctypes.c_int32, ctypes.c_int32, c_vp, c_vp, c_vp]
     lib.gs_pose_compose.argtypes = [ctypes.c_int32, c_vp, c_vp, c_vp, c_vp]
     lib.gs_pose_compose_bwd.argtypes = [ctypes.c_int32, c_vp, c_vp, c_vp, c_vp]
     lib.gs_adam_step.argtypes = [ctypes.POINTER(gs_adam_group), ctypes.c_int32, ctypes.c_int32,
@@ -348,12 +350,27 @@ def gs_l1_loss_grad(ctx, cams, rgb, target, v_rgb, loss, stream=None):
 
 
 def track_reproj_fwd_bwd(ctx, X, viewmat, intr, obs_cam, obs_pt, obs_xy, delta, lam, near_plane,
-                         loss, v_X, v_twist, residual=None, J_pose=None, J_X=None, stream=None):
+                         loss, v_X, v_twist, residual=None, J_pose=None, J_X=None, pt_index=None,
+                         stream=None):
+    """pt_index: (pt_off, pt_obs) from track_point_index, or None."""
+    pt_off, pt_obs = pt_index if pt_index is not None else (None, None)
     _check("track_reproj_fwd_bwd", load().track_reproj_fwd_bwd(
         ctx.handle, _ptr(X), int(X.shape[0]), _ptr(viewmat), _ptr(intr), int(viewmat.shape[0]),
         _ptr(obs_cam), _ptr(obs_pt), _ptr(obs_xy), int(obs_cam.shape[0]), float(delta),
         float(lam), float(near_plane), _ptr(residual), _ptr(loss), _ptr(v_X), _ptr(v_twist),
-        _ptr(J_pose), _ptr(J_X), _stream(stream)))
+        _ptr(J_pose), _ptr(J_X), _ptr(pt_off), _ptr(pt_obs), _stream(stream)))
+
+
+def track_point_index(ctx, obs_pt, n_points, stream=None):
+    """The point-major index of the observations (pt_off [Pt + 1], pt_obs [M],
+    int32 device tensors) for track_reproj_fwd_bwd's pt_index."""
+    import torch
+    M = int(obs_pt.shape[0])
+    pt_off = torch.empty(int(n_points) + 1, dtype=torch.int32, device=obs_pt.device)
+    pt_obs = torch.empty(max(M, 1), dtype=torch.int32, device=obs_pt.device)
+    _check("track_point_index", load().track_point_index(
+        ctx.handle, _ptr(obs_pt), M, int(n_points), _ptr(pt_off), _ptr(pt_obs), _stream(stream)))
+    return pt_off, pt_obs
 
 
 def gs_pose_compose(twist, base, out, stream=None):

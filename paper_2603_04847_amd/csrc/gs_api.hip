@@ -197,6 +197,7 @@ gs_status gs_ctx_create(gs_ctx** out, const gs_capacity* cap) {
     // the largest scan: radix digit counts, chunk counts, pair counts or tiles
     const int64_t scanmax = std::max<int64_t>(std::max<int64_t>((int64_t)hw, 16 * (c.nchunks + 1)), sortmax);
     A(dalloc(&c.scan_scratch, gs::scan_scratch_words(scanmax)));
+    c.scan_max = scanmax;
     A(dalloc(&c.scalars, 16));
     const int nv = cap->max_views;
     const int nc = cap->max_cams > 0 ? cap->max_cams : 1;
@@ -409,16 +410,28 @@ gs_status track_reproj_fwd_bwd(gs_ctx* h, const float* X, int32_t Pt, const floa
                                const float* intr, int32_t n_cams, const int32_t* obs_cam,
                                const int32_t* obs_pt, const float* obs_xy, int32_t M, float delta,
                                float lambda, float near_plane, float* residual, float* loss,
-                               float* v_X, float* v_twist, float* J_pose, float* J_X, void* stream) {
+                               float* v_X, float* v_twist, float* J_pose, float* J_X,
+                               const int32_t* pt_off, const int32_t* pt_obs, void* stream) {
     if (!h || Pt < 0 || n_cams < 0 || M < 0) return GS_ERR_INVALID_ARG;
     if (M > 0 && (!X || !viewmat || !intr || !obs_cam || !obs_pt || !obs_xy)) return GS_ERR_INVALID_ARG;
     if (!(delta > 0.f) || !(near_plane > 0.f) || !isfinite(lambda)) return GS_ERR_INVALID_ARG;
     if (v_twist && n_cams > h->c.cap.max_cams) return GS_ERR_CAPACITY;
     if (!v_twist && M > 0) return GS_ERR_INVALID_ARG;  // the twist accumulator must be drained
     if (!loss && M > 0) return GS_ERR_INVALID_ARG;
+    if ((pt_off == nullptr) != (pt_obs == nullptr)) return GS_ERR_INVALID_ARG;  // both or neither
     return from_hip(gs::launch_track(&h->c, X, Pt, viewmat, intr, n_cams, obs_cam, obs_pt, obs_xy, M,
                                      delta, lambda, near_plane, residual, loss, v_X, v_twist, J_pose,
-                                     J_X, (hipStream_t)stream));
+                                     J_X, pt_off, pt_obs, (hipStream_t)stream));
+}
+
+gs_status track_point_index(gs_ctx* h, const int32_t* obs_pt, int32_t M, int32_t Pt, int32_t* pt_off,
+                            int32_t* pt_obs, void* stream) {
+    if (!h || M < 0 || Pt < 0 || !pt_off || (M > 0 && (!obs_pt || !pt_obs))) return GS_ERR_INVALID_ARG;
+    // the scan reads pt_off as 16-byte vectors
+    if (reinterpret_cast<uintptr_t>(pt_off) % 16 != 0) return GS_ERR_INVALID_ARG;
+    // cursors live in the pair-count buffer, the scan in the context's scratch
+    if ((int64_t)Pt > h->c.cap.max_pairs || (int64_t)Pt + 1 > h->c.scan_max) return GS_ERR_CAPACITY;
+    return from_hip(gs::launch_track_index(&h->c, obs_pt, M, Pt, pt_off, pt_obs, (hipStream_t)stream));
 }
 
 gs_status gs_pose_compose(int32_t V, const float* twist, const float* base, float* out, void* stream) {

@@ -444,7 +444,12 @@ hipError_t launch_track(Ctx* c, const float* X, int Pt, const float* viewmat, co
                         int n_cams, const int32_t* obs_cam, const int32_t* obs_pt,
                         const float* obs_xy, int M, float delta, float lambda, float near_plane,
                         float* residual, float* loss, float* v_X, float* v_twist, float* J_pose,
-                        float* J_X, hipStream_t st);
+                        float* J_X, const int32_t* pt_off, const int32_t* pt_obs, hipStream_t st);
+// Point-major index of the observations for launch_track: pt_off[Pt + 1],
+// pt_obs[M] (each point's observations ascending; out-of-range points left
+// out).  Uses c->cnt (>= Pt words) and the scan scratch (>= Pt + 1 items).
+hipError_t launch_track_index(Ctx* c, const int32_t* obs_pt, int M, int Pt, int32_t* pt_off,
+                              int32_t* pt_obs, hipStream_t st);
 
 // optim.hip
 hipError_t launch_pose_compose(int V, const float* twist, const float* base, float* out,
@@ -476,6 +481,7 @@ struct Ctx {
     uint32_t* tcnt;        // [max_tiles] tile list lengths, then their scan
     uint32_t* ccnt;        // [16][ceil(used / 256) + 1] sub-tile counts per 256-entry chunk, then their scan
     int64_t nchunks;       // max_isect / 256 + 1
+    int64_t scan_max;      // longest array the scan scratch covers
     uint32_t* cbase;       // [nchunks][16] list place of each chunk's first entry per sub-tile
     uint32_t* bpre;        // [max_tiles][16] sub-tile prefixes at each block's list start
     int4* bplace;          // [max_tiles] first tile, row stride, tiles across / down per block

@@ -8,7 +8,8 @@
 // words few.  A step whose lanes straddle a camera boundary uses per-lane
 // atomics.  Track-point gradients are
 // scattered with three float atomics per observation (points are spread, so
-// these rarely collide).
+// these rarely collide), or, given a point-major index of the observations,
+// summed per point by a kernel of their own with no atomics.
 #include <algorithm>
 
 #include "gs_internal.h"
@@ -20,6 +21,60 @@ namespace {
 constexpr int kBlock = 256;
 
 constexpr int kTrackBlocks = 1024;
+
+// One observation's terms, the same arithmetic for every kernel that needs
+// them: camera point p = R X + t; masked if p_z < near; else the residual r,
+// the Huber value rho and the 2D gradient g = d(lambda rho)/dr pushed through
+// the projection: vp = J_pi^T g (the gradient at p).
+struct ObsTerms {
+    float R[9], p[3];
+    float r0, r1, rho, j00, j02, j11, j12, vp[3];
+    bool masked;
+};
+
+__device__ __forceinline__ void obs_terms(const float* __restrict__ X, int k,
+                                          const float* __restrict__ viewmat,
+                                          const float* __restrict__ intr, int ci,
+                                          const float* __restrict__ obs_xy, int o, float delta,
+                                          float lambda, float near_plane, ObsTerms& T) {
+    float t[3];
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) T.R[3 * r + c] = viewmat[12 * ci + 4 * r + c];
+        t[r] = viewmat[12 * ci + 4 * r + 3];
+    }
+    const float fx = intr[4 * ci], fy = intr[4 * ci + 1], cx = intr[4 * ci + 2], cy = intr[4 * ci + 3];
+    const float Xk[3] = {X[3 * (int64_t)k], X[3 * (int64_t)k + 1], X[3 * (int64_t)k + 2]};
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+        T.p[r] = T.R[3 * r] * Xk[0] + T.R[3 * r + 1] * Xk[1] + T.R[3 * r + 2] * Xk[2] + t[r];
+    T.masked = !(T.p[2] >= near_plane);
+    if (T.masked) return;
+    const float iz = 1.f / T.p[2];
+    const float u = T.p[0] * iz, w = T.p[1] * iz;
+    T.r0 = fx * u + cx - obs_xy[2 * (int64_t)o];
+    T.r1 = fy * w + cy - obs_xy[2 * (int64_t)o + 1];
+    const float s = T.r0 * T.r0 + T.r1 * T.r1;
+    float drho;
+    if (s <= delta * delta) {
+        T.rho = s;
+        drho = 1.f;
+    } else {
+        const float rs = sqrtf(s);
+        T.rho = 2.f * delta * rs - delta * delta;
+        drho = delta / rs;
+    }
+    // J_pi (2x3) = [[fx/z, 0, -fx x/z^2], [0, fy/z, -fy y/z^2]]
+    T.j00 = fx * iz;
+    T.j02 = -fx * u * iz;
+    T.j11 = fy * iz;
+    T.j12 = -fy * w * iz;
+    const float g0 = 2.f * lambda * drho * T.r0, g1 = 2.f * lambda * drho * T.r1;
+    T.vp[0] = T.j00 * g0;
+    T.vp[1] = T.j11 * g1;
+    T.vp[2] = T.j02 * g0 + T.j12 * g1;
+}
 
 __global__ __launch_bounds__(kBlock) void k_track(
     const float* __restrict__ X, int Pt, const float* __restrict__ viewmat,
@@ -62,20 +117,9 @@ __global__ __launch_bounds__(kBlock) void k_track(
     float tw[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     bool masked = false;
     if (ok_idx) {
-        float R[9], t[3];
-#pragma unroll
-        for (int r = 0; r < 3; r++) {
-#pragma unroll
-            for (int c = 0; c < 3; c++) R[3 * r + c] = viewmat[12 * ci + 4 * r + c];
-            t[r] = viewmat[12 * ci + 4 * r + 3];
-        }
-        const float fx = intr[4 * ci], fy = intr[4 * ci + 1], cx = intr[4 * ci + 2],
-                    cy = intr[4 * ci + 3];
-        const float Xk[3] = {X[3 * (int64_t)k], X[3 * (int64_t)k + 1], X[3 * (int64_t)k + 2]};
-        float p[3];
-#pragma unroll
-        for (int r = 0; r < 3; r++) p[r] = R[3 * r] * Xk[0] + R[3 * r + 1] * Xk[1] + R[3 * r + 2] * Xk[2] + t[r];
-        masked = !(p[2] >= near_plane);
+        ObsTerms T;
+        obs_terms(X, k, viewmat, intr, ci, obs_xy, o, delta, lambda, near_plane, T);
+        masked = T.masked;
         if (masked) {
             n_masked++;
             if (residual) {
@@ -87,25 +131,10 @@ __global__ __launch_bounds__(kBlock) void k_track(
             if (J_X)
                 for (int e = 0; e < 6; e++) J_X[6 * (int64_t)o + e] = 0.f;
         } else {
-            const float iz = 1.f / p[2];
-            const float u = p[0] * iz, w = p[1] * iz;
-            const float r0 = fx * u + cx - obs_xy[2 * (int64_t)o];
-            const float r1 = fy * w + cy - obs_xy[2 * (int64_t)o + 1];
-            const float s = r0 * r0 + r1 * r1;
-            float rho, drho;
-            if (s <= delta * delta) {
-                rho = s;
-                drho = 1.f;
-            } else {
-                const float rs = sqrtf(s);
-                rho = 2.f * delta * rs - delta * delta;
-                drho = delta / rs;
-            }
-            lo_sum += lambda * rho;
-            // J_pi (2x3) = [[fx/z, 0, -fx x/z^2], [0, fy/z, -fy y/z^2]]
-            const float j00 = fx * iz, j02 = -fx * u * iz, j11 = fy * iz, j12 = -fy * w * iz;
-            const float g0 = 2.f * lambda * drho * r0, g1 = 2.f * lambda * drho * r1;
-            const float vp[3] = {j00 * g0, j11 * g1, j02 * g0 + j12 * g1};
+            const float* R = T.R;
+            const float* p = T.p;
+            const float* vp = T.vp;
+            lo_sum += lambda * T.rho;
             if (v_X) {
 #pragma unroll
                 for (int c = 0; c < 3; c++)
@@ -118,9 +147,10 @@ __global__ __launch_bounds__(kBlock) void k_track(
             tw[4] = p[2] * vp[0] - p[0] * vp[2];
             tw[5] = p[0] * vp[1] - p[1] * vp[0];
             if (residual) {
-                residual[2 * (int64_t)o] = r0;
-                residual[2 * (int64_t)o + 1] = r1;
+                residual[2 * (int64_t)o] = T.r0;
+                residual[2 * (int64_t)o + 1] = T.r1;
             }
+            const float j00 = T.j00, j02 = T.j02, j11 = T.j11, j12 = T.j12;
             if (J_pose) {
                 // dr/dxi = J_pi [I | -[p]x]
                 float* Jp = J_pose + 12 * (int64_t)o;
@@ -183,27 +213,124 @@ __global__ __launch_bounds__(kBlock) void k_track(
     }
 }
 
+// The track points' gradients from a point-major index of the observations
+// (pt_off[Pt + 1], pt_obs: a point's observations, ascending): one thread per
+// point recomputes its observations' terms and adds their sum once, with no
+// atomics, in a fixed order.
+__global__ __launch_bounds__(kBlock) void k_track_points(
+    const float* __restrict__ X, int Pt, const float* __restrict__ viewmat,
+    const float* __restrict__ intr, int n_cams, const int32_t* __restrict__ obs_cam,
+    const float* __restrict__ obs_xy, const int32_t* __restrict__ pt_off,
+    const int32_t* __restrict__ pt_obs, float delta, float lambda, float near_plane,
+    float* __restrict__ v_X) {
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= Pt) return;
+    float acc[3] = {0.f, 0.f, 0.f};
+    const int j1 = pt_off[k + 1];
+    for (int j = pt_off[k]; j < j1; j++) {
+        const int o = pt_obs[j];
+        const int ci = obs_cam[o];
+        if (ci < 0 || ci >= n_cams) continue;
+        ObsTerms T;
+        obs_terms(X, k, viewmat, intr, ci, obs_xy, o, delta, lambda, near_plane, T);
+        if (T.masked) continue;
+#pragma unroll
+        for (int c = 0; c < 3; c++) acc[c] += T.R[c] * T.vp[0] + T.R[3 + c] * T.vp[1] + T.R[6 + c] * T.vp[2];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; c++) v_X[3 * (int64_t)k + c] += acc[c];
+}
+
+// The point-major index: counts per point, their scan, a fill through one
+// cursor per point, then each point's observations sorted ascending.
+__global__ __launch_bounds__(kBlock) void k_pt_count(const int32_t* __restrict__ obs_pt, int M, int Pt,
+                                                     int32_t* __restrict__ cnt) {
+    const int o = blockIdx.x * kBlock + threadIdx.x;
+    if (o >= M) return;
+    const int k = obs_pt[o];
+    if (k >= 0 && k < Pt) atomicAdd(&cnt[k], 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_pt_fill(const int32_t* __restrict__ obs_pt, int M, int Pt,
+                                                    const int32_t* __restrict__ pt_off,
+                                                    uint32_t* __restrict__ cursor,
+                                                    int32_t* __restrict__ pt_obs) {
+    const int o = blockIdx.x * kBlock + threadIdx.x;
+    if (o >= M) return;
+    const int k = obs_pt[o];
+    if (k >= 0 && k < Pt) pt_obs[pt_off[k] + (int)atomicAdd(&cursor[k], 1u)] = o;
+}
+
+__global__ __launch_bounds__(kBlock) void k_pt_sort(int Pt, const int32_t* __restrict__ pt_off,
+                                                    int32_t* __restrict__ pt_obs) {
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= Pt) return;
+    const int j0 = pt_off[k], j1 = pt_off[k + 1];
+    for (int j = j0 + 1; j < j1; j++) {  // insertion sort: tracks are short
+        const int v = pt_obs[j];
+        int i = j - 1;
+        while (i >= j0 && pt_obs[i] > v) {
+            pt_obs[i + 1] = pt_obs[i];
+            i--;
+        }
+        pt_obs[i + 1] = v;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_track(Ctx* c, const float* X, int Pt, const float* viewmat, const float* intr,
                         int n_cams, const int32_t* obs_cam, const int32_t* obs_pt,
                         const float* obs_xy, int M, float delta, float lambda, float near_plane,
                         float* residual, float* loss, float* v_X, float* v_twist, float* J_pose,
-                        float* J_X, hipStream_t st) {
+                        float* J_X, const int32_t* pt_off, const int32_t* pt_obs, hipStream_t st) {
+    const bool indexed = pt_off && pt_obs && v_X;
     if (M > 0) {
+        // with the point index the point gradients come from k_track_points
         hipLaunchKernelGGL(k_track, dim3(std::min((M + kBlock - 1) / kBlock, kTrackBlocks)),
                            dim3(kBlock), 0, st, X, Pt,
                            viewmat, intr, n_cams, obs_cam, obs_pt, obs_xy, M, delta, lambda,
-                           near_plane, residual, v_X, J_pose, J_X, c->twist_track,
+                           near_plane, residual, indexed ? nullptr : v_X, J_pose, J_X, c->twist_track,
                            c->loss_acc + 1, c->diag);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
+        if (indexed && Pt > 0) {
+            hipLaunchKernelGGL(k_track_points, dim3((Pt + kBlock - 1) / kBlock), dim3(kBlock), 0, st, X,
+                               Pt, viewmat, intr, n_cams, obs_cam, obs_xy, pt_off, pt_obs, delta, lambda,
+                               near_plane, v_X);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
     }
     hipError_t e = hipSuccess;
     if (v_twist && (e = launch_flush_acc(c->twist_track, v_twist, 6 * n_cams, st)) != hipSuccess)
         return e;
     if (loss) return launch_flush_acc(c->loss_acc + 1, loss, 1, st);
     return hipSuccess;
+}
+
+hipError_t launch_track_index(Ctx* c, const int32_t* obs_pt, int M, int Pt, int32_t* pt_off,
+                              int32_t* pt_obs, hipStream_t st) {
+    // counts in pt_off[0, Pt) (pt_off[Pt] = 0), their exclusive scan (pt_off[Pt]
+    // becomes the number indexed), then the fill through cursors in c->cnt
+    hipError_t e;
+    if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(pt_off), 0u, (int64_t)Pt + 1, st)) != hipSuccess)
+        return e;
+    if (Pt == 0) return hipSuccess;
+    if ((e = launch_fill_u32(c->cnt, 0u, Pt, st)) != hipSuccess) return e;
+    const unsigned gm = (unsigned)((M + kBlock - 1) / kBlock), gp = (unsigned)((Pt + kBlock - 1) / kBlock);
+    if (M > 0) {
+        hipLaunchKernelGGL(k_pt_count, dim3(gm), dim3(kBlock), 0, st, obs_pt, M, Pt, pt_off);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if ((e = exclusive_scan_u32(reinterpret_cast<uint32_t*>(pt_off), (int64_t)Pt + 1, nullptr,
+                                c->scan_scratch, c->diag + kDiagFlags, st)) != hipSuccess)
+        return e;
+    if (M > 0) {
+        hipLaunchKernelGGL(k_pt_fill, dim3(gm), dim3(kBlock), 0, st, obs_pt, M, Pt, pt_off, c->cnt, pt_obs);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_pt_sort, dim3(gp), dim3(kBlock), 0, st, Pt, pt_off, pt_obs);
+    return hipGetLastError();
 }
 
 }  // namespace gs

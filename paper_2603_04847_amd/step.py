@@ -74,6 +74,9 @@ class JointStep:
         self._cap = dict(max_pairs=Vb * self.N, max_tiles=tiles, max_views=Vb,
                          max_cams=self.n_cams)
         self.ctx = L.Context(max_isect=max_isect or 32 * P, **self._cap)
+        # the observations' point-major index (fixed for the scene): the track
+        # term then sums each point's gradient without atomics
+        self.pt_index = L.track_point_index(self.ctx, self.obs_pt, int(self.X.shape[0]))
         self.rgb = torch.empty((P, 3), device=device)
         self.T = torch.empty((P,), device=device)
         self.last = torch.empty((P,), device=device, dtype=torch.int32)
@@ -143,7 +146,7 @@ class JointStep:
         with t("track"):
             L.track_reproj_fwd_bwd(self.ctx, self.X, self.viewmat, self.intr, self.obs_cam,
                                    self.obs_pt, self.obs_xy, self.delta, self.lam, 0.01,
-                                   self.loss[1:2], self.v_X, self.v_tw_cur)
+                                   self.loss[1:2], self.v_X, self.v_tw_cur, pt_index=self.pt_index)
         with t("pose_compose_bwd"):
             L.gs_pose_compose_bwd(self.twist, self.v_tw_cur, self.v_tw)
         del P

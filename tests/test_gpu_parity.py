@@ -479,6 +479,52 @@ def test_track_matches_oracle(gs):
     _close(Jx.cpu().numpy().reshape(M, 2, 3), o["J_X"], what="J_X")
 
 
+def test_track_point_index_is_a_stable_csr(gs):
+    """The point-major index equals a stable sort of the observations by point
+    (each point's observations ascending); out-of-range points are left out."""
+    rng = np.random.default_rng(21)
+    Pt, M = 5000, 40000
+    obs_pt = rng.integers(-3, Pt + 3, size=M).astype(np.int32)
+    ctx = gs.Context(max_pairs=Pt, max_isect=1 << 16, max_tiles=16, max_views=1, max_cams=8)
+    pt_off, pt_obs = gs.track_point_index(ctx, _t(obs_pt, torch.int32), Pt)
+    torch.cuda.synchronize()
+    ok = (obs_pt >= 0) & (obs_pt < Pt)
+    order = np.argsort(np.where(ok, obs_pt, Pt), kind="stable")[: int(ok.sum())]
+    counts = np.bincount(obs_pt[ok], minlength=Pt)
+    off_ref = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    assert np.array_equal(pt_off.cpu().numpy(), off_ref)
+    assert np.array_equal(pt_obs.cpu().numpy()[: int(ok.sum())], order.astype(np.int32))
+
+
+def test_track_with_point_index_matches_oracle(gs):
+    """With the point-major index the point gradients are summed per point (no
+    atomics); they match the oracle and the atomic path, the rest is unchanged."""
+    sc = scenegen.make_config("C1")
+    X = sc["X"].copy()
+    vm, intr = sc["track_viewmat"], sc["track_intr"]
+    M3 = vm[0].reshape(3, 4).astype(np.float64)
+    X[0] = M3[:, :3].T @ (np.array([0.1, 0.2, -3.0]) - M3[:, 3])  # masked in camera 0
+    ctx = gs.Context(max_pairs=X.shape[0], max_isect=1 << 16, max_tiles=16, max_views=1, max_cams=8)
+    o = oracle.track(X, vm, intr, sc["obs_cam"], sc["obs_pt"], sc["obs_xy"], delta=1.0, lam=1e-4)
+    obs_pt = _t(sc["obs_pt"], torch.int32)
+    index = gs.track_point_index(ctx, obs_pt, X.shape[0])
+    out = {}
+    for name, pi in (("atomic", None), ("indexed", index)):
+        loss = torch.zeros(1, device="cuda")
+        v_X = torch.zeros((X.shape[0], 3), device="cuda")
+        v_tw = torch.zeros((5, 6), device="cuda")
+        res = torch.empty((len(sc["obs_cam"]), 2), device="cuda")
+        gs.track_reproj_fwd_bwd(ctx, _t(X), _t(vm), _t(intr), _t(sc["obs_cam"], torch.int32), obs_pt,
+                                _t(sc["obs_xy"]), 1.0, 1e-4, 0.01, loss, v_X, v_tw, residual=res,
+                                pt_index=pi)
+        out[name] = (loss.item(), v_X.cpu().numpy(), v_tw.cpu().numpy(), res.cpu().numpy())
+    la, vXa, twa, ra = out["atomic"]
+    li, vXi, twi, ri = out["indexed"]
+    _close(vXi, o["v_X"], what="v_X indexed")
+    _close(vXi, vXa, what="v_X indexed vs atomic")
+    assert np.array_equal(ri, ra) and np.array_equal(twi, twa) and li == la
+
+
 def test_pose_compose_and_backward(gs):
     rng = np.random.default_rng(8)
     V = 7
