@@ -222,7 +222,21 @@ __global__ __launch_bounds__(kBlock) void k_track_points(
     const float* __restrict__ intr, int n_cams, const int32_t* __restrict__ obs_cam,
     const float* __restrict__ obs_xy, const int32_t* __restrict__ pt_off,
     const int32_t* __restrict__ pt_obs, float delta, float lambda, float near_plane,
-    float* __restrict__ v_X) {
+    float* __restrict__ v_X, double* __restrict__ twist_acc, float* __restrict__ v_twist,
+    double* __restrict__ loss_acc, float* __restrict__ loss) {
+    // the first workgroup also drains k_track's twist and loss sums (that
+    // kernel has finished: this one runs after it on the same stream)
+    if (blockIdx.x == 0) {
+        if (v_twist)
+            for (int q = threadIdx.x; q < 6 * n_cams; q += kBlock) {
+                v_twist[q] += (float)twist_acc[q];
+                twist_acc[q] = 0.0;
+            }
+        if (loss && threadIdx.x == 0) {
+            *loss += (float)*loss_acc;
+            *loss_acc = 0.0;
+        }
+    }
     const int k = blockIdx.x * kBlock + threadIdx.x;
     if (k >= Pt) return;
     float acc[3] = {0.f, 0.f, 0.f};
@@ -295,10 +309,11 @@ hipError_t launch_track(Ctx* c, const float* X, int Pt, const float* viewmat, co
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         if (indexed && Pt > 0) {
+            // the point gradients, and the drain of the twist and loss sums
             hipLaunchKernelGGL(k_track_points, dim3((Pt + kBlock - 1) / kBlock), dim3(kBlock), 0, st, X,
                                Pt, viewmat, intr, n_cams, obs_cam, obs_xy, pt_off, pt_obs, delta, lambda,
-                               near_plane, v_X);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
+                               near_plane, v_X, c->twist_track, v_twist, c->loss_acc + 1, loss);
+            return hipGetLastError();
         }
     }
     hipError_t e = hipSuccess;

@@ -81,10 +81,16 @@ class JointStep:
         self.T = torch.empty((P,), device=device)
         self.last = torch.empty((P,), device=device, dtype=torch.int32)
         self.v_rgb = torch.empty((P, 3), device=device)
-        self.loss = torch.zeros((2,), device=device)
+        # the per-step accumulators (the point gradient, this step's twist
+        # gradient, the losses) share one buffer, so one fill clears them all;
+        # v_X leads, 16-byte aligned for the vector Adam path
+        n_tw, n_x = self.twist.numel(), self.X.numel()
+        o_tw = (n_x + 3) // 4 * 4
+        self._acc = torch.zeros(o_tw + n_tw + 2, device=device)
+        self.v_X = self._acc[:n_x].view_as(self.X)
+        self.v_tw_cur = self._acc[o_tw:o_tw + n_tw].view_as(self.twist)
+        self.loss = self._acc[o_tw + n_tw:]
         self.grads = {k: torch.empty_like(v) for k, v in self.params.items()}
-        self.v_X = torch.zeros_like(self.X)
-        self.v_tw_cur = torch.zeros_like(self.twist)
         self.v_tw = torch.zeros_like(self.twist)
         self.m = {k: torch.zeros_like(v) for k, v in self._opt_params().items()}
         self.v = {k: torch.zeros_like(v) for k, v in self._opt_params().items()}
@@ -126,9 +132,7 @@ class JointStep:
             L.gs_bin_sort(self.ctx, cams, self.N, s)
         with t("render_fwd"):
             L.gs_render_fwd(self.ctx, cams, s, None, self.rgb, self.T, self.last)
-        self.loss.zero_()
-        self.v_tw_cur.zero_()
-        self.v_X.zero_()
+        self._acc.zero_()  # v_X, v_tw_cur, loss
         with t("l1"):
             L.gs_l1_loss_grad(self.ctx, cams, self.rgb, self.targets[b], self.v_rgb, self.loss[0:1])
         with t("raster_bwd"):
