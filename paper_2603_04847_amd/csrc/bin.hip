@@ -294,6 +294,22 @@ __device__ __forceinline__ bool touches(uint64_t m, int q) {
     return tile_bits(m, q % kBlockTiles, q / kBlockTiles) != 0;
 }
 
+// All sixteen at once: bit q (= 4 sy + sx) set iff the mask meets sub-tile q.
+// Per 32-bit half (quadrant rows 4 h .. 4 h + 3): OR each tile's quadrant pair
+// in a row, then the row below into it, keep bit 2 sx of bytes 0 and 2 and
+// pack those eight bits into two nibbles.
+__device__ __forceinline__ uint32_t touch_half(uint32_t x) {
+    x |= x >> 1;
+    x |= x >> 8;
+    x &= 0x00550055u;
+    x = (x | (x >> 1)) & 0x00330033u;
+    x = (x | (x >> 2)) & 0x000F000Fu;
+    return (x & 0xFu) | ((x >> 12) & 0xF0u);
+}
+__device__ __forceinline__ uint32_t tile_touch16(uint64_t m) {
+    return touch_half((uint32_t)m) | (touch_half((uint32_t)(m >> 32)) << 8);
+}
+
 // Column stride of the chunk counts: one slot per chunk of the live entries
 // and a last one that stays 0, so the prefix at the very end of the list is
 // still read inside its column.
@@ -326,13 +342,16 @@ __global__ __launch_bounds__(kBlock) void k_chunk_count(const uint32_t* __restri
             const uint64_t mm = ((uint64_t)mhi[jc] << 32) | mlo[jc];
             m[u] = j < n ? mm : 0ull;
         }
+        uint32_t t[kChunkSteps];
+#pragma unroll
+        for (int u = 0; u < kChunkSteps; u++) t[u] = tile_touch16(m[u]);
         uint32_t cn = 0;
 #pragma unroll
         for (int q = 0; q < kBlockSub; q++) {
             uint32_t k = 0;
 #pragma unroll
-            for (int u = 0; u < kChunkSteps; u++) k += (uint32_t)__popcll(__ballot(touches(m[u], q)));
-            if (lane == q) cn = k;
+            for (int u = 0; u < kChunkSteps; u++) k += (uint32_t)__popcll(__ballot((t[u] >> q) & 1u));
+            cn = lane == q ? k : cn;  // lane q holds count q
         }
         if (lane < kBlockSub) ccnt[(int64_t)lane * stride + c] = cn;
     }
