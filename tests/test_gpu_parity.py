@@ -366,40 +366,39 @@ def test_render_bwd_matches_oracle(gs, name):
         _close(tw[v], og["twist"][v], what=f"twist view {v}")
 
 
-def test_full_size_batch_sampled_pixels_and_gradients(gs):
-    """The joint step's batch at full size (4 views of 1237x822, 1M Gaussians,
-    SH degree 3), in the configuration the benchmark times (16x16 tiles,
-    heaviest tile first): colour and transmittance of sampled pixels against
-    the oracle's per-pixel definition, and the backward with an image gradient
-    that is non-zero only at those pixels, so the oracle's gradients of every
-    Gaussian parameter and of each view's twist come from them alone."""
+def _full_size_check(gs, sub, tile, order, npix, min_ok, max_isect, seed):
+    """Sampled pixels and gradients of one full-size batch against the oracle:
+    colour and transmittance of `npix` random pixels against the oracle's
+    per-pixel definition, and the backward with an image gradient that is
+    non-zero only at those pixels, so the oracle's gradients of every Gaussian
+    parameter and of each view's twist come from them alone."""
     from paper_2603_04847_amd.splat import Splatter
-    sc = scenegen.make_config("C4")
-    b = scenegen.batch_views(4, sc["viewmat"].shape[0], 4, 1)[0]
-    sub = dict(sc, viewmat=sc["viewmat"][b], intr=sc["intr"][b], wh=sc["wh"][b])
-    N = sc["means"].shape[1]
-    ctx = gs.Context(max_pairs=4 * N, max_isect=120_000_000, max_tiles=20_000, max_views=4)
-    sp = Splatter(ctx, gs.default_settings(tile_w=16, tile_h=16, tile_order=1))
+    V = sub["viewmat"].shape[0]
+    N = sub["means"].shape[1]
+    T_max = int(sum(((w + tile[0] - 1) // tile[0]) * ((h + tile[1] - 1) // tile[1]) for w, h in sub["wh"]))
+    ctx = gs.Context(max_pairs=V * N, max_isect=max_isect, max_tiles=T_max, max_views=V)
+    sp = Splatter(ctx, gs.default_settings(tile_w=tile[0], tile_h=tile[1], tile_order=order))
     params = _params(sub)
     rgb, T, last, cams = sp.forward(params, 3, _t(sub["viewmat"]), _t(sub["intr"]), sub["wh"])
     torch.cuda.synchronize()
     assert ctx.status()["flags"] == 0
     P = cams.n_pixels
-    rng = np.random.default_rng(12)
-    pix = np.sort(rng.choice(P, size=300, replace=False))
+    rng = np.random.default_rng(seed)
+    pix = np.sort(rng.choice(P, size=npix, replace=False))
     w = rng.normal(size=(pix.size, 3))
-    o = oracle.render(oracle.project(sub), sub["wh"], pix=pix, v_rgb=w)
-    # at this depth complexity (~90 contributors per pixel) about a fifth of
-    # the pixels hold two splats within 4 ulp of depth: ambiguous, excluded
+    pr = oracle.project(sub)
+    o = oracle.render(pr, sub["wh"], pix=pix, v_rgb=w)
+    # deep lists hold pixels with two splats within a few ulp of depth:
+    # ambiguous, excluded
     ok = ~o["ambiguous"].astype(bool)
-    assert ok.sum() >= 200
+    assert ok.sum() >= min_ok
     g_rgb = rgb.cpu().numpy()[pix]
     g_T = T.cpu().numpy()[pix]
     _close(g_rgb[ok], o["rgb"][ok], scale=max(np.max(np.abs(o["rgb"][ok])), 1.0), what="rgb")
     _close(g_T[ok], o["T"][ok], scale=1.0, what="T_final")
     # backward: the image gradient at the sampled, non-ambiguous pixels only
     w[~ok] = 0.0
-    o = oracle.render(oracle.project(sub), sub["wh"], pix=pix, v_rgb=w)
+    o = oracle.render(pr, sub["wh"], pix=pix, v_rgb=w)
     og = oracle.project_bwd(sub, o["v2d"])
     v_img = np.zeros((P, 3))
     v_img[pix] = w
@@ -412,8 +411,36 @@ def test_full_size_batch_sampled_pixels_and_gradients(gs):
         band = slice(l * l, (l + 1) * (l + 1))
         _close(sh[band], og["sh"][band], what=f"sh band {l}")
     tw = v_tw.cpu().numpy()
-    for v in range(4):
+    for v in range(V):
         _close(tw[v], og["twist"][v], what=f"twist view {v}")
+
+
+def test_full_size_batch_sampled_pixels_and_gradients(gs):
+    """The joint step's batch at full size (4 views of 1237x822, 1M Gaussians,
+    SH degree 3), in the configuration the benchmark times (16x16 tiles,
+    heaviest tile first)."""
+    sc = scenegen.make_config("C4")
+    b = scenegen.batch_views(4, sc["viewmat"].shape[0], 4, 1)[0]
+    sub = dict(sc, viewmat=sc["viewmat"][b], intr=sc["intr"][b], wh=sc["wh"][b])
+    # at this depth complexity (~90 contributors per pixel) about a fifth of
+    # the pixels are ambiguous
+    _full_size_check(gs, sub, (16, 16), 1, 300, 200, 120_000_000, 12)
+
+
+def test_full_size_uneven_views_sampled(gs):
+    """The batched uneven-view workload at full size: 8 views from 640x480 to
+    1600x1066 around 3M clustered Gaussians (SH degree 3), one call."""
+    sc = scenegen.make_config("C3")
+    _full_size_check(gs, sc, (16, 16), 1, 100, 60, 400_000_000, 13)
+
+
+def test_full_size_large_scene_sampled(gs):
+    """The large-scene batch at full size (4 views of 1600x1066, 5M Gaussians,
+    SH degree 3) at the tile shape its benchmark picks (32x16)."""
+    sc = scenegen.make_config("C5")
+    b = scenegen.batch_views(5, sc["viewmat"].shape[0], 4, 1)[0]
+    sub = dict(sc, viewmat=sc["viewmat"][b], intr=sc["intr"][b], wh=sc["wh"][b])
+    _full_size_check(gs, sub, (32, 16), 0, 100, 60, 400_000_000, 14)
 
 
 def test_render_bwd_batched_views(gs):
