@@ -8,9 +8,9 @@
 // tile's list is consumed in batches of 64: each lane loads one splat record
 // (a gather of 40 B) and stages it in the wave's own LDS region; the wave then
 // walks the batch reading each splat's parameters with broadcast LDS loads
-// (one address for all lanes), synchronising only with itself.  The next
-// batch's list entries are requested right after the current records, so
-// their latency hides behind the compositing.  The backward walks the same
+// (one address for all lanes), synchronising only with itself.  Loads run two
+// batches ahead: while a batch composites, the next batch's records and the
+// list entries of the one after it are in flight.  The backward walks the same
 // lists back to front from each pixel's last contributor, recovering the
 // transmittance by division, and sums each splat's nine 2D gradients over the
 // whole wave (DPP and lane-swap steps) before one lane per component issues
@@ -139,21 +139,26 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
     const float amin = rp.alpha_min, amax = rp.alpha_max, tmin = rp.t_min;
     int ncontrib = 0, nent = 0;
     __shared__ BatchLds sb;
-    uint32_t idn = s < e ? batch_ids(ids, s, s, e) : 0u;
+    // Two-deep pipeline: while a batch composites, the next batch's records
+    // are in flight (their entries arrived during the batch before) and the
+    // entries of the batch after that are requested.
+    uint32_t id_cur = s < e ? batch_ids(ids, s, s, e) : 0u;
+    uint32_t id_nxt = s < e ? batch_ids(ids, s + kWave, s, e) : 0u;
+    LaneSplat ls_cur = {};
+    if (lane < e - s) ls_cur = load_splat(rec, id_cur & kPairMask);
     for (int b = s; b < e; b += kWave) {
         bool alive = false;
 #pragma unroll
         for (int k = 0; k < PPL; k++) alive |= !done[k];
         if (__ballot(alive) == 0) break;
-        const uint32_t id = idn;
+        const uint32_t id = id_cur;
         const int nb = min(kWave, e - b);
-        {
-            LaneSplat ls = {};
-            if (lane < nb) ls = load_splat(rec, id & kPairMask);
-            wave_lds_sync();  // the previous batch is read
-            stage_splat(sb, ls);
-        }
-        idn = batch_ids(ids, b + kWave, s, e);  // next batch, behind the records
+        wave_lds_sync();  // the previous batch is read
+        stage_splat(sb, ls_cur);
+        ls_cur = {};
+        if (lane < e - (b + kWave)) ls_cur = load_splat(rec, id_nxt & kPairMask);
+        id_cur = id_nxt;
+        id_nxt = batch_ids(ids, b + 2 * kWave, s, e);
         wave_lds_sync();
         nent += nb;
         for (int i = 0; i < nb; i++) {
@@ -299,7 +304,12 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ re
     const float vb = comp == 0 ? 1.f : 0.f, vc = comp == 1 ? 2.f : 0.f;
     __shared__ BatchLds sb;
     int b = s + ((lmax - 1) / kWave) * kWave;
-    uint32_t idn = batch_ids(ids, b, s, top);
+    // the same two-deep pipeline as the forward, walking down: the batches
+    // after the first (partial) one are full
+    uint32_t id_cur = batch_ids(ids, b, s, top);
+    uint32_t id_nxt = batch_ids(ids, b - kWave, s, top);
+    LaneSplat ls_cur = {};
+    if (lane < top - b) ls_cur = load_splat(rec, id_cur & kPairMask);
     // per-lane sums over the lane's pixels for the current splat: colour
     // weights, q = dL/dalpha e^-sigma (zero where alpha is clamped), and the
     // moments q dx, q dy, q dx^2, q dx dy, q dy^2; the exponent's gradient is
@@ -310,15 +320,14 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ re
     float m_x = 0.f, m_y = 0.f, m_xx = 0.f, m_xy = 0.f, m_yy = 0.f;
     bool any = false;
     for (; b >= s; b -= kWave) {
-        const uint32_t id = idn;
+        const uint32_t id = id_cur;
         const int nb = min(kWave, top - b);
-        {
-            LaneSplat ls = {};
-            if (lane < nb) ls = load_splat(rec, id & kPairMask);
-            wave_lds_sync();  // the previous batch is read
-            stage_splat(sb, ls);
-        }
-        idn = batch_ids(ids, b - kWave, s, top);  // next (lower) batch, behind the records
+        wave_lds_sync();  // the previous batch is read
+        stage_splat(sb, ls_cur);
+        ls_cur = {};
+        if (b - kWave >= s) ls_cur = load_splat(rec, id_nxt & kPairMask);
+        id_cur = id_nxt;
+        id_nxt = batch_ids(ids, b - 2 * kWave, s, top);
         wave_lds_sync();
         for (int i = nb - 1; i >= 0; i--) {
             const uint32_t idb = (uint32_t)bcast((int)id, i);
