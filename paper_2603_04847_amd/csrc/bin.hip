@@ -599,23 +599,34 @@ constexpr int kOrderBuckets = 513;
 constexpr int kOrderThreads = 1024;
 
 // One block: histogram of the buckets, their scan from the heaviest down, and
-// a scatter through LDS cursors.  For up to 2^20 tiles.
+// a scatter through LDS cursors.  For up to 2^20 tiles.  The bucket scan
+// runs over all threads at once.
 __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint32_t* __restrict__ bucket,
                                                                int64_t T,
                                                                uint32_t* __restrict__ order) {
     __shared__ uint32_t s_n[kOrderBuckets];
+    __shared__ uint32_t s_w[kOrderThreads / kWave];
     for (int q = threadIdx.x; q < kOrderBuckets; q += kOrderThreads) s_n[q] = 0;
     __syncthreads();
     for (int64_t t = threadIdx.x; t < T; t += kOrderThreads) atomicAdd(&s_n[bucket[t]], 1u);
     __syncthreads();
-    if (threadIdx.x == 0) {
-        // heaviest bucket first
-        uint32_t run = 0;
-        for (int q = kOrderBuckets - 1; q >= 0; q--) {
-            const uint32_t c = s_n[q];
-            s_n[q] = run;
-            run += c;
+    {
+        // exclusive scan from the heaviest bucket down, over all threads:
+        // thread i takes bucket kOrderBuckets - 1 - i
+        const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave;
+        const int qb = kOrderBuckets - 1 - tid;
+        const uint32_t c = qb >= 0 ? s_n[qb] : 0u;
+        uint32_t inc = c;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t x = __shfl_up(inc, off, kWave);
+            if (lane >= off) inc += x;
         }
+        if (lane == kWave - 1) s_w[w] = inc;
+        __syncthreads();
+        uint32_t before = 0;
+        for (int i = 0; i < w; i++) before += s_w[i];
+        if (qb >= 0) s_n[qb] = before + inc - c;
     }
     __syncthreads();
     for (int64_t t = threadIdx.x; t < T; t += kOrderThreads) {
