@@ -108,11 +108,6 @@ __device__ __forceinline__ int sum8_index(int lane) {
     return ((lane & 1) << 2) | (lane & 2) | ((lane >> 2) & 1);
 }
 
-__device__ __forceinline__ double wave_sum_d(double v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
-}
-
 __device__ __forceinline__ int wave_max_i(int v) {
     for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, kWave));
     return v;
