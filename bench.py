@@ -245,6 +245,11 @@ KERNEL_SOURCE = {"render_fwd": "raster.hip", "raster_bwd": "raster.hip", "projec
                  "adam": "optim.hip", "l1": "raster.hip"}
 
 
+# calls whose kernels HBM traffic bounds (the raster pair is VALU-bound, the
+# binning sequence latency- and VALU-bound)
+HBM_BOUND_CALLS = ("project", "project_bwd_adam", "l1", "adam")
+
+
 def algorithmic_flops(sz, call):
     return sz["n_eval"] * FLOPS_EVAL + sz["n_contrib"] * FLOPS_CONTRIB[call]
 
@@ -512,6 +517,9 @@ def main():
         "per_call_ms": per_call,
         "per_call_algorithmic_gbs": {k: round(alg[k] / (per_call[k] * 1e-3) / 1e9, 1)
                                      for k in per_call if k in alg},
+        # the calls bound by HBM: their algorithmic rate against the 8 TB/s peak
+        "hbm_frac_by_call": {k: round(alg[k] / (per_call[k] * 1e-3) / 8e12, 3)
+                             for k in HBM_BOUND_CALLS if k in alg and k in per_call},
         "timed_as": "hip_graph_replay" if res["graph_ms"] is not None else "eager",
         "eager_ms_per_step": round(ms_eager, 4),
         "step_ms_p10_p50_p90": (None if res["step_ms"] is None else

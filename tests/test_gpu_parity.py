@@ -427,6 +427,13 @@ def test_full_size_batch_sampled_pixels_and_gradients(gs):
     _full_size_check(gs, sub, (16, 16), 1, 300, 200, 120_000_000, 12)
 
 
+def test_full_size_single_view_sampled(gs):
+    """The single-view workload at full size (1237x822, 1M Gaussians, SH
+    degree 3) at 16x16 tiles, heaviest first."""
+    sc = scenegen.make_config("C2")
+    _full_size_check(gs, sc, (16, 16), 1, 200, 120, 150_000_000, 15)
+
+
 def test_full_size_uneven_views_sampled(gs):
     """The batched uneven-view workload at full size: 8 views from 640x480 to
     1600x1066 around 3M clustered Gaussians (SH degree 3), one call."""
