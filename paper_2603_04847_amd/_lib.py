@@ -15,6 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgs_hip.so")
 
 GS_OK = 0
+GS_ERR_CAPACITY = -2
 GS_ERR = {-1: "GS_ERR_INVALID_ARG", -2: "GS_ERR_CAPACITY", -3: "GS_ERR_HIP",
           -4: "GS_ERR_UNSUPPORTED"}
 GS_FLAG_ISECT_OVERFLOW = 1

@@ -75,8 +75,14 @@ class JointStep:
                          max_cams=self.n_cams)
         self.ctx = L.Context(max_isect=max_isect or 32 * P, **self._cap)
         # the observations' point-major index (fixed for the scene): the track
-        # term then sums each point's gradient without atomics
-        self.pt_index = L.track_point_index(self.ctx, self.obs_pt, int(self.X.shape[0]))
+        # term then sums each point's gradient without atomics; a context too
+        # small to build it keeps the atomic path
+        try:
+            self.pt_index = L.track_point_index(self.ctx, self.obs_pt, int(self.X.shape[0]))
+        except L.GsError as e:
+            if e.code != L.GS_ERR_CAPACITY:
+                raise
+            self.pt_index = None
         self.rgb = torch.empty((P, 3), device=device)
         self.T = torch.empty((P,), device=device)
         self.last = torch.empty((P,), device=device, dtype=torch.int32)
