@@ -231,7 +231,12 @@ __device__ __forceinline__ int64_t item_index(int64_t base, int w, int i, int la
 
 // Per-block digit counts, digit-major: hist[d * nb + block] with nb the number
 // of blocks that hold items (the live count), so the scan covers only those.
-// All loads of a thread are issued before the first ballot.
+// All loads of a thread are issued before the first count.  Counts need no
+// ranks: for 7- and 8-bit digits each item is one LDS add, and a wave whose
+// valid items share one digit (common in the top digit of clustered keys)
+// adds them at once; narrower digits of clustered keys (the block ids) would
+// pile many adds onto a few addresses, so there one lane per distinct digit
+// adds the count its ballot match found.
 template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                          const uint32_t* __restrict__ d_n,
@@ -256,9 +261,18 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restr
         for (int i = 0; i < ITEMS; i++) {
             const bool valid = item_index<ITEMS>(base, w, i, lane) < n;
             const uint32_t d = (k[i] >> shift) & mask;
-            const uint64_t peers = match_digit(d, valid, bits);
-            // one lane per digit adds the digit's count in this wave's histogram
-            if (valid && (peers & lanemask_lt()) == 0) s_h[w][d] += (uint32_t)__popcll(peers);
+            if (bits > 6) {
+                const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+                if (__ballot(valid && d != d0) == 0) {
+                    const uint64_t live = __ballot(valid);
+                    if (lane == 0 && live) atomicAdd(&s_h[w][d0], (uint32_t)__popcll(live));
+                } else if (valid) {
+                    atomicAdd(&s_h[w][d], 1u);
+                }
+            } else {
+                const uint64_t peers = match_digit(d, valid, bits);
+                if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&s_h[w][d], (uint32_t)__popcll(peers));
+            }
         }
     }
     __syncthreads();
