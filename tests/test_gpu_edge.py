@@ -1,0 +1,118 @@
+"""Degenerate inputs on the HIP path: no Gaussians, no splat that survives
+culling, no track observation.  Front-to-back compositing of an empty list
+(the rasterization of Sec. 3.3 and Algorithm 1, a sum over no terms) leaves
+the transmittance at 1 and the pixel at the background, and the track loss of
+Sec. 3.3 over no observation is 0, so these results are exact."""
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_04847_amd as P
+    P.load()
+    return P
+
+
+def _t(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype)
+
+
+def _scene(N, seed=31):
+    # ragged views: 203 = 12*16 + 11, 150 = 9*16 + 6; 70 x 45 is under 5 x 3 tiles
+    s = scenegen.frustum_scene(seed, 203, 150, 238.0, 238.0, max(N, 1), 3, -3.3, 0.6, sh_sd=0.2,
+                               unit_quats=False)
+    s2 = scenegen.frustum_scene(seed + 1, 70, 45, 82.0, 82.0, 1, 3, -3.3, 0.6, sh_sd=0.2,
+                                unit_quats=False)
+    s["viewmat"] = np.concatenate([s["viewmat"], s2["viewmat"]])
+    s["intr"] = np.concatenate([s["intr"], s2["intr"]])
+    s["wh"] = np.concatenate([s["wh"], s2["wh"]])
+    if N == 0:
+        for k in ("means", "log_scales", "quats", "opacity_logit", "sh"):
+            s[k] = s[k][..., :0]
+    return s
+
+
+def _run(gs, s, bg):
+    from paper_2603_04847_amd.splat import Splatter
+    N = s["means"].shape[1]
+    V = s["viewmat"].shape[0]
+    ctx = gs.Context(max_pairs=max(V * N, 1), max_isect=1 << 16, max_tiles=4096, max_views=V, max_cams=V)
+    sp = Splatter(ctx, gs.default_settings(), _t(bg))
+    params = {k: _t(s[k]) for k in ("means", "log_scales", "quats", "opacity_logit", "sh")}
+    rgb, T, last, cams = sp.forward(params, 3, _t(s["viewmat"]), _t(s["intr"]), s["wh"])
+    v_rgb = _t(np.random.default_rng(3).normal(size=(cams.n_pixels, 3)))
+    grads, v_tw = sp.backward(params, 3, cams, T, last, v_rgb)
+    torch.cuda.synchronize()
+    st = ctx.status()
+    return st, rgb.cpu().numpy(), T.cpu().numpy(), last.cpu().numpy(), grads, v_tw.cpu().numpy()
+
+
+def _assert_background(s, bg, st, rgb, T, last, v_tw):
+    P = int(sum(int(w) * int(h) for w, h in s["wh"]))
+    assert st["flags"] == 0 and st["n_isect"] == 0
+    assert rgb.shape == (P, 3) and np.array_equal(rgb, np.broadcast_to(bg.astype(np.float32), (P, 3)))
+    assert np.array_equal(T, np.ones(P, np.float32))
+    assert np.array_equal(last, np.zeros(P, np.int32))
+    assert np.array_equal(v_tw, np.zeros_like(v_tw))
+
+
+def test_no_gaussians_renders_background(gs):
+    s = _scene(0)
+    bg = np.array([0.25, 0.5, 0.75])
+    st, rgb, T, last, grads, v_tw = _run(gs, s, bg)
+    _assert_background(s, bg, st, rgb, T, last, v_tw)
+    assert all(g.numel() == 0 for g in grads.values())
+
+
+def test_all_splats_culled_renders_background_with_zero_gradients(gs):
+    """Every opacity far below the alpha gate: no splat is binned, the image is
+    the background, every gradient is exactly zero; the oracle culls them too."""
+    s = _scene(400)
+    s["opacity_logit"][:] = -40.0
+    bg = np.array([0.1, 0.6, 0.3])
+    st, rgb, T, last, grads, v_tw = _run(gs, s, bg)
+    _assert_background(s, bg, st, rgb, T, last, v_tw)
+    for k, g in grads.items():
+        assert not torch.any(g != 0).item(), k
+    # the oracle reaches the same image on the first view
+    s1 = dict(s, viewmat=s["viewmat"][:1], intr=s["intr"][:1], wh=s["wh"][:1])
+    o = oracle.render_fwd_bwd(s1, bg=bg)
+    assert np.allclose(o["rgb"], bg, rtol=0, atol=0)
+
+
+def test_track_without_observations(gs):
+    """No observation: zero loss and zero gradients, on the atomic and the
+    point-indexed paths; the index of no observations is all zeros."""
+    sc = scenegen.make_config("C1")
+    X = sc["X"]
+    Pt = X.shape[0]
+    vm, intr = sc["track_viewmat"], sc["track_intr"]
+    C = vm.shape[0]
+    ctx = gs.Context(max_pairs=Pt, max_isect=1 << 16, max_tiles=16, max_views=1, max_cams=C)
+    obs_cam = torch.zeros(0, dtype=torch.int32, device="cuda")
+    obs_pt = torch.zeros(0, dtype=torch.int32, device="cuda")
+    obs_xy = torch.zeros((0, 2), device="cuda")
+    index = gs.track_point_index(ctx, obs_pt, Pt)
+    torch.cuda.synchronize()
+    assert not torch.any(index[0] != 0).item()
+    for pi in (None, index):
+        loss = torch.zeros(1, device="cuda")
+        v_X = torch.zeros((Pt, 3), device="cuda")
+        v_tw = torch.zeros((C, 6), device="cuda")
+        ctx.reset_status()
+        gs.track_reproj_fwd_bwd(ctx, _t(X), _t(vm), _t(intr), obs_cam, obs_pt, obs_xy, 1.0, 1e-4, 0.01,
+                                loss, v_X, v_tw, pt_index=pi)
+        torch.cuda.synchronize()
+        assert loss.item() == 0.0
+        assert not torch.any(v_X != 0).item() and not torch.any(v_tw != 0).item()
+        assert ctx.status()["n_masked_obs"] == 0
