@@ -717,7 +717,10 @@ template <int DEG>
 void project_bwd_impl(Ctx* c, const gs_gaussians* g, const gs_cameras* cams, const ViewTable& vt,
                       const RasterParams& rp, const AdamGauss* adam, const gs_gaussians_grad* grads,
                       int accumulate, hipStream_t st) {
-    const dim3 grid(std::min((g->N + kBlock - 1) / kBlock, 1024)), block(kBlock);
+    // at most 2048 blocks, grid-striding beyond: per block one double atomic
+    // per view and twist component (measured on 1M Gaussians: 2048 blocks 2%
+    // faster than 1024, one round of resident blocks 1% slower)
+    const dim3 grid(std::min((g->N + kBlock - 1) / kBlock, 2048)), block(kBlock);
     const gs_gaussians_grad none{};
     const AdamGauss no_adam{};
     if (adam) {
