@@ -25,9 +25,9 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 # alpha_max, T_min, and the ambiguity bands used by the parity rule.
 CFG_DEFAULT = dict(near=0.01, eps2d=0.3, pad=0.3, alpha_min=1.0 / 255.0,
                    alpha_max=0.99, t_min=1e-4, band_pos=2.4e-7, band_t=2e-4,
-                   band_sig=2e-5, band_depth=1e-6)
+                   band_sig=2e-5, band_mid=1e-12)
 _CFG_ORDER = ["near", "eps2d", "pad", "alpha_min", "alpha_max", "t_min",
-              "band_pos", "band_t", "band_sig", "band_depth"]
+              "band_pos", "band_t", "band_sig", "band_mid"]
 
 _lib = None
 
@@ -104,7 +104,8 @@ def project(scene, viewmat=None, intr=None, wh=None, **cfg):
 
 def render(proj, wh, bg=None, pix=None, v_rgb=None, **cfg):
     """Brute-force compositing.  Returns a dict with rgb [n,3], T [n],
-    ncontrib [n], ngate [n], ambiguous [n] and v2d [V*N,9] (None without v_rgb)."""
+    ncontrib [n], ngate [n], nclamp [n], ambiguous [n] and v2d [V*N,9] (None
+    without v_rgb)."""
     lib = _load()
     wh = _i32(wh)
     V = wh.shape[0]
@@ -120,6 +121,7 @@ def render(proj, wh, bg=None, pix=None, v_rgb=None, **cfg):
     T = np.zeros(n)
     nc = np.zeros(n, np.int32)
     ng = np.zeros(n, np.int32)
+    ncl = np.zeros(n, np.int32)
     amb = np.zeros(n, np.int32)
     v2d = np.zeros((VN, 9)) if v_rgb is not None else None
     bga = None if bg is None else _f64(bg)
@@ -127,11 +129,12 @@ def render(proj, wh, bg=None, pix=None, v_rgb=None, **cfg):
         ctypes.c_int(V), _p(wh), ctypes.c_int(N), _p(_i32(proj["valid"])), _p(_f64(proj["depth"])),
         _p(_f64(proj["mean2d"])), _p(_f64(proj["conic"])), _p(_f64(proj["opacity"])),
         _p(_f64(proj["rgb"])), _p(bga), _p(cfg_array(**cfg)),
-        ctypes.c_longlong(n), _p(pix), _p(rgb), _p(T), _p(nc), _p(ng), _p(amb),
+        ctypes.c_longlong(n), _p(pix), _p(rgb), _p(T), _p(nc), _p(ng), _p(ncl), _p(amb),
         _p(None if v_rgb is None else _f64(v_rgb)), _p(v2d))
     if rc != 0:
         raise ValueError("or_render failed")
-    return dict(rgb=rgb, T=T, ncontrib=nc, ngate=ng, ambiguous=amb.astype(bool), v2d=v2d)
+    return dict(rgb=rgb, T=T, ncontrib=nc, ngate=ng, nclamp=ncl, ambiguous=amb.astype(bool),
+                v2d=v2d)
 
 
 def project_bwd(scene, v2d, viewmat=None, intr=None, wh=None, **cfg):
@@ -228,6 +231,47 @@ def sh_basis(deg, d, grad=False):
     dY = np.zeros((K, 3)) if grad else None
     lib.or_sh_basis(ctypes.c_int(deg), _p(d), _p(Y), _p(dY))
     return (Y, dY) if grad else Y
+
+
+def l1(rgb, target, wh):
+    """Photometric L1 term and its image gradient: (loss, v_rgb [P,3])."""
+    lib = _load()
+    wh = _i32(wh)
+    rgb, target = _f64(rgb), _f64(target)
+    v = np.zeros(rgb.shape)
+    loss = np.zeros(1)
+    if lib.or_l1(ctypes.c_int(wh.shape[0]), _p(wh), _p(rgb), _p(target), _p(loss), _p(v)) != 0:
+        raise ValueError("or_l1 failed")
+    return float(loss[0]), v
+
+
+# SSIM window and constants (Wang et al. 2004 defaults for data in [0, 1])
+SSIM_WIN, SSIM_SIGMA, SSIM_C1, SSIM_C2 = 11, 1.5, 0.01 ** 2, 0.03 ** 2
+
+
+def ssim(rgb, target, wh, grad=True, ssim_map=False, win=SSIM_WIN, sigma=SSIM_SIGMA,
+         c1=SSIM_C1, c2=SSIM_C2):
+    """Mean SSIM over views (each the mean over its pixels and channels).
+    Returns (ssim, v_rgb [P,3] or None, map [P,3] or None)."""
+    lib = _load()
+    wh = _i32(wh)
+    rgb, target = _f64(rgb), _f64(target)
+    v = np.zeros(rgb.shape) if grad else None
+    m = np.zeros(rgb.shape) if ssim_map else None
+    s = np.zeros(1)
+    rc = lib.or_ssim(ctypes.c_int(wh.shape[0]), _p(wh), _p(rgb), _p(target), ctypes.c_int(win),
+                     ctypes.c_double(sigma), ctypes.c_double(c1), ctypes.c_double(c2), _p(s),
+                     _p(m), _p(v))
+    if rc != 0:
+        raise ValueError("or_ssim failed")
+    return float(s[0]), v, m
+
+
+def photo_loss(rgb, target, wh, lam=0.2):
+    """L_photo = (1 - lam) L1 + lam (1 - SSIM) and its image gradient."""
+    l, vl = l1(rgb, target, wh)
+    s, vs, _ = ssim(rgb, target, wh)
+    return (1 - lam) * l + lam * (1 - s), (1 - lam) * vl - lam * vs
 
 
 def bin_sort(wh, tile, valid, mean2d, conic, opacity, depth, alpha_min=1.0 / 255.0,

@@ -321,25 +321,47 @@ int or_project(int N, int sh_degree, const double* means, const double* log_scal
 
 typedef struct {
     int g;
-    double depth, alpha, araw, sigma, dx, dy, T;
+    uint32_t dkey;  /* bits of the float32 rounding of the FP64 camera depth */
+    int dmid;       /* FP64 depth within the band of a float32 rounding midpoint */
+    double alpha, araw, sigma, dx, dy, T;
 } hit_t;
 
+/* The compositing order is ascending (float32 depth, pair index): depths are
+ * > near > 0, so the raw bits of the rounded depth order like the numbers.
+ * Within one view the pair index v*N + g orders like g. */
 static int hit_cmp(const void* pa, const void* pb) {
     const hit_t* a = (const hit_t*)pa;
     const hit_t* b = (const hit_t*)pb;
-    if (a->depth < b->depth) return -1;
-    if (a->depth > b->depth) return 1;
+    if (a->dkey != b->dkey) return a->dkey < b->dkey ? -1 : 1;
     return (a->g > b->g) - (a->g < b->g);
+}
+
+static uint32_t depth_key(double d) {
+    float f = (float)d;
+    uint32_t b;
+    memcpy(&b, &f, 4);
+    return b;
+}
+
+/* Could another FP64 evaluation of the same depth (differing in its last
+ * bits) round to a different float32?  Only when the FP64 value lies within
+ * `band` (relative) of a midpoint between two adjacent float32 values. */
+static int near_rounding_midpoint(double d, double band) {
+    float f = (float)d;
+    double lo = 0.5 * ((double)f + (double)nextafterf(f, -INFINITY));
+    double hi = 0.5 * ((double)f + (double)nextafterf(f, INFINITY));
+    double tol = band * fabs(d);
+    return fabs(d - lo) <= tol || fabs(d - hi) <= tol;
 }
 
 int or_render(int V, const int* wh, int N, const int* valid, const double* depth,
               const double* mean2d, const double* conic, const double* opacity,
               const double* rgb, const double* bg, const double* cfg,
               long long npix, const long long* pix,
-              double* out_rgb, double* out_T, int* out_ncontrib, int* out_ngate, int* ambiguous,
-              const double* v_rgb, double* v2d) {
+              double* out_rgb, double* out_T, int* out_ncontrib, int* out_ngate, int* out_nclamp,
+              int* ambiguous, const double* v_rgb, double* v2d) {
     const double amin = cfg[3], amax = cfg[4], tmin = cfg[5];
-    const double band_pos = cfg[6], band_t = cfg[7], band_sig = cfg[8], band_d = cfg[9];
+    const double band_pos = cfg[6], band_t = cfg[7], band_sig = cfg[8], band_mid = cfg[9];
     long long* voff = (long long*)malloc(sizeof(long long) * (V + 1));
     voff[0] = 0;
     for (int v = 0; v < V; v++) voff[v + 1] = voff[v] + (long long)wh[2 * v] * wh[2 * v + 1];
@@ -348,7 +370,7 @@ int or_render(int V, const int* wh, int N, const int* valid, const double* depth
 #pragma omp parallel
     {
         hit_t* hits = (hit_t*)malloc(sizeof(hit_t) * (size_t)(N > 0 ? N : 1));
-        double* gate_depth = (double*)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
+        uint32_t* gate_key = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(N > 0 ? N : 1));
         int* gate_g = (int*)malloc(sizeof(int) * (size_t)(N > 0 ? N : 1));
 #pragma omp for schedule(dynamic, 64)
         for (long long s = 0; s < npix; s++) {
@@ -378,24 +400,29 @@ int or_render(int V, const int* wh, int N, const int* valid, const double* depth
                 if (mag < 1.0) mag = 1.0;
                 double err = sqrt(gsx * gsx + gsy * gsy) * band_pos * mag + band_sig * sigma;
                 if (fabs(sigma - log(opacity[i] / amin)) <= err) {
-                    gate_depth[ng] = depth[i]; gate_g[ng] = g; ng++;
+                    gate_key[ng] = depth_key(depth[i]); gate_g[ng] = g; ng++;
                 }
                 if (opacity[i] > amax && fabs(sigma - log(opacity[i] / amax)) <= err) {
-                    gate_depth[ng] = depth[i]; gate_g[ng] = g; ng++;
+                    gate_key[ng] = depth_key(depth[i]); gate_g[ng] = g; ng++;
                 }
                 if (alpha < amin) continue;
-                hit_t h = {g, depth[i], alpha, araw, sigma, dx, dy, 0};
+                hit_t h = {g, depth_key(depth[i]), near_rounding_midpoint(depth[i], band_mid),
+                           alpha, araw, sigma, dx, dy, 0};
                 hits[nh++] = h;
             }
             qsort(hits, nh, sizeof(hit_t), hit_cmp);
             double T = 1.0, Cp[3] = {0, 0, 0};
-            int amb = 0, n = 0, stop = -1;
+            int amb = 0, n = 0, stop = -1, nclamp = 0;
             for (int k = 0; k < nh; k++) {
                 double Tn = T * (1.0 - hits[k].alpha);
                 if (fabs(Tn - tmin) <= band_t * tmin) amb = 1;
-                if (k + 1 < nh && fabs(hits[k + 1].depth - hits[k].depth) <= band_d * fabs(hits[k].depth))
+                /* two neighbours whose float32 depths are equal or adjacent
+                   could swap if either depth's rounding is not certain */
+                if (k + 1 < nh && hits[k + 1].dkey - hits[k].dkey <= 1u &&
+                    (hits[k].dmid || hits[k + 1].dmid))
                     amb = 1;
                 if (Tn < tmin) { stop = k; break; }
+                if (!(hits[k].araw < amax)) nclamp++;
                 hits[k].T = T;
                 size_t i = (size_t)v * N + hits[k].g;
                 for (int ch = 0; ch < 3; ch++) Cp[ch] += rgb[3 * i + ch] * hits[k].alpha * T;
@@ -406,7 +433,7 @@ int or_render(int V, const int* wh, int N, const int* valid, const double* depth
                before the stop */
             for (int j = 0; j < ng && !amb; j++) {
                 if (stop < 0) { amb = 1; break; }
-                hit_t key = {gate_g[j], gate_depth[j], 0, 0, 0, 0, 0, 0};
+                hit_t key = {gate_g[j], gate_key[j], 0, 0, 0, 0, 0, 0, 0};
                 if (hit_cmp(&key, &hits[stop]) < 0) amb = 1;
             }
             for (int ch = 0; ch < 3; ch++) {
@@ -416,6 +443,7 @@ int or_render(int V, const int* wh, int N, const int* valid, const double* depth
             if (out_T) out_T[s] = T;
             if (out_ncontrib) out_ncontrib[s] = n;
             if (out_ngate) out_ngate[s] = nh;
+            if (out_nclamp) out_nclamp[s] = nclamp;
             if (ambiguous) ambiguous[s] = amb;
             if (v_rgb && v2d) {
                 /* dC/d alpha_k = c_k T_k - (sum_{j>k} c_j alpha_j T_j + T_N bg) / (1 - alpha_k) */
@@ -459,7 +487,7 @@ int or_render(int V, const int* wh, int N, const int* valid, const double* depth
             }
         }
         free(hits);
-        free(gate_depth);
+        free(gate_key);
         free(gate_g);
     }
     free(voff);
@@ -900,4 +928,149 @@ long long or_bin_sort(int V, const int* wh, int tile_w, int tile_h, int N,
     free(buf);
     free(mbuf);
     return total <= cap ? total : -total;
+}
+
+/* ------------------------------------------------------------ photometric loss */
+/*
+ * L_photo = (1 - lambda) L1 + lambda (1 - SSIM), lambda = 0.2 (Sec. 3.3,
+ * eq. L_photo; Algorithm 1, photometric loss).  Both terms are means over the
+ * pixels and channels of one view, then over the views of the batch (the
+ * algorithm's per-view loss read as a mean).
+ */
+
+static long long view_offsets(int V, const int* wh, long long* off) {
+    off[0] = 0;
+    for (int v = 0; v < V; v++) off[v + 1] = off[v] + (long long)wh[2 * v] * wh[2 * v + 1];
+    return off[V];
+}
+
+int or_l1(int V, const int* wh, const double* rgb, const double* target, double* loss,
+          double* v_rgb) {
+    if (V <= 0) return -1;
+    long long* off = (long long*)malloc(sizeof(long long) * (V + 1));
+    view_offsets(V, wh, off);
+    double L = 0;
+    for (int v = 0; v < V; v++) {
+        long long n = off[v + 1] - off[v];
+        if (n <= 0) { free(off); return -1; }
+        double s = 0, w = 1.0 / (3.0 * (double)n * V);
+        for (long long i = 3 * off[v]; i < 3 * off[v + 1]; i++) {
+            double d = rgb[i] - target[i];
+            s += fabs(d);
+            /* |d| has derivative sign(d), taken as 0 at d = 0 */
+            if (v_rgb) v_rgb[i] = d > 0 ? w : (d < 0 ? -w : 0.0);
+        }
+        L += s * w;
+    }
+    if (loss) *loss = L;
+    free(off);
+    return 0;
+}
+
+/*
+ * SSIM (Wang et al. 2004) per channel with a win x win Gaussian window of
+ * standard deviation wsig (the outer product of the normalised 1D window),
+ * constants c1, c2, and the image extended by zeros beyond its border (the
+ * window keeps its weights there):
+ *   mu_x = w * x,  s_xx = w * x^2 - mu_x^2,  s_xy = w * (x y) - mu_x mu_y,
+ *   S = (2 mu_x mu_y + c1)(2 s_xy + c2) / ((mu_x^2 + mu_y^2 + c1)(s_xx + s_yy + c2)).
+ * ssim = mean over views of the mean of S over the view's pixels and channels.
+ * ssim_map[P][3] (may be NULL) receives S.  v_rgb[P][3] (may be NULL) receives
+ * d ssim / d rgb: S at p depends on x through mu_x(p), E_xx(p) = w * x^2 and
+ * E_xy(p) = w * (x y), so
+ *   d ssim / d x(q) = sum_p w(p - q) [dS/dmu_x(p) + 2 x(q) dS/dE_xx(p)
+ *                                      + y(q) dS/dE_xy(p)] / (3 P_v V).
+ */
+int or_ssim(int V, const int* wh, const double* rgb, const double* target, int win,
+            double wsig, double c1, double c2, double* ssim, double* ssim_map, double* v_rgb) {
+    if (V <= 0 || win <= 0 || (win & 1) == 0) return -1;
+    const int r = win / 2;
+    double* g = (double*)malloc(sizeof(double) * win);
+    double gs = 0;
+    for (int i = 0; i < win; i++) {
+        g[i] = exp(-(double)(i - r) * (i - r) / (2.0 * wsig * wsig));
+        gs += g[i];
+    }
+    for (int i = 0; i < win; i++) g[i] /= gs;
+    long long* off = (long long*)malloc(sizeof(long long) * (V + 1));
+    long long P = view_offsets(V, wh, off);
+    /* per pixel and channel: dS/dmu_x, dS/dE_xx, dS/dE_xy */
+    double* dS = v_rgb ? (double*)malloc(sizeof(double) * 9 * (size_t)(P > 0 ? P : 1)) : NULL;
+    double total = 0;
+    for (int v = 0; v < V; v++) {
+        const int W = wh[2 * v], H = wh[2 * v + 1];
+        const long long base = off[v];
+        double vsum = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : vsum)
+        for (int py = 0; py < H; py++)
+            for (int px = 0; px < W; px++) {
+                const long long p = base + (long long)py * W + px;
+                for (int ch = 0; ch < 3; ch++) {
+                    double mx = 0, my = 0, exx = 0, eyy = 0, exy = 0;
+                    for (int j = -r; j <= r; j++) {
+                        const int qy = py + j;
+                        if (qy < 0 || qy >= H) continue;
+                        for (int i = -r; i <= r; i++) {
+                            const int qx = px + i;
+                            if (qx < 0 || qx >= W) continue;
+                            const double w = g[j + r] * g[i + r];
+                            const long long q = base + (long long)qy * W + qx;
+                            const double x = rgb[3 * q + ch], y = target[3 * q + ch];
+                            mx += w * x;
+                            my += w * y;
+                            exx += w * x * x;
+                            eyy += w * y * y;
+                            exy += w * x * y;
+                        }
+                    }
+                    const double sxx = exx - mx * mx, syy = eyy - my * my, sxy = exy - mx * my;
+                    const double A1 = 2 * mx * my + c1, A2 = 2 * sxy + c2;
+                    const double B1 = mx * mx + my * my + c1, B2 = sxx + syy + c2;
+                    const double S = A1 * A2 / (B1 * B2);
+                    vsum += S;
+                    if (ssim_map) ssim_map[3 * p + ch] = S;
+                    if (dS) {
+                        /* S = A1 A2 / (B1 B2) with s_xx = E_xx - mu_x^2 and
+                           s_xy = E_xy - mu_x mu_y */
+                        const double D = B1 * B2;
+                        const double dN = 2 * my * A2 + A1 * (-2 * my);
+                        const double dD = 2 * mx * B2 + B1 * (-2 * mx);
+                        dS[9 * p + 3 * ch + 0] = (dN * D - A1 * A2 * dD) / (D * D);
+                        dS[9 * p + 3 * ch + 1] = -S / B2;
+                        dS[9 * p + 3 * ch + 2] = 2 * A1 / D;
+                    }
+                }
+            }
+        total += vsum / (3.0 * (double)(off[v + 1] - off[v]));
+        if (v_rgb) {
+            const double sc = 1.0 / (3.0 * (double)(off[v + 1] - off[v]) * V);
+#pragma omp parallel for schedule(dynamic, 4)
+            for (int qy = 0; qy < H; qy++)
+                for (int qx = 0; qx < W; qx++) {
+                    const long long q = base + (long long)qy * W + qx;
+                    for (int ch = 0; ch < 3; ch++) {
+                        const double x = rgb[3 * q + ch], y = target[3 * q + ch];
+                        double s = 0;
+                        for (int j = -r; j <= r; j++) {
+                            const int py = qy + j;
+                            if (py < 0 || py >= H) continue;
+                            for (int i = -r; i <= r; i++) {
+                                const int px = qx + i;
+                                if (px < 0 || px >= W) continue;
+                                const double w = g[j + r] * g[i + r];
+                                const long long p = base + (long long)py * W + px;
+                                const double* d = dS + 9 * p + 3 * ch;
+                                s += w * (d[0] + 2 * x * d[1] + y * d[2]);
+                            }
+                        }
+                        v_rgb[3 * q + ch] = s * sc;
+                    }
+                }
+        }
+    }
+    if (ssim) *ssim = total / V;
+    free(dS);
+    free(off);
+    free(g);
+    return 0;
 }

@@ -20,9 +20,13 @@
  *   3 alpha_min (1/255)     4 alpha_max (0.99)        5 T_min (1e-4)
  *   6 band: float32 position error of mean2d, relative to its magnitude
  *   7 band: T stop, relative  8 band: float32 relative error of sigma
- *   9 band: depth tie, relative
+ *   9 band: depth key, relative distance of the FP64 depth from a midpoint
+ *     between two adjacent float32 values
  * A pixel is flagged ambiguous when a decision that shapes it (alpha gate,
- * alpha clamp, transmittance stop, depth order) lies within these bands.
+ * alpha clamp, transmittance stop, depth order) lies within these bands.  The
+ * depth order is the order of the float32-rounded depth (ties by pair index),
+ * so it is in doubt only where two neighbours' rounded depths are equal or
+ * adjacent and one FP64 depth sits within the band of a rounding midpoint.
  */
 #ifndef GLOSPLAT_ORACLE_H
 #define GLOSPLAT_ORACLE_H
@@ -45,9 +49,12 @@ int or_project(int N, int sh_degree, const double* means, const double* log_scal
                double* conic, double* opacity, double* rgb, double* ext);
 
 /* Brute-force per-pixel compositing over all valid splats of the pixel's view,
- * in (depth, index) order, with the 1/255 alpha gate and the 1e-4 transmittance
- * stop.  npix/pix select global pixel indices (pix == NULL: all pixels).
- * out_ngate = number of splats passing the alpha gate at the pixel.
+ * in ascending (float32 rounding of the depth, Gaussian index) order, with the
+ * 1/255 alpha gate, the 0.99 alpha clamp and the 1e-4 transmittance stop, then
+ * C + T bg.  npix/pix select global pixel indices (pix == NULL: all pixels).
+ * out_ngate = number of splats passing the alpha gate at the pixel;
+ * out_nclamp = number of contributors whose alpha was clamped (any output
+ * pointer may be NULL).
  * If v_rgb != NULL the exact derivative of the image is pulled back from the
  * stored per-pixel list into v2d[V*N][9] (accumulated):
  *   (d/d mean2d.x, mean2d.y, conic A, B, C, opacity, r, g, b),
@@ -56,8 +63,8 @@ int or_render(int V, const int* wh, int N, const int* valid, const double* depth
               const double* mean2d, const double* conic, const double* opacity,
               const double* rgb, const double* bg, const double* cfg,
               long long npix, const long long* pix,
-              double* out_rgb, double* out_T, int* out_ncontrib, int* out_ngate, int* ambiguous,
-              const double* v_rgb, double* v2d);
+              double* out_rgb, double* out_T, int* out_ncontrib, int* out_ngate, int* out_nclamp,
+              int* ambiguous, const double* v_rgb, double* v2d);
 
 /* Chain rule from the per-pair 2D gradients to the Gaussian parameters (summed
  * over views, overwriting the outputs) and to each view's left-perturbation
@@ -101,6 +108,19 @@ long long or_bin_sort(int V, const int* wh, int tile_w, int tile_h, int N,
                       const int* valid, const float* mean2d, const float* conic,
                       const float* opacity, const float* depth, double alpha_min,
                       double margin, long long cap, long long* ranges, int* ids, int* masks);
+
+/* Photometric L1 term: loss = mean over views of the mean over the view's
+ * pixels and channels of |rgb - target|; v_rgb[P][3] (may be NULL) =
+ * sign(rgb - target) / (3 P_v V), with sign(0) = 0. */
+int or_l1(int V, const int* wh, const double* rgb, const double* target, double* loss,
+          double* v_rgb);
+
+/* SSIM with a win x win Gaussian window (std wsig), constants c1, c2 and zeros
+ * beyond the image border: ssim = mean over views of the mean over the view's
+ * pixels and channels of the SSIM map; ssim_map[P][3] and v_rgb[P][3] =
+ * d ssim / d rgb may be NULL. */
+int or_ssim(int V, const int* wh, const double* rgb, const double* target, int win,
+            double wsig, double c1, double c2, double* ssim, double* ssim_map, double* v_rgb);
 
 /* Real spherical-harmonic basis (Condon-Shortley phase) at unit direction d,
  * K = (deg+1)^2 values; dY[K][3] = gradient of the polynomial form, may be

@@ -196,27 +196,34 @@ def _read_i32(ptr, n):
 def test_bin_sort_real_scene_lists(gs):
     # Membership: every (tile, splat) the exact float64 test keeps with some
     # room to spare is listed; nothing listed is far outside.  Order: each
-    # list is ascending in (gpu float32 depth, pair).
+    # list is strictly ascending in (float32 depth bits of the GPU's own
+    # record, pair index), bit for bit.
     sc = _parity_scene(seed=5, N=1500)
     sp, params, rgb, T, last, cams, ctx = _render(gs, sc)
     st = ctx.status()
     b = ctx.buffers()
     nt = b["n_tiles"]
+    N = sc["means"].shape[1]
     ranges = _read_i32(b["tile_ranges"], 2 * nt).reshape(nt, 2)
     ids = (_read_i32(b["isect_ids"], st["n_isect"]).view(np.uint32) & 0x0FFFFFFF).astype(np.int64)
+    rec = gs._lib.copy_to_host(b["records"], N * 12, np.float32).reshape(N, 12)
+    dbits = rec[:, 2].copy().view(np.uint32).astype(np.int64)
     pr = oracle.project(sc)
     inner_r, inner = oracle.bin_sort(sc["wh"], (16, 16), pr["valid"], pr["mean2d"], pr["conic"],
                                      pr["opacity"], pr["depth"].astype(np.float32), margin=-0.05)
     outer_r, outer = oracle.bin_sort(sc["wh"], (16, 16), pr["valid"], pr["mean2d"], pr["conic"],
                                      pr["opacity"], pr["depth"].astype(np.float32), margin=0.05)
-    depth = pr["depth"]
+    n_ties = 0
     for t in range(nt):
         g = ids[ranges[t, 0]:ranges[t, 1]]
         gi = set(inner[inner_r[t, 0]:inner_r[t, 1]].tolist())
         go = set(outer[outer_r[t, 0]:outer_r[t, 1]].tolist())
         assert gi <= set(g.tolist()) <= go, t
-        d = depth[g]
-        assert np.all(np.diff(d) >= -1e-6 * np.abs(d[1:])), t
+        key = dbits[g] * (1 << 32) + g        # (depth bits, pair) as one integer
+        assert np.all(np.diff(key) > 0), t
+        n_ties += int(np.sum(np.diff(dbits[g]) == 0))
+        # the GPU's float32 depth is the rounding of the FP64 depth
+        np.testing.assert_allclose(rec[g, 2], pr["depth"][g], rtol=6e-8)
 
 
 # ------------------------------------------------------------------ forward
@@ -232,6 +239,32 @@ def test_render_fwd_matches_oracle(gs, name):
     g = rgb.cpu().numpy()
     _close(g[ok], o["rgb"][ok], scale=max(1.0, np.abs(o["rgb"]).max()), what="rgb")
     _close(T.cpu().numpy()[ok], o["T"][ok], scale=1.0, what="T_final")
+
+
+def test_render_with_clamped_opacities_matches_oracle(gs):
+    """A quarter of the Gaussians above the 0.99 opacity clamp (logits 6..9)
+    and large enough that ~4% of the pixels see a clamped alpha: image and every
+    gradient group against the oracle (clamped hits pass no opacity or
+    geometry gradient)."""
+    sc = _parity_scene(seed=23, N=1500)
+    rng = np.random.default_rng(23)
+    hi = rng.choice(1500, 375, replace=False)
+    sc["opacity_logit"][hi] = rng.uniform(6.0, 9.0, size=375).astype(np.float32)
+    sc["log_scales"][:, hi] += np.float32(2.0)
+    o = oracle.render_fwd_bwd(sc)
+    assert o["nclamp"].sum() > 800, o["nclamp"].sum()
+    assert o["ambiguous"].mean() < 0.02
+    sp, params, rgb, T, last, cams, ctx = _render(gs, sc)
+    ok = ~o["ambiguous"]
+    _close(rgb.cpu().numpy()[ok], o["rgb"][ok], scale=1.0, what="rgb")
+    _close(T.cpu().numpy()[ok], o["T"][ok], scale=1.0, what="T_final")
+    w = np.random.default_rng(1).normal(size=(cams.n_pixels, 3))
+    w[o["ambiguous"]] = 0.0
+    grads, v_tw = sp.backward(params, sc["sh_degree"], cams, T, last, _t(w))
+    og = oracle.render_fwd_bwd(sc, v_rgb=w)["grads"]
+    for k in ("means", "log_scales", "quats", "opacity_logit", "sh"):
+        _close(grads[k].cpu().numpy(), og[k], what=k)
+    _close(v_tw.cpu().numpy()[0], og["twist"][0], what="twist")
 
 
 def test_render_fwd_bitwise_independent_of_tile_shape(gs):
@@ -366,12 +399,14 @@ def test_render_bwd_matches_oracle(gs, name):
         _close(tw[v], og["twist"][v], what=f"twist view {v}")
 
 
-def _full_size_check(gs, sub, tile, order, npix, min_ok, max_isect, seed):
+def _full_size_check(gs, sub, tile, order, npix, max_isect, seed, min_frac=0.97):
     """Sampled pixels and gradients of one full-size batch against the oracle:
     colour and transmittance of `npix` random pixels against the oracle's
     per-pixel definition, and the backward with an image gradient that is
     non-zero only at those pixels, so the oracle's gradients of every Gaussian
-    parameter and of each view's twist come from them alone."""
+    parameter and of each view's twist come from them alone.  At least
+    `min_frac` of the sampled pixels must be free of ambiguity (a gate, clamp,
+    stop or depth-rounding decision within float32 error of its threshold)."""
     from paper_2603_04847_amd.splat import Splatter
     V = sub["viewmat"].shape[0]
     N = sub["means"].shape[1]
@@ -388,10 +423,9 @@ def _full_size_check(gs, sub, tile, order, npix, min_ok, max_isect, seed):
     w = rng.normal(size=(pix.size, 3))
     pr = oracle.project(sub)
     o = oracle.render(pr, sub["wh"], pix=pix, v_rgb=w)
-    # deep lists hold pixels with two splats within a few ulp of depth:
-    # ambiguous, excluded
     ok = ~o["ambiguous"].astype(bool)
-    assert ok.sum() >= min_ok
+    print(f"[full-size] {ok.sum()}/{npix} sampled pixels unambiguous", flush=True)
+    assert ok.mean() >= min_frac, ok.mean()
     g_rgb = rgb.cpu().numpy()[pix]
     g_T = T.cpu().numpy()[pix]
     _close(g_rgb[ok], o["rgb"][ok], scale=max(np.max(np.abs(o["rgb"][ok])), 1.0), what="rgb")
@@ -422,23 +456,21 @@ def test_full_size_batch_sampled_pixels_and_gradients(gs):
     sc = scenegen.make_config("C4")
     b = scenegen.batch_views(4, sc["viewmat"].shape[0], 4, 1)[0]
     sub = dict(sc, viewmat=sc["viewmat"][b], intr=sc["intr"][b], wh=sc["wh"][b])
-    # at this depth complexity (~90 contributors per pixel) about a fifth of
-    # the pixels are ambiguous
-    _full_size_check(gs, sub, (16, 16), 1, 300, 200, 120_000_000, 12)
+    _full_size_check(gs, sub, (16, 16), 1, 400, 120_000_000, 12)
 
 
 def test_full_size_single_view_sampled(gs):
     """The single-view workload at full size (1237x822, 1M Gaussians, SH
     degree 3) at 16x16 tiles, heaviest first."""
     sc = scenegen.make_config("C2")
-    _full_size_check(gs, sc, (16, 16), 1, 200, 120, 150_000_000, 15)
+    _full_size_check(gs, sc, (16, 16), 1, 400, 150_000_000, 15)
 
 
 def test_full_size_uneven_views_sampled(gs):
     """The batched uneven-view workload at full size: 8 views from 640x480 to
     1600x1066 around 3M clustered Gaussians (SH degree 3), one call."""
     sc = scenegen.make_config("C3")
-    _full_size_check(gs, sc, (16, 16), 1, 100, 60, 400_000_000, 13)
+    _full_size_check(gs, sc, (16, 16), 1, 300, 400_000_000, 13)
 
 
 def test_full_size_large_scene_sampled(gs):
@@ -447,7 +479,7 @@ def test_full_size_large_scene_sampled(gs):
     sc = scenegen.make_config("C5")
     b = scenegen.batch_views(5, sc["viewmat"].shape[0], 4, 1)[0]
     sub = dict(sc, viewmat=sc["viewmat"][b], intr=sc["intr"][b], wh=sc["wh"][b])
-    _full_size_check(gs, sub, (32, 16), 0, 100, 60, 400_000_000, 14)
+    _full_size_check(gs, sub, (32, 16), 0, 300, 400_000_000, 14)
 
 
 def test_render_bwd_batched_views(gs):
@@ -474,12 +506,11 @@ def test_l1_loss_grad(gs):
     v = torch.empty((P, 3), device="cuda")
     loss = torch.zeros(1, device="cuda")
     gs.gs_l1_loss_grad(ctx, cams, _t(a), _t(b), v, loss)
-    d = a.astype(np.float64) - b
-    pv = np.repeat(wh[:, 0] * wh[:, 1], wh[:, 0] * wh[:, 1])[:, None]
-    want_v = np.sign(d) / (3 * pv * 2)
-    want_l = np.mean([np.abs(d[:1200]).mean(), np.abs(d[1200:]).mean()])
+    want_l, want_v = oracle.l1(a, b, wh)
+    # the sign is decided exactly on both sides (float32 subtraction keeps it)
+    assert np.array_equal(np.sign(v.cpu().numpy()), np.sign(want_v))
     _close(v.cpu().numpy(), want_v, what="v_rgb")
-    assert abs(loss.item() - want_l) <= 1e-5 * want_l
+    assert abs(loss.item() - want_l) <= RTOL * want_l
 
 
 def test_track_matches_oracle(gs):

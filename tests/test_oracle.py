@@ -630,3 +630,270 @@ def test_tile_membership_against_dense_sampling():
         lst = ids[ranges[t, 0]:ranges[t, 1]]
         keys = [(depth[i].view(np.uint32), i) for i in lst]
         assert keys == sorted(keys)
+
+
+# ----------------------------------------------------------------- order, clamp, background
+
+def _one_pixel(pr, W=32, H=16, px=(10, 7), **kw):
+    wh = np.array([[W, H]], np.int32)
+    return oracle.render(pr, wh, pix=[px[1] * W + px[0]], **kw)
+
+
+def _splats(depth, mean2d, conic, opacity, rgb):
+    n = len(depth)
+    return dict(valid=np.ones(n, np.int32), depth=np.asarray(depth, float),
+                mean2d=np.asarray(mean2d, float).reshape(n, 2),
+                conic=np.asarray(conic, float).reshape(n, 3),
+                opacity=np.asarray(opacity, float), rgb=np.asarray(rgb, float).reshape(n, 3))
+
+
+def test_compositing_order_is_float32_depth_then_index():
+    # Splats 0 and 1 have FP64 depths 1e-8 apart (a twentieth of a float32 ulp
+    # at 3): both round to 3.0f, so index 0 composites first although it is
+    # farther.  Splats 2 and 3 are one float32 ulp apart: depth decides.
+    c0, c1 = np.array([1.0, 0.0, 0.0]), np.array([0.0, 0.0, 1.0])
+    a0, a1 = 0.6, 0.3
+    up = float(np.nextafter(np.float32(3.0), np.float32(4.0)))
+    for d0, d1, first in ((3.0 + 1e-8, 3.0, 0), (up, 3.0, 1)):
+        assert (np.float32(d0) == np.float32(d1)) == (first == 0)
+        pr = _splats([d0, d1], [[10.5, 7.5]] * 2, [[0.5, 0, 0.5]] * 2, [a0, a1], [c0, c1])
+        out = _one_pixel(pr)
+        if first == 0:
+            want = c0 * a0 + c1 * a1 * (1 - a0)
+        else:
+            want = c1 * a1 + c0 * a0 * (1 - a1)
+        np.testing.assert_allclose(out["rgb"][0], want, rtol=1e-14)
+
+
+def test_depth_order_ambiguity_only_near_a_rounding_midpoint():
+    # equal float32 depths, FP64 depths far from a rounding midpoint: the
+    # order (by index) is certain; the same pair with one depth 1e-15 relative
+    # from a midpoint is flagged
+    f = np.float32(3.0)
+    up = np.nextafter(f, np.float32(4.0))
+    mid = 0.5 * (float(f) + float(up))
+    pr = _splats([3.0 + 1e-8, 3.0], [[10.5, 7.5]] * 2, [[0.5, 0, 0.5]] * 2, [0.6, 0.3],
+                 [[1, 0, 0], [0, 0, 1]])
+    assert not _one_pixel(pr)["ambiguous"][0]
+    pr["depth"][0] = mid * (1 + 1e-15)
+    assert _one_pixel(pr)["ambiguous"][0]
+    # far apart in float32: never ambiguous
+    pr["depth"][1] = 2.0
+    assert not _one_pixel(pr)["ambiguous"][0]
+
+
+def test_alpha_clamp_closed_form():
+    # o = 0.995 at the splat's own centre: alpha = min(0.99, 0.995) = 0.99
+    c = np.array([0.2, 0.5, 0.9])
+    pr = _splats([2.0], [[10.5, 7.5]], [[0.5, 0.0, 0.5]], [0.995], [c])
+    v = np.array([[0.3, -0.7, 1.1]])
+    out = _one_pixel(pr, v_rgb=v)
+    np.testing.assert_allclose(out["rgb"][0], 0.99 * c, rtol=1e-15)
+    np.testing.assert_allclose(out["T"][0], 0.01, rtol=1e-13)
+    assert out["nclamp"][0] == 1
+    # off-centre with sigma = 0.002 the raw alpha 0.995 e^-0.002 = 0.99301 is
+    # still clamped: no gradient reaches the opacity or the geometry, the
+    # colour gets alpha T = 0.99
+    dx = np.sqrt(2 * 0.002 / 0.5)
+    pr = _splats([2.0], [[10.5 + dx, 7.5]], [[0.5, 0.0, 0.5]], [0.995], [c])
+    out = _one_pixel(pr, v_rgb=v)
+    g = out["v2d"][0]
+    np.testing.assert_array_equal(g[:6], 0.0)
+    np.testing.assert_allclose(g[6:], 0.99 * v[0], rtol=1e-14)
+    np.testing.assert_allclose(out["rgb"][0], 0.99 * c, rtol=1e-15)
+    # below the clamp (o = 0.985): alpha = o e^-sigma and d alpha / d o = e^-sigma
+    pr = _splats([2.0], [[10.5 + dx, 7.5]], [[0.5, 0.0, 0.5]], [0.985], [c])
+    out = _one_pixel(pr, v_rgb=v)
+    a = 0.985 * np.exp(-0.002)
+    np.testing.assert_allclose(out["rgb"][0], a * c, rtol=1e-14)
+    np.testing.assert_allclose(out["v2d"][0, 5], np.exp(-0.002) * float(v[0] @ c), rtol=1e-13)
+    assert out["nclamp"][0] == 0
+
+
+def test_background_closed_form():
+    # two splats in front of a background: C = c0 a0 + c1 a1 (1 - a0)
+    # + (1 - a0)(1 - a1) bg, and dC/da0 = c0 - c1 a1 - (1 - a1) bg
+    bg = np.array([0.25, 0.5, 0.75])
+    c0, c1 = np.array([0.9, 0.1, 0.3]), np.array([0.2, 0.8, 0.4])
+    o0, o1, sig = 0.7, 0.45, 0.1
+    dx = np.sqrt(2 * sig / 0.5)
+    pr = _splats([1.0, 2.0], [[10.5 + dx, 7.5], [10.5, 7.5]], [[0.5, 0, 0.5]] * 2, [o0, o1],
+                 [c0, c1])
+    v = np.array([[0.4, -1.3, 0.8]])
+    out = _one_pixel(pr, bg=bg, v_rgb=v)
+    a0, a1 = o0 * np.exp(-sig), o1
+    want = c0 * a0 + c1 * a1 * (1 - a0) + (1 - a0) * (1 - a1) * bg
+    np.testing.assert_allclose(out["rgb"][0], want, rtol=1e-14)
+    dC_da0 = c0 - c1 * a1 - (1 - a1) * bg
+    np.testing.assert_allclose(out["v2d"][0, 5], np.exp(-sig) * float(v[0] @ dC_da0), rtol=1e-12)
+    dC_da1 = (1 - a0) * (c1 - bg)
+    np.testing.assert_allclose(out["v2d"][1, 5], float(v[0] @ dC_da1), rtol=1e-12)
+    # a pixel no splat reaches shows the background with T = 1
+    out = oracle.render(pr, np.array([[32, 16]], np.int32), pix=[15 * 32 + 31], bg=bg)
+    np.testing.assert_array_equal(out["rgb"][0], bg)
+    assert out["T"][0] == 1.0
+
+
+def _clamp_state2(out):
+    return _clamp_state(out) + (out["nclamp"].copy(),)
+
+
+def test_gradients_with_background_and_clamped_splats_against_central_differences():
+    # a background colour and a fifth of the Gaussians above the 0.99 opacity
+    # clamp (logit 7..9, large): the clamped hits pass no opacity or geometry
+    # gradient, the background enters dC/dalpha through T_final bg
+    sc = _small_scene(17, N=50, deg=1)
+    sc = {k: (v.astype(np.float64) if isinstance(v, np.ndarray) and v.dtype == np.float32 else v)
+          for k, v in sc.items()}
+    rng = np.random.default_rng(3)
+    hi = rng.choice(50, 10, replace=False)
+    sc["opacity_logit"][hi] = rng.uniform(7.0, 9.0, size=10)
+    sc["log_scales"][:, hi] = np.log(rng.uniform(0.6, 1.0, size=(3, 10)))
+    bg = np.array([0.3, 0.6, 0.9])
+    w = rng.normal(size=(40 * 30, 3))
+
+    def loss(viewmat=None):
+        out = oracle.render_fwd_bwd(sc, bg=bg, viewmat=viewmat)
+        return float(np.sum(out["rgb"] * w)), out
+
+    L0, base = loss()
+    assert base["nclamp"].sum() > 20
+    st0 = _clamp_state2(base)
+    an = oracle.render_fwd_bwd(sc, v_rgb=w, bg=bg)["grads"]
+    for key in ("means", "log_scales", "quats", "opacity_logit"):
+        flat = sc[key].reshape(-1)
+        a = an[key].reshape(-1)
+        errs, n_ok = [], 0
+        for i in range(flat.size):
+            h = 1e-6 * max(1.0, abs(flat[i]))
+            old = flat[i]
+            flat[i] = old + h
+            Lp, op = loss()
+            flat[i] = old - h
+            Lm, om = loss()
+            flat[i] = old
+            if _same_state(st0, _clamp_state2(op)) and _same_state(st0, _clamp_state2(om)):
+                errs.append(abs(a[i] - (Lp - Lm) / (2 * h)))
+                n_ok += 1
+        assert n_ok > 0.95 * flat.size, key
+        assert max(errs) <= 1e-6 * np.max(np.abs(a)) + 1e-9, (key, max(errs))
+    for k in range(6):
+        xi = np.zeros(6)
+        xi[k] = 1e-6
+        Lp, op = loss(_left_perturb(sc["viewmat"][0], xi)[None])
+        Lm, om = loss(_left_perturb(sc["viewmat"][0], -xi)[None])
+        assert _same_state(st0, _clamp_state2(op)) and _same_state(st0, _clamp_state2(om))
+        assert abs((Lp - Lm) / 2e-6 - an["twist"][0, k]) <= 1e-6 * np.abs(an["twist"]).max() + 1e-9
+
+
+# ----------------------------------------------------------------- photometric terms
+
+def test_l1_closed_form_view_weighting_and_ties():
+    # two views of different sizes, |d| = 0.1 on the first and 0.3 on the
+    # second: the mean over views is 0.2 (pooling all pixels would give 0.277)
+    wh = np.array([[8, 5], [20, 11]], np.int32)
+    P0, P1 = 40, 220
+    rng = np.random.default_rng(2)
+    t = rng.uniform(0.3, 0.7, size=(P0 + P1, 3))
+    s = np.where(rng.uniform(size=t.shape) < 0.5, -1.0, 1.0)
+    x = t + s * np.concatenate([np.full((P0, 3), 0.1), np.full((P1, 3), 0.3)])
+    loss, v = oracle.l1(x, t, wh)
+    assert abs(loss - 0.2) < 1e-14
+    np.testing.assert_allclose(v[:P0], s[:P0] / (3 * P0 * 2), rtol=1e-15)
+    np.testing.assert_allclose(v[P0:], s[P0:] / (3 * P1 * 2), rtol=1e-15)
+    x[:7] = t[:7]                                   # exact ties: sign(0) = 0
+    loss, v = oracle.l1(x, t, wh)
+    np.testing.assert_array_equal(v[:7], 0.0)
+    # central differences away from ties
+    h = 1e-7
+    for i in rng.choice(x.size, 20, replace=False):
+        xp, xm = x.copy().reshape(-1), x.copy().reshape(-1)
+        if xp[i] == t.reshape(-1)[i]:
+            continue
+        xp[i] += h
+        xm[i] -= h
+        fd = (oracle.l1(xp.reshape(x.shape), t, wh)[0] - oracle.l1(xm.reshape(x.shape), t, wh)[0]) / (2 * h)
+        assert abs(fd - v.reshape(-1)[i]) <= 1e-6 * abs(v.reshape(-1)[i])
+
+
+def _gauss_window_1d(win=11, sigma=1.5):
+    i = np.arange(win) - win // 2
+    g = np.exp(-i ** 2 / (2 * sigma ** 2))
+    return g / g.sum()
+
+
+def _ssim_scalar(mx, my, sxx, syy, sxy, c1=oracle.SSIM_C1, c2=oracle.SSIM_C2):
+    return (2 * mx * my + c1) * (2 * sxy + c2) / ((mx ** 2 + my ** 2 + c1) * (sxx + syy + c2))
+
+
+def test_ssim_of_an_image_with_itself_is_one_with_zero_gradient():
+    rng = np.random.default_rng(5)
+    wh = np.array([[23, 17], [9, 6]], np.int32)
+    x = rng.uniform(size=(23 * 17 + 54, 3))
+    s, v, m = oracle.ssim(x, x, wh, ssim_map=True)
+    assert abs(s - 1) < 1e-14
+    np.testing.assert_allclose(m, 1.0, atol=1e-14)
+    np.testing.assert_allclose(v, 0.0, atol=1e-14)
+    y = rng.uniform(size=x.shape)
+    assert abs(oracle.ssim(x, y, wh, grad=False)[0] - oracle.ssim(y, x, wh, grad=False)[0]) < 1e-15
+
+
+def test_ssim_constant_images_closed_form_interior_and_border():
+    # constants a, b with zeros beyond the border: at a pixel whose window keeps
+    # mass m inside the image, mu = a m, E_xx = a^2 m, so s_xx = a^2 m (1 - m)
+    # and s_xy = a b m (1 - m); inside (m = 1) S = (2ab + c1) / (a^2 + b^2 + c1)
+    W, H = 30, 24
+    a, b = 0.62, 0.35
+    x = np.full((W * H, 3), a)
+    y = np.full((W * H, 3), b)
+    _, _, m = oracle.ssim(x, y, np.array([[W, H]], np.int32), grad=False, ssim_map=True)
+    m = m[:, 0].reshape(H, W)
+    g = _gauss_window_1d()
+    for (px, py) in ((15, 12), (0, 0), (3, 0), (29, 10), (7, 22)):
+        mx = sum(g[i + 5] for i in range(-5, 6) if 0 <= px + i < W)
+        my = sum(g[j + 5] for j in range(-5, 6) if 0 <= py + j < H)
+        mass = mx * my
+        want = _ssim_scalar(a * mass, b * mass, a * a * mass * (1 - mass), b * b * mass * (1 - mass),
+                            a * b * mass * (1 - mass))
+        # (E_xx - mu^2 cancels: rounding ~1e-16 against c2 ~1e-3)
+        assert abs(m[py, px] - want) <= 1e-10, (px, py, m[py, px], want)
+    assert abs(m[12, 15] - (2 * a * b + oracle.SSIM_C1) / (a * a + b * b + oracle.SSIM_C1)) < 1e-10
+
+
+def test_ssim_ramp_closed_form():
+    # x a ramp along u with slope s, y = k x + c: inside the image the window
+    # (symmetric, unit mass) gives mu_x = x(p), s_xx = s^2 var_w with var_w the
+    # window's second moment, s_xy = k s_xx, s_yy = k^2 s_xx
+    W, H = 40, 30
+    s_, k, c = 0.013, -0.7, 0.8
+    u = np.tile(np.arange(W), H).astype(float)
+    x = np.repeat((0.1 + s_ * u)[:, None], 3, axis=1)
+    y = k * x + c
+    _, _, m = oracle.ssim(x, y, np.array([[W, H]], np.int32), grad=False, ssim_map=True)
+    g = _gauss_window_1d()
+    var_w = float(np.sum(g * (np.arange(11) - 5.0) ** 2))
+    for (px, py) in ((5, 5), (20, 15), (34, 24)):
+        mu = 0.1 + s_ * px
+        sxx = s_ * s_ * var_w
+        want = _ssim_scalar(mu, k * mu + c, sxx, k * k * sxx, k * sxx)
+        got = m.reshape(H, W, 3)[py, px]
+        np.testing.assert_allclose(got, want, rtol=1e-12)
+
+
+def test_ssim_gradient_against_central_differences():
+    rng = np.random.default_rng(6)
+    wh = np.array([[14, 9], [7, 5]], np.int32)    # one view smaller than the window
+    P = 14 * 9 + 35
+    x = rng.uniform(size=(P, 3))
+    y = np.clip(x + rng.normal(0, 0.2, size=x.shape), 0, 1)
+    s, v, _ = oracle.ssim(x, y, wh)
+    h = 1e-6
+    flat = x.reshape(-1)
+    for i in range(flat.size):
+        old = flat[i]
+        flat[i] = old + h
+        sp = oracle.ssim(x, y, wh, grad=False)[0]
+        flat[i] = old - h
+        sm = oracle.ssim(x, y, wh, grad=False)[0]
+        flat[i] = old
+        assert abs((sp - sm) / (2 * h) - v.reshape(-1)[i]) <= 1e-7 * np.abs(v).max(), i
