@@ -157,7 +157,7 @@ def run_joint(torch, name, steps, warmup, tune=True, tile=None, order=0, graph=T
         for bb in range(len(batches)):
             g = torch.cuda.CUDAGraph()
             with torch.cuda.graph(g):
-                st.run(bb, step=st.step_count + 1)
+                st.run(bb)  # the device step counter advances on every replay
             graphs.append(g)
         torch.cuda.synchronize()
         for g in graphs:  # untimed first replays (graph upload)

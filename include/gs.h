@@ -84,9 +84,12 @@ typedef enum {
 
 /* Device status flags (gs_diag.flags). */
 #define GS_FLAG_ISECT_OVERFLOW 1u   /* tile-list entries exceeded max_isect */
-#define GS_FLAG_NONFINITE 2u        /* a non-finite projected splat was culled */
+#define GS_FLAG_NONFINITE 2u        /* a Gaussian with a non-finite parameter, or a pair whose
+                                       projected record was not finite, was culled (it
+                                       contributes nothing and receives no gradient) */
 #define GS_FLAG_SCAN_STALLED 4u     /* a device-wide scan stopped waiting for a preceding
-                                       workgroup (bounded wait); that step's lists are invalid */
+                                       workgroup (bounded wait); that step counts as overflowed:
+                                       its lists are empty, and no write leaves its buffer */
 #define GS_FLAG_COUNT_BOUND 8u      /* internal check: a pair met more blocks than the bound its
                                        slots were sized by; that step's lists are incomplete */
 
@@ -184,6 +187,12 @@ gs_status gs_ctx_create(gs_ctx** out, const gs_capacity* cap);
 gs_status gs_ctx_destroy(gs_ctx* ctx);
 /* Synchronise the device and read the status word. */
 gs_status gs_ctx_status(gs_ctx* ctx, gs_diag* out);
+/* Number of gs_bin_sort calls enqueued on the context so far (HOST value, no
+ * synchronisation).  The tile lists and projected records a backward reads
+ * are those of the latest gs_project / gs_bin_sort; a caller holding several
+ * forwards compares this number to the one it saw at its forward and
+ * re-projects and re-bins before a backward whose lists were replaced. */
+gs_status gs_ctx_generation(gs_ctx* ctx, int64_t* generation);
 /* Clear the status flags and counters (enqueued on stream). */
 gs_status gs_ctx_reset_status(gs_ctx* ctx, void* stream);
 /* Device pointers into the workspace (valid for the context's lifetime):
@@ -234,7 +243,12 @@ gs_status gs_project(gs_ctx* ctx, const gs_gaussians* g, const gs_cameras* cams,
 gs_status gs_bin_sort(gs_ctx* ctx, const gs_cameras* cams, int32_t N,
                       const gs_settings* s, const float* records, void* stream);
 
-/* Forward compositing over the tile lists of the last gs_bin_sort.
+/* The projected records and the tile lists live in the context: gs_project
+ * writes the records, gs_bin_sort the lists, and the render calls read the
+ * latest ones (they are not passed as arguments).
+ *
+ * Forward compositing (the Rasterize step of Algorithm 1, render step; the
+ * per-pixel definition above) over the tile lists of the last gs_bin_sort.
  * bg[3] (device, may be NULL = black).  Outputs rgb[P][3], T_final[P] and
  * last[P] = 1 + position, within its tile's list, of the pixel's final
  * contributor (0 if none); P = sum_v W_v H_v.  T_final and last are what the
@@ -244,12 +258,15 @@ gs_status gs_render_fwd(gs_ctx* ctx, const gs_cameras* cams, const gs_settings* 
                         const float* bg, float* rgb, float* T_final, int32_t* last,
                         void* stream);
 
-/* Backward of gs_project + gs_render_fwd for the image gradient v_rgb[P][3]:
+/* Backward of gs_project + gs_render_fwd (Algorithm 1, backward step: the
+ * gradient of the photometric loss to the Gaussians and, through the dual
+ * gradient flow, to each pose) for the image gradient v_rgb[P][3]:
  * walks each pixel's list back to front from `last`, recovering T by division,
  * reduces per splat over the wave before any global atomic, then chains the
  * per-pair 2D gradients to the Gaussian parameters (summed over views; written
  * or added per s->grad_accumulate) and adds each view's twist gradient into
- * row index[v] (or v) of v_twist.  `g` and `cams` must be those of the forward. */
+ * row index[v] (or v) of v_twist.  `g` and `cams` must be those of the forward.
+ * Every argument check of both halves runs before any work is enqueued. */
 gs_status gs_render_bwd(gs_ctx* ctx, const gs_gaussians* g, const gs_cameras* cams,
                         const gs_settings* s, const float* bg, const float* T_final,
                         const int32_t* last, const float* v_rgb, gs_gaussians_grad* grads,
@@ -321,7 +338,11 @@ gs_status gs_pose_compose_bwd(int32_t V, const float* twist, const float* g, flo
 
 /* One Adam step (Algorithm 1, update step) on up to GS_ADAM_MAX_GROUPS
  * parameter groups in one launch: p -= lr m_hat / (sqrt(v_hat) + eps) with
- * bias-corrected moments; m, v updated in place. */
+ * bias-corrected moments; m, v updated in place.  The step number t of the
+ * bias corrections 1 / (1 - beta^t) is *step_dev (a device int32 read when the
+ * kernel runs; values below 1 count as 1) when step_dev is not NULL, else
+ * `step` (>= 1).  With the device counter a captured HIP graph takes a new
+ * step number on every replay (see gs_step_advance). */
 #define GS_ADAM_MAX_GROUPS 16
 typedef struct {
     float* param;
@@ -333,7 +354,12 @@ typedef struct {
 } gs_adam_group;
 
 gs_status gs_adam_step(const gs_adam_group* groups, int32_t n_groups, int32_t step,
-                       float beta1, float beta2, float eps, void* stream);
+                       const int32_t* step_dev, float beta1, float beta2, float eps,
+                       void* stream);
+
+/* *step_dev += 1 on the device (enqueued on stream): the step counter a
+ * training step advances once before its Adam calls read it. */
+gs_status gs_step_advance(int32_t* step_dev, void* stream);
 
 /* Adam state of the five Gaussian arrays for gs_project_bwd_adam: params[q] is
  * the array of gs_gaussians it steps (means, log_scales, quats, opacity_logit,
@@ -352,10 +378,12 @@ typedef struct {
  * of being written, so the gradients never reach memory.  Same results as the
  * two calls (the element update is the same code); the twists are added into
  * v_twist as gs_project_bwd does.  The arrays of `adam->params` must be those
- * of `g`; step >= 1. */
+ * of `g`; the step number is *step_dev when step_dev is not NULL, else step
+ * (>= 1), as in gs_adam_step. */
 gs_status gs_project_bwd_adam(gs_ctx* ctx, const gs_gaussians* g, const gs_cameras* cams,
                               const gs_settings* s, const gs_gaussian_adam* adam, int32_t step,
-                              float beta1, float beta2, float eps, float* v_twist, void* stream);
+                              const int32_t* step_dev, float beta1, float beta2, float eps,
+                              float* v_twist, void* stream);
 
 #ifdef __cplusplus
 }

@@ -82,6 +82,7 @@ EXPORTS = [
     "gs_ctx_reset_status", "gs_ctx_buffers", "gs_ctx_tile_stats", "gs_project", "gs_bin_sort", "gs_render_fwd",
     "gs_render_bwd", "gs_raster_bwd", "gs_project_bwd", "gs_l1_loss_grad", "track_reproj_fwd_bwd", "gs_pose_compose",
     "gs_pose_compose_bwd", "gs_adam_step", "gs_project_bwd_adam", "track_point_index",
+    "gs_step_advance", "gs_ctx_generation",
 ]
 
 _lib = None
@@ -140,11 +141,13 @@ def load():
     lib.gs_pose_compose.argtypes = [ctypes.c_int32, c_vp, c_vp, c_vp, c_vp]
     lib.gs_pose_compose_bwd.argtypes = [ctypes.c_int32, c_vp, c_vp, c_vp, c_vp]
     lib.gs_adam_step.argtypes = [ctypes.POINTER(gs_adam_group), ctypes.c_int32, ctypes.c_int32,
-                                 ctypes.c_float, ctypes.c_float, ctypes.c_float, c_vp]
+                                 c_vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, c_vp]
     lib.gs_project_bwd_adam.argtypes = [c_vp, ctypes.POINTER(gs_gaussians), ctypes.POINTER(gs_cameras),
                                         ctypes.POINTER(gs_settings), ctypes.POINTER(gs_gaussian_adam),
-                                        ctypes.c_int32, ctypes.c_float, ctypes.c_float,
+                                        ctypes.c_int32, c_vp, ctypes.c_float, ctypes.c_float,
                                         ctypes.c_float, c_vp, c_vp]
+    lib.gs_step_advance.argtypes = [c_vp, c_vp]
+    lib.gs_ctx_generation.argtypes = [c_vp, ctypes.POINTER(ctypes.c_int64)]
     _lib = lib
     return lib
 
@@ -276,6 +279,12 @@ class Context:
         return dict(flags=d.flags, n_isect=d.n_isect, n_isect_needed=d.n_isect_needed,
                     n_masked_obs=d.n_masked_obs, n_visible=d.n_visible)
 
+    def generation(self):
+        """gs_bin_sort calls enqueued on this context so far."""
+        g = ctypes.c_int64()
+        _check("gs_ctx_generation", load().gs_ctx_generation(self.handle, ctypes.byref(g)))
+        return g.value
+
     def reset_status(self, stream=None):
         _check("gs_ctx_reset_status", load().gs_ctx_reset_status(self.handle, _stream(stream)))
 
@@ -385,9 +394,11 @@ def gs_pose_compose_bwd(twist, g, out, stream=None):
 
 
 def gs_project_bwd_adam(ctx, gaussians, cams, settings, params, exp_avg, exp_avg_sq, lrs, step,
-                        v_twist, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):
+                        v_twist, beta1=0.9, beta2=0.999, eps=1e-15, step_dev=None, stream=None):
     """params / exp_avg / exp_avg_sq: the five Gaussian tensors (means,
-    log_scales, quats, opacity_logit, sh) and their moments; lrs: five rates."""
+    log_scales, quats, opacity_logit, sh) and their moments; lrs: five rates;
+    step_dev: an int32 device tensor holding the step number (then `step` is
+    ignored)."""
     a = gs_gaussian_adam()
     for q in range(5):
         a.params[q] = _ptr(params[q])
@@ -396,14 +407,22 @@ def gs_project_bwd_adam(ctx, gaussians, cams, settings, params, exp_avg, exp_avg
         a.lr[q] = float(lrs[q])
     _check("gs_project_bwd_adam", load().gs_project_bwd_adam(
         ctx.handle, ctypes.byref(gaussians), ctypes.byref(cams.struct), ctypes.byref(settings),
-        ctypes.byref(a), int(step), float(beta1), float(beta2), float(eps), _ptr(v_twist),
-        _stream(stream)))
+        ctypes.byref(a), int(step), _ptr(step_dev), float(beta1), float(beta2), float(eps),
+        _ptr(v_twist), _stream(stream)))
 
 
-def gs_adam_step(groups, step, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):
-    """groups: list of (param, grad, exp_avg, exp_avg_sq, lr) tensors/floats."""
+def gs_adam_step(groups, step, beta1=0.9, beta2=0.999, eps=1e-15, step_dev=None, stream=None):
+    """groups: list of (param, grad, exp_avg, exp_avg_sq, lr) tensors/floats;
+    step_dev: an int32 device tensor holding the step number (then `step` is
+    ignored)."""
     arr = (gs_adam_group * len(groups))()
     for i, (p, g, m, v, lr) in enumerate(groups):
         arr[i] = gs_adam_group(_ptr(p), _ptr(g), _ptr(m), _ptr(v), int(p.numel()), float(lr))
-    _check("gs_adam_step", load().gs_adam_step(arr, len(groups), int(step), float(beta1),
-                                               float(beta2), float(eps), _stream(stream)))
+    _check("gs_adam_step", load().gs_adam_step(arr, len(groups), int(step), _ptr(step_dev),
+                                               float(beta1), float(beta2), float(eps),
+                                               _stream(stream)))
+
+
+def gs_step_advance(step_dev, stream=None):
+    """step_dev (int32 device tensor) += 1 on the device."""
+    _check("gs_step_advance", load().gs_step_advance(_ptr(step_dev), _stream(stream)))

@@ -157,7 +157,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(const float4* __restrict__ rec,
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     WaveUnits& wu = s_wu[w];
     const QuadGrid qg = quad_grid(rp.tile_w, rp.tile_h);
-    const bool any = *used != 0u;  // nothing is written after an overflow
+    const uint32_t lim = *used;    // nothing is written after an overflow
+    const bool any = lim != 0u;
     float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
     int v = 0;
     bool ok = false;
@@ -171,7 +172,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(const float4* __restrict__ rec,
     if (r < n && any) {
         pair = order[r];
         o0 = off[r];
-        c = (r + 1 < n ? off[r + 1] : *used) - o0;
+        const uint32_t o1 = r + 1 < n ? off[r + 1] : lim;
+        c = o1 > o0 ? o1 - o0 : 0u;
         if (c > 0) {
             a = rec[3 * (int64_t)pair];
             b = rec[3 * (int64_t)pair + 1];
@@ -213,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(const float4* __restrict__ rec,
             for (int bc = u.bc0; bc <= u.bc1; bc++) {
                 const uint64_t m = block_unit_mask(u, bc);
                 if (m == 0) continue;
-                if (o < wave_total) {  // never write outside the wave's slots
+                if (o < wave_total && base + o < lim) {  // never outside the wave's slots
                     okey[base + o] = brow + (uint32_t)bc;
                     opair[base + o] = pq;
                     omlo[base + o] = (uint32_t)m;
@@ -228,7 +230,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(const float4* __restrict__ rec,
     }
     // slots the count's bound left over get a sentinel block id past every
     // block and no mask, so no list ever reads them
-    for (uint32_t o = done + lane; o < wave_total; o += kWave) {
+    for (uint32_t o = done + lane; o < wave_total && base + o < lim; o += kWave) {
         okey[base + o] = (uint32_t)vt.block_off[vt.V];
         opair[base + o] = s_pair[w][0];
         omlo[base + o] = 0;
@@ -493,7 +495,8 @@ __global__ __launch_bounds__(kBlock) void k_chunk_expand(
     __shared__ uint32_t s_stage[kWaves][kStage];
     __shared__ uint32_t s_gpre[kWaves][kBlockSub + 1];  // group starts in the stage
     __shared__ uint32_t s_gbase[kWaves][kBlockSub];     // group starts in the lists
-    if (*tused == 0u) return;  // nothing is written after an overflow
+    const uint32_t tcap = *tused;  // list entries; every write stays below
+    if (tcap == 0u) return;        // nothing is written after an overflow
     const int64_t n = *used;
     const int64_t stride = chunk_stride(used);
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
@@ -546,7 +549,8 @@ __global__ __launch_bounds__(kBlock) void k_chunk_expand(
                     const uint32_t m4 = tile_bits(m[u], q % kBlockTiles, q / kBlockTiles);
                     // group q starts after the counts of sub-tiles 0 .. q-1
                     const uint32_t g0 = q == 0 ? 0u : (uint32_t)__builtin_amdgcn_readlane((int)inc, q - 1);
-                    if (m4) s_stage[w][g0 + run[q] + (uint32_t)__popcll(bal & lt)] = pr[u] | (m4 << kPairBits);
+                    const uint32_t si = g0 + run[q] + (uint32_t)__popcll(bal & lt);
+                    if (m4 && si < (uint32_t)kStage) s_stage[w][si] = pr[u] | (m4 << kPairBits);
                     run[q] += (uint32_t)__popcll(bal);
                 }
             }
@@ -557,7 +561,8 @@ __global__ __launch_bounds__(kBlock) void k_chunk_expand(
 #pragma unroll
                 for (int h = kBlockSub / 2; h > 0; h >>= 1)
                     if (s_gpre[w][q + h] <= f) q += h;
-                tids[s_gbase[w][q] + (f - s_gpre[w][q])] = s_stage[w][f];
+                const uint32_t ti = s_gbase[w][q] + (f - s_gpre[w][q]);
+                if (ti < tcap) tids[ti] = s_stage[w][f];
             }
             wave_lds_sync();  // the stage is read before the next chunk's writes
         } else if (__ballot(other) == 0) {
@@ -569,7 +574,8 @@ __global__ __launch_bounds__(kBlock) void k_chunk_expand(
                     if (bal == 0) continue;  // wave-uniform
                     const uint32_t m4 = tile_bits(m[u], q % kBlockTiles, q / kBlockTiles);
                     const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)cbq, q) + run[q];
-                    if (m4) tids[base + (uint32_t)__popcll(bal & lt)] = pr[u] | (m4 << kPairBits);
+                    const uint32_t ti = base + (uint32_t)__popcll(bal & lt);
+                    if (m4 && ti < tcap) tids[ti] = pr[u] | (m4 << kPairBits);
                     run[q] += (uint32_t)__popcll(bal);
                 }
             }
@@ -586,7 +592,8 @@ __global__ __launch_bounds__(kBlock) void k_chunk_expand(
                     if (m4) {
                         const uint32_t base = tbase[(int64_t)Bq * kBlockSub + q] +
                                               cpre[(int64_t)q * stride + c] + run[q];
-                        tids[base + (uint32_t)__popcll(bal & lt)] = pr[u] | (m4 << kPairBits);
+                        const uint32_t ti = base + (uint32_t)__popcll(bal & lt);
+                        if (ti < tcap) tids[ti] = pr[u] | (m4 << kPairBits);
                     }
                     run[q] += (uint32_t)__popcll(bal);
                 }

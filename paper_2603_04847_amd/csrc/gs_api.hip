@@ -264,6 +264,12 @@ gs_status gs_ctx_buffers(gs_ctx* h, float** records, int32_t** isect_ids, int32_
     return GS_OK;
 }
 
+gs_status gs_ctx_generation(gs_ctx* h, int64_t* generation) {
+    if (!h || !generation) return GS_ERR_INVALID_ARG;
+    *generation = h->c.generation;
+    return GS_OK;
+}
+
 gs_status gs_ctx_tile_stats(gs_ctx* h, const int32_t** tile_contrib, const int32_t** tile_entries,
                             const int32_t** tile_evals, const uint32_t** tile_order,
                             int32_t* ordered, int64_t* n_tiles) {
@@ -302,6 +308,7 @@ gs_status gs_bin_sort(gs_ctx* h, const gs_cameras* cams, int32_t N, const gs_set
     const gs::ViewTable vt = gs::make_view_table(cams->wh, cams->V, s->tile_w, s->tile_h, cams->index);
     if (vt.tile_off[vt.V] > h->c.cap.max_tiles) return GS_ERR_CAPACITY;
     const gs::RasterParams rp = gs::make_raster_params(s);
+    h->c.generation++;
     return from_hip(gs::launch_bin(&h->c, vt, N, rp, records, s->tile_order, (hipStream_t)stream));
 }
 
@@ -322,13 +329,35 @@ gs_status gs_render_fwd(gs_ctx* h, const gs_cameras* cams, const gs_settings* s,
     return from_hip(gs::launch_render_fwd(&h->c, vt, rp, bg, rgb, T_final, last, (hipStream_t)stream));
 }
 
-gs_status gs_raster_bwd(gs_ctx* h, const gs_cameras* cams, const gs_settings* s, const float* bg,
-                        const float* T_final, const int32_t* last, const float* v_rgb, void* stream) {
+static gs_status check_raster_bwd(gs_ctx* h, const gs_cameras* cams, const gs_settings* s,
+                                  const float* T_final, const int32_t* last, const float* v_rgb) {
     if (!h || !T_final || !last || !v_rgb) return GS_ERR_INVALID_ARG;
     gs_status r;
     if ((r = check_settings(s)) != GS_OK) return r;
     if ((r = check_cams(h->c, cams, false)) != GS_OK) return r;
+    return check_bins_match(h->c, cams, s);
+}
+
+static gs_status check_project_bwd(gs_ctx* h, const gs_gaussians* g, const gs_cameras* cams,
+                                   const gs_settings* s, const gs_gaussians_grad* grads,
+                                   const float* v_twist) {
+    if (!h || !v_twist) return GS_ERR_INVALID_ARG;
+    gs_status r;
+    if ((r = check_settings(s)) != GS_OK) return r;
+    if ((r = check_gaussians(g)) != GS_OK) return r;
+    if ((r = check_cams(h->c, cams, true)) != GS_OK) return r;
     if ((r = check_bins_match(h->c, cams, s)) != GS_OK) return r;
+    if (h->c.bin_N != g->N) return GS_ERR_INVALID_ARG;
+    if (grads && g->N > 0 && (!grads->means || !grads->log_scales || !grads->quats ||
+                              !grads->opacity_logit || !grads->sh))
+        return GS_ERR_INVALID_ARG;
+    return GS_OK;
+}
+
+gs_status gs_raster_bwd(gs_ctx* h, const gs_cameras* cams, const gs_settings* s, const float* bg,
+                        const float* T_final, const int32_t* last, const float* v_rgb, void* stream) {
+    gs_status r;
+    if ((r = check_raster_bwd(h, cams, s, T_final, last, v_rgb)) != GS_OK) return r;
     const gs::ViewTable vt = gs::make_view_table(cams->wh, cams->V, s->tile_w, s->tile_h, cams->index);
     const gs::RasterParams rp = gs::make_raster_params(s);
     return from_hip(gs::launch_render_bwd(&h->c, vt, rp, bg, T_final, last, v_rgb, (hipStream_t)stream));
@@ -336,16 +365,9 @@ gs_status gs_raster_bwd(gs_ctx* h, const gs_cameras* cams, const gs_settings* s,
 
 gs_status gs_project_bwd(gs_ctx* h, const gs_gaussians* g, const gs_cameras* cams, const gs_settings* s,
                          gs_gaussians_grad* grads, float* v_twist, void* stream) {
-    if (!h || !grads || !v_twist) return GS_ERR_INVALID_ARG;
+    if (!grads) return GS_ERR_INVALID_ARG;
     gs_status r;
-    if ((r = check_settings(s)) != GS_OK) return r;
-    if ((r = check_gaussians(g)) != GS_OK) return r;
-    if ((r = check_cams(h->c, cams, true)) != GS_OK) return r;
-    if ((r = check_bins_match(h->c, cams, s)) != GS_OK) return r;
-    if (h->c.bin_N != g->N) return GS_ERR_INVALID_ARG;
-    if (g->N > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logit ||
-                     !grads->sh))
-        return GS_ERR_INVALID_ARG;
+    if ((r = check_project_bwd(h, g, cams, s, grads, v_twist)) != GS_OK) return r;
     const gs::ViewTable vt = gs::make_view_table(cams->wh, cams->V, s->tile_w, s->tile_h, cams->index);
     const gs::RasterParams rp = gs::make_raster_params(s);
     return from_hip(gs::launch_project_bwd(&h->c, g, cams, vt, rp, nullptr, grads, s->grad_accumulate,
@@ -354,16 +376,13 @@ gs_status gs_project_bwd(gs_ctx* h, const gs_gaussians* g, const gs_cameras* cam
 
 gs_status gs_project_bwd_adam(gs_ctx* h, const gs_gaussians* g, const gs_cameras* cams,
                               const gs_settings* s, const gs_gaussian_adam* adam, int32_t step,
-                              float beta1, float beta2, float eps, float* v_twist, void* stream) {
-    if (!h || !adam || !v_twist || step <= 0) return GS_ERR_INVALID_ARG;
+                              const int32_t* step_dev, float beta1, float beta2, float eps,
+                              float* v_twist, void* stream) {
+    if (!adam || (!step_dev && step <= 0)) return GS_ERR_INVALID_ARG;
     if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f))
         return GS_ERR_INVALID_ARG;
     gs_status r;
-    if ((r = check_settings(s)) != GS_OK) return r;
-    if ((r = check_gaussians(g)) != GS_OK) return r;
-    if ((r = check_cams(h->c, cams, true)) != GS_OK) return r;
-    if ((r = check_bins_match(h->c, cams, s)) != GS_OK) return r;
-    if (h->c.bin_N != g->N) return GS_ERR_INVALID_ARG;
+    if ((r = check_project_bwd(h, g, cams, s, nullptr, v_twist)) != GS_OK) return r;
     // the parameters stepped are the arrays g points to (updated in place)
     const float* arrays[5] = {g->means, g->log_scales, g->quats, g->opacity_logit, g->sh};
     gs::AdamGauss a{};
@@ -378,8 +397,8 @@ gs_status gs_project_bwd_adam(gs_ctx* h, const gs_gaussians* g, const gs_cameras
     a.b1 = beta1;
     a.b2 = beta2;
     a.eps = eps;
-    a.ibc1 = (float)(1.0 / (1.0 - pow((double)beta1, step)));
-    a.ibc2 = (float)(1.0 / (1.0 - pow((double)beta2, step)));
+    a.step_dev = step_dev;
+    a.step = step;
     const gs::ViewTable vt = gs::make_view_table(cams->wh, cams->V, s->tile_w, s->tile_h, cams->index);
     const gs::RasterParams rp = gs::make_raster_params(s);
     return from_hip(gs::launch_project_bwd(&h->c, g, cams, vt, rp, &a, nullptr, 0, v_twist,
@@ -389,10 +408,12 @@ gs_status gs_project_bwd_adam(gs_ctx* h, const gs_gaussians* g, const gs_cameras
 gs_status gs_render_bwd(gs_ctx* h, const gs_gaussians* g, const gs_cameras* cams, const gs_settings* s,
                         const float* bg, const float* T_final, const int32_t* last, const float* v_rgb,
                         gs_gaussians_grad* grads, float* v_twist, void* stream) {
-    if (!h || !grads || !v_twist) return GS_ERR_INVALID_ARG;
+    // every check of both halves before anything is enqueued: a failed check
+    // must not leave 2D gradients behind in the context
+    if (!grads) return GS_ERR_INVALID_ARG;
     gs_status r;
-    if ((r = check_gaussians(g)) != GS_OK) return r;
-    if ((r = check_cams(h->c, cams, true)) != GS_OK) return r;
+    if ((r = check_raster_bwd(h, cams, s, T_final, last, v_rgb)) != GS_OK) return r;
+    if ((r = check_project_bwd(h, g, cams, s, grads, v_twist)) != GS_OK) return r;
     if ((r = gs_raster_bwd(h, cams, s, bg, T_final, last, v_rgb, stream)) != GS_OK) return r;
     return gs_project_bwd(h, g, cams, s, grads, v_twist, stream);
 }
@@ -444,9 +465,10 @@ gs_status gs_pose_compose_bwd(int32_t V, const float* twist, const float* g, flo
     return from_hip(gs::launch_pose_compose_bwd(V, twist, g, out, (hipStream_t)stream));
 }
 
-gs_status gs_adam_step(const gs_adam_group* groups, int32_t n_groups, int32_t step, float beta1,
-                       float beta2, float eps, void* stream) {
-    if (!groups || n_groups <= 0 || n_groups > GS_ADAM_MAX_GROUPS || step <= 0) return GS_ERR_INVALID_ARG;
+gs_status gs_adam_step(const gs_adam_group* groups, int32_t n_groups, int32_t step,
+                       const int32_t* step_dev, float beta1, float beta2, float eps, void* stream) {
+    if (!groups || n_groups <= 0 || n_groups > GS_ADAM_MAX_GROUPS || (!step_dev && step <= 0))
+        return GS_ERR_INVALID_ARG;
     if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f))
         return GS_ERR_INVALID_ARG;
     for (int q = 0; q < n_groups; q++) {
@@ -454,7 +476,13 @@ gs_status gs_adam_step(const gs_adam_group* groups, int32_t n_groups, int32_t st
         if (g.n < 0) return GS_ERR_INVALID_ARG;
         if (g.n > 0 && (!g.param || !g.grad || !g.exp_avg || !g.exp_avg_sq)) return GS_ERR_INVALID_ARG;
     }
-    return from_hip(gs::launch_adam(groups, n_groups, step, beta1, beta2, eps, (hipStream_t)stream));
+    return from_hip(gs::launch_adam(groups, n_groups, step, step_dev, beta1, beta2, eps,
+                                    (hipStream_t)stream));
+}
+
+gs_status gs_step_advance(int32_t* step_dev, void* stream) {
+    if (!step_dev) return GS_ERR_INVALID_ARG;
+    return from_hip(gs::launch_step_advance(step_dev, (hipStream_t)stream));
 }
 
 }  // extern "C"

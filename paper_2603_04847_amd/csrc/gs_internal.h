@@ -238,6 +238,27 @@ __device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, 
     p -= lr * (m * ibc1) / (sqrtf(v * ibc2) + eps);
 }
 
+// The bias corrections 1 / (1 - b^t) of Adam step t, read from the device
+// counter when there is one (a captured step then takes the step number the
+// counter holds at replay), else from the value passed; t < 1 counts as 1.
+// b^t by repeated squaring in double, then rounded once.
+__device__ __forceinline__ void adam_bias(const int32_t* step_dev, int step, float b1, float b2,
+                                          float& ibc1, float& ibc2) {
+    int t = step_dev ? *step_dev : step;
+    t = t < 1 ? 1 : t;
+    double p1 = 1.0, p2 = 1.0, q1 = b1, q2 = b2;
+    for (int e = t; e > 0; e >>= 1) {
+        if (e & 1) {
+            p1 *= q1;
+            p2 *= q2;
+        }
+        q1 *= q1;
+        q2 *= q2;
+    }
+    ibc1 = (float)(1.0 / (1.0 - p1));
+    ibc2 = (float)(1.0 / (1.0 - p2));
+}
+
 // Adam state of the five Gaussian arrays (means, log_scales, quats,
 // opacity_logit, sh) for the projection backward that also steps them.
 struct AdamGauss {
@@ -245,7 +266,10 @@ struct AdamGauss {
     float* m[5];
     float* v[5];
     float lr[5];
-    float b1, b2, eps, ibc1, ibc2;
+    float b1, b2, eps;
+    float ibc1, ibc2;          // set in the kernel from the step
+    const int32_t* step_dev;   // device step counter, or NULL: `step`
+    int step;
 };
 
 // A tile-list entry carries the pair index in its low 28 bits and the
@@ -451,8 +475,9 @@ hipError_t launch_pose_compose(int V, const float* twist, const float* base, flo
                                hipStream_t st);
 hipError_t launch_pose_compose_bwd(int V, const float* twist, const float* g, float* out,
                                    hipStream_t st);
-hipError_t launch_adam(const gs_adam_group* groups, int n, int step, float b1, float b2,
-                       float eps, hipStream_t st);
+hipError_t launch_adam(const gs_adam_group* groups, int n, int step, const int32_t* step_dev,
+                       float b1, float b2, float eps, hipStream_t st);
+hipError_t launch_step_advance(int32_t* step_dev, hipStream_t st);
 hipError_t launch_flush_acc(double* acc, float* out, int n, hipStream_t st);
 // out[6 * rows[v] + e] += acc[6 * v + e]; acc cleared (twists of a sampled batch)
 hipError_t launch_flush_twist_rows(double* acc, float* out, const ViewTable& vt, hipStream_t st);
@@ -499,6 +524,7 @@ struct Ctx {
     int64_t n_tiles, n_blocks;
     int bin_V, bin_N, bin_tw, bin_th;
     bool ordered;          // tile_order holds the order of the last bin step
+    int64_t generation;    // gs_bin_sort calls enqueued so far
 };
 
 }  // namespace gs

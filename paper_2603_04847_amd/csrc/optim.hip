@@ -105,8 +105,10 @@ constexpr int kAdamPerBlock = 256 * 4;
 
 // Each block updates 1024 consecutive elements of one group (float4 loads
 // when the group is 16-byte aligned).
-__global__ __launch_bounds__(256) void k_adam(AdamArgs a, float b1, float b2, float eps, float ibc1,
-                                              float ibc2) {
+__global__ __launch_bounds__(256) void k_adam(AdamArgs a, float b1, float b2, float eps,
+                                              const int32_t* __restrict__ step_dev, int step) {
+    float ibc1, ibc2;
+    adam_bias(step_dev, step, b1, b2, ibc1, ibc2);
     int q = 0;
     while (q + 1 < a.ng && (int64_t)blockIdx.x >= a.blk[q + 1]) q++;
     const int64_t i0 = ((int64_t)blockIdx.x - a.blk[q]) * kAdamPerBlock;
@@ -129,6 +131,10 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a, float b1, float b2, fl
         for (int64_t j = i0 + threadIdx.x; j < min(n, i0 + kAdamPerBlock); j += 256)
             adam_one(a.p[q][j], a.g[q][j], a.m[q][j], a.v[q][j], lr, b1, b2, eps, ibc1, ibc2);
     }
+}
+
+__global__ void k_step_advance(int32_t* __restrict__ step_dev) {
+    if (threadIdx.x == 0) *step_dev += 1;
 }
 
 __global__ void k_flush_acc(double* __restrict__ acc, float* __restrict__ out, int n) {
@@ -170,8 +176,8 @@ hipError_t launch_pose_compose_bwd(int V, const float* twist, const float* g, fl
     return hipGetLastError();
 }
 
-hipError_t launch_adam(const gs_adam_group* groups, int n, int step, float b1, float b2,
-                       float eps, hipStream_t st) {
+hipError_t launch_adam(const gs_adam_group* groups, int n, int step, const int32_t* step_dev,
+                       float b1, float b2, float eps, hipStream_t st) {
     AdamArgs a{};
     a.ng = n;
     a.blk[0] = 0;
@@ -189,9 +195,12 @@ hipError_t launch_adam(const gs_adam_group* groups, int n, int step, float b1, f
     const int64_t blocks = a.blk[n];
     if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
-    const float ibc1 = (float)(1.0 / (1.0 - pow((double)b1, step)));
-    const float ibc2 = (float)(1.0 / (1.0 - pow((double)b2, step)));
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(256), 0, st, a, b1, b2, eps, ibc1, ibc2);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(256), 0, st, a, b1, b2, eps, step_dev, step);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_advance(int32_t* step_dev, hipStream_t st) {
+    hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(64), 0, st, step_dev);
     return hipGetLastError();
 }
 

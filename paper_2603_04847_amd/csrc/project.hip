@@ -261,14 +261,25 @@ __global__ __launch_bounds__(kBlock) void k_project_fwd(gs_gaussians g, const fl
     for (int k = 0; k < K; k++)
 #pragma unroll
         for (int ch = 0; ch < 3; ch++) sh[k][ch] = g.sh[((int64_t)k * 3 + ch) * g.N + i];
-    bool nonfinite = false;
+    // a Gaussian with any non-finite parameter is culled in every view (and
+    // flagged): it contributes nothing, so it receives no gradient
+    bool bad = !isfinite(g.opacity_logit[i]);
+#pragma unroll
+    for (int k = 0; k < 3; k++) bad |= !isfinite(G.mu[k]) || !isfinite(g.log_scales[k * g.N + i]);
+#pragma unroll
+    for (int k = 0; k < 4; k++) bad |= !isfinite(G.q[k]);
+#pragma unroll
+    for (int k = 0; k < K; k++)
+#pragma unroll
+        for (int ch = 0; ch < 3; ch++) bad |= !isfinite(sh[k][ch]);
+    bool nonfinite = bad;
     for (int v = 0; v < vt.V; v++) {
         const Cam cam = load_cam(viewmat, intr, vt.cam[v]);
         Proj P;
-        project_one(G, cam, vt.W[v], vt.H[v], rp, P);
+        if (!bad) project_one(G, cam, vt.W[v], vt.H[v], rp, P);
         const int64_t pair = (int64_t)v * g.N + i;
         float4* r = rec + 3 * pair;
-        if (!P.valid || !(G.o > rp.alpha_min)) {
+        if (bad || !P.valid || !(G.o > rp.alpha_min)) {
             r[0] = make_float4(0.f, 0.f, 0.f, 0.f);
             continue;
         }
@@ -365,6 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_color(gs_gaussians g, co
                                  AdamGauss adam, float* __restrict__ vmu_dir,
                                  double* __restrict__ twist_acc) {
     constexpr int K = (DEG + 1) * (DEG + 1);
+    if (ADAM) adam_bias(adam.step_dev, adam.step, adam.b1, adam.b2, adam.ibc1, adam.ibc2);
     __shared__ float s_tw[kBlock / kWave][6];
     __shared__ double s_acc[6 * GS_MAX_VIEWS];  // this block's twist sums, all iterations
     for (int k = threadIdx.x; k < 6 * vt.V; k += kBlock) s_acc[k] = 0.0;
@@ -489,6 +501,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_geom(gs_gaussians g, con
                                  float* __restrict__ grad2d, gs_gaussians_grad out, int accumulate,
                                  AdamGauss adam, float* __restrict__ vmu_dir,
                                  double* __restrict__ twist_acc) {
+    if (ADAM) adam_bias(adam.step_dev, adam.step, adam.b1, adam.b2, adam.ibc1, adam.ibc2);
     __shared__ float s_tw[kBlock / kWave][6];
     __shared__ double s_acc[6 * GS_MAX_VIEWS];  // this block's twist sums, all iterations
     for (int k = threadIdx.x; k < 6 * vt.V; k += kBlock) s_acc[k] = 0.0;

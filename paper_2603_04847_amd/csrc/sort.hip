@@ -85,7 +85,10 @@ __device__ uint32_t wave_lookback(const uint64_t* words, int64_t t, uint32_t* fl
         const uint64_t need = first >= kWave - 1 ? ~0ull : ((2ull << first) - 1ull);
         if (none & need) {
             if (++polls > kSpinLimit) {
-                if (lane == 0 && flags) atomicOr(flags, (uint32_t)GS_FLAG_SCAN_STALLED);
+                if (lane == 0 && flags) {
+                    atomicOr(flags, (uint32_t)GS_FLAG_SCAN_STALLED);
+                    __atomic_thread_fence(__ATOMIC_RELEASE);
+                }
                 return excl;
             }
             __builtin_amdgcn_s_sleep(2);
@@ -98,10 +101,16 @@ __device__ uint32_t wave_lookback(const uint64_t* words, int64_t t, uint32_t* fl
     return excl;
 }
 
-__device__ __forceinline__ void cap_check(uint32_t t, const CapCheck& c) {
+// A scan whose look-back gave up (GS_FLAG_SCAN_STALLED) has offsets that are
+// not to be trusted: the check then treats the list as overflowed, so every
+// later stage writes nothing.
+__device__ __forceinline__ void cap_check(uint32_t t, const CapCheck& c, const uint32_t* flags) {
     if (!c.used) return;
+    const bool stalled =
+        flags && (__hip_atomic_load(flags, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) &
+                  (uint32_t)GS_FLAG_SCAN_STALLED) != 0u;
     const bool prev_over = c.prev_total && *c.prev_total != 0u && *c.prev_used == 0u;
-    const bool over = prev_over || (int64_t)t > c.cap;
+    const bool over = prev_over || stalled || (int64_t)t > c.cap;
     *c.used = over ? 0u : t;
     if (prev_over) return;
     c.diag[kDiagIsectTotal] = t;
@@ -134,7 +143,7 @@ __global__ __launch_bounds__(kThreads) void k_scan(uint32_t* __restrict__ data, 
     if (t >= ntiles) {
         if (t == 0 && threadIdx.x == 0) {
             if (total_out) *total_out = 0u;
-            cap_check(0u, chk);
+            cap_check(0u, chk, flags);
         }
     } else {
         const int64_t base = t * kScanTile + (int64_t)threadIdx.x * kScanItems;
@@ -167,7 +176,7 @@ __global__ __launch_bounds__(kThreads) void k_scan(uint32_t* __restrict__ data, 
                 s_excl = excl;
                 if (t == ntiles - 1) {
                     if (total_out) *total_out = excl + tot;
-                    cap_check(excl + tot, chk);
+                    cap_check(excl + tot, chk, flags);
                 }
             }
         }
@@ -358,9 +367,11 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
             const uint32_t key = s_key[j];
             const uint32_t d = (key >> shift) & mask;
             const uint32_t g = s_glob[d] + (j - s_start[d]);
-            kout[g] = key;
+            if (g < n) {  // always, unless a digit scan gave up (flagged)
+                kout[g] = key;
 #pragma unroll
-            for (int c = 0; c < NV; c++) va.out[c][g] = s_val[c][j];
+                for (int c = 0; c < NV; c++) va.out[c][g] = s_val[c][j];
+            }
         }
     }
 }

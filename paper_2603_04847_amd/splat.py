@@ -52,6 +52,13 @@ class Splatter:
         L.gs_render_fwd(self.ctx, cams, self.settings, self.bg, rgb, T, last, stream)
         return rgb, T, last, cams
 
+    def rebin(self, params, sh_degree, cams, stream=None):
+        """Project and bin again (the records and lists a later forward on the
+        same context replaced); deterministic, so they equal the forward's."""
+        g = L.make_gaussians(*(params[k] for k in PARAM_KEYS), sh_degree)
+        L.gs_project(self.ctx, g, cams, self.settings, stream)
+        L.gs_bin_sort(self.ctx, cams, g.N, self.settings, None, stream)
+
     def backward(self, params, sh_degree, cams, T, last, v_rgb, v_twist=None, grads=None,
                  stream=None):
         """Gradients of the last forward.  Returns (grads dict, v_twist [V,6]);
@@ -82,17 +89,22 @@ class RasterizeGaussians(torch.autograd.Function):
         actx.splatter = splatter
         actx.sh_degree = sh_degree
         actx.cams = cams
-        actx.params = params
         actx.keep = (viewmat, _dev(intr))
-        actx.save_for_backward(tw, T, last)
+        # the lists this forward built; a later forward on the context replaces them
+        actx.generation = splatter.ctx.generation()
+        actx.save_for_backward(tw, T, last, *(params[k] for k in PARAM_KEYS))
         actx.mark_non_differentiable(T, last)
         return rgb, T, last
 
     @staticmethod
     def backward(actx, v_rgb, _vT, _vlast):
-        tw, T, last = actx.saved_tensors
-        grads, v_tw_cur = actx.splatter.backward(actx.params, actx.sh_degree, actx.cams, T, last,
+        tw, T, last, *pv = actx.saved_tensors
+        params = dict(zip(PARAM_KEYS, pv))
+        if actx.splatter.ctx.generation() != actx.generation:
+            actx.splatter.rebin(params, actx.sh_degree, actx.cams)
+        grads, v_tw_cur = actx.splatter.backward(params, actx.sh_degree, actx.cams, T, last,
                                                  v_rgb.contiguous())
+        actx.generation = actx.splatter.ctx.generation()
         v_tw = torch.empty_like(tw)
         L.gs_pose_compose_bwd(tw, v_tw_cur, v_tw)
         return (grads["means"], grads["log_scales"], grads["quats"], grads["opacity_logit"],

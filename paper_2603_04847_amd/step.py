@@ -101,6 +101,10 @@ class JointStep:
         self.m = {k: torch.zeros_like(v) for k, v in self._opt_params().items()}
         self.v = {k: torch.zeros_like(v) for k, v in self._opt_params().items()}
         self.step_count = 0
+        # the Adam step number on the device: `run` advances it in a kernel and
+        # the Adam kernels read it, so a captured step replays as successive
+        # steps (1 / (1 - beta^t) changes every replay)
+        self.d_step = torch.zeros(1, device=device, dtype=torch.int32)
         self.cams = [L.Cameras(self.viewmat, self.intr, self.wh_all[b], index=b) for b in self.batches]
         self.g = L.make_gaussians(*(self.params[k] for k in PARAM_KEYS), self.sh_degree)
         self.gg = L.make_grads(*(self.grads[k] for k in PARAM_KEYS))
@@ -122,10 +126,11 @@ class JointStep:
         d["X"] = self.v_X
         return d
 
-    def forward_backward(self, b, timer=None, adam_step=None):
+    def forward_backward(self, b, timer=None, adam_step=None, step_dev=None):
         """a1-a9 and the twist chain, for batch b.  `timer(name)` brackets calls.
-        With `adam_step` (the Adam step number t), the projection backward also
-        takes the Gaussians' Adam step and self.grads is left untouched."""
+        With `adam_step` (the Adam step number t, or 0 with `step_dev` the
+        device counter holding it), the projection backward also takes the
+        Gaussians' Adam step and self.grads is left untouched."""
         t = timer or (lambda name: _Null())
         cams = self.cams[b]
         P = cams.n_pixels
@@ -143,7 +148,7 @@ class JointStep:
             L.gs_l1_loss_grad(self.ctx, cams, self.rgb, self.targets[b], self.v_rgb, self.loss[0:1])
         with t("raster_bwd"):
             L.gs_raster_bwd(self.ctx, cams, s, None, self.T, self.last, self.v_rgb)
-        if adam_step is None:
+        if adam_step is None and step_dev is None:
             with t("project_bwd"):
                 L.gs_project_bwd(self.ctx, self.g, cams, s, self.gg, self.v_tw_cur)
         else:
@@ -152,7 +157,8 @@ class JointStep:
                                       [self.params[k] for k in PARAM_KEYS],
                                       [self.m[k] for k in PARAM_KEYS],
                                       [self.v[k] for k in PARAM_KEYS],
-                                      [self.lr[k] for k in PARAM_KEYS], adam_step, self.v_tw_cur)
+                                      [self.lr[k] for k in PARAM_KEYS], adam_step, self.v_tw_cur,
+                                      step_dev=step_dev)
         with t("track"):
             L.track_reproj_fwd_bwd(self.ctx, self.X, self.viewmat, self.intr, self.obs_cam,
                                    self.obs_pt, self.obs_xy, self.delta, self.lam, 0.01,
@@ -161,27 +167,37 @@ class JointStep:
             L.gs_pose_compose_bwd(self.twist, self.v_tw_cur, self.v_tw)
         del P
 
-    def _next_step(self, step):
-        if step is None:
+    def set_step(self, n):
+        """Set the device step counter (the next `run` takes step n + 1)."""
+        self.d_step.fill_(int(n))
+        self.step_count = int(n)
+
+    def adam(self, timer=None, step=None, keys=None, step_dev=None):
+        """Adam on the groups `keys` (default: all) from their gradients, at
+        step `step`, or at the step the device counter `step_dev` holds."""
+        t = timer or (lambda name: _Null())
+        if step is None and step_dev is None:
             self.step_count += 1
             step = self.step_count
-        return step
-
-    def adam(self, timer=None, step=None, keys=None):
-        """Adam on the groups `keys` (default: all) from their gradients."""
-        t = timer or (lambda name: _Null())
-        step = self._next_step(step)
         p, g = self._opt_params(), self._opt_grads()
         groups = [(p[k], g[k], self.m[k], self.v[k], self.lr[k]) for k in (keys or p)]
         with t("adam"):
-            L.gs_adam_step(groups, step)
+            L.gs_adam_step(groups, step or 0, step_dev=step_dev)
 
     def run(self, b, timer=None, step=None):
         """One iteration: forward, backward with the Gaussians' Adam step fused
-        into the projection backward, then Adam on the twists and track points."""
-        step = self._next_step(step)
-        self.forward_backward(b, timer, adam_step=step)
-        self.adam(timer, step, keys=("twist", "X"))
+        into the projection backward, then Adam on the twists and track points.
+        Without `step` the device counter is advanced first and every Adam
+        kernel reads it (the form a captured graph replays); with `step` that
+        step number is used and the counter is left alone."""
+        if step is None:
+            L.gs_step_advance(self.d_step)
+            self.step_count += 1
+            self.forward_backward(b, timer, adam_step=0, step_dev=self.d_step)
+            self.adam(timer, keys=("twist", "X"), step_dev=self.d_step)
+        else:
+            self.forward_backward(b, timer, adam_step=step)
+            self.adam(timer, step, keys=("twist", "X"))
 
 
 class _Null:

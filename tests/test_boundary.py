@@ -62,7 +62,8 @@ def test_host_validation_without_device_work():
     huge = L.gs_capacity(1 << 40, 10, 10, 1, 1)
     assert lib.gs_ctx_create(ctypes.byref(h), ctypes.byref(huge)) == -2
     assert lib.gs_project(None, None, None, None, None) == -1
-    assert lib.gs_adam_step(None, 0, 1, 0.9, 0.999, 1e-15, None) == -1
+    assert lib.gs_adam_step(None, 0, 1, None, 0.9, 0.999, 1e-15, None) == -1
+    assert lib.gs_step_advance(None, None) == -1
     assert lib.gs_pose_compose(-1, None, None, None, None) == -1
 
 

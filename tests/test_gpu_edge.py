@@ -116,3 +116,80 @@ def test_track_without_observations(gs):
         assert loss.item() == 0.0
         assert not torch.any(v_X != 0).item() and not torch.any(v_tw != 0).item()
         assert ctx.status()["n_masked_obs"] == 0
+
+
+def test_nonfinite_parameters_are_culled_and_flagged(gs):
+    """Gaussians with a NaN or infinite parameter (a mean, a log-scale, a
+    quaternion, an opacity logit, an SH coefficient) raise GS_FLAG_NONFINITE
+    and drop out: the image and every other gradient equal the oracle's for
+    the scene without them, and their own gradients are exactly zero."""
+    from paper_2603_04847_amd.splat import Splatter
+    s = _scene(600, seed=41)
+    s1 = dict(s, viewmat=s["viewmat"][:1], intr=s["intr"][:1], wh=s["wh"][:1])
+    bad = np.array([3, 50, 77, 140, 201, 333, 420, 599])
+    s1 = {k: (np.array(v, copy=True) if isinstance(v, np.ndarray) else v) for k, v in s1.items()}
+    s1["means"][0, bad[0]] = np.nan
+    s1["means"][2, bad[1]] = np.inf
+    s1["log_scales"][1, bad[2]] = np.inf
+    s1["log_scales"][0, bad[3]] = -np.inf
+    s1["quats"][2, bad[4]] = np.nan
+    s1["opacity_logit"][bad[5]] = np.nan
+    s1["sh"][0, 1, bad[6]] = np.inf
+    s1["sh"][9, 2, bad[7]] = np.nan
+    keep = np.setdiff1d(np.arange(600), bad)
+    good = dict(s1)
+    for k in ("means", "log_scales", "quats", "sh"):
+        good[k] = s1[k][..., keep]
+    good["opacity_logit"] = s1["opacity_logit"][keep]
+    N = 600
+    ctx = gs.Context(max_pairs=N, max_isect=1 << 18, max_tiles=4096, max_views=1)
+    sp = Splatter(ctx)
+    params = {k: _t(s1[k]) for k in ("means", "log_scales", "quats", "opacity_logit", "sh")}
+    rgb, T, last, cams = sp.forward(params, 3, _t(s1["viewmat"]), _t(s1["intr"]), s1["wh"])
+    torch.cuda.synchronize()
+    assert ctx.status()["flags"] & gs._lib.GS_FLAG_NONFINITE
+    o = oracle.render_fwd_bwd(good)
+    ok = ~o["ambiguous"]
+    g = rgb.cpu().numpy()
+    assert np.all(np.isfinite(g))
+    assert np.max(np.abs(g[ok] - o["rgb"][ok])) <= 1e-4
+    w = np.random.default_rng(2).normal(size=(cams.n_pixels, 3))
+    w[o["ambiguous"]] = 0.0
+    grads, v_tw = sp.backward(params, 3, cams, T, last, _t(w))
+    og = oracle.render_fwd_bwd(good, v_rgb=w)["grads"]
+    for k in ("means", "log_scales", "quats", "opacity_logit", "sh"):
+        a = grads[k].cpu().numpy()
+        assert not np.any(a[..., bad]), k
+        err = np.max(np.abs(a[..., keep] - og[k]))
+        assert err <= 1e-4 * np.max(np.abs(og[k])), (k, err)
+    tw = v_tw.cpu().numpy()[0]
+    assert np.max(np.abs(tw - og["twist"][0])) <= 1e-4 * np.max(np.abs(og["twist"][0]))
+
+
+def test_render_bwd_checks_everything_before_enqueueing(gs):
+    """A backward rejected by an argument check (a missing gradient array)
+    enqueues nothing: the next, valid backward finds no stale 2D gradients."""
+    from paper_2603_04847_amd.splat import Splatter
+    import paper_2603_04847_amd._lib as L
+    s = _scene(500, seed=43)
+    s1 = dict(s, viewmat=s["viewmat"][:1], intr=s["intr"][:1], wh=s["wh"][:1])
+    ctx = gs.Context(max_pairs=500, max_isect=1 << 18, max_tiles=4096, max_views=1)
+    sp = Splatter(ctx)
+    params = {k: _t(s1[k]) for k in ("means", "log_scales", "quats", "opacity_logit", "sh")}
+    rgb, T, last, cams = sp.forward(params, 3, _t(s1["viewmat"]), _t(s1["intr"]), s1["wh"])
+    v_rgb = _t(np.random.default_rng(4).normal(size=(cams.n_pixels, 3)))
+    ref, ref_tw = sp.backward(params, 3, cams, T, last, v_rgb)
+    ref = {k: v.clone() for k, v in ref.items()}
+    g = L.make_gaussians(*(params[k] for k in ("means", "log_scales", "quats", "opacity_logit", "sh")), 3)
+    gr = {k: torch.empty_like(v) for k, v in params.items()}
+    bad = L.make_grads(gr["means"], gr["log_scales"], None, gr["opacity_logit"], gr["sh"])
+    v_tw = torch.zeros((1, 6), device="cuda")
+    with pytest.raises(gs.GsError) as e:
+        L.gs_render_bwd(ctx, g, cams, sp.settings, None, T, last, v_rgb, bad, v_tw)
+    assert e.value.code == -1
+    again, tw2 = sp.backward(params, 3, cams, T, last, v_rgb)
+    torch.cuda.synchronize()
+    for k in ref:
+        a, b = again[k].cpu().numpy(), ref[k].cpu().numpy()
+        assert np.max(np.abs(a - b)) <= 1e-5 * (np.max(np.abs(b)) + 1e-30), k
+    assert not torch.any(v_tw != 0).item()
