@@ -291,6 +291,19 @@ gs_status gs_project_bwd(gs_ctx* ctx, const gs_gaussians* g, const gs_cameras* c
 gs_status gs_l1_loss_grad(gs_ctx* ctx, const gs_cameras* cams, const float* rgb,
                           const float* target, float* v_rgb, float* loss, void* stream);
 
+/* The whole photometric loss (Sec. 3.3 eq. L_photo; Algorithm 1, photometric
+ * loss): loss += (1 - lambda_ssim) L1 + lambda_ssim (1 - SSIM), lambda_ssim =
+ * 0.2 in the paper, each term the mean over views of the mean over the view's
+ * pixels and channels; v_rgb[P][3] = its gradient, overwritten.  SSIM per
+ * channel with an 11 x 11 Gaussian window of standard deviation 1.5 (the outer
+ * product of the normalised 1D window), c1 = 0.01^2, c2 = 0.03^2 (data range
+ * 1), and zeros beyond each view's border; the L1 gradient is sign(d) with
+ * sign(0) = 0.  lambda_ssim in [0, 1] (0 gives gs_l1_loss_grad's result).
+ * loss[1] is a device float, accumulated. */
+gs_status gs_photo_loss_grad(gs_ctx* ctx, const gs_cameras* cams, const float* rgb,
+                             const float* target, float lambda_ssim, float* v_rgb, float* loss,
+                             void* stream);
+
 /* Track reprojection (Sec. 3.3 eq. L_BA^joint; Algorithm 1, joint BA loss):
  * for each observation o = (camera obs_cam[o], point obs_pt[o], pixel
  * obs_xy[o][2]):  p = R X + t; masked (no loss, no gradient, counted) if

@@ -82,7 +82,7 @@ EXPORTS = [
     "gs_ctx_reset_status", "gs_ctx_buffers", "gs_ctx_tile_stats", "gs_project", "gs_bin_sort", "gs_render_fwd",
     "gs_render_bwd", "gs_raster_bwd", "gs_project_bwd", "gs_l1_loss_grad", "track_reproj_fwd_bwd", "gs_pose_compose",
     "gs_pose_compose_bwd", "gs_adam_step", "gs_project_bwd_adam", "track_point_index",
-    "gs_step_advance", "gs_ctx_generation",
+    "gs_step_advance", "gs_ctx_generation", "gs_photo_loss_grad",
 ]
 
 _lib = None
@@ -137,6 +137,8 @@ def load():
         c_vp, c_vp, ctypes.c_int32, c_vp, c_vp, ctypes.c_int32, c_vp, c_vp, c_vp, ctypes.c_int32,
         ctypes.c_float, ctypes.c_float, ctypes.c_float, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
         c_vp, c_vp]
+    lib.gs_photo_loss_grad.argtypes = [c_vp, ctypes.POINTER(gs_cameras), c_vp, c_vp, ctypes.c_float,
+                                       c_vp, c_vp, c_vp]
     lib.track_point_index.argtypes = [c_vp, c_vp, ctypes.c_int32, ctypes.c_int32, c_vp, c_vp, c_vp]
     lib.gs_pose_compose.argtypes = [ctypes.c_int32, c_vp, c_vp, c_vp, c_vp]
     lib.gs_pose_compose_bwd.argtypes = [ctypes.c_int32, c_vp, c_vp, c_vp, c_vp]
@@ -357,6 +359,12 @@ def gs_l1_loss_grad(ctx, cams, rgb, target, v_rgb, loss, stream=None):
     _check("gs_l1_loss_grad", load().gs_l1_loss_grad(ctx.handle, ctypes.byref(cams.struct),
                                                      _ptr(rgb), _ptr(target), _ptr(v_rgb),
                                                      _ptr(loss), _stream(stream)))
+
+
+def gs_photo_loss_grad(ctx, cams, rgb, target, lambda_ssim, v_rgb, loss, stream=None):
+    _check("gs_photo_loss_grad", load().gs_photo_loss_grad(
+        ctx.handle, ctypes.byref(cams.struct), _ptr(rgb), _ptr(target), float(lambda_ssim),
+        _ptr(v_rgb), _ptr(loss), _stream(stream)))
 
 
 def track_reproj_fwd_bwd(ctx, X, viewmat, intr, obs_cam, obs_pt, obs_xy, delta, lam, near_plane,

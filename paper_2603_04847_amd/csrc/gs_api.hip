@@ -427,6 +427,16 @@ gs_status gs_l1_loss_grad(gs_ctx* h, const gs_cameras* cams, const float* rgb, c
     return from_hip(gs::launch_l1(&h->c, vt, rgb, target, v_rgb, loss, (hipStream_t)stream));
 }
 
+gs_status gs_photo_loss_grad(gs_ctx* h, const gs_cameras* cams, const float* rgb, const float* target,
+                             float lambda_ssim, float* v_rgb, float* loss, void* stream) {
+    if (!h || !rgb || !target || !v_rgb || !loss) return GS_ERR_INVALID_ARG;
+    if (!(lambda_ssim >= 0.f && lambda_ssim <= 1.f)) return GS_ERR_INVALID_ARG;
+    gs_status r;
+    if ((r = check_cams(h->c, cams, false)) != GS_OK) return r;
+    const gs::ViewTable vt = gs::make_view_table(cams->wh, cams->V, 16, 16, cams->index);
+    return from_hip(gs::launch_photo(&h->c, vt, rgb, target, lambda_ssim, v_rgb, loss, (hipStream_t)stream));
+}
+
 gs_status track_reproj_fwd_bwd(gs_ctx* h, const float* X, int32_t Pt, const float* viewmat,
                                const float* intr, int32_t n_cams, const int32_t* obs_cam,
                                const int32_t* obs_pt, const float* obs_xy, int32_t M, float delta,

@@ -458,6 +458,10 @@ hipError_t launch_render_bwd(Ctx* c, const ViewTable& vt, const RasterParams& rp
 hipError_t launch_l1(Ctx* c, const ViewTable& vt, const float* rgb, const float* target,
                      float* v_rgb, float* loss, hipStream_t st);
 
+// photo.hip: (1 - lambda) L1 + lambda (1 - SSIM) and its image gradient
+hipError_t launch_photo(Ctx* c, const ViewTable& vt, const float* rgb, const float* target,
+                        float lambda, float* v_rgb, float* loss, hipStream_t st);
+
 // track.hip
 hipError_t launch_track(Ctx* c, const float* X, int Pt, const float* viewmat, const float* intr,
                         int n_cams, const int32_t* obs_cam, const int32_t* obs_pt,

@@ -5,7 +5,9 @@ the C ABI, without Python-side arithmetic:
   a2  project the Gaussians into the sampled views          gs_project
   a3+a4 bin and key-sort the tile intersections             gs_bin_sort
   a5  front-to-back composite                               gs_render_fwd
-  a6  L1 loss and its image gradient                        gs_l1_loss_grad
+  a6  photometric loss (1 - l) L1 + l (1 - SSIM), l = 0.2,  gs_photo_loss_grad
+      and its image gradient (l = 0: L1 alone,               (gs_l1_loss_grad)
+      gs_l1_loss_grad)
   a7  raster backward (2D gradients)                        gs_raster_bwd
   a8  chain to Gaussian parameters + per-view twists        gs_project_bwd
   a9  track reprojection Huber loss, grads to X and twists  track_reproj_fwd_bwd
@@ -40,7 +42,7 @@ class JointStep:
     can be captured in a HIP graph."""
 
     def __init__(self, scene, batches, targets, device="cuda", settings=None, max_isect=None,
-                 lam=1e-4, delta=1.0, extent=None):
+                 lam=1e-4, delta=1.0, extent=None, lambda_ssim=0.2):
         f = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device, torch.float32)
         self.sh_degree = int(scene["sh_degree"])
         self.params = {k: f(scene[k]) for k in PARAM_KEYS}
@@ -59,6 +61,7 @@ class JointStep:
         self.targets = [f(t) for t in targets]
         self.settings = settings if settings is not None else L.default_settings()
         self.lam, self.delta = lam, delta
+        self.lambda_ssim = float(lambda_ssim)
         if extent is None:
             c = np.stack([-(np.asarray(scene["viewmat"][i]).reshape(3, 4)[:, :3].T
                             @ np.asarray(scene["viewmat"][i]).reshape(3, 4)[:, 3])
@@ -144,8 +147,14 @@ class JointStep:
         with t("render_fwd"):
             L.gs_render_fwd(self.ctx, cams, s, None, self.rgb, self.T, self.last)
         self._acc.zero_()  # v_X, v_tw_cur, loss
-        with t("l1"):
-            L.gs_l1_loss_grad(self.ctx, cams, self.rgb, self.targets[b], self.v_rgb, self.loss[0:1])
+        if self.lambda_ssim > 0:
+            with t("photo"):
+                L.gs_photo_loss_grad(self.ctx, cams, self.rgb, self.targets[b], self.lambda_ssim,
+                                     self.v_rgb, self.loss[0:1])
+        else:
+            with t("l1"):
+                L.gs_l1_loss_grad(self.ctx, cams, self.rgb, self.targets[b], self.v_rgb,
+                                  self.loss[0:1])
         with t("raster_bwd"):
             L.gs_raster_bwd(self.ctx, cams, s, None, self.T, self.last, self.v_rgb)
         if adam_step is None and step_dev is None:
