@@ -328,6 +328,29 @@ gs_status track_reproj_fwd_bwd(gs_ctx* ctx, const float* X, int32_t Pt,
                                float* v_twist, float* J_pose, float* J_X,
                                const int32_t* pt_off, const int32_t* pt_obs, void* stream);
 
+/* track_reproj_fwd_bwd without a context, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, results and errors as
+ * track_reproj_fwd_bwd minus the context; it allocates nothing and
+ * synchronises nothing.  Its accumulators (per-camera twist sums and the loss
+ * in double, status words) live in one fixed array of device memory inside
+ * the library, 6 x GS_NOALLOC_MAX_CAMS doubles plus a few words (about 197
+ * KB), one copy per GPU, held until the process ends; each call clears the
+ * part it uses first.  n_cams > GS_NOALLOC_MAX_CAMS returns GS_ERR_CAPACITY;
+ * a device index >= GS_NOALLOC_MAX_DEVICES returns GS_ERR_HIP.  The count of
+ * masked observations is not reported (track_reproj_fwd_bwd reports it).
+ * Calls that overlap on one GPU (on different streams, or from different
+ * threads without ordering) share that array and race: order them. */
+#define GS_NOALLOC_MAX_CAMS 4096
+#define GS_NOALLOC_MAX_DEVICES 64
+gs_status track_reproj_fwd_bwd_noalloc(const float* X, int32_t Pt, const float* viewmat,
+                                       const float* intr, int32_t n_cams, const int32_t* obs_cam,
+                                       const int32_t* obs_pt, const float* obs_xy, int32_t M,
+                                       float delta, float lambda, float near_plane,
+                                       float* residual, float* loss, float* v_X, float* v_twist,
+                                       float* J_pose, float* J_X, const int32_t* pt_off,
+                                       const int32_t* pt_obs, void* stream);
+
 /* The point-major index of track observations that track_reproj_fwd_bwd can
  * take (it depends on obs_pt only, so a scene builds it once):
  * pt_off[Pt + 1] (device, 16-byte aligned): point k's observations are

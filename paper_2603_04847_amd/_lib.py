@@ -82,7 +82,7 @@ EXPORTS = [
     "gs_ctx_reset_status", "gs_ctx_buffers", "gs_ctx_tile_stats", "gs_project", "gs_bin_sort", "gs_render_fwd",
     "gs_render_bwd", "gs_raster_bwd", "gs_project_bwd", "gs_l1_loss_grad", "track_reproj_fwd_bwd", "gs_pose_compose",
     "gs_pose_compose_bwd", "gs_adam_step", "gs_project_bwd_adam", "track_point_index",
-    "gs_step_advance", "gs_ctx_generation", "gs_photo_loss_grad",
+    "gs_step_advance", "gs_ctx_generation", "track_reproj_fwd_bwd_noalloc", "gs_photo_loss_grad",
 ]
 
 _lib = None
@@ -139,6 +139,10 @@ def load():
         c_vp, c_vp]
     lib.gs_photo_loss_grad.argtypes = [c_vp, ctypes.POINTER(gs_cameras), c_vp, c_vp, ctypes.c_float,
                                        c_vp, c_vp, c_vp]
+    lib.track_reproj_fwd_bwd_noalloc.argtypes = [
+        c_vp, ctypes.c_int32, c_vp, c_vp, ctypes.c_int32, c_vp, c_vp, c_vp, ctypes.c_int32,
+        ctypes.c_float, ctypes.c_float, ctypes.c_float, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
+        c_vp, c_vp]
     lib.track_point_index.argtypes = [c_vp, c_vp, ctypes.c_int32, ctypes.c_int32, c_vp, c_vp, c_vp]
     lib.gs_pose_compose.argtypes = [ctypes.c_int32, c_vp, c_vp, c_vp, c_vp]
     lib.gs_pose_compose_bwd.argtypes = [ctypes.c_int32, c_vp, c_vp, c_vp, c_vp]
@@ -374,6 +378,18 @@ def track_reproj_fwd_bwd(ctx, X, viewmat, intr, obs_cam, obs_pt, obs_xy, delta, 
     pt_off, pt_obs = pt_index if pt_index is not None else (None, None)
     _check("track_reproj_fwd_bwd", load().track_reproj_fwd_bwd(
         ctx.handle, _ptr(X), int(X.shape[0]), _ptr(viewmat), _ptr(intr), int(viewmat.shape[0]),
+        _ptr(obs_cam), _ptr(obs_pt), _ptr(obs_xy), int(obs_cam.shape[0]), float(delta),
+        float(lam), float(near_plane), _ptr(residual), _ptr(loss), _ptr(v_X), _ptr(v_twist),
+        _ptr(J_pose), _ptr(J_X), _ptr(pt_off), _ptr(pt_obs), _stream(stream)))
+
+
+def track_reproj_fwd_bwd_noalloc(X, viewmat, intr, obs_cam, obs_pt, obs_xy, delta, lam,
+                                 near_plane, loss, v_X, v_twist, residual=None, J_pose=None,
+                                 J_X=None, pt_index=None, stream=None):
+    """track_reproj_fwd_bwd without a context (the library allocates nothing)."""
+    pt_off, pt_obs = pt_index if pt_index is not None else (None, None)
+    _check("track_reproj_fwd_bwd_noalloc", load().track_reproj_fwd_bwd_noalloc(
+        _ptr(X), int(X.shape[0]), _ptr(viewmat), _ptr(intr), int(viewmat.shape[0]),
         _ptr(obs_cam), _ptr(obs_pt), _ptr(obs_xy), int(obs_cam.shape[0]), float(delta),
         float(lam), float(near_plane), _ptr(residual), _ptr(loss), _ptr(v_X), _ptr(v_twist),
         _ptr(J_pose), _ptr(J_X), _ptr(pt_off), _ptr(pt_obs), _stream(stream)))

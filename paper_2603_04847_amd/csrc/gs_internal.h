@@ -468,6 +468,21 @@ hipError_t launch_track(Ctx* c, const float* X, int Pt, const float* viewmat, co
                         const float* obs_xy, int M, float delta, float lambda, float near_plane,
                         float* residual, float* loss, float* v_X, float* v_twist, float* J_pose,
                         float* J_X, const int32_t* pt_off, const int32_t* pt_obs, hipStream_t st);
+// The same with the accumulators given explicitly: twist_acc [n_cams][6] and
+// loss_acc [1] (double, zero on entry, left zero), diag [kDiagCount] (the
+// masked count is added to diag[kDiagMasked]).
+struct TrackScratch {
+    double* twist_acc;
+    double* loss_acc;
+    uint32_t* diag;
+};
+hipError_t launch_track_scratch(const TrackScratch& sc, const float* X, int Pt, const float* viewmat,
+                                const float* intr, int n_cams, const int32_t* obs_cam,
+                                const int32_t* obs_pt, const float* obs_xy, int M, float delta,
+                                float lambda, float near_plane, float* residual, float* loss,
+                                float* v_X, float* v_twist, float* J_pose, float* J_X,
+                                const int32_t* pt_off, const int32_t* pt_obs, hipStream_t st);
+hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t st);
 // Point-major index of the observations for launch_track: pt_off[Pt + 1],
 // pt_obs[M] (each point's observations ascending; out-of-range points left
 // out).  Uses c->cnt (>= Pt words) and the scan scratch (>= Pt + 1 items).

@@ -133,6 +133,12 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a, float b1, float b2, fl
     }
 }
 
+__global__ void k_fill_f64(double* __restrict__ p, double v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
 __global__ void k_step_advance(int32_t* __restrict__ step_dev) {
     if (threadIdx.x == 0) *step_dev += 1;
 }
@@ -213,6 +219,14 @@ hipError_t launch_flush_acc(double* acc, float* out, int n, hipStream_t st) {
 hipError_t launch_flush_twist_rows(double* acc, float* out, const ViewTable& vt, hipStream_t st) {
     if (vt.V <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_flush_twist_rows, dim3((6 * vt.V + 255) / 256), dim3(256), 0, st, acc, out, vt);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)blocks), dim3(256), 0, st, p, v, n);
     return hipGetLastError();
 }
 

@@ -298,28 +298,40 @@ hipError_t launch_track(Ctx* c, const float* X, int Pt, const float* viewmat, co
                         const float* obs_xy, int M, float delta, float lambda, float near_plane,
                         float* residual, float* loss, float* v_X, float* v_twist, float* J_pose,
                         float* J_X, const int32_t* pt_off, const int32_t* pt_obs, hipStream_t st) {
+    const TrackScratch sc = {c->twist_track, c->loss_acc + 1, c->diag};
+    return launch_track_scratch(sc, X, Pt, viewmat, intr, n_cams, obs_cam, obs_pt, obs_xy, M, delta,
+                                lambda, near_plane, residual, loss, v_X, v_twist, J_pose, J_X, pt_off,
+                                pt_obs, st);
+}
+
+hipError_t launch_track_scratch(const TrackScratch& sc, const float* X, int Pt, const float* viewmat,
+                                const float* intr, int n_cams, const int32_t* obs_cam,
+                                const int32_t* obs_pt, const float* obs_xy, int M, float delta,
+                                float lambda, float near_plane, float* residual, float* loss,
+                                float* v_X, float* v_twist, float* J_pose, float* J_X,
+                                const int32_t* pt_off, const int32_t* pt_obs, hipStream_t st) {
     const bool indexed = pt_off && pt_obs && v_X;
     if (M > 0) {
         // with the point index the point gradients come from k_track_points
         hipLaunchKernelGGL(k_track, dim3(std::min((M + kBlock - 1) / kBlock, kTrackBlocks)),
                            dim3(kBlock), 0, st, X, Pt,
                            viewmat, intr, n_cams, obs_cam, obs_pt, obs_xy, M, delta, lambda,
-                           near_plane, residual, indexed ? nullptr : v_X, J_pose, J_X, c->twist_track,
-                           c->loss_acc + 1, c->diag);
+                           near_plane, residual, indexed ? nullptr : v_X, J_pose, J_X, sc.twist_acc,
+                           sc.loss_acc, sc.diag);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         if (indexed && Pt > 0) {
             // the point gradients, and the drain of the twist and loss sums
             hipLaunchKernelGGL(k_track_points, dim3((Pt + kBlock - 1) / kBlock), dim3(kBlock), 0, st, X,
                                Pt, viewmat, intr, n_cams, obs_cam, obs_xy, pt_off, pt_obs, delta, lambda,
-                               near_plane, v_X, c->twist_track, v_twist, c->loss_acc + 1, loss);
+                               near_plane, v_X, sc.twist_acc, v_twist, sc.loss_acc, loss);
             return hipGetLastError();
         }
     }
     hipError_t e = hipSuccess;
-    if (v_twist && (e = launch_flush_acc(c->twist_track, v_twist, 6 * n_cams, st)) != hipSuccess)
+    if (v_twist && (e = launch_flush_acc(sc.twist_acc, v_twist, 6 * n_cams, st)) != hipSuccess)
         return e;
-    if (loss) return launch_flush_acc(c->loss_acc + 1, loss, 1, st);
+    if (loss) return launch_flush_acc(sc.loss_acc, loss, 1, st);
     return hipSuccess;
 }
 
