@@ -2,11 +2,14 @@
 """Throughput of the joint pose-appearance step on one MI355X.
 
 Metric: forward+backward megapixels per second with pose gradients.  The
-default workload is the full joint step on 150 cameras at 1237x822, 1M
-Gaussians (SH degree 3), 100k tracks, 4 views per step: every step runs pose
-composition, projection, bin/sort, compositing, L1, raster and projection
-backward, track reprojection, the twist chain and Adam.  Inputs are seeded
-synthetic scenes resident in HBM before the timed region.
+default workload is the large scene: 1000 cameras at 1600x1066, 5M Gaussians
+(SH degree 3), 1.5M tracks (6.5M observations), 4 views per step; every step
+runs pose composition, projection, bin/sort, compositing, the photometric loss
+(L1 + SSIM, lambda 0.2), raster and projection backward, track reprojection
+over all observations, the twist chain and Adam.  The joint step of 150
+cameras at 1237x822 and 1M Gaussians is timed too and reported under
+`extra_workloads`.  Inputs are seeded synthetic scenes resident in HBM before
+the timed region.
 
 The timed steps are replayed from captured HIP graphs (one per batch of
 views, every kernel of the step); the same steps run eagerly, call by call,
@@ -17,7 +20,7 @@ roofline of the dominant kernel, the batched-vs-per-view comparison on the
 8-view uneven-resolution scene (3M Gaussians), and the FP64 oracle timed on a
 bounded sample of the same workload on the host cores.
 
-  python bench.py [--steps K] [--warmup W] [--workload C4|C2|C3|C5]
+  python bench.py [--steps K] [--warmup W] [--workload C5|C4|C2|C3] [--lambda-ssim L]
 """
 
 from __future__ import annotations
@@ -100,13 +103,15 @@ def make_workload(name):
     return sc, batches, targets
 
 
-def run_joint(torch, name, steps, warmup, tune=True, tile=None, order=0, graph=True):
+def run_joint(torch, name, steps, warmup, tune=True, tile=None, order=0, graph=True,
+              lambda_ssim=0.2):
     from paper_2603_04847_amd import _lib as L
     from paper_2603_04847_amd.autotune import autotune
     from paper_2603_04847_amd.step import JointStep
     sc, batches, targets = make_workload(name)
     P = max(int(sum(int(sc["wh"][v, 0]) * int(sc["wh"][v, 1]) for v in b)) for b in batches)
-    st = JointStep(sc, batches, targets, max_isect=min(2**30 - 65536, 48 * P))
+    st = JointStep(sc, batches, targets, max_isect=min(2**30 - 65536, 48 * P),
+                   lambda_ssim=lambda_ssim)
     tuning = None
     if tile is not None:
         st.settings = L.default_settings(tile_w=tile[0], tile_h=tile[1], tile_order=order)
@@ -216,6 +221,8 @@ def algorithmic_bytes(sz):
         "bin_sort": sz["n_isect"] * 36,
         "render_fwd": sz["C_f"] * 40 + sz["P"] * 20,
         "l1": sz["P"] * 36,
+        # images in, gradient out (the SSIM window sums stay in LDS)
+        "photo": sz["P"] * 36,
         "raster_bwd": sz["C_f"] * 40 + sz["P"] * 20 + sz["n_visible"] * 36,
         "project_bwd": sz["n_visible"] * 36 + 2 * sz["N"] * pg,
         # 2D gradients in; parameters, first and second moments in and out
@@ -238,20 +245,42 @@ FLOPS_CONTRIB = {"render_fwd": 10, "raster_bwd": 34}
 FP32_PEAK_TFLOPS = 157.3
 ALU_KERNELS = ("render_fwd", "raster_bwd")
 # calls that launch one kernel (the others are sequences: bin_sort is ~25)
-SINGLE_KERNEL = ("project", "render_fwd", "l1", "raster_bwd", "track", "adam")
+SINGLE_KERNEL = ("project", "render_fwd", "l1", "photo", "raster_bwd", "track", "adam")
 KERNEL_SOURCE = {"render_fwd": "raster.hip", "raster_bwd": "raster.hip", "project": "project.hip",
                  "project_bwd": "project.hip", "project_bwd_adam": "project.hip",
                  "bin_sort": "bin.hip", "track": "track.hip",
-                 "adam": "optim.hip", "l1": "raster.hip"}
+                 "adam": "optim.hip", "l1": "raster.hip", "photo": "photo.hip"}
 
 
 # calls whose kernels HBM traffic bounds (the raster pair is VALU-bound, the
 # binning sequence latency- and VALU-bound)
 HBM_BOUND_CALLS = ("project", "project_bwd_adam", "l1", "adam")
+# the steps of one forward + backward with pose gradients (a2-a8), and the
+# whole step (a1-a10: adds the track term and Adam on twists and points)
+A2_A8 = ("project", "bin_sort", "render_fwd", "l1", "photo", "raster_bwd", "project_bwd",
+         "project_bwd_adam")
+STEP_CALLS = A2_A8 + ("track", "adam")
 
 
 def algorithmic_flops(sz, call):
     return sz["n_eval"] * FLOPS_EVAL + sz["n_contrib"] * FLOPS_CONTRIB[call]
+
+
+def hbm_step(alg, per_call, step_ms):
+    a = [k for k in A2_A8 if k in per_call and k in alg]
+    w = [k for k in STEP_CALLS if k in per_call and k in alg]
+    b_a, t_a = sum(alg[k] for k in a), sum(per_call[k] for k in a)
+    b_w = sum(alg[k] for k in w)
+    return {"a2_a8": {"bytes": int(b_a), "ms": round(t_a, 4),
+                      "gbs": round(b_a / (t_a * 1e-3) / 1e9, 1),
+                      "frac": round(b_a / (t_a * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)},
+            "step": {"bytes": int(b_w), "ms": round(step_ms, 4),
+                     "gbs": round(b_w / (step_ms * 1e-3) / 1e9, 1),
+                     "frac": round(b_w / (step_ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)},
+            "bytes_by_call": {k: int(alg[k]) for k in w},
+            "model": ("project N(44+12K) + 48 N_v; bin_sort 36 I; render_fwd 40 C_f + 20 P; "
+                      "photo / l1 36 P; raster_bwd 40 C_f + 20 P + 36 N_v; project_bwd_adam "
+                      "36 N_v + 6 N(44+12K); track 28 M + 24 Pt; adam 28 per parameter")}
 
 
 def source_sha(call):
@@ -278,7 +307,9 @@ def measured_traffic(call, workload):
 
 def batched_vs_per_view(torch, steps, warmup):
     """fwd+bwd (pose grads included) over the 8 uneven views of C3: one batched
-    call per stage vs the same library called once per view."""
+    call per stage vs the same library called once per view.  The tile shape
+    and launch order are the fastest of the candidates for the batched call
+    (timed here); the per-view path runs at the same settings."""
     import scenegen
     import paper_2603_04847_amd as P
     from paper_2603_04847_amd import _lib as L
@@ -301,27 +332,47 @@ def batched_vs_per_view(torch, steps, warmup):
     loss = torch.zeros(1, device="cuda")
     v_tw = torch.zeros((V, 6), device="cuda")
     pix_off = np.concatenate([[0], np.cumsum(wh[:, 0].astype(np.int64) * wh[:, 1])])
-    tiles = int(sum(((w + 15) // 16) * ((h + 15) // 16) for w, h in wh))
-    # probe the intersection count
-    ctx = P.Context(max_pairs=V * N, max_isect=2**28, max_tiles=tiles, max_views=V)
     cams_b = L.Cameras(vm, intr, wh)
-    s = L.default_settings()
-    L.gs_project(ctx, g, cams_b, s)
-    L.gs_bin_sort(ctx, cams_b, N, s)
-    need = ctx.status()["n_isect_needed"]
-    ctx.close()
-    ctx = P.Context(max_pairs=V * N, max_isect=int(need * 1.1) + 4096, max_tiles=tiles, max_views=V)
     cams_v = [L.Cameras(vm[v:v + 1], intr[v:v + 1], wh[v:v + 1]) for v in range(V)]
-    s_acc = L.default_settings(grad_accumulate=1)
+    cap_max = 2**30 - 65536
 
-    def batched():
+    def make_ctx(tile):
+        tiles = int(sum(((w + tile[0] - 1) // tile[0]) * ((h + tile[1] - 1) // tile[1]) for w, h in wh))
+        ctx = P.Context(max_pairs=V * N, max_isect=cap_max, max_tiles=tiles, max_views=V)
+        s = L.default_settings(tile_w=tile[0], tile_h=tile[1])
+        L.gs_project(ctx, g, cams_b, s)
+        L.gs_bin_sort(ctx, cams_b, N, s)
+        st = ctx.status()
+        need = st["n_isect_needed"]
+        ctx.close()
+        if st["flags"] & L.GS_FLAG_ISECT_OVERFLOW or need * 1.1 + 4096 > cap_max:
+            return None, need
+        return P.Context(max_pairs=V * N, max_isect=int(need * 1.1) + 4096, max_tiles=tiles,
+                         max_views=V), need
+
+    def timed(fn, n):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(n):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / n
+
+    def batched(ctx, s):
         L.gs_project(ctx, g, cams_b, s)
         L.gs_bin_sort(ctx, cams_b, N, s)
         L.gs_render_fwd(ctx, cams_b, s, None, rgb, T, last)
         L.gs_l1_loss_grad(ctx, cams_b, rgb, target, v_rgb, loss)
         L.gs_render_bwd(ctx, g, cams_b, s, None, T, last, v_rgb, gg, v_tw)
 
-    def per_view():
+    def per_view(ctx, s):
+        s_acc = L.default_settings(tile_w=s.tile_w, tile_h=s.tile_h, tile_order=s.tile_order,
+                                   grad_accumulate=1)
         for v in range(V):
             a, b = int(pix_off[v]), int(pix_off[v + 1])
             c = cams_v[v]
@@ -332,23 +383,42 @@ def batched_vs_per_view(torch, steps, warmup):
             L.gs_render_bwd(ctx, g, c, s if v == 0 else s_acc, None, T[a:b], last[a:b],
                             v_rgb[a:b], gg, v_tw[v:v + 1])
 
+    cand = {}
+    best = None
+    for tile in ((16, 16), (32, 16), (16, 8)):
+        ctx, need = make_ctx(tile)
+        if ctx is None:
+            cand[f"{tile[0]}x{tile[1]}"] = "lists exceed the capacity limit"
+            continue
+        for order in (0, 1):
+            s = L.default_settings(tile_w=tile[0], tile_h=tile[1], tile_order=order)
+            ms = timed(lambda: batched(ctx, s), max(2, steps // 2))
+            cand[f"{tile[0]}x{tile[1]}/{order}"] = round(ms, 3)
+            if best is None or ms < best[0]:
+                best = (ms, tile, order, need)
+        ctx.close()
+    _, tile, order, need = best
+    ctx, need = make_ctx(tile)
+    s = L.default_settings(tile_w=tile[0], tile_h=tile[1], tile_order=order)
     out = {}
-    for name, fn in (("batched", batched), ("per_view", per_view)):
-        for _ in range(warmup):
-            fn()
-        torch.cuda.synchronize()
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(steps):
-            fn()
-        b.record()
-        torch.cuda.synchronize()
-        ms = a.elapsed_time(b) / steps
+    for name, fn in (("batched", lambda: batched(ctx, s)), ("per_view", lambda: per_view(ctx, s))):
+        ms = timed(fn, steps)
         out[name] = dict(ms=round(ms, 3), mp_s=round(Ptot / ms / 1e3, 1))
     out["speedup"] = round(out["per_view"]["ms"] / out["batched"]["ms"], 2)
     out["config"] = WORKLOADS["C3"]
+    out["tile"] = f"{tile[0]}x{tile[1]}"
+    out["tile_order"] = order
+    out["autotune_ms"] = cand
     out["n_isect"] = int(need)
+    # the stated load imbalance on the exact tile lists
+    L.gs_project(ctx, g, cams_b, s)
+    L.gs_bin_sort(ctx, cams_b, N, s)
+    b = ctx.buffers()
+    nt = b["n_tiles"]
+    rng = L.copy_to_host(b["tile_ranges"], 2 * nt, np.int32).reshape(nt, 2)
+    lens = (rng[:, 1] - rng[:, 0]).astype(np.int64)
+    nz = lens[lens > 0]
+    out["tile_list_len_max_over_median"] = round(float(nz.max() / np.median(nz)), 1)
     ctx.close()
     return out
 
@@ -373,12 +443,15 @@ def copy_bandwidth(torch, mib=1024, reps=5):
     return round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)
 
 
-def cpu_baseline(res, seconds_target=20.0):
+def cpu_baseline(res, seconds_target=20.0, lambda_ssim=0.2, max_gaussians=1_000_000,
+                 max_obs=2_000_000):
     """The FP64 oracle on the host cores, on a bounded sample of the same
     workload: the projection and its backward for the batch's views, the track
-    term over all observations, and compositing (with backward) of a random
-    sample of pixels; the compositing time is fitted over sample sizes and
-    taken at all pixels."""
+    term, and compositing (with backward) of a random sample of pixels; the
+    compositing time is fitted over sample sizes and taken at all pixels.  On
+    scenes of more than `max_gaussians` Gaussians (or `max_obs` observations)
+    the oracle runs on the first ones and its per-Gaussian (per-observation)
+    times are scaled to the whole scene: every part of it is linear in them."""
     import oracle
     sc, b = res["sc"], res["batches"][0]
     st = res["st"]
@@ -386,10 +459,17 @@ def cpu_baseline(res, seconds_target=20.0):
     vm = st.viewmat.cpu().numpy()[b]
     intr = sc["intr"][b]
     wh = sc["wh"][b]
+    t_start = time.time()
+    Ns = min(sz["N"], max_gaussians)
+    fN = sz["N"] / Ns
     sub = dict(sc, viewmat=vm, intr=intr, wh=wh)
+    for k in ("means", "log_scales", "quats"):
+        sub[k] = np.ascontiguousarray(sc[k][:, :Ns])
+    sub["opacity_logit"] = np.ascontiguousarray(sc["opacity_logit"][:Ns])
+    sub["sh"] = np.ascontiguousarray(sc["sh"][:, :, :Ns])
     t0 = time.time()
     proj = oracle.project(sub)
-    t_proj = time.time() - t0
+    t_proj = (time.time() - t0) * fN
     rng = np.random.default_rng(0)
     # the oracle's compositing time is a fixed part (per-view set-up) plus a
     # part per pixel: two calibration sizes give the per-pixel cost, a third,
@@ -412,25 +492,41 @@ def cpu_baseline(res, seconds_target=20.0):
     log(f"[bench] oracle: {n_pix} px {t_pix:.1f}s")
     per_px = max((t_pix - t1) / (n_pix - n1), 1e-12)
     fixed = max(t1 - per_px * n1, 0.0)
-    t_pix_all = fixed + per_px * sz["P"]
+    t_pix_all = (fixed + per_px * sz["P"]) * fN
     t0 = time.time()
     oracle.project_bwd(sub, r["v2d"])
-    t_pbwd = time.time() - t0
-    t_track = 0.0
+    t_pbwd = (time.time() - t0) * fN
+    t_track, Ms = 0.0, 0
     if sz["M"] > 0:
+        Ms = min(sz["M"], max_obs)
         t0 = time.time()
-        oracle.track(sc["X"], st.viewmat.cpu().numpy(), sc["intr"], sc["obs_cam"], sc["obs_pt"],
-                     sc["obs_xy"], jacobians=False)
-        t_track = time.time() - t0
-    t_step = t_proj + t_pix_all + t_pbwd + t_track
+        oracle.track(sc["X"], st.viewmat.cpu().numpy(), sc["intr"], sc["obs_cam"][:Ms],
+                     sc["obs_pt"][:Ms], sc["obs_xy"][:Ms], jacobians=False)
+        t_track = (time.time() - t0) * sz["M"] / Ms
+    # the photometric loss on a crop of view 0 (its cost is linear in pixels)
+    t_photo, n_crop = 0.0, 0
+    if lambda_ssim > 0:
+        W0, H0 = int(wh[0, 0]), int(wh[0, 1])
+        cw, ch = min(W0, 400), min(H0, 300)
+        img = st.rgb[:W0 * H0].cpu().numpy().reshape(H0, W0, 3)[:ch, :cw].reshape(-1, 3)
+        tgt = st.targets[0][:W0 * H0].cpu().numpy().reshape(H0, W0, 3)[:ch, :cw].reshape(-1, 3)
+        n_crop = cw * ch
+        t0 = time.time()
+        oracle.photo_loss(img, tgt, np.array([[cw, ch]], np.int32), lam=lambda_ssim)
+        t_photo = (time.time() - t0) * sz["P"] / n_crop
+    t_step = t_proj + t_pix_all + t_pbwd + t_track + t_photo
     return dict(value=round(sz["P"] / t_step / 1e6, 6), unit="MP/s", cores=oracle.num_threads(),
                 kind="oracle",
-                sample=(f"batch 0 of the workload: projection + its backward of {sz['V']} views x "
-                        f"{sz['N']} Gaussians, track term over {sz['M']} observations, and "
-                        f"compositing + backward of {n_pix} random pixels of {sz['P']} "
-                        f"(its time fitted as {fixed:.2f}s + {per_px * 1e3:.3f} ms per pixel from "
-                        f"samples of {n1}, {n2} and {n_pix} pixels, then taken at all pixels); "
-                        f"measured {t_proj + t1 + t2 + t_pix + t_pbwd + t_track:.1f}s"))
+                sample=(f"batch 0 of the workload on its first {Ns} of {sz['N']} Gaussians and "
+                        f"first {Ms} of {sz['M']} observations (times scaled by {fN:.2f} and "
+                        f"{(sz['M'] / Ms) if Ms else 0:.2f}): projection + its backward of "
+                        f"{sz['V']} views, track term, and compositing + backward of {n_pix} "
+                        f"random pixels of {sz['P']} (its time fitted as {fixed:.2f}s + "
+                        f"{per_px * 1e3:.3f} ms per pixel from samples of {n1}, {n2} and {n_pix} "
+                        f"pixels, then taken at all pixels)"
+                        + (f", and the photometric loss (L1 + SSIM) on a {n_crop}-pixel crop of "
+                           f"view 0 scaled to all pixels" if n_crop else "")
+                        + f"; measured {time.time() - t_start:.1f}s"))
 
 
 def main():
@@ -438,7 +534,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="C4", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="C5", choices=sorted(WORKLOADS))
+    ap.add_argument("--lambda-ssim", type=float, default=0.2,
+                    help="weight of the SSIM term in the photometric loss (0: L1 alone)")
+    ap.add_argument("--no-extra", action="store_true", help="skip the extra C4 timing")
     ap.add_argument("--no-tune", action="store_true", help="keep 16x16 tiles, natural order")
     ap.add_argument("--tile", default=None, help="fixed tile shape WxH (skips the autotuner)")
     ap.add_argument("--order", type=int, default=0, help="tile launch order with --tile")
@@ -475,7 +574,8 @@ def main():
 
     tile = tuple(int(x) for x in args.tile.split("x")) if args.tile else None
     res = run_joint(torch, args.workload, args.steps, args.warmup, tune=not args.no_tune,
-                    tile=tile, order=args.order, graph=not args.no_graph)
+                    tile=tile, order=args.order, graph=not args.no_graph,
+                    lambda_ssim=args.lambda_ssim)
     sz = res["sizes"]
     # the timed steps: replayed from captured HIP graphs (the production mode:
     # the same kernels, no per-call host work between them), else eager
@@ -520,6 +620,11 @@ def main():
         # the calls bound by HBM: their algorithmic rate against the 8 TB/s peak
         "hbm_frac_by_call": {k: round(alg[k] / (per_call[k] * 1e-3) / 8e12, 3)
                              for k in HBM_BOUND_CALLS if k in alg and k in per_call},
+        # the step's algorithmic HBM bytes against its time and the 8 TB/s peak:
+        # a2-a8 (forward + backward with pose gradients) over the sum of those
+        # calls' eager times, and the whole step (plus track and Adam) over the
+        # replayed step time
+        "hbm_step": hbm_step(alg, per_call, ms),
         "timed_as": "hip_graph_replay" if res["graph_ms"] is not None else "eager",
         "eager_ms_per_step": round(ms_eager, 4),
         "step_ms_p10_p50_p90": (None if res["step_ms"] is None else
@@ -540,7 +645,24 @@ def main():
         line["batched_vs_per_view"] = batched_vs_per_view(torch, max(2, args.steps // 4), 1)
     if not args.no_cpu_baseline:
         log("[bench] oracle CPU baseline")
-        line["cpu_baseline"] = cpu_baseline(res)
+        line["cpu_baseline"] = cpu_baseline(res, lambda_ssim=args.lambda_ssim)
+    if not args.no_extra and args.workload != "C4":
+        # the joint step of 150 cameras at 1237x822 and 1M Gaussians, at the tile
+        # shape and order its autotuning picks (16x16, heaviest tile first)
+        del res
+        torch.cuda.empty_cache()
+        log("[bench] extra workload C4")
+        r4 = run_joint(torch, "C4", args.steps, args.warmup, tune=False, tile=(16, 16), order=1,
+                       graph=not args.no_graph, lambda_ssim=args.lambda_ssim)
+        ms4 = r4["graph_ms"] if r4["graph_ms"] is not None else r4["ms"]
+        pc4 = {k: round(v, 4) for k, v in r4["per_call"].items()}
+        line["extra_workloads"] = {"C4": {
+            "workload": f"C4: {WORKLOADS['C4']}", "value": round(r4["sizes"]["P"] / ms4 / 1e3, 2),
+            "unit": "MP/s", "ms_per_step": round(ms4, 4),
+            "timed_as": "hip_graph_replay" if r4["graph_ms"] is not None else "eager",
+            "eager_ms_per_step": round(r4["ms"], 4), "tile": "16x16", "tile_order": 1,
+            "per_call_ms": pc4, "hbm_step": hbm_step(algorithmic_bytes(r4["sizes"]), pc4, ms4),
+            "status_flags": r4["status"]["flags"]}}
     print(json.dumps(line), flush=True)
 
 

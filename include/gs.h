@@ -304,6 +304,25 @@ gs_status gs_photo_loss_grad(gs_ctx* ctx, const gs_cameras* cams, const float* r
                              const float* target, float lambda_ssim, float* v_rgb, float* loss,
                              void* stream);
 
+/* Gaussians from SfM points (Sec. 3.3, initialisation; Algorithm 1,
+ * initialise G from the SfM points): for each point i of points[n][3] (with
+ * colour rgb[n][3] in [0, 1]): mean = the point; an isotropic scale s = the
+ * mean Euclidean distance to its k nearest other points (k = 4 in the paper;
+ * all other points when there are fewer; s raised to 1e-7 when smaller),
+ * log_scales = log s on all three axes; identity rotation (1, 0, 0, 0);
+ * opacity_logit = log(opacity / (1 - opacity)) (opacity = 0.1 in the paper);
+ * sh degree-0 band = (rgb - 0.5) 2 sqrt(pi), so the renderer's colour rule
+ * gives back rgb; the other bands zero.  Outputs in the planar layout of
+ * gs_gaussians (caller-owned device arrays).  The neighbours are exact (a
+ * uniform grid searched in growing shells); any of several equidistant
+ * neighbours may be taken, which leaves s unchanged.  1 <= k <= GS_INIT_MAX_K;
+ * n <= the context's max_pairs (it uses the pair-sized workspace). */
+#define GS_INIT_MAX_K 8
+gs_status gs_init_gaussians(gs_ctx* ctx, const float* points, const float* rgb, int32_t n,
+                            int32_t k, float opacity, int32_t sh_degree, float* means,
+                            float* log_scales, float* quats, float* opacity_logit, float* sh,
+                            void* stream);
+
 /* Track reprojection (Sec. 3.3 eq. L_BA^joint; Algorithm 1, joint BA loss):
  * for each observation o = (camera obs_cam[o], point obs_pt[o], pixel
  * obs_xy[o][2]):  p = R X + t; masked (no loss, no gradient, counted) if

@@ -274,6 +274,37 @@ def photo_loss(rgb, target, wh, lam=0.2):
     return (1 - lam) * l + lam * (1 - s), (1 - lam) * vl - lam * vs
 
 
+def knn_mean_dist(points, k=4, queries=None):
+    """Mean distance of each point (or of the points `queries` index) to its k
+    nearest other points (brute force)."""
+    lib = _load()
+    pts = _f64(points).reshape(-1, 3)
+    q = None if queries is None else np.ascontiguousarray(queries, dtype=np.int64)
+    nq = pts.shape[0] if q is None else q.shape[0]
+    out = np.zeros(nq)
+    if lib.or_knn_mean_dist(ctypes.c_longlong(pts.shape[0]), _p(pts), ctypes.c_int(k),
+                            ctypes.c_longlong(nq), _p(q), _p(out)) != 0:
+        raise ValueError("or_knn_mean_dist failed")
+    return out
+
+
+def init_gaussians(points, rgb, sh_degree=3, k=4, opacity=0.1, s_min=1e-7):
+    """Gaussians from SfM points (planar layout, float64)."""
+    lib = _load()
+    pts = _f64(points).reshape(-1, 3)
+    n = pts.shape[0]
+    K = (sh_degree + 1) ** 2
+    out = dict(means=np.zeros((3, n)), log_scales=np.zeros((3, n)), quats=np.zeros((4, n)),
+               opacity_logit=np.zeros(n), sh=np.zeros((K, 3, n)))
+    rc = lib.or_init_gaussians(ctypes.c_longlong(n), _p(pts), _p(_f64(rgb).reshape(-1, 3)),
+                               ctypes.c_int(k), ctypes.c_double(opacity), ctypes.c_double(s_min),
+                               ctypes.c_int(sh_degree), _p(out["means"]), _p(out["log_scales"]),
+                               _p(out["quats"]), _p(out["opacity_logit"]), _p(out["sh"]))
+    if rc != 0:
+        raise ValueError("or_init_gaussians failed")
+    return out
+
+
 def bin_sort(wh, tile, valid, mean2d, conic, opacity, depth, alpha_min=1.0 / 255.0,
              margin=0.0, with_masks=False):
     """Tile lists ordered by (float32 depth bits, pair index).  Returns

@@ -1074,3 +1074,73 @@ int or_ssim(int V, const int* wh, const double* rgb, const double* target, int w
     free(g);
     return 0;
 }
+
+/* ------------------------------------------------------------ Gaussian initialisation */
+/*
+ * Each SfM point starts one Gaussian (Sec. 3.3, first paragraph; Algorithm 1,
+ * initialisation): mean = the point, an isotropic scale equal to the mean
+ * Euclidean distance to its k = 4 nearest other points (found here by brute
+ * force over all points), opacity 0.1, and spherical harmonics holding the
+ * point's colour in the degree-0 band (rgb = 0.5 + C0 sh_0, C0 = 1/(2 sqrt(pi)),
+ * the colour rule of the renderer), higher bands zero, identity rotation.
+ * With fewer than k other points all of them are used; a scale below s_min
+ * (coincident points) is raised to s_min.
+ */
+int or_knn_mean_dist(long long n, const double* pts, int k, long long nq, const long long* q_idx,
+                     double* out) {
+    if (n < 0 || k <= 0 || k > 64) return -1;
+    if (!q_idx) nq = n;
+    int fail = 0;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long long qi = 0; qi < nq; qi++) {
+        const long long i = q_idx ? q_idx[qi] : qi;
+        if (i < 0 || i >= n) { fail = 1; continue; }
+        double best[64];
+        int nb = 0;
+        for (long long j = 0; j < n; j++) {
+            if (j == i) continue;
+            double dx = pts[3 * j] - pts[3 * i], dy = pts[3 * j + 1] - pts[3 * i + 1],
+                   dz = pts[3 * j + 2] - pts[3 * i + 2];
+            double d = sqrt(dx * dx + dy * dy + dz * dz);
+            /* keep the k smallest distances, ascending */
+            if (nb < k) {
+                int p = nb++;
+                while (p > 0 && best[p - 1] > d) { best[p] = best[p - 1]; p--; }
+                best[p] = d;
+            } else if (d < best[k - 1]) {
+                int p = k - 1;
+                while (p > 0 && best[p - 1] > d) { best[p] = best[p - 1]; p--; }
+                best[p] = d;
+            }
+        }
+        double s = 0;
+        for (int q = 0; q < nb; q++) s += best[q];
+        out[qi] = nb > 0 ? s / nb : 0.0;
+    }
+    return fail ? -1 : 0;
+}
+
+int or_init_gaussians(long long n, const double* pts, const double* rgb, int k, double opacity,
+                      double s_min, int sh_degree, double* means, double* log_scales,
+                      double* quats, double* opacity_logit, double* sh) {
+    if (sh_degree < 0 || sh_degree > 3 || !(opacity > 0 && opacity < 1)) return -1;
+    double* d = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (or_knn_mean_dist(n, pts, k, n, NULL, d) != 0) { free(d); return -1; }
+    const int K = (sh_degree + 1) * (sh_degree + 1);
+    const double C0 = 1.0 / (2.0 * sqrt(PI));
+    for (long long i = 0; i < n; i++) {
+        double s = d[i] > s_min ? d[i] : s_min;
+        for (int a = 0; a < 3; a++) {
+            means[(size_t)a * n + i] = pts[3 * i + a];
+            log_scales[(size_t)a * n + i] = log(s);
+        }
+        quats[i] = 1.0;
+        quats[(size_t)n + i] = quats[2 * (size_t)n + i] = quats[3 * (size_t)n + i] = 0.0;
+        opacity_logit[i] = log(opacity / (1.0 - opacity));
+        for (int c = 0; c < K; c++)
+            for (int ch = 0; ch < 3; ch++)
+                sh[((size_t)c * 3 + ch) * n + i] = c == 0 ? (rgb[3 * i + ch] - 0.5) / C0 : 0.0;
+    }
+    free(d);
+    return 0;
+}

@@ -122,6 +122,20 @@ int or_l1(int V, const int* wh, const double* rgb, const double* target, double*
 int or_ssim(int V, const int* wh, const double* rgb, const double* target, int win,
             double wsig, double c1, double c2, double* ssim, double* ssim_map, double* v_rgb);
 
+/* Mean Euclidean distance of points (pts[n][3]) to their k nearest other
+ * points (all of them when fewer), by brute force: for the nq points q_idx[]
+ * (q_idx == NULL: all n) into out[nq]. */
+int or_knn_mean_dist(long long n, const double* pts, int k, long long nq, const long long* q_idx,
+                     double* out);
+
+/* Gaussians from SfM points: means = pts, isotropic log-scale = log(max(mean
+ * distance to the k nearest other points, s_min)), identity rotation, opacity
+ * logit = logit(opacity), SH degree-0 band = (rgb - 0.5) / C0, other bands 0.
+ * Outputs in the planar layout of the Gaussians. */
+int or_init_gaussians(long long n, const double* pts, const double* rgb, int k, double opacity,
+                      double s_min, int sh_degree, double* means, double* log_scales,
+                      double* quats, double* opacity_logit, double* sh);
+
 /* Real spherical-harmonic basis (Condon-Shortley phase) at unit direction d,
  * K = (deg+1)^2 values; dY[K][3] = gradient of the polynomial form, may be
  * NULL. */

@@ -83,6 +83,7 @@ EXPORTS = [
     "gs_render_bwd", "gs_raster_bwd", "gs_project_bwd", "gs_l1_loss_grad", "track_reproj_fwd_bwd", "gs_pose_compose",
     "gs_pose_compose_bwd", "gs_adam_step", "gs_project_bwd_adam", "track_point_index",
     "gs_step_advance", "gs_ctx_generation", "track_reproj_fwd_bwd_noalloc", "gs_photo_loss_grad",
+    "gs_init_gaussians",
 ]
 
 _lib = None
@@ -137,6 +138,9 @@ def load():
         c_vp, c_vp, ctypes.c_int32, c_vp, c_vp, ctypes.c_int32, c_vp, c_vp, c_vp, ctypes.c_int32,
         ctypes.c_float, ctypes.c_float, ctypes.c_float, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
         c_vp, c_vp]
+    lib.gs_init_gaussians.argtypes = [c_vp, c_vp, c_vp, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_float, ctypes.c_int32, c_vp, c_vp, c_vp, c_vp,
+                                      c_vp, c_vp]
     lib.gs_photo_loss_grad.argtypes = [c_vp, ctypes.POINTER(gs_cameras), c_vp, c_vp, ctypes.c_float,
                                        c_vp, c_vp, c_vp]
     lib.track_reproj_fwd_bwd_noalloc.argtypes = [
@@ -363,6 +367,23 @@ def gs_l1_loss_grad(ctx, cams, rgb, target, v_rgb, loss, stream=None):
     _check("gs_l1_loss_grad", load().gs_l1_loss_grad(ctx.handle, ctypes.byref(cams.struct),
                                                      _ptr(rgb), _ptr(target), _ptr(v_rgb),
                                                      _ptr(loss), _stream(stream)))
+
+
+def gs_init_gaussians(ctx, points, rgb, sh_degree=3, k=4, opacity=0.1, out=None, stream=None):
+    """Gaussians from points [n,3] and colours [n,3] (device tensors); returns
+    the dict of planar parameter tensors (or fills `out`)."""
+    import torch
+    n = int(points.shape[0])
+    K = (int(sh_degree) + 1) ** 2
+    if out is None:
+        f = lambda *shape: torch.empty(shape, device=points.device, dtype=torch.float32)
+        out = dict(means=f(3, n), log_scales=f(3, n), quats=f(4, n), opacity_logit=f(n),
+                   sh=f(K, 3, n))
+    _check("gs_init_gaussians", load().gs_init_gaussians(
+        ctx.handle, _ptr(points), _ptr(rgb), n, int(k), float(opacity), int(sh_degree),
+        _ptr(out["means"]), _ptr(out["log_scales"]), _ptr(out["quats"]),
+        _ptr(out["opacity_logit"]), _ptr(out["sh"]), _stream(stream)))
+    return out
 
 
 def gs_photo_loss_grad(ctx, cams, rgb, target, lambda_ssim, v_rgb, loss, stream=None):

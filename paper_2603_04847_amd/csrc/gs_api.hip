@@ -204,6 +204,7 @@ gs_status gs_ctx_create(gs_ctx** out, const gs_capacity* cap) {
     A(dalloc(&c.twist_render, (size_t)6 * nv));
     A(dalloc(&c.twist_track, (size_t)6 * nc));
     A(dalloc(&c.loss_acc, 4));
+    A(dalloc(&c.aux, gs::kAuxFloats));
     A(dalloc(&c.diag, gs::kDiagCount));
     if (e == hipSuccess) A(hipMemset(c.grad2d, 0, sizeof(float) * GS_GRAD2D_FLOATS * (P > 0 ? P : 1)));
     if (e == hipSuccess) A(hipMemset(c.twist_render, 0, sizeof(double) * 6 * nv));
@@ -228,7 +229,7 @@ gs_status gs_ctx_destroy(gs_ctx* h) {
     void* ptrs[] = {c.rec, c.grad2d, c.vmu_dir, c.cnt, c.off, c.pk[0], c.pk[1], c.pv[0], c.pv[1],
                     c.ik[0], c.ik[1], c.iv[0], c.iv[1], c.im[0], c.im[1], c.tcnt, c.ccnt, c.cbase, c.bpre, c.bplace, c.tbase, c.tranges, c.tids,
                     c.ranges, c.tile_order, c.tk[0], c.tk[1], c.tile_contrib, c.tile_entries, c.tile_evals, c.hist,
-                    c.scan_scratch, c.scalars, c.twist_render, c.twist_track, c.loss_acc, c.diag};
+                    c.scan_scratch, c.scalars, c.twist_render, c.twist_track, c.loss_acc, c.aux, c.diag};
     hipDeviceSynchronize();
     for (void* p : ptrs)
         if (p) hipFree(p);
@@ -435,6 +436,20 @@ gs_status gs_photo_loss_grad(gs_ctx* h, const gs_cameras* cams, const float* rgb
     if ((r = check_cams(h->c, cams, false)) != GS_OK) return r;
     const gs::ViewTable vt = gs::make_view_table(cams->wh, cams->V, 16, 16, cams->index);
     return from_hip(gs::launch_photo(&h->c, vt, rgb, target, lambda_ssim, v_rgb, loss, (hipStream_t)stream));
+}
+
+gs_status gs_init_gaussians(gs_ctx* h, const float* points, const float* rgb, int32_t n, int32_t k,
+                            float opacity, int32_t sh_degree, float* means, float* log_scales,
+                            float* quats, float* opacity_logit, float* sh, void* stream) {
+    if (!h || n < 0 || k < 1 || k > GS_INIT_MAX_K) return GS_ERR_INVALID_ARG;
+    if (sh_degree < 0 || sh_degree > 3) return GS_ERR_UNSUPPORTED;
+    if (!(opacity > 0.f && opacity < 1.f)) return GS_ERR_INVALID_ARG;
+    if (n > 0 && (!points || !rgb || !means || !log_scales || !quats || !opacity_logit || !sh))
+        return GS_ERR_INVALID_ARG;
+    if ((int64_t)n > h->c.cap.max_pairs) return GS_ERR_CAPACITY;
+    return from_hip(gs::launch_init_gaussians(&h->c, points, rgb, n, k, opacity, sh_degree, means,
+                                              log_scales, quats, opacity_logit, sh,
+                                              (hipStream_t)stream));
 }
 
 gs_status track_reproj_fwd_bwd(gs_ctx* h, const float* X, int32_t Pt, const float* viewmat,

@@ -43,6 +43,8 @@ enum DiagSlot {
 
 struct Ctx;  // defined in gs_api.hip
 
+constexpr int kAuxFloats = 8192;
+
 // ------------------------------------------------------------------ device helpers
 
 __device__ __forceinline__ float bcast(float v, int lane) {
@@ -458,6 +460,12 @@ hipError_t launch_render_bwd(Ctx* c, const ViewTable& vt, const RasterParams& rp
 hipError_t launch_l1(Ctx* c, const ViewTable& vt, const float* rgb, const float* target,
                      float* v_rgb, float* loss, hipStream_t st);
 
+// init.hip: Gaussians from points (k-nearest-neighbour scales); uses the
+// pair-sized sort buffers, records, counts and aux of the context
+hipError_t launch_init_gaussians(Ctx* c, const float* pts, const float* rgb, int n, int k,
+                                 float opacity, int sh_degree, float* means, float* log_scales,
+                                 float* quats, float* logit, float* sh, hipStream_t st);
+
 // photo.hip: (1 - lambda) L1 + lambda (1 - SSIM) and its image gradient
 hipError_t launch_photo(Ctx* c, const ViewTable& vt, const float* rgb, const float* target,
                         float lambda, float* v_rgb, float* loss, hipStream_t st);
@@ -538,6 +546,7 @@ struct Ctx {
     double* twist_render;  // [max_views][6]
     double* twist_track;   // [max_cams][6]
     double* loss_acc;      // [4]
+    float* aux;            // [kAuxFloats] small per-call device scratch (bounding boxes, grid)
     uint32_t* diag;        // [kDiagCount]
     // state of the last bin step
     int64_t n_tiles, n_blocks;

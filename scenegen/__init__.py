@@ -238,13 +238,13 @@ def _blob_points(rng, n, n_blobs=50, ball_r=1.5, sig_lo=0.02, sig_hi=0.4, dirich
 
 
 def blob_scene(seed, resolutions, N, sh_degree=3, log_scale_mu=-4.0, log_scale_sd=0.7,
-               sh_sd=0.1, n_blobs=50, make_target=True):
+               sh_sd=0.1, n_blobs=50, make_target=True, dirichlet=0.3):
     """Cameras on a sphere of radius 4 around a mixture of isotropic blobs of
-    Gaussians (configs C3, C4, C5).  Blob weights are Dirichlet(0.3), so the
-    per-tile load is very uneven."""
+    Gaussians (configs C3, C4, C5).  Blob weights are Dirichlet(`dirichlet`)
+    (0.3 unless given), so the per-tile load is very uneven."""
     rng = _rng(seed)
     viewmat, intr, wh = sphere_cameras(rng, resolutions)
-    means = _blob_points(rng, N, n_blobs)
+    means = _blob_points(rng, N, n_blobs, dirichlet=dirichlet)
     log_scales, q, logit, sh = _gaussian_params(rng, N, sh_degree, log_scale_mu,
                                                 log_scale_sd, sh_sd)
     P = int(sum(w * h for w, h in resolutions))
@@ -395,6 +395,9 @@ def batch_views(seed, n_views, batch, steps):
     return [np.sort(rng.choice(n_views, size=batch, replace=False)) for _ in range(steps)]
 
 
+C3_DIRICHLET = 0.05
+
+
 def make_config(name, seed=None):
     """The five named workloads.  Returns the scene dict (see module doc)."""
     name = name.upper()
@@ -406,7 +409,11 @@ def make_config(name, seed=None):
         return frustum_scene(2 if seed is None else seed, W, H, FX_PER_W * W,
                              FX_PER_W * W, 1_000_000, 3, -4.0, 0.7, sh_sd=0.1)
     if name == "C3":
-        s = blob_scene(3 if seed is None else seed, C3_RESOLUTIONS, 3_000_000)
+        # Dirichlet(0.05) blob weights: the recipe lowers the concentration from
+        # 0.3 until the largest per-tile splat count is at least 100 times the
+        # median (0.3 gives about 42, 0.1 about 110, 0.05 about 140)
+        s = blob_scene(3 if seed is None else seed, C3_RESOLUTIONS, 3_000_000,
+                       dirichlet=C3_DIRICHLET)
         s.pop("_rng")
         return s
     if name == "C4":

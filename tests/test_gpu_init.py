@@ -1,0 +1,90 @@
+"""Gaussians from SfM points (Sec. 3.3, initialisation) through the C ABI
+against the FP64 oracle's brute-force k-nearest-neighbour definition:
+clustered points with far outliers and coincident points, tiny sets (fewer
+points than k + 1, a single point), a lattice, and the large scene's 1.5M
+track points on a sample."""
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_04847_amd as P
+    P.load()
+    return P
+
+
+def _t(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype)
+
+
+def _gpu_init(gs, pts, rgb, sh_degree=3, k=4):
+    n = pts.shape[0]
+    ctx = gs.Context(max_pairs=max(n, 1), max_isect=1 << 10, max_tiles=16, max_views=1)
+    out = gs.gs_init_gaussians(ctx, _t(pts), _t(rgb), sh_degree=sh_degree, k=k)
+    torch.cuda.synchronize()
+    return {kk: v.cpu().numpy() for kk, v in out.items()}
+
+
+def test_init_matches_oracle_on_clustered_points_with_outliers(gs):
+    rng = np.random.default_rng(12)
+    pts = np.concatenate([rng.normal(0, 0.05, (6000, 3)), rng.normal(1, 0.3, (8000, 3)),
+                          rng.uniform(-3, 3, (200, 3)), [[40.0, -25.0, 9.0], [-30.0, 31.0, -17.0]]])
+    pts[100:104] = pts[99]                                        # five coincident points
+    pts = pts.astype(np.float32)
+    rgb = rng.uniform(size=pts.shape).astype(np.float32)
+    g = _gpu_init(gs, pts, rgb)
+    o = oracle.init_gaussians(pts, rgb, sh_degree=3)
+    np.testing.assert_array_equal(g["means"], pts.T)
+    s_g, s_o = np.exp(g["log_scales"].astype(np.float64)), np.exp(o["log_scales"])
+    assert np.max(np.abs(s_g / s_o - 1)) <= 1e-5
+    assert np.all(g["log_scales"][0] == g["log_scales"][1]) and np.all(g["log_scales"][0] == g["log_scales"][2])
+    np.testing.assert_array_equal(g["quats"][0], 1.0)
+    np.testing.assert_array_equal(g["quats"][1:], 0.0)
+    np.testing.assert_allclose(g["opacity_logit"], o["opacity_logit"], rtol=1e-6)
+    np.testing.assert_allclose(g["sh"][0], o["sh"][0], rtol=1e-6, atol=1e-7)
+    assert np.all(g["sh"][1:] == 0)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5])
+def test_init_tiny_sets(gs, n):
+    rng = np.random.default_rng(n)
+    pts = rng.uniform(-1, 1, (n, 3)).astype(np.float32)
+    rgb = rng.uniform(size=(n, 3)).astype(np.float32)
+    g = _gpu_init(gs, pts, rgb, sh_degree=0)
+    o = oracle.init_gaussians(pts, rgb, sh_degree=0)
+    s_g, s_o = np.exp(g["log_scales"].astype(np.float64)), np.exp(o["log_scales"])
+    assert np.max(np.abs(s_g / s_o - 1)) <= 1e-5
+
+
+def test_init_lattice(gs):
+    a = 0.25
+    gr = np.arange(20) * a
+    pts = np.stack(np.meshgrid(gr, gr, gr, indexing="ij"), -1).reshape(-1, 3).astype(np.float32)
+    rgb = np.full(pts.shape, 0.5, np.float32)
+    g = _gpu_init(gs, pts, rgb, sh_degree=1)
+    o = oracle.init_gaussians(pts, rgb, sh_degree=1)
+    s_g, s_o = np.exp(g["log_scales"].astype(np.float64)), np.exp(o["log_scales"])
+    assert np.max(np.abs(s_g / s_o - 1)) <= 1e-5
+
+
+def test_init_large_scene_track_points_sampled(gs):
+    """The large scene's 1.5M track points (clustered in 50 blobs): every
+    scale against the brute-force oracle on 1500 sampled points."""
+    sc = scenegen.make_config("C5")
+    pts = sc["X"].astype(np.float32)
+    rgb = np.random.default_rng(1).uniform(size=pts.shape).astype(np.float32)
+    g = _gpu_init(gs, pts, rgb)
+    idx = np.sort(np.random.default_rng(2).choice(pts.shape[0], 1500, replace=False))
+    d = oracle.knn_mean_dist(pts, 4, queries=idx)
+    s_g = np.exp(g["log_scales"][0, idx].astype(np.float64))
+    assert np.max(np.abs(s_g / np.maximum(d, 1e-7) - 1)) <= 1e-5

@@ -447,6 +447,7 @@ def _full_size_check(gs, sub, tile, order, npix, max_isect, seed, min_frac=0.97)
     tw = v_tw.cpu().numpy()
     for v in range(V):
         _close(tw[v], og["twist"][v], what=f"twist view {v}")
+    return ctx
 
 
 def test_full_size_batch_sampled_pixels_and_gradients(gs):
@@ -470,7 +471,16 @@ def test_full_size_uneven_views_sampled(gs):
     """The batched uneven-view workload at full size: 8 views from 640x480 to
     1600x1066 around 3M clustered Gaussians (SH degree 3), one call."""
     sc = scenegen.make_config("C3")
-    _full_size_check(gs, sc, (16, 16), 1, 300, 400_000_000, 13)
+    ctx = _full_size_check(gs, sc, (16, 16), 1, 300, 400_000_000, 13)
+    # the workload's stated load imbalance, on the exact tile lists: the
+    # longest list is at least 100 times the median non-empty one
+    b = ctx.buffers()
+    nt = b["n_tiles"]
+    ranges = _read_i32(b["tile_ranges"], 2 * nt).reshape(nt, 2)
+    lens = (ranges[:, 1] - ranges[:, 0]).astype(np.int64)
+    nz = lens[lens > 0]
+    print(f"[C3] tile lists: max {nz.max()}, median {np.median(nz):.0f}", flush=True)
+    assert nz.max() >= 100 * np.median(nz)
 
 
 def test_full_size_large_scene_sampled(gs):

@@ -897,3 +897,53 @@ def test_ssim_gradient_against_central_differences():
         sm = oracle.ssim(x, y, wh, grad=False)[0]
         flat[i] = old
         assert abs((sp - sm) / (2 * h) - v.reshape(-1)[i]) <= 1e-7 * np.abs(v).max(), i
+
+
+# ----------------------------------------------------------------- initialisation from SfM points
+
+def test_knn_mean_distance_against_scipy_kdtree():
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(8)
+    pts = np.concatenate([rng.normal(0, 0.3, (700, 3)), rng.uniform(-2, 2, (300, 3))])
+    d, _ = cKDTree(pts).query(pts, k=5)
+    np.testing.assert_allclose(oracle.knn_mean_dist(pts, 4), d[:, 1:].mean(axis=1), rtol=1e-12)
+    np.testing.assert_allclose(oracle.knn_mean_dist(pts, 1), d[:, 1], rtol=1e-12)
+
+
+def test_knn_mean_distance_lattice_and_line_closed_forms():
+    a = 0.37
+    g = np.arange(5) * a
+    lat = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    d = oracle.knn_mean_dist(lat, 4).reshape(5, 5, 5)
+    assert abs(d[2, 2, 2] - a) < 1e-14                       # six neighbours at a
+    assert abs(d[0, 0, 0] - (3 + np.sqrt(2)) * a / 4) < 1e-14  # corner: a, a, a, sqrt(2) a
+    line = np.zeros((9, 3))
+    line[:, 1] = np.arange(9) * a
+    d = oracle.knn_mean_dist(line, 4)
+    assert abs(d[4] - 1.5 * a) < 1e-14 and abs(d[0] - 2.5 * a) < 1e-14
+    # fewer other points than k: all of them
+    tri = np.array([[0, 0, 0], [1.0, 0, 0], [0, 2.0, 0]])
+    np.testing.assert_allclose(oracle.knn_mean_dist(tri, 4), [1.5, (1 + np.sqrt(5)) / 2, (2 + np.sqrt(5)) / 2],
+                               rtol=1e-14)
+
+
+def test_init_gaussians_closed_forms():
+    rng = np.random.default_rng(9)
+    pts = rng.uniform(-1, 1, (50, 3))
+    pts[7] = pts[3]                                   # coincident pair
+    pts[8] = pts[3]
+    pts[9] = pts[3]
+    pts[10] = pts[3]                                  # five coincident points: distance 0
+    rgb = rng.uniform(size=(50, 3))
+    g = oracle.init_gaussians(pts, rgb, sh_degree=2, s_min=1e-7)
+    np.testing.assert_array_equal(g["means"], pts.T)
+    C0 = 1 / (2 * np.sqrt(np.pi))
+    np.testing.assert_allclose(0.5 + C0 * g["sh"][0], rgb.T, rtol=1e-14)
+    assert np.all(g["sh"][1:] == 0) and g["sh"].shape == (9, 3, 50)
+    np.testing.assert_allclose(1 / (1 + np.exp(-g["opacity_logit"])), 0.1, rtol=1e-14)
+    np.testing.assert_array_equal(g["quats"][0], 1.0)
+    np.testing.assert_array_equal(g["quats"][1:], 0.0)
+    d = oracle.knn_mean_dist(pts, 4)
+    np.testing.assert_allclose(np.exp(g["log_scales"]), np.broadcast_to(np.maximum(d, 1e-7), (3, 50)),
+                               rtol=1e-14)
+    assert d[3] == 0.0 and abs(np.exp(g["log_scales"][0, 3]) - 1e-7) < 1e-20
