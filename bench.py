@@ -443,7 +443,7 @@ def copy_bandwidth(torch, mib=1024, reps=5):
     return round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)
 
 
-def cpu_baseline(res, seconds_target=20.0, lambda_ssim=0.2, max_gaussians=1_000_000,
+def cpu_baseline(res, seconds_target=12.0, lambda_ssim=0.2, max_gaussians=1_000_000,
                  max_obs=2_000_000):
     """The FP64 oracle on the host cores, on a bounded sample of the same
     workload: the projection and its backward for the batch's views, the track

@@ -323,6 +323,42 @@ gs_status gs_init_gaussians(gs_ctx* ctx, const float* points, const float* rgb, 
                             float* log_scales, float* quats, float* opacity_logit, float* sh,
                             void* stream);
 
+/* One Levenberg-Marquardt step of bundle adjustment (Sec. 3.2 "Bundle
+ * Adjustment", eq. L_BA^SfM: Huber on the squared reprojection error, poses on
+ * SE(3), Levenberg-Marquardt), iteratively reweighted: for each observation
+ * (camera obs_cam, point obs_pt, pixel obs_xy) with residual r = pi_i(X_k) -
+ * x, s = |r|^2, weight w = 1 (s <= delta^2) or delta / sqrt(s), and Jacobian
+ * J = dr/d(xi_i, X_k) (xi the left twist at the current pose, translation
+ * first, as everywhere in this library), the step d = (d_twist, d_X) solves
+ *   (H + lm_lambda diag(H)) d = -g,   H = sum w J^T J,   g = sum w J^T r.
+ * Observations with p_z < near_plane are left out; a camera or a point with
+ * no observation is held fixed (d = 0).  The points are eliminated (Schur
+ * complement) and the 6 n_cams camera system is solved by conjugate
+ * gradients preconditioned with its inverse 6x6 diagonal blocks, in double,
+ * for max_iter iterations or until the residual is below tol times the
+ * right-hand side (a device flag ends the iteration: the call stays
+ * graph-capturable).  The step is to be applied as T_i <- Exp(d_twist_i) T_i
+ * (gs_pose_compose) and X_k <- X_k + d_X_k.
+ * X[Pt][3], viewmat[n_cams][12], intr[n_cams][4]; observations SORTED BY
+ * CAMERA (otherwise stats[4] = 1 and the step is zero); pt_off / pt_obs: the
+ * point-major index of the observations from track_point_index.
+ * Outputs: d_twist[n_cams][6], d_X[Pt][3] (device floats, overwritten); stats
+ * (device float[5], may be NULL): iterations run, final relative residual,
+ * the robust cost sum rho before the step, masked observations, unsorted
+ * flag.  lm_lambda > 0. */
+#define GS_BA_MAX_CAMS 65536
+typedef struct gs_ba gs_ba;
+/* BA workspace: 96 B per point and 676 B per camera of device memory,
+ * allocated once. */
+gs_status gs_ba_create(gs_ba** out, int64_t max_points, int32_t max_cams);
+gs_status gs_ba_destroy(gs_ba* ba);
+gs_status gs_ba_lm_step(gs_ba* ba, const float* X, int32_t Pt, const float* viewmat,
+                        const float* intr, int32_t n_cams, const int32_t* obs_cam,
+                        const int32_t* obs_pt, const float* obs_xy, int32_t M,
+                        const int32_t* pt_off, const int32_t* pt_obs, float delta,
+                        float lm_lambda, float near_plane, int32_t max_iter, float tol,
+                        float* d_twist, float* d_X, float* stats, void* stream);
+
 /* Track reprojection (Sec. 3.3 eq. L_BA^joint; Algorithm 1, joint BA loss):
  * for each observation o = (camera obs_cam[o], point obs_pt[o], pixel
  * obs_xy[o][2]):  p = R X + t; masked (no loss, no gradient, counted) if

@@ -305,6 +305,57 @@ def init_gaussians(points, rgb, sh_degree=3, k=4, opacity=0.1, s_min=1e-7):
     return out
 
 
+def ba_normal(X, viewmat, intr, obs_cam, obs_pt, obs_xy, delta=1.0, near=0.01):
+    """Dense Gauss-Newton normal equations of the Huber BA cost: (H, g, cost,
+    masked), unknowns ordered cameras (6 each) then points (3 each)."""
+    lib = _load()
+    X = _f64(X).reshape(-1, 3)
+    viewmat = _f64(viewmat).reshape(-1, 12)
+    n = 6 * viewmat.shape[0] + 3 * X.shape[0]
+    H = np.zeros((n, n))
+    g = np.zeros(n)
+    cost = np.zeros(1)
+    m = lib.or_ba_normal(ctypes.c_int(X.shape[0]), _p(X), ctypes.c_int(viewmat.shape[0]), _p(viewmat),
+                         _p(_f64(intr)), ctypes.c_int(len(obs_cam)), _p(_i32(obs_cam)), _p(_i32(obs_pt)),
+                         _p(_f64(obs_xy)), ctypes.c_double(delta), ctypes.c_double(near), _p(H),
+                         _p(g), _p(cost))
+    if m < 0:
+        raise ValueError("or_ba_normal failed")
+    return H, g, float(cost[0]), m
+
+
+def ba_step(X, viewmat, intr, obs_cam, obs_pt, obs_xy, delta=1.0, lm_lambda=1e-3, near=0.01):
+    """One LM step: d solves (H + lambda diag(H)) d = -g over the unknowns with a
+    non-zero diagonal (the others stay 0).  Returns (d_twist [ncam,6],
+    d_X [Pt,3], cost).  The solve is LAPACK's (numpy)."""
+    H, g, cost, _ = ba_normal(X, viewmat, intr, obs_cam, obs_pt, obs_xy, delta, near)
+    A = H + lm_lambda * np.diag(np.diag(H))
+    live = np.diag(H) > 0
+    d = np.zeros_like(g)
+    d[live] = np.linalg.solve(A[np.ix_(live, live)], -g[live])
+    nc = np.asarray(viewmat).reshape(-1, 12).shape[0]
+    return d[:6 * nc].reshape(nc, 6), d[6 * nc:].reshape(-1, 3), cost
+
+
+def ba_normal_residual(X, viewmat, intr, obs_cam, obs_pt, obs_xy, d_twist, d_X, delta=1.0,
+                       lm_lambda=1e-3, near=0.01):
+    """(H + lambda diag(H)) d + g for d = (d_twist, d_X), per observation (any
+    size); returns (cameras part [ncam,6], points part [Pt,3])."""
+    lib = _load()
+    X = _f64(X).reshape(-1, 3)
+    viewmat = _f64(viewmat).reshape(-1, 12)
+    nc = viewmat.shape[0]
+    d = np.concatenate([_f64(d_twist).reshape(-1), _f64(d_X).reshape(-1)])
+    out = np.zeros_like(d)
+    rc = lib.or_ba_normal_residual(ctypes.c_int(X.shape[0]), _p(X), ctypes.c_int(nc), _p(viewmat),
+                                   _p(_f64(intr)), ctypes.c_int(len(obs_cam)), _p(_i32(obs_cam)),
+                                   _p(_i32(obs_pt)), _p(_f64(obs_xy)), ctypes.c_double(delta),
+                                   ctypes.c_double(near), ctypes.c_double(lm_lambda), _p(d), _p(out))
+    if rc != 0:
+        raise ValueError("or_ba_normal_residual failed")
+    return out[:6 * nc].reshape(nc, 6), out[6 * nc:].reshape(-1, 3)
+
+
 def bin_sort(wh, tile, valid, mean2d, conic, opacity, depth, alpha_min=1.0 / 255.0,
              margin=0.0, with_masks=False):
     """Tile lists ordered by (float32 depth bits, pair index).  Returns

@@ -1144,3 +1144,134 @@ int or_init_gaussians(long long n, const double* pts, const double* rgb, int k, 
     free(d);
     return 0;
 }
+
+/* ------------------------------------------------------------ one LM step of bundle adjustment */
+/*
+ * Bundle adjustment minimises sum_obs rho_Huber(|pi_i(X_k) - x|^2) over the
+ * poses (SE(3), here left twists xi_i at the current pose) and the points X_k
+ * (Sec. 3.2 "Bundle Adjustment", eq. L_BA^SfM), by Levenberg-Marquardt.  One
+ * step, iteratively reweighted: with r the residual, s = |r|^2 and the weight
+ * w = rho'(s) (1 for an inlier s <= delta^2, delta / sqrt(s) otherwise), the
+ * Gauss-Newton normal equations of the robust cost are
+ *   H = sum_obs w J^T J,   g = sum_obs w J^T r,   J = dr/d(xi, X),
+ * and the step solves (H + lambda diag(H)) d = -g.  Masked observations
+ * (p_z < near) are left out.  Unknowns whose diagonal is zero (a camera or a
+ * point with no observation) are held fixed (d = 0).
+ * Unknowns are ordered cameras first (6 each: rho, phi), then points (3).
+ */
+typedef struct {
+    int ok;
+    double r[2], w, Jp[12], Jx[6], rho;
+} obs_lin_t;
+
+static void ba_linearise(const double* X, const double* viewmat, const double* intr, int ci, int k,
+                         const double* xy, double delta, double near_plane, obs_lin_t* L) {
+    double R[9], t[3], p[3];
+    for (int a = 0; a < 3; a++) {
+        for (int b = 0; b < 3; b++) R[3 * a + b] = viewmat[12 * ci + 4 * a + b];
+        t[a] = viewmat[12 * ci + 4 * a + 3];
+    }
+    mat3_vec(R, X + 3 * (size_t)k, p);
+    for (int a = 0; a < 3; a++) p[a] += t[a];
+    L->ok = p[2] >= near_plane;
+    if (!L->ok) return;
+    double fx = intr[4 * ci], fy = intr[4 * ci + 1], cx = intr[4 * ci + 2], cy = intr[4 * ci + 3];
+    double z = p[2];
+    L->r[0] = fx * p[0] / z + cx - xy[0];
+    L->r[1] = fy * p[1] / z + cy - xy[1];
+    double s = L->r[0] * L->r[0] + L->r[1] * L->r[1];
+    L->w = s <= delta * delta ? 1.0 : delta / sqrt(s);
+    L->rho = s <= delta * delta ? s : 2 * delta * sqrt(s) - delta * delta;
+    double Jpi[6] = {fx / z, 0, -fx * p[0] / (z * z), 0, fy / z, -fy * p[1] / (z * z)};
+    double D[18] = {1, 0, 0, 0, p[2], -p[1],
+                    0, 1, 0, -p[2], 0, p[0],
+                    0, 0, 1, p[1], -p[0], 0};
+    for (int a = 0; a < 2; a++) {
+        for (int b = 0; b < 6; b++) {
+            double v = 0;
+            for (int e = 0; e < 3; e++) v += Jpi[3 * a + e] * D[6 * e + b];
+            L->Jp[6 * a + b] = v;
+        }
+        for (int b = 0; b < 3; b++) {
+            double v = 0;
+            for (int e = 0; e < 3; e++) v += Jpi[3 * a + e] * R[3 * e + b];
+            L->Jx[3 * a + b] = v;
+        }
+    }
+}
+
+/* Dense undamped H [n][n] and g [n] (n = 6 ncam + 3 Pt) and the robust cost
+ * sum rho; returns the number of masked observations, -1 on a bad index. */
+int or_ba_normal(int Pt, const double* X, int ncam, const double* viewmat, const double* intr,
+                 int M, const int* obs_cam, const int* obs_pt, const double* obs_xy, double delta,
+                 double near_plane, double* H, double* g, double* cost) {
+    const long long n = 6LL * ncam + 3LL * Pt;
+    memset(H, 0, sizeof(double) * (size_t)(n * n));
+    memset(g, 0, sizeof(double) * (size_t)n);
+    double C = 0;
+    int masked = 0;
+    for (int o = 0; o < M; o++) {
+        int ci = obs_cam[o], k = obs_pt[o];
+        if (ci < 0 || ci >= ncam || k < 0 || k >= Pt) return -1;
+        obs_lin_t L;
+        ba_linearise(X, viewmat, intr, ci, k, obs_xy + 2 * (size_t)o, delta, near_plane, &L);
+        if (!L.ok) { masked++; continue; }
+        C += L.rho;
+        /* this observation's row block J = [.. Jp at camera ci .. Jx at point k ..] */
+        long long idx[9];
+        double J[2][9];
+        for (int b = 0; b < 6; b++) idx[b] = 6LL * ci + b;
+        for (int b = 0; b < 3; b++) idx[6 + b] = 6LL * ncam + 3LL * k + b;
+        for (int a = 0; a < 2; a++) {
+            for (int b = 0; b < 6; b++) J[a][b] = L.Jp[6 * a + b];
+            for (int b = 0; b < 3; b++) J[a][6 + b] = L.Jx[3 * a + b];
+        }
+        for (int u = 0; u < 9; u++) {
+            g[idx[u]] += L.w * (J[0][u] * L.r[0] + J[1][u] * L.r[1]);
+            for (int v = 0; v < 9; v++)
+                H[idx[u] * n + idx[v]] += L.w * (J[0][u] * J[0][v] + J[1][u] * J[1][v]);
+        }
+    }
+    if (cost) *cost = C;
+    return masked;
+}
+
+/* out = (H + lambda diag(H)) d + g, accumulated observation by observation
+ * (no dense matrix: any size).  Fixed unknowns (zero diagonal) contribute
+ * nothing because their columns are zero. */
+int or_ba_normal_residual(int Pt, const double* X, int ncam, const double* viewmat,
+                          const double* intr, int M, const int* obs_cam, const int* obs_pt,
+                          const double* obs_xy, double delta, double near_plane, double lambda,
+                          const double* d, double* out) {
+    const long long n = 6LL * ncam + 3LL * Pt;
+    double* diag = (double*)calloc((size_t)n, sizeof(double));
+    memset(out, 0, sizeof(double) * (size_t)n);
+    for (int o = 0; o < M; o++) {
+        int ci = obs_cam[o], k = obs_pt[o];
+        if (ci < 0 || ci >= ncam || k < 0 || k >= Pt) { free(diag); return -1; }
+        obs_lin_t L;
+        ba_linearise(X, viewmat, intr, ci, k, obs_xy + 2 * (size_t)o, delta, near_plane, &L);
+        if (!L.ok) continue;
+        long long idx[9];
+        double J[2][9];
+        for (int b = 0; b < 6; b++) idx[b] = 6LL * ci + b;
+        for (int b = 0; b < 3; b++) idx[6 + b] = 6LL * ncam + 3LL * k + b;
+        for (int a = 0; a < 2; a++) {
+            for (int b = 0; b < 6; b++) J[a][b] = L.Jp[6 * a + b];
+            for (int b = 0; b < 3; b++) J[a][6 + b] = L.Jx[3 * a + b];
+        }
+        /* J d for this observation */
+        double Jd[2] = {0, 0};
+        for (int u = 0; u < 9; u++) {
+            Jd[0] += J[0][u] * d[idx[u]];
+            Jd[1] += J[1][u] * d[idx[u]];
+        }
+        for (int u = 0; u < 9; u++) {
+            out[idx[u]] += L.w * (J[0][u] * (Jd[0] + L.r[0]) + J[1][u] * (Jd[1] + L.r[1]));
+            diag[idx[u]] += L.w * (J[0][u] * J[0][u] + J[1][u] * J[1][u]);
+        }
+    }
+    for (long long i = 0; i < n; i++) out[i] += lambda * diag[i] * d[i];
+    free(diag);
+    return 0;
+}

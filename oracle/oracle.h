@@ -136,6 +136,20 @@ int or_init_gaussians(long long n, const double* pts, const double* rgb, int k, 
                       double s_min, int sh_degree, double* means, double* log_scales,
                       double* quats, double* opacity_logit, double* sh);
 
+/* Bundle adjustment, one Levenberg-Marquardt step (iteratively reweighted
+ * Gauss-Newton on the Huber cost): the dense undamped normal equations
+ * H [n][n], g [n] (n = 6 ncam + 3 Pt; cameras first, left twists (rho, phi),
+ * then points) and the robust cost; returns the masked-observation count. */
+int or_ba_normal(int Pt, const double* X, int ncam, const double* viewmat, const double* intr,
+                 int M, const int* obs_cam, const int* obs_pt, const double* obs_xy, double delta,
+                 double near_plane, double* H, double* g, double* cost);
+
+/* out[n] = (H + lambda diag(H)) d + g, accumulated per observation (any size). */
+int or_ba_normal_residual(int Pt, const double* X, int ncam, const double* viewmat,
+                          const double* intr, int M, const int* obs_cam, const int* obs_pt,
+                          const double* obs_xy, double delta, double near_plane, double lambda,
+                          const double* d, double* out);
+
 /* Real spherical-harmonic basis (Condon-Shortley phase) at unit direction d,
  * K = (deg+1)^2 values; dY[K][3] = gradient of the polynomial form, may be
  * NULL. */

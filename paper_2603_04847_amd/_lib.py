@@ -83,7 +83,7 @@ EXPORTS = [
     "gs_render_bwd", "gs_raster_bwd", "gs_project_bwd", "gs_l1_loss_grad", "track_reproj_fwd_bwd", "gs_pose_compose",
     "gs_pose_compose_bwd", "gs_adam_step", "gs_project_bwd_adam", "track_point_index",
     "gs_step_advance", "gs_ctx_generation", "track_reproj_fwd_bwd_noalloc", "gs_photo_loss_grad",
-    "gs_init_gaussians",
+    "gs_init_gaussians", "gs_ba_create", "gs_ba_destroy", "gs_ba_lm_step",
 ]
 
 _lib = None
@@ -138,6 +138,12 @@ def load():
         c_vp, c_vp, ctypes.c_int32, c_vp, c_vp, ctypes.c_int32, c_vp, c_vp, c_vp, ctypes.c_int32,
         ctypes.c_float, ctypes.c_float, ctypes.c_float, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
         c_vp, c_vp]
+    lib.gs_ba_create.argtypes = [ctypes.POINTER(c_vp), ctypes.c_int64, ctypes.c_int32]
+    lib.gs_ba_destroy.argtypes = [c_vp]
+    lib.gs_ba_lm_step.argtypes = [c_vp, c_vp, ctypes.c_int32, c_vp, c_vp, ctypes.c_int32, c_vp, c_vp,
+                                  c_vp, ctypes.c_int32, c_vp, c_vp, ctypes.c_float, ctypes.c_float,
+                                  ctypes.c_float, ctypes.c_int32, ctypes.c_float, c_vp, c_vp, c_vp,
+                                  c_vp]
     lib.gs_init_gaussians.argtypes = [c_vp, c_vp, c_vp, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.c_float, ctypes.c_int32, c_vp, c_vp, c_vp, c_vp,
                                       c_vp, c_vp]
@@ -367,6 +373,37 @@ def gs_l1_loss_grad(ctx, cams, rgb, target, v_rgb, loss, stream=None):
     _check("gs_l1_loss_grad", load().gs_l1_loss_grad(ctx.handle, ctypes.byref(cams.struct),
                                                      _ptr(rgb), _ptr(target), _ptr(v_rgb),
                                                      _ptr(loss), _stream(stream)))
+
+
+class BundleAdjuster:
+    """A gs_ba workspace (one Levenberg-Marquardt step of bundle adjustment)."""
+
+    def __init__(self, max_points, max_cams):
+        h = c_vp()
+        _check("gs_ba_create", load().gs_ba_create(ctypes.byref(h), int(max_points), int(max_cams)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().gs_ba_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gs_ba_lm_step(ba, X, viewmat, intr, obs_cam, obs_pt, obs_xy, pt_index, delta, lm_lambda,
+                  near_plane, max_iter, tol, d_twist, d_X, stats=None, stream=None):
+    """pt_index: (pt_off, pt_obs) from track_point_index."""
+    pt_off, pt_obs = pt_index
+    _check("gs_ba_lm_step", load().gs_ba_lm_step(
+        ba.handle, _ptr(X), int(X.shape[0]), _ptr(viewmat), _ptr(intr), int(viewmat.shape[0]),
+        _ptr(obs_cam), _ptr(obs_pt), _ptr(obs_xy), int(obs_cam.shape[0]), _ptr(pt_off),
+        _ptr(pt_obs), float(delta), float(lm_lambda), float(near_plane), int(max_iter),
+        float(tol), _ptr(d_twist), _ptr(d_X), _ptr(stats), _stream(stream)))
 
 
 def gs_init_gaussians(ctx, points, rgb, sh_degree=3, k=4, opacity=0.1, out=None, stream=None):

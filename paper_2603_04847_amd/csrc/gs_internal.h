@@ -466,6 +466,22 @@ hipError_t launch_init_gaussians(Ctx* c, const float* pts, const float* rgb, int
                                  float opacity, int sh_degree, float* means, float* log_scales,
                                  float* quats, float* logit, float* sh, hipStream_t st);
 
+// ba.hip: one Levenberg-Marquardt step of bundle adjustment
+struct BaInputs {
+    const float* X;
+    const float* viewmat;
+    const float* intr;
+    const int32_t* obs_cam;
+    const int32_t* obs_pt;
+    const float* obs_xy;
+    const int32_t* pt_off;
+    const int32_t* pt_obs;
+    int Pt, n_cams, M, max_iter;
+    float delta, lambda, near_plane, tol;
+};
+hipError_t launch_ba_step(gs_ba* ba, const BaInputs& in, float* d_twist, float* d_X, float* stats,
+                          hipStream_t st);
+
 // photo.hip: (1 - lambda) L1 + lambda (1 - SSIM) and its image gradient
 hipError_t launch_photo(Ctx* c, const ViewTable& vt, const float* rgb, const float* target,
                         float lambda, float* v_rgb, float* loss, hipStream_t st);

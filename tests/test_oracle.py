@@ -947,3 +947,106 @@ def test_init_gaussians_closed_forms():
     np.testing.assert_allclose(np.exp(g["log_scales"]), np.broadcast_to(np.maximum(d, 1e-7), (3, 50)),
                                rtol=1e-14)
     assert d[3] == 0.0 and abs(np.exp(g["log_scales"][0, 3]) - 1e-7) < 1e-20
+
+
+# ----------------------------------------------------------------- bundle adjustment, one LM step
+
+def _ba_problem(seed=50, ncam=4, Pt=30, noise=0.0, perturb=0.0):
+    rng = np.random.default_rng(seed)
+    vms, intr = [], []
+    for i in range(ncam):
+        R = Rotation.from_rotvec(rng.normal(0, 0.2, 3)).as_matrix()
+        vms.append(_viewmat(R, np.array([0.3 * i, -0.1 * i, 0.0]) + rng.normal(0, 0.05, 3)))
+        intr.append([300.0, 310.0, 160.0, 120.0])
+    vms, intr = np.array(vms), np.array(intr)
+    X = rng.uniform(-1, 1, (Pt, 3)) + np.array([0, 0, 5.0])
+    cam, pt, xy = [], [], []
+    for k in range(Pt):
+        for i in sorted(rng.choice(ncam, size=min(ncam, 3), replace=False)):
+            M3 = vms[i].reshape(3, 4)
+            p = M3[:, :3] @ X[k] + M3[:, 3]
+            cam.append(i)
+            pt.append(k)
+            xy.append([intr[i, 0] * p[0] / p[2] + intr[i, 2], intr[i, 1] * p[1] / p[2] + intr[i, 3]])
+    order = np.argsort(cam, kind="stable")
+    cam, pt, xy = np.array(cam)[order], np.array(pt)[order], np.array(xy)[order]
+    xy = xy + rng.normal(0, noise, xy.shape) if noise else xy
+    if perturb:
+        vms = np.stack([_left_perturb(v, rng.normal(0, perturb, 6) * np.array([1, 1, 1, .3, .3, .3]))
+                        for v in vms])
+        X = X + rng.normal(0, perturb, X.shape)
+    return X, vms, intr, cam.astype(np.int32), pt.astype(np.int32), xy
+
+
+def test_ba_gradient_is_the_track_gradient():
+    X, vm, intr, cam, pt, xy = _ba_problem(noise=2.0)       # inliers and outliers
+    H, g, cost, masked = oracle.ba_normal(X, vm, intr, cam, pt, xy, delta=1.0)
+    t = oracle.track(X, vm, intr, cam, pt, xy, delta=1.0, lam=1.0)
+    nc = vm.shape[0]
+    np.testing.assert_allclose(g[:6 * nc], t["v_twist"].reshape(-1) / 2, rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(g[6 * nc:], t["v_X"].reshape(-1) / 2, rtol=1e-10, atol=1e-12)
+    assert abs(cost - t["loss"]) <= 1e-10 * cost and masked == 0
+    np.testing.assert_allclose(H, H.T, atol=1e-9 * np.abs(H).max())
+
+
+def test_ba_gauss_newton_matrix_is_the_hessian_at_zero_residual():
+    # all observations exact (r = 0, every one an inlier): the Hessian of
+    # cost / 2 = sum |r|^2 / 2 is J^T J = H; central differences of g
+    X, vm, intr, cam, pt, xy = _ba_problem(seed=51, ncam=3, Pt=8)
+    H, g, _, _ = oracle.ba_normal(X, vm, intr, cam, pt, xy)
+    assert np.max(np.abs(g)) < 1e-9
+    nc = vm.shape[0]
+    h = 1e-6
+    for col in range(H.shape[0]):
+        if col < 6 * nc:
+            i, e = divmod(col, 6)
+            xi = np.zeros(6)
+            xi[e] = h
+            vp, vmn = vm.copy(), vm.copy()
+            vp[i] = _left_perturb(vm[i], xi)
+            vmn[i] = _left_perturb(vm[i], -xi)
+            gp = oracle.ba_normal(X, vp, intr, cam, pt, xy)[1]
+            gm = oracle.ba_normal(X, vmn, intr, cam, pt, xy)[1]
+        else:
+            k, e = divmod(col - 6 * nc, 3)
+            Xp, Xm = X.copy(), X.copy()
+            Xp[k, e] += h
+            Xm[k, e] -= h
+            gp = oracle.ba_normal(Xp, vm, intr, cam, pt, xy)[1]
+            gm = oracle.ba_normal(Xm, vm, intr, cam, pt, xy)[1]
+        fd = (gp - gm) / (2 * h)
+        assert np.max(np.abs(fd - H[:, col])) <= 1e-6 * np.abs(H).max(), col
+
+
+def test_ba_lm_steps_converge_and_steepest_descent_limit():
+    X, vm, intr, cam, pt, xy = _ba_problem(seed=52, ncam=4, Pt=25, perturb=0.01)
+    costs = []
+    for it in range(6):
+        dtw, dX, cost = oracle.ba_step(X, vm, intr, cam, pt, xy, lm_lambda=1e-6)
+        costs.append(cost)
+        vm = np.stack([_left_perturb(vm[i], dtw[i]) for i in range(vm.shape[0])])
+        X = X + dX
+    assert costs[0] > 1.0 and costs[-1] < 1e-12 * costs[0], costs
+    assert all(b <= a for a, b in zip(costs, costs[1:]))
+    # a large damping turns the step into scaled steepest descent
+    X, vm, intr, cam, pt, xy = _ba_problem(seed=53, noise=1.5)
+    H, g, _, _ = oracle.ba_normal(X, vm, intr, cam, pt, xy)
+    lam = 1e8
+    dtw, dX, _ = oracle.ba_step(X, vm, intr, cam, pt, xy, lm_lambda=lam)
+    d = np.concatenate([dtw.reshape(-1), dX.reshape(-1)])
+    np.testing.assert_allclose(d * lam * np.diag(H), -g, rtol=1e-6, atol=1e-9 * np.abs(g).max())
+
+
+def test_ba_normal_residual_matches_the_dense_system():
+    X, vm, intr, cam, pt, xy = _ba_problem(seed=54, noise=1.5)
+    H, g, _, _ = oracle.ba_normal(X, vm, intr, cam, pt, xy)
+    rng = np.random.default_rng(0)
+    nc = vm.shape[0]
+    d = rng.normal(size=g.shape)
+    rc, rp = oracle.ba_normal_residual(X, vm, intr, cam, pt, xy, d[:6 * nc], d[6 * nc:], lm_lambda=0.3)
+    want = (H + 0.3 * np.diag(np.diag(H))) @ d + g
+    np.testing.assert_allclose(np.concatenate([rc.reshape(-1), rp.reshape(-1)]), want, rtol=1e-10,
+                               atol=1e-10 * np.abs(want).max())
+    dtw, dX, _ = oracle.ba_step(X, vm, intr, cam, pt, xy, lm_lambda=0.3)
+    rc, rp = oracle.ba_normal_residual(X, vm, intr, cam, pt, xy, dtw, dX, lm_lambda=0.3)
+    assert np.max(np.abs(np.concatenate([rc.reshape(-1), rp.reshape(-1)]))) <= 1e-9 * np.abs(g).max()
