@@ -476,6 +476,36 @@ gs_status gs_project_bwd_adam(gs_ctx* ctx, const gs_gaussians* g, const gs_camer
                               const int32_t* step_dev, float beta1, float beta2, float eps,
                               float* v_twist, void* stream);
 
+/* MCMC densification (Sec. 3.3, stochastic density control; Algorithm 1,
+ * MCMCDensify), relocation: every Gaussian whose opacity sigmoid(logit) is
+ * at most dead_opacity (0.005) moves onto a live one drawn with probability
+ * proportional to opacity; a source drawn c times ends as n = c + 1 copies
+ * with opacity 1 - (1 - o)^(1/n) and scale multiplied by
+ * o / sum_{i=1..n} sum_{k=0..i-1} C(i-1, k) (-1)^k o'^(k+1) / sqrt(k+1)
+ * (n capped at 51 in both rules); copies take the source's mean, rotation and
+ * SH; the Adam moments of sources and copies are zeroed.  The draw is exact
+ * integer arithmetic: weight floor(o 2^24) (o in double), Gaussian j (dead)
+ * takes the first index whose inclusive weight prefix exceeds floor(u[j] W),
+ * W the total, u[N] device floats in [0, 1) supplied by the caller (the
+ * library draws no random numbers).  state: the five planar parameter arrays
+ * of N Gaussians and their moments (lr unused), updated in place.  src[N]
+ * (device, may be NULL) receives each Gaussian's source or -1; n_relocated
+ * (device int32, may be NULL) the count.  To grow the set, enlarge the
+ * arrays with dead slots (opacity logit far below the threshold, zero
+ * moments) and relocate.  N <= the context's max_pairs. */
+gs_status gs_mcmc_relocate(gs_ctx* ctx, const gs_gaussian_adam* state, int32_t N,
+                           int32_t sh_degree, const float* u, float dead_opacity, int32_t* src,
+                           int32_t* n_relocated, void* stream);
+
+/* MCMC densification, noise on the means after an update:
+ * mu += scale sigmoid(-k (o - t)) Sigma eta, Sigma = R diag(exp(2 s)) R^T the
+ * Gaussian's covariance, eta[3][N] standard normal draws supplied by the
+ * caller, scale = the noise weight times the position learning rate (the
+ * adopted method uses k = 100, t = 0.005). */
+gs_status gs_mcmc_noise(float* means, const float* log_scales, const float* quats,
+                        const float* opacity_logit, int32_t N, const float* eta, float scale,
+                        float k, float t, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -356,6 +356,40 @@ def ba_normal_residual(X, viewmat, intr, obs_cam, obs_pt, obs_xy, d_twist, d_X, 
     return out[:6 * nc].reshape(nc, 6), out[6 * nc:].reshape(-1, 3)
 
 
+def mcmc_relocate(g, moments, u, sh_degree, t_dead=0.005):
+    """MCMC relocation on float64 copies: g = dict of the five planar arrays,
+    moments = (exp_avg dict, exp_avg_sq dict) in the same layout, u [N].
+    Returns (new g, new moments, src [N], n_relocated)."""
+    lib = _load()
+    keys = ("means", "log_scales", "quats", "opacity_logit", "sh")
+    G = {k: np.array(g[k], dtype=np.float64, copy=True, order="C") for k in keys}
+    M1 = {k: np.array(moments[0][k], dtype=np.float64, copy=True, order="C") for k in keys}
+    M2 = {k: np.array(moments[1][k], dtype=np.float64, copy=True, order="C") for k in keys}
+    N = G["opacity_logit"].shape[0]
+    src = np.zeros(N, np.int64)
+    nrel = ctypes.c_longlong()
+    arr1 = (ctypes.c_void_p * 5)(*[M1[k].ctypes.data for k in keys])
+    arr2 = (ctypes.c_void_p * 5)(*[M2[k].ctypes.data for k in keys])
+    rc = lib.or_mcmc_relocate(ctypes.c_longlong(N), ctypes.c_int(sh_degree), _p(G["means"]),
+                              _p(G["log_scales"]), _p(G["quats"]), _p(G["opacity_logit"]),
+                              _p(G["sh"]), arr1, arr2, _p(_f64(u)), ctypes.c_double(t_dead),
+                              _p(src), ctypes.byref(nrel))
+    if rc != 0:
+        raise ValueError("or_mcmc_relocate failed")
+    return G, (M1, M2), src, int(nrel.value)
+
+
+def mcmc_noise(g, eta, scale, k=100.0, t=0.005):
+    """Means after the MCMC noise step (float64 copy)."""
+    lib = _load()
+    means = np.array(g["means"], dtype=np.float64, copy=True, order="C")
+    N = means.shape[1]
+    lib.or_mcmc_noise(ctypes.c_longlong(N), _p(means), _p(_f64(g["log_scales"])),
+                      _p(_f64(g["quats"])), _p(_f64(g["opacity_logit"])), _p(_f64(eta)),
+                      ctypes.c_double(scale), ctypes.c_double(k), ctypes.c_double(t))
+    return means
+
+
 def bin_sort(wh, tile, valid, mean2d, conic, opacity, depth, alpha_min=1.0 / 255.0,
              margin=0.0, with_masks=False):
     """Tile lists ordered by (float32 depth bits, pair index).  Returns

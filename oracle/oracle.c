@@ -1275,3 +1275,130 @@ int or_ba_normal_residual(int Pt, const double* X, int ncam, const double* viewm
     free(diag);
     return 0;
 }
+
+/* ------------------------------------------------------------ MCMC densification */
+/*
+ * The stochastic density control the paper adopts (Sec. 3.3, first paragraph;
+ * Algorithm 1, MCMC densification): Gaussians whose opacity is at most
+ * t_dead are "dead" and are moved onto live ones, each dead Gaussian taking a
+ * source drawn from the live ones with probability proportional to opacity;
+ * a source chosen by c dead Gaussians ends as n = c + 1 identical copies
+ * whose opacity o' = 1 - (1 - o)^(1/n) keeps the combined opacity at the
+ * centre, and whose scale is multiplied by o / sum_{i=1..n} sum_{k=0..i-1}
+ * C(i-1, k) (-1)^k o'^(k+1) / sqrt(k+1), which keeps the integral of the
+ * combined opacity along an axis.  Copies take the source's mean, rotation and
+ * colour; the Adam moments of sources and copies restart at zero.  As in the
+ * adopted method, n is capped at 51 in these two rules (a source drawn more
+ * often still gives every draw a copy).
+ *
+ * Sampling is exact in integers: the weight of a live Gaussian is
+ * floor(o 2^24) with o = sigmoid(logit) in double, the draw for dead Gaussian
+ * j is the first live index whose inclusive weight prefix exceeds
+ * floor(u_j W) (u_j in [0, 1) given, W the total weight, the product taken in
+ * double).
+ */
+static double mcmc_scale_factor(double o, double op, int n) {
+    double denom = 0;
+    for (int i = 1; i <= n; i++) {
+        double binom_c = 1;  /* C(i-1, k), built up in k */
+        for (int k = 0; k <= i - 1; k++) {
+            denom += binom_c * ((k & 1) ? -1.0 : 1.0) * pow(op, k + 1) / sqrt((double)(k + 1));
+            binom_c = binom_c * (i - 1 - k) / (k + 1);
+        }
+    }
+    return o / denom;
+}
+
+int or_mcmc_relocate(long long N, int sh_degree, double* means, double* log_scales, double* quats,
+                     double* opacity_logit, double* sh, double* const* exp_avg,
+                     double* const* exp_avg_sq, const double* u, double t_dead, long long* src,
+                     long long* n_relocated) {
+    if (N < 0 || sh_degree < 0 || sh_degree > 3) return -1;
+    const int K = (sh_degree + 1) * (sh_degree + 1);
+    const long long rows[5] = {3, 3, 4, 1, 3LL * K};
+    double* P[5] = {means, log_scales, quats, opacity_logit, sh};
+    unsigned long long* cdf = (unsigned long long*)malloc(sizeof(unsigned long long) * (size_t)(N > 0 ? N : 1));
+    long long* count = (long long*)calloc((size_t)(N > 0 ? N : 1), sizeof(long long));
+    double* o = (double*)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
+    unsigned long long W = 0;
+    for (long long i = 0; i < N; i++) {
+        o[i] = 1.0 / (1.0 + exp(-opacity_logit[i]));
+        if (o[i] > t_dead) W += (unsigned long long)floor(o[i] * 16777216.0);
+        cdf[i] = W;
+    }
+    long long moved = 0;
+    for (long long j = 0; j < N; j++) {
+        src[j] = -1;
+        if (o[j] > t_dead || W == 0) continue;
+        unsigned long long tv = (unsigned long long)floor(u[j] * (double)W);
+        /* first index with cdf > tv */
+        long long lo = 0, hi = N;
+        while (lo < hi) {
+            long long mid = (lo + hi) / 2;
+            if (cdf[mid] > tv) hi = mid; else lo = mid + 1;
+        }
+        src[j] = lo;
+        count[lo]++;
+        moved++;
+    }
+    /* sources: opacity and scale of their n copies */
+    for (long long s = 0; s < N; s++) {
+        if (count[s] == 0) continue;
+        int n = count[s] + 1 < 51 ? (int)count[s] + 1 : 51;
+        double op = 1.0 - pow(1.0 - o[s], 1.0 / n);
+        double f = mcmc_scale_factor(o[s], op, n);
+        opacity_logit[s] = log(op / (1.0 - op));
+        for (int a = 0; a < 3; a++) log_scales[(size_t)a * N + s] += log(f);
+        for (int q = 0; q < 5; q++)
+            for (long long r = 0; r < rows[q]; r++) {
+                exp_avg[q][(size_t)r * N + s] = 0;
+                exp_avg_sq[q][(size_t)r * N + s] = 0;
+            }
+    }
+    /* targets: copies of their (updated) source */
+    for (long long j = 0; j < N; j++) {
+        long long s = src[j];
+        if (s < 0) continue;
+        for (int q = 0; q < 5; q++)
+            for (long long r = 0; r < rows[q]; r++) {
+                P[q][(size_t)r * N + j] = P[q][(size_t)r * N + s];
+                exp_avg[q][(size_t)r * N + j] = 0;
+                exp_avg_sq[q][(size_t)r * N + j] = 0;
+            }
+    }
+    if (n_relocated) *n_relocated = moved;
+    free(cdf);
+    free(count);
+    free(o);
+    return 0;
+}
+
+/* Noise on the means after an update (the same adopted method): mu += scale *
+ * sigmoid(-k (o - t)) * Sigma eta, Sigma = Rq diag(exp(2 s)) Rq^T the
+ * Gaussian's covariance (normalised quaternion), eta [3][N] given normal
+ * draws, scale = the noise weight times the position learning rate. */
+void or_mcmc_noise(long long N, double* means, const double* log_scales, const double* quats,
+                   const double* opacity_logit, const double* eta, double scale, double k, double t) {
+    for (long long i = 0; i < N; i++) {
+        double q[4], qn = 0;
+        for (int a = 0; a < 4; a++) { q[a] = quats[(size_t)a * N + i]; qn += q[a] * q[a]; }
+        qn = sqrt(qn);
+        for (int a = 0; a < 4; a++) q[a] /= qn;
+        double R[9];
+        quat_to_rot(q, R);
+        double s2[3];
+        for (int a = 0; a < 3; a++) s2[a] = exp(2 * log_scales[(size_t)a * N + i]);
+        double o = 1.0 / (1.0 + exp(-opacity_logit[i]));
+        double gate = 1.0 / (1.0 + exp(k * (o - t)));
+        double e[3] = {eta[i], eta[(size_t)N + i], eta[2 * (size_t)N + i]};
+        for (int a = 0; a < 3; a++) {
+            double v = 0;
+            for (int b = 0; b < 3; b++) {
+                double S = 0;
+                for (int c = 0; c < 3; c++) S += R[3 * a + c] * s2[c] * R[3 * b + c];
+                v += S * e[b];
+            }
+            means[(size_t)a * N + i] += scale * gate * v;
+        }
+    }
+}

@@ -150,6 +150,23 @@ int or_ba_normal_residual(int Pt, const double* X, int ncam, const double* viewm
                           const double* obs_xy, double delta, double near_plane, double lambda,
                           const double* d, double* out);
 
+/* MCMC relocation of dead Gaussians (opacity <= t_dead) onto live ones drawn
+ * with probability proportional to opacity (integer weights floor(o 2^24),
+ * draws floor(u_j W) given by u[N]); the n copies of a source take opacity
+ * 1 - (1 - o)^(1/n) and their scale is multiplied by o / sum_i sum_k
+ * C(i-1,k) (-1)^k o'^(k+1) / sqrt(k+1), with n capped at 51 in both rules;
+ * moments of sources and copies reset.
+ * In place on the planar arrays; exp_avg / exp_avg_sq: the five moment arrays
+ * of each.  src[N] = source of each relocated Gaussian, -1 otherwise. */
+int or_mcmc_relocate(long long N, int sh_degree, double* means, double* log_scales, double* quats,
+                     double* opacity_logit, double* sh, double* const* exp_avg,
+                     double* const* exp_avg_sq, const double* u, double t_dead, long long* src,
+                     long long* n_relocated);
+
+/* MCMC noise on the means: mu += scale sigmoid(-k (o - t)) Sigma eta. */
+void or_mcmc_noise(long long N, double* means, const double* log_scales, const double* quats,
+                   const double* opacity_logit, const double* eta, double scale, double k, double t);
+
 /* Real spherical-harmonic basis (Condon-Shortley phase) at unit direction d,
  * K = (deg+1)^2 values; dY[K][3] = gradient of the polynomial form, may be
  * NULL. */

@@ -12,7 +12,8 @@ from . import _lib
 from ._lib import (BundleAdjuster, Cameras, Context, GsError, default_settings, gs_adam_step, gs_bin_sort,
                    gs_l1_loss_grad, gs_pose_compose, gs_pose_compose_bwd, gs_project,
                    gs_project_bwd, gs_project_bwd_adam, gs_raster_bwd, gs_render_bwd, gs_render_fwd,
-                   gs_ba_lm_step, gs_init_gaussians, gs_photo_loss_grad, gs_step_advance, load, track_point_index,
+                   gs_ba_lm_step, gs_init_gaussians, gs_mcmc_noise, gs_mcmc_relocate,
+                   gs_photo_loss_grad, gs_step_advance, load, track_point_index,
                    track_reproj_fwd_bwd)
 
 __all__ = [
@@ -20,5 +21,5 @@ __all__ = [
     "gs_render_fwd", "gs_render_bwd", "gs_raster_bwd", "gs_project_bwd", "gs_l1_loss_grad", "track_reproj_fwd_bwd",
     "gs_pose_compose", "gs_pose_compose_bwd", "gs_adam_step", "gs_project_bwd_adam", "track_point_index",
     "gs_step_advance", "gs_photo_loss_grad", "gs_init_gaussians", "BundleAdjuster",
-    "gs_ba_lm_step",
+    "gs_ba_lm_step", "gs_mcmc_relocate", "gs_mcmc_noise",
 ]

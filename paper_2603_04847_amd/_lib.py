@@ -83,7 +83,8 @@ EXPORTS = [
     "gs_render_bwd", "gs_raster_bwd", "gs_project_bwd", "gs_l1_loss_grad", "track_reproj_fwd_bwd", "gs_pose_compose",
     "gs_pose_compose_bwd", "gs_adam_step", "gs_project_bwd_adam", "track_point_index",
     "gs_step_advance", "gs_ctx_generation", "track_reproj_fwd_bwd_noalloc", "gs_photo_loss_grad",
-    "gs_init_gaussians", "gs_ba_create", "gs_ba_destroy", "gs_ba_lm_step",
+    "gs_init_gaussians", "gs_ba_create", "gs_ba_destroy", "gs_ba_lm_step", "gs_mcmc_relocate",
+    "gs_mcmc_noise",
 ]
 
 _lib = None
@@ -138,6 +139,10 @@ def load():
         c_vp, c_vp, ctypes.c_int32, c_vp, c_vp, ctypes.c_int32, c_vp, c_vp, c_vp, ctypes.c_int32,
         ctypes.c_float, ctypes.c_float, ctypes.c_float, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
         c_vp, c_vp]
+    lib.gs_mcmc_relocate.argtypes = [c_vp, ctypes.POINTER(gs_gaussian_adam), ctypes.c_int32,
+                                     ctypes.c_int32, c_vp, ctypes.c_float, c_vp, c_vp, c_vp]
+    lib.gs_mcmc_noise.argtypes = [c_vp, c_vp, c_vp, c_vp, ctypes.c_int32, c_vp, ctypes.c_float,
+                                  ctypes.c_float, ctypes.c_float, c_vp]
     lib.gs_ba_create.argtypes = [ctypes.POINTER(c_vp), ctypes.c_int64, ctypes.c_int32]
     lib.gs_ba_destroy.argtypes = [c_vp]
     lib.gs_ba_lm_step.argtypes = [c_vp, c_vp, ctypes.c_int32, c_vp, c_vp, ctypes.c_int32, c_vp, c_vp,
@@ -373,6 +378,29 @@ def gs_l1_loss_grad(ctx, cams, rgb, target, v_rgb, loss, stream=None):
     _check("gs_l1_loss_grad", load().gs_l1_loss_grad(ctx.handle, ctypes.byref(cams.struct),
                                                      _ptr(rgb), _ptr(target), _ptr(v_rgb),
                                                      _ptr(loss), _stream(stream)))
+
+
+def gs_mcmc_relocate(ctx, params, exp_avg, exp_avg_sq, sh_degree, u, dead_opacity=0.005,
+                     src=None, n_relocated=None, stream=None):
+    """params / exp_avg / exp_avg_sq: the five planar Gaussian tensors (means,
+    log_scales, quats, opacity_logit, sh) and their moments, updated in place;
+    u: [N] uniforms in [0, 1) (device)."""
+    a = gs_gaussian_adam()
+    for q in range(5):
+        a.params[q] = _ptr(params[q])
+        a.exp_avg[q] = _ptr(exp_avg[q])
+        a.exp_avg_sq[q] = _ptr(exp_avg_sq[q])
+        a.lr[q] = 0.0
+    _check("gs_mcmc_relocate", load().gs_mcmc_relocate(
+        ctx.handle, ctypes.byref(a), int(params[3].shape[0]), int(sh_degree), _ptr(u),
+        float(dead_opacity), _ptr(src), _ptr(n_relocated), _stream(stream)))
+
+
+def gs_mcmc_noise(means, log_scales, quats, opacity_logit, eta, scale, k=100.0, t=0.005,
+                  stream=None):
+    _check("gs_mcmc_noise", load().gs_mcmc_noise(
+        _ptr(means), _ptr(log_scales), _ptr(quats), _ptr(opacity_logit), int(means.shape[1]),
+        _ptr(eta), float(scale), float(k), float(t), _stream(stream)))
 
 
 class BundleAdjuster:

@@ -15,7 +15,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libgs_hip.so")
 BUILD = os.path.join(ROOT, "_build")
 SOURCES = ["gs_api.hip", "sort.hip", "bin.hip", "project.hip", "raster.hip", "track.hip",
-           "optim.hip", "noalloc.hip", "photo.hip", "init.hip", "ba.hip"]
+           "optim.hip", "noalloc.hip", "photo.hip", "init.hip", "ba.hip", "mcmc.hip"]
 ARCH = os.environ.get("GS_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",

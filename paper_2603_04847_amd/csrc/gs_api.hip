@@ -3,6 +3,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <cmath>
 #include <stdlib.h>
 #include <string.h>
 
@@ -436,6 +437,32 @@ gs_status gs_photo_loss_grad(gs_ctx* h, const gs_cameras* cams, const float* rgb
     if ((r = check_cams(h->c, cams, false)) != GS_OK) return r;
     const gs::ViewTable vt = gs::make_view_table(cams->wh, cams->V, 16, 16, cams->index);
     return from_hip(gs::launch_photo(&h->c, vt, rgb, target, lambda_ssim, v_rgb, loss, (hipStream_t)stream));
+}
+
+gs_status gs_mcmc_relocate(gs_ctx* h, const gs_gaussian_adam* state, int32_t N, int32_t sh_degree,
+                           const float* u, float dead_opacity, int32_t* src, int32_t* n_relocated,
+                           void* stream) {
+    if (!h || !state || N < 0) return GS_ERR_INVALID_ARG;
+    if (sh_degree < 0 || sh_degree > 3) return GS_ERR_UNSUPPORTED;
+    if (!(dead_opacity >= 0.f && dead_opacity < 1.f)) return GS_ERR_INVALID_ARG;
+    if (N > 0) {
+        if (!u) return GS_ERR_INVALID_ARG;
+        for (int q = 0; q < 5; q++)
+            if (!state->params[q] || !state->exp_avg[q] || !state->exp_avg_sq[q]) return GS_ERR_INVALID_ARG;
+    }
+    if ((int64_t)N > h->c.cap.max_pairs) return GS_ERR_CAPACITY;
+    return from_hip(gs::launch_mcmc_relocate(&h->c, state, N, sh_degree, u, dead_opacity, src, n_relocated,
+                                             (hipStream_t)stream));
+}
+
+gs_status gs_mcmc_noise(float* means, const float* log_scales, const float* quats,
+                        const float* opacity_logit, int32_t N, const float* eta, float scale, float k,
+                        float t, void* stream) {
+    if (N < 0 || (N > 0 && (!means || !log_scales || !quats || !opacity_logit || !eta)))
+        return GS_ERR_INVALID_ARG;
+    if (!std::isfinite(scale) || !std::isfinite(k) || !std::isfinite(t)) return GS_ERR_INVALID_ARG;
+    return from_hip(gs::launch_mcmc_noise(means, log_scales, quats, opacity_logit, N, eta, scale, k, t,
+                                          (hipStream_t)stream));
 }
 
 gs_status gs_init_gaussians(gs_ctx* h, const float* points, const float* rgb, int32_t n, int32_t k,

@@ -466,6 +466,14 @@ hipError_t launch_init_gaussians(Ctx* c, const float* pts, const float* rgb, int
                                  float opacity, int sh_degree, float* means, float* log_scales,
                                  float* quats, float* logit, float* sh, hipStream_t st);
 
+// mcmc.hip: relocation of dead Gaussians and noise on the means
+hipError_t launch_mcmc_relocate(Ctx* c, const gs_gaussian_adam* state, int N, int sh_degree,
+                                const float* u, float t_dead, int32_t* src, int32_t* n_moved,
+                                hipStream_t st);
+hipError_t launch_mcmc_noise(float* means, const float* log_scales, const float* quats,
+                             const float* logit, int N, const float* eta, float scale, float k, float t,
+                             hipStream_t st);
+
 // ba.hip: one Levenberg-Marquardt step of bundle adjustment
 struct BaInputs {
     const float* X;

@@ -1,0 +1,133 @@
+"""MCMC densification (Sec. 3.3 stochastic density control; Algorithm 1,
+MCMCDensify) through the C ABI against the FP64 oracle, with the random
+numbers passed in: the draws (integer decisions) bit-exact, copies bit-exact,
+the opacity and scale rule to float rounding, moments zeroed where touched and
+unchanged elsewhere; growth through dead slots; the noise on the means; and
+the large scene's 5M Gaussians."""
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+KEYS = ("means", "log_scales", "quats", "opacity_logit", "sh")
+
+
+@pytest.fixture(scope="module")
+def gs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_04847_amd as P
+    P.load()
+    return P
+
+
+def _t(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype)
+
+
+def _state(rng, N, deg, dead_frac):
+    K = (deg + 1) ** 2
+    g = dict(means=rng.normal(size=(3, N)), log_scales=rng.normal(-3, 0.3, (3, N)),
+             quats=rng.normal(size=(4, N)), opacity_logit=rng.normal(0, 2, N),
+             sh=rng.normal(0, 0.2, (K, 3, N)))
+    g["opacity_logit"][rng.uniform(size=N) < dead_frac] = -9.0
+    g["opacity_logit"][:3] = 6.0                      # three very opaque ones, drawn often
+    g = {k: v.astype(np.float32) for k, v in g.items()}
+    m1 = {k: rng.normal(size=v.shape).astype(np.float32) for k, v in g.items()}
+    m2 = {k: rng.uniform(size=v.shape).astype(np.float32) for k, v in g.items()}
+    return g, m1, m2
+
+
+def _relocate(gs, g, m1, m2, u, deg):
+    N = g["opacity_logit"].shape[0]
+    ctx = gs.Context(max_pairs=N, max_isect=1 << 10, max_tiles=16, max_views=1)
+    P = [_t(g[k]) for k in KEYS]
+    A = [_t(m1[k]) for k in KEYS]
+    B = [_t(m2[k]) for k in KEYS]
+    src = torch.empty(N, dtype=torch.int32, device="cuda")
+    n = torch.zeros(1, dtype=torch.int32, device="cuda")
+    gs.gs_mcmc_relocate(ctx, P, A, B, deg, _t(u), 0.005, src=src, n_relocated=n)
+    torch.cuda.synchronize()
+    h = lambda L: {k: t.cpu().numpy() for k, t in zip(KEYS, L)}
+    return h(P), h(A), h(B), src.cpu().numpy(), int(n.item())
+
+
+def _compare(g, m1, m2, u, deg, got):
+    G, A, B, src, n = got
+    OG, (OA, OB), osrc, on = oracle.mcmc_relocate(g, (m1, m2), u.astype(np.float64), deg)
+    assert np.array_equal(src, osrc) and n == on
+    moved = src >= 0
+    sources = np.zeros(src.shape, bool)
+    sources[src[moved]] = True
+    touched = moved | sources
+    for k in ("means", "quats", "sh"):
+        assert np.array_equal(G[k], OG[k].astype(np.float32)), k      # copies, bit for bit
+    np.testing.assert_allclose(G["opacity_logit"], OG["opacity_logit"], rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(G["log_scales"], OG["log_scales"], rtol=1e-6, atol=1e-6)
+    for k in KEYS:
+        assert not np.any(A[k][..., touched]) and not np.any(B[k][..., touched]), k
+        assert np.array_equal(A[k][..., ~touched], m1[k][..., ~touched]), k
+        assert np.array_equal(B[k][..., ~touched], m2[k][..., ~touched]), k
+    return n, sources
+
+
+def test_mcmc_relocate_matches_oracle(gs):
+    rng = np.random.default_rng(70)
+    N, deg = 20000, 3
+    g, m1, m2 = _state(rng, N, deg, 0.3)
+    u = rng.uniform(size=N).astype(np.float32)
+    n, sources = _compare(g, m1, m2, u, deg, _relocate(gs, g, m1, m2, u, deg))
+    assert n > 5000 and sources[:3].all()
+
+
+def test_mcmc_grow_through_dead_slots(gs):
+    """Growing the set: the arrays are enlarged with dead slots, and the
+    relocation fills them with copies drawn by opacity."""
+    rng = np.random.default_rng(71)
+    N, add, deg = 3000, 600, 1
+    g, m1, m2 = _state(rng, N, deg, 0.0)
+    pad = lambda a, v: np.concatenate([a, np.full(a.shape[:-1] + (add,), v, np.float32)], axis=-1)
+    g2 = {k: pad(v, -20.0 if k == "opacity_logit" else 0.0) for k, v in g.items()}
+    m12 = {k: pad(v, 0.0) for k, v in m1.items()}
+    m22 = {k: pad(v, 0.0) for k, v in m2.items()}
+    u = rng.uniform(size=N + add).astype(np.float32)
+    n, _ = _compare(g2, m12, m22, u, deg, _relocate(gs, g2, m12, m22, u, deg))
+    assert n == add
+
+
+def test_mcmc_noise_matches_oracle(gs):
+    rng = np.random.default_rng(72)
+    N = 10000
+    g, _, _ = _state(rng, N, 0, 0.2)
+    o = rng.uniform(0.0, 0.05, N)
+    g["opacity_logit"] = np.log(o / (1 - o)).astype(np.float32)
+    eta = rng.normal(size=(3, N)).astype(np.float32)
+    means = _t(g["means"])
+    gs.gs_mcmc_noise(means, _t(g["log_scales"]), _t(g["quats"]), _t(g["opacity_logit"]), _t(eta),
+                     5e5 * 1.6e-4)
+    torch.cuda.synchronize()
+    want = oracle.mcmc_noise(g, eta, scale=5e5 * 1.6e-4)
+    d_gpu = means.cpu().numpy().astype(np.float64) - g["means"]
+    d_or = want - g["means"]
+    assert np.max(np.abs(d_gpu - d_or)) <= 1e-4 * np.max(np.abs(d_or)) + 1e-6
+
+
+def test_mcmc_relocate_large_scene(gs):
+    """The large scene's 5M Gaussians (SH degree 3) with a fifth of them dead."""
+    sc = scenegen.make_config("C5")
+    rng = np.random.default_rng(73)
+    g = {k: np.ascontiguousarray(sc[k]) for k in KEYS}
+    N = g["opacity_logit"].shape[0]
+    g["opacity_logit"] = g["opacity_logit"].copy()
+    g["opacity_logit"][rng.uniform(size=N) < 0.2] = -9.0
+    m1 = {k: np.zeros_like(v) for k, v in g.items()}
+    m2 = {k: np.zeros_like(v) for k, v in g.items()}
+    u = rng.uniform(size=N).astype(np.float32)
+    got = _relocate(gs, g, m1, m2, u, 3)
+    n, _ = _compare(g, m1, m2, u, 3, got)
+    assert n > 0.19 * N

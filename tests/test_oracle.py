@@ -1050,3 +1050,133 @@ def test_ba_normal_residual_matches_the_dense_system():
     dtw, dX, _ = oracle.ba_step(X, vm, intr, cam, pt, xy, lm_lambda=0.3)
     rc, rp = oracle.ba_normal_residual(X, vm, intr, cam, pt, xy, dtw, dX, lm_lambda=0.3)
     assert np.max(np.abs(np.concatenate([rc.reshape(-1), rp.reshape(-1)]))) <= 1e-9 * np.abs(g).max()
+
+
+# ----------------------------------------------------------------- MCMC relocation and noise
+
+def _mcmc_scene(N, rng, sh_degree=1, logit=None):
+    K = (sh_degree + 1) ** 2
+    g = dict(means=rng.normal(size=(3, N)), log_scales=rng.normal(-3, 0.3, (3, N)),
+             quats=rng.normal(size=(4, N)), opacity_logit=rng.normal(0, 2, N) if logit is None else logit,
+             sh=rng.normal(0, 0.2, (K, 3, N)))
+    m1 = {k: rng.normal(size=v.shape) for k, v in g.items()}
+    m2 = {k: rng.uniform(size=v.shape) for k, v in g.items()}
+    return g, (m1, m2)
+
+
+@pytest.mark.parametrize("o", [0.05, 0.3, 0.9])
+@pytest.mark.parametrize("n", [1, 2, 3, 6])
+def test_mcmc_copies_keep_centre_opacity_and_axis_integral(o, n):
+    # one live Gaussian (opacity o) and n - 1 dead ones: all move onto it, so
+    # n copies share it; their combined opacity at the centre is o, and the
+    # integral of the combined opacity along an axis equals o sigma sqrt(2 pi)
+    from scipy.integrate import quad
+    rng = np.random.default_rng(n)
+    logit = np.concatenate([[np.log(o / (1 - o))], np.full(n - 1, -8.0)])
+    g, mom = _mcmc_scene(n, rng, logit=logit)
+    u = rng.uniform(size=n)
+    G, M, src, moved = oracle.mcmc_relocate(g, mom, u, 1)
+    assert moved == n - 1 and np.all(src[1:] == 0) and src[0] == -1
+    op = 1 / (1 + np.exp(-G["opacity_logit"]))
+    np.testing.assert_allclose(op, op[0], rtol=1e-12)
+    assert abs(1 - (1 - op[0]) ** n - o) < 1e-12
+    f = np.exp(G["log_scales"][0, 0] - g["log_scales"][0, 0])
+    sig = 0.7
+    integ, _ = quad(lambda x: 1 - (1 - op[0] * np.exp(-x * x / (2 * (sig * f) ** 2))) ** n, -np.inf, np.inf,
+                    epsabs=1e-13, epsrel=1e-12)
+    assert abs(integ - o * sig * np.sqrt(2 * np.pi)) <= 1e-9
+    # copies carry the source; every touched moment restarts at zero
+    for k in ("means", "quats", "sh", "log_scales"):
+        assert np.all(G[k][..., 1:] == G[k][..., :1]), k
+    np.testing.assert_array_equal(G["means"][:, 0], g["means"][:, 0])
+    if n > 1:
+        for k in M[0]:
+            assert np.all(M[0][k] == 0) and np.all(M[1][k] == 0), k
+
+
+def test_mcmc_draws_follow_the_integer_opacity_weights():
+    rng = np.random.default_rng(60)
+    N = 4000
+    g, mom = _mcmc_scene(N, rng)
+    o = 1 / (1 + np.exp(-g["opacity_logit"]))
+    dead = o <= 0.005
+    g["opacity_logit"][rng.choice(N, 1500, replace=False)] = -9.0    # many dead ones
+    o = 1 / (1 + np.exp(-g["opacity_logit"]))
+    dead = o <= 0.005
+    u = rng.uniform(size=N)
+    G, M, src, moved = oracle.mcmc_relocate(g, mom, u, 1)
+    assert moved == dead.sum()
+    # independent draw: numpy cumulative sum of the integer weights
+    w = np.where(dead, 0, np.floor(o * 2 ** 24)).astype(np.int64)
+    cdf = np.cumsum(w)
+    want = np.searchsorted(cdf, np.floor(u * float(cdf[-1])).astype(np.int64), side="right")
+    np.testing.assert_array_equal(src[dead], want[dead])
+    assert np.all(src[~dead] == -1)
+    # never a dead source; the untouched live Gaussians keep everything
+    assert not np.any(dead[src[dead]])
+    untouched = ~dead & ~np.isin(np.arange(N), src[dead])
+    for k in g:
+        np.testing.assert_array_equal(G[k][..., untouched], g[k][..., untouched])
+        np.testing.assert_array_equal(M[0][k][..., untouched], mom[0][k][..., untouched])
+
+
+def test_mcmc_draw_frequencies_match_opacity():
+    # 200k draws onto 5 live Gaussians: frequencies within 5 sigma of o / sum o
+    # (each source far past the cap of 51 copies in the opacity rule)
+    rng = np.random.default_rng(61)
+    logit = np.concatenate([[-2.0, -0.5, 0.0, 1.0, 3.0], np.full(200_000, -9.0)])
+    g, mom = _mcmc_scene(logit.size, rng, sh_degree=0, logit=logit)
+    G, M, src, moved = oracle.mcmc_relocate(g, mom, rng.uniform(size=logit.size), 0)
+    o = 1 / (1 + np.exp(-logit[:5]))
+    p = o / o.sum()
+    cnt = np.bincount(src[5:], minlength=5)
+    assert np.all(np.abs(cnt - 200_000 * p) <= 5 * np.sqrt(200_000 * p * (1 - p)))
+
+
+def test_mcmc_nothing_to_move():
+    rng = np.random.default_rng(62)
+    g, mom = _mcmc_scene(50, rng, logit=np.full(50, 1.0))          # all alive
+    G, M, src, moved = oracle.mcmc_relocate(g, mom, rng.uniform(size=50), 1)
+    assert moved == 0 and np.all(src == -1)
+    g, mom = _mcmc_scene(50, rng, logit=np.full(50, -9.0))         # all dead
+    G, M, src, moved = oracle.mcmc_relocate(g, mom, rng.uniform(size=50), 1)
+    assert moved == 0
+    for k in g:
+        np.testing.assert_array_equal(G[k], g[k])
+
+
+def test_mcmc_noise_closed_form():
+    rng = np.random.default_rng(63)
+    N = 40
+    # opacities around the dead threshold, where the gate is neither 0 nor 1
+    o0 = rng.uniform(0.001, 0.03, N)
+    g, _ = _mcmc_scene(N, rng, logit=np.log(o0 / (1 - o0)))
+    g["quats"] = np.tile([[2.0], [0.0], [0.0], [0.0]], (1, N))        # identity rotation
+    s = np.exp(rng.normal(-2, 0.2, N))
+    g["log_scales"] = np.tile(np.log(s), (3, 1))
+    eta = rng.normal(size=(3, N))
+    out = oracle.mcmc_noise(g, eta, scale=3.0, k=100.0, t=0.005)
+    o = 1 / (1 + np.exp(-g["opacity_logit"]))
+    gate = 1 / (1 + np.exp(100 * (o - 0.005)))
+    np.testing.assert_allclose(out - g["means"], 3.0 * gate * s ** 2 * eta, rtol=1e-9, atol=1e-15)
+    # a rotated anisotropic Gaussian: the displacement is Sigma eta
+    g2 = dict(g)
+    R = Rotation.random(random_state=3)
+    qx, qy, qz, qw = R.as_quat()
+    g2["quats"] = np.tile([[qw], [qx], [qy], [qz]], (1, N))
+    ls = np.log(np.array([0.1, 0.02, 0.3]))
+    g2["log_scales"] = np.tile(ls[:, None], (1, N))
+    out = oracle.mcmc_noise(g2, eta, scale=1.0)
+    Sig = R.as_matrix() @ np.diag(np.exp(2 * ls)) @ R.as_matrix().T
+    np.testing.assert_allclose(out - g2["means"], (Sig @ eta) * gate, rtol=1e-10, atol=1e-15)
+
+
+def test_mcmc_copy_count_cap():
+    # 60 dead Gaussians onto one live one: 61 copies, the opacity rule at n = 51
+    rng = np.random.default_rng(64)
+    o = 0.6
+    g, mom = _mcmc_scene(61, rng, logit=np.concatenate([[np.log(o / (1 - o))], np.full(60, -9.0)]))
+    G, M, src, moved = oracle.mcmc_relocate(g, mom, rng.uniform(size=61), 1)
+    assert moved == 60
+    op = 1 / (1 + np.exp(-G["opacity_logit"]))
+    np.testing.assert_allclose(op, 1 - (1 - o) ** (1 / 51), rtol=1e-12)
