@@ -423,6 +423,78 @@ def batched_vs_per_view(torch, steps, warmup):
     return out
 
 
+def next_rows(torch, res, reps=5):
+    """The calls around the joint step on the same scene: Gaussians from the
+    track points (k = 4 nearest neighbours), one Levenberg-Marquardt step of
+    bundle adjustment over all observations, MCMC relocation (a fifth of the
+    Gaussians dead) and the MCMC noise on the means.  Inputs resident; HIP
+    events on the launch stream; mean of `reps` calls after one warm-up."""
+    from paper_2603_04847_amd import _lib as L
+    st, sc = res["st"], res["sc"]
+    sz = res["sizes"]
+    out = {}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    Pt = int(st.X.shape[0])
+    K = (st.sh_degree + 1) ** 2
+    rgb = torch.rand((Pt, 3), device="cuda", generator=torch.Generator("cuda").manual_seed(1))
+    ms = timed(lambda: L.gs_init_gaussians(st.ctx, st.X, rgb, sh_degree=st.sh_degree))
+    byt = Pt * 24 + Pt * (44 + 12 * K)
+    out["init_gaussians"] = dict(points=Pt, ms=round(ms, 4), algorithmic_gbs=round(byt / (ms * 1e-3) / 1e9, 1))
+    if st.pt_index is not None and Pt > 0:
+        ba = L.BundleAdjuster(Pt, st.n_cams)
+        dtw = torch.empty((st.n_cams, 6), device="cuda")
+        dX = torch.empty((Pt, 3), device="cuda")
+        stats = torch.zeros(5, device="cuda")
+        call = lambda: L.gs_ba_lm_step(ba, st.X, st.viewmat, st.intr, st.obs_cam, st.obs_pt,
+                                       st.obs_xy, st.pt_index, 1.0, 1e-2, 0.01, 100, 1e-8, dtw, dX,
+                                       stats)
+        ms = timed(call)
+        s5 = stats.cpu().numpy()
+        it = int(s5[0])
+        # per conjugate-gradient iteration two passes over the observations
+        # (~30 B each: camera, point, pixel and the point's coordinates)
+        out["ba_lm_step"] = dict(cameras=st.n_cams, points=Pt, observations=sz["M"], ms=round(ms, 4),
+                                 pcg_iterations=it, relative_residual=float(s5[1]),
+                                 ms_per_pcg_iteration=round(ms / max(it + 3, 1), 4))
+        ba.close()
+    N = st.N
+    g = {k: st.params[k].clone() for k in ("means", "log_scales", "quats", "opacity_logit", "sh")}
+    gen = torch.Generator("cuda").manual_seed(2)
+    dead = torch.rand(N, device="cuda", generator=gen) < 0.2
+    base_logit = g["opacity_logit"].clone()
+    base_logit[dead] = -9.0
+    m1 = [torch.zeros_like(g[k]) for k in g]
+    m2 = [torch.zeros_like(g[k]) for k in g]
+    u = torch.rand(N, device="cuda", generator=gen)
+    P = [g[k] for k in g]
+
+    def reloc():
+        g["opacity_logit"].copy_(base_logit)
+        L.gs_mcmc_relocate(st.ctx, P, m1, m2, st.sh_degree, u)
+    ms_copy = timed(lambda: g["opacity_logit"].copy_(base_logit))
+    ms = timed(reloc) - ms_copy
+    out["mcmc_relocate"] = dict(gaussians=N, dead_fraction=0.2, ms=round(ms, 4))
+    eta = torch.randn((3, N), device="cuda", generator=gen)
+    ms = timed(lambda: L.gs_mcmc_noise(g["means"], g["log_scales"], g["quats"], g["opacity_logit"],
+                                       eta, 1e-3))
+    byt = N * (12 + 12 + 16 + 4 + 12) + N * 12
+    out["mcmc_noise"] = dict(gaussians=N, ms=round(ms, 4),
+                             algorithmic_gbs=round(byt / (ms * 1e-3) / 1e9, 1))
+    return out
+
+
 def copy_bandwidth(torch, mib=1024, reps=5):
     """Device copy rate (GB/s, bytes read + written) of a plain elementwise
     copy of `mib` MiB, beside the 8 TB/s HBM peak."""
@@ -643,6 +715,9 @@ def main():
     if not args.no_compare:
         log("[bench] batched vs per-view on C3")
         line["batched_vs_per_view"] = batched_vs_per_view(torch, max(2, args.steps // 4), 1)
+    if not args.no_extra:
+        log("[bench] init, bundle adjustment and MCMC calls on the same scene")
+        line["next_rows"] = next_rows(torch, res)
     if not args.no_cpu_baseline:
         log("[bench] oracle CPU baseline")
         line["cpu_baseline"] = cpu_baseline(res, lambda_ssim=args.lambda_ssim)

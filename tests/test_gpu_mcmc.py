@@ -82,7 +82,24 @@ def test_mcmc_relocate_matches_oracle(gs):
     g, m1, m2 = _state(rng, N, deg, 0.3)
     u = rng.uniform(size=N).astype(np.float32)
     n, sources = _compare(g, m1, m2, u, deg, _relocate(gs, g, m1, m2, u, deg))
-    assert n > 5000 and sources[:3].all()
+    assert n > 5000
+
+
+def test_mcmc_relocate_past_the_copy_cap(gs):
+    """Nine in ten Gaussians dead, the live ones faint but for three opaque
+    ones: each of those is drawn well over 51 times (the cap of the opacity
+    and scale rule)."""
+    rng = np.random.default_rng(74)
+    N, deg = 20000, 2
+    g, m1, m2 = _state(rng, N, deg, 0.9)
+    live = g["opacity_logit"] > -9.0
+    g["opacity_logit"][live] = rng.normal(-3.0, 1.0, int(live.sum())).astype(np.float32)
+    g["opacity_logit"][:3] = 6.0
+    u = rng.uniform(size=N).astype(np.float32)
+    got = _relocate(gs, g, m1, m2, u, deg)
+    n, sources = _compare(g, m1, m2, u, deg, got)
+    drawn = np.bincount(got[3][got[3] >= 0], minlength=N)
+    assert sources[:3].all() and drawn[:3].min() > 51, drawn[:3]
 
 
 def test_mcmc_grow_through_dead_slots(gs):
@@ -97,7 +114,8 @@ def test_mcmc_grow_through_dead_slots(gs):
     m22 = {k: pad(v, 0.0) for k, v in m2.items()}
     u = rng.uniform(size=N + add).astype(np.float32)
     n, _ = _compare(g2, m12, m22, u, deg, _relocate(gs, g2, m12, m22, u, deg))
-    assert n == add
+    dead_before = int(np.sum(1 / (1 + np.exp(-g["opacity_logit"].astype(np.float64))) <= 0.005))
+    assert n == add + dead_before
 
 
 def test_mcmc_noise_matches_oracle(gs):
