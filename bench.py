@@ -390,7 +390,7 @@ def batched_vs_per_view(torch, steps, warmup):
         if ctx is None:
             cand[f"{tile[0]}x{tile[1]}"] = "lists exceed the capacity limit"
             continue
-        for order in (0, 1):
+        for order in (0, 1, 2):
             s = L.default_settings(tile_w=tile[0], tile_h=tile[1], tile_order=order)
             ms = timed(lambda: batched(ctx, s), max(2, steps // 2))
             cand[f"{tile[0]}x{tile[1]}/{order}"] = round(ms, 3)

@@ -121,7 +121,12 @@ typedef struct {
                                  the tiles heaviest first: by decreasing bucket of the
                                  list length, 16 buckets per octave (bucket of n > 0:
                                  1 + 16 floor(log2 n) + the 4 bits after n's leading
-                                 bit; 0 for an empty list), any order inside a bucket */
+                                 bit; 0 for an empty list), any order inside a bucket;
+                                 2: tiles walked by 4x4 blocks, each block's 16 tiles on
+                                 consecutive workgroups of one XCD (workgroups are dealt
+                                 round-robin over the 8 XCDs), so neighbouring tiles read
+                                 their shared splats through one L2.  The image does not
+                                 depend on the order */
     int32_t eval_stats;       /* 0; 1: gs_render_fwd also counts per tile the contributing
                                  pairs, list entries read and (pixel, splat) evaluations
                                  (gs_ctx_tile_stats), a slower variant */

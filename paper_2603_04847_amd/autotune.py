@@ -22,7 +22,7 @@ def _need(step, b):
     return st["n_isect_needed"]
 
 
-def autotune(step, shapes=TILE_SHAPES, orders=(0, 1), iters=3, big=None):
+def autotune(step, shapes=TILE_SHAPES, orders=(0, 1, 2), iters=3, big=None):
     """Time each (tile shape, order) on `step` (a JointStep) over every batch
     of views (`iters` rounds; their loads differ) and leave the fastest in
     step.settings with a tight capacity.  A shape whose lists do not fit the

@@ -51,6 +51,7 @@ RasterParams make_raster_params(const gs_settings* s) {
     rp.tile_w = s->tile_w;
     rp.tile_h = s->tile_h;
     rp.eval_stats = s->eval_stats;
+    rp.tile_order = s->tile_order;
     return rp;
 }
 
@@ -68,6 +69,7 @@ bool tile_ok(int tw, int th) {
 gs_status check_settings(const gs_settings* s) {
     if (!s) return GS_ERR_INVALID_ARG;
     if (!tile_ok(s->tile_w, s->tile_h)) return GS_ERR_UNSUPPORTED;
+    if (s->tile_order < 0 || s->tile_order > 2) return GS_ERR_INVALID_ARG;
     if (!(s->alpha_min > 0.f && s->alpha_min < s->alpha_max && s->alpha_max < 1.f) ||
         !(s->t_min > 0.f && s->t_min < 1.f) || !(s->near_plane > 0.f) || !(s->eps2d >= 0.f) ||
         !(s->fov_pad >= 0.f))
@@ -311,7 +313,8 @@ gs_status gs_bin_sort(gs_ctx* h, const gs_cameras* cams, int32_t N, const gs_set
     if (vt.tile_off[vt.V] > h->c.cap.max_tiles) return GS_ERR_CAPACITY;
     const gs::RasterParams rp = gs::make_raster_params(s);
     h->c.generation++;
-    return from_hip(gs::launch_bin(&h->c, vt, N, rp, records, s->tile_order, (hipStream_t)stream));
+    // only the heaviest-first order needs a permutation of the tiles
+    return from_hip(gs::launch_bin(&h->c, vt, N, rp, records, s->tile_order == 1, (hipStream_t)stream));
 }
 
 static gs_status check_bins_match(const gs::Ctx& c, const gs_cameras* cams, const gs_settings* s) {

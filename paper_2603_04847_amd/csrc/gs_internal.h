@@ -29,6 +29,7 @@ struct RasterParams {
     float near_plane, eps2d, fov_pad;
     int tile_w, tile_h;
     int eval_stats;
+    int tile_order;
 };
 
 // Device status words (one array in the context).

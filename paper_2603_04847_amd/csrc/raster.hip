@@ -59,6 +59,38 @@ struct TileMap {
     }
 };
 
+// The tile of this workgroup.  Orders 0 and 1 number the workgroups like the
+// tiles (1 through the heaviest-first permutation).  Order 2 is for the L2
+// caches: workgroups are dealt round-robin over the chip's 8 XCDs, each with
+// its own L2, so workgroups b, b + 8, b + 16, ... share one.  Tiles are walked
+// block by block (4 x 4 tiles, row-major inside the block) and each block's
+// 16 tiles go to 16 consecutive workgroups of one XCD: neighbouring tiles,
+// which share most of their splats, read them through the same L2.  Returns
+// false for a workgroup whose slot falls outside the view (edge blocks).
+constexpr int kXcds = 8;
+constexpr int kBlockTileCount = kBlockTiles * kBlockTiles;
+
+__device__ __forceinline__ bool block_tile(const uint32_t* order, int mode, const ViewTable& vt, int& t) {
+    const int b = blockIdx.x;
+    if (mode != 2) {
+        t = order ? (int)order[b] : b;
+        return true;
+    }
+    const int x = b % kXcds, j = b / kXcds;
+    const int s = ((j / kBlockTileCount) * kXcds + x) * kBlockTileCount + j % kBlockTileCount;
+    const int gb = s / kBlockTileCount, w = s % kBlockTileCount;
+    if (gb >= vt.block_off[vt.V]) return false;
+    int v = 0;
+    while (v + 1 < vt.V && gb >= vt.block_off[v + 1]) v++;
+    const int lb = gb - vt.block_off[v];
+    const int tx = (lb % vt.bx[v]) * kBlockTiles + w % kBlockTiles;
+    const int ty = (lb / vt.bx[v]) * kBlockTiles + w / kBlockTiles;
+    const int gy = (vt.tile_off[v + 1] - vt.tile_off[v]) / vt.gx[v];
+    if (tx >= vt.gx[v] || ty >= gy) return false;
+    t = vt.tile_off[v] + ty * vt.gx[v] + tx;
+    return true;
+}
+
 // One splat record as a lane loads it: position, opacity, the base-2 conic,
 // colour.
 struct LaneSplat {
@@ -107,10 +139,11 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
                                                    int32_t* __restrict__ out_last,
                                                    int32_t* __restrict__ tile_contrib,
                                                    int32_t* __restrict__ tile_entries,
-                                                   int32_t* __restrict__ tile_evals) {
+                                                   int32_t* __restrict__ tile_evals, int mode) {
     using TM = TileMap<TW, TH>;
     constexpr int PPL = TM::PPL;
-    const int t = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
+    int t;
+    if (!block_tile(order, mode, vt, t)) return;
     const int v = tile_view(vt, t);
     const int lt = t - vt.tile_off[v];
     const int gx = vt.gx[v], W = vt.W[v], H = vt.H[v];
@@ -244,10 +277,11 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ re
                                                    const float* __restrict__ T_final,
                                                    const int32_t* __restrict__ last_in,
                                                    const float* __restrict__ v_rgb,
-                                                   float* __restrict__ grad2d) {
+                                                   float* __restrict__ grad2d, int mode) {
     using TM = TileMap<TW, TH>;
     constexpr int PPL = TM::PPL;
-    const int t = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
+    int t;
+    if (!block_tile(order, mode, vt, t)) return;
     const int v = tile_view(vt, t);
     const int lt = t - vt.tile_off[v];
     const int gx = vt.gx[v], W = vt.W[v], H = vt.H[v];
@@ -422,30 +456,40 @@ __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ rgb,
     }
 }
 
+// workgroups of a raster launch: one per tile, or for the XCD order one per
+// slot of every 4 x 4 block, rounded to whole rounds over the XCDs
+unsigned raster_grid(const Ctx* c, const ViewTable& vt, int mode) {
+    if (mode != 2) return (unsigned)c->n_tiles;
+    const int64_t slots = (int64_t)vt.block_off[vt.V] * kBlockTileCount;
+    const int64_t round = (int64_t)kXcds * kBlockTileCount;
+    return (unsigned)((slots + round - 1) / round * round);
+}
+
 template <int TW, int TH>
 hipError_t fwd_impl(Ctx* c, const ViewTable& vt, const RasterParams& rp, const float* bg,
-                    float* rgb, float* T_final, int32_t* last, const uint32_t* order,
+                    float* rgb, float* T_final, int32_t* last, const uint32_t* order, int mode,
                     hipStream_t st) {
+    const unsigned grid = raster_grid(c, vt, mode);
     if (rp.eval_stats)
-        hipLaunchKernelGGL((k_render_fwd<TW, TH, true>), dim3((unsigned)c->n_tiles), dim3(64), 0, st,
+        hipLaunchKernelGGL((k_render_fwd<TW, TH, true>), dim3(grid), dim3(64), 0, st,
                            reinterpret_cast<const float4*>(c->rec), reinterpret_cast<const int32_t*>(c->tids),
                            c->tranges, order, vt, rp, bg, rgb, T_final, last, c->tile_contrib,
-                           c->tile_entries, c->tile_evals);
+                           c->tile_entries, c->tile_evals, mode);
     else
-        hipLaunchKernelGGL((k_render_fwd<TW, TH, false>), dim3((unsigned)c->n_tiles), dim3(64), 0, st,
+        hipLaunchKernelGGL((k_render_fwd<TW, TH, false>), dim3(grid), dim3(64), 0, st,
                            reinterpret_cast<const float4*>(c->rec), reinterpret_cast<const int32_t*>(c->tids),
                            c->tranges, order, vt, rp, bg, rgb, T_final, last, c->tile_contrib,
-                           c->tile_entries, c->tile_evals);
+                           c->tile_entries, c->tile_evals, mode);
     return hipGetLastError();
 }
 
 template <int TW, int TH>
 hipError_t bwd_impl(Ctx* c, const ViewTable& vt, const RasterParams& rp, const float* bg,
                     const float* T_final, const int32_t* last, const float* v_rgb,
-                    const uint32_t* order, hipStream_t st) {
-    hipLaunchKernelGGL((k_render_bwd<TW, TH>), dim3((unsigned)c->n_tiles), dim3(64), 0, st,
+                    const uint32_t* order, int mode, hipStream_t st) {
+    hipLaunchKernelGGL((k_render_bwd<TW, TH>), dim3(raster_grid(c, vt, mode)), dim3(64), 0, st,
                        reinterpret_cast<const float4*>(c->rec), reinterpret_cast<const int32_t*>(c->tids), c->tranges, order,
-                       vt, rp, bg, T_final, last, v_rgb, c->grad2d);
+                       vt, rp, bg, T_final, last, v_rgb, c->grad2d, mode);
     return hipGetLastError();
 }
 
@@ -455,11 +499,12 @@ hipError_t launch_render_fwd(Ctx* c, const ViewTable& vt, const RasterParams& rp
                              float* rgb, float* T_final, int32_t* last, hipStream_t st) {
     if (c->n_tiles <= 0) return hipSuccess;
     const uint32_t* order = c->ordered ? c->tile_order : nullptr;
+    const int mode = rp.tile_order == 2 ? 2 : (order ? 1 : 0);
     const int TW = rp.tile_w, TH = rp.tile_h;
-    if (TW == 16 && TH == 16) return fwd_impl<16, 16>(c, vt, rp, bg, rgb, T_final, last, order, st);
-    if (TW == 16 && TH == 8) return fwd_impl<16, 8>(c, vt, rp, bg, rgb, T_final, last, order, st);
-    if (TW == 8 && TH == 8) return fwd_impl<8, 8>(c, vt, rp, bg, rgb, T_final, last, order, st);
-    if (TW == 32 && TH == 16) return fwd_impl<32, 16>(c, vt, rp, bg, rgb, T_final, last, order, st);
+    if (TW == 16 && TH == 16) return fwd_impl<16, 16>(c, vt, rp, bg, rgb, T_final, last, order, mode, st);
+    if (TW == 16 && TH == 8) return fwd_impl<16, 8>(c, vt, rp, bg, rgb, T_final, last, order, mode, st);
+    if (TW == 8 && TH == 8) return fwd_impl<8, 8>(c, vt, rp, bg, rgb, T_final, last, order, mode, st);
+    if (TW == 32 && TH == 16) return fwd_impl<32, 16>(c, vt, rp, bg, rgb, T_final, last, order, mode, st);
     return hipErrorInvalidValue;
 }
 
@@ -468,11 +513,12 @@ hipError_t launch_render_bwd(Ctx* c, const ViewTable& vt, const RasterParams& rp
                              hipStream_t st) {
     if (c->n_tiles <= 0) return hipSuccess;
     const uint32_t* order = c->ordered ? c->tile_order : nullptr;
+    const int mode = rp.tile_order == 2 ? 2 : (order ? 1 : 0);
     const int TW = rp.tile_w, TH = rp.tile_h;
-    if (TW == 16 && TH == 16) return bwd_impl<16, 16>(c, vt, rp, bg, T_final, last, v_rgb, order, st);
-    if (TW == 16 && TH == 8) return bwd_impl<16, 8>(c, vt, rp, bg, T_final, last, v_rgb, order, st);
-    if (TW == 8 && TH == 8) return bwd_impl<8, 8>(c, vt, rp, bg, T_final, last, v_rgb, order, st);
-    if (TW == 32 && TH == 16) return bwd_impl<32, 16>(c, vt, rp, bg, T_final, last, v_rgb, order, st);
+    if (TW == 16 && TH == 16) return bwd_impl<16, 16>(c, vt, rp, bg, T_final, last, v_rgb, order, mode, st);
+    if (TW == 16 && TH == 8) return bwd_impl<16, 8>(c, vt, rp, bg, T_final, last, v_rgb, order, mode, st);
+    if (TW == 8 && TH == 8) return bwd_impl<8, 8>(c, vt, rp, bg, T_final, last, v_rgb, order, mode, st);
+    if (TW == 32 && TH == 16) return bwd_impl<32, 16>(c, vt, rp, bg, T_final, last, v_rgb, order, mode, st);
     return hipErrorInvalidValue;
 }
 

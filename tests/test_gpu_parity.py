@@ -347,6 +347,30 @@ def test_tile_order_and_contributor_counts(gs):
         assert ev[t] == want, t
 
 
+@pytest.mark.parametrize("tile", [(16, 16), (16, 8), (8, 8), (32, 16)])
+def test_xcd_launch_order_changes_nothing(gs, tile):
+    """The XCD-grouped launch order (tiles walked by 4x4 blocks, a block per
+    XCD) gives the image, transmittance and contributor indices of the natural
+    order bit for bit, and the same gradients (up to the order of float
+    atomics), over ragged views."""
+    s = scenegen.blob_scene(17, [(203, 150), (96, 64), (130, 77)], 15000, sh_degree=2)
+    s.pop("_rng")
+    outs = []
+    for order in (0, 2):
+        st = gs.default_settings(tile_w=tile[0], tile_h=tile[1], tile_order=order)
+        sp, params, rgb, T, last, cams, ctx = _render(gs, s, settings=st)
+        w = _t(np.random.default_rng(2).normal(size=(cams.n_pixels, 3)))
+        grads, v_tw = sp.backward(params, 2, cams, T, last, w)
+        torch.cuda.synchronize()
+        outs.append((rgb.cpu().numpy(), T.cpu().numpy(), last.cpu().numpy(),
+                     {k: v.cpu().numpy() for k, v in grads.items()}, v_tw.cpu().numpy()))
+    a, b = outs
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    for k in a[3]:
+        _close(b[3][k], a[3][k], rtol=1e-5, what=k)
+    _close(b[4], a[4], rtol=1e-5, what="twist")
+
+
 def test_batched_views_bitwise_equal_per_view(gs):
     s = scenegen.blob_scene(11, [(160, 120), (203, 150), (96, 64)], 20000, sh_degree=3)
     s.pop("_rng")
