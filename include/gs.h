@@ -319,9 +319,12 @@ gs_status gs_photo_loss_grad(gs_ctx* ctx, const gs_cameras* cams, const float* r
  * sh degree-0 band = (rgb - 0.5) 2 sqrt(pi), so the renderer's colour rule
  * gives back rgb; the other bands zero.  Outputs in the planar layout of
  * gs_gaussians (caller-owned device arrays).  The neighbours are exact (a
- * uniform grid searched in growing shells); any of several equidistant
- * neighbours may be taken, which leaves s unchanged.  1 <= k <= GS_INIT_MAX_K;
- * n <= the context's max_pairs (it uses the pair-sized workspace). */
+ * bounding-volume hierarchy over the points in Morton order, searched depth
+ * first and pruned by the k-th distance found so far); any of several
+ * equidistant neighbours may be taken, which leaves s unchanged.  Points must
+ * be finite (a non-finite point is never taken as a neighbour and gets an
+ * undefined scale).  1 <= k <= GS_INIT_MAX_K; n <= the context's max_pairs
+ * (it uses the pair-sized workspace). */
 #define GS_INIT_MAX_K 8
 gs_status gs_init_gaussians(gs_ctx* ctx, const float* points, const float* rgb, int32_t n,
                             int32_t k, float opacity, int32_t sh_degree, float* means,

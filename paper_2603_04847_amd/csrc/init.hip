@@ -2,18 +2,22 @@
 // the mean distance to its k nearest other points, identity rotation, one
 // opacity, and the point's colour in the degree-0 SH band.
 //
-// The k nearest neighbours come from a uniform grid: the points' bounding box
-// is cut into cubic cells of side h (about four points per cell on average),
-// the points are sorted by cell id (x fastest), and each point visits the
-// cells around its own in shells of growing Chebyshev radius r.  Once it holds
-// k candidates and the k-th distance is at most r h, no point outside the
-// shells seen can be nearer (every such point lies at least r h away), so the
-// search stops: the result is exact.  In the sorted order the cells of one
-// grid row are contiguous, so a shell is a set of row ranges, each found by
-// one binary search.  A point still short of that after kMaxRing shells (an
-// outlier far from the rest) falls back to a scan of all points.  Points are
-// processed in sorted order and gathered into it first, so neighbouring
-// threads read the same cells.
+// The k nearest neighbours are exact and come from a bounding-volume
+// hierarchy over the points in Morton order (10 bits per axis over the
+// bounding cube).  Leaves hold kLeaf consecutive points of that order; the
+// tree over the leaves is complete and implicit (heap numbering: node v has
+// children 2v and 2v+1, the leaves are NL..2NL-1, padded with empty boxes) and
+// stores each node's axis-aligned box of its points.  Because the boxes are
+// the points' own boxes and the leaves split by count, not by space, the
+// search adapts to the density: clustered scenes (dense blobs next to sparse
+// outliers) cost about the same per point as uniform ones.  Each point first
+// takes the kWin points on either side of it in the sorted order (almost
+// always near it) as candidates, which bounds its k-th distance, then walks
+// the tree depth first without a stack (left child first; after a subtree,
+// climb while on a right child, then step to the sibling) and skips every
+// box farther than the current k-th distance.  The box distance is computed
+// with the same float operations as the point distances and is monotone in
+// them, so no point nearer than the bound is ever skipped.
 #include <math.h>
 
 #include <algorithm>
@@ -26,14 +30,17 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kMaxK = GS_INIT_MAX_K;
-constexpr int kMaxRing = 6;
-constexpr int kMaxDim = 1024;       // cells per axis (ids fit in 30 bits)
-constexpr int kBoxBlocks = 1024;    // blocks of the bounding-box reduction
-constexpr float kSMin = 1e-7f;      // smallest scale (coincident points)
+constexpr int kLeaf = 8;           // points per leaf
+constexpr int kWin = 8;            // sorted neighbours taken on each side first
+constexpr int kBoxBlocks = 1024;   // blocks of the bounding-box reduction
+constexpr int kUpBlock = 256;      // nodes per block in the bottom-up box pass
+constexpr float kSMin = 1e-7f;     // smallest scale (coincident points)
 
+static_assert(2 * kWin >= kMaxK, "the window must hold k candidates");
+
+// Morton cells: origin and 1024 / (side of the bounding cube)
 struct Grid {
-    float ox, oy, oz, h, ih;
-    int nx, ny, nz;
+    float ox, oy, oz, ih;
 };
 
 // per block: min and max of x, y, z
@@ -70,9 +77,9 @@ __global__ __launch_bounds__(kBlock) void k_box_partial(const float* __restrict_
     }
 }
 
-// The grid: cell side from the box volume per point (about four points per
-// cell), at most kMaxDim cells per axis.
-__global__ void k_grid(const float* __restrict__ part, int nb, int n, Grid* __restrict__ g) {
+// The Morton grid: 1024 cells per axis over the bounding cube (the order only
+// serves locality; the search does not depend on the cells).
+__global__ void k_grid(const float* __restrict__ part, int nb, Grid* __restrict__ g) {
     if (threadIdx.x != 0) return;
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int b = 0; b < nb; b++)
@@ -80,28 +87,28 @@ __global__ void k_grid(const float* __restrict__ part, int nb, int n, Grid* __re
             lo[a] = fminf(lo[a], part[6 * b + a]);
             hi[a] = fmaxf(hi[a], part[6 * b + 3 + a]);
         }
-    const float ex = hi[0] - lo[0], ey = hi[1] - lo[1], ez = hi[2] - lo[2];
-    const float emax = fmaxf(ex, fmaxf(ey, ez));
-    // a degenerate box (a plane, a line, a point) still gets a positive volume
-    const float fl = fmaxf(emax * 1e-3f, 1e-20f);
-    const double vol = (double)fmaxf(ex, fl) * fmaxf(ey, fl) * fmaxf(ez, fl);
-    float h = (float)cbrt(4.0 * vol / (double)(n > 0 ? n : 1));
-    h = fmaxf(h, emax / (float)(kMaxDim - 1));
-    if (!(h > 0.f)) h = 1.f;  // all points coincide
+    const float e = fmaxf(hi[0] - lo[0], fmaxf(hi[1] - lo[1], hi[2] - lo[2]));
     Grid G;
     G.ox = lo[0];
     G.oy = lo[1];
     G.oz = lo[2];
-    G.h = h;
-    G.ih = 1.f / h;
-    G.nx = min((int)(ex * G.ih) + 1, kMaxDim);
-    G.ny = min((int)(ey * G.ih) + 1, kMaxDim);
-    G.nz = min((int)(ez * G.ih) + 1, kMaxDim);
+    G.ih = (e > 0.f && e < INFINITY) ? 1024.f / e : 0.f;  // all points coincide: one cell
     *g = G;
 }
 
-__device__ __forceinline__ int cell_of(float v, float o, float ih, int nd) {
-    return min(max((int)((v - o) * ih), 0), nd - 1);
+__device__ __forceinline__ uint32_t cell_of(float v, float o, float ih) {
+    const float c = (v - o) * ih;
+    return c >= 1023.f ? 1023u : (c > 0.f ? (uint32_t)c : 0u);  // NaN goes to 0
+}
+
+// 10 bits spread to every third bit
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {
+    v &= 1023u;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
 }
 
 __global__ __launch_bounds__(kBlock) void k_cell_keys(const float* __restrict__ pts, int n,
@@ -111,10 +118,10 @@ __global__ __launch_bounds__(kBlock) void k_cell_keys(const float* __restrict__ 
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const Grid g = *gp;
-    const int cx = cell_of(pts[3 * (int64_t)i], g.ox, g.ih, g.nx);
-    const int cy = cell_of(pts[3 * (int64_t)i + 1], g.oy, g.ih, g.ny);
-    const int cz = cell_of(pts[3 * (int64_t)i + 2], g.oz, g.ih, g.nz);
-    keys[i] = (uint32_t)cx + (uint32_t)g.nx * ((uint32_t)cy + (uint32_t)g.ny * (uint32_t)cz);
+    const uint32_t cx = cell_of(pts[3 * (int64_t)i], g.ox, g.ih);
+    const uint32_t cy = cell_of(pts[3 * (int64_t)i + 1], g.oy, g.ih);
+    const uint32_t cz = cell_of(pts[3 * (int64_t)i + 2], g.oz, g.ih);
+    keys[i] = spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2);
     vals[i] = (uint32_t)i;
 }
 
@@ -126,16 +133,6 @@ __global__ __launch_bounds__(kBlock) void k_gather(const float* __restrict__ pts
     if (j >= n) return;
     const int64_t q = vals[j];
     sp[j] = make_float4(pts[3 * q], pts[3 * q + 1], pts[3 * q + 2], 0.f);
-}
-
-__device__ __forceinline__ int lower_bound(const uint32_t* __restrict__ a, int n, uint32_t key) {
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (a[mid] < key) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
 }
 
 // the K smallest squared distances seen, ascending (K >= k: the first k of
@@ -171,70 +168,119 @@ struct TopK {
     }
 };
 
-template <int K>
-__device__ __forceinline__ void scan_range(const uint32_t* __restrict__ keys,
-                                           const float4* __restrict__ sp, int n, uint32_t k0,
-                                           uint32_t k1, int self, float4 p, TopK<K>& best) {
-    for (int j = lower_bound(keys, n, k0); j < n && keys[j] <= k1; j++) {
-        if (j == self) continue;
-        const float4 o = sp[j];
-        const float dx = o.x - p.x, dy = o.y - p.y, dz = o.z - p.z;
-        best.push(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz)));
+// leaf boxes: tree[2v] = (min x, y, z, -), tree[2v + 1] = (max x, y, z, -);
+// padded leaves get an empty box (+inf, -inf), which every bound skips
+__global__ __launch_bounds__(kBlock) void k_leaf_box(const float4* __restrict__ sp, int n, int NL,
+                                                     float4* __restrict__ tree) {
+    const int l = blockIdx.x * kBlock + threadIdx.x;
+    if (l >= NL) return;
+    float4 lo = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
+    float4 hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.f);
+    const int a = l * kLeaf, b = min(n, a + kLeaf);
+    for (int i = a; i < b; i++) {
+        const float4 p = sp[i];
+        lo.x = fminf(lo.x, p.x);
+        lo.y = fminf(lo.y, p.y);
+        lo.z = fminf(lo.z, p.z);
+        hi.x = fmaxf(hi.x, p.x);
+        hi.y = fmaxf(hi.y, p.y);
+        hi.z = fmaxf(hi.z, p.z);
+    }
+    tree[2 * (int64_t)(NL + l)] = lo;
+    tree[2 * (int64_t)(NL + l) + 1] = hi;
+}
+
+// Boxes of the inner nodes from their children, up to nine levels per launch:
+// block b makes the nodes m + 256 b .. m + 256 b + 255 of level [m, 2m) (the
+// level below is done), then their parents from its own results in LDS, and
+// so on while it holds more than one node.  m is a power of two.
+__global__ __launch_bounds__(kUpBlock) void k_tree_up(float4* __restrict__ tree, int m) {
+    __shared__ float4 slo[kUpBlock], shi[kUpBlock];
+    const int t = threadIdx.x;
+    int cnt = min(kUpBlock, m);
+    int base = m + blockIdx.x * kUpBlock;
+    float4 lo, hi;
+    if (t < cnt) {
+        const int64_t c = 2 * (int64_t)(base + t);
+        const float4 l0 = tree[2 * c], h0 = tree[2 * c + 1], l1 = tree[2 * c + 2], h1 = tree[2 * c + 3];
+        lo = make_float4(fminf(l0.x, l1.x), fminf(l0.y, l1.y), fminf(l0.z, l1.z), 0.f);
+        hi = make_float4(fmaxf(h0.x, h1.x), fmaxf(h0.y, h1.y), fmaxf(h0.z, h1.z), 0.f);
+        tree[2 * (int64_t)(base + t)] = lo;
+        tree[2 * (int64_t)(base + t) + 1] = hi;
+        slo[t] = lo;
+        shi[t] = hi;
+    }
+    while (cnt > 1) {
+        __syncthreads();
+        cnt >>= 1;
+        base >>= 1;
+        if (t < cnt) {
+            const float4 l0 = slo[2 * t], h0 = shi[2 * t], l1 = slo[2 * t + 1], h1 = shi[2 * t + 1];
+            lo = make_float4(fminf(l0.x, l1.x), fminf(l0.y, l1.y), fminf(l0.z, l1.z), 0.f);
+            hi = make_float4(fmaxf(h0.x, h1.x), fmaxf(h0.y, h1.y), fmaxf(h0.z, h1.z), 0.f);
+        }
+        __syncthreads();
+        if (t < cnt) {
+            slo[t] = lo;
+            shi[t] = hi;
+            tree[2 * (int64_t)(base + t)] = lo;
+            tree[2 * (int64_t)(base + t) + 1] = hi;
+        }
     }
 }
 
+__device__ __forceinline__ float dist2(float4 o, float4 p) {
+    const float dx = o.x - p.x, dy = o.y - p.y, dz = o.z - p.z;
+    return __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+}
+
+// squared distance from p to a box; for any point q in the box each axis
+// difference is at least the box's, in float too (rounding is monotone), so
+// this never exceeds dist2(q, p)
+__device__ __forceinline__ float box_dist2(float4 lo, float4 hi, float4 p) {
+    const float ex = fmaxf(fmaxf(lo.x - p.x, p.x - hi.x), 0.f);
+    const float ey = fmaxf(fmaxf(lo.y - p.y, p.y - hi.y), 0.f);
+    const float ez = fmaxf(fmaxf(lo.z - p.z, p.z - hi.z), 0.f);
+    return __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez));
+}
+
 // one thread per point, in sorted order; the mean of the k nearest distances
-// goes to s[original index]
+// goes to s[original index].  With n <= 2 kWin + 1 the window holds every
+// point and there is no tree.
 template <int K>
-__global__ __launch_bounds__(kBlock) void k_knn(const uint32_t* __restrict__ keys,
-                                                const uint32_t* __restrict__ vals,
+__global__ __launch_bounds__(kBlock) void k_knn(const uint32_t* __restrict__ vals,
                                                 const float4* __restrict__ sp, int n, int k,
-                                                const Grid* __restrict__ gp, float* __restrict__ s) {
+                                                const float4* __restrict__ tree, int NL,
+                                                float* __restrict__ s) {
     const int j = blockIdx.x * kBlock + threadIdx.x;
     if (j >= n) return;
-    const Grid g = *gp;
     const float4 p = sp[j];
-    const uint32_t key = keys[j];
-    const int cx = (int)(key % (uint32_t)g.nx);
-    const int cy = (int)((key / (uint32_t)g.nx) % (uint32_t)g.ny);
-    const int cz = (int)(key / ((uint32_t)g.nx * (uint32_t)g.ny));
     const int kk = min(k, n - 1);
     TopK<K> best;
     best.init();
-    bool done = kk <= 0;
-    // a point outside the shells seen so far is at least r h away; the margin
-    // covers the rounding of the cell assignment
-    for (int r = 0; r <= kMaxRing && !done; r++) {
-        for (int dz = -r; dz <= r; dz++) {
-            const int z = cz + dz;
-            if (z < 0 || z >= g.nz) continue;
-            for (int dy = -r; dy <= r; dy++) {
-                const int y = cy + dy;
-                if (y < 0 || y >= g.ny) continue;
-                const uint32_t row = (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z);
-                if (dz == -r || dz == r || dy == -r || dy == r) {
-                    const int x0 = max(cx - r, 0), x1 = min(cx + r, g.nx - 1);
-                    scan_range<K>(keys, sp, n, row + x0, row + x1, j, p, best);
-                } else {
-                    if (cx - r >= 0) scan_range<K>(keys, sp, n, row + cx - r, row + cx - r, j, p, best);
-                    if (cx + r < g.nx) scan_range<K>(keys, sp, n, row + cx + r, row + cx + r, j, p, best);
-                }
+    const int j1 = min(n - 1, max(j - kWin, 0) + 2 * kWin);
+    const int j0 = max(0, j1 - 2 * kWin);
+    for (int i = j0; i <= j1; i++)
+        if (i != j) best.push(dist2(sp[i], p));
+    float bound = kk > 0 ? best.at(kk - 1) : 0.f;
+    if (n > 2 * kWin + 1 && bound > 0.f) {
+        int v = 1;
+        while (true) {
+            bool go = box_dist2(tree[2 * (int64_t)v], tree[2 * (int64_t)v + 1], p) <= bound;
+            if (go && v >= NL) {
+                const int a = (v - NL) * kLeaf, b = min(n, a + kLeaf);
+                for (int i = a; i < b; i++)
+                    if (i < j0 || i > j1) best.push(dist2(sp[i], p));
+                bound = best.at(kk - 1);
+                go = false;
             }
-        }
-        const float reach = (float)r * g.h * (1.f - 1e-4f);
-        done = best.cnt >= kk && best.at(kk - 1) <= reach * reach;
-        // every cell of the grid seen: nothing is left
-        if (cx - r <= 0 && cy - r <= 0 && cz - r <= 0 && cx + r >= g.nx - 1 && cy + r >= g.ny - 1 &&
-            cz + r >= g.nz - 1)
-            done = true;
-    }
-    if (!done) {
-        best.init();
-        for (int i = 0; i < n; i++) {
-            if (i == j) continue;
-            const float4 o = sp[i];
-            const float dx = o.x - p.x, dy = o.y - p.y, dz = o.z - p.z;
-            best.push(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz)));
+            if (go) {
+                v = 2 * v;
+                continue;
+            }
+            while (v & 1) v >>= 1;  // finished a right child: climb
+            if (v == 0) break;      // climbed past the root
+            v += 1;                 // the right sibling
         }
     }
     float m = 0.f;
@@ -285,7 +331,7 @@ hipError_t launch_init_gaussians(Ctx* c, const float* pts, const float* rgb, int
     float* part = c->aux;
     Grid* grid = reinterpret_cast<Grid*>(c->aux + 6 * kBoxBlocks);
     hipLaunchKernelGGL(k_box_partial, dim3(nb), dim3(kBlock), 0, st, pts, n, part);
-    hipLaunchKernelGGL(k_grid, dim3(1), dim3(64), 0, st, part, nb, n, grid);
+    hipLaunchKernelGGL(k_grid, dim3(1), dim3(64), 0, st, part, nb, grid);
     const unsigned g = (unsigned)((n + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_cell_keys, dim3(g), dim3(kBlock), 0, st, pts, n, grid, c->pk[0], c->pv[0]);
     hipError_t e = hipGetLastError();
@@ -293,15 +339,27 @@ hipError_t launch_init_gaussians(Ctx* c, const float* pts, const float* rgb, int
     const int side = radix_sort_pairs(c->pk[0], c->pv[0], c->pk[1], c->pv[1], n, nullptr, 0, 30,
                                       c->hist, c->scan_scratch, c->diag + kDiagFlags, st, &e);
     if (e != hipSuccess) return e;
-    const uint32_t* keys = c->pk[side];
     const uint32_t* vals = c->pv[side];
+    // sorted points, then the tree, in the record buffer (12 floats per pair):
+    // 16 n bytes and 32 * 2 NL <= 16 n + 48 bytes (NL < 2 ceil(n / 8))
     float4* sp = reinterpret_cast<float4*>(c->rec);
+    float4* tree = sp + n;
     float* s = reinterpret_cast<float*>(c->cnt);
     hipLaunchKernelGGL(k_gather, dim3(g), dim3(kBlock), 0, st, pts, n, vals, sp);
+    int NL = 0;
+    if (n > 2 * kWin + 1) {
+        const int nl = (n + kLeaf - 1) / kLeaf;
+        NL = 1;
+        while (NL < nl) NL *= 2;
+        hipLaunchKernelGGL(k_leaf_box, dim3((NL + kBlock - 1) / kBlock), dim3(kBlock), 0, st, sp, n, NL,
+                           tree);
+        for (int m = NL / 2; m >= 1; m /= 2 * kUpBlock)
+            hipLaunchKernelGGL(k_tree_up, dim3(std::max(1, m / kUpBlock)), dim3(kUpBlock), 0, st, tree, m);
+    }
     if (k <= 4)
-        hipLaunchKernelGGL(k_knn<4>, dim3(g), dim3(kBlock), 0, st, keys, vals, sp, n, k, grid, s);
+        hipLaunchKernelGGL(k_knn<4>, dim3(g), dim3(kBlock), 0, st, vals, sp, n, k, tree, NL, s);
     else
-        hipLaunchKernelGGL(k_knn<kMaxK>, dim3(g), dim3(kBlock), 0, st, keys, vals, sp, n, k, grid, s);
+        hipLaunchKernelGGL(k_knn<kMaxK>, dim3(g), dim3(kBlock), 0, st, vals, sp, n, k, tree, NL, s);
     const float lg = logf(opacity / (1.f - opacity));
     const int K = (sh_degree + 1) * (sh_degree + 1);
     hipLaunchKernelGGL(k_init_write, dim3(g), dim3(kBlock), 0, st, pts, rgb, n, K, lg, s, means,

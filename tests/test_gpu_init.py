@@ -88,3 +88,23 @@ def test_init_large_scene_track_points_sampled(gs):
     d = oracle.knn_mean_dist(pts, 4, queries=idx)
     s_g = np.exp(g["log_scales"][0, idx].astype(np.float64))
     assert np.max(np.abs(s_g / np.maximum(d, 1e-7) - 1)) <= 1e-5
+
+
+def test_init_k8_dense_duplicates_and_shells(gs):
+    """k = 8 (the largest) with a thousand coincident points (scale at its
+    floor), points on a tiny sphere next to a wide cloud, and points on
+    concentric shells: the density varies by many orders of magnitude."""
+    rng = np.random.default_rng(5)
+    dup = np.repeat(rng.normal(0, 1, (1, 3)), 1000, axis=0)
+    v = rng.normal(size=(500, 3))
+    sphere = 1e-3 * v / np.linalg.norm(v, axis=1, keepdims=True) + 2.0
+    cloud = rng.uniform(-4, 4, (3000, 3))
+    w = rng.normal(size=(2000, 3))
+    shells = (w / np.linalg.norm(w, axis=1, keepdims=True)) * rng.choice([0.5, 1.0, 1.5], (2000, 1)) - 2.0
+    pts = np.concatenate([dup, sphere, cloud, shells])[rng.permutation(6500)].astype(np.float32)
+    rgb = rng.uniform(size=pts.shape).astype(np.float32)
+    g = _gpu_init(gs, pts, rgb, sh_degree=0, k=8)
+    o = oracle.init_gaussians(pts, rgb, sh_degree=0, k=8)
+    s_g, s_o = np.exp(g["log_scales"].astype(np.float64)), np.exp(o["log_scales"])
+    assert np.max(np.abs(s_g / s_o - 1)) <= 1e-5
+    assert np.sum(s_o[0] <= 1.000001e-7) == 1000       # the coincident points sit at the floor
