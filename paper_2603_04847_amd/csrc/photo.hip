@@ -106,23 +106,28 @@ __global__ __launch_bounds__(kThreads) void k_photo(PhotoArgs a, Window win) {
         // halo, columns of the tile plus the ring
         for (int item = tid; item < kIn * (kMid / kRunA); item += kThreads) {
             const int r = item / (kMid / kRunA), c0 = (item % (kMid / kRunA)) * kRunA;
+            // the run's inputs and their squares and products, formed once
             float xs[kRunA + kTaps - 1], ys[kRunA + kTaps - 1];
+            float xx[kRunA + kTaps - 1], yy[kRunA + kTaps - 1], xy[kRunA + kTaps - 1];
 #pragma unroll
             for (int k = 0; k < kRunA + kTaps - 1; k++) {
                 xs[k] = s.X[r][c0 + k];
                 ys[k] = s.Y[r][c0 + k];
+                xx[k] = xs[k] * xs[k];
+                yy[k] = ys[k] * ys[k];
+                xy[k] = xs[k] * ys[k];
             }
 #pragma unroll
             for (int j = 0; j < kRunA; j++) {
                 float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f;
 #pragma unroll
                 for (int k = 0; k < kTaps; k++) {
-                    const float g = win.g[k], xv = xs[j + k], yv = ys[j + k];
-                    m0 = __builtin_fmaf(g, xv, m0);
-                    m1 = __builtin_fmaf(g, yv, m1);
-                    m2 = __builtin_fmaf(g * xv, xv, m2);
-                    m3 = __builtin_fmaf(g * yv, yv, m3);
-                    m4 = __builtin_fmaf(g * xv, yv, m4);
+                    const float g = win.g[k];
+                    m0 = __builtin_fmaf(g, xs[j + k], m0);
+                    m1 = __builtin_fmaf(g, ys[j + k], m1);
+                    m2 = __builtin_fmaf(g, xx[j + k], m2);
+                    m3 = __builtin_fmaf(g, yy[j + k], m3);
+                    m4 = __builtin_fmaf(g, xy[j + k], m4);
                 }
                 s.u.H[0][r][c0 + j] = m0;
                 s.u.H[1][r][c0 + j] = m1;
