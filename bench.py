@@ -601,6 +601,206 @@ def cpu_baseline(res, seconds_target=12.0, lambda_ssim=0.2, max_gaussians=1_000_
                         + f"; measured {time.time() - t_start:.1f}s"))
 
 
+# -------------------------------------------------------------- counter summaries
+
+# the counter passes: one rocprofv3 run each (a pass holds at most 4 TCC, 4 TCP
+# and 8 SQ counters); FETCH_SIZE and WRITE_SIZE also on the copy probe
+COUNTER_PASSES = {
+    "fetch": ["FETCH_SIZE"],
+    "write": ["WRITE_SIZE"],
+    "l2": ["TCC_HIT_sum", "TCC_MISS_sum", "TCC_ATOMIC_sum", "TCP_TCC_ATOMIC_WITH_RET_REQ_sum",
+           "TCP_TCC_ATOMIC_WITHOUT_RET_REQ_sum"],
+    "lds": ["SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE", "SQ_INSTS_LDS", "SQ_WAIT_INST_LDS",
+            "SQ_LDS_ADDR_CONFLICT", "SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES"],
+    "valu": ["SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_THREAD_CYCLES_VALU", "SQ_WAIT_ANY",
+             "SQ_ACTIVE_INST_ANY", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR", "SQ_INSTS_SALU",
+             "GRBM_GUI_ACTIVE"],
+}
+N_CU, N_XCD, WAVE = 256, 8, 64
+
+
+def _short_kernel(name):
+    n = name[5:] if name.startswith("void ") else name
+    n = n.replace("gs::(anonymous namespace)::", "")
+    depth, out = 0, ""
+    for ch in n:
+        if ch == "(" and depth == 0:
+            break
+        depth += ch == "<"
+        depth -= ch == ">"
+        out += ch
+    return out
+
+
+def _read_pass(raw, name):
+    """Dispatches of one counter pass in launch order: [(kernel, {counter: value}, ns)]."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(raw, name, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter file under {os.path.join(raw, name)}")
+    disp = {}
+    for f in files:
+        for r in csv.DictReader(open(f)):
+            d = disp.setdefault(int(r["Dispatch_Id"]), [r["Kernel_Name"], {},
+                                                          int(r["End_Timestamp"]) - int(r["Start_Timestamp"])])
+            d[1][r["Counter_Name"]] = d[1].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    return [tuple(disp[k]) for k in sorted(disp)]
+
+
+def _bench_line(raw, name):
+    for ln in open(os.path.join(raw, name + ".log")):
+        if ln.startswith("{"):
+            return json.loads(ln)
+    return None
+
+
+# the kernels of each timed call (bin_sort: every dispatch from k_count to k_chunk_expand)
+CALL_KERNELS = {
+    "project": lambda k: k.startswith("k_project_fwd<"),
+    "render_fwd": lambda k: k.startswith("k_render_fwd<") and k.endswith("false>"),
+    "raster_bwd": lambda k: k.startswith("k_render_bwd<"),
+    "photo": lambda k: k == "k_photo",
+    "project_bwd_adam": lambda k: k in ("k_project_bwd_color<3, true>", "k_project_bwd_geom<true>"),
+    "track": lambda k: k in ("k_track", "k_track_points"),
+    "adam": lambda k: k == "k_adam",
+}
+
+
+def _per_call(disp, counter):
+    """Per-launch totals of one counter for each timed call."""
+    out = {}
+    for call, sel in CALL_KERNELS.items():
+        tot = [v.get(counter, 0.0) for k, v, _ in disp if sel(_short_kernel(k))]
+        first = [k for k, _, _ in disp if sel(_short_kernel(k))]
+        n_first = sum(1 for k in first if _short_kernel(k) == _short_kernel(first[0])) if first else 0
+        if n_first:
+            out[call] = sum(tot) / n_first
+    segs, cur = [], None
+    for k, v, _ in disp:
+        sk = _short_kernel(k)
+        if sk == "k_count":
+            cur = 0.0
+        if cur is not None:
+            cur += v.get(counter, 0.0)
+        if sk == "k_chunk_expand" and cur is not None:
+            segs.append(cur)
+            cur = None
+    if segs:
+        out["bin_sort"] = sum(segs) / len(segs)
+    return out
+
+
+def summarize_counters(raw, workload):
+    """profiles/kernels_<workload>_hbm_traffic.json (HBM bytes per launch of each
+    timed call, FETCH_SIZE and WRITE_SIZE scaled by what they read for a 1 GiB
+    streaming copy) and profiles/kernels_<workload>_counters.md (per kernel:
+    HBM bytes, L2 hit rate, atomics, LDS bank conflicts, VALU busy and lanes
+    active) from the rocprofv3 passes under `raw`."""
+    cf = [v["FETCH_SIZE"] for k, v, _ in _read_pass(raw, "copy_fetch")
+          if "AUnaryFunctor" in k or "MulFunctor" in k or "BinaryFunctor" in k]
+    cw = [v["WRITE_SIZE"] for k, v, _ in _read_pass(raw, "copy_write")
+          if "AUnaryFunctor" in k or "MulFunctor" in k or "BinaryFunctor" in k]
+    gib_kib = float(1 << 20)
+    f_scale = gib_kib / float(np.median(cf))
+    w_scale = gib_kib / float(np.median(cw))
+    P = {n: _read_pass(raw, f"{workload}_{n}") for n in COUNTER_PASSES}
+    line = _bench_line(raw, f"{workload}_fetch") or {}
+    alg = (line.get("hbm_step") or {}).get("bytes_by_call", {})
+    fetch = _per_call(P["fetch"], "FETCH_SIZE")
+    write = _per_call(P["write"], "WRITE_SIZE")
+    traffic = {"workload": workload, "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
+               "note": ("HBM bytes per launch of each timed call: FETCH_SIZE and WRITE_SIZE (KiB) "
+                        "times 1024 times the copy-probe factor; src_sha is the hash of the call's "
+                        "kernel sources when the counters were taken")}
+    for call in fetch:
+        if call in write:
+            traffic[call] = {"src_sha": source_sha(call),
+                             "fetch_bytes": int(fetch[call] * 1024 * f_scale),
+                             "write_bytes": int(write[call] * 1024 * w_scale),
+                             "algorithmic_bytes": alg.get(call)}
+    with open(os.path.join(ROOT, "profiles", f"kernels_{workload}_hbm_traffic.json"), "w") as fh:
+        json.dump(traffic, fh, indent=1)
+        fh.write("\n")
+    # per kernel, averaged over its dispatches in each pass
+    agg = {}
+    for n, disp in P.items():
+        for k, v, ns in disp:
+            a = agg.setdefault(_short_kernel(k), {"_n": {}, "_ns": []})
+            a["_n"][n] = a["_n"].get(n, 0) + 1
+            if n == "valu":
+                a["_ns"].append(ns)
+            for c, x in v.items():
+                a[c] = a.get(c, 0.0) + x
+    rows = []
+    for k, a in agg.items():
+        if not a["_ns"] or np.mean(a["_ns"]) < 20e3:
+            continue
+
+        def per(c, n):
+            return a.get(c, 0.0) / max(a["_n"].get(n, 0), 1)
+        hit, miss = per("TCC_HIT_sum", "l2"), per("TCC_MISS_sum", "l2")
+        lds_act = per("SQ_LDS_IDX_ACTIVE", "lds")
+        act_valu = per("SQ_ACTIVE_INST_VALU", "valu")
+        grbm = per("GRBM_GUI_ACTIVE", "valu") / N_XCD
+        rows.append((np.mean(a["_ns"]), k, a["_n"].get("valu", 0),
+                     per("FETCH_SIZE", "fetch") * 1024 * f_scale / 1e6,
+                     per("WRITE_SIZE", "write") * 1024 * w_scale / 1e6,
+                     hit / max(hit + miss, 1.0),
+                     per("TCC_ATOMIC_sum", "l2"),
+                     per("TCP_TCC_ATOMIC_WITH_RET_REQ_sum", "l2") + per("TCP_TCC_ATOMIC_WITHOUT_RET_REQ_sum", "l2"),
+                     per("SQ_LDS_BANK_CONFLICT", "lds") / lds_act if lds_act else 0.0,
+                     per("SQ_INSTS_LDS", "lds"),
+                     act_valu / N_CU / grbm if grbm else 0.0,
+                     per("SQ_THREAD_CYCLES_VALU", "valu") / (act_valu * WAVE) if act_valu else 0.0,
+                     per("SQ_WAIT_ANY", "valu") / max(per("SQ_WAVE_CYCLES", "lds"), 1.0)))
+    rows.sort(reverse=True)
+    cmd_pass = ("cd /tmp && rocprofv3 --pmc <counters of the pass> --output-format csv -d "
+                "/root/repo/gpurun_out/pmc/{W}_<pass> -o run -- python3 /root/repo/bench.py --workload {W} "
+                "--steps 2 --warmup 1 --tile {T} --order 0 --no-compare --no-cpu-baseline --no-extra "
+                "--no-graph").format(W=workload, T=(line.get("config") or {}).get("tile", "?"))
+    md = [f"# Counters of the joint step, {workload}, per kernel (rocprofv3 --pmc)", "",
+          "Passes (one rocprofv3 run each; the counters of a pass in brackets):", ""]
+    md += [f"- `{n}`: " + " ".join(c) for n, c in COUNTER_PASSES.items()]
+    md += ["", "Command of a pass, and of the copy probe that calibrates FETCH_SIZE / WRITE_SIZE "
+           "(passes `copy_fetch`, `copy_write`):", "", "```", cmd_pass,
+           "cd /tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv -d /root/repo/gpurun_out/pmc/copy_fetch "
+           "-o run -- python3 /root/repo/bench.py --copy-probe 1024", "```", "",
+           "Summary written by `python bench.py --summarize-counters gpurun_out/pmc --workload "
+           f"{workload}` (also writes `kernels_{workload}_hbm_traffic.json`).", "",
+           f"Copy probe (1 GiB read and 1 GiB written per launch): FETCH_SIZE reads "
+           f"{1 / f_scale:.3f} of the bytes read, WRITE_SIZE {1 / w_scale:.3f} of the bytes written; "
+           "the HBM columns below are scaled by the inverse.", "",
+           "| kernel | launches | us (under counters) | HBM read MB | HBM write MB | L2 hit | "
+           "TCC atomics | TCP->TCC atomic req | LDS bank-conflict cycles / LDS active | LDS insts | "
+           "VALU busy | VALU lanes active | wait share |",
+           "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for r in rows:
+        md.append(f"| `{r[1]}` | {r[2]} | {r[0] / 1e3:.1f} | {r[3]:.1f} | {r[4]:.1f} | {r[5]:.3f} | "
+                  f"{r[6]:.3g} | {r[7]:.3g} | {r[8]:.4f} | {r[9]:.3g} | {r[10]:.3f} | {r[11]:.3f} | "
+                  f"{r[12]:.3f} |")
+    md += ["", "Per timed call, HBM bytes per launch against the algorithmic bytes of the bench's "
+           "model (the same run's bench line):", "",
+           "| call | HBM read MB | HBM write MB | algorithmic MB | measured / algorithmic |",
+           "|---|---:|---:|---:|---:|"]
+    for call in ("project", "bin_sort", "render_fwd", "photo", "raster_bwd", "project_bwd_adam",
+                 "track", "adam"):
+        t = traffic.get(call)
+        if not t:
+            continue
+        a = t["algorithmic_bytes"]
+        tot = t["fetch_bytes"] + t["write_bytes"]
+        md.append(f"| {call} | {t['fetch_bytes'] / 1e6:.1f} | {t['write_bytes'] / 1e6:.1f} | "
+                  f"{(a or 0) / 1e6:.1f} | {(tot / a if a else float('nan')):.2f} |")
+    md += ["", "Columns: L2 hit = TCC_HIT / (TCC_HIT + TCC_MISS); VALU busy = SQ_ACTIVE_INST_VALU / "
+           f"{N_CU} CUs / (GRBM_GUI_ACTIVE / {N_XCD} XCDs); VALU lanes active = SQ_THREAD_CYCLES_VALU / "
+           "(SQ_ACTIVE_INST_VALU x 64); wait share = SQ_WAIT_ANY / SQ_WAVE_CYCLES (two passes of "
+           "the same work). Kernels under 20 us left out."]
+    with open(os.path.join(ROOT, "profiles", f"kernels_{workload}_counters.md"), "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    print(json.dumps(traffic, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -620,7 +820,13 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip batched vs per-view (C3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing")
+    ap.add_argument("--summarize-counters", default=None, metavar="DIR",
+                    help="write the counter summaries under profiles/ from the rocprofv3 passes in DIR "
+                         "(no GPU needed) and exit")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters, args.workload)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the hot path "
               "here has no multi-GPU code", file=sys.stderr)
