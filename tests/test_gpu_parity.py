@@ -119,6 +119,39 @@ def test_bin_sort_bit_exact_on_synthetic_records(gs, tile):
     assert np.array_equal(ent >> 28, masks_o.astype(np.uint32))
 
 
+def test_bin_sort_bit_exact_past_2048_blocks(gs):
+    """8x8 tiles on a 2048x1536 view and a 640x480 one: 3072 + 300 blocks of
+    4x4 tiles, so the block ids take 12 bits and the block-key sort runs as
+    two 6-bit passes instead of its single 11-bit pass; lists stay
+    bit-exact."""
+    wh = np.array([[2048, 1536], [640, 480]], np.int32)
+    N = 500
+    r = scenegen.synthetic_records(17, 2, wh, N, tile=(8, 8))
+    rec = np.zeros((2 * N, 12), np.float32)
+    rec[:, 0:2] = r["mean2d"]
+    rec[:, 2] = r["depth"]
+    rec[:, 3] = np.where(r["valid"] > 0, r["opacity"], 0.0)
+    rec[:, 4:7] = r["conic"]
+    rec[:, 7:10] = r["rgb"]
+    ctx = gs.Context(max_pairs=2 * N, max_isect=2_000_000, max_tiles=200_000, max_views=2)
+    s = gs.default_settings(tile_w=8, tile_h=8)
+    cams = gs.Cameras(_t(np.zeros((2, 12))), _t(np.zeros((2, 4))), wh)
+    gs.gs_bin_sort(ctx, cams, N, s, _t(rec))
+    st = ctx.status()
+    assert st["flags"] == 0
+    ranges_o, ids_o, masks_o = oracle.bin_sort(wh, (8, 8), r["valid"], r["mean2d"], r["conic"],
+                                               r["opacity"], r["depth"], with_masks=True)
+    assert st["n_isect"] == len(ids_o)
+    b = ctx.buffers()
+    T = b["n_tiles"]
+    assert T == ranges_o.shape[0]
+    ranges = _read_i32(b["tile_ranges"], 2 * T).reshape(T, 2)
+    ent = _read_i32(b["isect_ids"], len(ids_o)).view(np.uint32)
+    assert np.array_equal(ranges, ranges_o.astype(np.int32))
+    assert np.array_equal(ent & 0x0FFFFFFF, ids_o.astype(np.uint32))
+    assert np.array_equal(ent >> 28, masks_o.astype(np.uint32))
+
+
 def test_bin_sort_bit_exact_with_many_scan_tiles(gs):
     """A large capacity makes the capacity-sized scans (chunk counts, block-key
     digit counts) span hundreds of 4096-item tiles, so the single-pass scans
