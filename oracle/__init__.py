@@ -32,6 +32,17 @@ _CFG_ORDER = ["near", "eps2d", "pad", "alpha_min", "alpha_max", "t_min",
 _lib = None
 
 
+def build_sanitized(path):
+    """The oracle built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (every report fatal) into `path`; loaded instead of the plain build when
+    the ORACLE_LIB environment variable names it (with libasan preloaded)."""
+    subprocess.check_call(["gcc", "-O1", "-g", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                           "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                           "-fno-omit-frame-pointer", "-Wall", "-Wno-unknown-pragmas",
+                           "-o", path, _SRC, "-lm"])
+    return path
+
+
 def build(force=True):
     """Compile the oracle (gcc, -O2, OpenMP)."""
     if force or not os.path.exists(_LIB):
@@ -45,9 +56,13 @@ def build(force=True):
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build()
-        _lib = ctypes.CDLL(_LIB)
+        alt = os.environ.get("ORACLE_LIB")
+        if alt:
+            _lib = ctypes.CDLL(alt)
+        else:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build()
+            _lib = ctypes.CDLL(_LIB)
         _lib.or_bin_sort.restype = ctypes.c_longlong
     return _lib
 
