@@ -587,8 +587,41 @@ def cpu_baseline(res, seconds_target=12.0, lambda_ssim=0.2, max_gaussians=1_000_
         oracle.photo_loss(img, tgt, np.array([[cw, ch]], np.int32), lam=lambda_ssim)
         t_photo = (time.time() - t0) * sz["P"] / n_crop
     t_step = t_proj + t_pix_all + t_pbwd + t_track + t_photo
-    return dict(value=round(sz["P"] / t_step / 1e6, 6), unit="MP/s", cores=oracle.num_threads(),
-                kind="oracle",
+    # one thread: the same three pieces (compositing of 256 pixels, the
+    # projection of the first 50k Gaussians, the track term on the first 100k
+    # observations) timed on all threads and on one; the all-core estimate
+    # divided by that ratio
+    cores = oracle.num_threads()
+
+    def pieces():
+        t0 = time.time()
+        pix = np.random.default_rng(1).choice(sz["P"], size=256, replace=False)
+        oracle.render(proj, wh, pix=pix, v_rgb=np.ones((256, 3)))
+        s1 = dict(sub)
+        for k in ("means", "log_scales", "quats"):
+            s1[k] = np.ascontiguousarray(sub[k][:, :50000])
+        s1["opacity_logit"] = np.ascontiguousarray(sub["opacity_logit"][:50000])
+        s1["sh"] = np.ascontiguousarray(sub["sh"][:, :, :50000])
+        oracle.project(s1)
+        if sz["M"] > 0:
+            m1 = min(sz["M"], 100000)
+            oracle.track(sc["X"], st.viewmat.cpu().numpy(), sc["intr"], sc["obs_cam"][:m1],
+                         sc["obs_pt"][:m1], sc["obs_xy"][:m1], jacobians=False)
+        return time.time() - t0
+    t_all = pieces()
+    oracle.set_num_threads(1)
+    try:
+        t_one = pieces()
+    finally:
+        oracle.set_num_threads(cores)
+    ratio = t_one / max(t_all, 1e-9)
+    single = dict(value=round(sz["P"] / (t_step * ratio) / 1e6, 7), unit="MP/s", cores=1,
+                  all_cores_speedup=round(ratio, 2),
+                  sample=(f"the all-core estimate divided by the one-thread / all-thread time "
+                          f"ratio of compositing 256 pixels, projecting 50k Gaussians and the "
+                          f"track term on 100k observations ({t_one:.1f}s vs {t_all:.2f}s)"))
+    return dict(value=round(sz["P"] / t_step / 1e6, 6), unit="MP/s", cores=cores,
+                kind="oracle", single_thread=single,
                 sample=(f"batch 0 of the workload on its first {Ns} of {sz['N']} Gaussians and "
                         f"first {Ms} of {sz['M']} observations (times scaled by {fN:.2f} and "
                         f"{(sz['M'] / Ms) if Ms else 0:.2f}): projection + its backward of "

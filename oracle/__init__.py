@@ -93,6 +93,11 @@ def num_threads():
     return _load().or_num_threads()
 
 
+def set_num_threads(n):
+    """Threads of the oracle's parallel loops from now on (timing runs)."""
+    _load().or_set_num_threads(int(n))
+
+
 def project(scene, viewmat=None, intr=None, wh=None, **cfg):
     """Per-(view, Gaussian) projection.  Returns a dict of [V*N, ...] arrays."""
     lib = _load()

@@ -41,6 +41,15 @@ int or_num_threads(void) {
 #endif
 }
 
+/* Threads of the following parallel loops (timing runs only). */
+void or_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------ small linear algebra */
 
 static void mat3_mul(const double* A, const double* B, double* C) {

@@ -173,6 +173,7 @@ void or_mcmc_noise(long long N, double* means, const double* log_scales, const d
 void or_sh_basis(int deg, const double* d, double* Y, double* dY);
 
 int or_num_threads(void);
+void or_set_num_threads(int n);
 
 #ifdef __cplusplus
 }
