@@ -186,8 +186,8 @@ const char* gs_strerror(gs_status s);
 void gs_default_settings(gs_settings* s);
 
 /* Create a context: allocates the whole workspace once (device memory of about
- * 48+36+24 B per pair + 36 B per list entry + 40 B per tile).  *out is NULL
- * on failure. */
+ * 48+36+24 B per pair + 36 B per list entry + 40 B per tile, and 12 KB per
+ * camera up to GS_TRACK_PM_MAX_CAMS).  *out is NULL on failure. */
 gs_status gs_ctx_create(gs_ctx** out, const gs_capacity* cap);
 gs_status gs_ctx_destroy(gs_ctx* ctx);
 /* Synchronise the device and read the status word. */
@@ -382,20 +382,30 @@ gs_status gs_ba_lm_step(gs_ba* ba, const float* X, int32_t Pt, const float* view
  * sorted is faster).  pt_off / pt_obs (both NULL, or both set): a point-major
  * index of the observations built by track_point_index for these obs_pt, M and
  * Pt; with it v_X is summed per point (no atomics, a fixed order) instead of
- * scattered with atomics per observation; the results agree up to rounding. */
+ * scattered with atomics per observation; the results agree up to rounding.
+ * pm_cam / pm_xy (both NULL, or both set, and then the index too): the
+ * observations' cameras and pixels in that point-major order (track_point_index
+ * writes them); with them, and with n_cams <= GS_TRACK_PM_MAX_CAMS, no
+ * residual or Jacobian asked for and v_X given, the whole term is one pass
+ * over the points reading every array in order (per-workgroup twist sums in
+ * LDS, then summed over the workgroups in a fixed order): no global atomics,
+ * the same results up to rounding.  Otherwise they are not read. */
+#define GS_TRACK_PM_MAX_CAMS 2048
 gs_status track_reproj_fwd_bwd(gs_ctx* ctx, const float* X, int32_t Pt,
                                const float* viewmat, const float* intr, int32_t n_cams,
                                const int32_t* obs_cam, const int32_t* obs_pt,
                                const float* obs_xy, int32_t M, float delta, float lambda,
                                float near_plane, float* residual, float* loss, float* v_X,
                                float* v_twist, float* J_pose, float* J_X,
-                               const int32_t* pt_off, const int32_t* pt_obs, void* stream);
+                               const int32_t* pt_off, const int32_t* pt_obs,
+                               const int32_t* pm_cam, const float* pm_xy, void* stream);
 
 /* track_reproj_fwd_bwd without a context, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops, harnesses
  * that forbid hipMalloc).  Same arguments, results and errors as
  * track_reproj_fwd_bwd minus the context; it allocates nothing and
- * synchronises nothing.  Its accumulators (per-camera twist sums and the loss
+ * synchronises nothing (it takes no point-major copies: pm_cam / pm_xy of
+ * track_reproj_fwd_bwd are not among its arguments).  Its accumulators (per-camera twist sums and the loss
  * in double, status words) live in one fixed array of device memory inside
  * the library, 6 x GS_NOALLOC_MAX_CAMS doubles plus a few words (about 197
  * KB), one copy per GPU, held until the process ends; each call clears the
@@ -419,10 +429,16 @@ gs_status track_reproj_fwd_bwd_noalloc(const float* X, int32_t Pt, const float* 
  * pt_off[Pt + 1] (device, 16-byte aligned): point k's observations are
  * pt_obs[pt_off[k] .. pt_off[k + 1]), ascending; pt_obs[M] (device) receives
  * pt_off[Pt] <= M indices (observations whose point is outside [0, Pt) are left
- * out).  Both caller-owned.  GS_ERR_CAPACITY if Pt exceeds the context's
- * max_pairs or its scan workspace. */
+ * out).  Both caller-owned.  obs_cam[M], obs_xy[M][2] and pm_cam[M],
+ * pm_xy[M][2] (all four NULL, or all set, unless M = 0; device,
+ * caller-owned): the
+ * observations' cameras and pixels copied into pm_* in the index's order
+ * (pm_cam[j] = obs_cam[pt_obs[j]], j < pt_off[Pt]), for track_reproj_fwd_bwd's
+ * point-major pass; obs_xy and pm_xy 8-byte aligned.  GS_ERR_CAPACITY if Pt
+ * exceeds the context's max_pairs or its scan workspace. */
 gs_status track_point_index(gs_ctx* ctx, const int32_t* obs_pt, int32_t M, int32_t Pt,
-                            int32_t* pt_off, int32_t* pt_obs, void* stream);
+                            int32_t* pt_off, int32_t* pt_obs, const int32_t* obs_cam,
+                            const float* obs_xy, int32_t* pm_cam, float* pm_xy, void* stream);
 
 /* Pose composition T_i = Exp(dxi_i) T_i^(0) (Algorithm 1, pose adjustment,
  * with (+) read as left composition): twist[V][6] = (rho, phi), base[V][12],

@@ -138,7 +138,7 @@ def load():
     lib.track_reproj_fwd_bwd.argtypes = [
         c_vp, c_vp, ctypes.c_int32, c_vp, c_vp, ctypes.c_int32, c_vp, c_vp, c_vp, ctypes.c_int32,
         ctypes.c_float, ctypes.c_float, ctypes.c_float, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
-        c_vp, c_vp]
+        c_vp, c_vp, c_vp, c_vp]
     lib.gs_mcmc_relocate.argtypes = [c_vp, ctypes.POINTER(gs_gaussian_adam), ctypes.c_int32,
                                      ctypes.c_int32, c_vp, ctypes.c_float, c_vp, c_vp, c_vp]
     lib.gs_mcmc_noise.argtypes = [c_vp, c_vp, c_vp, c_vp, ctypes.c_int32, c_vp, ctypes.c_float,
@@ -158,7 +158,8 @@ def load():
         c_vp, ctypes.c_int32, c_vp, c_vp, ctypes.c_int32, c_vp, c_vp, c_vp, ctypes.c_int32,
         ctypes.c_float, ctypes.c_float, ctypes.c_float, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
         c_vp, c_vp]
-    lib.track_point_index.argtypes = [c_vp, c_vp, ctypes.c_int32, ctypes.c_int32, c_vp, c_vp, c_vp]
+    lib.track_point_index.argtypes = [c_vp, c_vp, ctypes.c_int32, ctypes.c_int32, c_vp, c_vp, c_vp,
+                                      c_vp, c_vp, c_vp, c_vp]
     lib.gs_pose_compose.argtypes = [ctypes.c_int32, c_vp, c_vp, c_vp, c_vp]
     lib.gs_pose_compose_bwd.argtypes = [ctypes.c_int32, c_vp, c_vp, c_vp, c_vp]
     lib.gs_adam_step.argtypes = [ctypes.POINTER(gs_adam_group), ctypes.c_int32, ctypes.c_int32,
@@ -425,8 +426,8 @@ class BundleAdjuster:
 
 def gs_ba_lm_step(ba, X, viewmat, intr, obs_cam, obs_pt, obs_xy, pt_index, delta, lm_lambda,
                   near_plane, max_iter, tol, d_twist, d_X, stats=None, stream=None):
-    """pt_index: (pt_off, pt_obs) from track_point_index."""
-    pt_off, pt_obs = pt_index
+    """pt_index: from track_point_index (its first two arrays are used)."""
+    pt_off, pt_obs = pt_index[:2]
     _check("gs_ba_lm_step", load().gs_ba_lm_step(
         ba.handle, _ptr(X), int(X.shape[0]), _ptr(viewmat), _ptr(intr), int(viewmat.shape[0]),
         _ptr(obs_cam), _ptr(obs_pt), _ptr(obs_xy), int(obs_cam.shape[0]), _ptr(pt_off),
@@ -460,20 +461,31 @@ def gs_photo_loss_grad(ctx, cams, rgb, target, lambda_ssim, v_rgb, loss, stream=
 def track_reproj_fwd_bwd(ctx, X, viewmat, intr, obs_cam, obs_pt, obs_xy, delta, lam, near_plane,
                          loss, v_X, v_twist, residual=None, J_pose=None, J_X=None, pt_index=None,
                          stream=None):
-    """pt_index: (pt_off, pt_obs) from track_point_index, or None."""
-    pt_off, pt_obs = pt_index if pt_index is not None else (None, None)
+    """pt_index: from track_point_index, (pt_off, pt_obs) or (pt_off, pt_obs,
+    pm_cam, pm_xy) with the point-major copies; or None."""
+    pt_off, pt_obs, pm_cam, pm_xy = _index_parts(pt_index)
     _check("track_reproj_fwd_bwd", load().track_reproj_fwd_bwd(
         ctx.handle, _ptr(X), int(X.shape[0]), _ptr(viewmat), _ptr(intr), int(viewmat.shape[0]),
         _ptr(obs_cam), _ptr(obs_pt), _ptr(obs_xy), int(obs_cam.shape[0]), float(delta),
         float(lam), float(near_plane), _ptr(residual), _ptr(loss), _ptr(v_X), _ptr(v_twist),
-        _ptr(J_pose), _ptr(J_X), _ptr(pt_off), _ptr(pt_obs), _stream(stream)))
+        _ptr(J_pose), _ptr(J_X), _ptr(pt_off), _ptr(pt_obs), _ptr(pm_cam), _ptr(pm_xy),
+        _stream(stream)))
+
+
+def _index_parts(pt_index):
+    if pt_index is None:
+        return None, None, None, None
+    if len(pt_index) == 2:
+        return pt_index[0], pt_index[1], None, None
+    return tuple(pt_index)
 
 
 def track_reproj_fwd_bwd_noalloc(X, viewmat, intr, obs_cam, obs_pt, obs_xy, delta, lam,
                                  near_plane, loss, v_X, v_twist, residual=None, J_pose=None,
                                  J_X=None, pt_index=None, stream=None):
-    """track_reproj_fwd_bwd without a context (the library allocates nothing)."""
-    pt_off, pt_obs = pt_index if pt_index is not None else (None, None)
+    """track_reproj_fwd_bwd without a context (the library allocates nothing);
+    point-major copies in pt_index are not used."""
+    pt_off, pt_obs = _index_parts(pt_index)[:2]
     _check("track_reproj_fwd_bwd_noalloc", load().track_reproj_fwd_bwd_noalloc(
         _ptr(X), int(X.shape[0]), _ptr(viewmat), _ptr(intr), int(viewmat.shape[0]),
         _ptr(obs_cam), _ptr(obs_pt), _ptr(obs_xy), int(obs_cam.shape[0]), float(delta),
@@ -481,16 +493,23 @@ def track_reproj_fwd_bwd_noalloc(X, viewmat, intr, obs_cam, obs_pt, obs_xy, delt
         _ptr(J_pose), _ptr(J_X), _ptr(pt_off), _ptr(pt_obs), _stream(stream)))
 
 
-def track_point_index(ctx, obs_pt, n_points, stream=None):
+def track_point_index(ctx, obs_pt, n_points, obs_cam=None, obs_xy=None, stream=None):
     """The point-major index of the observations (pt_off [Pt + 1], pt_obs [M],
-    int32 device tensors) for track_reproj_fwd_bwd's pt_index."""
+    int32 device tensors) for track_reproj_fwd_bwd's pt_index; with obs_cam and
+    obs_xy also their point-major copies (pm_cam [M], pm_xy [M, 2]), returned
+    as a 4-tuple."""
     import torch
     M = int(obs_pt.shape[0])
     pt_off = torch.empty(int(n_points) + 1, dtype=torch.int32, device=obs_pt.device)
     pt_obs = torch.empty(max(M, 1), dtype=torch.int32, device=obs_pt.device)
+    pm_cam = pm_xy = None
+    if obs_cam is not None:
+        pm_cam = torch.empty(max(M, 1), dtype=torch.int32, device=obs_pt.device)
+        pm_xy = torch.empty((max(M, 1), 2), dtype=torch.float32, device=obs_pt.device)
     _check("track_point_index", load().track_point_index(
-        ctx.handle, _ptr(obs_pt), M, int(n_points), _ptr(pt_off), _ptr(pt_obs), _stream(stream)))
-    return pt_off, pt_obs
+        ctx.handle, _ptr(obs_pt), M, int(n_points), _ptr(pt_off), _ptr(pt_obs), _ptr(obs_cam),
+        _ptr(obs_xy), _ptr(pm_cam), _ptr(pm_xy), _stream(stream)))
+    return (pt_off, pt_obs) if obs_cam is None else (pt_off, pt_obs, pm_cam, pm_xy)
 
 
 def gs_pose_compose(twist, base, out, stream=None):

@@ -206,6 +206,12 @@ gs_status gs_ctx_create(gs_ctx** out, const gs_capacity* cap) {
     const int nc = cap->max_cams > 0 ? cap->max_cams : 1;
     A(dalloc(&c.twist_render, (size_t)6 * nv));
     A(dalloc(&c.twist_track, (size_t)6 * nc));
+    // the point-major track pass: per-workgroup twist and loss sums
+    c.pm_cams = cap->max_cams > 0 ? std::min(cap->max_cams, GS_TRACK_PM_MAX_CAMS) : 0;
+    if (c.pm_cams > 0) {
+        A(dalloc(&c.track_part, (size_t)gs::kTrackPmBlocks * 6 * c.pm_cams));
+        A(dalloc(&c.track_loss_part, (size_t)gs::kTrackPmBlocks));
+    }
     A(dalloc(&c.loss_acc, 4));
     A(dalloc(&c.aux, gs::kAuxFloats));
     A(dalloc(&c.diag, gs::kDiagCount));
@@ -232,7 +238,8 @@ gs_status gs_ctx_destroy(gs_ctx* h) {
     void* ptrs[] = {c.rec, c.grad2d, c.vmu_dir, c.cnt, c.off, c.pk[0], c.pk[1], c.pv[0], c.pv[1],
                     c.ik[0], c.ik[1], c.iv[0], c.iv[1], c.im[0], c.im[1], c.tcnt, c.ccnt, c.cbase, c.bpre, c.bplace, c.tbase, c.tranges, c.tids,
                     c.ranges, c.tile_order, c.tk[0], c.tk[1], c.tile_contrib, c.tile_entries, c.tile_evals, c.hist,
-                    c.scan_scratch, c.scalars, c.twist_render, c.twist_track, c.loss_acc, c.aux, c.diag};
+                    c.scan_scratch, c.scalars, c.twist_render, c.twist_track, c.track_part,
+                    c.track_loss_part, c.loss_acc, c.aux, c.diag};
     hipDeviceSynchronize();
     for (void* p : ptrs)
         if (p) hipFree(p);
@@ -487,7 +494,8 @@ gs_status track_reproj_fwd_bwd(gs_ctx* h, const float* X, int32_t Pt, const floa
                                const int32_t* obs_pt, const float* obs_xy, int32_t M, float delta,
                                float lambda, float near_plane, float* residual, float* loss,
                                float* v_X, float* v_twist, float* J_pose, float* J_X,
-                               const int32_t* pt_off, const int32_t* pt_obs, void* stream) {
+                               const int32_t* pt_off, const int32_t* pt_obs, const int32_t* pm_cam,
+                               const float* pm_xy, void* stream) {
     if (!h || Pt < 0 || n_cams < 0 || M < 0) return GS_ERR_INVALID_ARG;
     if (M > 0 && (!X || !viewmat || !intr || !obs_cam || !obs_pt || !obs_xy)) return GS_ERR_INVALID_ARG;
     if (!(delta > 0.f) || !(near_plane > 0.f) || !isfinite(lambda)) return GS_ERR_INVALID_ARG;
@@ -495,19 +503,31 @@ gs_status track_reproj_fwd_bwd(gs_ctx* h, const float* X, int32_t Pt, const floa
     if (!v_twist && M > 0) return GS_ERR_INVALID_ARG;  // the twist accumulator must be drained
     if (!loss && M > 0) return GS_ERR_INVALID_ARG;
     if ((pt_off == nullptr) != (pt_obs == nullptr)) return GS_ERR_INVALID_ARG;  // both or neither
+    if ((pm_cam == nullptr) != (pm_xy == nullptr)) return GS_ERR_INVALID_ARG;
+    if (pm_cam && !pt_off) return GS_ERR_INVALID_ARG;  // the copies come with their index
     return from_hip(gs::launch_track(&h->c, X, Pt, viewmat, intr, n_cams, obs_cam, obs_pt, obs_xy, M,
                                      delta, lambda, near_plane, residual, loss, v_X, v_twist, J_pose,
-                                     J_X, pt_off, pt_obs, (hipStream_t)stream));
+                                     J_X, pt_off, pt_obs, pm_cam, pm_xy, (hipStream_t)stream));
 }
 
 gs_status track_point_index(gs_ctx* h, const int32_t* obs_pt, int32_t M, int32_t Pt, int32_t* pt_off,
-                            int32_t* pt_obs, void* stream) {
+                            int32_t* pt_obs, const int32_t* obs_cam, const float* obs_xy,
+                            int32_t* pm_cam, float* pm_xy, void* stream) {
     if (!h || M < 0 || Pt < 0 || !pt_off || (M > 0 && (!obs_pt || !pt_obs))) return GS_ERR_INVALID_ARG;
+    // the point-major copies: all four arrays or none (no observations: nothing
+    // to copy, any pointers); pixels read as float2
+    const int ncopy = (obs_cam != nullptr) + (obs_xy != nullptr) + (pm_cam != nullptr) + (pm_xy != nullptr);
+    if (M > 0 && ncopy != 0 && ncopy != 4) return GS_ERR_INVALID_ARG;
+    if (M > 0 && ncopy == 4 &&
+        (reinterpret_cast<uintptr_t>(obs_xy) % 8 != 0 || reinterpret_cast<uintptr_t>(pm_xy) % 8 != 0))
+        return GS_ERR_INVALID_ARG;
+    if (ncopy != 4) obs_cam = nullptr, obs_xy = nullptr, pm_cam = nullptr, pm_xy = nullptr;
     // the scan reads pt_off as 16-byte vectors
     if (reinterpret_cast<uintptr_t>(pt_off) % 16 != 0) return GS_ERR_INVALID_ARG;
     // cursors live in the pair-count buffer, the scan in the context's scratch
     if ((int64_t)Pt > h->c.cap.max_pairs || (int64_t)Pt + 1 > h->c.scan_max) return GS_ERR_CAPACITY;
-    return from_hip(gs::launch_track_index(&h->c, obs_pt, M, Pt, pt_off, pt_obs, (hipStream_t)stream));
+    return from_hip(gs::launch_track_index(&h->c, obs_pt, M, Pt, pt_off, pt_obs, obs_cam, obs_xy, pm_cam,
+                                           pm_xy, (hipStream_t)stream));
 }
 
 gs_status gs_pose_compose(int32_t V, const float* twist, const float* base, float* out, void* stream) {

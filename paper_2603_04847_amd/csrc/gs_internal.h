@@ -496,11 +496,14 @@ hipError_t launch_photo(Ctx* c, const ViewTable& vt, const float* rgb, const flo
                         float lambda, float* v_rgb, float* loss, hipStream_t st);
 
 // track.hip
+// Workgroups of the point-major track pass (each keeps its twist sums in LDS).
+constexpr int kTrackPmBlocks = 512;
 hipError_t launch_track(Ctx* c, const float* X, int Pt, const float* viewmat, const float* intr,
                         int n_cams, const int32_t* obs_cam, const int32_t* obs_pt,
                         const float* obs_xy, int M, float delta, float lambda, float near_plane,
                         float* residual, float* loss, float* v_X, float* v_twist, float* J_pose,
-                        float* J_X, const int32_t* pt_off, const int32_t* pt_obs, hipStream_t st);
+                        float* J_X, const int32_t* pt_off, const int32_t* pt_obs,
+                        const int32_t* pm_cam, const float* pm_xy, hipStream_t st);
 // The same with the accumulators given explicitly: twist_acc [n_cams][6] and
 // loss_acc [1] (double, zero on entry, left zero), diag [kDiagCount] (the
 // masked count is added to diag[kDiagMasked]).
@@ -518,9 +521,12 @@ hipError_t launch_track_scratch(const TrackScratch& sc, const float* X, int Pt, 
 hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t st);
 // Point-major index of the observations for launch_track: pt_off[Pt + 1],
 // pt_obs[M] (each point's observations ascending; out-of-range points left
-// out).  Uses c->cnt (>= Pt words) and the scan scratch (>= Pt + 1 items).
+// out), and optionally the cameras and pixels in that order (pm_cam, pm_xy
+// from obs_cam, obs_xy).  Uses c->cnt (>= Pt words) and the scan scratch
+// (>= Pt + 1 items).
 hipError_t launch_track_index(Ctx* c, const int32_t* obs_pt, int M, int Pt, int32_t* pt_off,
-                              int32_t* pt_obs, hipStream_t st);
+                              int32_t* pt_obs, const int32_t* obs_cam, const float* obs_xy,
+                              int32_t* pm_cam, float* pm_xy, hipStream_t st);
 
 // optim.hip
 hipError_t launch_pose_compose(int V, const float* twist, const float* base, float* out,
@@ -570,6 +576,9 @@ struct Ctx {
     uint32_t* scalars;     // small device counters
     double* twist_render;  // [max_views][6]
     double* twist_track;   // [max_cams][6]
+    float* track_part;     // [kTrackPmBlocks][6 pm_cams] per-workgroup twist sums (point-major pass)
+    double* track_loss_part;  // [kTrackPmBlocks] per-workgroup loss sums
+    int pm_cams;           // cameras the point-major pass can hold (0: none)
     double* loss_acc;      // [4]
     float* aux;            // [kAuxFloats] small per-call device scratch (bounding boxes, grid)
     uint32_t* diag;        // [kDiagCount]

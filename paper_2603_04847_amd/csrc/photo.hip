@@ -104,8 +104,10 @@ __global__ __launch_bounds__(kThreads) void k_photo(PhotoArgs a, Window win) {
         __syncthreads();
         // ---- horizontal window sums of x, y, x^2, y^2, x y: every row of the
         // halo, columns of the tile plus the ring
+        // consecutive lanes take consecutive rows at one column run: the odd
+        // row strides (53, 43 words) put their LDS words in distinct banks
         for (int item = tid; item < kIn * (kMid / kRunA); item += kThreads) {
-            const int r = item / (kMid / kRunA), c0 = (item % (kMid / kRunA)) * kRunA;
+            const int r = item % kIn, c0 = (item / kIn) * kRunA;
             // the run's inputs and their squares and products, formed once
             float xs[kRunA + kTaps - 1], ys[kRunA + kTaps - 1];
             float xx[kRunA + kTaps - 1], yy[kRunA + kTaps - 1], xy[kRunA + kTaps - 1];

@@ -10,6 +10,14 @@
 // scattered with three float atomics per observation (points are spread, so
 // these rarely collide), or, given a point-major index of the observations,
 // summed per point by a kernel of their own with no atomics.
+//
+// Given also the observations' cameras and pixels copied into point-major
+// order (once per scene), the whole term is one pass over the points that
+// reads every array in order: each workgroup keeps per-camera twist sums in
+// LDS (float atomics there, no global atomics), writes them out once, and a
+// second kernel sums the workgroups' rows in a fixed order in double.  Without the copies the
+// camera-major pass gathers a random point per observation and the point
+// pass a random observation per index entry.
 #include <algorithm>
 
 #include "gs_internal.h"
@@ -255,6 +263,128 @@ __global__ __launch_bounds__(kBlock) void k_track_points(
     for (int c = 0; c < 3; c++) v_X[3 * (int64_t)k + c] += acc[c];
 }
 
+// The point-major pass (see the file comment): one thread per point (grid
+// stride), its observations' terms from the point-major copies; v_X written
+// once per point; twist sums per workgroup in LDS, 6 n_cams floats.  (One
+// thread per observation, the point found by a search of the chunk's offsets
+// in LDS and its gradient gathered by LDS atomics, measured 30% slower: the
+// search is a chain of dependent LDS loads and a point's observations collide
+// on its three words.)
+__global__ __launch_bounds__(kBlock) void k_track_pm(
+    const float* __restrict__ X, int Pt, const float* __restrict__ viewmat,
+    const float* __restrict__ intr, int n_cams, const int32_t* __restrict__ pt_off,
+    const int32_t* __restrict__ pm_cam, const float* __restrict__ pm_xy, float delta, float lambda,
+    float near_plane, float* __restrict__ v_X, float* __restrict__ part,
+    double* __restrict__ loss_part, uint32_t* __restrict__ diag) {
+    extern __shared__ float s_tw[];  // [n_cams][6]
+    __shared__ float s_loss[kBlock / kWave];
+    __shared__ uint32_t s_mask[kBlock / kWave];
+    for (int q = threadIdx.x; q < 6 * n_cams; q += kBlock) s_tw[q] = 0.f;
+    __syncthreads();
+    float lo_sum = 0.f;
+    uint32_t n_masked = 0;
+    for (int k = blockIdx.x * kBlock + threadIdx.x; k < Pt; k += gridDim.x * kBlock) {
+        const int j0 = pt_off[k], j1 = pt_off[k + 1];
+        if (j0 >= j1) continue;
+        float acc[3] = {0.f, 0.f, 0.f};
+        for (int j = j0; j < j1; j++) {
+            const int ci = pm_cam[j];
+            if (ci < 0 || ci >= n_cams) continue;
+            ObsTerms T;
+            obs_terms(X, k, viewmat, intr, ci, pm_xy, j, delta, lambda, near_plane, T);
+            if (T.masked) {
+                n_masked++;
+                continue;
+            }
+            lo_sum += lambda * T.rho;
+            const float* R = T.R;
+            const float* p = T.p;
+            const float* vp = T.vp;
+#pragma unroll
+            for (int c = 0; c < 3; c++) acc[c] += R[c] * vp[0] + R[3 + c] * vp[1] + R[6 + c] * vp[2];
+            float* tw = s_tw + 6 * ci;
+            atomicAdd(tw + 0, vp[0]);
+            atomicAdd(tw + 1, vp[1]);
+            atomicAdd(tw + 2, vp[2]);
+            atomicAdd(tw + 3, p[1] * vp[2] - p[2] * vp[1]);
+            atomicAdd(tw + 4, p[2] * vp[0] - p[0] * vp[2]);
+            atomicAdd(tw + 5, p[0] * vp[1] - p[1] * vp[0]);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; c++) v_X[3 * (int64_t)k + c] += acc[c];
+    }
+    const float ls = wave_sum(lo_sum);
+    uint32_t nm = n_masked;
+    for (int off = 32; off > 0; off >>= 1) nm += __shfl_xor(nm, off, kWave);
+    if (__lane_id() == 0) {
+        s_loss[threadIdx.x / kWave] = ls;
+        s_mask[threadIdx.x / kWave] = nm;
+    }
+    __syncthreads();
+    float* row = part + (int64_t)blockIdx.x * 6 * n_cams;
+    for (int q = threadIdx.x; q < 6 * n_cams; q += kBlock) row[q] = s_tw[q];
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        uint32_t tm = 0;
+        for (int q = 0; q < kBlock / kWave; q++) {
+            tot += s_loss[q];
+            tm += s_mask[q];
+        }
+        loss_part[blockIdx.x] = tot;
+        if (tm) atomicAdd(&diag[kDiagMasked], tm);
+    }
+}
+
+// Sum of the point-major pass's workgroup rows, in double and a fixed order:
+// 64 columns per workgroup, eight waves over interleaved rows; workgroup 0
+// also sums the loss.
+constexpr int kPmReduceWaves = 8;
+
+__global__ __launch_bounds__(kWave * kPmReduceWaves) void k_track_pm_reduce(
+    const float* __restrict__ part, const double* __restrict__ loss_part, int nblk, int n6,
+    float* __restrict__ v_twist, float* __restrict__ loss) {
+    __shared__ double s[kPmReduceWaves][kWave];
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    const int q = blockIdx.x * kWave + lane;
+    double a = 0.0;
+    if (q < n6)
+        for (int b = w; b < nblk; b += kPmReduceWaves) a += part[(int64_t)b * n6 + q];
+    s[w][lane] = a;
+    __syncthreads();
+    if (w == 0 && q < n6) {
+        double t = 0.0;
+        for (int i = 0; i < kPmReduceWaves; i++) t += s[i][lane];
+        v_twist[q] += (float)t;
+    }
+    if (blockIdx.x == 0) {
+        __syncthreads();
+        double l = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += kWave * kPmReduceWaves) l += loss_part[b];
+        s[w][lane] = l;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int i = 0; i < kPmReduceWaves; i++)
+                for (int j = 0; j < kWave; j++) t += s[i][j];
+            *loss += (float)t;
+        }
+    }
+}
+
+// The observations' cameras and pixels in the index's order.
+__global__ __launch_bounds__(kBlock) void k_pm_gather(const int32_t* __restrict__ pt_off, int Pt,
+                                                      const int32_t* __restrict__ pt_obs,
+                                                      const int32_t* __restrict__ obs_cam,
+                                                      const float2* __restrict__ obs_xy,
+                                                      int32_t* __restrict__ pm_cam,
+                                                      float2* __restrict__ pm_xy) {
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= pt_off[Pt]) return;
+    const int o = pt_obs[j];
+    pm_cam[j] = obs_cam[o];
+    pm_xy[j] = obs_xy[o];
+}
+
 // The point-major index: counts per point, their scan, a fill through one
 // cursor per point, then each point's observations sorted ascending.
 __global__ __launch_bounds__(kBlock) void k_pt_count(const int32_t* __restrict__ obs_pt, int M, int Pt,
@@ -297,7 +427,22 @@ hipError_t launch_track(Ctx* c, const float* X, int Pt, const float* viewmat, co
                         int n_cams, const int32_t* obs_cam, const int32_t* obs_pt,
                         const float* obs_xy, int M, float delta, float lambda, float near_plane,
                         float* residual, float* loss, float* v_X, float* v_twist, float* J_pose,
-                        float* J_X, const int32_t* pt_off, const int32_t* pt_obs, hipStream_t st) {
+                        float* J_X, const int32_t* pt_off, const int32_t* pt_obs,
+                        const int32_t* pm_cam, const float* pm_xy, hipStream_t st) {
+    const bool pm = pm_cam && pm_xy && pt_off && pt_obs && v_X && v_twist && loss && !residual &&
+                    !J_pose && !J_X && n_cams <= c->pm_cams && c->track_part;
+    if (pm && M > 0 && Pt > 0) {
+        hipLaunchKernelGGL(k_track_pm, dim3(kTrackPmBlocks), dim3(kBlock), sizeof(float) * 6 * n_cams, st,
+                           X, Pt, viewmat, intr, n_cams, pt_off, pm_cam, pm_xy, delta, lambda, near_plane,
+                           v_X, c->track_part, c->track_loss_part, c->diag);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const int n6 = 6 * n_cams;
+        hipLaunchKernelGGL(k_track_pm_reduce, dim3((unsigned)std::max((n6 + kWave - 1) / kWave, 1)),
+                           dim3(kWave * kPmReduceWaves), 0, st, c->track_part, c->track_loss_part,
+                           kTrackPmBlocks, n6, v_twist, loss);
+        return hipGetLastError();
+    }
     const TrackScratch sc = {c->twist_track, c->loss_acc + 1, c->diag};
     return launch_track_scratch(sc, X, Pt, viewmat, intr, n_cams, obs_cam, obs_pt, obs_xy, M, delta,
                                 lambda, near_plane, residual, loss, v_X, v_twist, J_pose, J_X, pt_off,
@@ -336,7 +481,8 @@ hipError_t launch_track_scratch(const TrackScratch& sc, const float* X, int Pt, 
 }
 
 hipError_t launch_track_index(Ctx* c, const int32_t* obs_pt, int M, int Pt, int32_t* pt_off,
-                              int32_t* pt_obs, hipStream_t st) {
+                              int32_t* pt_obs, const int32_t* obs_cam, const float* obs_xy,
+                              int32_t* pm_cam, float* pm_xy, hipStream_t st) {
     // counts in pt_off[0, Pt) (pt_off[Pt] = 0), their exclusive scan (pt_off[Pt]
     // becomes the number indexed), then the fill through cursors in c->cnt
     hipError_t e;
@@ -357,7 +503,13 @@ hipError_t launch_track_index(Ctx* c, const int32_t* obs_pt, int M, int Pt, int3
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_pt_sort, dim3(gp), dim3(kBlock), 0, st, Pt, pt_off, pt_obs);
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (pm_cam && obs_cam && M > 0) {
+        hipLaunchKernelGGL(k_pm_gather, dim3(gm), dim3(kBlock), 0, st, pt_off, Pt, pt_obs, obs_cam,
+                           reinterpret_cast<const float2*>(obs_xy), pm_cam, reinterpret_cast<float2*>(pm_xy));
+        return hipGetLastError();
+    }
+    return hipSuccess;
 }
 
 }  // namespace gs

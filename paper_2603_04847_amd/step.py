@@ -77,11 +77,12 @@ class JointStep:
         self._cap = dict(max_pairs=Vb * self.N, max_tiles=tiles, max_views=Vb,
                          max_cams=self.n_cams)
         self.ctx = L.Context(max_isect=max_isect or 32 * P, **self._cap)
-        # the observations' point-major index (fixed for the scene): the track
-        # term then sums each point's gradient without atomics; a context too
-        # small to build it keeps the atomic path
+        # the observations' point-major index and copies (fixed for the scene):
+        # the track term is then one in-order pass over the points without
+        # atomics; a context too small to build it keeps the atomic path
         try:
-            self.pt_index = L.track_point_index(self.ctx, self.obs_pt, int(self.X.shape[0]))
+            self.pt_index = L.track_point_index(self.ctx, self.obs_pt, int(self.X.shape[0]),
+                                                self.obs_cam, self.obs_xy)
         except L.GsError as e:
             if e.code != L.GS_ERR_CAPACITY:
                 raise
@@ -175,6 +176,38 @@ class JointStep:
         with t("pose_compose_bwd"):
             L.gs_pose_compose_bwd(self.twist, self.v_tw_cur, self.v_tw)
         del P
+
+    def save_state(self, path):
+        """Checkpoint to an .npz file: every optimised array (the Gaussians,
+        the camera twists, the track points), its two Adam moments, the base
+        poses and both step counters (host and device).  Plain arrays only,
+        nothing pickled."""
+        arrs = {}
+        for k, v in self._opt_params().items():
+            arrs["param/" + k] = v.detach().cpu().numpy()
+            arrs["m/" + k] = self.m[k].cpu().numpy()
+            arrs["v/" + k] = self.v[k].cpu().numpy()
+        arrs["base_viewmat"] = self.base.cpu().numpy()
+        arrs["sh_degree"] = np.array([self.sh_degree], np.int64)
+        arrs["step"] = np.array([self.step_count, int(self.d_step.item())], np.int64)
+        np.savez(path, **arrs)
+
+    def load_state(self, path):
+        """Restore a checkpoint written by save_state into this step's arrays,
+        in place (captured graphs keep pointing at them).  Shapes must match."""
+        with np.load(path, allow_pickle=False) as z:
+            if int(z["sh_degree"][0]) != self.sh_degree:
+                raise ValueError("checkpoint has another SH degree")
+            for k, v in self._opt_params().items():
+                for name, dst in (("param/", v), ("m/", self.m[k]), ("v/", self.v[k])):
+                    a = z[name + k]
+                    if tuple(a.shape) != tuple(dst.shape):
+                        raise ValueError(f"checkpoint {name}{k} has shape {a.shape}, not {tuple(dst.shape)}")
+                    dst.copy_(torch.from_numpy(a))
+            self.base.copy_(torch.from_numpy(z["base_viewmat"]))
+            host, dev = (int(x) for x in z["step"])
+        self.d_step.fill_(dev)
+        self.step_count = host
 
     def set_step(self, n):
         """Set the device step counter (the next `run` takes step n + 1)."""

@@ -103,9 +103,10 @@ def test_track_without_observations(gs):
     obs_pt = torch.zeros(0, dtype=torch.int32, device="cuda")
     obs_xy = torch.zeros((0, 2), device="cuda")
     index = gs.track_point_index(ctx, obs_pt, Pt)
+    index_pm = gs.track_point_index(ctx, obs_pt, Pt, obs_cam, obs_xy)
     torch.cuda.synchronize()
     assert not torch.any(index[0] != 0).item()
-    for pi in (None, index):
+    for pi in (None, index, index_pm):
         loss = torch.zeros(1, device="cuda")
         v_X = torch.zeros((Pt, 3), device="cuda")
         v_tw = torch.zeros((C, 6), device="cuda")

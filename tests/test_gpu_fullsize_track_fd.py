@@ -49,20 +49,22 @@ def test_track_term_full_size(gs, name):
     print(f"[track] {name}: {M} observations, {C} cameras, {Pt} points", flush=True)
     o = oracle.track(X, vm, intr, cam, pt, xy, delta=1.0, lam=1e-4, jacobians=False)
     ctx = gs.Context(max_pairs=Pt + 1, max_isect=1 << 10, max_tiles=16, max_views=1, max_cams=C)
-    obs_pt = _t(pt, torch.int32)
+    obs_pt, obs_cam, obs_xy = _t(pt, torch.int32), _t(cam, torch.int32), _t(xy)
     index = gs.track_point_index(ctx, obs_pt, Pt)
-    for pi in (None, index):
+    index_pm = gs.track_point_index(ctx, obs_pt, Pt, obs_cam, obs_xy)
+    for what, pi in (("atomic", None), ("indexed", index), ("point-major", index_pm)):
         loss = torch.zeros(1, device="cuda")
         v_X = torch.zeros((Pt, 3), device="cuda")
         v_tw = torch.zeros((C, 6), device="cuda")
-        res = torch.empty((M, 2), device="cuda")
+        # the point-major pass runs when no residual is asked for
+        res = torch.empty((M, 2), device="cuda") if what != "point-major" else None
         ctx.reset_status()
-        gs.track_reproj_fwd_bwd(ctx, _t(X), _t(vm), _t(intr), _t(cam, torch.int32), obs_pt, _t(xy), 1.0,
+        gs.track_reproj_fwd_bwd(ctx, _t(X), _t(vm), _t(intr), obs_cam, obs_pt, obs_xy, 1.0,
                                 1e-4, 0.01, loss, v_X, v_tw, residual=res, pt_index=pi)
         torch.cuda.synchronize()
-        what = "indexed" if pi is not None else "atomic"
         assert ctx.status()["n_masked_obs"] == int(o["masked"].sum())
-        _close(res.cpu().numpy(), o["residual"], f"{what} residual")
+        if res is not None:
+            _close(res.cpu().numpy(), o["residual"], f"{what} residual")
         assert abs(loss.item() - o["loss"]) <= 1e-4 * o["loss"], what
         _close(v_X.cpu().numpy(), o["v_X"], f"{what} v_X")
         tw = v_tw.cpu().numpy()

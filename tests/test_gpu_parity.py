@@ -618,14 +618,21 @@ def test_track_point_index_is_a_stable_csr(gs):
     Pt, M = 5000, 40000
     obs_pt = rng.integers(-3, Pt + 3, size=M).astype(np.int32)
     ctx = gs.Context(max_pairs=Pt, max_isect=1 << 16, max_tiles=16, max_views=1, max_cams=8)
-    pt_off, pt_obs = gs.track_point_index(ctx, _t(obs_pt, torch.int32), Pt)
+    cam = rng.integers(0, 8, size=M).astype(np.int32)
+    xy = rng.uniform(0, 500, size=(M, 2)).astype(np.float32)
+    pt_off, pt_obs, pm_cam, pm_xy = gs.track_point_index(ctx, _t(obs_pt, torch.int32), Pt,
+                                                         _t(cam, torch.int32), _t(xy))
     torch.cuda.synchronize()
     ok = (obs_pt >= 0) & (obs_pt < Pt)
-    order = np.argsort(np.where(ok, obs_pt, Pt), kind="stable")[: int(ok.sum())]
+    n = int(ok.sum())
+    order = np.argsort(np.where(ok, obs_pt, Pt), kind="stable")[:n]
     counts = np.bincount(obs_pt[ok], minlength=Pt)
     off_ref = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
     assert np.array_equal(pt_off.cpu().numpy(), off_ref)
-    assert np.array_equal(pt_obs.cpu().numpy()[: int(ok.sum())], order.astype(np.int32))
+    assert np.array_equal(pt_obs.cpu().numpy()[:n], order.astype(np.int32))
+    # the point-major copies of the cameras and pixels, bit for bit
+    assert np.array_equal(pm_cam.cpu().numpy()[:n], cam[order])
+    assert np.array_equal(pm_xy.cpu().numpy()[:n], xy[order])
 
 
 def test_track_with_point_index_matches_oracle(gs):
@@ -639,22 +646,59 @@ def test_track_with_point_index_matches_oracle(gs):
     ctx = gs.Context(max_pairs=X.shape[0], max_isect=1 << 16, max_tiles=16, max_views=1, max_cams=8)
     o = oracle.track(X, vm, intr, sc["obs_cam"], sc["obs_pt"], sc["obs_xy"], delta=1.0, lam=1e-4)
     obs_pt = _t(sc["obs_pt"], torch.int32)
+    obs_cam, obs_xy = _t(sc["obs_cam"], torch.int32), _t(sc["obs_xy"])
     index = gs.track_point_index(ctx, obs_pt, X.shape[0])
+    index_pm = gs.track_point_index(ctx, obs_pt, X.shape[0], obs_cam, obs_xy)
     out = {}
-    for name, pi in (("atomic", None), ("indexed", index)):
+    for name, pi in (("atomic", None), ("indexed", index), ("point-major", index_pm)):
         loss = torch.zeros(1, device="cuda")
         v_X = torch.zeros((X.shape[0], 3), device="cuda")
         v_tw = torch.zeros((5, 6), device="cuda")
-        res = torch.empty((len(sc["obs_cam"]), 2), device="cuda")
-        gs.track_reproj_fwd_bwd(ctx, _t(X), _t(vm), _t(intr), _t(sc["obs_cam"], torch.int32), obs_pt,
-                                _t(sc["obs_xy"]), 1.0, 1e-4, 0.01, loss, v_X, v_tw, residual=res,
-                                pt_index=pi)
-        out[name] = (loss.item(), v_X.cpu().numpy(), v_tw.cpu().numpy(), res.cpu().numpy())
+        # the point-major pass writes no residual (asking for one selects the
+        # other paths)
+        res = torch.empty((len(sc["obs_cam"]), 2), device="cuda") if name != "point-major" else None
+        ctx.reset_status()
+        gs.track_reproj_fwd_bwd(ctx, _t(X), _t(vm), _t(intr), obs_cam, obs_pt, obs_xy, 1.0, 1e-4, 0.01,
+                                loss, v_X, v_tw, residual=res, pt_index=pi)
+        torch.cuda.synchronize()
+        assert ctx.status()["n_masked_obs"] == int(o["masked"].sum()) > 0, name
+        out[name] = (loss.item(), v_X.cpu().numpy(), v_tw.cpu().numpy(),
+                     res.cpu().numpy() if res is not None else None)
     la, vXa, twa, ra = out["atomic"]
     li, vXi, twi, ri = out["indexed"]
     _close(vXi, o["v_X"], what="v_X indexed")
     _close(vXi, vXa, what="v_X indexed vs atomic")
     assert np.array_equal(ri, ra) and np.array_equal(twi, twa) and li == la
+    lp, vXp, twp, _ = out["point-major"]
+    _close(vXp, o["v_X"], what="v_X point-major")
+    for v in range(5):
+        _close(twp[v], o["v_twist"][v], what=f"twist {v} point-major")
+    assert abs(lp - o["loss"]) <= RTOL * o["loss"]
+
+
+def test_track_point_major_past_the_camera_limit(gs):
+    """More cameras than the point-major pass holds in LDS: the call takes
+    the indexed path and the results still match the oracle."""
+    sc = scenegen.make_config("C1")
+    X = sc["X"]
+    C = 2100                                             # > GS_TRACK_PM_MAX_CAMS
+    vm = np.concatenate([sc["track_viewmat"]] * (C // 5 + 1))[:C]
+    intr = np.concatenate([sc["track_intr"]] * (C // 5 + 1))[:C]
+    rng = np.random.default_rng(3)
+    cam = (sc["obs_cam"] + 5 * rng.integers(0, C // 5, size=len(sc["obs_cam"]))).astype(np.int32)
+    ctx = gs.Context(max_pairs=X.shape[0], max_isect=1 << 16, max_tiles=16, max_views=1, max_cams=C)
+    o = oracle.track(X, vm, intr, cam, sc["obs_pt"], sc["obs_xy"], delta=1.0, lam=1e-4, jacobians=False)
+    obs_pt, obs_cam, obs_xy = _t(sc["obs_pt"], torch.int32), _t(cam, torch.int32), _t(sc["obs_xy"])
+    index_pm = gs.track_point_index(ctx, obs_pt, X.shape[0], obs_cam, obs_xy)
+    loss = torch.zeros(1, device="cuda")
+    v_X = torch.zeros((X.shape[0], 3), device="cuda")
+    v_tw = torch.zeros((C, 6), device="cuda")
+    gs.track_reproj_fwd_bwd(ctx, _t(X), _t(vm), _t(intr), obs_cam, obs_pt, obs_xy, 1.0, 1e-4, 0.01,
+                            loss, v_X, v_tw, pt_index=index_pm)
+    torch.cuda.synchronize()
+    _close(v_X.cpu().numpy(), o["v_X"], what="v_X")
+    _close(v_tw.cpu().numpy(), o["v_twist"], what="twists")
+    assert abs(loss.item() - o["loss"]) <= RTOL * o["loss"]
 
 
 def test_pose_compose_and_backward(gs):

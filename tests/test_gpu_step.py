@@ -294,3 +294,41 @@ def test_two_forwards_then_backward(gs):
         _close(params[k].grad.cpu().numpy(), g0[k] + g1[k], k)
     want = np.concatenate([g0["twist"], g1["twist"]])  # J_l(0) = I
     _close(tw.grad.cpu().numpy(), want, "twist")
+
+
+def test_checkpoint_round_trip(gs, tmp_path):
+    """save_state / load_state: two steps, a checkpoint, a third step; then
+    the checkpoint loaded back into a step perturbed by two more steps and the
+    third step taken again from it: the same parameters, moments and step
+    counters (to the atomics' summation-order rounding)."""
+    from paper_2603_04847_amd.step import JointStep
+    sc = scenegen.blob_scene(9, [(150, 110)] * 4, 8000, sh_degree=3)
+    rng = sc.pop("_rng")
+    sc.update(scenegen.make_tracks(rng, 1500, sc["viewmat"], sc["intr"], sc["wh"], 10))
+    batches = [np.array([0, 3]), np.array([1, 2])]
+    targets = [scenegen.view_targets(9, sc["wh"], b) for b in batches]
+    st = JointStep(sc, batches, targets, max_isect=3_000_000)
+    st.run(0)
+    st.run(1)
+    f = tmp_path / "state.npz"
+    st.save_state(str(f))
+    st.run(0)
+    torch.cuda.synchronize()
+    want = {k: (v.detach().cpu().numpy().copy(), st.m[k].cpu().numpy().copy(), st.v[k].cpu().numpy().copy())
+            for k, v in st._opt_params().items()}
+    st.run(1)
+    st.run(0)
+    st.load_state(str(f))
+    assert st.step_count == 2 and int(st.d_step.item()) == 2
+    st.run(0)
+    torch.cuda.synchronize()
+    assert st.step_count == 3 and int(st.d_step.item()) == 3
+    for k, v in st._opt_params().items():
+        for got, ref, what in ((v.detach().cpu().numpy(), want[k][0], "param"),
+                               (st.m[k].cpu().numpy(), want[k][1], "m"),
+                               (st.v[k].cpu().numpy(), want[k][2], "v")):
+            bad = np.abs(got - ref) > 1e-5 * (1e-3 + np.abs(ref))
+            assert np.mean(bad) < 2e-3, (k, what)
+    with np.load(str(f), allow_pickle=False) as z:
+        assert set(z["step"].tolist()) == {2}
+        assert z["param/sh"].shape == tuple(st.params["sh"].shape)
