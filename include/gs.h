@@ -349,7 +349,9 @@ gs_status gs_init_gaussians(gs_ctx* ctx, const float* points, const float* rgb, 
  * (gs_pose_compose) and X_k <- X_k + d_X_k.
  * X[Pt][3], viewmat[n_cams][12], intr[n_cams][4]; observations SORTED BY
  * CAMERA (otherwise stats[4] = 1 and the step is zero); pt_off / pt_obs: the
- * point-major index of the observations from track_point_index.
+ * point-major index of the observations from track_point_index; pm_cam /
+ * pm_xy (both NULL, or both set): its point-major copies of obs_cam and
+ * obs_xy, which the passes over the points then read in order.
  * Outputs: d_twist[n_cams][6], d_X[Pt][3] (device floats, overwritten); stats
  * (device float[5], may be NULL): iterations run, final relative residual,
  * the robust cost sum rho before the step, masked observations, unsorted
@@ -363,9 +365,10 @@ gs_status gs_ba_destroy(gs_ba* ba);
 gs_status gs_ba_lm_step(gs_ba* ba, const float* X, int32_t Pt, const float* viewmat,
                         const float* intr, int32_t n_cams, const int32_t* obs_cam,
                         const int32_t* obs_pt, const float* obs_xy, int32_t M,
-                        const int32_t* pt_off, const int32_t* pt_obs, float delta,
-                        float lm_lambda, float near_plane, int32_t max_iter, float tol,
-                        float* d_twist, float* d_X, float* stats, void* stream);
+                        const int32_t* pt_off, const int32_t* pt_obs, const int32_t* pm_cam,
+                        const float* pm_xy, float delta, float lm_lambda, float near_plane,
+                        int32_t max_iter, float tol, float* d_twist, float* d_X, float* stats,
+                        void* stream);
 
 /* Track reprojection (Sec. 3.3 eq. L_BA^joint; Algorithm 1, joint BA loss):
  * for each observation o = (camera obs_cam[o], point obs_pt[o], pixel

@@ -146,9 +146,9 @@ def load():
     lib.gs_ba_create.argtypes = [ctypes.POINTER(c_vp), ctypes.c_int64, ctypes.c_int32]
     lib.gs_ba_destroy.argtypes = [c_vp]
     lib.gs_ba_lm_step.argtypes = [c_vp, c_vp, ctypes.c_int32, c_vp, c_vp, ctypes.c_int32, c_vp, c_vp,
-                                  c_vp, ctypes.c_int32, c_vp, c_vp, ctypes.c_float, ctypes.c_float,
-                                  ctypes.c_float, ctypes.c_int32, ctypes.c_float, c_vp, c_vp, c_vp,
-                                  c_vp]
+                                  c_vp, ctypes.c_int32, c_vp, c_vp, c_vp, c_vp, ctypes.c_float,
+                                  ctypes.c_float, ctypes.c_float, ctypes.c_int32, ctypes.c_float, c_vp,
+                                  c_vp, c_vp, c_vp]
     lib.gs_init_gaussians.argtypes = [c_vp, c_vp, c_vp, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.c_float, ctypes.c_int32, c_vp, c_vp, c_vp, c_vp,
                                       c_vp, c_vp]
@@ -426,13 +426,14 @@ class BundleAdjuster:
 
 def gs_ba_lm_step(ba, X, viewmat, intr, obs_cam, obs_pt, obs_xy, pt_index, delta, lm_lambda,
                   near_plane, max_iter, tol, d_twist, d_X, stats=None, stream=None):
-    """pt_index: from track_point_index (its first two arrays are used)."""
-    pt_off, pt_obs = pt_index[:2]
+    """pt_index: from track_point_index, with or without the point-major
+    copies (with them the passes over the points read them in order)."""
+    pt_off, pt_obs, pm_cam, pm_xy = _index_parts(pt_index)
     _check("gs_ba_lm_step", load().gs_ba_lm_step(
         ba.handle, _ptr(X), int(X.shape[0]), _ptr(viewmat), _ptr(intr), int(viewmat.shape[0]),
         _ptr(obs_cam), _ptr(obs_pt), _ptr(obs_xy), int(obs_cam.shape[0]), _ptr(pt_off),
-        _ptr(pt_obs), float(delta), float(lm_lambda), float(near_plane), int(max_iter),
-        float(tol), _ptr(d_twist), _ptr(d_X), _ptr(stats), _stream(stream)))
+        _ptr(pt_obs), _ptr(pm_cam), _ptr(pm_xy), float(delta), float(lm_lambda), float(near_plane),
+        int(max_iter), float(tol), _ptr(d_twist), _ptr(d_X), _ptr(stats), _stream(stream)))
 
 
 def gs_init_gaussians(ctx, points, rgb, sh_degree=3, k=4, opacity=0.1, out=None, stream=None):

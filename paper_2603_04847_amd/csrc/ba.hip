@@ -157,7 +157,7 @@ __global__ __launch_bounds__(kBlock) void k_ba_points(BaObs a, const int32_t* __
     if (k < a.Pt) {
         double V[6] = {0, 0, 0, 0, 0, 0}, g[3] = {0, 0, 0};
         for (int j = pt_off[k]; j < pt_off[k + 1]; j++) {
-            const int o = pt_obs[j];
+            const int o = pt_obs ? pt_obs[j] : j;  // no index: the arrays are point-major
             const int ci = a.obs_cam[o];
             if (ci < 0 || ci >= a.n_cams) continue;
             Lin L;
@@ -365,7 +365,7 @@ __global__ __launch_bounds__(kBlock) void k_ba_pt_apply(BaObs a, const int32_t* 
     if (k >= a.Pt) return;
     double t[3] = {0, 0, 0};
     for (int j = pt_off[k]; j < pt_off[k + 1]; j++) {
-        const int o = pt_obs[j];
+        const int o = pt_obs ? pt_obs[j] : j;  // no index: the arrays are point-major
         const int ci = a.obs_cam[o];
         if (ci < 0 || ci >= a.n_cams) continue;
         Lin L;
@@ -519,16 +519,25 @@ hipError_t launch_ba_step(gs_ba* ba, const BaInputs& in, float* d_twist, float* 
     a.delta = in.delta;
     a.near_plane = in.near_plane;
     a.lambda = in.lambda;
+    // the point passes read the point-major copies in order when there are
+    // some (no index then), else the caller's arrays through the index
+    BaObs ap = a;
+    const int32_t* pidx = in.pt_obs;
+    if (in.pm_cam && in.pm_xy) {
+        ap.obs_cam = in.pm_cam;
+        ap.obs_xy = in.pm_xy;
+        pidx = nullptr;
+    }
     const unsigned gp = (unsigned)std::max((in.Pt + kBlock - 1) / kBlock, 1);
     const unsigned gr = (unsigned)std::min(std::max((std::max(in.M, in.n_cams + 1) + kBlock - 1) / kBlock, 1), 4096);
     hipLaunchKernelGGL(k_ba_clear, dim3(1), dim3(64), 0, st, ba->sc);
     hipLaunchKernelGGL(k_ba_ranges, dim3(gr), dim3(kBlock), 0, st, a, ba->cam_off, ba->sc);
-    hipLaunchKernelGGL(k_ba_points, dim3(gp), dim3(kBlock), 0, st, a, in.pt_off, in.pt_obs, ba->pt, ba->sc);
+    hipLaunchKernelGGL(k_ba_points, dim3(gp), dim3(kBlock), 0, st, ap, in.pt_off, pidx, ba->pt, ba->sc);
     if (in.n_cams > 0)
         hipLaunchKernelGGL(k_ba_cams, dim3(in.n_cams), dim3(kBlock), 0, st, a, ba->cam_off, ba->pt, ba->cam);
     hipLaunchKernelGGL(k_ba_pcg_init, dim3(1), dim3(kVec), 0, st, in.n_cams, ba->cam, ba->sc);
     for (int it = 0; it < in.max_iter; it++) {
-        hipLaunchKernelGGL(k_ba_pt_apply, dim3(gp), dim3(kBlock), 0, st, a, in.pt_off, in.pt_obs, ba->cam,
+        hipLaunchKernelGGL(k_ba_pt_apply, dim3(gp), dim3(kBlock), 0, st, ap, in.pt_off, pidx, ba->cam,
                            oP, ba->pt, ba->sc, 0);
         if (in.n_cams > 0)
             hipLaunchKernelGGL(k_ba_cam_apply, dim3(in.n_cams), dim3(kBlock), 0, st, a, ba->cam_off, ba->pt,
@@ -537,7 +546,7 @@ hipError_t launch_ba_step(gs_ba* ba, const BaInputs& in, float* d_twist, float* 
                            (double)in.tol * (double)in.tol);
     }
     // back-substitution for the points with the final camera step
-    hipLaunchKernelGGL(k_ba_pt_apply, dim3(gp), dim3(kBlock), 0, st, a, in.pt_off, in.pt_obs, ba->cam, oX,
+    hipLaunchKernelGGL(k_ba_pt_apply, dim3(gp), dim3(kBlock), 0, st, ap, in.pt_off, pidx, ba->cam, oX,
                        ba->pt, ba->sc, 1);
     const int nout = std::max(6 * in.n_cams, 3 * in.Pt);
     hipLaunchKernelGGL(k_ba_finish, dim3((unsigned)std::max((nout + kBlock - 1) / kBlock, 1)), dim3(kBlock), 0, st,
@@ -584,14 +593,16 @@ gs_status gs_ba_destroy(gs_ba* b) {
 gs_status gs_ba_lm_step(gs_ba* b, const float* X, int32_t Pt, const float* viewmat, const float* intr,
                         int32_t n_cams, const int32_t* obs_cam, const int32_t* obs_pt,
                         const float* obs_xy, int32_t M, const int32_t* pt_off, const int32_t* pt_obs,
-                        float delta, float lm_lambda, float near_plane, int32_t max_iter, float tol,
-                        float* d_twist, float* d_X, float* stats, void* stream) {
+                        const int32_t* pm_cam, const float* pm_xy, float delta, float lm_lambda,
+                        float near_plane, int32_t max_iter, float tol, float* d_twist, float* d_X,
+                        float* stats, void* stream) {
     if (!b || Pt < 0 || n_cams < 0 || M < 0 || max_iter < 0) return GS_ERR_INVALID_ARG;
     if ((int64_t)Pt > b->max_points || n_cams > b->max_cams) return GS_ERR_CAPACITY;
     if (!(delta > 0.f) || !(lm_lambda > 0.f) || !(near_plane > 0.f) || !(tol >= 0.f)) return GS_ERR_INVALID_ARG;
     if ((n_cams > 0 && (!viewmat || !intr || !d_twist)) || (Pt > 0 && (!X || !pt_off || !d_X)) ||
         (M > 0 && (!obs_cam || !obs_pt || !obs_xy || !pt_obs)))
         return GS_ERR_INVALID_ARG;
+    if ((pm_cam == nullptr) != (pm_xy == nullptr)) return GS_ERR_INVALID_ARG;  // both or neither
     gs::BaInputs in;
     in.X = X;
     in.viewmat = viewmat;
@@ -601,6 +612,8 @@ gs_status gs_ba_lm_step(gs_ba* b, const float* X, int32_t Pt, const float* viewm
     in.obs_xy = obs_xy;
     in.pt_off = pt_off;
     in.pt_obs = pt_obs;
+    in.pm_cam = pm_cam;
+    in.pm_xy = pm_xy;
     in.Pt = Pt;
     in.n_cams = n_cams;
     in.M = M;

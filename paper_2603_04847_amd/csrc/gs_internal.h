@@ -485,6 +485,8 @@ struct BaInputs {
     const float* obs_xy;
     const int32_t* pt_off;
     const int32_t* pt_obs;
+    const int32_t* pm_cam;  // point-major copies (or NULL: read through pt_obs)
+    const float* pm_xy;
     int Pt, n_cams, M, max_iter;
     float delta, lambda, near_plane, tol;
 };

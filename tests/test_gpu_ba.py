@@ -36,16 +36,19 @@ def _close(a, b, what, rtol=1e-4):
     assert err <= rtol * np.max(np.abs(b)), f"{what}: {err:.3e} vs {rtol * np.max(np.abs(b)):.3e}"
 
 
-def _step(gs, X, vm, intr, cam, pt, xy, lm_lambda, max_iter=500, tol=1e-12):
+def _step(gs, X, vm, intr, cam, pt, xy, lm_lambda, max_iter=500, tol=1e-12, copies=True):
+    """One step; with `copies` the index carries the point-major copies of
+    the cameras and pixels (the passes over the points read those)."""
     Pt, C = X.shape[0], vm.shape[0]
     ctx = gs.Context(max_pairs=Pt + 1, max_isect=1 << 10, max_tiles=16, max_views=1, max_cams=C)
-    obs_pt = _t(pt, torch.int32)
-    index = gs.track_point_index(ctx, obs_pt, Pt)
+    obs_pt, obs_cam, obs_xy = _t(pt, torch.int32), _t(cam, torch.int32), _t(xy)
+    index = (gs.track_point_index(ctx, obs_pt, Pt, obs_cam, obs_xy) if copies
+             else gs.track_point_index(ctx, obs_pt, Pt))
     ba = gs.BundleAdjuster(Pt, C)
     dtw = torch.empty((C, 6), device="cuda")
     dX = torch.empty((Pt, 3), device="cuda")
     stats = torch.zeros(5, device="cuda")
-    gs.gs_ba_lm_step(ba, _t(X), _t(vm), _t(intr), _t(cam, torch.int32), obs_pt, _t(xy), index, 1.0,
+    gs.gs_ba_lm_step(ba, _t(X), _t(vm), _t(intr), obs_cam, obs_pt, obs_xy, index, 1.0,
                      lm_lambda, 0.01, max_iter, tol, dtw, dX, stats)
     torch.cuda.synchronize()
     return dtw.cpu().numpy(), dX.cpu().numpy(), stats.cpu().numpy()
@@ -70,10 +73,11 @@ def _problem():
             sc["obs_pt"], sc["obs_xy"])
 
 
+@pytest.mark.parametrize("copies", [False, True])
 @pytest.mark.parametrize("lm_lambda", [1e-3, 1.0])
-def test_ba_step_matches_oracle(gs, lm_lambda):
+def test_ba_step_matches_oracle(gs, lm_lambda, copies):
     X, vm, intr, cam, pt, xy = _problem()
-    dtw, dX, stats = _step(gs, X, vm, intr, cam, pt, xy, lm_lambda)
+    dtw, dX, stats = _step(gs, X, vm, intr, cam, pt, xy, lm_lambda, copies=copies)
     otw, oX, cost = oracle.ba_step(X, vm, intr, cam, pt, xy, lm_lambda=lm_lambda)
     print(f"[ba] lambda {lm_lambda}: {int(stats[0])} PCG iterations, residual {stats[1]:.2e}", flush=True)
     assert stats[1] <= 1e-8 and stats[4] == 0
