@@ -695,7 +695,7 @@ CALL_KERNELS = {
     "raster_bwd": lambda k: k.startswith("k_render_bwd<"),
     "photo": lambda k: k == "k_photo",
     "project_bwd_adam": lambda k: k in ("k_project_bwd_color<3, true>", "k_project_bwd_geom<true>"),
-    "track": lambda k: k in ("k_track", "k_track_points"),
+    "track": lambda k: k in ("k_track", "k_track_points", "k_track_pm", "k_track_pm_reduce"),
     "adam": lambda k: k == "k_adam",
 }
 
@@ -834,6 +834,53 @@ def summarize_counters(raw, workload):
     print(json.dumps(traffic, indent=1))
 
 
+def summarize_trace(raw, workload, cmd):
+    """profiles/joint_step_<workload>_kernel_trace.md from a rocprofv3
+    --kernel-trace --stats run of this bench (`cmd`): per kernel, launches and
+    durations, and the live HIP-event time of the dominant kernel from the same
+    run's bench line beside the trace's average for it."""
+    import csv
+    import glob
+    f = glob.glob(os.path.join(raw, "**", "*kernel_stats.csv"), recursive=True)
+    if not f:
+        raise SystemExit(f"no kernel_stats.csv under {raw}")
+    rows = list(csv.DictReader(open(f[0])))
+    line = None
+    for ln in open(os.path.join(raw + ".json")) if os.path.exists(raw + ".json") else []:
+        if ln.startswith("{"):
+            line = json.loads(ln)
+    md = [f"# Joint step, {workload}: per-kernel durations (rocprofv3 kernel trace)", "",
+          "Command (the repository at /root/repo; the bench line goes to the .json beside the "
+          "trace directory):", "", "```", cmd, "```", "",
+          f"Summary written by `python bench.py --summarize-trace {raw} --workload {workload}`.", "",
+          "| kernel | calls | total ms | avg us | min us | max us | % |",
+          "|---|---:|---:|---:|---:|---:|---:|"]
+    trace_avg = {}
+    for r in rows:
+        name = _short_kernel(r["Name"])
+        trace_avg[name] = float(r["AverageNs"]) / 1e3
+        if float(r["Percentage"]) < 0.05:
+            continue
+        md.append(f"| `{name[:70]}` | {r['Calls']} | {int(r['TotalDurationNs']) / 1e6:.3f} | "
+                  f"{float(r['AverageNs']) / 1e3:.1f} | {int(r['MinNs']) / 1e3:.1f} | "
+                  f"{int(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    if line:
+        roof = line.get("roofline") or {}
+        dom = roof.get("kernel")
+        kname = {"raster_bwd": "k_render_bwd", "render_fwd": "k_render_fwd"}.get(dom)
+        tr = [v for k, v in trace_avg.items() if kname and k.startswith(kname) and not k.endswith("true>")]
+        md += ["", f"Workload: {line['config']['workload']}; tile {line['config']['tile']}, order "
+               f"{line['config']['tile_order']}.", "",
+               f"Agreement with the live timing: the same run's bench line measured `{dom}` at "
+               f"{roof.get('avg_ms', 0) * 1e3:.1f} us per call (HIP events on its stream, under the "
+               f"profiler: {line['value']} MP/s); the trace average of its kernel is "
+               + (f"{max(tr):.1f} us." if tr else "not found.")]
+    out = os.path.join(ROOT, "profiles", f"joint_step_{workload}_kernel_trace.md")
+    with open(out, "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    print(out)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -856,9 +903,16 @@ def main():
     ap.add_argument("--summarize-counters", default=None, metavar="DIR",
                     help="write the counter summaries under profiles/ from the rocprofv3 passes in DIR "
                          "(no GPU needed) and exit")
+    ap.add_argument("--summarize-trace", default=None, metavar="DIR",
+                    help="write profiles/joint_step_<workload>_kernel_trace.md from the rocprofv3 "
+                         "kernel trace in DIR (and the bench line in DIR.json) and exit")
+    ap.add_argument("--trace-cmd", default="", help="the command that made the trace (for the summary)")
     args = ap.parse_args()
     if args.summarize_counters:
         summarize_counters(args.summarize_counters, args.workload)
+        return
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, args.workload, args.trace_cmd)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the hot path "
