@@ -377,26 +377,20 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_color(gs_gaussians g, co
                                  double* __restrict__ twist_acc) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     if (ADAM) adam_bias(adam.step_dev, adam.step, adam.b1, adam.b2, adam.ibc1, adam.ibc2);
-    __shared__ float s_tw[kBlock / kWave][6];
     __shared__ double s_acc[6 * GS_MAX_VIEWS];  // this block's twist sums, all iterations
     for (int k = threadIdx.x; k < 6 * vt.V; k += kBlock) s_acc[k] = 0.0;
     __syncthreads();
     const int N = g.N;
-    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
-    // one view's twist terms of the block: wave sums, then the block's waves
+    const int lane = threadIdx.x % kWave;
+    // one view's twist terms: a wave sum, which the wave's first lane adds to
+    // the block's double sums in LDS (no block barrier per view: the loads of
+    // the waves that run ahead stay in flight)
     auto twist_reduce = [&](int v, const float* tw) {
 #pragma unroll
         for (int e = 0; e < 6; e++) {
             const float sm = wave_sum(tw[e]);
-            if (lane == 0) s_tw[wv][e] = sm;
+            if (lane == 0 && sm != 0.f) atomicAdd(&s_acc[6 * v + e], (double)sm);
         }
-        __syncthreads();
-        if (threadIdx.x < 6) {
-            double sm = 0.0;
-            for (int q = 0; q < kBlock / kWave; q++) sm += (double)s_tw[q][threadIdx.x];
-            s_acc[6 * v + threadIdx.x] += sm;
-        }
-        __syncthreads();
     };
     // grid-stride over Gaussians: a bounded number of blocks keeps the twist
     // atomics (one per block, view and component) few
@@ -502,26 +496,20 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_geom(gs_gaussians g, con
                                  AdamGauss adam, float* __restrict__ vmu_dir,
                                  double* __restrict__ twist_acc) {
     if (ADAM) adam_bias(adam.step_dev, adam.step, adam.b1, adam.b2, adam.ibc1, adam.ibc2);
-    __shared__ float s_tw[kBlock / kWave][6];
     __shared__ double s_acc[6 * GS_MAX_VIEWS];  // this block's twist sums, all iterations
     for (int k = threadIdx.x; k < 6 * vt.V; k += kBlock) s_acc[k] = 0.0;
     __syncthreads();
     const int N = g.N;
-    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
-    // one view's twist terms of the block: wave sums, then the block's waves
+    const int lane = threadIdx.x % kWave;
+    // one view's twist terms: a wave sum, which the wave's first lane adds to
+    // the block's double sums in LDS (no block barrier per view: the loads of
+    // the waves that run ahead stay in flight)
     auto twist_reduce = [&](int v, const float* tw) {
 #pragma unroll
         for (int e = 0; e < 6; e++) {
             const float sm = wave_sum(tw[e]);
-            if (lane == 0) s_tw[wv][e] = sm;
+            if (lane == 0 && sm != 0.f) atomicAdd(&s_acc[6 * v + e], (double)sm);
         }
-        __syncthreads();
-        if (threadIdx.x < 6) {
-            double sm = 0.0;
-            for (int q = 0; q < kBlock / kWave; q++) sm += (double)s_tw[q][threadIdx.x];
-            s_acc[6 * v + threadIdx.x] += sm;
-        }
-        __syncthreads();
     };
     // grid-stride over Gaussians: a bounded number of blocks keeps the twist
     // atomics (one per block, view and component) few
