@@ -479,7 +479,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_color(gs_gaussians g, co
             if (active) {
 #pragma unroll
                 for (int e = 0; e < 3; e++) vmu_dir[(int64_t)e * N + i] = v_mu[e];
-                step_entries<ADAM, 3 * K, 8, true>(v_sh, [](int) { return 4; }, [](int j) { return j; }, i, N,
+                step_entries<ADAM, 3 * K, 16, true>(v_sh, [](int) { return 4; }, [](int j) { return j; }, i, N,
                                                     adam, out, accumulate, sh);
             }
         }
