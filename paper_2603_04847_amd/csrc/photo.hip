@@ -69,7 +69,7 @@ struct PhotoLds {
 
 // Runs: horizontal passes write 6 (first) or 8 (partials) consecutive
 // columns per work item, vertical passes 6 or 8 consecutive rows.
-constexpr int kRunA = 6;  // 42 = 7 x 6
+constexpr int kRunA = 7;  // 42 = 6 x 7: 252 vertical items, one per thread
 constexpr int kRunB = 8;  // 32 = 4 x 8
 
 __global__ __launch_bounds__(kThreads) void k_photo(PhotoArgs a, Window win) {
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(kThreads) void k_photo(PhotoArgs a, Window win) {
         // ---- vertical window sums over the tile and ring, then S and its
         // partial derivatives; held in registers until every thread has read
         // the horizontal sums (the partials take their place in LDS)
-        constexpr int kItemsA = kMid * (kMid / kRunA);           // 294
+        constexpr int kItemsA = kMid * (kMid / kRunA);           // 252
         constexpr int kPerThreadA = (kItemsA + kThreads - 1) / kThreads;  // 2
         float dv[kPerThreadA][kRunA][3];
 #pragma unroll
