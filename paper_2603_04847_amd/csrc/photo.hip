@@ -71,6 +71,7 @@ struct PhotoLds {
 // columns per work item, vertical passes 6 or 8 consecutive rows.
 constexpr int kRunA = 7;  // 42 = 6 x 7: 252 vertical items, one per thread
 constexpr int kRunB = 8;  // 32 = 4 x 8
+constexpr int kRunC = 4;  // the last vertical pass: 32 = 8 x 4, one item per thread
 
 __global__ __launch_bounds__(kThreads) void k_photo(PhotoArgs a, Window win) {
     __shared__ PhotoLds s;
@@ -223,16 +224,17 @@ __global__ __launch_bounds__(kThreads) void k_photo(PhotoArgs a, Window win) {
         }
         __syncthreads();
         // ---- vertical window sums over the tile, the gradient, the L1 term
-        if (tid < kT * (kT / kRunB)) {
-            const int c = tid % kT, r0 = (tid / kT) * kRunB;
-            float ag[3][kRunB];
+        static_assert(kT * (kT / kRunC) <= kThreads, "one item per thread");
+        if (tid < kT * (kT / kRunC)) {
+            const int c = tid % kT, r0 = (tid / kT) * kRunC;
+            float ag[3][kRunC];
 #pragma unroll
             for (int m = 0; m < 3; m++) {
-                float col[kRunB + kTaps - 1];
+                float col[kRunC + kTaps - 1];
 #pragma unroll
-                for (int k = 0; k < kRunB + kTaps - 1; k++) col[k] = s.u.d.E[m][r0 + k][c];
+                for (int k = 0; k < kRunC + kTaps - 1; k++) col[k] = s.u.d.E[m][r0 + k][c];
 #pragma unroll
-                for (int j = 0; j < kRunB; j++) {
+                for (int j = 0; j < kRunC; j++) {
                     float acc = 0.f;
 #pragma unroll
                     for (int k = 0; k < kTaps; k++) acc = __builtin_fmaf(win.g[k], col[j + k], acc);
@@ -241,7 +243,7 @@ __global__ __launch_bounds__(kThreads) void k_photo(PhotoArgs a, Window win) {
             }
             const int px = x0 + c;
 #pragma unroll
-            for (int j = 0; j < kRunB; j++) {
+            for (int j = 0; j < kRunC; j++) {
                 const int py = y0 + r0 + j;
                 if (px >= W || py >= H) continue;
                 const float xv = s.X[2 * kR + r0 + j][2 * kR + c];
