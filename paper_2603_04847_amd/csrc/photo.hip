@@ -67,8 +67,9 @@ struct PhotoLds {
     float red[2][kThreads / kWave];
 };
 
-// Runs: horizontal passes write 6 (first) or 8 (partials) consecutive
-// columns per work item, vertical passes 6 or 8 consecutive rows.
+// Runs: horizontal passes write 7 (first) or 8 (partials) consecutive
+// columns per work item, vertical passes 7 (first) or 4 (last) consecutive
+// rows.
 constexpr int kRunA = 7;  // 42 = 6 x 7: 252 vertical items, one per thread
 constexpr int kRunB = 8;  // 32 = 4 x 8
 constexpr int kRunC = 4;  // the last vertical pass: 32 = 8 x 4, one item per thread
@@ -205,21 +206,21 @@ __global__ __launch_bounds__(kThreads) void k_photo(PhotoArgs a, Window win) {
         }
         __syncthreads();
         // ---- horizontal window sums of the partials: rows of tile and ring,
-        // columns of the tile
-        for (int item = tid; item < kMid * (kT / kRunB); item += kThreads) {
-            const int r = item / (kT / kRunB), c0 = (item % (kT / kRunB)) * kRunB;
+        // columns of the tile; one map per item (504 items for 256 threads),
+        // consecutive lanes on consecutive rows
+        constexpr int kItemsB = kMid * (kT / kRunB);  // per map: 168
+        for (int item = tid; item < 3 * kItemsB; item += kThreads) {
+            const int m = item / kItemsB, rest = item % kItemsB;
+            const int r = rest % kMid, c0 = (rest / kMid) * kRunB;
+            float row[kRunB + kTaps - 1];
 #pragma unroll
-            for (int m = 0; m < 3; m++) {
-                float row[kRunB + kTaps - 1];
+            for (int k = 0; k < kRunB + kTaps - 1; k++) row[k] = s.u.d.D[m][r][c0 + k];
 #pragma unroll
-                for (int k = 0; k < kRunB + kTaps - 1; k++) row[k] = s.u.d.D[m][r][c0 + k];
+            for (int j = 0; j < kRunB; j++) {
+                float acc = 0.f;
 #pragma unroll
-                for (int j = 0; j < kRunB; j++) {
-                    float acc = 0.f;
-#pragma unroll
-                    for (int k = 0; k < kTaps; k++) acc = __builtin_fmaf(win.g[k], row[j + k], acc);
-                    s.u.d.E[m][r][c0 + j] = acc;
-                }
+                for (int k = 0; k < kTaps; k++) acc = __builtin_fmaf(win.g[k], row[j + k], acc);
+                s.u.d.E[m][r][c0 + j] = acc;
             }
         }
         __syncthreads();
