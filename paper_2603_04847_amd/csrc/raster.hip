@@ -149,12 +149,16 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
     const int gx = vt.gx[v], W = vt.W[v], H = vt.H[v];
     const int tx = lt % gx, ty = lt / gx;
     const int lane = threadIdx.x;
+    const float amin = rp.alpha_min, amax = rp.alpha_max, tmin = rp.t_min;
     float fx[PPL], fy[PPL], T[PPL], C0[PPL], C1[PPL], C2[PPL];
     int last[PPL];
     // per slot: entries met so far whose mask covers the slot's quadrants (the
     // same for the whole wave), and its value at each pixel's last contributor
     int qn[PPL], lastq[PPL];
-    bool done[PPL];
+    // the pixel's alpha gate: alpha_min while it composites, 2 (above every
+    // alpha) once it has stopped or when it lies outside the view, so one
+    // compare both gates and skips
+    float gmin[PPL];
 #pragma unroll
     for (int k = 0; k < PPL; k++) {
         int x, y;
@@ -162,14 +166,13 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
         const int px = tx * TW + x, py = ty * TH + y;
         fx[k] = px + 0.5f;
         fy[k] = py + 0.5f;
-        done[k] = !(px < W && py < H);
+        gmin[k] = (px < W && py < H) ? amin : 2.f;
         T[k] = 1.f;
         C0[k] = C1[k] = C2[k] = 0.f;
         last[k] = 0;
         qn[k] = lastq[k] = 0;
     }
     const int s = ranges[2 * t], e = ranges[2 * t + 1];
-    const float amin = rp.alpha_min, amax = rp.alpha_max, tmin = rp.t_min;
     int ncontrib = 0, nent = 0;
     __shared__ BatchLds sb;
     // Two-deep pipeline: while a batch composites, the next batch's records
@@ -182,7 +185,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
     for (int b = s; b < e; b += kWave) {
         bool alive = false;
 #pragma unroll
-        for (int k = 0; k < PPL; k++) alive |= !done[k];
+        for (int k = 0; k < PPL; k++) alive |= gmin[k] <= 1.f;
         if (__ballot(alive) == 0) break;
         const uint32_t id = id_cur;
         const int nb = min(kWave, e - b);
@@ -204,7 +207,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
             for (int k = 0; k < PPL; k++) {
                 if (!(m & TM::quads(k))) continue;  // wave-uniform
                 if (EVALS) qn[k]++;
-                if (__ballot(!done[k]) == 0) continue;  // wave-uniform: the slot has stopped
+                if (__ballot(gmin[k] <= 1.f) == 0) continue;  // wave-uniform: the slot has stopped
                 const float dx = mx - fx[k];
                 const float dy = my - fy[k];
                 // listed splats have positive-definite conics (binning drops the
@@ -213,12 +216,13 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
                 // min(amax, o 2^e2) as one median (the product is >= 0)
                 const float alpha = __builtin_amdgcn_fmed3f(o * __builtin_amdgcn_exp2f(e2), 0.f, amax);
                 const float Tn = T[k] * (1.f - alpha);
-                // the gate; then the splat that would take T below t_min stops
-                // the pixel instead of contributing.  Decided without branches,
-                // one branch for the update.
-                const bool gate = !done[k] && alpha >= amin;
+                // the gate (never passed by a stopped pixel); then the splat
+                // that would take T below t_min stops the pixel instead of
+                // contributing.  Decided without branches, one branch for the
+                // update.
+                const bool gate = alpha >= gmin[k];
                 const bool stop = gate && Tn < tmin;
-                done[k] = done[k] || stop;
+                gmin[k] = stop ? 2.f : gmin[k];
                 if (gate && !stop) {
                     const float w = alpha * T[k];
                     C0[k] = __builtin_fmaf(cr, w, C0[k]);
