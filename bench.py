@@ -104,14 +104,14 @@ def make_workload(name):
 
 
 def run_joint(torch, name, steps, warmup, tune=True, tile=None, order=0, graph=True,
-              lambda_ssim=0.2):
+              lambda_ssim=0.2, lazy_lists=True):
     from paper_2603_04847_amd import _lib as L
     from paper_2603_04847_amd.autotune import autotune
     from paper_2603_04847_amd.step import JointStep
     sc, batches, targets = make_workload(name)
     P = max(int(sum(int(sc["wh"][v, 0]) * int(sc["wh"][v, 1]) for v in b)) for b in batches)
     st = JointStep(sc, batches, targets, max_isect=min(2**30 - 65536, 48 * P),
-                   lambda_ssim=lambda_ssim)
+                   lambda_ssim=lambda_ssim, lazy_lists=lazy_lists)
     tuning = None
     if tile is not None:
         st.settings = L.default_settings(tile_w=tile[0], tile_h=tile[1], tile_order=order)
@@ -372,7 +372,7 @@ def batched_vs_per_view(torch, steps, warmup):
 
     def per_view(ctx, s):
         s_acc = L.default_settings(tile_w=s.tile_w, tile_h=s.tile_h, tile_order=s.tile_order,
-                                   grad_accumulate=1)
+                                   grad_accumulate=1, lazy_lists=1)
         for v in range(V):
             a, b = int(pix_off[v]), int(pix_off[v + 1])
             c = cams_v[v]
@@ -391,7 +391,7 @@ def batched_vs_per_view(torch, steps, warmup):
             cand[f"{tile[0]}x{tile[1]}"] = "lists exceed the capacity limit"
             continue
         for order in (0, 1, 2):
-            s = L.default_settings(tile_w=tile[0], tile_h=tile[1], tile_order=order)
+            s = L.default_settings(tile_w=tile[0], tile_h=tile[1], tile_order=order, lazy_lists=1)
             ms = timed(lambda: batched(ctx, s), max(2, steps // 2))
             cand[f"{tile[0]}x{tile[1]}/{order}"] = round(ms, 3)
             if best is None or ms < best[0]:
@@ -399,7 +399,7 @@ def batched_vs_per_view(torch, steps, warmup):
         ctx.close()
     _, tile, order, need = best
     ctx, need = make_ctx(tile)
-    s = L.default_settings(tile_w=tile[0], tile_h=tile[1], tile_order=order)
+    s = L.default_settings(tile_w=tile[0], tile_h=tile[1], tile_order=order, lazy_lists=1)
     out = {}
     for name, fn in (("batched", lambda: batched(ctx, s)), ("per_view", lambda: per_view(ctx, s))):
         ms = timed(fn, steps)
@@ -900,6 +900,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip batched vs per-view (C3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing")
+    ap.add_argument("--full-lists", action="store_true",
+                    help="bin into complete tile lists (gs_settings.lazy_lists = 0)")
     ap.add_argument("--summarize-counters", default=None, metavar="DIR",
                     help="write the counter summaries under profiles/ from the rocprofv3 passes in DIR "
                          "(no GPU needed) and exit")
@@ -940,7 +942,7 @@ def main():
     tile = tuple(int(x) for x in args.tile.split("x")) if args.tile else None
     res = run_joint(torch, args.workload, args.steps, args.warmup, tune=not args.no_tune,
                     tile=tile, order=args.order, graph=not args.no_graph,
-                    lambda_ssim=args.lambda_ssim)
+                    lambda_ssim=args.lambda_ssim, lazy_lists=not args.full_lists)
     sz = res["sizes"]
     # the timed steps: replayed from captured HIP graphs (the production mode:
     # the same kernels, no per-call host work between them), else eager
@@ -977,7 +979,8 @@ def main():
                    "views_per_step": sz["V"], "pixels_per_step": sz["P"], "gaussians": sz["N"],
                    "observations": sz["M"],
                    "tile": f"{res['st'].settings.tile_w}x{res['st'].settings.tile_h}",
-                   "tile_order": int(res["st"].settings.tile_order)},
+                   "tile_order": int(res["st"].settings.tile_order),
+                   "tile_lists": "lazy" if res["st"].lazy_lists else "full"},
         "roofline": roof,
         "per_call_ms": per_call,
         "per_call_algorithmic_gbs": {k: round(alg[k] / (per_call[k] * 1e-3) / 1e9, 1)
@@ -1021,7 +1024,8 @@ def main():
         torch.cuda.empty_cache()
         log("[bench] extra workload C4")
         r4 = run_joint(torch, "C4", args.steps, args.warmup, tune=False, tile=(16, 16), order=1,
-                       graph=not args.no_graph, lambda_ssim=args.lambda_ssim)
+                       graph=not args.no_graph, lambda_ssim=args.lambda_ssim,
+                       lazy_lists=not args.full_lists)
         ms4 = r4["graph_ms"] if r4["graph_ms"] is not None else r4["ms"]
         pc4 = {k: round(v, 4) for k, v in r4["per_call"].items()}
         line["extra_workloads"] = {"C4": {

@@ -130,6 +130,16 @@ typedef struct {
     int32_t eval_stats;       /* 0; 1: gs_render_fwd also counts per tile the contributing
                                  pairs, list entries read and (pixel, splat) evaluations
                                  (gs_ctx_tile_stats), a slower variant */
+    int32_t lazy_lists;       /* 0: gs_bin_sort writes every tile list in full;
+                                 1: it stops at the per-block lists and the tile list
+                                 lengths, and gs_render_fwd draws each tile's list from
+                                 its block's list, writing the part it reads (up to the
+                                 batch of 64 in which the tile's last pixel stopped) to
+                                 the tile lists.  The backward reads no further than that
+                                 part; run without a forward since the bin step, it first
+                                 writes the lists in full.  Images and gradients are the
+                                 same bit for bit; only the unread list tails are left
+                                 unwritten */
 } gs_settings;
 
 typedef struct {
@@ -204,7 +214,8 @@ gs_status gs_ctx_reset_status(gs_ctx* ctx, void* stream);
  * records [max_pairs][12], the tile lists [max_isect] (pair index in the low
  * 28 bits, the 4-bit quadrant mask in the top 4), tile ranges [max_tiles][2]
  * (start, end) int32, and the tile count of the last gs_bin_sort (HOST
- * value). */
+ * value).  After a gs_bin_sort with lazy_lists = 1 a tile list holds only the
+ * entries a forward (or backward) has written since. */
 gs_status gs_ctx_buffers(gs_ctx* ctx, float** records, int32_t** isect_ids,
                          int32_t** tile_ranges, int64_t* n_tiles);
 
@@ -244,7 +255,10 @@ gs_status gs_project(gs_ctx* ctx, const gs_gaussians* g, const gs_cameras* cams,
  * layout above.  max_isect bounds the total list length; overflow sets
  * GS_FLAG_ISECT_OVERFLOW, leaves every list empty, and n_isect_needed reports
  * the need (or, when even the 4x4-tile blocks the lists are built from
- * overflowed, a lower bound of it). */
+ * overflowed, a lower bound of it).  With s->lazy_lists = 1 the tile ranges
+ * are the same but the entries are left to the forward (gs_settings); the
+ * render calls follow the mode of the last gs_bin_sort, whatever their own
+ * settings say. */
 gs_status gs_bin_sort(gs_ctx* ctx, const gs_cameras* cams, int32_t N,
                       const gs_settings* s, const float* records, void* stream);
 

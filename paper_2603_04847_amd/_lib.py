@@ -42,7 +42,7 @@ class gs_settings(ctypes.Structure):
                 ("fov_pad", ctypes.c_float), ("alpha_min", ctypes.c_float),
                 ("alpha_max", ctypes.c_float), ("t_min", ctypes.c_float),
                 ("grad_accumulate", ctypes.c_int32), ("tile_order", ctypes.c_int32),
-                ("eval_stats", ctypes.c_int32)]
+                ("eval_stats", ctypes.c_int32), ("lazy_lists", ctypes.c_int32)]
 
 
 class gs_gaussians(ctypes.Structure):

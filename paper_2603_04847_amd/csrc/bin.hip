@@ -24,6 +24,9 @@
 //     and of the tile totals place every entry, written as (pair | 4-bit mask
 //     << 28) in block-list order.  Sorting (block, pair) entries instead of (tile, pair)
 //     ones moves about a quarter of the data through the radix passes.
+//     Lazy lists stop before the entries of step 6 (the ranges are kept): the
+//     forward filters each tile's entries out of its block's list itself and
+//     writes the part it reads.
 #include <algorithm>
 
 #include "gs_internal.h"
@@ -664,6 +667,8 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
     const int64_t NB = vt.block_off[vt.V];
     hipError_t e = hipSuccess;
     c->ordered = false;
+    c->lists_lazy = false;
+    c->lists_filled = false;
     if (npairs > 0) {
         const unsigned gp = (unsigned)((npairs + kBlock - 1) / kBlock);
         hipLaunchKernelGGL(k_count, dim3(gp), dim3(kBlock), 0, st, rec, N, vt, rp, c->cnt, c->pk[0],
@@ -694,14 +699,14 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
         uint32_t* Vv[3][2] = {{c->iv[0], c->iv[1]}, {c->im[0], c->im[1]}, {c->im[0] + I, c->im[1] + I}};
         const int side2 = radix_sort_kv3(K, Vv, I, used, 0, bbits, c->hist, c->scan_scratch, c->diag + kDiagFlags, st, &e);
         if (e != hipSuccess) return e;
-        const uint32_t* bpair = c->iv[side2];
+        c->block_side = side2;
         const uint32_t* bmlo = c->im[side2];
         const uint32_t* bmhi = c->im[side2] + I;
         const unsigned gi = (unsigned)std::min<int64_t>((I + kBlock - 1) / kBlock, 4096);
         hipLaunchKernelGGL(k_ranges, dim3(gi), dim3(kBlock), 0, st, c->ik[side2], used, c->ranges,
                            (uint32_t)NB);
         // tile lists: chunk counts and their scan, per-block prefixes and tile
-        // list lengths, the tile scan and ranges, then the lists
+        // list lengths, the tile scan and ranges (the entries follow at the end)
         if (T > 0) {
             uint32_t* ttotal = c->scalars + 2;
             uint32_t* tused = c->scalars + 3;
@@ -725,11 +730,6 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
             const bool bucketed = tile_order && T <= ((int64_t)1 << 20);
             hipLaunchKernelGGL(k_tile_ranges, dim3(gt), dim3(kBlock), 0, st, c->tcnt, ttotal, tused, vt,
                                rp.tile_h, T, c->bpre, c->tranges, c->tbase, bucketed ? c->tk[0] : nullptr);
-            hipLaunchKernelGGL(k_chunk_bases, dim3((unsigned)((nch * kBlockSub + kBlock - 1) / kBlock)),
-                               dim3(kBlock), 0, st, c->ik[side2], used, c->ccnt, c->tbase, (uint32_t)NB, nch,
-                               c->cbase);
-            hipLaunchKernelGGL(k_chunk_expand, dim3(gch), dim3(kBlock), 0, st, c->ik[side2], bpair, bmlo,
-                               bmhi, used, tused, c->ccnt, c->tbase, c->cbase, (uint32_t)NB, c->tids);
         }
         if (tile_order && T > 0 && T <= ((int64_t)1 << 20)) {
             // the weights were written with the tile ranges
@@ -762,6 +762,28 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
     c->bin_N = N;
     c->bin_tw = rp.tile_w;
     c->bin_th = rp.tile_h;
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // the entries themselves: now, or drawn by the forward from the block lists
+    if (npairs > 0 && T > 0) {
+        if (rp.lazy_lists) c->lists_lazy = true;
+        else return launch_expand_lists(c, st);
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_expand_lists(Ctx* c, hipStream_t st) {
+    const int64_t NB = c->n_blocks, nch = c->nchunks, I = c->cap.max_isect;
+    const int side = c->block_side;
+    const uint32_t* used = c->scalars + 1;
+    const uint32_t* tused = c->scalars + 3;
+    const unsigned gch = (unsigned)std::min<int64_t>((nch + kWaves - 1) / kWaves, 8192);
+    hipLaunchKernelGGL(k_chunk_bases, dim3((unsigned)((nch * kBlockSub + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, st, c->ik[side], used, c->ccnt, c->tbase, (uint32_t)NB, nch,
+                       c->cbase);
+    hipLaunchKernelGGL(k_chunk_expand, dim3(gch), dim3(kBlock), 0, st, c->ik[side], c->iv[side],
+                       c->im[side], c->im[side] + I, used, tused, c->ccnt, c->tbase, c->cbase,
+                       (uint32_t)NB, c->tids);
+    c->lists_lazy = false;
     return hipGetLastError();
 }
 

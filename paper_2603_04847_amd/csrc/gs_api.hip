@@ -52,6 +52,7 @@ RasterParams make_raster_params(const gs_settings* s) {
     rp.tile_h = s->tile_h;
     rp.eval_stats = s->eval_stats;
     rp.tile_order = s->tile_order;
+    rp.lazy_lists = s->lazy_lists;
     return rp;
 }
 
@@ -70,6 +71,7 @@ gs_status check_settings(const gs_settings* s) {
     if (!s) return GS_ERR_INVALID_ARG;
     if (!tile_ok(s->tile_w, s->tile_h)) return GS_ERR_UNSUPPORTED;
     if (s->tile_order < 0 || s->tile_order > 2) return GS_ERR_INVALID_ARG;
+    if (s->lazy_lists != 0 && s->lazy_lists != 1) return GS_ERR_INVALID_ARG;
     if (!(s->alpha_min > 0.f && s->alpha_min < s->alpha_max && s->alpha_max < 1.f) ||
         !(s->t_min > 0.f && s->t_min < 1.f) || !(s->near_plane > 0.f) || !(s->eps2d >= 0.f) ||
         !(s->fov_pad >= 0.f))
@@ -142,6 +144,7 @@ void gs_default_settings(gs_settings* s) {
     s->grad_accumulate = 0;
     s->tile_order = 0;
     s->eval_stats = 0;
+    s->lazy_lists = 0;
 }
 
 gs_status gs_ctx_create(gs_ctx** out, const gs_capacity* cap) {

@@ -30,6 +30,7 @@ struct RasterParams {
     int tile_w, tile_h;
     int eval_stats;
     int tile_order;
+    int lazy_lists;
 };
 
 // Device status words (one array in the context).
@@ -453,6 +454,9 @@ hipError_t launch_project_bwd(Ctx* c, const gs_gaussians* g, const gs_cameras* c
                               hipStream_t st);
 
 // raster.hip
+// The tile lists in full from the block lists of the last bin step (for a
+// backward after a lazy bin step with no forward in between).
+hipError_t launch_expand_lists(Ctx* c, hipStream_t st);
 hipError_t launch_render_fwd(Ctx* c, const ViewTable& vt, const RasterParams& rp, const float* bg,
                              float* rgb, float* T_final, int32_t* last, hipStream_t st);
 hipError_t launch_render_bwd(Ctx* c, const ViewTable& vt, const RasterParams& rp, const float* bg,
@@ -588,6 +592,11 @@ struct Ctx {
     int64_t n_tiles, n_blocks;
     int bin_V, bin_N, bin_tw, bin_th;
     bool ordered;          // tile_order holds the order of the last bin step
+    // lazy lists: the last bin step stopped at the block lists (block_side is
+    // the ping-pong side they ended on); filled: a forward has written the
+    // part of each tile list a backward reads
+    bool lists_lazy, lists_filled;
+    int block_side;
     int64_t generation;    // gs_bin_sort calls enqueued so far
 };
 

@@ -128,7 +128,25 @@ __device__ __forceinline__ uint32_t batch_ids(const int32_t* __restrict__ ids, i
     return (j >= s && j < e) ? id : 0u;
 }
 
-template <int TW, int TH, bool EVALS>
+// Where a forward over lazy lists draws its tiles' entries from: the sorted
+// block lists (pair; low and high 32 bits of the 64-bit quadrant mask), the
+// block ranges, and the tile lists it writes what it reads into.
+struct BlockSrc {
+    const uint32_t* pair;
+    const uint32_t* mlo;
+    const uint32_t* mhi;
+    const int32_t* branges;
+    uint32_t* tids;
+};
+
+// Block-list entries a lazy forward keeps in flight (loads of 64 each), and
+// the LDS ring its filtered entries queue in: at most 63 waiting plus one
+// refill of kPull * 64.
+constexpr int kPull = 4;
+constexpr uint32_t kRing = 512;
+static_assert(kRing >= kWave - 1 + kPull * kWave, "ring");
+
+template <int TW, int TH, bool EVALS, bool LAZY>
 __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ rec,
                                                    const int32_t* __restrict__ ids,
                                                    const int32_t* __restrict__ ranges,
@@ -139,7 +157,8 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
                                                    int32_t* __restrict__ out_last,
                                                    int32_t* __restrict__ tile_contrib,
                                                    int32_t* __restrict__ tile_entries,
-                                                   int32_t* __restrict__ tile_evals, int mode) {
+                                                   int32_t* __restrict__ tile_evals, int mode,
+                                                   BlockSrc src) {
     using TM = TileMap<TW, TH>;
     constexpr int PPL = TM::PPL;
     int t;
@@ -172,14 +191,82 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
         last[k] = 0;
         qn[k] = lastq[k] = 0;
     }
-    const int s = ranges[2 * t], e = ranges[2 * t + 1];
+    const int s = ranges[2 * t];
+    int e = ranges[2 * t + 1];
     int ncontrib = 0, nent = 0;
     __shared__ BatchLds sb;
+    // Lazy lists: the tile's list is its block's list filtered by the tile's
+    // four mask bits (the definition of the tile lists).  Block entries are
+    // loaded kPull * 64 at a time, one load ahead; the entries that meet the
+    // tile queue in an LDS ring in list order (qt queued, qh handed out, both
+    // wave-uniform) and are handed out 64 at a time, each batch written to the
+    // tile list as it is drawn, so the backward finds every entry up to the
+    // last contributor.
+    __shared__ uint32_t s_ring[LAZY ? kRing : 1];
+    uint32_t lp[kPull], lm[kPull];
+    int bpf = 0, bend = 0, msh = 0;
+    uint32_t qh = 0, qt = 0;
+    const uint32_t* mw = nullptr;
+    auto pull = [&](int p0) {
+        bpf = p0;
+#pragma unroll
+        for (int u = 0; u < kPull; u++) {
+            const int j = min(p0 + u * kWave + lane, bend - 1);
+            lp[u] = src.pair[j];
+            lm[u] = mw[j];
+        }
+    };
+    auto take = [&]() {
+#pragma unroll
+        for (int u = 0; u < kPull; u++) {
+            const uint32_t w = lm[u];
+            uint32_t m4 = ((w >> msh) & 3u) | (((w >> (msh + 8)) & 3u) << 2);
+            m4 = bpf + u * kWave + lane < bend ? m4 : 0u;
+            const uint64_t bal = __ballot(m4 != 0u);
+            // set bits of bal below this lane
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+            if (m4) s_ring[(qt + below) % kRing] = lp[u] | (m4 << kPairBits);
+            qt += (uint32_t)__popcll(bal);
+        }
+        bpf += kPull * kWave;
+    };
+    // the next `want` entries (got < want only if the block list ran out
+    // first, which the exact list lengths rule out)
+    auto draw = [&](int want, int& got) -> uint32_t {
+        while ((int)(qt - qh) < want && bpf < bend) {
+            take();
+            if (bpf < bend) pull(bpf);
+        }
+        got = min(want, (int)(qt - qh));
+        wave_lds_sync();
+        const uint32_t id = lane < got ? s_ring[(qh + (uint32_t)lane) % kRing] : 0u;
+        qh += (uint32_t)got;
+        return id;
+    };
     // Two-deep pipeline: while a batch composites, the next batch's records
     // are in flight (their entries arrived during the batch before) and the
     // entries of the batch after that are requested.
-    uint32_t id_cur = s < e ? batch_ids(ids, s, s, e) : 0u;
-    uint32_t id_nxt = s < e ? batch_ids(ids, s + kWave, s, e) : 0u;
+    uint32_t id_cur = 0u, id_nxt = 0u;
+    if constexpr (LAZY) {
+        const int sx = tx % kBlockTiles, sy = ty % kBlockTiles;
+        const int B = vt.block_off[v] + (ty / kBlockTiles) * vt.bx[v] + tx / kBlockTiles;
+        bend = src.branges[2 * B + 1];
+        bpf = s < e ? src.branges[2 * B] : bend;
+        mw = sy < 2 ? src.mlo : src.mhi;
+        msh = 16 * (sy % 2) + 2 * sx;
+        if (bpf < bend) pull(bpf);
+        if (s < e) {
+            const int want = min(kWave, e - s);
+            int got;
+            id_cur = draw(want, got);
+            if (got < want) e = s + got;
+            if (lane < got) src.tids[s + lane] = id_cur;
+        }
+    } else {
+        id_cur = s < e ? batch_ids(ids, s, s, e) : 0u;
+        id_nxt = s < e ? batch_ids(ids, s + kWave, s, e) : 0u;
+    }
     LaneSplat ls_cur = {};
     if (lane < e - s) ls_cur = load_splat(rec, id_cur & kPairMask);
     for (int b = s; b < e; b += kWave) {
@@ -192,9 +279,22 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
         wave_lds_sync();  // the previous batch is read
         stage_splat(sb, ls_cur);
         ls_cur = {};
-        if (lane < e - (b + kWave)) ls_cur = load_splat(rec, id_nxt & kPairMask);
-        id_cur = id_nxt;
-        id_nxt = batch_ids(ids, b + 2 * kWave, s, e);
+        if constexpr (LAZY) {
+            const int want = min(kWave, e - (b + kWave));
+            if (want > 0) {
+                int got;
+                id_cur = draw(want, got);
+                if (got < want) e = b + kWave + got;
+                if (lane < got) {
+                    src.tids[b + kWave + lane] = id_cur;
+                    ls_cur = load_splat(rec, id_cur & kPairMask);
+                }
+            }
+        } else {
+            if (lane < e - (b + kWave)) ls_cur = load_splat(rec, id_nxt & kPairMask);
+            id_cur = id_nxt;
+            id_nxt = batch_ids(ids, b + 2 * kWave, s, e);
+        }
         wave_lds_sync();
         nent += nb;
         for (int i = 0; i < nb; i++) {
@@ -469,22 +569,33 @@ unsigned raster_grid(const Ctx* c, const ViewTable& vt, int mode) {
     return (unsigned)((slots + round - 1) / round * round);
 }
 
+template <int TW, int TH, bool EVALS, bool LAZY>
+void fwd_launch(Ctx* c, const ViewTable& vt, const RasterParams& rp, const float* bg, float* rgb,
+                float* T_final, int32_t* last, const uint32_t* order, int mode, const BlockSrc& src,
+                hipStream_t st) {
+    hipLaunchKernelGGL((k_render_fwd<TW, TH, EVALS, LAZY>), dim3(raster_grid(c, vt, mode)), dim3(64), 0,
+                       st, reinterpret_cast<const float4*>(c->rec), reinterpret_cast<const int32_t*>(c->tids),
+                       c->tranges, order, vt, rp, bg, rgb, T_final, last, c->tile_contrib,
+                       c->tile_entries, c->tile_evals, mode, src);
+}
+
 template <int TW, int TH>
 hipError_t fwd_impl(Ctx* c, const ViewTable& vt, const RasterParams& rp, const float* bg,
                     float* rgb, float* T_final, int32_t* last, const uint32_t* order, int mode,
                     hipStream_t st) {
-    const unsigned grid = raster_grid(c, vt, mode);
-    if (rp.eval_stats)
-        hipLaunchKernelGGL((k_render_fwd<TW, TH, true>), dim3(grid), dim3(64), 0, st,
-                           reinterpret_cast<const float4*>(c->rec), reinterpret_cast<const int32_t*>(c->tids),
-                           c->tranges, order, vt, rp, bg, rgb, T_final, last, c->tile_contrib,
-                           c->tile_entries, c->tile_evals, mode);
-    else
-        hipLaunchKernelGGL((k_render_fwd<TW, TH, false>), dim3(grid), dim3(64), 0, st,
-                           reinterpret_cast<const float4*>(c->rec), reinterpret_cast<const int32_t*>(c->tids),
-                           c->tranges, order, vt, rp, bg, rgb, T_final, last, c->tile_contrib,
-                           c->tile_entries, c->tile_evals, mode);
-    return hipGetLastError();
+    BlockSrc src = {};
+    if (c->lists_lazy) {
+        const int sd = c->block_side;
+        src = {c->iv[sd], c->im[sd], c->im[sd] + c->cap.max_isect, c->ranges, c->tids};
+        if (rp.eval_stats) fwd_launch<TW, TH, true, true>(c, vt, rp, bg, rgb, T_final, last, order, mode, src, st);
+        else fwd_launch<TW, TH, false, true>(c, vt, rp, bg, rgb, T_final, last, order, mode, src, st);
+    } else {
+        if (rp.eval_stats) fwd_launch<TW, TH, true, false>(c, vt, rp, bg, rgb, T_final, last, order, mode, src, st);
+        else fwd_launch<TW, TH, false, false>(c, vt, rp, bg, rgb, T_final, last, order, mode, src, st);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e == hipSuccess && c->lists_lazy) c->lists_filled = true;
+    return e;
 }
 
 template <int TW, int TH>
@@ -516,6 +627,11 @@ hipError_t launch_render_bwd(Ctx* c, const ViewTable& vt, const RasterParams& rp
                              const float* T_final, const int32_t* last, const float* v_rgb,
                              hipStream_t st) {
     if (c->n_tiles <= 0) return hipSuccess;
+    // lazy lists with no forward since the bin step: write them in full first
+    if (c->lists_lazy && !c->lists_filled) {
+        const hipError_t e = launch_expand_lists(c, st);
+        if (e != hipSuccess) return e;
+    }
     const uint32_t* order = c->ordered ? c->tile_order : nullptr;
     const int mode = rp.tile_order == 2 ? 2 : (order ? 1 : 0);
     const int TW = rp.tile_w, TH = rp.tile_h;

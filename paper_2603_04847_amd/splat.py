@@ -34,7 +34,9 @@ class Splatter:
 
     def __init__(self, ctx: L.Context, settings=None, bg=None):
         self.ctx = ctx
-        self.settings = settings if settings is not None else L.default_settings()
+        # without settings of the caller's, the tile lists are left to the
+        # forward (gs_settings.lazy_lists): nothing here reads them
+        self.settings = settings if settings is not None else L.default_settings(lazy_lists=1)
         self.bg = bg
 
     def forward(self, params, sh_degree, viewmat, intr, wh, stream=None):

@@ -42,7 +42,7 @@ class JointStep:
     can be captured in a HIP graph."""
 
     def __init__(self, scene, batches, targets, device="cuda", settings=None, max_isect=None,
-                 lam=1e-4, delta=1.0, extent=None, lambda_ssim=0.2):
+                 lam=1e-4, delta=1.0, extent=None, lambda_ssim=0.2, lazy_lists=True):
         f = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device, torch.float32)
         self.sh_degree = int(scene["sh_degree"])
         self.params = {k: f(scene[k]) for k in PARAM_KEYS}
@@ -60,6 +60,9 @@ class JointStep:
         self.batches = [np.asarray(b, np.int32) for b in batches]
         self.targets = [f(t) for t in targets]
         self.settings = settings if settings is not None else L.default_settings()
+        # the step never reads the tile lists itself: by default the forward
+        # writes only the part of each list it reads (gs_settings.lazy_lists)
+        self.lazy_lists = bool(lazy_lists)
         self.lam, self.delta = lam, delta
         self.lambda_ssim = float(lambda_ssim)
         if extent is None:
@@ -139,6 +142,7 @@ class JointStep:
         cams = self.cams[b]
         P = cams.n_pixels
         s = self.settings
+        s.lazy_lists = int(self.lazy_lists)
         with t("pose_compose"):
             L.gs_pose_compose(self.twist, self.base, self.viewmat)
         with t("project"):

@@ -46,6 +46,7 @@ def test_library_loads_and_binding_covers_exports():
         assert n in L.EXPORTS, n
     s = L.default_settings()
     assert (s.tile_w, s.tile_h) == (16, 16)
+    assert s.lazy_lists == 0  # gs_bin_sort writes the tile lists in full by default
     assert abs(s.alpha_min - 1 / 255) < 1e-9 and abs(s.t_min - 1e-4) < 1e-9
     assert lib.gs_strerror(-2) == b"size exceeds the context's capacity"
 
