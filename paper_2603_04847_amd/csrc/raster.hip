@@ -142,8 +142,8 @@ struct BlockSrc {
 // Block-list entries a lazy forward keeps in flight (loads of 64 each), and
 // the LDS ring its filtered entries queue in: at most 63 waiting plus one
 // refill of kPull * 64.
-constexpr int kPull = 4;
-constexpr uint32_t kRing = 512;
+constexpr int kPull = 8;
+constexpr uint32_t kRing = 1024;
 static_assert(kRing >= kWave - 1 + kPull * kWave, "ring");
 
 template <int TW, int TH, bool EVALS, bool LAZY>
@@ -251,8 +251,9 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ re
     if constexpr (LAZY) {
         const int sx = tx % kBlockTiles, sy = ty % kBlockTiles;
         const int B = vt.block_off[v] + (ty / kBlockTiles) * vt.bx[v] + tx / kBlockTiles;
+        // the block's entries are requested without waiting for the tile range
         bend = src.branges[2 * B + 1];
-        bpf = s < e ? src.branges[2 * B] : bend;
+        bpf = src.branges[2 * B];
         mw = sy < 2 ? src.mlo : src.mhi;
         msh = 16 * (sy % 2) + 2 * sx;
         if (bpf < bend) pull(bpf);
