@@ -456,20 +456,22 @@ def test_render_bwd_matches_oracle(gs, name):
         _close(tw[v], og["twist"][v], what=f"twist view {v}")
 
 
-def _full_size_check(gs, sub, tile, order, npix, max_isect, seed, min_frac=0.97):
+def _full_size_check(gs, sub, tile, order, npix, max_isect, seed, min_frac=0.97, lazy=0):
     """Sampled pixels and gradients of one full-size batch against the oracle:
     colour and transmittance of `npix` random pixels against the oracle's
     per-pixel definition, and the backward with an image gradient that is
     non-zero only at those pixels, so the oracle's gradients of every Gaussian
     parameter and of each view's twist come from them alone.  At least
     `min_frac` of the sampled pixels must be free of ambiguity (a gate, clamp,
-    stop or depth-rounding decision within float32 error of its threshold)."""
+    stop or depth-rounding decision within float32 error of its threshold).
+    `lazy` = 1 leaves the tile lists to the forward (gs_settings.lazy_lists)."""
     from paper_2603_04847_amd.splat import Splatter
     V = sub["viewmat"].shape[0]
     N = sub["means"].shape[1]
     T_max = int(sum(((w + tile[0] - 1) // tile[0]) * ((h + tile[1] - 1) // tile[1]) for w, h in sub["wh"]))
     ctx = gs.Context(max_pairs=V * N, max_isect=max_isect, max_tiles=T_max, max_views=V)
-    sp = Splatter(ctx, gs.default_settings(tile_w=tile[0], tile_h=tile[1], tile_order=order))
+    sp = Splatter(ctx, gs.default_settings(tile_w=tile[0], tile_h=tile[1], tile_order=order,
+                                           lazy_lists=lazy))
     params = _params(sub)
     rgb, T, last, cams = sp.forward(params, 3, _t(sub["viewmat"]), _t(sub["intr"]), sub["wh"])
     torch.cuda.synchronize()
@@ -510,11 +512,11 @@ def _full_size_check(gs, sub, tile, order, npix, max_isect, seed, min_frac=0.97)
 def test_full_size_batch_sampled_pixels_and_gradients(gs):
     """The joint step's batch at full size (4 views of 1237x822, 1M Gaussians,
     SH degree 3), in the configuration the benchmark times (16x16 tiles,
-    heaviest tile first)."""
+    heaviest tile first, lazy tile lists)."""
     sc = scenegen.make_config("C4")
     b = scenegen.batch_views(4, sc["viewmat"].shape[0], 4, 1)[0]
     sub = dict(sc, viewmat=sc["viewmat"][b], intr=sc["intr"][b], wh=sc["wh"][b])
-    _full_size_check(gs, sub, (16, 16), 1, 400, 120_000_000, 12)
+    _full_size_check(gs, sub, (16, 16), 1, 400, 120_000_000, 12, lazy=1)
 
 
 def test_full_size_single_view_sampled(gs):
@@ -542,11 +544,12 @@ def test_full_size_uneven_views_sampled(gs):
 
 def test_full_size_large_scene_sampled(gs):
     """The large-scene batch at full size (4 views of 1600x1066, 5M Gaussians,
-    SH degree 3) at the tile shape its benchmark picks (32x16)."""
+    SH degree 3) in the configuration its benchmark picks (32x16 tiles, the
+    XCD launch order, lazy tile lists)."""
     sc = scenegen.make_config("C5")
     b = scenegen.batch_views(5, sc["viewmat"].shape[0], 4, 1)[0]
     sub = dict(sc, viewmat=sc["viewmat"][b], intr=sc["intr"][b], wh=sc["wh"][b])
-    _full_size_check(gs, sub, (32, 16), 0, 300, 400_000_000, 14)
+    _full_size_check(gs, sub, (32, 16), 2, 300, 400_000_000, 14, lazy=1)
 
 
 def test_render_bwd_batched_views(gs):
