@@ -748,13 +748,23 @@ def test_adam_matches_oracle(gs):
 
 # ------------------------------------------------------------------ error paths
 
-def test_capacity_overflow_is_flagged(gs):
+@pytest.mark.parametrize("lazy", [0, 1])
+def test_capacity_overflow_is_flagged(gs, lazy):
+    """An overflowed bin step is flagged and leaves every list empty: the
+    image is the background, and a backward over it adds nothing (with full
+    and with lazy lists)."""
     sc = _parity_scene(seed=40, N=800)
     ctx = _ctx(gs, sc, max_isect=100)
-    _render(gs, sc, ctx=ctx)
+    sp, params, rgb, T, last, cams, _ = _render(gs, sc, ctx=ctx, settings=gs.default_settings(lazy_lists=lazy))
     st = ctx.status()
     assert st["flags"] & 1
     assert st["n_isect_needed"] > 100 and st["n_isect"] == 0
+    assert torch.all(T == 1.0) and torch.all(last == 0) and torch.all(rgb == 0.0)
+    grads, v_tw = sp.backward(params, sc["sh_degree"], cams, T, last, torch.ones_like(rgb))
+    torch.cuda.synchronize()
+    for k in grads:
+        assert torch.all(grads[k] == 0.0), k
+    assert torch.all(v_tw == 0.0)
 
 
 def test_host_argument_errors(gs):
