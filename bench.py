@@ -104,14 +104,14 @@ def make_workload(name):
 
 
 def run_joint(torch, name, steps, warmup, tune=True, tile=None, order=0, graph=True,
-              lambda_ssim=0.2, lazy_lists=True):
+              lambda_ssim=0.2, lazy_lists=True, overlap_track=True):
     from paper_2603_04847_amd import _lib as L
     from paper_2603_04847_amd.autotune import autotune
     from paper_2603_04847_amd.step import JointStep
     sc, batches, targets = make_workload(name)
     P = max(int(sum(int(sc["wh"][v, 0]) * int(sc["wh"][v, 1]) for v in b)) for b in batches)
     st = JointStep(sc, batches, targets, max_isect=min(2**30 - 65536, 48 * P),
-                   lambda_ssim=lambda_ssim, lazy_lists=lazy_lists)
+                   lambda_ssim=lambda_ssim, lazy_lists=lazy_lists, overlap_track=overlap_track)
     tuning = None
     if tile is not None:
         st.settings = L.default_settings(tile_w=tile[0], tile_h=tile[1], tile_order=order)
@@ -902,6 +902,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing")
     ap.add_argument("--full-lists", action="store_true",
                     help="bin into complete tile lists (gs_settings.lazy_lists = 0)")
+    ap.add_argument("--serial-track", action="store_true",
+                    help="run the track term in line instead of on a second stream")
     ap.add_argument("--summarize-counters", default=None, metavar="DIR",
                     help="write the counter summaries under profiles/ from the rocprofv3 passes in DIR "
                          "(no GPU needed) and exit")
@@ -942,7 +944,8 @@ def main():
     tile = tuple(int(x) for x in args.tile.split("x")) if args.tile else None
     res = run_joint(torch, args.workload, args.steps, args.warmup, tune=not args.no_tune,
                     tile=tile, order=args.order, graph=not args.no_graph,
-                    lambda_ssim=args.lambda_ssim, lazy_lists=not args.full_lists)
+                    lambda_ssim=args.lambda_ssim, lazy_lists=not args.full_lists,
+                    overlap_track=not args.serial_track)
     sz = res["sizes"]
     # the timed steps: replayed from captured HIP graphs (the production mode:
     # the same kernels, no per-call host work between them), else eager
@@ -980,7 +983,8 @@ def main():
                    "observations": sz["M"],
                    "tile": f"{res['st'].settings.tile_w}x{res['st'].settings.tile_h}",
                    "tile_order": int(res["st"].settings.tile_order),
-                   "tile_lists": "lazy" if res["st"].lazy_lists else "full"},
+                   "tile_lists": "lazy" if res["st"].lazy_lists else "full",
+                   "track_stream": "second" if res["st"].overlap_track else "in line"},
         "roofline": roof,
         "per_call_ms": per_call,
         "per_call_algorithmic_gbs": {k: round(alg[k] / (per_call[k] * 1e-3) / 1e9, 1)
@@ -1025,7 +1029,7 @@ def main():
         log("[bench] extra workload C4")
         r4 = run_joint(torch, "C4", args.steps, args.warmup, tune=False, tile=(16, 16), order=1,
                        graph=not args.no_graph, lambda_ssim=args.lambda_ssim,
-                       lazy_lists=not args.full_lists)
+                       lazy_lists=not args.full_lists, overlap_track=not args.serial_track)
         ms4 = r4["graph_ms"] if r4["graph_ms"] is not None else r4["ms"]
         pc4 = {k: round(v, 4) for k, v in r4["per_call"].items()}
         line["extra_workloads"] = {"C4": {

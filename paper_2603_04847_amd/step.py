@@ -42,7 +42,8 @@ class JointStep:
     can be captured in a HIP graph."""
 
     def __init__(self, scene, batches, targets, device="cuda", settings=None, max_isect=None,
-                 lam=1e-4, delta=1.0, extent=None, lambda_ssim=0.2, lazy_lists=True):
+                 lam=1e-4, delta=1.0, extent=None, lambda_ssim=0.2, lazy_lists=True,
+                 overlap_track=True):
         f = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device, torch.float32)
         self.sh_degree = int(scene["sh_degree"])
         self.params = {k: f(scene[k]) for k in PARAM_KEYS}
@@ -63,6 +64,12 @@ class JointStep:
         # the step never reads the tile lists itself: by default the forward
         # writes only the part of each list it reads (gs_settings.lazy_lists)
         self.lazy_lists = bool(lazy_lists)
+        # without a timer, the track term runs on a second stream beside the
+        # projection, binning and raster (it shares none of their buffers; it
+        # joins before the projection backward adds its twist rows).  Timed
+        # calls run in order, one at a time.
+        self.overlap_track = bool(overlap_track)
+        self._side = torch.cuda.Stream(device=device) if overlap_track else None
         self.lam, self.delta = lam, delta
         self.lambda_ssim = float(lambda_ssim)
         if extent is None:
@@ -145,13 +152,24 @@ class JointStep:
         s.lazy_lists = int(self.lazy_lists)
         with t("pose_compose"):
             L.gs_pose_compose(self.twist, self.base, self.viewmat)
+        side = self._side if (self.overlap_track and timer is None) else None
+        if side is not None:
+            self._acc.zero_()  # v_X, v_tw_cur, loss
+            main = torch.cuda.current_stream()
+            side.wait_stream(main)
+            with torch.cuda.stream(side):
+                L.track_reproj_fwd_bwd(self.ctx, self.X, self.viewmat, self.intr, self.obs_cam,
+                                       self.obs_pt, self.obs_xy, self.delta, self.lam, 0.01,
+                                       self.loss[1:2], self.v_X, self.v_tw_cur, pt_index=self.pt_index,
+                                       stream=side)
         with t("project"):
             L.gs_project(self.ctx, self.g, cams, s)
         with t("bin_sort"):
             L.gs_bin_sort(self.ctx, cams, self.N, s)
         with t("render_fwd"):
             L.gs_render_fwd(self.ctx, cams, s, None, self.rgb, self.T, self.last)
-        self._acc.zero_()  # v_X, v_tw_cur, loss
+        if side is None:
+            self._acc.zero_()  # v_X, v_tw_cur, loss
         if self.lambda_ssim > 0:
             with t("photo"):
                 L.gs_photo_loss_grad(self.ctx, cams, self.rgb, self.targets[b], self.lambda_ssim,
@@ -162,6 +180,8 @@ class JointStep:
                                   self.loss[0:1])
         with t("raster_bwd"):
             L.gs_raster_bwd(self.ctx, cams, s, None, self.T, self.last, self.v_rgb)
+        if side is not None:
+            torch.cuda.current_stream().wait_stream(side)
         if adam_step is None and step_dev is None:
             with t("project_bwd"):
                 L.gs_project_bwd(self.ctx, self.g, cams, s, self.gg, self.v_tw_cur)
@@ -173,10 +193,11 @@ class JointStep:
                                       [self.v[k] for k in PARAM_KEYS],
                                       [self.lr[k] for k in PARAM_KEYS], adam_step, self.v_tw_cur,
                                       step_dev=step_dev)
-        with t("track"):
-            L.track_reproj_fwd_bwd(self.ctx, self.X, self.viewmat, self.intr, self.obs_cam,
-                                   self.obs_pt, self.obs_xy, self.delta, self.lam, 0.01,
-                                   self.loss[1:2], self.v_X, self.v_tw_cur, pt_index=self.pt_index)
+        if side is None:
+            with t("track"):
+                L.track_reproj_fwd_bwd(self.ctx, self.X, self.viewmat, self.intr, self.obs_cam,
+                                       self.obs_pt, self.obs_xy, self.delta, self.lam, 0.01,
+                                       self.loss[1:2], self.v_X, self.v_tw_cur, pt_index=self.pt_index)
         with t("pose_compose_bwd"):
             L.gs_pose_compose_bwd(self.twist, self.v_tw_cur, self.v_tw)
         del P

@@ -332,3 +332,31 @@ def test_checkpoint_round_trip(gs, tmp_path):
     with np.load(str(f), allow_pickle=False) as z:
         assert set(z["step"].tolist()) == {2}
         assert z["param/sh"].shape == tuple(st.params["sh"].shape)
+
+
+def test_track_on_a_second_stream_matches_in_line(gs):
+    """The joint step with the track term on its own stream (the default: it
+    joins before the projection backward adds its twist rows) against the
+    same step with every call in line."""
+    from paper_2603_04847_amd.step import JointStep
+    sc = scenegen.blob_scene(9, [(150, 110)] * 4, 12000, sh_degree=3)
+    rng = sc.pop("_rng")
+    sc.update(scenegen.make_tracks(rng, 2000, sc["viewmat"], sc["intr"], sc["wh"], 10))
+    batches = [np.array([0, 3]), np.array([1, 2])]
+    targets = [scenegen.view_targets(9, sc["wh"], b) for b in batches]
+    st = JointStep(sc, batches, targets, max_isect=3_000_000)
+    assert st.overlap_track
+    outs = []
+    for overlap in (True, False):
+        st.overlap_track = overlap
+        st.forward_backward(1)
+        torch.cuda.synchronize()
+        outs.append(dict(v_X=st.v_X.cpu().numpy().copy(), v_tw=st.v_tw.cpu().numpy().copy(),
+                         loss=st.loss.cpu().numpy().copy(),
+                         **{k: v.cpu().numpy().copy() for k, v in st.grads.items()}))
+    a, b = outs
+    # the track term's sums run in a fixed order: its gradient is the same bit for bit
+    assert np.array_equal(a["v_X"], b["v_X"])
+    assert a["loss"][1] == b["loss"][1]
+    for k in a:
+        _close(a[k], b[k], f"{k} (second stream vs in line)", rtol=1e-5)
