@@ -10,10 +10,7 @@
 // walks the batch reading each splat's parameters with broadcast LDS loads
 // (one address for all lanes), synchronising only with itself.  Loads run two
 // batches ahead: while a batch composites, the next batch's records and the
-// list entries of the one after it are in flight.  Over lazy lists the
-// forward draws each batch from its block's list instead (filtered by the
-// tile's mask bits) and writes it to the tile list for the backward.  The
-// backward walks the same
+// list entries of the one after it are in flight.  The backward walks the same
 // lists back to front from each pixel's last contributor, recovering the
 // transmittance by division, and sums each splat's nine 2D gradients over the
 // whole wave (DPP and lane-swap steps) before one lane per component issues
