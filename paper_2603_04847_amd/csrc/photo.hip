@@ -55,8 +55,8 @@ struct PhotoArgs {
 // after a barrier, the three partial-derivative maps (kMid x kMid) and their
 // horizontal window sums (kMid rows x kT columns).
 struct PhotoLds {
-    float X[kIn][kIn + 1];
-    float Y[kIn][kIn + 1];
+    float X[kIn][kIn + 3];  // columns kIn.. are read only for outputs past kMid
+    float Y[kIn][kIn + 3];
     union {
         float H[5][kIn][kMid + 1];
         struct {
@@ -67,10 +67,12 @@ struct PhotoLds {
     float red[2][kThreads / kWave];
 };
 
-// Runs: horizontal passes write 7 (first) or 8 (partials) consecutive
+// Runs: horizontal passes write 11 (first) or 8 (partials) consecutive
 // columns per work item, vertical passes 7 (first) or 4 (last) consecutive
 // rows.
-constexpr int kRunA = 7;  // 42 = 6 x 7: 252 vertical items, one per thread
+constexpr int kRunH = 11;  // 42 <= 4 x 11: 208 horizontal items, one per thread
+constexpr int kGroupsH = (kMid + kRunH - 1) / kRunH;
+constexpr int kRunA = 7;   // 42 = 6 x 7: 252 vertical items, one per thread
 constexpr int kRunB = 8;  // 32 = 4 x 8
 constexpr int kRunC = 4;  // the last vertical pass: 32 = 8 x 4, one item per thread
 
@@ -88,33 +90,55 @@ __global__ __launch_bounds__(kThreads) void k_photo(PhotoArgs a, Window win) {
     const float wv = 1.f / (3.f * (float)W * (float)H * (float)a.vt.V);
     const float lam = a.lambda;
     float l1_part = 0.f, s_part = 0.f;
-#pragma unroll 1
-    for (int ch = 0; ch < 3; ch++) {
-        // ---- the two images with the halo (zeros outside the view)
-        for (int i = tid; i < kIn * kIn; i += kThreads) {
+    // the two images of a channel with the halo (zeros outside the view): all
+    // of a thread's loads are issued at once, into registers, and stored to
+    // LDS when the channel starts (one round trip to memory per channel, not
+    // one per 256 pixels, and for the second and third channels hidden
+    // behind the previous channel's work)
+    constexpr int kLoads = (kIn * kIn + kThreads - 1) / kThreads;  // 11
+    float ldx[kLoads], ldy[kLoads];
+    auto issue = [&](int ch) {
+        // the pixel indexes are formed anew per channel (kept opaque to the
+        // compiler): held across the channel loop they would cost 44 registers
+        int t0 = tid;
+        asm volatile("" : "+v"(t0));
+#pragma unroll
+        for (int u = 0; u < kLoads; u++) {
+            const int i = t0 + u * kThreads;
             const int r = i / kIn, c = i % kIn;
             const int px = x0 - 2 * kR + c, py = y0 - 2 * kR + r;
-            float xv = 0.f, yv = 0.f;
-            if (px >= 0 && px < W && py >= 0 && py < H) {
+            ldx[u] = ldy[u] = 0.f;
+            if (i < kIn * kIn && px >= 0 && px < W && py >= 0 && py < H) {
                 const int64_t q = poff + (int64_t)py * W + px;
-                xv = a.rgb[3 * q + ch];
-                yv = a.target[3 * q + ch];
+                ldx[u] = a.rgb[3 * q + ch];
+                ldy[u] = a.target[3 * q + ch];
             }
-            s.X[r][c] = xv;
-            s.Y[r][c] = yv;
+        }
+    };
+    issue(0);
+#pragma unroll 1
+    for (int ch = 0; ch < 3; ch++) {
+#pragma unroll
+        for (int u = 0; u < kLoads; u++) {
+            const int i = tid + u * kThreads;
+            if (i < kIn * kIn) {
+                s.X[i / kIn][i % kIn] = ldx[u];
+                s.Y[i / kIn][i % kIn] = ldy[u];
+            }
         }
         __syncthreads();
         // ---- horizontal window sums of x, y, x^2, y^2, x y: every row of the
         // halo, columns of the tile plus the ring
         // consecutive lanes take consecutive rows at one column run: the odd
         // row strides (53, 43 words) put their LDS words in distinct banks
-        for (int item = tid; item < kIn * (kMid / kRunA); item += kThreads) {
-            const int r = item % kIn, c0 = (item / kIn) * kRunA;
+        // (the last run's outputs past kMid are computed and dropped)
+        for (int item = tid; item < kIn * kGroupsH; item += kThreads) {
+            const int r = item % kIn, c0 = (item / kIn) * kRunH;
             // the run's inputs and their squares and products, formed once
-            float xs[kRunA + kTaps - 1], ys[kRunA + kTaps - 1];
-            float xx[kRunA + kTaps - 1], yy[kRunA + kTaps - 1], xy[kRunA + kTaps - 1];
+            float xs[kRunH + kTaps - 1], ys[kRunH + kTaps - 1];
+            float xx[kRunH + kTaps - 1], yy[kRunH + kTaps - 1], xy[kRunH + kTaps - 1];
 #pragma unroll
-            for (int k = 0; k < kRunA + kTaps - 1; k++) {
+            for (int k = 0; k < kRunH + kTaps - 1; k++) {
                 xs[k] = s.X[r][c0 + k];
                 ys[k] = s.Y[r][c0 + k];
                 xx[k] = xs[k] * xs[k];
@@ -122,7 +146,8 @@ __global__ __launch_bounds__(kThreads) void k_photo(PhotoArgs a, Window win) {
                 xy[k] = xs[k] * ys[k];
             }
 #pragma unroll
-            for (int j = 0; j < kRunA; j++) {
+            for (int j = 0; j < kRunH; j++) {
+                if (c0 + j >= kMid) break;
                 float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f;
 #pragma unroll
                 for (int k = 0; k < kTaps; k++) {
@@ -205,6 +230,8 @@ __global__ __launch_bounds__(kThreads) void k_photo(PhotoArgs a, Window win) {
             }
         }
         __syncthreads();
+        // the next channel's loads, in flight behind the last two passes
+        if (ch + 1 < 3) issue(ch + 1);
         // ---- horizontal window sums of the partials: rows of tile and ring,
         // columns of the tile; one map per item (504 items for 256 threads),
         // consecutive lanes on consecutive rows
