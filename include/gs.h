@@ -188,8 +188,11 @@ typedef struct {
  * caller-built record array in this layout. */
 #define GS_RECORD_FLOATS 12
 
-/* Per-pair 2D gradient, 9 floats per pair (accumulated by the raster backward):
- *   d/d(mean2d.x, mean2d.y, conic A, B, C, opacity, red, green, blue). */
+/* Per-pair 2D gradient, 9 floats per pair, accumulated by the raster backward
+ * into the context:
+ *   d/d(mean2d.x, mean2d.y, conic A, B, C, opacity, red, green, blue).
+ * They are held in two planes: the first six of every pair, then (after
+ * max_pairs such groups) the last three of every pair. */
 #define GS_GRAD2D_FLOATS 9
 
 const char* gs_strerror(gs_status s);

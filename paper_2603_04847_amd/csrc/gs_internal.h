@@ -47,6 +47,13 @@ struct Ctx;  // defined in gs_api.hip
 
 constexpr int kAuxFloats = 8192;
 
+// The per-pair 2D gradients live in two planes of one buffer: six floats per
+// pair for the geometry (mean x, y, conic A, B, C, opacity) and, after the
+// pair capacity's worth of those, three per pair for the colour, so the two
+// halves of the projection backward each read only their own part.
+constexpr int kGradGeo = 6;
+constexpr int kGradCol = 3;
+
 // ------------------------------------------------------------------ device helpers
 
 __device__ __forceinline__ float bcast(float v, int lane) {
@@ -552,7 +559,8 @@ struct Ctx {
     gs_capacity cap;
     int device;
     float* rec;            // [max_pairs][12]
-    float* grad2d;         // [max_pairs][9], kept zero between backward calls
+    float* grad2d;         // [max_pairs][6] geometry, then [max_pairs][3] colour; kept zero
+                           // between backward calls
     float* vmu_dir;        // [3][max_pairs] the colour's share of the mean gradient (backward)
     uint32_t* cnt;         // [max_pairs] list entries per pair
     uint32_t* off;         // [max_pairs] entry counts in depth order, then their scan

@@ -372,7 +372,7 @@ __device__ __forceinline__ void step_entries(const float (&gr)[NE], Arr arr, Row
 template <int DEG, bool ADAM>
 __global__ __launch_bounds__(kBlock) void k_project_bwd_color(gs_gaussians g, const float* __restrict__ viewmat,
                                  const float* __restrict__ intr, ViewTable vt, RasterParams rp,
-                                 float* __restrict__ grad2d, gs_gaussians_grad out, int accumulate,
+                                 float* __restrict__ grad_col, gs_gaussians_grad out, int accumulate,
                                  AdamGauss adam, float* __restrict__ vmu_dir,
                                  double* __restrict__ twist_acc) {
     constexpr int K = (DEG + 1) * (DEG + 1);
@@ -415,7 +415,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_color(gs_gaussians g, co
             // the next view's colour gradients are requested ahead, as above
             float gcn[3];
             {
-                const float* gp0 = grad2d + 9 * (int64_t)(active ? i : 0) + 6;
+                const float* gp0 = grad_col + kGradCol * (int64_t)(active ? i : 0);
 #pragma unroll
                 for (int k = 0; k < 3; k++) gcn[k] = (active && vt.V > 0) ? gp0[k] : 0.f;
             }
@@ -423,12 +423,12 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_color(gs_gaussians g, co
                 float tw[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
                 const float gc[3] = {gcn[0], gcn[1], gcn[2]};
                 if (v + 1 < vt.V) {
-                    const float* gq = grad2d + 9 * ((int64_t)(v + 1) * N + (active ? i : 0)) + 6;
+                    const float* gq = grad_col + kGradCol * ((int64_t)(v + 1) * N + (active ? i : 0));
 #pragma unroll
                     for (int k = 0; k < 3; k++) gcn[k] = active ? gq[k] : 0.f;
                 }
                 if (active) {
-                    float* gp = grad2d + 9 * ((int64_t)v * N + i) + 6;
+                    float* gp = grad_col + kGradCol * ((int64_t)v * N + i);
                     // a pair that was never rendered (culled, or outside every
                     // list) has no gradient at all
                     if (gc[0] != 0.f || gc[1] != 0.f || gc[2] != 0.f) {
@@ -492,7 +492,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_color(gs_gaussians g, co
 template <bool ADAM>
 __global__ __launch_bounds__(kBlock) void k_project_bwd_geom(gs_gaussians g, const float* __restrict__ viewmat,
                                  const float* __restrict__ intr, ViewTable vt, RasterParams rp,
-                                 float* __restrict__ grad2d, gs_gaussians_grad out, int accumulate,
+                                 float* __restrict__ grad_geo, gs_gaussians_grad out, int accumulate,
                                  AdamGauss adam, float* __restrict__ vmu_dir,
                                  double* __restrict__ twist_acc) {
     if (ADAM) adam_bias(adam.step_dev, adam.step, adam.b1, adam.b2, adam.ibc1, adam.ibc2);
@@ -531,7 +531,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_geom(gs_gaussians g, con
             // chain runs, so their latency hides behind it
             float G9n[6];
             {
-                const float* gp0 = grad2d + 9 * (int64_t)(active ? i : 0);
+                const float* gp0 = grad_geo + kGradGeo * (int64_t)(active ? i : 0);
 #pragma unroll
                 for (int k = 0; k < 6; k++) G9n[k] = (active && vt.V > 0) ? gp0[k] : 0.f;
             }
@@ -541,12 +541,12 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_geom(gs_gaussians g, con
 #pragma unroll
                 for (int k = 0; k < 6; k++) G9[k] = G9n[k];
                 if (v + 1 < vt.V) {
-                    const float* gq = grad2d + 9 * ((int64_t)(v + 1) * N + (active ? i : 0));
+                    const float* gq = grad_geo + kGradGeo * ((int64_t)(v + 1) * N + (active ? i : 0));
 #pragma unroll
                     for (int k = 0; k < 6; k++) G9n[k] = active ? gq[k] : 0.f;
                 }
                 if (active) {
-                    float* gp = grad2d + 9 * ((int64_t)v * N + i);
+                    float* gp = grad_geo + kGradGeo * ((int64_t)v * N + i);
                     bool nz = false;
 #pragma unroll
                     for (int k = 0; k < 6; k++) nz |= G9[k] != 0.f;
@@ -724,17 +724,19 @@ void project_bwd_impl(Ctx* c, const gs_gaussians* g, const gs_cameras* cams, con
     const dim3 grid(std::min((g->N + kBlock - 1) / kBlock, 2048)), block(kBlock);
     const gs_gaussians_grad none{};
     const AdamGauss no_adam{};
+    float* geo = c->grad2d;
+    float* col = c->grad2d + kGradGeo * c->cap.max_pairs;
     if (adam) {
         hipLaunchKernelGGL((k_project_bwd_color<DEG, true>), grid, block, 0, st, *g, cams->viewmat,
-                           cams->intr, vt, rp, c->grad2d, none, 0, *adam, c->vmu_dir, c->twist_render);
+                           cams->intr, vt, rp, col, none, 0, *adam, c->vmu_dir, c->twist_render);
         hipLaunchKernelGGL((k_project_bwd_geom<true>), grid, block, 0, st, *g, cams->viewmat, cams->intr,
-                           vt, rp, c->grad2d, none, 0, *adam, c->vmu_dir, c->twist_render);
+                           vt, rp, geo, none, 0, *adam, c->vmu_dir, c->twist_render);
     } else {
         hipLaunchKernelGGL((k_project_bwd_color<DEG, false>), grid, block, 0, st, *g, cams->viewmat,
-                           cams->intr, vt, rp, c->grad2d, *grads, accumulate, no_adam, c->vmu_dir,
+                           cams->intr, vt, rp, col, *grads, accumulate, no_adam, c->vmu_dir,
                            c->twist_render);
         hipLaunchKernelGGL((k_project_bwd_geom<false>), grid, block, 0, st, *g, cams->viewmat,
-                           cams->intr, vt, rp, c->grad2d, *grads, accumulate, no_adam, c->vmu_dir,
+                           cams->intr, vt, rp, geo, *grads, accumulate, no_adam, c->vmu_dir,
                            c->twist_render);
     }
 }

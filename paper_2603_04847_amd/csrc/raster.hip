@@ -382,7 +382,8 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ re
                                                    const float* __restrict__ T_final,
                                                    const int32_t* __restrict__ last_in,
                                                    const float* __restrict__ v_rgb,
-                                                   float* __restrict__ grad2d, int mode) {
+                                                   float* __restrict__ grad_geo,
+                                                   float* __restrict__ grad_col, int mode) {
     using TM = TileMap<TW, TH>;
     constexpr int PPL = TM::PPL;
     int t;
@@ -521,7 +522,8 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ re
                                                   __builtin_fmaf(vb, qb, vc * qc) * QY);
                 const float val = __builtin_fmaf(o * kLn2, mean, E * __builtin_fmaf(kS, o, kE));
                 const int64_t p = idb & kPairMask;
-                atomicAdd(grad2d + GS_GRAD2D_FLOATS * p + comp, val);
+                atomicAdd(comp < kGradGeo ? grad_geo + kGradGeo * p + comp
+                                          : grad_col + kGradCol * p + (comp - kGradGeo), val);
             }
             g_r = g_g = g_b = g_o = 0.f;
             m_x = m_y = m_xx = m_xy = m_yy = 0.f;
@@ -605,7 +607,8 @@ hipError_t bwd_impl(Ctx* c, const ViewTable& vt, const RasterParams& rp, const f
                     const uint32_t* order, int mode, hipStream_t st) {
     hipLaunchKernelGGL((k_render_bwd<TW, TH>), dim3(raster_grid(c, vt, mode)), dim3(64), 0, st,
                        reinterpret_cast<const float4*>(c->rec), reinterpret_cast<const int32_t*>(c->tids), c->tranges, order,
-                       vt, rp, bg, T_final, last, v_rgb, c->grad2d, mode);
+                       vt, rp, bg, T_final, last, v_rgb, c->grad2d,
+                       c->grad2d + kGradGeo * c->cap.max_pairs, mode);
     return hipGetLastError();
 }
 
