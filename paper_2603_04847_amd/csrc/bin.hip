@@ -101,40 +101,22 @@ __global__ __launch_bounds__(kBlock) void k_count(const float4* __restrict__ rec
     // the block ranges start empty (the sorted keys fill the blocks that have entries)
     for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < nbr; k += (int64_t)gridDim.x * kBlock)
         branges[k] = 0;
-    __shared__ WaveUnits s_wu[kWaves];
-    __shared__ uint32_t s_cnt[kWaves][kWave];
     const int64_t pair = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-    WaveUnits& wu = s_wu[w];
-    const QuadGrid qg = quad_grid(rp.tile_w, rp.tile_h);
-    float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
-    int v = 0;
-    bool ok = false;
-    if (pair < (int64_t)vt.V * N) {
-        v = (int)(pair / N);
-        a = rec[3 * pair];
-        b = rec[3 * pair + 1];
-        ok = record_ok(a, b, rp.alpha_min);
+    if (pair >= (int64_t)vt.V * N) return;
+    const int v = (int)(pair / N);
+    const float4 a = rec[3 * pair], b = rec[3 * pair + 1];
+    // an upper bound per block row (the emit pass fills what it over-counts),
+    // each lane over its own splat's rows
+    uint32_t c = 0;
+    if (record_ok(a, b, rp.alpha_min)) {
+        const SplatSpan sp = splat_span(a, b, vt.H[v], quad_grid(rp.tile_w, rp.tile_h), rp.alpha_min);
+        if (sp.r0 <= sp.r1)
+            for (int br = sp.r0 / kBlockQuads; br <= sp.r1 / kBlockQuads; br++)
+                c += (uint32_t)unit_band_count(sp, br, vt.W[v], vt.H[v], quad_grid(rp.tile_w, rp.tile_h));
     }
-    uint32_t U;
-    wave_units_load(wu, lane, ok, a, b, v, vt, rp, U);
-    s_cnt[w][lane] = 0;
-    __syncthreads();
-    // an upper bound per unit (the emit pass fills what it over-counts)
-    for (uint32_t j = lane; j < U; j += kWave) {
-        const int q = seg_search(wu.upre, kWave, j);
-        const int vq = wu.v[q];
-        const int br = wu.sp[q].r0 / kBlockQuads + (int)(j - wu.upre[q]);
-        const int n = unit_band_count(wu.sp[q], br, vt.W[vq], vt.H[vq], qg);
-        if (n) atomicAdd(&s_cnt[w][q], (uint32_t)n);
-    }
-    __syncthreads();
-    if (pair < (int64_t)vt.V * N) {
-        const uint32_t c = s_cnt[w][lane];
-        cnt[pair] = c;
-        key[pair] = c > 0 ? __float_as_uint(a.z) : 0xFFFFFFFFu;
-        val[pair] = (uint32_t)pair;
-    }
+    cnt[pair] = c;
+    key[pair] = c > 0 ? __float_as_uint(a.z) : 0xFFFFFFFFu;
+    val[pair] = (uint32_t)pair;
 }
 
 // One (block key; pair, mask) entry per block met, pairs in depth order: rank
