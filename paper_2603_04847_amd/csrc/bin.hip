@@ -7,7 +7,7 @@
 //              pairs get key 0xFFFFFFFF and no blocks.
 //  2. sort the pairs by depth key (stable LSD radix from pair order, so equal
 //     depths stay in pair order): this is the (depth, pair) order.  The pair
-//     index and its block count travel with the key.
+//     index and its block count travel with the key, packed in one word.
 //  3. scan the block counts in that order and emit one (block, pair, 64-bit
 //     quadrant mask) entry per block met, from the exact per-quadrant-row
 //     spans; entries of one pair are contiguous, pairs in depth order, and the
@@ -97,7 +97,8 @@ __global__ __launch_bounds__(kBlock) void k_count(const float4* __restrict__ rec
                                                   uint32_t* __restrict__ cnt,
                                                   uint32_t* __restrict__ key,
                                                   uint32_t* __restrict__ val,
-                                                  int32_t* __restrict__ branges, int64_t nbr) {
+                                                  int32_t* __restrict__ branges, int64_t nbr,
+                                                  int pbits) {
     // the block ranges start empty (the sorted keys fill the blocks that have entries)
     for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < nbr; k += (int64_t)gridDim.x * kBlock)
         branges[k] = 0;
@@ -116,7 +117,21 @@ __global__ __launch_bounds__(kBlock) void k_count(const float4* __restrict__ rec
     }
     cnt[pair] = c;
     key[pair] = c > 0 ? __float_as_uint(a.z) : 0xFFFFFFFFu;
-    val[pair] = (uint32_t)pair;
+    // the pair index in the low pbits, the count above it (all ones when it
+    // does not fit: the full count is then read back from cnt)
+    val[pair] = (uint32_t)pair | (min(c, ~0u >> pbits) << pbits);
+}
+
+// The entry counts in depth order from the sorted packed words.
+__global__ __launch_bounds__(kBlock) void k_unpack_counts(const uint32_t* __restrict__ packed,
+                                                          const uint32_t* __restrict__ cnt, int64_t n,
+                                                          int pbits, uint32_t* __restrict__ out) {
+    const uint32_t esc = ~0u >> pbits, pmask = (1u << pbits) - 1u;
+    for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r < n; r += (int64_t)gridDim.x * kBlock) {
+        const uint32_t w = packed[r];
+        const uint32_t c = w >> pbits;
+        out[r] = c == esc ? cnt[w & pmask] : c;
+    }
 }
 
 // One (block key; pair, mask) entry per block met, pairs in depth order: rank
@@ -128,7 +143,7 @@ __global__ __launch_bounds__(kBlock) void k_count(const float4* __restrict__ rec
 // keys sort before the culled ones' 0xFFFFFFFF).
 __global__ __launch_bounds__(kBlock) void k_emit(const float4* __restrict__ rec, int N, ViewTable vt,
                                                  RasterParams rp, const uint32_t* __restrict__ order,
-                                                 const uint32_t* __restrict__ off,
+                                                 uint32_t pmask, const uint32_t* __restrict__ off,
                                                  const uint32_t* __restrict__ keys, int64_t n,
                                                  const uint32_t* __restrict__ used,
                                                  uint32_t* __restrict__ okey,
@@ -155,7 +170,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(const float4* __restrict__ rec,
         if (vis && !next_vis) diag[kDiagVisible] = (uint32_t)(r + 1);
     }
     if (r < n && any) {
-        pair = order[r];
+        pair = order[r] & pmask;
         o0 = off[r];
         const uint32_t o1 = r + 1 < n ? off[r + 1] : lim;
         c = o1 > o0 ? o1 - o0 : 0u;
@@ -653,17 +668,19 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
     c->lists_filled = false;
     if (npairs > 0) {
         const unsigned gp = (unsigned)((npairs + kBlock - 1) / kBlock);
+        int pbits = 1;  // bits of a pair index (the capacity keeps it at most 26)
+        while (((int64_t)1 << pbits) < npairs) pbits++;
         hipLaunchKernelGGL(k_count, dim3(gp), dim3(kBlock), 0, st, rec, N, vt, rp, c->cnt, c->pk[0],
-                           c->pv[0], c->ranges, 2 * NB);
-        // the pair and its entry count travel with the depth key; the sorted
-        // counts are then scanned in place into the entry offsets
-        uint32_t* PK[2] = {c->pk[0], c->pk[1]};
-        uint32_t* PV[2][2] = {{c->pv[0], c->pv[1]}, {c->cnt, c->off}};
-        const int side = radix_sort_kv2(PK, PV, npairs, nullptr, 0, 32, c->hist, c->scan_scratch,
-                                        c->diag + kDiagFlags, st, &e);
+                           c->pv[0], c->ranges, 2 * NB, pbits);
+        // the pair and its entry count travel with the depth key as one word;
+        // the sorted counts are then unpacked and scanned into the entry offsets
+        const int side = radix_sort_pairs(c->pk[0], c->pv[0], c->pk[1], c->pv[1], npairs, nullptr, 0, 32,
+                                          c->hist, c->scan_scratch, c->diag + kDiagFlags, st, &e);
         if (e != hipSuccess) return e;
         const uint32_t* order = c->pv[side];
-        uint32_t* off = PV[1][side];
+        uint32_t* off = c->off;
+        hipLaunchKernelGGL(k_unpack_counts, dim3((unsigned)std::min<int64_t>(gp, 8192)), dim3(kBlock), 0, st,
+                           order, c->cnt, npairs, pbits, off);
         uint32_t* total = c->scalars + 0;
         uint32_t* used = c->scalars + 1;
         // the scan's last tile checks the block-entry total against the capacity
@@ -672,7 +689,8 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
                                     &chk_blocks)) != hipSuccess)
             return e;
         const int64_t I = c->cap.max_isect;
-        hipLaunchKernelGGL(k_emit, dim3(gp), dim3(kBlock), 0, st, rec, N, vt, rp, order, off,
+        hipLaunchKernelGGL(k_emit, dim3(gp), dim3(kBlock), 0, st, rec, N, vt, rp, order,
+                           (uint32_t)((1u << pbits) - 1u), off,
                            c->pk[side], npairs, used, c->ik[0], c->iv[0], c->im[0], c->im[0] + I, c->diag);
         int bbits = 1;  // block ids and the sentinel NB
         while (((int64_t)1 << bbits) <= NB) bbits++;
