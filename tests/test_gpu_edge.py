@@ -194,3 +194,50 @@ def test_render_bwd_checks_everything_before_enqueueing(gs):
         a, b = again[k].cpu().numpy(), ref[k].cpu().numpy()
         assert np.max(np.abs(a - b)) <= 1e-5 * (np.max(np.abs(b)) + 1e-30), k
     assert not torch.any(v_tw != 0).item()
+
+
+def test_entry_counts_past_the_packed_count_field(gs):
+    """The depth sort carries each pair's block-entry count in the bits above
+    its pair index; past 2^25 pairs that leaves 6 bits, and larger counts are
+    read back from the per-pair array.  48 splats of unit scale, each meeting
+    far more than 63 blocks of a 1024 x 768 view, render the same image with
+    and without 2^25 - 47 culled Gaussians after them (the pair indices of the
+    48 do not change), and their gradients agree to float-atomic rounding."""
+    from paper_2603_04847_amd.splat import Splatter
+    s = scenegen.frustum_scene(47, 1024, 768, 600.0, 600.0, 48, 0, 0.0, 0.0, sh_sd=0.3)
+    keys = ("means", "log_scales", "quats", "opacity_logit", "sh")
+    small = {k: _t(s[k]) for k in keys}
+    n_big = (1 << 25) + 1
+    pad = n_big - 48
+    big = {
+        "means": torch.cat([small["means"], torch.zeros((3, pad), device="cuda")], 1),
+        "log_scales": torch.cat([small["log_scales"], torch.full((3, pad), -5.0, device="cuda")], 1),
+        "quats": torch.cat([small["quats"], torch.tensor([[1.0], [0.0], [0.0], [0.0]], device="cuda").expand(4, pad)], 1),
+        "opacity_logit": torch.cat([small["opacity_logit"], torch.full((pad,), -40.0, device="cuda")]),
+        "sh": torch.cat([small["sh"], torch.zeros((1, 3, pad), device="cuda")], 2),
+    }
+    big = {k: v.contiguous() for k, v in big.items()}
+    vm, intr = _t(s["viewmat"]), _t(s["intr"])
+    v_rgb = _t(np.random.default_rng(5).normal(size=(1024 * 768, 3)))
+    out = []
+    for params, n in ((small, 48), (big, n_big)):
+        print(f"[entry counts] N = {n}", flush=True)
+        ctx = gs.Context(max_pairs=n, max_isect=1 << 20, max_tiles=4096, max_views=1)
+        sp = Splatter(ctx)
+        rgb, T, last, cams = sp.forward(params, 0, vm, intr, s["wh"])
+        grads, v_tw = sp.backward(params, 0, cams, T, last, v_rgb)
+        torch.cuda.synchronize()
+        st = ctx.status()
+        assert st["flags"] == 0, st
+        out.append((rgb.cpu().numpy(), T.cpu().numpy(), last.cpu().numpy(),
+                    {k: g[..., :48].cpu().numpy() for k, g in grads.items()}, v_tw.cpu().numpy(),
+                    st["n_isect"]))
+        del ctx, sp, grads
+    (r0, T0, l0, g0, tw0, i0), (r1, T1, l1, g1, tw1, i1) = out
+    # tile entries past 48 x 63 x 16: some splat meets more than 63 blocks of
+    # 16 tiles, so its count took the escape
+    assert i0 == i1 and i0 > 48 * 63 * 16
+    assert np.array_equal(r0, r1) and np.array_equal(T0, T1) and np.array_equal(l0, l1)
+    for k in keys:
+        assert np.max(np.abs(g0[k] - g1[k])) <= 1e-5 * (np.max(np.abs(g0[k])) + 1e-30), k
+    assert np.max(np.abs(tw0 - tw1)) <= 1e-5 * np.max(np.abs(tw0))
