@@ -122,18 +122,6 @@ __global__ __launch_bounds__(kBlock) void k_count(const float4* __restrict__ rec
     val[pair] = (uint32_t)pair | (min(c, ~0u >> pbits) << pbits);
 }
 
-// The entry counts in depth order from the sorted packed words.
-__global__ __launch_bounds__(kBlock) void k_unpack_counts(const uint32_t* __restrict__ packed,
-                                                          const uint32_t* __restrict__ cnt, int64_t n,
-                                                          int pbits, uint32_t* __restrict__ out) {
-    const uint32_t esc = ~0u >> pbits, pmask = (1u << pbits) - 1u;
-    for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r < n; r += (int64_t)gridDim.x * kBlock) {
-        const uint32_t w = packed[r];
-        const uint32_t c = w >> pbits;
-        out[r] = c == esc ? cnt[w & pmask] : c;
-    }
-}
-
 // One (block key; pair, mask) entry per block met, pairs in depth order: rank
 // r's entries fill [off[r], off[r + 1]) (the last rank ends at the total).  The
 // 64 ranks of a wave own one contiguous output range; in each round every lane
@@ -679,14 +667,14 @@ hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp
         if (e != hipSuccess) return e;
         const uint32_t* order = c->pv[side];
         uint32_t* off = c->off;
-        hipLaunchKernelGGL(k_unpack_counts, dim3((unsigned)std::min<int64_t>(gp, 8192)), dim3(kBlock), 0, st,
-                           order, c->cnt, npairs, pbits, off);
         uint32_t* total = c->scalars + 0;
         uint32_t* used = c->scalars + 1;
-        // the scan's last tile checks the block-entry total against the capacity
+        // the counts, unpacked as the scan loads them; its last tile checks
+        // the block-entry total against the capacity
         const CapCheck chk_blocks = {c->cap.max_isect, used, c->diag, nullptr, nullptr};
-        if ((e = exclusive_scan_u32(off, npairs, total, c->scan_scratch, c->diag + kDiagFlags, st,
-                                    &chk_blocks)) != hipSuccess)
+        const ScanUnpack un = {order, c->cnt, pbits};
+        if ((e = exclusive_scan_u32_unpack(off, un, npairs, total, c->scan_scratch, c->diag + kDiagFlags, st,
+                                           &chk_blocks)) != hipSuccess)
             return e;
         const int64_t I = c->cap.max_isect;
         hipLaunchKernelGGL(k_emit, dim3(gp), dim3(kBlock), 0, st, rec, N, vt, rp, order,

@@ -424,6 +424,16 @@ struct CapCheck {
 };
 hipError_t exclusive_scan_u32(uint32_t* data, int64_t n, uint32_t* total_out, uint32_t* scratch,
                               uint32_t* flags, hipStream_t st, const CapCheck* chk = nullptr);
+// The same, with the input unpacked on load from words that hold an index in
+// their low pbits and a count above it: the count, or cnt[index] where the
+// count field is all ones.  The scan is written to data (not to src).
+struct ScanUnpack {
+    const uint32_t* src;
+    const uint32_t* cnt;
+    int pbits;
+};
+hipError_t exclusive_scan_u32_unpack(uint32_t* data, const ScanUnpack& un, int64_t n, uint32_t* total_out,
+                                     uint32_t* scratch, uint32_t* flags, hipStream_t st, const CapCheck* chk);
 // The same over a length the device holds: mul * (ceil(*d_cnt / per) + add),
 // at most max_n (the launch covers max_n).
 hipError_t exclusive_scan_u32_dev(uint32_t* data, int64_t max_n, const uint32_t* d_cnt, int64_t per,

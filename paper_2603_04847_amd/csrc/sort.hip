@@ -131,13 +131,14 @@ constexpr int64_t kWideScan = (int64_t)1 << 23;
 // The length is max_n, or, with d_cnt, mul * (ceil(*d_cnt / per) + add)
 // clamped to max_n (a count only the device knows: the grid covers max_n and
 // tiles past the length only take their tickets).
-template <int THREADS>
+template <int THREADS, bool UNPACK = false>
 __global__ __launch_bounds__(THREADS) void k_scan(uint32_t* __restrict__ data, int64_t max_n,
                                                    const uint32_t* __restrict__ d_cnt, int64_t per,
                                                    int64_t mul, int64_t add,
                                                    uint32_t* __restrict__ total_out,
                                                    uint32_t* __restrict__ ws,
-                                                   uint32_t* __restrict__ flags, CapCheck chk) {
+                                                   uint32_t* __restrict__ flags, CapCheck chk,
+                                                   ScanUnpack un) {
     constexpr int TILE = THREADS * kScanItems;
     __shared__ uint32_t s_w[THREADS / kWave];
     __shared__ uint32_t s_t, s_excl, s_last;
@@ -157,8 +158,9 @@ __global__ __launch_bounds__(THREADS) void k_scan(uint32_t* __restrict__ data, i
         const int64_t base = t * TILE + (int64_t)threadIdx.x * kScanItems;
         const bool full = base + kScanItems <= n;
         uint32_t v[kScanItems];
+        const uint32_t* in = UNPACK ? un.src : data;
         if (full) {
-            const uint4* p = reinterpret_cast<const uint4*>(data + base);
+            const uint4* p = reinterpret_cast<const uint4*>(in + base);
 #pragma unroll
             for (int i = 0; i < kScanItems / 4; i++) {
                 const uint4 q = p[i];
@@ -169,7 +171,15 @@ __global__ __launch_bounds__(THREADS) void k_scan(uint32_t* __restrict__ data, i
             }
         } else {
 #pragma unroll
-            for (int i = 0; i < kScanItems; i++) v[i] = base + i < n ? data[base + i] : 0u;
+            for (int i = 0; i < kScanItems; i++) v[i] = base + i < n ? in[base + i] : 0u;
+        }
+        if (UNPACK) {
+            const uint32_t esc = ~0u >> un.pbits, pmask = (1u << un.pbits) - 1u;
+#pragma unroll
+            for (int i = 0; i < kScanItems; i++) {
+                const uint32_t c = v[i] >> un.pbits;
+                v[i] = c == esc ? un.cnt[v[i] & pmask] : c;
+            }
         }
         uint32_t s = 0;
 #pragma unroll
@@ -394,25 +404,35 @@ namespace {
 
 hipError_t scan_launch(uint32_t* data, int64_t max_n, const uint32_t* d_cnt, int64_t per, int64_t mul,
                        int64_t add, uint32_t* total_out, uint32_t* scratch, uint32_t* flags,
-                       hipStream_t st, const CapCheck* chk) {
+                       hipStream_t st, const CapCheck* chk, const ScanUnpack* un = nullptr) {
     CapCheck ck = {};
     if (chk) ck = *chk;
     // nothing to scan: done, unless a capacity check must still see the 0 total
     if (max_n <= 0 && !ck.used) return hipSuccess;
     if (max_n < 0) max_n = 0;
     // whole-tile vector accesses need 16-byte alignment
-    if (reinterpret_cast<uintptr_t>(data) % 16 != 0 || (d_cnt && (per <= 0 || mul <= 0 || add < 0)))
+    if (reinterpret_cast<uintptr_t>(data) % 16 != 0 || (d_cnt && (per <= 0 || mul <= 0 || add < 0)) ||
+        (un && (reinterpret_cast<uintptr_t>(un->src) % 16 != 0 || un->pbits < 1 || un->pbits > 31)))
         return hipErrorInvalidValue;
+    const ScanUnpack u = un ? *un : ScanUnpack{nullptr, nullptr, 1};
     if (max_n > kWideScan) {
         const int64_t ntw = (max_n + kWideThreads * kScanItems - 1) / (kWideThreads * kScanItems);
-        hipLaunchKernelGGL(k_scan<kWideThreads>, dim3((unsigned)ntw), dim3(kWideThreads), 0, st, data, max_n,
-                           d_cnt, per, mul, add, total_out, scratch, flags, ck);
+        if (un)
+            hipLaunchKernelGGL((k_scan<kWideThreads, true>), dim3((unsigned)ntw), dim3(kWideThreads), 0, st, data,
+                               max_n, d_cnt, per, mul, add, total_out, scratch, flags, ck, u);
+        else
+            hipLaunchKernelGGL((k_scan<kWideThreads, false>), dim3((unsigned)ntw), dim3(kWideThreads), 0, st, data,
+                               max_n, d_cnt, per, mul, add, total_out, scratch, flags, ck, u);
         return hipGetLastError();
     }
     const int64_t nt = std::max<int64_t>((max_n + kScanTile - 1) / kScanTile, 1);
     if (nt > ((int64_t)1 << 31)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_scan<kThreads>, dim3((unsigned)nt), dim3(kThreads), 0, st, data, max_n, d_cnt, per, mul,
-                       add, total_out, scratch, flags, ck);
+    if (un)
+        hipLaunchKernelGGL((k_scan<kThreads, true>), dim3((unsigned)nt), dim3(kThreads), 0, st, data, max_n, d_cnt,
+                           per, mul, add, total_out, scratch, flags, ck, u);
+    else
+        hipLaunchKernelGGL((k_scan<kThreads, false>), dim3((unsigned)nt), dim3(kThreads), 0, st, data, max_n, d_cnt,
+                           per, mul, add, total_out, scratch, flags, ck, u);
     return hipGetLastError();
 }
 
@@ -427,6 +447,11 @@ hipError_t exclusive_scan_u32_dev(uint32_t* data, int64_t max_n, const uint32_t*
 hipError_t exclusive_scan_u32(uint32_t* data, int64_t n, uint32_t* total_out, uint32_t* scratch,
                               uint32_t* flags, hipStream_t st, const CapCheck* chk) {
     return scan_launch(data, n, nullptr, 1, 1, 0, total_out, scratch, flags, st, chk);
+}
+
+hipError_t exclusive_scan_u32_unpack(uint32_t* data, const ScanUnpack& un, int64_t n, uint32_t* total_out,
+                                     uint32_t* scratch, uint32_t* flags, hipStream_t st, const CapCheck* chk) {
+    return scan_launch(data, n, nullptr, 1, 1, 0, total_out, scratch, flags, st, chk, &un);
 }
 
 // sized for the smallest block (2048 items)
