@@ -834,8 +834,8 @@ def summarize_counters(raw, workload):
     print(json.dumps(traffic, indent=1))
 
 
-def summarize_trace(raw, workload, cmd):
-    """profiles/joint_step_<workload>_kernel_trace.md from a rocprofv3
+def summarize_trace(raw, workload, cmd, stem=None):
+    """profiles/<stem or joint_step_<workload>>_kernel_trace.md from a rocprofv3
     --kernel-trace --stats run of this bench (`cmd`): per kernel, launches and
     durations, and the live HIP-event time of the dominant kernel from the same
     run's bench line beside the trace's average for it."""
@@ -849,10 +849,12 @@ def summarize_trace(raw, workload, cmd):
     for ln in open(os.path.join(raw + ".json")) if os.path.exists(raw + ".json") else []:
         if ln.startswith("{"):
             line = json.loads(ln)
-    md = [f"# Joint step, {workload}: per-kernel durations (rocprofv3 kernel trace)", "",
+    title = f"Joint step, {workload}" if not stem else stem.replace("_", " ")
+    md = [f"# {title}: per-kernel durations (rocprofv3 kernel trace)", "",
           "Command (the repository at /root/repo; the bench line goes to the .json beside the "
           "trace directory):", "", "```", cmd, "```", "",
-          f"Summary written by `python bench.py --summarize-trace {raw} --workload {workload}`.", "",
+          f"Summary written by `python bench.py --summarize-trace {raw} --workload {workload}"
+          + (f" --trace-name {stem}" if stem else "") + "`.", "",
           "| kernel | calls | total ms | avg us | min us | max us | % |",
           "|---|---:|---:|---:|---:|---:|---:|"]
     trace_avg = {}
@@ -875,7 +877,7 @@ def summarize_trace(raw, workload, cmd):
                f"{roof.get('avg_ms', 0) * 1e3:.1f} us per call (HIP events on its stream, under the "
                f"profiler: {line['value']} MP/s); the trace average of its kernel is "
                + (f"{max(tr):.1f} us." if tr else "not found.")]
-    out = os.path.join(ROOT, "profiles", f"joint_step_{workload}_kernel_trace.md")
+    out = os.path.join(ROOT, "profiles", f"{stem or 'joint_step_' + workload}_kernel_trace.md")
     with open(out, "w") as fh:
         fh.write("\n".join(md) + "\n")
     print(out)
@@ -911,12 +913,14 @@ def main():
                     help="write profiles/joint_step_<workload>_kernel_trace.md from the rocprofv3 "
                          "kernel trace in DIR (and the bench line in DIR.json) and exit")
     ap.add_argument("--trace-cmd", default="", help="the command that made the trace (for the summary)")
+    ap.add_argument("--trace-name", default=None,
+                    help="file name stem of the trace summary (default joint_step_<workload>)")
     args = ap.parse_args()
     if args.summarize_counters:
         summarize_counters(args.summarize_counters, args.workload)
         return
     if args.summarize_trace:
-        summarize_trace(args.summarize_trace, args.workload, args.trace_cmd)
+        summarize_trace(args.summarize_trace, args.workload, args.trace_cmd, args.trace_name)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the hot path "
