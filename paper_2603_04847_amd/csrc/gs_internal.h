@@ -451,10 +451,6 @@ int radix_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int
 int radix_sort_kv3(uint32_t* K[2], uint32_t* V[3][2], int64_t max_n, const uint32_t* d_n, int lo,
                    int hi, uint32_t* hist, uint32_t* scan_scratch, uint32_t* flags, hipStream_t st,
                    hipError_t* err);
-// ... and with two
-int radix_sort_kv2(uint32_t* K[2], uint32_t* V[2][2], int64_t max_n, const uint32_t* d_n, int lo,
-                   int hi, uint32_t* hist, uint32_t* scan_scratch, uint32_t* flags, hipStream_t st,
-                   hipError_t* err);
 
 // bin.hip
 hipError_t launch_bin(Ctx* c, const ViewTable& vt, int N, const RasterParams& rp,

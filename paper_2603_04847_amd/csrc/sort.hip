@@ -494,20 +494,16 @@ int radix_sort_impl(uint32_t* K[2], uint32_t* V[NV][2], int64_t max_n, const uin
             va.in[c] = V[c][cur];
             va.out[c] = V[c][cur ^ 1];
         }
-        // large single-value inputs: 8192 items per block (longer runs per
-        // digit in the scatter); the block sort of a list capacity past 2^27
-        // 4096 (fewer digit counts to scan); a depth sort past 2^23 pairs
-        // 4096 (runs of 16 items per digit: 20M pairs sort 80 us faster over
-        // the four passes than with 2048, and 8192 is 250 us slower); the
-        // others 2048: a depth sort of a few million items still gives every
-        // CU several blocks, and a block sort of tens of millions of entries
-        // gains from the shorter blocks (measured: at 70M capacity 2048 beats
-        // 4096 by 15 us, at 333M it loses by 120 us)
+        // large single-value inputs (the depth sort, whose one value word
+        // packs the pair and its entry count): 8192 items per block, for
+        // longer runs per digit in the scatter; the block sort of a list
+        // capacity past 2^27 4096 (fewer digit counts to scan); the others
+        // 2048: a sort of a few million items still gives every CU several
+        // blocks, and a block sort of tens of millions of entries gains from
+        // the shorter blocks (measured: at 70M capacity 2048 beats 4096 by
+        // 15 us, at 333M it loses by 120 us)
         if (NV == 1 && max_n > ((int64_t)1 << 22))
             *err = radix_pass<32, NV>(K[cur], K[cur ^ 1], va, max_n, d_n, shift, bits, hist,
-                                      scan_scratch, flags, st);
-        else if (NV == 2 && max_n > ((int64_t)1 << 23))
-            *err = radix_pass<16, NV>(K[cur], K[cur ^ 1], va, max_n, d_n, shift, bits, hist,
                                       scan_scratch, flags, st);
         else if (NV == 3 && max_n > ((int64_t)1 << 27))
             *err = radix_pass<16, NV>(K[cur], K[cur ^ 1], va, max_n, d_n, shift, bits, hist,
@@ -536,12 +532,6 @@ int radix_sort_kv3(uint32_t* K[2], uint32_t* V[3][2], int64_t max_n, const uint3
                    int hi, uint32_t* hist, uint32_t* scan_scratch, uint32_t* flags, hipStream_t st,
                    hipError_t* err) {
     return radix_sort_impl<3>(K, V, max_n, d_n, lo, hi, hist, scan_scratch, flags, st, err);
-}
-
-int radix_sort_kv2(uint32_t* K[2], uint32_t* V[2][2], int64_t max_n, const uint32_t* d_n, int lo,
-                   int hi, uint32_t* hist, uint32_t* scan_scratch, uint32_t* flags, hipStream_t st,
-                   hipError_t* err) {
-    return radix_sort_impl<2>(K, V, max_n, d_n, lo, hi, hist, scan_scratch, flags, st, err);
 }
 
 }  // namespace gs
