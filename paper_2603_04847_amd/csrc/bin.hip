@@ -129,7 +129,35 @@ __global__ __launch_bounds__(kBlock) void k_count(const float4* __restrict__ rec
 // wave's range.  Counts come from adjacent offsets, so the only access by pair
 // index is the record.  Also reports the number of visible pairs (their depth
 // keys sort before the culled ones' 0xFFFFFFFF).
-__global__ __launch_bounds__(kBlock) void k_emit(const float4* __restrict__ rec, int N, ViewTable vt,
+// The masks of a unit whose block columns fit within four blocks, all at once:
+// row i's quadrant columns as one run of bits counted from the unit's first
+// block column, then a 4 x 4 byte transpose of rows 0-3 and of rows 4-7, so
+// that block bc0 + k has mask hi[k] << 32 | lo[k] (the same as
+// block_unit_mask(u, bc0 + k)).
+struct UnitMasks4 {
+    uint32_t lo[4], hi[4];
+};
+
+__device__ __forceinline__ void unit_masks4(const BlockUnit& u, UnitMasks4& w) {
+    const int base = kBlockQuads * u.bc0;
+    uint32_t S[kBlockQuads];
+#pragma unroll
+    for (int i = 0; i < kBlockQuads; i++) {
+        // a non-empty row starts at or after the first block column and ends
+        // within the fourth: 0 <= a <= b <= 31
+        const int a = u.c0[i] - base, b = u.c1[i] - base;
+        S[i] = u.c0[i] <= u.c1[i] ? ((2u << (b - a)) - 1u) << a : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        w.lo[k] = ((S[0] >> (8 * k)) & 0xFFu) | (((S[1] >> (8 * k)) & 0xFFu) << 8) |
+                  (((S[2] >> (8 * k)) & 0xFFu) << 16) | ((S[3] >> (8 * k)) << 24);
+        w.hi[k] = ((S[4] >> (8 * k)) & 0xFFu) | (((S[5] >> (8 * k)) & 0xFFu) << 8) |
+                  (((S[6] >> (8 * k)) & 0xFFu) << 16) | ((S[7] >> (8 * k)) << 24);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) void k_emit(const float4* __restrict__ rec, int N, ViewTable vt,
                                                  RasterParams rp, const uint32_t* __restrict__ order,
                                                  uint32_t pmask, const uint32_t* __restrict__ off,
                                                  const uint32_t* __restrict__ keys, int64_t n,
@@ -196,13 +224,15 @@ __global__ __launch_bounds__(kBlock) void k_emit(const float4* __restrict__ rec,
         }
         uint32_t rt;
         uint32_t o = done + wave_excl_scan(ne, rt);
+        // when every unit of the round spans at most four block columns, the
+        // masks come from one transpose per unit instead of eight rows per block
+        const bool narrow = __ballot(ne != 0u && u.bc1 - u.bc0 >= 4) == 0;
         if (ne) {
             const int vq = wu.v[q];
             const uint32_t brow = (uint32_t)vt.block_off[vq] + (uint32_t)(br * vt.bx[vq]);
             const uint32_t pq = s_pair[w][q];
-            for (int bc = u.bc0; bc <= u.bc1; bc++) {
-                const uint64_t m = block_unit_mask(u, bc);
-                if (m == 0) continue;
+            auto put = [&](int bc, uint64_t m) {
+                if (m == 0) return;
                 if (o < wave_total && base + o < lim) {  // never outside the wave's slots
                     okey[base + o] = brow + (uint32_t)bc;
                     opair[base + o] = pq;
@@ -212,6 +242,17 @@ __global__ __launch_bounds__(kBlock) void k_emit(const float4* __restrict__ rec,
                     bound_broken = true;
                 }
                 o++;
+            };
+            if (narrow) {
+                UnitMasks4 um;
+                unit_masks4(u, um);
+                for (int k = 0; k <= u.bc1 - u.bc0; k++) {
+                    const uint32_t l = k == 0 ? um.lo[0] : k == 1 ? um.lo[1] : k == 2 ? um.lo[2] : um.lo[3];
+                    const uint32_t h = k == 0 ? um.hi[0] : k == 1 ? um.hi[1] : k == 2 ? um.hi[2] : um.hi[3];
+                    put(u.bc0 + k, ((uint64_t)h << 32) | l);
+                }
+            } else {
+                for (int bc = u.bc0; bc <= u.bc1; bc++) put(bc, block_unit_mask(u, bc));
             }
         }
         done += rt;
