@@ -129,18 +129,11 @@ __global__ __launch_bounds__(kBlock) void k_count(const float4* __restrict__ rec
 // wave's range.  Counts come from adjacent offsets, so the only access by pair
 // index is the record.  Also reports the number of visible pairs (their depth
 // keys sort before the culled ones' 0xFFFFFFFF).
-// The masks of a unit whose block columns fit within four blocks, all at once:
-// row i's quadrant columns as one run of bits counted from the unit's first
-// block column, then a 4 x 4 byte transpose of rows 0-3 and of rows 4-7, so
-// that block bc0 + k has mask hi[k] << 32 | lo[k] (the same as
-// block_unit_mask(u, bc0 + k)).
-struct UnitMasks4 {
-    uint32_t lo[4], hi[4];
-};
-
-__device__ __forceinline__ void unit_masks4(const BlockUnit& u, UnitMasks4& w) {
+// Masks of a unit whose block columns fit within four blocks: row i's quadrant
+// columns as one run of bits counted from the unit's first block column, so
+// that byte k of run i is row i of the mask of block bc0 + k.
+__device__ __forceinline__ void unit_runs4(const BlockUnit& u, uint32_t (&S)[kBlockQuads]) {
     const int base = kBlockQuads * u.bc0;
-    uint32_t S[kBlockQuads];
 #pragma unroll
     for (int i = 0; i < kBlockQuads; i++) {
         // a non-empty row starts at or after the first block column and ends
@@ -148,13 +141,17 @@ __device__ __forceinline__ void unit_masks4(const BlockUnit& u, UnitMasks4& w) {
         const int a = u.c0[i] - base, b = u.c1[i] - base;
         S[i] = u.c0[i] <= u.c1[i] ? ((2u << (b - a)) - 1u) << a : 0u;
     }
-#pragma unroll
-    for (int k = 0; k < 4; k++) {
-        w.lo[k] = ((S[0] >> (8 * k)) & 0xFFu) | (((S[1] >> (8 * k)) & 0xFFu) << 8) |
-                  (((S[2] >> (8 * k)) & 0xFFu) << 16) | ((S[3] >> (8 * k)) << 24);
-        w.hi[k] = ((S[4] >> (8 * k)) & 0xFFu) | (((S[5] >> (8 * k)) & 0xFFu) << 8) |
-                  (((S[6] >> (8 * k)) & 0xFFu) << 16) | ((S[7] >> (8 * k)) << 24);
-    }
+}
+
+// The mask of block bc0 + k from the runs: byte k of runs 0-7 gathered with
+// byte permutes (v_perm_b32 selector values 0-3 take bytes of its second
+// operand, 4-7 of its first, 12 gives zero); equal to block_unit_mask.
+__device__ __forceinline__ uint64_t runs_mask4(const uint32_t (&S)[kBlockQuads], int k) {
+    const uint32_t sa = 0x0C0C0400u + 0x0101u * (uint32_t)k;      // bytes 0, 1
+    const uint32_t sb = 0x04000C0Cu + 0x01010000u * (uint32_t)k;  // bytes 2, 3
+    const uint32_t lo = __builtin_amdgcn_perm(S[1], S[0], sa) | __builtin_amdgcn_perm(S[3], S[2], sb);
+    const uint32_t hi = __builtin_amdgcn_perm(S[5], S[4], sa) | __builtin_amdgcn_perm(S[7], S[6], sb);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) void k_emit(const float4* __restrict__ rec, int N, ViewTable vt,
@@ -225,7 +222,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) voi
         uint32_t rt;
         uint32_t o = done + wave_excl_scan(ne, rt);
         // when every unit of the round spans at most four block columns, the
-        // masks come from one transpose per unit instead of eight rows per block
+        // masks come from per-row bit runs, four byte permutes per block,
+        // instead of eight clamped rows per block
         const bool narrow = __ballot(ne != 0u && u.bc1 - u.bc0 >= 4) == 0;
         if (ne) {
             const int vq = wu.v[q];
@@ -244,13 +242,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) voi
                 o++;
             };
             if (narrow) {
-                UnitMasks4 um;
-                unit_masks4(u, um);
-                for (int k = 0; k <= u.bc1 - u.bc0; k++) {
-                    const uint32_t l = k == 0 ? um.lo[0] : k == 1 ? um.lo[1] : k == 2 ? um.lo[2] : um.lo[3];
-                    const uint32_t h = k == 0 ? um.hi[0] : k == 1 ? um.hi[1] : k == 2 ? um.hi[2] : um.hi[3];
-                    put(u.bc0 + k, ((uint64_t)h << 32) | l);
-                }
+                uint32_t S[kBlockQuads];
+                unit_runs4(u, S);
+                for (int k = 0; k <= u.bc1 - u.bc0; k++) put(u.bc0 + k, runs_mask4(S, k));
             } else {
                 for (int bc = u.bc0; bc <= u.bc1; bc++) put(bc, block_unit_mask(u, bc));
             }
