@@ -495,15 +495,16 @@ int radix_sort_impl(uint32_t* K[2], uint32_t* V[NV][2], int64_t max_n, const uin
             va.out[c] = V[c][cur ^ 1];
         }
         // large single-value inputs (the depth sort, whose one value word
-        // packs the pair and its entry count): 8192 items per block, for
-        // longer runs per digit in the scatter; the block sort of a list
+        // packs the pair and its entry count): 4096 items per block (on the
+        // 20M pairs of the large scene 0.06 ms faster over the four passes
+        // than 8192, and 0.08 ms faster than 2048); the block sort of a list
         // capacity past 2^27 4096 (fewer digit counts to scan); the others
         // 2048: a sort of a few million items still gives every CU several
         // blocks, and a block sort of tens of millions of entries gains from
         // the shorter blocks (measured: at 70M capacity 2048 beats 4096 by
         // 15 us, at 333M it loses by 120 us)
         if (NV == 1 && max_n > ((int64_t)1 << 22))
-            *err = radix_pass<32, NV>(K[cur], K[cur ^ 1], va, max_n, d_n, shift, bits, hist,
+            *err = radix_pass<16, NV>(K[cur], K[cur ^ 1], va, max_n, d_n, shift, bits, hist,
                                       scan_scratch, flags, st);
         else if (NV == 3 && max_n > ((int64_t)1 << 27))
             *err = radix_pass<16, NV>(K[cur], K[cur ^ 1], va, max_n, d_n, shift, bits, hist,
