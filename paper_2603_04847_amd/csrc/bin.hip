@@ -129,21 +129,19 @@ __global__ __launch_bounds__(kBlock) void k_count(const float4* __restrict__ rec
 // wave's range.  Counts come from adjacent offsets, so the only access by pair
 // index is the record.  Also reports the number of visible pairs (their depth
 // keys sort before the culled ones' 0xFFFFFFFF).
-// Masks of a unit whose block columns fit within four blocks: row i's quadrant
-// columns as one run of bits counted from the unit's first block column, so
-// that byte k of run i is row i of the mask of block bc0 + k.
-__device__ __forceinline__ void unit_runs4(const BlockUnit& u, uint32_t (&S)[kBlockQuads]) {
-    const int base = kBlockQuads * u.bc0;
+// Masks of four block columns of a unit from q0 = 8 c on: row i's quadrant
+// columns inside [q0, q0 + 32) as one run of bits counted from q0, so that
+// byte k of run i is row i of the mask of block column c + k.
+__device__ __forceinline__ void unit_runs4(const BlockUnit& u, int c, uint32_t (&S)[kBlockQuads]) {
+    const int base = kBlockQuads * c;
 #pragma unroll
     for (int i = 0; i < kBlockQuads; i++) {
-        // a non-empty row starts at or after the first block column and ends
-        // within the fourth: 0 <= a <= b <= 31
-        const int a = u.c0[i] - base, b = u.c1[i] - base;
-        S[i] = u.c0[i] <= u.c1[i] ? ((2u << (b - a)) - 1u) << a : 0u;
+        const int a = max(u.c0[i] - base, 0), b = min(u.c1[i] - base, 31);
+        S[i] = (u.c0[i] <= u.c1[i] && a <= b) ? ((2u << (b - a)) - 1u) << a : 0u;
     }
 }
 
-// The mask of block bc0 + k from the runs: byte k of runs 0-7 gathered with
+// The mask of block column c + k from the runs: byte k of runs 0-7 gathered with
 // byte permutes (v_perm_b32 selector values 0-3 take bytes of its second
 // operand, 4-7 of its first, 12 gives zero); equal to block_unit_mask.
 __device__ __forceinline__ uint64_t runs_mask4(const uint32_t (&S)[kBlockQuads], int k) {
@@ -221,10 +219,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) voi
         }
         uint32_t rt;
         uint32_t o = done + wave_excl_scan(ne, rt);
-        // when every unit of the round spans at most four block columns, the
-        // masks come from per-row bit runs, four byte permutes per block,
-        // instead of eight clamped rows per block
-        const bool narrow = __ballot(ne != 0u && u.bc1 - u.bc0 >= 4) == 0;
         if (ne) {
             const int vq = wu.v[q];
             const uint32_t brow = (uint32_t)vt.block_off[vq] + (uint32_t)(br * vt.bx[vq]);
@@ -241,12 +235,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) voi
                 }
                 o++;
             };
-            if (narrow) {
+            // four block columns at a time: per-row bit runs, then four byte
+            // permutes per block instead of eight clamped rows
+            for (int c = u.bc0; c <= u.bc1; c += 4) {
                 uint32_t S[kBlockQuads];
-                unit_runs4(u, S);
-                for (int k = 0; k <= u.bc1 - u.bc0; k++) put(u.bc0 + k, runs_mask4(S, k));
-            } else {
-                for (int bc = u.bc0; bc <= u.bc1; bc++) put(bc, block_unit_mask(u, bc));
+                unit_runs4(u, c, S);
+                const int kn = min(3, u.bc1 - c);
+                for (int k = 0; k <= kn; k++) put(c + k, runs_mask4(S, k));
             }
         }
         done += rt;
