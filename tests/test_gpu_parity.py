@@ -185,12 +185,15 @@ def test_bin_sort_bit_exact_with_many_scan_tiles(gs):
         assert np.array_equal(ent >> 28, masks_o.astype(np.uint32)), rep
 
 
-def test_bin_sort_bit_exact_with_wide_splats(gs):
+@pytest.mark.parametrize("view", [(256, 192), (1040, 144)])
+def test_bin_sort_bit_exact_with_wide_splats(gs, view):
     """Most splats cover the whole view, so a 256-entry chunk of a block list
     holds more tile entries than the expansion stages in LDS (2048): those
     chunks take the direct-store path, the rest the staged one; lists stay
-    bit-exact."""
-    wh = np.array([[256, 192]], np.int32)
+    bit-exact.  The 1040-px view is 17 block columns wide (the last one
+    ragged), so the emit pass builds a whole-view splat's masks in five runs
+    of four block columns."""
+    wh = np.array([view], np.int32)
     N = 2000
     r = scenegen.synthetic_records(13, 1, wh, N, tile=(16, 16))
     huge = np.random.default_rng(5).uniform(size=N) < 0.6
