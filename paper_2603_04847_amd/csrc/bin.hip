@@ -122,13 +122,6 @@ __global__ __launch_bounds__(kBlock) void k_count(const float4* __restrict__ rec
     val[pair] = (uint32_t)pair | (min(c, ~0u >> pbits) << pbits);
 }
 
-// One (block key; pair, mask) entry per block met, pairs in depth order: rank
-// r's entries fill [off[r], off[r + 1]) (the last rank ends at the total).  The
-// 64 ranks of a wave own one contiguous output range; in each round every lane
-// takes one unit (block row) and writes its entries at the unit's place in the
-// wave's range.  Counts come from adjacent offsets, so the only access by pair
-// index is the record.  Also reports the number of visible pairs (their depth
-// keys sort before the culled ones' 0xFFFFFFFF).
 // Masks of four block columns of a unit from q0 = 8 c on: row i's quadrant
 // columns inside [q0, q0 + 32) as one run of bits counted from q0, so that
 // byte k of run i is row i of the mask of block column c + k.
@@ -152,6 +145,13 @@ __device__ __forceinline__ uint64_t runs_mask4(const uint32_t (&S)[kBlockQuads],
     return ((uint64_t)hi << 32) | lo;
 }
 
+// One (block key; pair, mask) entry per block met, pairs in depth order: rank
+// r's entries fill [off[r], off[r + 1]) (the last rank ends at the total).  The
+// 64 ranks of a wave own one contiguous output range; in each round every lane
+// takes one unit (block row) and writes its entries at the unit's place in the
+// wave's range.  Counts come from adjacent offsets, so the only access by pair
+// index is the record.  Also reports the number of visible pairs (their depth
+// keys sort before the culled ones' 0xFFFFFFFF).
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) void k_emit(const float4* __restrict__ rec, int N, ViewTable vt,
                                                  RasterParams rp, const uint32_t* __restrict__ order,
                                                  uint32_t pmask, const uint32_t* __restrict__ off,
